@@ -1,0 +1,219 @@
+/*
+ * clean.h -- C ABI of the MI355X (gfx950) Hogbom CLEAN library.
+ *
+ * Operations (Wright, Adamek, Armour, "Distribution of the Hogbom CLEAN
+ * Algorithm Using Tiled Images with Feedback", arXiv 2501.01461):
+ *
+ *   clean_hogbom          the Hogbom minor loop (Section 3, the two update
+ *                         equations): find the pixel of largest |residual|,
+ *                         append (position, gain * value) to the component
+ *                         list, subtract gain * value * PSF centred there.
+ *   clean_tiled_feedback  the tiled form with feedback (Sections 2 and 3,
+ *                         Figs. 1-3): tiles run their own minor loops on their
+ *                         own pixels; at a fixed interval each tile's new
+ *                         components, convolved with the full PSF (the
+ *                         cross-coupling image), are subtracted from every
+ *                         other tile.
+ *   clean_batched         many independent Hogbom problems of uneven size, each
+ *                         with its own PSF, in one persistent launch (not in the
+ *                         paper; a serving form of the same minor loop).
+ *   clean_psf_to_f16      converts an FP32 PSF to FP16 storage (round to
+ *                         nearest even) for the half-traffic PSF option.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Images are row-major float32, ny rows of nx pixels; a pixel's index is
+ *   y * nx + x.  The PSF is row-major, psf_ny x psf_nx with psf_ny >= 2*ny and
+ *   psf_nx >= 2*nx, its centre (peak) at (psf_ny/2, psf_nx/2).  Subtracting the
+ *   PSF "centred on p" updates pixel q with psf[q - p + centre]; with the size
+ *   rule no index ever leaves the PSF.
+ * - Unless stated, every pointer argument is a DEVICE pointer (memory from
+ *   hipMalloc or a torch CUDA tensor on the current device) and the CALLER owns
+ *   it; the library never frees caller memory.  `clean_params`, `clean_stats`
+ *   and `clean_problem` arrays are HOST memory.
+ * - `stream` is a hipStream_t (NULL = the default stream).  Work is queued on
+ *   it, and every call synchronises the stream before it returns (the stats
+ *   need the device's counters), so calls are synchronous.
+ * - Return value: CLEAN_OK, or a negative clean_status.  Arguments are checked
+ *   before anything is launched; on an argument error nothing is written.
+ *   clean_last_error() gives a thread-local message for the last failure.
+ * - Arithmetic (the FP32 path): component = fl32((float)gain * v); each pixel
+ *   update is one fused multiply-add r = fma(-component, psf, r); the peak is
+ *   the largest |r| with ties going to the lowest index; the stop tests, made
+ *   before each append, are n == max_iter, then (double)|v| < threshold, then
+ *   n == capacity.  IEEE subnormals are kept.  With an FP32 PSF the plain
+ *   path's components and residual are bit-identical to a serial CPU run of
+ *   the same definition.
+ * - Non-finite input: with CLEAN_FLAG_CHECK_FINITE the dirty image (and the
+ *   PSF) are scanned first and CLEAN_E_NONFINITE is returned if any value is
+ *   NaN or infinite; without it the result for such input is undefined.
+ * - Concurrency: calls that use the library's internal workspace (workspace ==
+ *   NULL) must not overlap on one device; pass separate workspaces to overlap.
+ */
+#ifndef CLEAN_H
+#define CLEAN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    CLEAN_OK = 0,
+    CLEAN_E_INVAL = -1,       /* bad argument (message in clean_last_error)   */
+    CLEAN_E_NONFINITE = -2,   /* NaN/Inf found with CLEAN_FLAG_CHECK_FINITE   */
+    CLEAN_E_NOMEM = -3,       /* workspace allocation failed / too small      */
+    CLEAN_E_HIP = -4,         /* a HIP runtime call failed                    */
+    CLEAN_E_TIMEOUT = -5,     /* a device-side wait exceeded its time limit   */
+    CLEAN_E_UNSUPPORTED = -6  /* shape or option outside what is implemented  */
+} clean_status;
+
+typedef enum {
+    CLEAN_STOP_MAXITER = 0,   /* max_iter components were found               */
+    CLEAN_STOP_THRESHOLD = 1, /* every peak is below the threshold            */
+    CLEAN_STOP_CAPACITY = 2   /* comp_cap components were found first         */
+} clean_stop;
+
+typedef enum { CLEAN_PSF_F32 = 0, CLEAN_PSF_F16 = 1 } clean_psf_dtype;
+
+enum {
+    CLEAN_FLAG_CHECK_FINITE = 1   /* scan inputs for NaN/Inf before starting   */
+};
+
+typedef struct {
+    double gain;          /* loop gain, 0 < gain <= 1 (applied as float)          */
+    double threshold;     /* Jy; stop when |peak| < threshold; >= 0               */
+    int64_t max_iter;     /* total minor iterations (all tiles together); >= 0    */
+    int32_t psf_dtype;    /* clean_psf_dtype of the `psf` argument                */
+    int32_t flags;        /* CLEAN_FLAG_* bits                                    */
+    int32_t wg_per_tile;  /* launch shape: workgroups per tile (0 = library pick) */
+    int32_t px_per_thread;/* launch shape: residual pixels per thread, one of
+                             4, 8, 16, 32, 64, 128 (0 = library pick)              */
+} clean_params;
+
+typedef struct {
+    int64_t n_iter;       /* components written                                   */
+    int32_t stop_reason;  /* clean_stop                                           */
+    int32_t n_rounds;     /* feedback rounds (tiled); 0 for plain                 */
+    double final_peak;    /* signed value of the largest |residual| at the stop   */
+    double residual_rms;  /* sqrt(mean(residual^2)), float64 accumulation         */
+    double model_flux;    /* sum of all components, float64 accumulation          */
+    float device_ms;      /* device time of the call (HIP events)                 */
+    int32_t wg_per_tile;  /* launch shape that was used                           */
+    int32_t px_per_thread;
+    int32_t workgroups;   /* total workgroups in the persistent launch            */
+} clean_stats;
+
+/*
+ * clean_hogbom -- plain Hogbom CLEAN on one image (Section 3, eqs. 1 and 2).
+ *
+ *   dirty      [ny*nx] float32 input image; may alias `residual` (in place).
+ *   psf        [psf_ny*psf_nx] float32, or float16 bits when
+ *              p->psf_dtype == CLEAN_PSF_F16 (values are widened to float32
+ *              before the fma).
+ *   residual   [ny*nx] float32 output.
+ *   comp_idx   [comp_cap] int32 output: pixel index of component k, in the
+ *              order found.
+ *   comp_flux  [comp_cap] float32 output: component value k.
+ *   model      [ny*nx] float64 output or NULL: per-pixel sum of components in
+ *              list order.
+ *   workspace  device scratch of workspace_bytes (>= clean_workspace_size()),
+ *              or NULL to use a library-owned buffer.
+ *   stats      host output, may be NULL.
+ * Limits: ny*nx <= 2^28 - 1; psf byte size < 2^32.
+ */
+int clean_hogbom(const float *dirty, int ny, int nx,
+                 const void *psf, int psf_ny, int psf_nx,
+                 const clean_params *p,
+                 float *residual,
+                 int32_t *comp_idx, float *comp_flux, int64_t comp_cap,
+                 double *model,
+                 void *workspace, size_t workspace_bytes,
+                 clean_stats *stats, void *stream);
+
+/*
+ * clean_tiled_feedback -- tiled Hogbom CLEAN with feedback (Sections 2-3).
+ *
+ * Tiles: tile (i, j), id i*tiles_x + j, covers rows [i*ny/tiles_y,
+ * (i+1)*ny/tiles_y) and columns [j*nx/tiles_x, (j+1)*nx/tiles_x) (floor
+ * division).  Each round: tiles whose peak is >= threshold are active; each
+ * active tile runs up to `feedback_interval` minor iterations on its own pixels
+ * (when fewer than |active| * interval iterations remain, the remainder is split
+ * evenly, lower tile ids taking the extra one); then every tile's new
+ * components are placed on a component image (float64 sums in the order found,
+ * rounded once to float32) and, for every pixel q of tile s,
+ *   acc = 0;  for every other tile t in ascending order, for each of its
+ *   non-zero component pixels c in row-major order:
+ *             acc = fmaf(value_c, psf[q - c + centre], acc);
+ *   r[q] = r[q] - acc.
+ * The run stops at the start of a round when max_iter components exist, when
+ * no tile is active, or when comp_cap components exist.  Every round ends with
+ * its feedback, so residual + components (*) PSF = dirty holds at return.
+ *
+ *   comp_idx/comp_flux   order: round, then tile id, then local iteration.
+ *   feedback_interval    1 .. 4096.
+ *   tiles_y, tiles_x     1 .. ny (nx); at most 1024 tiles.
+ * Other arguments as for clean_hogbom.  With tiles_y = tiles_x = 1 the result
+ * equals clean_hogbom's bit for bit.
+ */
+int clean_tiled_feedback(const float *dirty, int ny, int nx,
+                         const void *psf, int psf_ny, int psf_nx,
+                         int tiles_y, int tiles_x, int feedback_interval,
+                         const clean_params *p,
+                         float *residual,
+                         int32_t *comp_idx, float *comp_flux, int64_t comp_cap,
+                         double *model,
+                         void *workspace, size_t workspace_bytes,
+                         clean_stats *stats, void *stream);
+
+/*
+ * One problem of a batch: the fields mirror clean_hogbom's arguments (device
+ * pointers, caller-owned).  threshold and max_iter are per problem; gain,
+ * psf_dtype and flags come from the shared clean_params.
+ */
+typedef struct {
+    const float *dirty;
+    const void *psf;
+    float *residual;
+    int32_t *comp_idx;
+    float *comp_flux;
+    double *model;        /* may be NULL */
+    int64_t comp_cap;
+    int64_t max_iter;
+    double threshold;
+    int32_t ny, nx, psf_ny, psf_nx;
+} clean_problem;
+
+/*
+ * clean_batched -- n independent plain Hogbom problems in one persistent
+ * launch.  Workgroup clusters take problems from a device queue, largest
+ * first; each problem's result is identical to clean_hogbom on it alone.
+ *   probs  host array of n problems; stats host array of n (may be NULL).
+ * Uses the library's internal workspace; n <= 65536.
+ */
+int clean_batched(const clean_problem *probs, int n, const clean_params *shared,
+                  clean_stats *stats, void *stream);
+
+/* Bytes of device workspace clean_hogbom (tiles 1x1) or clean_tiled_feedback
+ * needs for this shape; 0 on invalid arguments. */
+size_t clean_workspace_size(int ny, int nx, int tiles_y, int tiles_x,
+                            int feedback_interval, const clean_params *p);
+
+/* FP32 -> FP16 (round to nearest even) of n values, on `stream`; synchronous. */
+int clean_psf_to_f16(const float *psf, uint16_t *out, int64_t n, void *stream);
+
+/* Static description of a clean_status value. */
+const char *clean_strerror(int status);
+
+/* Thread-local detail of the last failing call on this thread ("" if none). */
+const char *clean_last_error(void);
+
+/* Library version string. */
+const char *clean_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CLEAN_H */

@@ -1,0 +1,361 @@
+"""Pins for the CPU oracle: each checks it against something other than itself.
+
+* the single-point-source closed form (cumulative flux A(1-(1-g)^n));
+* the invariant dirty - residual = model (*) PSF, with the convolution done by
+  scipy's FFT convolution (an independent library routine);
+* exact rational arithmetic on tiny dyadic inputs (tests/exact_clean.py), for
+  plain CLEAN and for the tiled form with feedback;
+* crafted exact ties (lowest row-major index wins), the stop rules;
+* the feedback step against scipy's FFT convolution of each tile's components;
+* special cases: one tile is plain CLEAN; one round of tiles is plain CLEAN on
+  each cropped tile; resuming from a residual continues the same sequence.
+
+Asymmetric, non-square PSFs and non-square images are used throughout so that a
+flipped or transposed index cannot pass.
+"""
+import numpy as np
+import pytest
+from scipy.signal import fftconvolve
+
+import oracle
+from paper_2501_01461_amd import synth
+from tests import exact_clean
+
+STOP_MAXITER, STOP_THRESHOLD, STOP_CAPACITY = 0, 1, 2
+
+
+def rng(*k):
+    return np.random.default_rng([7, *k])
+
+
+def asym_psf(My, Mx, seed, spread=0.6):
+    return synth.random_psf(My, Mx, rng(seed, 1), spread).astype(np.float32)
+
+
+def point_source_dirty(ny, nx, psf, py, px, A):
+    cy, cx = psf.shape[0] // 2, psf.shape[1] // 2
+    win = psf[cy - py:cy - py + ny, cx - px:cx - px + nx].astype(np.float64)
+    return (A * win).astype(np.float32)
+
+
+def model_conv(model, psf, ny, nx):
+    """sum_p model[p] * psf[q - p + centre] via scipy's FFT convolution."""
+    cy, cx = psf.shape[0] // 2, psf.shape[1] // 2
+    full = fftconvolve(model.astype(np.float64), psf.astype(np.float64), mode="full")
+    return full[cy:cy + ny, cx:cx + nx]
+
+
+# ------------------------------------------------------------ closed form --
+
+@pytest.mark.parametrize("precision", ["f32", "f64"])
+def test_single_point_source_closed_form(precision):
+    ny, nx = 40, 56
+    psf = asym_psf(2 * ny + 2, 2 * nx + 4, 11, spread=0.5)
+    py, px, A = 17, 29, 2.1
+    dirty = point_source_dirty(ny, nx, psf, py, px, A)
+    n = 60
+    out = oracle.hogbom(dirty, psf, gain=0.1, threshold=0.0, max_iter=n, precision=precision)
+    assert out["n_iter"] == n and out["stop"] == STOP_MAXITER
+    assert np.all(out["idx"] == py * nx + px)
+    # effective gain: the working precision's rounding of 0.1
+    g = float(np.float32(0.1)) if precision == "f32" else 0.1
+    A0 = float(dirty[py, px])
+    k = np.arange(1, n + 1)
+    cum = np.cumsum(out["flux"].astype(np.float64))
+    closed = A0 * (1.0 - (1.0 - g) ** k)
+    eps = 2.0 ** -24 if precision == "f32" else 2.0 ** -53
+    assert np.max(np.abs(cum - closed)) <= 4 * n * eps * A0
+    # each component is g times what is left
+    comp_closed = g * A0 * (1.0 - g) ** (k - 1)
+    assert np.max(np.abs(out["flux"] - comp_closed)) <= 4 * n * eps * A0
+    # residual = dirty - A(1-(1-g)^n) * PSF centred on the source
+    cy, cx = psf.shape[0] // 2, psf.shape[1] // 2
+    win = psf[cy - py:cy - py + ny, cx - px:cx - px + nx].astype(np.float64)
+    res_closed = dirty.astype(np.float64) - closed[-1] * win
+    assert np.max(np.abs(out["residual"] - res_closed)) <= 4 * n * eps * A0
+    # model holds the whole cleaned flux at the one position
+    assert out["model"][py, px] == pytest.approx(cum[-1], abs=4 * n * eps * A0)
+    assert np.count_nonzero(out["model"]) == 1
+
+
+# -------------------------------------------------------------- invariant --
+
+@pytest.mark.parametrize("precision", ["f32", "f64"])
+def test_invariant_plain(precision):
+    ny, nx = 48, 36
+    psf = asym_psf(2 * ny, 2 * nx + 6, 21)
+    r = rng(22)
+    dirty = (r.normal(0, 0.05, (ny, nx)) + (r.random((ny, nx)) < 0.02) * r.uniform(-2, 2, (ny, nx)))
+    dirty = dirty.astype(np.float32)
+    n = 300
+    out = oracle.hogbom(dirty, psf, gain=0.1, threshold=0.0, max_iter=n, precision=precision)
+    lhs = dirty.astype(np.float64) - out["residual"].astype(np.float64)
+    rhs = model_conv(out["model"], psf, ny, nx)
+    scale = np.abs(dirty).max()
+    tol = (8 * n * 2.0 ** -24 * scale) if precision == "f32" else 1e-11 * n * scale
+    assert np.max(np.abs(lhs - rhs)) <= tol
+    # the model equals the component list summed per position
+    m2 = np.zeros(ny * nx)
+    np.add.at(m2, out["idx"], out["flux"].astype(np.float64))
+    assert np.array_equal(m2.reshape(ny, nx), out["model"])
+
+
+@pytest.mark.parametrize("precision", ["f32", "f64"])
+@pytest.mark.parametrize("tiles,interval", [((2, 2), 7), ((3, 2), 20), ((2, 3), 1)])
+def test_invariant_tiled(precision, tiles, interval):
+    ny, nx = 30, 42
+    psf = asym_psf(2 * ny + 4, 2 * nx, 31)
+    r = rng(32)
+    dirty = (r.normal(0, 0.05, (ny, nx)) + (r.random((ny, nx)) < 0.03) * r.uniform(-2, 2, (ny, nx)))
+    dirty = dirty.astype(np.float32)
+    n = 250
+    out = oracle.tiled(dirty, psf, tiles, interval, gain=0.1, threshold=0.0, max_iter=n, precision=precision)
+    assert out["n_iter"] == n
+    lhs = dirty.astype(np.float64) - out["residual"].astype(np.float64)
+    rhs = model_conv(out["model"], psf, ny, nx)
+    scale = np.abs(dirty).max()
+    tol = (16 * n * 2.0 ** -24 * scale) if precision == "f32" else 1e-11 * n * scale
+    assert np.max(np.abs(lhs - rhs)) <= tol
+
+
+# ------------------------------------------------- exact rational arithmetic --
+
+def dyadic_case(seed, ny, nx, My, Mx):
+    r = rng(100, seed)
+    dirty = (r.integers(-2 ** 21, 2 ** 21 + 1, (ny, nx)) / 2.0 ** 20).astype(np.float32)
+    psf = (r.integers(-39321, 39322, (My, Mx)) / 2.0 ** 16).astype(np.float32)
+    psf[My // 2, Mx // 2] = 1.0
+    return dirty, psf
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_plain_against_exact_rationals(seed):
+    ny, nx = 10, 13
+    dirty, psf = dyadic_case(seed, ny, nx, 2 * ny + 2, 2 * nx)
+    n = 25
+    r_ex, comps, margins = exact_clean.hogbom(dirty, psf, 0.1, 0.0, n)
+    out = oracle.hogbom(dirty, psf, 0.1, 0.0, n, precision="f64")
+    ex_idx = np.array([c[0] for c in comps])
+    ex_flux = np.array([float(c[1]) for c in comps])
+    # positions agree up to the first step whose exact runner-up is within rounding reach
+    k_ok = next((k for k, m in enumerate(margins) if float(m) < 1e-9), len(margins))
+    assert k_ok >= 10, "seed has an early near-tie; pick another"
+    assert np.array_equal(out["idx"][:k_ok], ex_idx[:k_ok])
+    assert np.max(np.abs(out["flux"][:k_ok] - ex_flux[:k_ok])) < 1e-12
+    if k_ok == len(margins):
+        res_ex = np.array([[float(r_ex[(y, x)]) for x in range(nx)] for y in range(ny)])
+        assert np.max(np.abs(out["residual"] - res_ex)) < 1e-12
+    # FP32 run against the exact run with the float32 gain
+    r32, comps32, m32 = exact_clean.hogbom(dirty, psf, float(np.float32(0.1)), 0.0, n)
+    o32 = oracle.hogbom(dirty, psf, 0.1, 0.0, n, precision="f32")
+    k32 = next((k for k, m in enumerate(m32) if float(m) < 1e-4), len(m32))
+    assert np.array_equal(o32["idx"][:k32], np.array([c[0] for c in comps32])[:k32])
+    assert np.max(np.abs(o32["flux"][:k32] - np.array([float(c[1]) for c in comps32])[:k32]),
+                  initial=0.0) < 1e-5
+
+
+@pytest.mark.parametrize("seed,tiles,interval", [(0, (2, 2), 3), (1, (2, 2), 5), (2, (3, 2), 2),
+                                                 (3, (1, 3), 4), (4, (2, 1), 6), (5, (2, 2), 1)])
+def test_tiled_against_exact_rationals(seed, tiles, interval):
+    ny, nx = 10, 12
+    dirty, psf = dyadic_case(50 + seed, ny, nx, 2 * ny, 2 * nx + 2)
+    n = 24
+    r_ex, comps, margins, rounds = exact_clean.tiled(dirty, psf, tiles, interval, 0.1, 0.0, n)
+    out = oracle.tiled(dirty, psf, tiles, interval, 0.1, 0.0, n, precision="f64")
+    assert out["n_iter"] == len(comps) == n
+    assert out["n_rounds"] == rounds
+    assert min(float(m) for m in margins) > 1e-9, "near-tie in this seed; pick another"
+    assert np.array_equal(out["idx"], np.array([c[0] for c in comps]))
+    assert np.max(np.abs(out["flux"] - np.array([float(c[1]) for c in comps]))) < 1e-12
+    res_ex = np.array([[float(r_ex[(y, x)]) for x in range(nx)] for y in range(ny)])
+    assert np.max(np.abs(out["residual"] - res_ex)) < 1e-12
+
+
+def gauss_dyadic_psf(My, Mx, s):
+    y, x = np.mgrid[0:My, 0:Mx]
+    g = np.exp(-((y - My // 2) ** 2 + (x - Mx // 2) ** 2) / (2 * s * s))
+    return (np.round(g * 2 ** 16) / 2 ** 16).astype(np.float32)
+
+
+def test_tiled_threshold_against_exact_rationals():
+    """A threshold-stopped tiled run: round count, stop reason and every
+    component position agree with exact arithmetic."""
+    r = np.random.default_rng([7, 177])
+    ny = nx = 12
+    d = np.round(r.normal(0, 0.01, (ny, nx)) * 2 ** 20) / 2 ** 20
+    for _ in range(5):
+        d[r.integers(ny), r.integers(nx)] += np.round(r.uniform(-2, 2) * 2 ** 20) / 2 ** 20
+    dirty = d.astype(np.float32)
+    psf = gauss_dyadic_psf(24, 24, 1.2)
+    thr = 0.5
+    r_ex, comps, margins, rounds = exact_clean.tiled(dirty, psf, (2, 2), 4, 0.1, thr, 500)
+    out = oracle.tiled(dirty, psf, (2, 2), 4, 0.1, thr, 500, precision="f64")
+    assert out["stop"] == STOP_THRESHOLD and len(comps) < 500
+    assert out["n_iter"] == len(comps) and out["n_rounds"] == rounds
+    assert min(float(m) for m in margins) > 1e-9
+    assert np.array_equal(out["idx"], np.array([c[0] for c in comps]))
+    assert np.max(np.abs(out["flux"] - np.array([float(c[1]) for c in comps]))) < 1e-12
+
+
+# -------------------------------------------------------- ties and stops --
+
+@pytest.mark.parametrize("precision", ["f32", "f64"])
+def test_ties_lowest_index_wins(precision):
+    ny, nx = 8, 9
+    psf = np.zeros((16, 18), np.float32)
+    psf[8, 9] = 1.0
+    d = np.zeros((ny, nx), np.float32)
+    d[5, 2] = 1.5          # index 47
+    d[3, 7] = -1.5         # index 34: same |value|, lower index
+    d[6, 0] = 1.5          # index 54
+    out = oracle.hogbom(d, psf, 0.5, 0.0, 3, precision=precision)
+    assert list(out["idx"]) == [34, 47, 54]
+    assert out["flux"][0] == -0.75 and out["flux"][1] == 0.75
+    # all-zero image: index 0 is the peak, a zero component is appended
+    z = oracle.hogbom(np.zeros((ny, nx), np.float32), psf, 0.5, 0.0, 2, precision=precision)
+    assert list(z["idx"]) == [0, 0] and np.all(z["flux"] == 0)
+
+
+@pytest.mark.parametrize("precision", ["f32", "f64"])
+def test_stop_rules(precision):
+    ny, nx = 12, 10
+    psf = asym_psf(24, 20, 41)
+    dirty = point_source_dirty(ny, nx, psf, 4, 6, 1.0)
+    o = oracle.hogbom(dirty, psf, 0.1, 0.0, 0, precision=precision)
+    assert o["n_iter"] == 0 and o["stop"] == STOP_MAXITER
+    assert np.array_equal(o["residual"], dirty.astype(o["residual"].dtype))
+    o = oracle.hogbom(dirty, psf, 0.1, 1.0000001, 50, precision=precision)
+    assert o["n_iter"] == 0 and o["stop"] == STOP_THRESHOLD
+    # |peak| == threshold is not below it: one more iteration happens
+    o = oracle.hogbom(dirty, psf, 0.1, 1.0, 50, precision=precision)
+    assert o["n_iter"] == 1 and o["stop"] == STOP_THRESHOLD
+    o = oracle.hogbom(dirty, psf, 0.1, 0.0, 50, cap=7, precision=precision)
+    assert o["n_iter"] == 7 and o["stop"] == STOP_CAPACITY
+    o = oracle.hogbom(dirty, psf, 0.5, 0.2, 50, precision=precision)
+    assert o["stop"] == STOP_THRESHOLD and o["n_iter"] == 3     # 1, 0.5, 0.25 > 0.2; 0.125 < 0.2
+
+
+def test_invalid_arguments():
+    d = np.zeros((8, 8), np.float32)
+    with pytest.raises(ValueError):
+        oracle.hogbom(d, np.zeros((15, 16), np.float32))       # PSF too small
+    with pytest.raises(ValueError):
+        oracle.hogbom(d, np.zeros((16, 16), np.float32), gain=0.0)
+    with pytest.raises(ValueError):
+        oracle.tiled(d, np.zeros((16, 16), np.float32), tiles=(9, 1))
+    with pytest.raises(ValueError):
+        oracle.tiled(d, np.zeros((16, 16), np.float32), interval=0)
+
+
+# --------------------------------------------------------------- feedback --
+
+@pytest.mark.parametrize("precision", ["f32", "f64"])
+@pytest.mark.parametrize("tiles", [(2, 2), (3, 4), (1, 2)])
+def test_feedback_against_fft_convolution(precision, tiles):
+    ny, nx = 36, 40
+    psf = asym_psf(2 * ny + 2, 2 * nx, 61)
+    r = rng(62, tiles[0], tiles[1])
+    res = r.normal(0, 1, (ny, nx)).astype(np.float32)
+    ty, tx = tiles
+    ct, ci, cf = [], [], []
+    for t in range(ty * tx):
+        tp = exact_clean.tile_pixels(ny, nx, ty, tx, t)
+        for _ in range(r.integers(0, 9)):
+            y, x = tp[r.integers(len(tp))]
+            ct.append(t)
+            ci.append(y * nx + x)
+            cf.append(r.uniform(-1, 1))
+    cf = np.asarray(cf, np.float32 if precision == "f32" else np.float64)
+    out = oracle.feedback(res, psf, tiles, ct, ci, cf, precision=precision)
+    expect = res.astype(np.float64).copy()
+    for t in range(ty * tx):
+        cimg = np.zeros(ny * nx)
+        for k in range(len(ci)):
+            if ct[k] == t:
+                cimg[ci[k]] += float(cf[k])
+        xc = model_conv(cimg.reshape(ny, nx), psf, ny, nx)
+        mask = np.ones((ny, nx), bool)
+        for (y, x) in exact_clean.tile_pixels(ny, nx, ty, tx, t):
+            mask[y, x] = False
+        expect[mask] -= xc[mask]
+    tol = 1e-4 if precision == "f32" else 1e-11
+    assert np.max(np.abs(out - expect)) < tol
+    # own-tile pixels are untouched by their own components: with only tile 0's
+    # components, tile 0 must come back bit-identical
+    sel = [k for k in range(len(ct)) if ct[k] == 0]
+    o0 = oracle.feedback(res, psf, tiles, [ct[k] for k in sel], [ci[k] for k in sel], cf[sel], precision)
+    for (y, x) in exact_clean.tile_pixels(ny, nx, ty, tx, 0):
+        assert o0[y, x] == res.astype(o0.dtype)[y, x]
+
+
+def test_feedback_rejects_components_outside_their_tile():
+    psf = asym_psf(16, 16, 71)
+    with pytest.raises(ValueError):
+        oracle.feedback(np.zeros((8, 8), np.float32), psf, (2, 2), [0], [7], np.ones(1, np.float32))
+
+
+# ---------------------------------------------------------- special cases --
+
+@pytest.mark.parametrize("precision", ["f32", "f64"])
+@pytest.mark.parametrize("interval", [1, 13, 1000])
+def test_one_tile_is_plain(precision, interval):
+    c = synth.make_config(0)
+    a = oracle.hogbom(c["dirty"], c["psf"], 0.1, 5e-3, 400, precision=precision)
+    b = oracle.tiled(c["dirty"], c["psf"], (1, 1), interval, 0.1, 5e-3, 400, precision=precision)
+    assert a["n_iter"] == b["n_iter"] and a["stop"] == b["stop"]
+    assert np.array_equal(a["idx"], b["idx"]) and np.array_equal(a["flux"], b["flux"])
+    assert np.array_equal(a["residual"], b["residual"]) and np.array_equal(a["model"], b["model"])
+
+
+@pytest.mark.parametrize("precision", ["f32", "f64"])
+def test_one_round_is_plain_on_each_cropped_tile(precision):
+    ny, nx = 30, 44
+    psf = asym_psf(2 * ny, 2 * nx, 81)
+    r = rng(82)
+    dirty = (r.normal(0, 0.05, (ny, nx)) + (r.random((ny, nx)) < 0.05) * r.uniform(-2, 2, (ny, nx)))
+    dirty = dirty.astype(np.float32)
+    tiles, per_tile = (2, 3), 40
+    T = tiles[0] * tiles[1]
+    out = oracle.tiled(dirty, psf, tiles, per_tile, 0.1, 0.0, T * per_tile, precision=precision)
+    assert out["n_rounds"] == 1
+    k = 0
+    for t in range(T):
+        i, j = divmod(t, tiles[1])
+        y0, y1 = i * ny // tiles[0], (i + 1) * ny // tiles[0]
+        x0, x1 = j * nx // tiles[1], (j + 1) * nx // tiles[1]
+        crop = np.ascontiguousarray(dirty[y0:y1, x0:x1])
+        p = oracle.hogbom(crop, psf, 0.1, 0.0, per_tile, precision=precision)
+        gy, gx = p["idx"] // (x1 - x0) + y0, p["idx"] % (x1 - x0) + x0
+        assert np.array_equal(out["idx"][k:k + per_tile], gy * nx + gx)
+        assert np.array_equal(out["flux"][k:k + per_tile], p["flux"])
+        k += per_tile
+
+
+def test_budget_split_of_the_last_round():
+    ny, nx = 24, 24
+    psf = asym_psf(48, 48, 91)
+    dirty = rng(92).normal(0, 1, (ny, nx)).astype(np.float32)
+    # 4 tiles, interval 10, 47 iterations: round 1 = 4 x 10, round 2 = 7 split 2,2,2,1
+    out = oracle.tiled(dirty, psf, (2, 2), 10, 0.1, 0.0, 47)
+    assert out["n_iter"] == 47 and out["n_rounds"] == 2
+    tile_of = lambda q: (q // nx >= 12) * 2 + (q % nx >= 12)
+    last = [tile_of(q) for q in out["idx"][40:]]
+    assert last == [0, 0, 1, 1, 2, 2, 3]
+
+
+def test_resume_continues_the_sequence():
+    c = synth.make_config(0)
+    full = oracle.hogbom(c["dirty"], c["psf"], 0.1, 0.0, 300)
+    a = oracle.hogbom(c["dirty"], c["psf"], 0.1, 0.0, 120)
+    b = oracle.hogbom(a["residual"], c["psf"], 0.1, 0.0, 180)
+    assert np.array_equal(full["idx"], np.concatenate([a["idx"], b["idx"]]))
+    assert np.array_equal(full["flux"], np.concatenate([a["flux"], b["flux"]]))
+    assert np.array_equal(full["residual"], b["residual"])
+
+
+def test_fp32_close_to_fp64_on_the_small_workload():
+    c = synth.make_config(0)
+    a = oracle.hogbom(c["dirty"], c["psf"], 0.1, 5e-3, 1000, precision="f32")
+    b = oracle.hogbom(c["dirty"], c["psf"], 0.1, 5e-3, 1000, precision="f64")
+    assert a["n_iter"] == b["n_iter"]
+    assert np.max(np.abs(a["model"] - b["model"])) < 1e-5
