@@ -90,7 +90,7 @@ typedef struct {
     int32_t flags;        /* CLEAN_FLAG_* bits                                    */
     int32_t wg_per_tile;  /* launch shape: workgroups per tile (0 = library pick) */
     int32_t px_per_thread;/* launch shape: residual pixels per thread, one of
-                             4, 8, 16, 32, 64, 128 (0 = library pick)              */
+                             4, 8, 16, 32, 64 (0 = library pick)              */
 } clean_params;
 
 typedef struct {
@@ -153,7 +153,7 @@ int clean_hogbom(const float *dirty, int ny, int nx,
  * its feedback, so residual + components (*) PSF = dirty holds at return.
  *
  *   comp_idx/comp_flux   order: round, then tile id, then local iteration.
- *   feedback_interval    1 .. 4096.
+ *   feedback_interval    1 .. 2048.
  *   tiles_y, tiles_x     1 .. ny (nx); at most 1024 tiles.
  * Other arguments as for clean_hogbom.  With tiles_y = tiles_x = 1 the result
  * equals clean_hogbom's bit for bit.

@@ -11,13 +11,16 @@
  * Algorithm Using Tiled Images with Feedback", arXiv 2501.01461), written out
  * in the order the paper gives it, with no blocking, fusion or reordering.
  *
- * Build: cc -O3 -mavx2 -mfma -ffp-contract=off -fno-fast-math -shared -fPIC
+ * Build: cc -O3 -mavx2 -mfma -ffp-contract=off -fno-fast-math -fopenmp -shared -fPIC
  *        (no contraction: every fused multiply-add below is an explicit fma).
+ *        OpenMP only splits loops whose iterations touch disjoint pixels with
+ *        unchanged per-pixel arithmetic, so any thread count gives the same
+ *        bits as one thread; the peak search stays a serial scan.
  *
  * Readings of points the paper leaves open (each also listed in the design
  * notes; the paper states none of them):
  *   - "highest intensity" is the largest |r|; the component keeps the signed
- *     value.  Ties go to the lowest row-major index (strict '>' in the scan).
+ *     value.  Ties go to the lowest row-major index.
  *   - component = fl(gain * v), one rounding in the working precision.
  *   - the PSF is at least twice the image on each axis, centred at
  *     (psf_ny/2, psf_nx/2); pixel q gets psf[q - p + centre] (no clipping).
@@ -58,18 +61,31 @@ static int check_common(int ny, int nx, int psf_ny, int psf_nx, double gain, dou
 /* ---------------------------------------------------------------- FP32 -- */
 
 /* Position of the highest |r| inside the rectangle [y0,y1) x [x0,x1) of a
- * row-major image of width nx, scanning in row-major order and replacing only
- * on a strictly larger value, so the lowest index wins a tie. */
+ * row-major image of width nx: the lowest row-major index whose |r| equals the
+ * largest |r| (so the lowest index wins a tie).  Two plain scans: the largest
+ * value, then the first pixel holding it.  |r| is compared through its bit
+ * pattern: with the sign bit cleared, IEEE-754 values order exactly as their
+ * bit patterns read as unsigned integers (NaN would rank above infinity; the
+ * inputs are finite). */
+static uint32_t abs_bits_f32(float v)
+{
+    uint32_t b;
+    memcpy(&b, &v, sizeof b);
+    return b & 0x7FFFFFFFu;
+}
+
 static int64_t peak_f32(const float *r, int nx, int y0, int y1, int x0, int x1)
 {
-    int64_t best = (int64_t)y0 * nx + x0;
-    float best_abs = fabsf(r[best]);
+    uint32_t best = 0;
     for (int y = y0; y < y1; ++y)
         for (int x = x0; x < x1; ++x) {
-            float a = fabsf(r[(int64_t)y * nx + x]);
-            if (a > best_abs) { best_abs = a; best = (int64_t)y * nx + x; }
+            uint32_t a = abs_bits_f32(r[(int64_t)y * nx + x]);
+            best = a > best ? a : best;
         }
-    return best;
+    for (int y = y0; y < y1; ++y)
+        for (int x = x0; x < x1; ++x)
+            if (abs_bits_f32(r[(int64_t)y * nx + x]) == best) return (int64_t)y * nx + x;
+    return (int64_t)y0 * nx + x0;   /* not reached */
 }
 
 /* r[q] -= c * PSF centred on p, for q in the rectangle (eq. 2 of Section 3). */
@@ -77,6 +93,7 @@ static void subtract_psf_f32(float *r, int nx, int y0, int y1, int x0, int x1, i
                              const float *psf, int psf_nx, int cy, int cx)
 {
     int py = (int)(p / nx), px = (int)(p % nx);
+#pragma omp parallel for schedule(static) if ((int64_t)(y1 - y0) * (x1 - x0) > 65536)
     for (int y = y0; y < y1; ++y) {
         const float *prow = psf + (int64_t)(y - py + cy) * psf_nx + (cx - px);
         float *rrow = r + (int64_t)y * nx;
@@ -122,22 +139,32 @@ int oracle_hogbom_f32(const float *dirty, int ny, int nx, const float *psf, int 
 
 /* ---------------------------------------------------------------- FP64 -- */
 
+static uint64_t abs_bits_f64(double v)
+{
+    uint64_t b;
+    memcpy(&b, &v, sizeof b);
+    return b & 0x7FFFFFFFFFFFFFFFull;
+}
+
 static int64_t peak_f64(const double *r, int nx, int y0, int y1, int x0, int x1)
 {
-    int64_t best = (int64_t)y0 * nx + x0;
-    double best_abs = fabs(r[best]);
+    uint64_t best = 0;
     for (int y = y0; y < y1; ++y)
         for (int x = x0; x < x1; ++x) {
-            double a = fabs(r[(int64_t)y * nx + x]);
-            if (a > best_abs) { best_abs = a; best = (int64_t)y * nx + x; }
+            uint64_t a = abs_bits_f64(r[(int64_t)y * nx + x]);
+            best = a > best ? a : best;
         }
-    return best;
+    for (int y = y0; y < y1; ++y)
+        for (int x = x0; x < x1; ++x)
+            if (abs_bits_f64(r[(int64_t)y * nx + x]) == best) return (int64_t)y * nx + x;
+    return (int64_t)y0 * nx + x0;   /* not reached */
 }
 
 static void subtract_psf_f64(double *r, int nx, int y0, int y1, int x0, int x1, int64_t p, double c,
                              const float *psf, int psf_nx, int cy, int cx)
 {
     int py = (int)(p / nx), px = (int)(p % nx);
+#pragma omp parallel for schedule(static) if ((int64_t)(y1 - y0) * (x1 - x0) > 65536)
     for (int y = y0; y < y1; ++y) {
         const float *prow = psf + (int64_t)(y - py + cy) * psf_nx + (cx - px);
         double *rrow = r + (int64_t)y * nx;
@@ -254,6 +281,7 @@ static int feedback_f32(float *r, int ny, int nx, int ty, int tx, const float *p
     /* step 2: subtract the sum of the other tiles' cross-coupling images */
     for (int s = 0; s < ntiles; ++s) {
         rect own = tile_rect(ny, nx, ty, tx, s);
+#pragma omp parallel for schedule(dynamic, 4) if (npix > 65536)
         for (int y = own.y0; y < own.y1; ++y)
             for (int x = own.x0; x < own.x1; ++x) {
                 float acc = 0.0f;
@@ -296,6 +324,7 @@ static int feedback_f64(double *r, int ny, int nx, int ty, int tx, const float *
     start[ntiles] = nnz;
     for (int s = 0; s < ntiles; ++s) {
         rect own = tile_rect(ny, nx, ty, tx, s);
+#pragma omp parallel for schedule(dynamic, 4) if (npix > 65536)
         for (int y = own.y0; y < own.y1; ++y)
             for (int x = own.x0; x < own.x1; ++x) {
                 double acc = 0.0;

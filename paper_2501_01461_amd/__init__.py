@@ -1,0 +1,7 @@
+"""MI355X (gfx950) Hogbom CLEAN and tiled CLEAN with feedback.
+
+The compute runs in ``libclean.so`` (HIP kernels behind a C ABI, include/clean.h);
+``_native`` is its thin ctypes binding and ``synth`` the seeded input generator.
+"""
+from ._native import (CleanError, hogbom, load, psf_to_f16, tiled_feedback,  # noqa: F401
+                      version)

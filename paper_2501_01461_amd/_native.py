@@ -1,0 +1,186 @@
+"""ctypes binding of the gfx950 CLEAN library (libclean.so).
+
+Argument marshalling only: torch CUDA tensors supply device memory and the
+current stream; every step of the computation runs in the library's kernels.
+There is no CPU fallback: if the library is missing or no GPU is present the
+calls raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libclean.so")
+
+CLEAN_OK = 0
+STATUS = {0: "CLEAN_OK", -1: "CLEAN_E_INVAL", -2: "CLEAN_E_NONFINITE", -3: "CLEAN_E_NOMEM",
+          -4: "CLEAN_E_HIP", -5: "CLEAN_E_TIMEOUT", -6: "CLEAN_E_UNSUPPORTED"}
+STOP_NAMES = {0: "maxiter", 1: "threshold", 2: "capacity"}
+PSF_F32, PSF_F16 = 0, 1
+FLAG_CHECK_FINITE = 1
+
+# every symbol include/clean.h declares
+EXPORTS = ("clean_hogbom", "clean_tiled_feedback", "clean_batched", "clean_workspace_size",
+           "clean_psf_to_f16", "clean_strerror", "clean_last_error", "clean_version")
+
+
+class Params(C.Structure):
+    _fields_ = [("gain", C.c_double), ("threshold", C.c_double), ("max_iter", C.c_int64),
+                ("psf_dtype", C.c_int32), ("flags", C.c_int32), ("wg_per_tile", C.c_int32),
+                ("px_per_thread", C.c_int32)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("n_iter", C.c_int64), ("stop_reason", C.c_int32), ("n_rounds", C.c_int32),
+                ("final_peak", C.c_double), ("residual_rms", C.c_double), ("model_flux", C.c_double),
+                ("device_ms", C.c_float), ("wg_per_tile", C.c_int32), ("px_per_thread", C.c_int32),
+                ("workgroups", C.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class Problem(C.Structure):
+    _fields_ = [("dirty", C.c_void_p), ("psf", C.c_void_p), ("residual", C.c_void_p),
+                ("comp_idx", C.c_void_p), ("comp_flux", C.c_void_p), ("model", C.c_void_p),
+                ("comp_cap", C.c_int64), ("max_iter", C.c_int64), ("threshold", C.c_double),
+                ("ny", C.c_int32), ("nx", C.c_int32), ("psf_ny", C.c_int32), ("psf_nx", C.c_int32)]
+
+
+class CleanError(RuntimeError):
+    def __init__(self, status, detail):
+        super().__init__(f"{STATUS.get(status, status)}: {detail}")
+        self.status = status
+
+
+_lib = None
+
+
+def load():
+    """Load libclean.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it first (python -m paper_2501_01461_amd.build)")
+    lib = C.CDLL(LIB_PATH)
+    P, i32, i64, sz = C.c_void_p, C.c_int, C.c_int64, C.c_size_t
+    lib.clean_hogbom.argtypes = [P, i32, i32, P, i32, i32, C.POINTER(Params), P, P, P, i64, P, P, sz,
+                                 C.POINTER(Stats), P]
+    lib.clean_tiled_feedback.argtypes = [P, i32, i32, P, i32, i32, i32, i32, i32, C.POINTER(Params), P, P, P,
+                                         i64, P, P, sz, C.POINTER(Stats), P]
+    lib.clean_batched.argtypes = [C.POINTER(Problem), i32, C.POINTER(Params), C.POINTER(Stats), P]
+    lib.clean_workspace_size.argtypes = [i32, i32, i32, i32, i32, C.POINTER(Params)]
+    lib.clean_workspace_size.restype = sz
+    lib.clean_psf_to_f16.argtypes = [P, P, i64, P]
+    for f in (lib.clean_hogbom, lib.clean_tiled_feedback, lib.clean_batched, lib.clean_psf_to_f16):
+        f.restype = C.c_int
+    lib.clean_strerror.argtypes = [C.c_int]
+    lib.clean_strerror.restype = C.c_char_p
+    lib.clean_last_error.restype = C.c_char_p
+    lib.clean_version.restype = C.c_char_p
+    _lib = lib
+    return lib
+
+
+def _check(status):
+    if status != CLEAN_OK:
+        raise CleanError(status, load().clean_last_error().decode())
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("no GPU: the CLEAN library runs only on the device")
+    return torch
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream():
+    torch = _torch()
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _params(gain, threshold, max_iter, psf, flags, wg_per_tile, px_per_thread):
+    torch = _torch()
+    if psf.dtype == torch.float16:
+        dt = PSF_F16
+    elif psf.dtype == torch.float32:
+        dt = PSF_F32
+    else:
+        raise TypeError("psf must be float32 or float16")
+    return Params(float(gain), float(threshold), int(max_iter), dt, int(flags), int(wg_per_tile),
+                  int(px_per_thread))
+
+
+def _prep(dirty, psf):
+    torch = _torch()
+    if dirty.dtype != torch.float32 or dirty.dim() != 2 or psf.dim() != 2:
+        raise TypeError("dirty must be 2-D float32; psf 2-D float32/float16")
+    if not (dirty.is_cuda and psf.is_cuda):
+        raise TypeError("dirty and psf must be device tensors")
+    return dirty.contiguous(), psf.contiguous()
+
+
+def _outputs(dirty, cap, model):
+    torch = _torch()
+    ny, nx = dirty.shape
+    dev = dirty.device
+    res = torch.empty((ny, nx), dtype=torch.float32, device=dev)
+    idx = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
+    flux = torch.empty(max(cap, 1), dtype=torch.float32, device=dev)
+    mod = torch.empty((ny, nx), dtype=torch.float64, device=dev) if model else None
+    return res, idx, flux, mod
+
+
+def hogbom(dirty, psf, gain=0.1, threshold=0.0, max_iter=1000, cap=None, model=True, check_finite=False,
+           wg_per_tile=0, px_per_thread=0, out=None):
+    """Plain Hogbom CLEAN; returns dict(residual, idx, flux, model, stats)."""
+    lib = load()
+    dirty, psf = _prep(dirty, psf)
+    cap = int(max_iter if cap is None else cap)
+    res, idx, flux, mod = out if out is not None else _outputs(dirty, cap, model)
+    p = _params(gain, threshold, max_iter, psf, FLAG_CHECK_FINITE if check_finite else 0, wg_per_tile,
+                px_per_thread)
+    st = Stats()
+    ny, nx = dirty.shape
+    _check(lib.clean_hogbom(_ptr(dirty), ny, nx, _ptr(psf), psf.shape[0], psf.shape[1], C.byref(p), _ptr(res),
+                            _ptr(idx), _ptr(flux), cap, _ptr(mod), None, 0, C.byref(st), _stream()))
+    n = st.n_iter
+    return dict(residual=res, idx=idx[:n], flux=flux[:n], model=mod, stats=st.as_dict())
+
+
+def tiled_feedback(dirty, psf, tiles=(2, 2), interval=100, gain=0.1, threshold=0.0, max_iter=1000, cap=None,
+                   model=True, check_finite=False, wg_per_tile=0, px_per_thread=0, out=None):
+    """Tiled Hogbom CLEAN with feedback; returns dict(residual, idx, flux, model, stats)."""
+    lib = load()
+    dirty, psf = _prep(dirty, psf)
+    cap = int(max_iter if cap is None else cap)
+    res, idx, flux, mod = out if out is not None else _outputs(dirty, cap, model)
+    p = _params(gain, threshold, max_iter, psf, FLAG_CHECK_FINITE if check_finite else 0, wg_per_tile,
+                px_per_thread)
+    st = Stats()
+    ny, nx = dirty.shape
+    _check(lib.clean_tiled_feedback(_ptr(dirty), ny, nx, _ptr(psf), psf.shape[0], psf.shape[1], int(tiles[0]),
+                                    int(tiles[1]), int(interval), C.byref(p), _ptr(res), _ptr(idx), _ptr(flux), cap,
+                                    _ptr(mod), None, 0, C.byref(st), _stream()))
+    n = st.n_iter
+    return dict(residual=res, idx=idx[:n], flux=flux[:n], model=mod, stats=st.as_dict())
+
+
+def psf_to_f16(psf):
+    """FP32 -> FP16 (round to nearest even) on the device."""
+    torch = _torch()
+    lib = load()
+    psf = psf.contiguous()
+    out = torch.empty(psf.shape, dtype=torch.float16, device=psf.device)
+    _check(lib.clean_psf_to_f16(_ptr(psf), _ptr(out), psf.numel(), _stream()))
+    return out
+
+
+def version():
+    return load().clean_version().decode()

@@ -1,0 +1,524 @@
+// clean_api.hip -- host entry points of the CLEAN library (the C ABI declared
+// in include/clean.h): argument checks, workspace, launch shape, workgroup
+// placement over the XCDs, cooperative launch, statistics.
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "clean.h"
+#include "clean_device.h"
+
+namespace cleanhip {
+template <int K, int V, typename PT> __global__ void hogbom_kernel(const KArgs a);
+template <int K, int V, typename PT> __global__ void tiled_kernel(const KArgs a);
+__global__ void finite_check_kernel(const float *x, int64_t n, uint32_t *flag);
+__global__ void finite_check_half_kernel(const unsigned short *x, int64_t n, uint32_t *flag);
+__global__ void to_half_kernel(const float *x, unsigned short *y, int64_t n);
+__global__ void finalize_kernel(const double *partial, int n, DevStat *st);
+} // namespace cleanhip
+
+using namespace cleanhip;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+#define HIPCHK(call)                                                                       \
+    do {                                                                                   \
+        hipError_t e_ = (call);                                                            \
+        if (e_ != hipSuccess)                                                              \
+            return fail(CLEAN_E_HIP, "%s failed: %s", #call, hipGetErrorString(e_));       \
+    } while (0)
+
+// ------------------------------------------------------------ workspace --
+
+struct Workspace {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+};
+std::mutex g_ws_mu;
+Workspace g_ws[64];
+
+int internal_workspace(int dev, size_t need, void **out)
+{
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    if (dev < 0 || dev >= 64) return fail(CLEAN_E_INVAL, "device %d out of range", dev);
+    Workspace &w = g_ws[dev];
+    if (w.bytes < need) {
+        if (w.ptr) {
+            (void)hipDeviceSynchronize();
+            (void)hipFree(w.ptr);
+            w.ptr = nullptr;
+            w.bytes = 0;
+        }
+        size_t sz = std::max(need, (size_t)1 << 20);
+        if (hipMalloc(&w.ptr, sz) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(CLEAN_E_NOMEM, "workspace allocation of %zu bytes failed", sz);
+        }
+        w.bytes = sz;
+    }
+    *out = w.ptr;
+    return CLEAN_OK;
+}
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// Layout of one call's workspace.  The header part (control block, stats,
+// exchange slots, tile keys, counts) is cleared before each launch.
+struct Layout {
+    size_t ctl, dstat, xslots, tile_key, rb_n, ag_n, header_end;
+    size_t role, rb_idx, rb_flux, ag_pos, ag_flux, accbuf, partial, total;
+};
+
+Layout make_layout(int T, int cs, int slot_pad, int interval, int W, int64_t npix, bool tiled)
+{
+    Layout L{};
+    size_t o = 0;
+    L.ctl = o;       o = align_up(o + sizeof(DevCtl), 256);
+    L.dstat = o;     o = align_up(o + sizeof(DevStat), 256);
+    L.xslots = o;    o = align_up(o + (size_t)T * 2 * slot_pad * 8, 256);
+    L.tile_key = o;  o = align_up(o + (size_t)T * 8, 256);
+    L.rb_n = o;      o = align_up(o + (size_t)T * 4, 256);
+    L.ag_n = o;      o = align_up(o + (size_t)T * 4, 256);
+    L.header_end = o;
+    L.role = o;      o = align_up(o + (size_t)W * 4, 256);
+    const size_t list = tiled ? (size_t)T * interval * 4 : 0;
+    L.rb_idx = o;    o = align_up(o + list, 256);
+    L.rb_flux = o;   o = align_up(o + list, 256);
+    L.ag_pos = o;    o = align_up(o + list, 256);
+    L.ag_flux = o;   o = align_up(o + list, 256);
+    L.accbuf = o;    o = align_up(o + (tiled ? (size_t)npix * 4 : 0), 256);
+    L.partial = o;   o = align_up(o + (size_t)T * cs * 8, 256);
+    L.total = o;
+    return L;
+}
+
+// ---------------------------------------------------------- kernel table --
+
+using KFn = void (*)(const KArgs);
+
+template <int V, typename PT> KFn plain_fn(int K)
+{
+    if constexpr (V == 4) {
+        switch (K) {
+        case 1: return hogbom_kernel<1, 4, PT>;
+        case 2: return hogbom_kernel<2, 4, PT>;
+        case 4: return hogbom_kernel<4, 4, PT>;
+        case 8: return hogbom_kernel<8, 4, PT>;
+        case 16: return hogbom_kernel<16, 4, PT>;
+        }
+    } else {
+        switch (K) {
+        case 4: return hogbom_kernel<4, 1, PT>;
+        case 16: return hogbom_kernel<16, 1, PT>;
+        case 64: return hogbom_kernel<64, 1, PT>;
+        }
+    }
+    return nullptr;
+}
+
+template <int V, typename PT> KFn tiled_fn(int K)
+{
+    if constexpr (V == 4) {
+        switch (K) {
+        case 1: return tiled_kernel<1, 4, PT>;
+        case 2: return tiled_kernel<2, 4, PT>;
+        case 4: return tiled_kernel<4, 4, PT>;
+        case 8: return tiled_kernel<8, 4, PT>;
+        case 16: return tiled_kernel<16, 4, PT>;
+        }
+    } else {
+        switch (K) {
+        case 4: return tiled_kernel<4, 1, PT>;
+        case 16: return tiled_kernel<16, 1, PT>;
+        case 64: return tiled_kernel<64, 1, PT>;
+        }
+    }
+    return nullptr;
+}
+
+KFn pick(bool tiled, bool half, int V, int K)
+{
+    if (tiled) {
+        if (V == 4) return half ? tiled_fn<4, __half>(K) : tiled_fn<4, float>(K);
+        return half ? tiled_fn<1, __half>(K) : tiled_fn<1, float>(K);
+    }
+    if (V == 4) return half ? plain_fn<4, __half>(K) : plain_fn<4, float>(K);
+    return half ? plain_fn<1, __half>(K) : plain_fn<1, float>(K);
+}
+
+bool valid_ppt(int V, int ppt)
+{
+    if (V == 4) return ppt == 4 || ppt == 8 || ppt == 16 || ppt == 32 || ppt == 64;
+    return ppt == 4 || ppt == 16 || ppt == 64;
+}
+
+// Launch shape for a tile of npix pixels: workgroups per cluster (cs) and
+// pixels per thread (ppt = K*V).  Small clusters keep the per-iteration
+// exchange short; the pixels per thread bound each workgroup's PSF traffic.
+int choose_shape(int64_t npix, int V, int user_cs, int user_ppt, int &cs, int &ppt)
+{
+    if (user_ppt) {
+        if (!valid_ppt(V, user_ppt))
+            return fail(CLEAN_E_INVAL, "px_per_thread %d not available (tile width %s a multiple of 4)", user_ppt,
+                        V == 4 ? "is" : "is not");
+        ppt = user_ppt;
+        cs = user_cs ? user_cs : (int)((npix + (int64_t)WG * ppt - 1) / ((int64_t)WG * ppt));
+    } else if (user_cs) {
+        cs = user_cs;
+        const int opts4[] = {4, 8, 16, 32, 64}, opts1[] = {4, 16, 64};
+        const int *opts = V == 4 ? opts4 : opts1;
+        const int nopt = V == 4 ? 5 : 3;
+        ppt = opts[nopt - 1];
+        for (int i = 0; i < nopt; ++i)
+            if ((int64_t)cs * WG * opts[i] >= npix) { ppt = opts[i]; break; }
+    } else {
+        const int opts4[] = {4, 8, 16, 32, 64}, opts1[] = {4, 16, 64};
+        const int *opts = V == 4 ? opts4 : opts1;
+        const int nopt = V == 4 ? 5 : 3;
+        // smallest ppt up to 32 that fits one workgroup, else 32 px/thread with
+        // as many workgroups as needed, growing ppt when clusters get large
+        ppt = 0;
+        for (int i = 0; i < nopt; ++i)
+            if ((int64_t)WG * opts[i] >= npix && opts[i] <= 64) { ppt = opts[i]; cs = 1; break; }
+        if (!ppt) {
+            ppt = V == 4 ? 32 : 16;
+            cs = (int)((npix + (int64_t)WG * ppt - 1) / ((int64_t)WG * ppt));
+            while (cs > 16 && ppt < opts[nopt - 1]) {
+                for (int i = 0; i < nopt; ++i)
+                    if (opts[i] > ppt) { ppt = opts[i]; break; }
+                cs = (int)((npix + (int64_t)WG * ppt - 1) / ((int64_t)WG * ppt));
+            }
+        }
+    }
+    if ((int64_t)cs * WG * ppt < npix)
+        return fail(CLEAN_E_INVAL, "launch shape %d workgroups x %d px/thread cannot hold %lld pixels", cs, ppt,
+                    (long long)npix);
+    if (cs < 1 || cs > 4096) return fail(CLEAN_E_UNSUPPORTED, "cluster of %d workgroups not supported", cs);
+    return CLEAN_OK;
+}
+
+int device_timeout_ticks(int dev, uint64_t &ticks)
+{
+    int khz = 0;
+    HIPCHK(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
+    if (khz <= 0) khz = 100000;
+    ticks = (uint64_t)khz * 1000ull * 20ull;     // 20 seconds per wait
+    return CLEAN_OK;
+}
+
+int check_common(const float *dirty, int ny, int nx, const void *psf, int psf_ny, int psf_nx, const clean_params *p,
+                 float *residual, int32_t *comp_idx, float *comp_flux, int64_t comp_cap)
+{
+    if (!p) return fail(CLEAN_E_INVAL, "params is NULL");
+    if (!dirty || !psf || !residual) return fail(CLEAN_E_INVAL, "dirty, psf and residual must be non-NULL");
+    if (comp_cap > 0 && (!comp_idx || !comp_flux)) return fail(CLEAN_E_INVAL, "component arrays are NULL");
+    if (ny <= 0 || nx <= 0) return fail(CLEAN_E_INVAL, "image size %d x %d", ny, nx);
+    if ((int64_t)ny * nx > (1ll << 28) - 1) return fail(CLEAN_E_UNSUPPORTED, "image of %lld pixels exceeds 2^28-1", (long long)ny * nx);
+    if (psf_ny < 2 * (int64_t)ny || psf_nx < 2 * (int64_t)nx)
+        return fail(CLEAN_E_INVAL, "PSF %d x %d must be at least twice the image %d x %d", psf_ny, psf_nx, ny, nx);
+    const uint64_t es = p->psf_dtype == CLEAN_PSF_F16 ? 2 : 4;
+    if ((uint64_t)psf_ny * psf_nx * es > (1ull << 34)) return fail(CLEAN_E_UNSUPPORTED, "PSF larger than 16 GiB");
+    if ((int64_t)ny * psf_nx + nx >= (1ll << 31) / (int64_t)es)
+        return fail(CLEAN_E_UNSUPPORTED, "image x PSF row length too large for 32-bit offsets");
+    if (!(p->gain > 0.0 && p->gain <= 1.0)) return fail(CLEAN_E_INVAL, "gain %g not in (0, 1]", p->gain);
+    if (!(p->threshold >= 0.0)) return fail(CLEAN_E_INVAL, "threshold %g < 0", p->threshold);
+    if (p->max_iter < 0) return fail(CLEAN_E_INVAL, "max_iter %lld < 0", (long long)p->max_iter);
+    if (comp_cap < 0) return fail(CLEAN_E_INVAL, "comp_cap < 0");
+    if (p->psf_dtype != CLEAN_PSF_F32 && p->psf_dtype != CLEAN_PSF_F16)
+        return fail(CLEAN_E_INVAL, "psf_dtype %d", p->psf_dtype);
+    if (p->wg_per_tile < 0 || p->px_per_thread < 0) return fail(CLEAN_E_INVAL, "negative launch shape");
+    return CLEAN_OK;
+}
+
+// Shared driver of the plain and tiled forms.
+int run(bool tiled, const float *dirty, int ny, int nx, const void *psf, int psf_ny, int psf_nx, int tiles_y,
+        int tiles_x, int interval, const clean_params *p, float *residual, int32_t *comp_idx, float *comp_flux,
+        int64_t comp_cap, double *model, void *workspace, size_t workspace_bytes, clean_stats *stats,
+        void *stream_v)
+{
+    int st = check_common(dirty, ny, nx, psf, psf_ny, psf_nx, p, residual, comp_idx, comp_flux, comp_cap);
+    if (st) return st;
+    if (tiled) {
+        if (tiles_y < 1 || tiles_x < 1 || tiles_y > ny || tiles_x > nx)
+            return fail(CLEAN_E_INVAL, "tile grid %d x %d for a %d x %d image", tiles_y, tiles_x, ny, nx);
+        if ((int64_t)tiles_y * tiles_x > MAX_TILES)
+            return fail(CLEAN_E_UNSUPPORTED, "%d tiles exceed %d", tiles_y * tiles_x, MAX_TILES);
+        if (interval < 1 || interval > MAX_INTERVAL)
+            return fail(CLEAN_E_INVAL, "feedback interval %d not in [1, %d]", interval, MAX_INTERVAL);
+    } else {
+        tiles_y = tiles_x = 1;
+        interval = 1;
+    }
+    hipStream_t stream = (hipStream_t)stream_v;
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    int ncu = 0;
+    HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+
+    const int T = tiles_y * tiles_x;
+    // tile geometry: widths all multiples of 4 allow 4-wide pixel groups
+    int64_t max_tile = 0;
+    bool w4 = true;
+    for (int i = 0; i < tiles_y; ++i)
+        for (int j = 0; j < tiles_x; ++j) {
+            const int h = (int)((int64_t)(i + 1) * ny / tiles_y - (int64_t)i * ny / tiles_y);
+            const int w = (int)((int64_t)(j + 1) * nx / tiles_x - (int64_t)j * nx / tiles_x);
+            max_tile = std::max<int64_t>(max_tile, (int64_t)h * w);
+            if (w % 4) w4 = false;
+        }
+    const int V = w4 ? 4 : 1;
+    int cs = 0, ppt = 0;
+    st = choose_shape(max_tile, V, p->wg_per_tile, p->px_per_thread, cs, ppt);
+    if (st) return st;
+    const int K = ppt / V;
+    const bool half = p->psf_dtype == CLEAN_PSF_F16;
+    KFn fn = pick(tiled, half, V, K);
+    if (!fn) return fail(CLEAN_E_UNSUPPORTED, "no kernel for %d x %d pixels per thread", K, V);
+
+    const size_t dyn_lds = tiled ? std::max((size_t)16 * interval, (size_t)8 * GATHER_CHUNK) : 0;
+    int occ = 0;
+    HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void *)fn, WG, dyn_lds));
+    const int max_wg = occ * ncu;
+
+    // placement: cluster c lives on XCD c % 8 (workgroup b runs on XCD b % 8)
+    int W;
+    std::vector<int32_t> role;
+    if (!tiled) {
+        W = cs;
+        if (W > max_wg) return fail(CLEAN_E_UNSUPPORTED, "%d workgroups cannot be co-resident (max %d)", W, max_wg);
+        role.resize(W);
+        for (int b = 0; b < W; ++b) role[b] = b;
+    } else {
+        std::vector<int> need(8, 0);
+        for (int c = 0; c < T; ++c) need[c % 8] += cs;
+        int per_xcd = *std::max_element(need.begin(), need.end());
+        W = 8 * per_xcd;
+        const int helpers_target = std::min(max_wg, 2 * ncu);   // workgroups for the feedback gather
+        if (W < helpers_target) W = helpers_target / 8 * 8;
+        if (W > max_wg) {
+            // fall back to packing clusters without XCD affinity
+            W = T * cs;
+            if (W > max_wg) return fail(CLEAN_E_UNSUPPORTED, "%d workgroups cannot be co-resident (max %d)", W, max_wg);
+            role.assign(W, -1);
+            for (int c = 0; c < T; ++c)
+                for (int g = 0; g < cs; ++g) role[c * cs + g] = (c << 16) | g;
+        } else {
+            per_xcd = W / 8;
+            role.assign(W, -1);
+            std::vector<int> fill(8, 0);
+            for (int c = 0; c < T; ++c) {
+                const int x = c % 8;
+                for (int g = 0; g < cs; ++g) {
+                    const int j = fill[x]++;
+                    role[x + 8 * j] = (c << 16) | g;
+                }
+            }
+        }
+    }
+
+    const int slot_pad = (cs + 31) / 32 * 32;
+    const int64_t npix = (int64_t)ny * nx;
+    const Layout L = make_layout(T, cs, slot_pad, interval, W, npix, tiled);
+    char *ws = (char *)workspace;
+    if (ws) {
+        if (workspace_bytes < L.total)
+            return fail(CLEAN_E_NOMEM, "workspace of %zu bytes < %zu needed", workspace_bytes, L.total);
+    } else {
+        void *wp = nullptr;
+        st = internal_workspace(dev, L.total, &wp);
+        if (st) return st;
+        ws = (char *)wp;
+    }
+
+    KArgs a{};
+    a.dirty = dirty;
+    a.residual = residual;
+    a.model = model;
+    a.psf = psf;
+    a.psf_bytes = (uint64_t)psf_ny * psf_nx * (half ? 2 : 4);
+    a.ny = ny; a.nx = nx; a.psf_ny = psf_ny; a.psf_nx = psf_nx;
+    a.cy = psf_ny / 2; a.cx = psf_nx / 2;
+    a.ty = tiles_y; a.tx = tiles_x; a.T = T;
+    a.cs = cs;
+    a.slot_pad = slot_pad;
+    a.interval = interval;
+    a.gather_parts = std::max(1, W / T);
+    a.gain = (float)p->gain;
+    a.threshold = p->threshold;
+    a.max_iter = p->max_iter;
+    a.cap = comp_cap;
+    st = device_timeout_ticks(dev, a.timeout_ticks);
+    if (st) return st;
+    a.comp_idx = comp_idx;
+    a.comp_flux = comp_flux;
+    a.ctl = (DevCtl *)(ws + L.ctl);
+    a.dstat = (DevStat *)(ws + L.dstat);
+    a.role = (const int32_t *)(ws + L.role);
+    a.xslots = (uint64_t *)(ws + L.xslots);
+    a.tile_key = (uint64_t *)(ws + L.tile_key);
+    a.rb_idx = (int32_t *)(ws + L.rb_idx);
+    a.rb_flux = (float *)(ws + L.rb_flux);
+    a.rb_n = (int32_t *)(ws + L.rb_n);
+    a.ag_pos = (int32_t *)(ws + L.ag_pos);
+    a.ag_flux = (float *)(ws + L.ag_flux);
+    a.ag_n = (int32_t *)(ws + L.ag_n);
+    a.accbuf = (float *)(ws + L.accbuf);
+    a.partial = (double *)(ws + L.partial);
+
+    HIPCHK(hipMemsetAsync(ws, 0, L.header_end, stream));
+    HIPCHK(hipMemcpyAsync(ws + L.role, role.data(), role.size() * 4, hipMemcpyHostToDevice, stream));
+    if (p->flags & CLEAN_FLAG_CHECK_FINITE) {
+        uint32_t *flag = &a.ctl->finite_bad;
+        hipLaunchKernelGGL(finite_check_kernel, dim3(1024), dim3(256), 0, stream, dirty, npix, flag);
+        if (half)
+            hipLaunchKernelGGL(finite_check_half_kernel, dim3(1024), dim3(256), 0, stream,
+                               (const unsigned short *)psf, (int64_t)psf_ny * psf_nx, flag);
+        else
+            hipLaunchKernelGGL(finite_check_kernel, dim3(1024), dim3(256), 0, stream, (const float *)psf,
+                               (int64_t)psf_ny * psf_nx, flag);
+        HIPCHK(hipGetLastError());
+        uint32_t bad = 0;
+        HIPCHK(hipMemcpyAsync(&bad, flag, 4, hipMemcpyDeviceToHost, stream));
+        HIPCHK(hipStreamSynchronize(stream));
+        if (bad) return fail(CLEAN_E_NONFINITE, "non-finite value in the dirty image or PSF");
+    }
+
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    HIPCHK(hipEventRecord(e0, stream));
+    void *args[] = {(void *)&a};
+    hipError_t le = hipLaunchCooperativeKernel((const void *)fn, dim3(W), dim3(WG), args, (unsigned)dyn_lds, stream);
+    if (le != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        return fail(CLEAN_E_HIP, "cooperative launch of %d x %d failed: %s", W, WG, hipGetErrorString(le));
+    }
+    HIPCHK(hipEventRecord(e1, stream));
+    hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(64), 0, stream, a.partial, T * cs, a.dstat);
+    HIPCHK(hipGetLastError());
+    DevStat ds{};
+    DevCtl ctl{};
+    HIPCHK(hipMemcpyAsync(&ds, a.dstat, sizeof ds, hipMemcpyDeviceToHost, stream));
+    HIPCHK(hipMemcpyAsync(&ctl, a.ctl, sizeof ctl, hipMemcpyDeviceToHost, stream));
+    HIPCHK(hipStreamSynchronize(stream));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (ctl.abort & ABORT_TIMEOUT) return fail(CLEAN_E_TIMEOUT, "a device-side wait timed out");
+    if (ctl.abort) return fail(CLEAN_E_HIP, "device abort code %u", ctl.abort);
+    if (stats) {
+        stats->n_iter = ds.n_iter;
+        stats->stop_reason = ds.stop;
+        stats->n_rounds = ds.n_rounds;
+        stats->final_peak = ds.final_peak;
+        stats->residual_rms = std::sqrt(ds.sumsq / (double)npix);
+        stats->model_flux = ds.model_flux;
+        stats->device_ms = ms;
+        stats->wg_per_tile = cs;
+        stats->px_per_thread = ppt;
+        stats->workgroups = W;
+    }
+    return CLEAN_OK;
+}
+
+} // namespace
+
+extern "C" {
+
+int clean_hogbom(const float *dirty, int ny, int nx, const void *psf, int psf_ny, int psf_nx, const clean_params *p,
+                 float *residual, int32_t *comp_idx, float *comp_flux, int64_t comp_cap, double *model,
+                 void *workspace, size_t workspace_bytes, clean_stats *stats, void *stream)
+{
+    g_last_error.clear();
+    return run(false, dirty, ny, nx, psf, psf_ny, psf_nx, 1, 1, 1, p, residual, comp_idx, comp_flux, comp_cap, model,
+               workspace, workspace_bytes, stats, stream);
+}
+
+int clean_tiled_feedback(const float *dirty, int ny, int nx, const void *psf, int psf_ny, int psf_nx, int tiles_y,
+                         int tiles_x, int feedback_interval, const clean_params *p, float *residual,
+                         int32_t *comp_idx, float *comp_flux, int64_t comp_cap, double *model, void *workspace,
+                         size_t workspace_bytes, clean_stats *stats, void *stream)
+{
+    g_last_error.clear();
+    return run(true, dirty, ny, nx, psf, psf_ny, psf_nx, tiles_y, tiles_x, feedback_interval, p, residual, comp_idx,
+               comp_flux, comp_cap, model, workspace, workspace_bytes, stats, stream);
+}
+
+int clean_batched(const clean_problem *probs, int n, const clean_params *shared, clean_stats *stats, void *stream)
+{
+    g_last_error.clear();
+    (void)probs; (void)n; (void)shared; (void)stats; (void)stream;
+    return fail(CLEAN_E_UNSUPPORTED, "clean_batched is not built yet");
+}
+
+size_t clean_workspace_size(int ny, int nx, int tiles_y, int tiles_x, int feedback_interval, const clean_params *p)
+{
+    if (!p || ny <= 0 || nx <= 0 || tiles_y < 1 || tiles_x < 1 || tiles_y > ny || tiles_x > nx) return 0;
+    const bool tiled = !(tiles_y == 1 && tiles_x == 1);
+    const int T = tiles_y * tiles_x;
+    if (T > MAX_TILES) return 0;
+    if (tiled && (feedback_interval < 1 || feedback_interval > MAX_INTERVAL)) return 0;
+    // an upper bound over the launch shapes the library may pick
+    const int64_t npix = (int64_t)ny * nx;
+    const int cs_max = 4096;
+    const int W_max = 8192;
+    const Layout L = make_layout(T, tiled ? cs_max / T + 64 : cs_max, (cs_max + 31) / 32 * 32,
+                                 tiled ? feedback_interval : 1, W_max, npix, tiled);
+    return L.total;
+}
+
+int clean_psf_to_f16(const float *psf, uint16_t *out, int64_t n, void *stream_v)
+{
+    g_last_error.clear();
+    if (!psf || !out || n < 0) return fail(CLEAN_E_INVAL, "bad arguments");
+    hipStream_t stream = (hipStream_t)stream_v;
+    if (n == 0) return CLEAN_OK;
+    hipLaunchKernelGGL(to_half_kernel, dim3(2048), dim3(256), 0, stream, psf, (unsigned short *)out, n);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(stream));
+    return CLEAN_OK;
+}
+
+const char *clean_strerror(int status)
+{
+    switch (status) {
+    case CLEAN_OK: return "ok";
+    case CLEAN_E_INVAL: return "invalid argument";
+    case CLEAN_E_NONFINITE: return "non-finite input";
+    case CLEAN_E_NOMEM: return "out of device memory or workspace too small";
+    case CLEAN_E_HIP: return "HIP runtime error";
+    case CLEAN_E_TIMEOUT: return "device-side wait timed out";
+    case CLEAN_E_UNSUPPORTED: return "unsupported shape or option";
+    }
+    return "unknown status";
+}
+
+const char *clean_last_error(void) { return g_last_error.c_str(); }
+
+const char *clean_version(void) { return "cleanhip 0.1.0 (gfx950)"; }
+
+} // extern "C"

@@ -1,0 +1,73 @@
+// clean_device.h -- definitions shared by the gfx950 kernels and the host
+// entry points of the CLEAN library (kernel arguments, device control block).
+#pragma once
+#include <stdint.h>
+
+namespace cleanhip {
+
+constexpr int WG = 512;                 // threads per workgroup (8 waves of 64)
+constexpr int NWAVES = WG / 64;
+constexpr int MAX_TILES = 1024;
+constexpr int MAX_INTERVAL = 2048;
+constexpr int GATHER_CHUNK = 2048;      // components staged in LDS per pass
+constexpr int GATHER_M = 4;             // pixel groups per thread per gather pass
+
+enum { STOP_MAXITER = 0, STOP_THRESHOLD = 1, STOP_CAPACITY = 2 };
+enum : uint32_t { ABORT_TIMEOUT = 1u };
+
+// Control words: each on its own 128-byte line.
+struct DevCtl {
+    uint32_t abort;
+    uint32_t pad0[31];
+    uint32_t barrier;
+    uint32_t pad1[31];
+    uint32_t finite_bad;
+    uint32_t pad2[31];
+};
+
+struct DevStat {
+    int64_t n_iter;
+    int32_t stop;
+    int32_t n_rounds;
+    double final_peak;
+    double model_flux;
+    double sumsq;
+    double pad[3];
+};
+
+struct KArgs {
+    const float *dirty;
+    float *residual;
+    double *model;
+    const void *psf;
+    uint64_t psf_bytes;
+    int ny, nx, psf_ny, psf_nx, cy, cx;
+    int ty, tx, T;
+    int cs;                 // workgroups per tile cluster
+    int slot_pad;           // u64 slots per parity block of a cluster
+    int interval;           // feedback interval (tiled)
+    int gather_parts;       // gather work items per tile
+    float gain;
+    double threshold;
+    int64_t max_iter;
+    int64_t cap;
+    uint64_t timeout_ticks;
+    int32_t *comp_idx;
+    float *comp_flux;
+    // workspace
+    DevCtl *ctl;
+    DevStat *dstat;
+    const int32_t *role;    // per workgroup: tile << 16 | rank, or -1 (helper)
+    uint64_t *xslots;       // [T][2][slot_pad]
+    uint64_t *tile_key;     // [T]
+    int32_t *rb_idx;        // [T][interval] raw round lists
+    float *rb_flux;
+    int32_t *rb_n;          // [T]
+    int32_t *ag_pos;        // [T][interval] aggregated round lists (ascending position)
+    float *ag_flux;
+    int32_t *ag_n;          // [T]
+    float *accbuf;          // [ny*nx] feedback sums
+    double *partial;        // [T*cs] per-workgroup sum of squared residuals
+};
+
+} // namespace cleanhip

@@ -1,0 +1,764 @@
+// clean_kernels.hip -- gfx950 kernels for the Hogbom CLEAN minor loop and its
+// tiled-with-feedback form (Wright, Adamek, Armour, arXiv 2501.01461,
+// Sections 2 and 3).  Host entry points live in clean_api.hip.
+//
+// Design (one persistent, cooperatively launched kernel per call):
+//  * The residual lives in VGPRs for the whole run.  A tile (the whole image for
+//    plain CLEAN) is owned by a cluster of `cs` workgroups; thread t of cluster
+//    rank g owns K groups of V consecutive pixels, group k at tile-local flat
+//    index ((k*cs + g)*WG + t)*V.  Only the peak key crosses workgroups.
+//  * One minor iteration: every thread applies r = fma(-c, psf[q - p + ctr], r)
+//    to its pixels and keeps its own largest |r| (lowest index on ties); a
+//    wave/LDS reduction gives the workgroup's key; the cluster's keys are
+//    exchanged through per-workgroup slots written and polled with agent-scope
+//    relaxed atomics (no fences: nothing else crosses workgroups per iteration).
+//  * Tiled rounds add three grid barriers: after the local loops (round lists
+//    published), after the feedback gather (all workgroups, including helpers,
+//    compute the cross-coupling sum for a share of the pixels into a float32
+//    buffer), and after each cluster has applied it and re-found its peak.
+//  * Every wait is bounded: a wall-clock limit or an abort flag set by any
+//    workgroup ends it, and the kernel then returns with an error code.
+//
+// Peak key (64 bits): |v| bits (31) << 33 | (0x0FFFFFFF - f) << 5 | sign << 4 |
+// tag (4).  The unsigned max of keys is the largest |v|, then the lowest
+// tile-local index f (row-major inside the tile, so the lowest image index);
+// the tag marks which exchange a published key belongs to.
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+#include <stdint.h>
+
+#include "clean_device.h"
+
+namespace cleanhip {
+
+// ------------------------------------------------------------ primitives --
+
+__device__ __forceinline__ uint64_t ld_agent(const uint64_t *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint32_t ld_agent32(const uint32_t *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_agent(uint64_t *p, uint64_t v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ uint64_t make_key(uint32_t bits, uint32_t f)
+{
+    return ((uint64_t)(bits & 0x7FFFFFFFu) << 33) | ((uint64_t)(0x0FFFFFFFu - f) << 5) |
+           ((uint64_t)(bits >> 31) << 4);
+}
+__device__ __forceinline__ float key_value(uint64_t k)
+{
+    uint32_t a = (uint32_t)(k >> 33);
+    uint32_t s = (uint32_t)(k >> 4) & 1u;
+    return __uint_as_float(a | (s << 31));
+}
+__device__ __forceinline__ uint32_t key_f(uint64_t k)
+{
+    return 0x0FFFFFFFu - (uint32_t)((k >> 5) & 0x0FFFFFFFu);
+}
+__device__ __forceinline__ uint64_t umax64(uint64_t a, uint64_t b) { return a > b ? a : b; }
+
+__device__ __forceinline__ uint64_t wave_max64(uint64_t k)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) k = umax64(k, __shfl_xor(k, off));
+    return k;
+}
+
+__device__ __forceinline__ double wave_sum64f(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
+
+// Raw buffer resource over [base, base + bytes): loads past the end return 0
+// instead of touching memory, a guard behind the host's shape checks.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void *base, uint64_t bytes)
+{
+    uint32_t n = bytes > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)bytes;
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)n, 0x00020000);
+}
+
+// V consecutive PSF values, widened to float, at byte offset `off`.
+template <typename PT, int V> struct PsfLoad;
+template <> struct PsfLoad<float, 4> {
+    static __device__ __forceinline__ void load(__amdgpu_buffer_rsrc_t rs, uint32_t off, float *o)
+    {
+        auto v = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)off, 0, 0);
+        o[0] = __uint_as_float(v[0]); o[1] = __uint_as_float(v[1]);
+        o[2] = __uint_as_float(v[2]); o[3] = __uint_as_float(v[3]);
+    }
+};
+template <> struct PsfLoad<float, 1> {
+    static __device__ __forceinline__ void load(__amdgpu_buffer_rsrc_t rs, uint32_t off, float *o)
+    {
+        o[0] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, (int)off, 0, 0));
+    }
+};
+template <> struct PsfLoad<__half, 4> {
+    static __device__ __forceinline__ void load(__amdgpu_buffer_rsrc_t rs, uint32_t off, float *o)
+    {
+        auto v = __builtin_amdgcn_raw_buffer_load_b64(rs, (int)off, 0, 0);
+        o[0] = __half2float(__ushort_as_half((unsigned short)(v[0] & 0xFFFFu)));
+        o[1] = __half2float(__ushort_as_half((unsigned short)(v[0] >> 16)));
+        o[2] = __half2float(__ushort_as_half((unsigned short)(v[1] & 0xFFFFu)));
+        o[3] = __half2float(__ushort_as_half((unsigned short)(v[1] >> 16)));
+    }
+};
+template <> struct PsfLoad<__half, 1> {
+    static __device__ __forceinline__ void load(__amdgpu_buffer_rsrc_t rs, uint32_t off, float *o)
+    {
+        o[0] = __half2float(__ushort_as_half(__builtin_amdgcn_raw_buffer_load_b16(rs, (int)off, 0, 0)));
+    }
+};
+
+// ------------------------------------------------------- abort & timing --
+
+__device__ __forceinline__ bool aborted(const KArgs &a)
+{
+    return ld_agent32(&a.ctl->abort) != 0;
+}
+__device__ __forceinline__ void raise_abort(const KArgs &a, uint32_t code)
+{
+    __hip_atomic_fetch_or(&a.ctl->abort, code, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// ------------------------------------------------ workgroup reduction ----
+
+// Max of the workgroup's keys; valid in every thread on return.
+__device__ __forceinline__ uint64_t wg_max_key(uint64_t k, uint64_t *s_red)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    k = wave_max64(k);
+    if (lane == 0) s_red[wave] = k;
+    __syncthreads();
+    uint64_t r = s_red[0];
+#pragma unroll
+    for (int w = 1; w < NWAVES; ++w) r = umax64(r, s_red[w]);
+    __syncthreads();
+    return r;
+}
+
+// Cluster all-reduce (max) of workgroup keys, exchange number `e`.
+// Returns false if the run was aborted.  `wgkey` must be uniform in the WG.
+__device__ bool cluster_max(const KArgs &a, uint64_t *slots, int cs, int rank, uint32_t e, uint64_t wgkey,
+                            uint64_t *s_bcast, int *s_ok, uint64_t &out)
+{
+    if (cs == 1) { out = wgkey; return true; }
+    const uint64_t tag = (uint64_t)((e & 7u) + 1u);
+    uint64_t *blk = slots + (size_t)(e & 1u) * a.slot_pad;
+    if (threadIdx.x < 64) {
+        if (threadIdx.x == 0) st_agent(&blk[rank], (wgkey & ~15ull) | tag);
+        uint64_t best = 0;
+        bool ok = true;
+        const uint64_t t0 = wall_clock64();
+        uint32_t spins = 0;
+        for (;;) {
+            bool have = true;
+            best = 0;
+            for (int s = threadIdx.x; s < cs; s += 64) {
+                uint64_t v = ld_agent(&blk[s]);
+                if ((v & 15ull) != tag) have = false;
+                best = umax64(best, v);
+            }
+            if (__all(have)) break;
+            if ((++spins & 63u) == 0) {
+                if (aborted(a)) { ok = false; break; }
+                if (wall_clock64() - t0 > a.timeout_ticks) { raise_abort(a, ABORT_TIMEOUT); ok = false; break; }
+            }
+        }
+        best = wave_max64(best);
+        if (threadIdx.x == 0) { *s_bcast = best & ~15ull; *s_ok = ok; }
+    }
+    __syncthreads();
+    out = *s_bcast;
+    bool ok = *s_ok;
+    __syncthreads();
+    return ok;
+}
+
+// Grid-wide barrier with release/acquire at agent scope.  `epoch` counts the
+// barriers this workgroup has passed; all workgroups pass them in order.
+__device__ bool grid_barrier(const KArgs &a, uint32_t &epoch, int *s_ok)
+{
+    __syncthreads();
+    epoch += 1;
+    if (threadIdx.x == 0) {
+        bool ok = true;
+        const uint32_t target = epoch * (uint32_t)gridDim.x;
+        __threadfence();
+        __hip_atomic_fetch_add(&a.ctl->barrier, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint64_t t0 = wall_clock64();
+        while (ld_agent32(&a.ctl->barrier) < target) {
+            if (ld_agent32(&a.ctl->abort)) { ok = false; break; }
+            if (wall_clock64() - t0 > a.timeout_ticks) { raise_abort(a, ABORT_TIMEOUT); ok = false; break; }
+            __builtin_amdgcn_s_sleep(1);
+        }
+        __threadfence();
+        *s_ok = ok;
+    }
+    __syncthreads();
+    bool ok = *s_ok;
+    __syncthreads();
+    return ok;
+}
+
+__device__ __forceinline__ void tile_rect(const KArgs &a, int t, int &y0, int &x0, int &h, int &w)
+{
+    const int i = t / a.tx, j = t % a.tx;
+    y0 = (int)((int64_t)i * a.ny / a.ty);
+    const int y1 = (int)((int64_t)(i + 1) * a.ny / a.ty);
+    x0 = (int)((int64_t)j * a.nx / a.tx);
+    const int x1 = (int)((int64_t)(j + 1) * a.nx / a.tx);
+    h = y1 - y0;
+    w = x1 - x0;
+}
+
+// ------------------------------------------------- the register tile -----
+
+template <int K, int V, typename PT> struct RegTile {
+    float r[K][V];
+    int32_t qoff[K];        // (y)*psf_nx + (x) of the group's first pixel, image coords
+    uint64_t valid;         // bit k: group k inside the tile
+    int y0, x0, h, w;       // tile rectangle
+    int cs, rank;
+
+    __device__ __forceinline__ uint32_t group_f(int k) const
+    {
+        return (uint32_t)(((k * cs + rank) * WG + (int)threadIdx.x) * V);
+    }
+
+    __device__ void load(const KArgs &a)
+    {
+        valid = 0;
+        const int hw = h * w;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const uint32_t f = group_f(k);
+            if ((int64_t)f < hw) {
+                valid |= 1ull << k;
+                const int y = (int)(f / (uint32_t)w), x = (int)(f % (uint32_t)w);
+                qoff[k] = (y0 + y) * a.psf_nx + (x0 + x);
+                const int64_t img = (int64_t)(y0 + y) * a.nx + (x0 + x);
+#pragma unroll
+                for (int e = 0; e < V; ++e) r[k][e] = a.dirty[img + e];
+                if (a.model) {
+#pragma unroll
+                    for (int e = 0; e < V; ++e) a.model[img + e] = 0.0;
+                }
+            } else {
+                qoff[k] = 0;
+#pragma unroll
+                for (int e = 0; e < V; ++e) r[k][e] = 0.0f;
+            }
+        }
+    }
+
+    __device__ void store(const KArgs &a, double &sumsq) const
+    {
+        sumsq = 0.0;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            if (valid & (1ull << k)) {
+                const uint32_t f = group_f(k);
+                const int y = (int)(f / (uint32_t)w), x = (int)(f % (uint32_t)w);
+                const int64_t img = (int64_t)(y0 + y) * a.nx + (x0 + x);
+#pragma unroll
+                for (int e = 0; e < V; ++e) {
+                    a.residual[img + e] = r[k][e];
+                    sumsq += (double)r[k][e] * (double)r[k][e];
+                }
+            }
+        }
+    }
+
+    // Thread-local peak key over the owned pixels (lowest f wins ties).
+    __device__ __forceinline__ uint64_t local_key() const
+    {
+        if (!(valid & 1ull)) return 0;
+        uint32_t bb = __float_as_uint(r[0][0]);
+        uint32_t bf = group_f(0);
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+#pragma unroll
+            for (int e = 0; e < V; ++e) {
+                if (k == 0 && e == 0) continue;
+                const uint32_t bits = __float_as_uint(r[k][e]);
+                const bool take = ((valid >> k) & 1ull) && ((bits & 0x7FFFFFFFu) > (bb & 0x7FFFFFFFu));
+                bb = take ? bits : bb;
+                bf = take ? group_f(k) + e : bf;
+            }
+        }
+        return make_key(bb, bf);
+    }
+
+    // r -= c * PSF centred on image pixel (py, px).
+    __device__ __forceinline__ void subtract(const KArgs &a, int py, int px, float c)
+    {
+        const int64_t w0 = (int64_t)(a.cy - py) * a.psf_nx + (a.cx - px);
+        const char *base = (const char *)a.psf + w0 * (int64_t)sizeof(PT);
+        const __amdgpu_buffer_rsrc_t rs = make_rsrc(base, a.psf_bytes - (uint64_t)w0 * sizeof(PT));
+        float pv[K][V];
+#pragma unroll
+        for (int k = 0; k < K; ++k) PsfLoad<PT, V>::load(rs, (uint32_t)qoff[k] * (uint32_t)sizeof(PT), pv[k]);
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+#pragma unroll
+            for (int e = 0; e < V; ++e) r[k][e] = __builtin_fmaf(-c, pv[k][e], r[k][e]);
+    }
+
+    // r -= acc (float32 feedback buffer, image layout).
+    __device__ __forceinline__ void apply_feedback(const KArgs &a)
+    {
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            if (valid & (1ull << k)) {
+                const uint32_t f = group_f(k);
+                const int y = (int)(f / (uint32_t)w), x = (int)(f % (uint32_t)w);
+                const int64_t img = (int64_t)(y0 + y) * a.nx + (x0 + x);
+#pragma unroll
+                for (int e = 0; e < V; ++e) r[k][e] = r[k][e] - a.accbuf[img + e];
+            }
+        }
+    }
+
+    // Which (rank, thread) owns tile-local index f.
+    __device__ __forceinline__ bool owns(uint32_t f) const
+    {
+        const uint32_t u = f / (uint32_t)V;
+        const uint32_t t = u % (uint32_t)WG;
+        const uint32_t g = (u / (uint32_t)WG) % (uint32_t)cs;
+        return t == threadIdx.x && (int)g == rank;
+    }
+};
+
+// ------------------------------------------------------ plain kernel -----
+
+template <int K, int V, typename PT>
+__global__ void __launch_bounds__(WG) hogbom_kernel(const KArgs a)
+{
+    __shared__ uint64_t s_red[NWAVES];
+    __shared__ uint64_t s_bcast;
+    __shared__ int s_ok;
+
+    const int32_t role = a.role[blockIdx.x];
+    if (role < 0) return;                       // no helpers in the plain form
+    const int cs = a.cs, rank = role & 0xFFFF;
+    uint64_t *slots = a.xslots;
+
+    RegTile<K, V, PT> T;
+    T.cs = cs;
+    T.rank = rank;
+    T.y0 = 0; T.x0 = 0; T.h = a.ny; T.w = a.nx;
+    T.load(a);
+
+    uint32_t e = 0;
+    uint64_t cur;
+    if (!cluster_max(a, slots, cs, rank, e++, wg_max_key(T.local_key(), s_red), &s_bcast, &s_ok, cur)) return;
+
+    const bool leader = rank == 0 && threadIdx.x == 0;
+    int64_t n = 0;
+    int32_t stop;
+    double mflux = 0.0;
+    const int64_t limit_cap = a.cap;
+    for (;;) {
+        const float v = key_value(cur);
+        if (n == a.max_iter) { stop = STOP_MAXITER; break; }
+        if ((double)fabsf(v) < a.threshold) { stop = STOP_THRESHOLD; break; }
+        if (n == limit_cap) { stop = STOP_CAPACITY; break; }
+        const float c = a.gain * v;
+        const uint32_t fp = key_f(cur);
+        const int py = (int)(fp / (uint32_t)a.nx), px = (int)(fp % (uint32_t)a.nx);
+        if (leader) {
+            a.comp_idx[n] = (int32_t)fp;
+            a.comp_flux[n] = c;
+            mflux += (double)c;
+        }
+        if (a.model && T.owns(fp)) a.model[fp] += (double)c;
+        T.subtract(a, py, px, c);
+        const uint64_t wk = wg_max_key(T.local_key(), s_red);
+        if (!cluster_max(a, slots, cs, rank, e++, wk, &s_bcast, &s_ok, cur)) return;
+        n += 1;
+    }
+    double ss;
+    T.store(a, ss);
+    ss = wave_sum64f(ss);
+    __shared__ double s_ss[NWAVES];
+    if ((threadIdx.x & 63) == 0) s_ss[threadIdx.x >> 6] = ss;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double tot = 0.0;
+        for (int w = 0; w < NWAVES; ++w) tot += s_ss[w];
+        a.partial[rank] = tot;
+    }
+    if (leader) {
+        a.dstat->n_iter = n;
+        a.dstat->stop = stop;
+        a.dstat->n_rounds = 0;
+        a.dstat->final_peak = (double)key_value(cur);
+        a.dstat->model_flux = mflux;
+    }
+}
+
+// ------------------------------------------------------ tiled kernel -----
+
+// Aggregate the leader's round list (LDS) by position: distinct positions in
+// ascending order, each with the float64 sum of its components in the order
+// found, rounded once to float32; zero sums are dropped.  Writes the raw list
+// and the aggregated list of tile t to global memory.
+__device__ void aggregate_round(const KArgs &a, int t, int L, int32_t *l_idx, float *l_flux, int32_t *l_tmp,
+                                float *l_sum, int *s_cnt)
+{
+    const size_t base = (size_t)t * a.interval;
+    for (int j = threadIdx.x; j < L; j += WG) {
+        a.rb_idx[base + j] = l_idx[j];
+        a.rb_flux[base + j] = l_flux[j];
+    }
+    // pass 1: heads (first occurrence) get their sum; l_tmp = 1 for a kept head
+    for (int j = threadIdx.x; j < L; j += WG) {
+        const int32_t q = l_idx[j];
+        bool head = true;
+        for (int k = 0; k < j; ++k)
+            if (l_idx[k] == q) { head = false; break; }
+        int keep = 0;
+        float fs = 0.0f;
+        if (head) {
+            double s = 0.0;
+            for (int k = j; k < L; ++k)
+                if (l_idx[k] == q) s += (double)l_flux[k];
+            keep = s != 0.0;
+            fs = (float)s;
+        }
+        l_tmp[j] = keep;
+        l_sum[j] = fs;
+    }
+    __syncthreads();
+    // pass 2: rank of each kept head among kept heads by position
+    for (int j = threadIdx.x; j < L; j += WG) {
+        if (!l_tmp[j]) continue;
+        const int32_t q = l_idx[j];
+        int rk = 0;
+        for (int k = 0; k < L; ++k) rk += (l_tmp[k] != 0) & (l_idx[k] < q);
+        a.ag_pos[base + rk] = q;
+        a.ag_flux[base + rk] = l_sum[j];
+    }
+    if (threadIdx.x == 0) *s_cnt = 0;
+    __syncthreads();
+    int mine = 0;
+    for (int j = threadIdx.x; j < L; j += WG) mine += l_tmp[j] != 0;
+    if (mine) atomicAdd(s_cnt, mine);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        a.rb_n[t] = L;
+        a.ag_n[t] = *s_cnt;
+    }
+}
+
+// Workgroup-wide sum of an int (every thread gets it).
+__device__ __forceinline__ int wg_sum_int(int v, int *s_tmp)
+{
+    if (threadIdx.x == 0) *s_tmp = 0;
+    __syncthreads();
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    if ((threadIdx.x & 63) == 0 && v) atomicAdd(s_tmp, v);
+    __syncthreads();
+    int r = *s_tmp;
+    __syncthreads();
+    return r;
+}
+
+template <int K, int V, typename PT>
+__global__ void __launch_bounds__(WG) tiled_kernel(const KArgs a)
+{
+    __shared__ uint64_t s_red[NWAVES];
+    __shared__ uint64_t s_bcast;
+    __shared__ int s_ok, s_tmp, s_cnt;
+    __shared__ int32_t s_off[MAX_TILES + 1];    // exclusive prefix of per-tile counts
+    extern __shared__ __align__(16) unsigned char s_dyn[];
+
+    const int32_t role = a.role[blockIdx.x];
+    const bool is_cluster = role >= 0;
+    const int tile = is_cluster ? (role >> 16) : -1;
+    const int rank = is_cluster ? (role & 0xFFFF) : 0;
+    const int cs = a.cs;
+    const int T = a.T;
+    uint64_t *slots = is_cluster ? a.xslots + (size_t)tile * 2 * a.slot_pad : nullptr;
+    const bool tile_leader_wg = is_cluster && rank == 0;
+
+    // round-list LDS (leader workgroup) and gather staging (everyone) share s_dyn
+    int32_t *l_idx = (int32_t *)s_dyn;
+    float *l_flux = (float *)(s_dyn + 4 * (size_t)a.interval);
+    int32_t *l_tmp = (int32_t *)(s_dyn + 8 * (size_t)a.interval);
+    float *l_sum = (float *)(s_dyn + 12 * (size_t)a.interval);
+    int32_t *g_shift = (int32_t *)s_dyn;
+    float *g_flux = (float *)(s_dyn + 4 * (size_t)GATHER_CHUNK);
+
+    RegTile<K, V, PT> R;
+    uint32_t e = 0, epoch = 0;
+    uint64_t cur = 0;
+    if (is_cluster) {
+        R.cs = cs;
+        R.rank = rank;
+        tile_rect(a, tile, R.y0, R.x0, R.h, R.w);
+        R.load(a);
+        if (!cluster_max(a, slots, cs, rank, e++, wg_max_key(R.local_key(), s_red), &s_bcast, &s_ok, cur)) return;
+        if (tile_leader_wg && threadIdx.x == 0) a.tile_key[tile] = cur;
+    }
+    if (!grid_barrier(a, epoch, &s_ok)) return;
+
+    const int64_t limit = a.max_iter < a.cap ? a.max_iter : a.cap;
+    int64_t used = 0;
+    int32_t rounds = 0, stop = STOP_MAXITER;
+    double mflux = 0.0;
+    for (;;) {
+        // ---- round control, computed identically by every workgroup
+        int na_part = 0, rk_part = 0;
+        for (int t = threadIdx.x; t < T; t += WG) {
+            const uint64_t k = a.tile_key[t];
+            const int act = (double)fabsf(key_value(k)) >= a.threshold;
+            na_part += act;
+            rk_part += act && (t < tile);
+        }
+        const int na = wg_sum_int(na_part, &s_tmp);
+        const int my_rank = wg_sum_int(rk_part, &s_tmp);
+        if (used == a.max_iter) { stop = STOP_MAXITER; break; }
+        if (na == 0) { stop = STOP_THRESHOLD; break; }
+        if (used == a.cap) { stop = STOP_CAPACITY; break; }
+        const int64_t rem = limit - used;
+        int64_t budget = 0;
+        if (is_cluster) {
+            const bool act = (double)fabsf(key_value(cur)) >= a.threshold;
+            if (act) budget = rem >= (int64_t)na * a.interval ? a.interval
+                                                                : rem / na + (my_rank < rem % na ? 1 : 0);
+        }
+
+        // ---- local minor loops
+        if (is_cluster) {
+            int L = 0;
+            for (int64_t it = 0; it < budget; ++it) {
+                const float v = key_value(cur);
+                if ((double)fabsf(v) < a.threshold) break;
+                const float c = a.gain * v;
+                const uint32_t fp = key_f(cur);
+                const int ly = (int)(fp / (uint32_t)R.w), lx = (int)(fp % (uint32_t)R.w);
+                const int py = R.y0 + ly, px = R.x0 + lx;
+                const int32_t img = py * a.nx + px;
+                if (tile_leader_wg && threadIdx.x == 0) { l_idx[L] = img; l_flux[L] = c; }
+                if (a.model && R.owns(fp)) a.model[img] += (double)c;
+                R.subtract(a, py, px, c);
+                L += 1;
+                if (it + 1 < budget) {
+                    const uint64_t wk = wg_max_key(R.local_key(), s_red);
+                    if (!cluster_max(a, slots, cs, rank, e++, wk, &s_bcast, &s_ok, cur)) return;
+                }
+            }
+            if (tile_leader_wg) {
+                __syncthreads();
+                aggregate_round(a, tile, L, l_idx, l_flux, l_tmp, l_sum, &s_cnt);
+            }
+        }
+        if (!grid_barrier(a, epoch, &s_ok)) return;                        // A
+
+        // ---- round bookkeeping: every workgroup reads the counts
+        for (int t = threadIdx.x; t < T; t += WG) s_off[t + 1] = a.rb_n[t];
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            s_off[0] = 0;
+            for (int t = 0; t < T; ++t) s_off[t + 1] += s_off[t];
+        }
+        __syncthreads();
+        const int32_t nround = s_off[T];
+        if (blockIdx.x == 0) {
+            // append this round's components in (tile, local iteration) order
+            double fsum = 0.0;
+            for (int t = 0; t < T; ++t) {
+                const int32_t cnt = s_off[t + 1] - s_off[t];
+                for (int j = threadIdx.x; j < cnt; j += WG) {
+                    const float fl = a.rb_flux[(size_t)t * a.interval + j];
+                    a.comp_idx[used + s_off[t] + j] = a.rb_idx[(size_t)t * a.interval + j];
+                    a.comp_flux[used + s_off[t] + j] = fl;
+                    fsum += (double)fl;
+                }
+            }
+            fsum = wave_sum64f(fsum);
+            __shared__ double s_fs[NWAVES];
+            if ((threadIdx.x & 63) == 0) s_fs[threadIdx.x >> 6] = fsum;
+            __syncthreads();
+            if (threadIdx.x == 0)
+                for (int w = 0; w < NWAVES; ++w) mflux += s_fs[w];
+        }
+        used += nround;
+        __syncthreads();
+        for (int t = threadIdx.x; t < T; t += WG) s_off[t + 1] = a.ag_n[t];
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            s_off[0] = 0;
+            for (int t = 0; t < T; ++t) s_off[t + 1] += s_off[t];
+        }
+        __syncthreads();
+
+        // ---- feedback gather: acc[q] = sum over other tiles' components
+        {
+            const int parts = a.gather_parts;
+            const int nitems = T * parts;
+            for (int item = blockIdx.x; item < nitems; item += gridDim.x) {
+                const int s = item % T, part = item / T;
+                int y0, x0, h, w;
+                tile_rect(a, s, y0, x0, h, w);
+                const int ngroups = (h * w) / V;
+                const int per = (ngroups + parts - 1) / parts;
+                const int g_lo = part * per;
+                const int g_hi = min(ngroups, g_lo + per);
+                const int32_t total = s_off[T] - (s_off[s + 1] - s_off[s]);
+                for (int gb = g_lo; gb < g_hi; gb += WG * GATHER_M) {
+                    float acc[GATHER_M][V];
+                    int32_t goff[GATHER_M];
+                    int64_t gimg[GATHER_M];
+                    bool gv[GATHER_M];
+#pragma unroll
+                    for (int m = 0; m < GATHER_M; ++m) {
+                        const int g = gb + m * WG + (int)threadIdx.x;
+                        gv[m] = g < g_hi;
+                        const int f = g * V;
+                        const int y = f / w, x = f % w;
+                        goff[m] = gv[m] ? (y0 + y) * a.psf_nx + (x0 + x) : 0;
+                        gimg[m] = (int64_t)(y0 + y) * a.nx + (x0 + x);
+#pragma unroll
+                        for (int v = 0; v < V; ++v) acc[m][v] = 0.0f;
+                    }
+                    // components of tiles != s, in tile order, raster order inside a tile
+                    for (int32_t c0 = 0; c0 < total; c0 += GATHER_CHUNK) {
+                        const int32_t cn = min((int32_t)GATHER_CHUNK, total - c0);
+                        __syncthreads();
+                        for (int j = threadIdx.x; j < cn; j += WG) {
+                            int32_t gi = c0 + j;                 // index in the list without tile s
+                            if (gi >= s_off[s]) gi += s_off[s + 1] - s_off[s];
+                            // find the tile of concatenated entry gi
+                            int lo = 0, hi = T;                  // s_off[lo] <= gi < s_off[hi]
+                            while (hi - lo > 1) { const int mid = (lo + hi) >> 1; if (s_off[mid] <= gi) lo = mid; else hi = mid; }
+                            const size_t src = (size_t)lo * a.interval + (gi - s_off[lo]);
+                            const int32_t pos = a.ag_pos[src];
+                            const int py = pos / a.nx, px = pos % a.nx;
+                            g_shift[j] = (a.cy - py) * a.psf_nx + (a.cx - px);
+                            g_flux[j] = a.ag_flux[src];
+                        }
+                        __syncthreads();
+                        for (int j = 0; j < cn; ++j) {
+                            const int32_t sh = __builtin_amdgcn_readfirstlane(g_shift[j]);
+                            const float fl = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, g_flux[j])));
+                            const char *base = (const char *)a.psf + (int64_t)sh * (int64_t)sizeof(PT);
+                            const __amdgpu_buffer_rsrc_t rs = make_rsrc(base, a.psf_bytes - (uint64_t)sh * sizeof(PT));
+#pragma unroll
+                            for (int m = 0; m < GATHER_M; ++m) {
+                                float pv[V];
+                                PsfLoad<PT, V>::load(rs, (uint32_t)goff[m] * (uint32_t)sizeof(PT), pv);
+#pragma unroll
+                                for (int v = 0; v < V; ++v) acc[m][v] = __builtin_fmaf(fl, pv[v], acc[m][v]);
+                            }
+                        }
+                    }
+#pragma unroll
+                    for (int m = 0; m < GATHER_M; ++m)
+                        if (gv[m]) {
+#pragma unroll
+                            for (int v = 0; v < V; ++v) a.accbuf[gimg[m] + v] = acc[m][v];
+                        }
+                }
+            }
+        }
+        if (!grid_barrier(a, epoch, &s_ok)) return;                        // B
+
+        // ---- apply feedback and find each tile's new peak
+        if (is_cluster) {
+            R.apply_feedback(a);
+            const uint64_t wk = wg_max_key(R.local_key(), s_red);
+            if (!cluster_max(a, slots, cs, rank, e++, wk, &s_bcast, &s_ok, cur)) return;
+            if (tile_leader_wg && threadIdx.x == 0) a.tile_key[tile] = cur;
+        }
+        rounds += 1;
+        if (!grid_barrier(a, epoch, &s_ok)) return;                        // C
+    }
+
+    // ---- results
+    if (is_cluster) {
+        double ss;
+        R.store(a, ss);
+        ss = wave_sum64f(ss);
+        __shared__ double s_ss[NWAVES];
+        if ((threadIdx.x & 63) == 0) s_ss[threadIdx.x >> 6] = ss;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double tot = 0.0;
+            for (int w = 0; w < NWAVES; ++w) tot += s_ss[w];
+            a.partial[tile * cs + rank] = tot;
+        }
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        uint64_t best = a.tile_key[0];
+        for (int t = 1; t < T; ++t) {
+            const uint64_t k = a.tile_key[t];
+            if ((k >> 33) > (best >> 33)) best = k;       // largest |v|, lowest tile id on ties
+        }
+        a.dstat->n_iter = used;
+        a.dstat->stop = stop;
+        a.dstat->n_rounds = rounds;
+        a.dstat->final_peak = (double)key_value(best);
+        a.dstat->model_flux = mflux;
+    }
+}
+
+// ------------------------------------------------------ small kernels ----
+
+__global__ void finite_check_kernel(const float *x, int64_t n, uint32_t *flag)
+{
+    int bad = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        bad |= !__builtin_isfinite(x[i]);
+    if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(flag, 1u);
+}
+
+__global__ void finite_check_half_kernel(const unsigned short *x, int64_t n, uint32_t *flag)
+{
+    int bad = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        bad |= (x[i] & 0x7C00u) == 0x7C00u;
+    if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(flag, 1u);
+}
+
+__global__ void to_half_kernel(const float *x, unsigned short *y, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        y[i] = __half_as_ushort(__float2half_rn(x[i]));
+}
+
+// Sum the per-workgroup squared-residual partials in a fixed order.
+__global__ void finalize_kernel(const double *partial, int n, DevStat *st)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        double s = 0.0;
+        for (int i = 0; i < n; ++i) s += partial[i];
+        st->sumsq = s;
+    }
+}
+
+// ----------------------------------------------------- instantiations ----
+
+#define INST(K, V, PT)                                                       \
+    template __global__ void hogbom_kernel<K, V, PT>(const KArgs a);        \
+    template __global__ void tiled_kernel<K, V, PT>(const KArgs a);
+
+#define INST_ALL_K(V, PT) INST(1, V, PT) INST(2, V, PT) INST(4, V, PT) INST(8, V, PT) INST(16, V, PT)
+INST_ALL_K(4, float)
+INST_ALL_K(4, __half)
+INST(4, 1, float) INST(16, 1, float) INST(64, 1, float)
+INST(4, 1, __half) INST(16, 1, __half) INST(64, 1, __half)
+
+} // namespace cleanhip

@@ -1,0 +1,222 @@
+"""GPU parity: the HIP path against the CPU oracle, bit for bit (FP32 path).
+
+Every case runs the same seeded inputs through the C ABI (via the ctypes
+binding) and through the oracle, and compares the component list (positions
+and float32 bits), the residual's float32 bits, the float64 model's bits, the
+iteration count and the stop reason.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2501_01461_amd import synth
+from tests.gpu_util import announce, assert_same_run, bits, dev, host
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    import paper_2501_01461_amd as P
+    P.load()
+    return P
+
+
+def sparse_dirty(ny, nx, seed, density=0.02, noise=0.02):
+    r = np.random.default_rng([11, seed])
+    d = r.normal(0, noise, (ny, nx)) + (r.random((ny, nx)) < density) * r.uniform(-2, 2, (ny, nx))
+    return d.astype(np.float32)
+
+
+def asym_psf(My, Mx, seed, spread=0.3):
+    return synth.random_psf(My, Mx, np.random.default_rng([12, seed]), spread).astype(np.float32)
+
+
+# ------------------------------------------------------------------ plain --
+
+PLAIN_CASES = [
+    # ny, nx, psf extra (y, x), seed, wg_per_tile, px_per_thread, max_iter, threshold
+    (64, 64, (0, 0), 1, 0, 0, 300, 0.0),
+    (37, 50, (2, 6), 2, 0, 0, 300, 0.0),          # width not a multiple of 4: scalar groups
+    (96, 128, (4, 0), 3, 3, 8, 250, 0.0),         # 3 workgroups exactly full
+    (200, 160, (0, 8), 4, 2, 32, 400, 0.0),       # ragged tail in the last workgroup
+    (128, 256, (2, 2), 5, 5, 16, 300, 0.05),      # threshold stop
+    (300, 36, (0, 4), 6, 0, 0, 200, 0.0),         # tall and narrow
+    (50, 50, (0, 2), 7, 7, 4, 150, 0.0),          # width 50: scalar groups, 7 workgroups
+]
+
+
+@pytest.mark.parametrize("case", PLAIN_CASES, ids=[f"{c[0]}x{c[1]}-wg{c[4]}-ppt{c[5]}" for c in PLAIN_CASES])
+def test_plain_bitexact_small(lib, case):
+    ny, nx, extra, seed, wg, ppt, n, thr = case
+    announce("plain", case)
+    dirty = sparse_dirty(ny, nx, seed)
+    psf = asym_psf(2 * ny + extra[0], 2 * nx + extra[1], seed)
+    ref = oracle.hogbom(dirty, psf, 0.1, thr, n)
+    out = lib.hogbom(dev(dirty), dev(psf), 0.1, thr, n, wg_per_tile=wg, px_per_thread=ppt)
+    assert_same_run(out, ref)
+
+
+def test_plain_config0(lib):
+    announce("plain config0")
+    c = synth.make_config(0)
+    ref = oracle.hogbom(c["dirty"], c["psf"], c["gain"], c["threshold"], c["max_iter"])
+    out = lib.hogbom(dev(c["dirty"]), dev(c["psf"]), c["gain"], c["threshold"], c["max_iter"])
+    assert ref["stop"] == 1 and 500 < ref["n_iter"] < 1000
+    assert_same_run(out, ref)
+    st = out["stats"]
+    assert st["final_peak"] == float(np.float32(ref["residual"].ravel()[np.argmax(np.abs(ref["residual"]))]))
+    assert st["model_flux"] == pytest.approx(float(np.sum(ref["flux"].astype(np.float64))), rel=1e-12)
+    rms = float(np.sqrt(np.mean(ref["residual"].astype(np.float64) ** 2)))
+    assert st["residual_rms"] == pytest.approx(rms, rel=1e-12)
+
+
+@pytest.mark.parametrize("wg,ppt", [(2, 0), (2, 64), (4, 32), (8, 16), (16, 8), (32, 4), (3, 64), (5, 0)])
+def test_plain_launch_shape_does_not_change_results(lib, wg, ppt):
+    announce("plain shapes", wg, ppt)
+    c = synth.make_config(0)
+    ref = oracle.hogbom(c["dirty"], c["psf"], 0.1, 5e-3, 400)
+    out = lib.hogbom(dev(c["dirty"]), dev(c["psf"]), 0.1, 5e-3, 400, wg_per_tile=wg, px_per_thread=ppt)
+    assert_same_run(out, ref)
+
+
+def test_plain_config1_full(lib):
+    """The full 1024^2 / 20000-iteration plain run, bit for bit."""
+    announce("plain config1 full")
+    c = synth.make_config(1)
+    ref = oracle.hogbom(c["dirty"], c["psf"], 0.1, 0.0, c["max_iter"])
+    out = lib.hogbom(dev(c["dirty"]), dev(c["psf"]), 0.1, 0.0, c["max_iter"])
+    assert_same_run(out, ref)
+
+
+def test_ties_and_zero_image(lib):
+    announce("ties")
+    psf = np.zeros((16, 20), np.float32)
+    psf[8, 10] = 1.0
+    d = np.zeros((8, 10), np.float32)
+    d[5, 2] = 1.5
+    d[3, 7] = -1.5
+    d[6, 0] = 1.5
+    ref = oracle.hogbom(d, psf, 0.5, 0.0, 3)
+    out = lib.hogbom(dev(d), dev(psf), 0.5, 0.0, 3)
+    assert list(host(out["idx"])) == [37, 52, 60]
+    assert_same_run(out, ref)
+    z = np.zeros((8, 10), np.float32)
+    out = lib.hogbom(dev(z), dev(psf), 0.5, 0.0, 2)
+    assert list(host(out["idx"])) == [0, 0]
+
+
+@pytest.mark.parametrize("max_iter,thr,cap,stop", [(0, 0.0, None, 0), (50, 10.0, None, 1), (50, 0.0, 7, 2),
+                                                   (5, 0.0, 5, 0)])
+def test_stop_rules(lib, max_iter, thr, cap, stop):
+    announce("stop", max_iter, thr, cap)
+    dirty = sparse_dirty(40, 44, 9)
+    psf = asym_psf(80, 88, 9)
+    ref = oracle.hogbom(dirty, psf, 0.1, thr, max_iter, cap=cap)
+    out = lib.hogbom(dev(dirty), dev(psf), 0.1, thr, max_iter, cap=cap)
+    assert out["stats"]["stop_reason"] == stop
+    assert_same_run(out, ref)
+
+
+def test_in_place_residual(lib):
+    """dirty may alias residual."""
+    announce("in place")
+    import torch
+    dirty = sparse_dirty(64, 72, 10)
+    psf = asym_psf(128, 144, 10)
+    ref = oracle.hogbom(dirty, psf, 0.1, 0.0, 100)
+    d = dev(dirty)
+    idx = torch.empty(100, dtype=torch.int32, device="cuda")
+    flux = torch.empty(100, dtype=torch.float32, device="cuda")
+    mod = torch.empty((64, 72), dtype=torch.float64, device="cuda")
+    out = lib.hogbom(d, dev(psf), 0.1, 0.0, 100, out=(d, idx, flux, mod))
+    assert_same_run(out, ref)
+
+
+# ----------------------------------------------------------- FP16 PSF -----
+
+def test_fp16_psf_matches_oracle_on_rounded_psf(lib):
+    announce("fp16 psf")
+    import torch
+    c = synth.make_config(0)
+    psf16 = c["psf"].astype(np.float16)
+    ref = oracle.hogbom(c["dirty"], psf16.astype(np.float32), 0.1, 5e-3, 1000)
+    p16 = lib.psf_to_f16(dev(c["psf"]))
+    assert np.array_equal(host(p16).view(np.uint16), psf16.view(np.uint16))
+    out = lib.hogbom(dev(c["dirty"]), p16, 0.1, 5e-3, 1000)
+    assert_same_run(out, ref)
+    # its error against the float64 oracle, stated in Jy
+    r64 = oracle.hogbom(c["dirty"], c["psf"], 0.1, 5e-3, 1000, precision="f64")
+    err = float(np.max(np.abs(host(out["model"]) - r64["model"])))
+    print(f"fp16 PSF: max |model - fp64 model| = {err:.3e} Jy", flush=True)
+    assert err < 0.05
+
+
+def test_psf_to_f16_rounding(lib):
+    announce("psf_to_f16")
+    r = np.random.default_rng(5)
+    x = np.concatenate([r.normal(0, 1, 100000), r.normal(0, 1e-5, 1000), [65504.0, 65520.0, 1e-8, -0.0]])
+    x = x.astype(np.float32)
+    y = lib.psf_to_f16(dev(x))
+    assert np.array_equal(host(y).view(np.uint16), x.astype(np.float16).view(np.uint16))
+
+
+# ----------------------------------------------------------------- tiled --
+
+TILED_CASES = [
+    # ny, nx, tiles, interval, seed, max_iter, threshold, wg, ppt
+    (64, 64, (2, 2), 10, 21, 300, 0.0, 0, 0),
+    (60, 72, (3, 2), 7, 22, 250, 0.0, 0, 0),
+    (48, 80, (1, 4), 1, 23, 120, 0.0, 0, 0),
+    (96, 96, (2, 3), 50, 24, 400, 0.05, 0, 0),      # threshold stop
+    (50, 62, (2, 2), 13, 25, 200, 0.0, 0, 0),       # odd tile widths: scalar groups
+    (128, 128, (4, 4), 20, 26, 600, 0.0, 2, 4),     # 2 workgroups per tile
+    (64, 128, (2, 2), 2048, 27, 1000, 0.0, 0, 0),   # one round
+    (40, 40, (1, 1), 9, 28, 100, 0.0, 0, 0),        # one tile
+]
+
+
+@pytest.mark.parametrize("case", TILED_CASES, ids=[f"{c[0]}x{c[1]}-{c[2][0]}x{c[2][1]}-I{c[3]}" for c in TILED_CASES])
+def test_tiled_bitexact_small(lib, case):
+    ny, nx, tiles, interval, seed, n, thr, wg, ppt = case
+    announce("tiled", case)
+    dirty = sparse_dirty(ny, nx, seed, density=0.03)
+    psf = asym_psf(2 * ny, 2 * nx + 2, seed, spread=0.2)
+    ref = oracle.tiled(dirty, psf, tiles, interval, 0.1, thr, n)
+    out = lib.tiled_feedback(dev(dirty), dev(psf), tiles, interval, 0.1, thr, n, wg_per_tile=wg, px_per_thread=ppt)
+    assert out["stats"]["n_rounds"] == ref["n_rounds"]
+    assert_same_run(out, ref)
+
+
+def test_tiled_one_tile_equals_plain(lib):
+    announce("tiled 1x1 vs plain")
+    c = synth.make_config(0)
+    a = lib.hogbom(dev(c["dirty"]), dev(c["psf"]), 0.1, 5e-3, 1000)
+    b = lib.tiled_feedback(dev(c["dirty"]), dev(c["psf"]), (1, 1), 64, 0.1, 5e-3, 1000)
+    assert a["stats"]["n_iter"] == b["stats"]["n_iter"]
+    assert np.array_equal(host(a["idx"]), host(b["idx"]))
+    assert np.array_equal(bits(host(a["flux"])), bits(host(b["flux"])))
+    assert np.array_equal(bits(host(a["residual"])), bits(host(b["residual"])))
+
+
+def test_tiled_config1_full(lib):
+    """The full 1024^2, 2x2 tiles, interval 100, 20000-iteration run, bit for bit."""
+    announce("tiled config1 full")
+    c = synth.make_config(1)
+    ref = oracle.tiled(c["dirty"], c["psf"], c["tiles"], c["interval"], 0.1, 0.0, c["max_iter"])
+    out = lib.tiled_feedback(dev(c["dirty"]), dev(c["psf"]), c["tiles"], c["interval"], 0.1, 0.0, c["max_iter"])
+    assert out["stats"]["n_rounds"] == ref["n_rounds"]
+    assert_same_run(out, ref)
+
+
+def test_nonfinite_input_rejected(lib):
+    announce("nonfinite")
+    d = sparse_dirty(32, 32, 30)
+    d[3, 4] = np.nan
+    psf = asym_psf(64, 64, 30)
+    with pytest.raises(lib.CleanError) as e:
+        lib.hogbom(dev(d), dev(psf), 0.1, 0.0, 10, check_finite=True)
+    assert e.value.status == -2
