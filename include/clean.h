@@ -104,6 +104,9 @@ typedef struct {
     int32_t wg_per_tile;  /* launch shape that was used                           */
     int32_t px_per_thread;
     int32_t workgroups;   /* total workgroups in the persistent launch            */
+    float phase_us[3];    /* tiled: device time in the local loops, the feedback
+                             gather and the apply + re-peak phases, summed over
+                             rounds (microseconds, wall clock); 0 for plain       */
 } clean_stats;
 
 /*

@@ -35,10 +35,12 @@ class Stats(C.Structure):
     _fields_ = [("n_iter", C.c_int64), ("stop_reason", C.c_int32), ("n_rounds", C.c_int32),
                 ("final_peak", C.c_double), ("residual_rms", C.c_double), ("model_flux", C.c_double),
                 ("device_ms", C.c_float), ("wg_per_tile", C.c_int32), ("px_per_thread", C.c_int32),
-                ("workgroups", C.c_int32)]
+                ("workgroups", C.c_int32), ("phase_us", C.c_float * 3)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        d = {k: getattr(self, k) for k, _ in self._fields_}
+        d["phase_us"] = list(self.phase_us)
+        return d
 
 
 class Problem(C.Structure):
@@ -170,6 +172,47 @@ def tiled_feedback(dirty, psf, tiles=(2, 2), interval=100, gain=0.1, threshold=0
                                     _ptr(mod), None, 0, C.byref(st), _stream()))
     n = st.n_iter
     return dict(residual=res, idx=idx[:n], flux=flux[:n], model=mod, stats=st.as_dict())
+
+
+def batched(problems, gain=0.1, model=True, check_finite=False, px_per_thread=0):
+    """Independent plain Hogbom problems in one persistent launch.
+
+    problems: list of dicts with device tensors "dirty" (float32 2-D) and "psf"
+    (float32 or float16, all the same dtype), and "threshold", "max_iter",
+    optional "cap".  Returns a list of dict(residual, idx, flux, model, stats).
+    """
+    torch = _torch()
+    lib = load()
+    n = len(problems)
+    arr = (Problem * max(n, 1))()
+    keep, outs = [], []
+    psf_dtype = None
+    for i, q in enumerate(problems):
+        d, p = _prep(q["dirty"], q["psf"])
+        if psf_dtype is None:
+            psf_dtype = p.dtype
+        elif p.dtype != psf_dtype:
+            raise TypeError("all PSFs of a batch must share one dtype")
+        cap = int(q.get("cap", q["max_iter"]))
+        res, idx, flux, mod = _outputs(d, cap, model)
+        keep += [d, p]
+        outs.append((res, idx, flux, mod))
+        ny, nx = d.shape
+        arr[i] = Problem(d.data_ptr(), p.data_ptr(), res.data_ptr(), idx.data_ptr(), flux.data_ptr(),
+                         mod.data_ptr() if mod is not None else None, cap, int(q["max_iter"]),
+                         float(q["threshold"]), ny, nx, p.shape[0], p.shape[1])
+    if n == 0:
+        return []
+    dt = PSF_F16 if psf_dtype == torch.float16 else PSF_F32
+    prm = Params(float(gain), 0.0, 0, dt, FLAG_CHECK_FINITE if check_finite else 0, 0, int(px_per_thread))
+    stats = (Stats * n)()
+    _check(lib.clean_batched(arr, n, C.byref(prm), stats, _stream()))
+    res = []
+    for i in range(n):
+        r, idx, flux, mod = outs[i]
+        k = stats[i].n_iter
+        res.append(dict(residual=r, idx=idx[:k], flux=flux[:k], model=mod, stats=stats[i].as_dict()))
+    return res
 
 
 def psf_to_f16(psf):

@@ -20,6 +20,8 @@
 namespace cleanhip {
 template <int K, int V, typename PT> __global__ void hogbom_kernel(const KArgs a);
 template <int K, int V, typename PT> __global__ void tiled_kernel(const KArgs a);
+template <int K, int V, typename PT> __global__ void batched_kernel(const BatchArgs b);
+__global__ void finalize_batch_kernel(const PlainJob *jobs, int n);
 __global__ void finite_check_kernel(const float *x, int64_t n, uint32_t *flag);
 __global__ void finite_check_half_kernel(const unsigned short *x, int64_t n, uint32_t *flag);
 __global__ void to_half_kernel(const float *x, unsigned short *y, int64_t n);
@@ -156,6 +158,34 @@ template <int V, typename PT> KFn tiled_fn(int K)
         }
     }
     return nullptr;
+}
+
+using BFn = void (*)(const BatchArgs);
+
+template <int V, typename PT> BFn batched_fn(int K)
+{
+    if constexpr (V == 4) {
+        switch (K) {
+        case 1: return batched_kernel<1, 4, PT>;
+        case 2: return batched_kernel<2, 4, PT>;
+        case 4: return batched_kernel<4, 4, PT>;
+        case 8: return batched_kernel<8, 4, PT>;
+        case 16: return batched_kernel<16, 4, PT>;
+        }
+    } else {
+        switch (K) {
+        case 4: return batched_kernel<4, 1, PT>;
+        case 16: return batched_kernel<16, 1, PT>;
+        case 64: return batched_kernel<64, 1, PT>;
+        }
+    }
+    return nullptr;
+}
+
+BFn pick_batched(bool half, int V, int K)
+{
+    if (V == 4) return half ? batched_fn<4, __half>(K) : batched_fn<4, float>(K);
+    return half ? batched_fn<1, __half>(K) : batched_fn<1, float>(K);
 }
 
 KFn pick(bool tiled, bool half, int V, int K)
@@ -441,6 +471,8 @@ int run(bool tiled, const float *dirty, int ny, int nx, const void *psf, int psf
         stats->wg_per_tile = cs;
         stats->px_per_thread = ppt;
         stats->workgroups = W;
+        const double us_per_tick = 1e6 / (double)(a.timeout_ticks / 20ull);
+        for (int i = 0; i < 3; ++i) stats->phase_us[i] = (float)(ds.phase_ticks[i] * us_per_tick);
     }
     return CLEAN_OK;
 }
@@ -468,11 +500,172 @@ int clean_tiled_feedback(const float *dirty, int ny, int nx, const void *psf, in
                comp_flux, comp_cap, model, workspace, workspace_bytes, stats, stream);
 }
 
-int clean_batched(const clean_problem *probs, int n, const clean_params *shared, clean_stats *stats, void *stream)
+int clean_batched(const clean_problem *probs, int n, const clean_params *shared, clean_stats *stats, void *stream_v)
 {
     g_last_error.clear();
-    (void)probs; (void)n; (void)shared; (void)stats; (void)stream;
-    return fail(CLEAN_E_UNSUPPORTED, "clean_batched is not built yet");
+    if (!probs || !shared) return fail(CLEAN_E_INVAL, "probs and shared params must be non-NULL");
+    if (n < 0 || n > 65536) return fail(CLEAN_E_INVAL, "batch of %d problems not in [0, 65536]", n);
+    if (n == 0) return CLEAN_OK;
+    const bool half = shared->psf_dtype == CLEAN_PSF_F16;
+    bool w4 = true;
+    int64_t max_pix = 0;
+    for (int i = 0; i < n; ++i) {
+        const clean_problem &q = probs[i];
+        clean_params pi = *shared;
+        pi.threshold = q.threshold;
+        pi.max_iter = q.max_iter;
+        int st = check_common(q.dirty, q.ny, q.nx, q.psf, q.psf_ny, q.psf_nx, &pi, q.residual, q.comp_idx,
+                              q.comp_flux, q.comp_cap);
+        if (st) return fail(st, "problem %d: %s", i, g_last_error.c_str());
+        if (q.nx % 4) w4 = false;
+        max_pix = std::max<int64_t>(max_pix, (int64_t)q.ny * q.nx);
+    }
+    const int V = w4 ? 4 : 1;
+    int ppt = shared->px_per_thread;
+    if (ppt == 0) ppt = V == 4 ? 32 : 16;
+    if (!valid_ppt(V, ppt)) return fail(CLEAN_E_INVAL, "px_per_thread %d not available", ppt);
+    const int K = ppt / V;
+    BFn fn = pick_batched(half, V, K);
+    if (!fn) return fail(CLEAN_E_UNSUPPORTED, "no batched kernel for %d x %d pixels per thread", K, V);
+    hipStream_t stream = (hipStream_t)stream_v;
+    int dev = 0, ncu = 0, occ = 0;
+    HIPCHK(hipGetDevice(&dev));
+    HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void *)fn, WG, 0));
+    const int max_wg = occ * ncu;
+
+    // cluster size per problem, then largest problems first
+    std::vector<int> cs(n);
+    for (int i = 0; i < n; ++i) {
+        const int64_t np = (int64_t)probs[i].ny * probs[i].nx;
+        cs[i] = (int)((np + (int64_t)WG * ppt - 1) / ((int64_t)WG * ppt));
+        if (cs[i] > max_wg)
+            return fail(CLEAN_E_UNSUPPORTED, "problem %d needs %d workgroups, only %d fit", i, cs[i], max_wg);
+    }
+    std::vector<int> order(n);
+    for (int i = 0; i < n; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+        const int64_t px = (int64_t)probs[x].ny * probs[x].nx, py = (int64_t)probs[y].ny * probs[y].nx;
+        return px > py;
+    });
+
+    // workspace: control | jobs | seat0 | stats | slots | partials
+    std::vector<int32_t> seat0(n + 1, 0);
+    size_t nslots = 0, npart = 0;
+    for (int r = 0; r < n; ++r) {
+        const int i = order[r];
+        seat0[r + 1] = seat0[r] + cs[i];
+        nslots += (size_t)2 * ((cs[i] + 31) / 32 * 32);
+        npart += cs[i];
+    }
+    size_t o = 0;
+    const size_t o_ctl = o;   o = align_up(o + sizeof(DevCtl), 256);
+    const size_t o_stat = o;  o = align_up(o + sizeof(DevStat) * n, 256);
+    const size_t o_slots = o; o = align_up(o + nslots * 8, 256);
+    const size_t head_end = o;
+    const size_t o_jobs = o;  o = align_up(o + sizeof(PlainJob) * n, 256);
+    const size_t o_seat = o;  o = align_up(o + sizeof(int32_t) * (n + 1), 256);
+    const size_t o_part = o;  o = align_up(o + npart * 8, 256);
+    void *wp = nullptr;
+    int st = internal_workspace(dev, o, &wp);
+    if (st) return st;
+    char *ws = (char *)wp;
+
+    uint64_t ticks = 0;
+    st = device_timeout_ticks(dev, ticks);
+    if (st) return st;
+    std::vector<PlainJob> jobs(n);
+    size_t so = 0, po = 0;
+    for (int r = 0; r < n; ++r) {
+        const int i = order[r];
+        const clean_problem &q = probs[i];
+        PlainJob &j = jobs[r];
+        j.dirty = q.dirty; j.residual = q.residual; j.model = q.model;
+        j.psf = q.psf; j.psf_bytes = (uint64_t)q.psf_ny * q.psf_nx * (half ? 2 : 4);
+        j.ny = q.ny; j.nx = q.nx; j.psf_nx = q.psf_nx; j.cy = q.psf_ny / 2; j.cx = q.psf_nx / 2;
+        j.cs = cs[i];
+        j.slot_pad = (cs[i] + 31) / 32 * 32;
+        j.gain = (float)shared->gain;
+        j.threshold = q.threshold;
+        j.max_iter = q.max_iter;
+        j.cap = q.comp_cap;
+        j.comp_idx = q.comp_idx; j.comp_flux = q.comp_flux;
+        j.slots = (uint64_t *)(ws + o_slots) + so;
+        j.dstat = (DevStat *)(ws + o_stat) + r;
+        j.partial = (double *)(ws + o_part) + po;
+        so += (size_t)2 * j.slot_pad;
+        po += cs[i];
+    }
+    BatchArgs b{};
+    b.jobs = (const PlainJob *)(ws + o_jobs);
+    b.seat0 = (const int32_t *)(ws + o_seat);
+    b.n = n;
+    b.ctl = (DevCtl *)(ws + o_ctl);
+    b.timeout_ticks = ticks;
+    HIPCHK(hipMemsetAsync(ws, 0, head_end, stream));
+    HIPCHK(hipMemcpyAsync(ws + o_jobs, jobs.data(), sizeof(PlainJob) * n, hipMemcpyHostToDevice, stream));
+    HIPCHK(hipMemcpyAsync(ws + o_seat, seat0.data(), sizeof(int32_t) * (n + 1), hipMemcpyHostToDevice, stream));
+    if (shared->flags & CLEAN_FLAG_CHECK_FINITE) {
+        uint32_t *flag = &b.ctl->finite_bad;
+        for (int i = 0; i < n; ++i) {
+            const clean_problem &q = probs[i];
+            hipLaunchKernelGGL(finite_check_kernel, dim3(256), dim3(256), 0, stream, q.dirty, (int64_t)q.ny * q.nx, flag);
+            if (half)
+                hipLaunchKernelGGL(finite_check_half_kernel, dim3(256), dim3(256), 0, stream,
+                                   (const unsigned short *)q.psf, (int64_t)q.psf_ny * q.psf_nx, flag);
+            else
+                hipLaunchKernelGGL(finite_check_kernel, dim3(256), dim3(256), 0, stream, (const float *)q.psf,
+                                   (int64_t)q.psf_ny * q.psf_nx, flag);
+        }
+        HIPCHK(hipGetLastError());
+        uint32_t bad = 0;
+        HIPCHK(hipMemcpyAsync(&bad, flag, 4, hipMemcpyDeviceToHost, stream));
+        HIPCHK(hipStreamSynchronize(stream));
+        if (bad) return fail(CLEAN_E_NONFINITE, "non-finite value in a dirty image or PSF");
+    }
+    const int W = std::min(max_wg, seat0[n]);
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    HIPCHK(hipEventRecord(e0, stream));
+    void *args[] = {(void *)&b};
+    hipError_t le = hipLaunchCooperativeKernel((const void *)fn, dim3(W), dim3(WG), args, 0, stream);
+    if (le != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        return fail(CLEAN_E_HIP, "cooperative launch of %d x %d failed: %s", W, WG, hipGetErrorString(le));
+    }
+    HIPCHK(hipEventRecord(e1, stream));
+    hipLaunchKernelGGL(finalize_batch_kernel, dim3((n + 255) / 256), dim3(256), 0, stream, b.jobs, n);
+    HIPCHK(hipGetLastError());
+    std::vector<DevStat> ds(n);
+    DevCtl ctl{};
+    HIPCHK(hipMemcpyAsync(ds.data(), ws + o_stat, sizeof(DevStat) * n, hipMemcpyDeviceToHost, stream));
+    HIPCHK(hipMemcpyAsync(&ctl, b.ctl, sizeof ctl, hipMemcpyDeviceToHost, stream));
+    HIPCHK(hipStreamSynchronize(stream));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (ctl.abort & ABORT_TIMEOUT) return fail(CLEAN_E_TIMEOUT, "a device-side wait timed out");
+    if (ctl.abort) return fail(CLEAN_E_HIP, "device abort code %u", ctl.abort);
+    if (stats) {
+        for (int r = 0; r < n; ++r) {
+            const int i = order[r];
+            clean_stats &s = stats[i];
+            memset(&s, 0, sizeof s);
+            s.n_iter = ds[r].n_iter;
+            s.stop_reason = ds[r].stop;
+            s.final_peak = ds[r].final_peak;
+            s.residual_rms = std::sqrt(ds[r].sumsq / ((double)probs[i].ny * probs[i].nx));
+            s.model_flux = ds[r].model_flux;
+            s.device_ms = ms;
+            s.wg_per_tile = cs[i];
+            s.px_per_thread = ppt;
+            s.workgroups = W;
+        }
+    }
+    return CLEAN_OK;
 }
 
 size_t clean_workspace_size(int ny, int nx, int tiles_y, int tiles_x, int feedback_interval, const clean_params *p)

@@ -23,6 +23,8 @@ struct DevCtl {
     uint32_t pad1[31];
     uint32_t finite_bad;
     uint32_t pad2[31];
+    uint32_t seat;          // batched: next seat to hand out
+    uint32_t pad3[31];
 };
 
 struct DevStat {
@@ -32,7 +34,36 @@ struct DevStat {
     double final_peak;
     double model_flux;
     double sumsq;
-    double pad[3];
+    uint64_t phase_ticks[3];   // tiled: local loops, feedback gather, apply + re-peak (wall-clock ticks)
+};
+
+// One plain CLEAN problem as a workgroup cluster sees it.
+struct PlainJob {
+    const float *dirty;
+    float *residual;
+    double *model;
+    const void *psf;
+    uint64_t psf_bytes;
+    int ny, nx, psf_nx, cy, cx;
+    int cs;                 // workgroups in the cluster
+    int slot_pad;
+    float gain;
+    double threshold;
+    int64_t max_iter;
+    int64_t cap;
+    int32_t *comp_idx;
+    float *comp_flux;
+    uint64_t *slots;        // [2][slot_pad]
+    DevStat *dstat;
+    double *partial;        // [cs]
+};
+
+struct BatchArgs {
+    const PlainJob *jobs;   // [n], largest first
+    const int32_t *seat0;   // [n + 1] first seat of each problem
+    int n;
+    DevCtl *ctl;
+    uint64_t timeout_ticks;
 };
 
 struct KArgs {

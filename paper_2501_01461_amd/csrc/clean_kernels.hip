@@ -121,13 +121,19 @@ template <> struct PsfLoad<__half, 1> {
 
 // ------------------------------------------------------- abort & timing --
 
-__device__ __forceinline__ bool aborted(const KArgs &a)
+// Where waits look for an abort and how long they may last.
+struct Sync {
+    DevCtl *ctl;
+    uint64_t timeout_ticks;
+};
+
+__device__ __forceinline__ bool aborted(const Sync &y)
 {
-    return ld_agent32(&a.ctl->abort) != 0;
+    return ld_agent32(&y.ctl->abort) != 0;
 }
-__device__ __forceinline__ void raise_abort(const KArgs &a, uint32_t code)
+__device__ __forceinline__ void raise_abort(const Sync &y, uint32_t code)
 {
-    __hip_atomic_fetch_or(&a.ctl->abort, code, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_fetch_or(&y.ctl->abort, code, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // ------------------------------------------------ workgroup reduction ----
@@ -148,12 +154,12 @@ __device__ __forceinline__ uint64_t wg_max_key(uint64_t k, uint64_t *s_red)
 
 // Cluster all-reduce (max) of workgroup keys, exchange number `e`.
 // Returns false if the run was aborted.  `wgkey` must be uniform in the WG.
-__device__ bool cluster_max(const KArgs &a, uint64_t *slots, int cs, int rank, uint32_t e, uint64_t wgkey,
-                            uint64_t *s_bcast, int *s_ok, uint64_t &out)
+__device__ bool cluster_max(const Sync &y, uint64_t *slots, int slot_pad, int cs, int rank, uint32_t e,
+                            uint64_t wgkey, uint64_t *s_bcast, int *s_ok, uint64_t &out)
 {
     if (cs == 1) { out = wgkey; return true; }
     const uint64_t tag = (uint64_t)((e & 7u) + 1u);
-    uint64_t *blk = slots + (size_t)(e & 1u) * a.slot_pad;
+    uint64_t *blk = slots + (size_t)(e & 1u) * slot_pad;
     if (threadIdx.x < 64) {
         if (threadIdx.x == 0) st_agent(&blk[rank], (wgkey & ~15ull) | tag);
         uint64_t best = 0;
@@ -170,8 +176,8 @@ __device__ bool cluster_max(const KArgs &a, uint64_t *slots, int cs, int rank, u
             }
             if (__all(have)) break;
             if ((++spins & 63u) == 0) {
-                if (aborted(a)) { ok = false; break; }
-                if (wall_clock64() - t0 > a.timeout_ticks) { raise_abort(a, ABORT_TIMEOUT); ok = false; break; }
+                if (aborted(y)) { ok = false; break; }
+                if (wall_clock64() - t0 > y.timeout_ticks) { raise_abort(y, ABORT_TIMEOUT); ok = false; break; }
             }
         }
         best = wave_max64(best);
@@ -186,7 +192,7 @@ __device__ bool cluster_max(const KArgs &a, uint64_t *slots, int cs, int rank, u
 
 // Grid-wide barrier with release/acquire at agent scope.  `epoch` counts the
 // barriers this workgroup has passed; all workgroups pass them in order.
-__device__ bool grid_barrier(const KArgs &a, uint32_t &epoch, int *s_ok)
+__device__ bool grid_barrier(const Sync &y, uint32_t &epoch, int *s_ok)
 {
     __syncthreads();
     epoch += 1;
@@ -194,11 +200,11 @@ __device__ bool grid_barrier(const KArgs &a, uint32_t &epoch, int *s_ok)
         bool ok = true;
         const uint32_t target = epoch * (uint32_t)gridDim.x;
         __threadfence();
-        __hip_atomic_fetch_add(&a.ctl->barrier, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(&y.ctl->barrier, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         const uint64_t t0 = wall_clock64();
-        while (ld_agent32(&a.ctl->barrier) < target) {
-            if (ld_agent32(&a.ctl->abort)) { ok = false; break; }
-            if (wall_clock64() - t0 > a.timeout_ticks) { raise_abort(a, ABORT_TIMEOUT); ok = false; break; }
+        while (ld_agent32(&y.ctl->barrier) < target) {
+            if (ld_agent32(&y.ctl->abort)) { ok = false; break; }
+            if (wall_clock64() - t0 > y.timeout_ticks) { raise_abort(y, ABORT_TIMEOUT); ok = false; break; }
             __builtin_amdgcn_s_sleep(1);
         }
         __threadfence();
@@ -223,6 +229,17 @@ __device__ __forceinline__ void tile_rect(const KArgs &a, int t, int &y0, int &x
 
 // ------------------------------------------------- the register tile -----
 
+// The arrays of one image.
+struct Img {
+    const float *dirty;
+    float *residual;
+    double *model;          // may be null
+    const float *accbuf;    // tiled feedback sums (image layout), else null
+    const void *psf;
+    uint64_t psf_bytes;
+    int nx, psf_nx, cy, cx;
+};
+
 template <int K, int V, typename PT> struct RegTile {
     float r[K][V];
     int32_t qoff[K];        // (y)*psf_nx + (x) of the group's first pixel, image coords
@@ -235,7 +252,7 @@ template <int K, int V, typename PT> struct RegTile {
         return (uint32_t)(((k * cs + rank) * WG + (int)threadIdx.x) * V);
     }
 
-    __device__ void load(const KArgs &a)
+    __device__ void load(const Img &a)
     {
         valid = 0;
         const int hw = h * w;
@@ -261,7 +278,7 @@ template <int K, int V, typename PT> struct RegTile {
         }
     }
 
-    __device__ void store(const KArgs &a, double &sumsq) const
+    __device__ void store(const Img &a, double &sumsq) const
     {
         sumsq = 0.0;
 #pragma unroll
@@ -300,7 +317,7 @@ template <int K, int V, typename PT> struct RegTile {
     }
 
     // r -= c * PSF centred on image pixel (py, px).
-    __device__ __forceinline__ void subtract(const KArgs &a, int py, int px, float c)
+    __device__ __forceinline__ void subtract(const Img &a, int py, int px, float c)
     {
         const int64_t w0 = (int64_t)(a.cy - py) * a.psf_nx + (a.cx - px);
         const char *base = (const char *)a.psf + w0 * (int64_t)sizeof(PT);
@@ -315,7 +332,7 @@ template <int K, int V, typename PT> struct RegTile {
     }
 
     // r -= acc (float32 feedback buffer, image layout).
-    __device__ __forceinline__ void apply_feedback(const KArgs &a)
+    __device__ __forceinline__ void apply_feedback(const Img &a)
     {
 #pragma unroll
         for (int k = 0; k < K; ++k) {
@@ -341,69 +358,124 @@ template <int K, int V, typename PT> struct RegTile {
 
 // ------------------------------------------------------ plain kernel -----
 
+// Sum of the workgroup's squared residuals, in a fixed order, to partial[slot].
 template <int K, int V, typename PT>
-__global__ void __launch_bounds__(WG) hogbom_kernel(const KArgs a)
+__device__ void store_and_sum(const RegTile<K, V, PT> &R, const Img &im, double *partial, int slot)
 {
-    __shared__ uint64_t s_red[NWAVES];
-    __shared__ uint64_t s_bcast;
-    __shared__ int s_ok;
-
-    const int32_t role = a.role[blockIdx.x];
-    if (role < 0) return;                       // no helpers in the plain form
-    const int cs = a.cs, rank = role & 0xFFFF;
-    uint64_t *slots = a.xslots;
-
-    RegTile<K, V, PT> T;
-    T.cs = cs;
-    T.rank = rank;
-    T.y0 = 0; T.x0 = 0; T.h = a.ny; T.w = a.nx;
-    T.load(a);
-
-    uint32_t e = 0;
-    uint64_t cur;
-    if (!cluster_max(a, slots, cs, rank, e++, wg_max_key(T.local_key(), s_red), &s_bcast, &s_ok, cur)) return;
-
-    const bool leader = rank == 0 && threadIdx.x == 0;
-    int64_t n = 0;
-    int32_t stop;
-    double mflux = 0.0;
-    const int64_t limit_cap = a.cap;
-    for (;;) {
-        const float v = key_value(cur);
-        if (n == a.max_iter) { stop = STOP_MAXITER; break; }
-        if ((double)fabsf(v) < a.threshold) { stop = STOP_THRESHOLD; break; }
-        if (n == limit_cap) { stop = STOP_CAPACITY; break; }
-        const float c = a.gain * v;
-        const uint32_t fp = key_f(cur);
-        const int py = (int)(fp / (uint32_t)a.nx), px = (int)(fp % (uint32_t)a.nx);
-        if (leader) {
-            a.comp_idx[n] = (int32_t)fp;
-            a.comp_flux[n] = c;
-            mflux += (double)c;
-        }
-        if (a.model && T.owns(fp)) a.model[fp] += (double)c;
-        T.subtract(a, py, px, c);
-        const uint64_t wk = wg_max_key(T.local_key(), s_red);
-        if (!cluster_max(a, slots, cs, rank, e++, wk, &s_bcast, &s_ok, cur)) return;
-        n += 1;
-    }
-    double ss;
-    T.store(a, ss);
-    ss = wave_sum64f(ss);
     __shared__ double s_ss[NWAVES];
+    double ss;
+    R.store(im, ss);
+    ss = wave_sum64f(ss);
     if ((threadIdx.x & 63) == 0) s_ss[threadIdx.x >> 6] = ss;
     __syncthreads();
     if (threadIdx.x == 0) {
         double tot = 0.0;
         for (int w = 0; w < NWAVES; ++w) tot += s_ss[w];
-        a.partial[rank] = tot;
+        partial[slot] = tot;
     }
+    __syncthreads();
+}
+
+// Plain Hogbom CLEAN of one image by a cluster of j.cs workgroups; this
+// workgroup is cluster rank `rank`.  Returns false if the run was aborted.
+template <int K, int V, typename PT> __device__ bool run_plain(const PlainJob &j, int rank, const Sync &y)
+{
+    __shared__ uint64_t s_red[NWAVES];
+    __shared__ uint64_t s_bcast;
+    __shared__ int s_ok;
+
+    const Img im{j.dirty, j.residual, j.model, nullptr, j.psf, j.psf_bytes, j.nx, j.psf_nx, j.cy, j.cx};
+    RegTile<K, V, PT> T;
+    T.cs = j.cs;
+    T.rank = rank;
+    T.y0 = 0; T.x0 = 0; T.h = j.ny; T.w = j.nx;
+    T.load(im);
+
+    uint32_t e = 0;
+    uint64_t cur;
+    if (!cluster_max(y, j.slots, j.slot_pad, j.cs, rank, e++, wg_max_key(T.local_key(), s_red), &s_bcast, &s_ok, cur))
+        return false;
+
+    const bool leader = rank == 0 && threadIdx.x == 0;
+    int64_t n = 0;
+    int32_t stop;
+    double mflux = 0.0;
+    for (;;) {
+        // peak (eq. 1): value and position from the cluster's key
+        const float v = key_value(cur);
+        if (n == j.max_iter) { stop = STOP_MAXITER; break; }
+        if ((double)fabsf(v) < j.threshold) { stop = STOP_THRESHOLD; break; }
+        if (n == j.cap) { stop = STOP_CAPACITY; break; }
+        const float c = j.gain * v;
+        const uint32_t fp = key_f(cur);
+        const int py = (int)(fp / (uint32_t)j.nx), px = (int)(fp % (uint32_t)j.nx);
+        if (leader) {
+            j.comp_idx[n] = (int32_t)fp;
+            j.comp_flux[n] = c;
+            mflux += (double)c;
+        }
+        if (j.model && T.owns(fp)) j.model[fp] += (double)c;
+        // subtraction (eq. 2) fused with the next peak search
+        T.subtract(im, py, px, c);
+        const uint64_t wk = wg_max_key(T.local_key(), s_red);
+        if (!cluster_max(y, j.slots, j.slot_pad, j.cs, rank, e++, wk, &s_bcast, &s_ok, cur)) return false;
+        n += 1;
+    }
+    store_and_sum(T, im, j.partial, rank);
     if (leader) {
-        a.dstat->n_iter = n;
-        a.dstat->stop = stop;
-        a.dstat->n_rounds = 0;
-        a.dstat->final_peak = (double)key_value(cur);
-        a.dstat->model_flux = mflux;
+        j.dstat->n_iter = n;
+        j.dstat->stop = stop;
+        j.dstat->n_rounds = 0;
+        j.dstat->final_peak = (double)key_value(cur);
+        j.dstat->model_flux = mflux;
+    }
+    return true;
+}
+
+template <int K, int V, typename PT>
+__global__ void __launch_bounds__(WG) hogbom_kernel(const KArgs a)
+{
+    const int32_t role = a.role[blockIdx.x];
+    if (role < 0) return;                       // no helpers in the plain form
+    const Sync y{a.ctl, a.timeout_ticks};
+    PlainJob j;
+    j.dirty = a.dirty; j.residual = a.residual; j.model = a.model;
+    j.psf = a.psf; j.psf_bytes = a.psf_bytes;
+    j.ny = a.ny; j.nx = a.nx; j.psf_nx = a.psf_nx; j.cy = a.cy; j.cx = a.cx;
+    j.gain = a.gain; j.threshold = a.threshold; j.max_iter = a.max_iter; j.cap = a.cap;
+    j.comp_idx = a.comp_idx; j.comp_flux = a.comp_flux;
+    j.slots = a.xslots; j.slot_pad = a.slot_pad; j.cs = a.cs;
+    j.dstat = a.dstat; j.partial = a.partial;
+    run_plain<K, V, PT>(j, role & 0xFFFF, y);
+}
+
+// Many independent images in one launch.  Problems are laid out largest
+// first; problem i owns the seats [seat0[i], seat0[i+1]) and each seat is one
+// workgroup of its cluster.  A workgroup takes the next seat from a device
+// counter, runs that problem with its cluster, then takes another.  Seats go
+// out in order and every workgroup is resident, so the earliest unfinished
+// problem always has its seats held by running workgroups: no deadlock.
+template <int K, int V, typename PT>
+__global__ void __launch_bounds__(WG) batched_kernel(const BatchArgs b)
+{
+    __shared__ int s_seat;
+    const Sync y{b.ctl, b.timeout_ticks};
+    const int total = b.seat0[b.n];
+    for (;;) {
+        if (threadIdx.x == 0)
+            s_seat = (int)__hip_atomic_fetch_add(&b.ctl->seat, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __syncthreads();
+        const int seat = s_seat;
+        __syncthreads();
+        if (seat >= total) return;
+        int lo = 0, hi = b.n;                   // seat0[lo] <= seat < seat0[lo + 1]
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (b.seat0[mid] <= seat) lo = mid; else hi = mid;
+        }
+        const PlainJob j = b.jobs[lo];
+        if (!run_plain<K, V, PT>(j, seat - b.seat0[lo], y)) return;
+        if (aborted(y)) return;
     }
 }
 
@@ -484,6 +556,8 @@ __global__ void __launch_bounds__(WG) tiled_kernel(const KArgs a)
     __shared__ int32_t s_off[MAX_TILES + 1];    // exclusive prefix of per-tile counts
     extern __shared__ __align__(16) unsigned char s_dyn[];
 
+    const Sync y{a.ctl, a.timeout_ticks};
+    const Img im{a.dirty, a.residual, a.model, a.accbuf, a.psf, a.psf_bytes, a.nx, a.psf_nx, a.cy, a.cx};
     const int32_t role = a.role[blockIdx.x];
     const bool is_cluster = role >= 0;
     const int tile = is_cluster ? (role >> 16) : -1;
@@ -508,16 +582,18 @@ __global__ void __launch_bounds__(WG) tiled_kernel(const KArgs a)
         R.cs = cs;
         R.rank = rank;
         tile_rect(a, tile, R.y0, R.x0, R.h, R.w);
-        R.load(a);
-        if (!cluster_max(a, slots, cs, rank, e++, wg_max_key(R.local_key(), s_red), &s_bcast, &s_ok, cur)) return;
+        R.load(im);
+        if (!cluster_max(y, slots, a.slot_pad, cs, rank, e++, wg_max_key(R.local_key(), s_red), &s_bcast, &s_ok, cur))
+            return;
         if (tile_leader_wg && threadIdx.x == 0) a.tile_key[tile] = cur;
     }
-    if (!grid_barrier(a, epoch, &s_ok)) return;
+    if (!grid_barrier(y, epoch, &s_ok)) return;
 
     const int64_t limit = a.max_iter < a.cap ? a.max_iter : a.cap;
     int64_t used = 0;
     int32_t rounds = 0, stop = STOP_MAXITER;
     double mflux = 0.0;
+    uint64_t ph_local = 0, ph_gather = 0, ph_apply = 0, tp0 = 0, tp1 = 0;
     for (;;) {
         // ---- round control, computed identically by every workgroup
         int na_part = 0, rk_part = 0;
@@ -541,6 +617,7 @@ __global__ void __launch_bounds__(WG) tiled_kernel(const KArgs a)
         }
 
         // ---- local minor loops
+        if (blockIdx.x == 0) tp0 = wall_clock64();
         if (is_cluster) {
             int L = 0;
             for (int64_t it = 0; it < budget; ++it) {
@@ -553,11 +630,11 @@ __global__ void __launch_bounds__(WG) tiled_kernel(const KArgs a)
                 const int32_t img = py * a.nx + px;
                 if (tile_leader_wg && threadIdx.x == 0) { l_idx[L] = img; l_flux[L] = c; }
                 if (a.model && R.owns(fp)) a.model[img] += (double)c;
-                R.subtract(a, py, px, c);
+                R.subtract(im, py, px, c);
                 L += 1;
                 if (it + 1 < budget) {
                     const uint64_t wk = wg_max_key(R.local_key(), s_red);
-                    if (!cluster_max(a, slots, cs, rank, e++, wk, &s_bcast, &s_ok, cur)) return;
+                    if (!cluster_max(y, slots, a.slot_pad, cs, rank, e++, wk, &s_bcast, &s_ok, cur)) return;
                 }
             }
             if (tile_leader_wg) {
@@ -565,7 +642,8 @@ __global__ void __launch_bounds__(WG) tiled_kernel(const KArgs a)
                 aggregate_round(a, tile, L, l_idx, l_flux, l_tmp, l_sum, &s_cnt);
             }
         }
-        if (!grid_barrier(a, epoch, &s_ok)) return;                        // A
+        if (!grid_barrier(y, epoch, &s_ok)) return;                        // A
+        if (blockIdx.x == 0) { tp1 = wall_clock64(); ph_local += tp1 - tp0; tp0 = tp1; }
 
         // ---- round bookkeeping: every workgroup reads the counts
         for (int t = threadIdx.x; t < T; t += WG) s_off[t + 1] = a.rb_n[t];
@@ -674,33 +752,23 @@ __global__ void __launch_bounds__(WG) tiled_kernel(const KArgs a)
                 }
             }
         }
-        if (!grid_barrier(a, epoch, &s_ok)) return;                        // B
+        if (!grid_barrier(y, epoch, &s_ok)) return;                        // B
+        if (blockIdx.x == 0) { tp1 = wall_clock64(); ph_gather += tp1 - tp0; tp0 = tp1; }
 
         // ---- apply feedback and find each tile's new peak
         if (is_cluster) {
-            R.apply_feedback(a);
+            R.apply_feedback(im);
             const uint64_t wk = wg_max_key(R.local_key(), s_red);
-            if (!cluster_max(a, slots, cs, rank, e++, wk, &s_bcast, &s_ok, cur)) return;
+            if (!cluster_max(y, slots, a.slot_pad, cs, rank, e++, wk, &s_bcast, &s_ok, cur)) return;
             if (tile_leader_wg && threadIdx.x == 0) a.tile_key[tile] = cur;
         }
         rounds += 1;
-        if (!grid_barrier(a, epoch, &s_ok)) return;                        // C
+        if (!grid_barrier(y, epoch, &s_ok)) return;                        // C
+        if (blockIdx.x == 0) { tp1 = wall_clock64(); ph_apply += tp1 - tp0; }
     }
 
     // ---- results
-    if (is_cluster) {
-        double ss;
-        R.store(a, ss);
-        ss = wave_sum64f(ss);
-        __shared__ double s_ss[NWAVES];
-        if ((threadIdx.x & 63) == 0) s_ss[threadIdx.x >> 6] = ss;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            double tot = 0.0;
-            for (int w = 0; w < NWAVES; ++w) tot += s_ss[w];
-            a.partial[tile * cs + rank] = tot;
-        }
-    }
+    if (is_cluster) store_and_sum(R, im, a.partial, tile * cs + rank);
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         uint64_t best = a.tile_key[0];
         for (int t = 1; t < T; ++t) {
@@ -710,6 +778,9 @@ __global__ void __launch_bounds__(WG) tiled_kernel(const KArgs a)
         a.dstat->n_iter = used;
         a.dstat->stop = stop;
         a.dstat->n_rounds = rounds;
+        a.dstat->phase_ticks[0] = ph_local;
+        a.dstat->phase_ticks[1] = ph_gather;
+        a.dstat->phase_ticks[2] = ph_apply;
         a.dstat->final_peak = (double)key_value(best);
         a.dstat->model_flux = mflux;
     }
@@ -749,10 +820,21 @@ __global__ void finalize_kernel(const double *partial, int n, DevStat *st)
     }
 }
 
+// The same for every problem of a batch (one thread per problem).
+__global__ void finalize_batch_kernel(const PlainJob *jobs, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double s = 0.0;
+    for (int r = 0; r < jobs[i].cs; ++r) s += jobs[i].partial[r];
+    jobs[i].dstat->sumsq = s;
+}
+
 // ----------------------------------------------------- instantiations ----
 
 #define INST(K, V, PT)                                                       \
     template __global__ void hogbom_kernel<K, V, PT>(const KArgs a);        \
+    template __global__ void batched_kernel<K, V, PT>(const BatchArgs b);   \
     template __global__ void tiled_kernel<K, V, PT>(const KArgs a);
 
 #define INST_ALL_K(V, PT) INST(1, V, PT) INST(2, V, PT) INST(4, V, PT) INST(8, V, PT) INST(16, V, PT)

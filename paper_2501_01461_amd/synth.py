@@ -99,7 +99,9 @@ def y_array_psf(M: int, rng: np.random.Generator, n_samples: int = 1,
         iv = np.floor(v + 0.5).astype(np.int64)
         np.add.at(grid, (iv % M, iu % M), 1.0)
         np.add.at(grid, ((-iv) % M, (-iu) % M), 1.0)
-    img = np.real(np.fft.ifft2(grid))
+    # the grid is real and symmetric under (u, v) -> (-u, -v), so its inverse
+    # FFT is real: take it from the half spectrum
+    img = _irfft2(grid[:, :M // 2 + 1], s=(M, M))
     img = np.fft.fftshift(img)
     img /= img[M // 2, M // 2]
     return img

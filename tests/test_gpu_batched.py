@@ -1,0 +1,101 @@
+"""GPU parity of the batched form: every problem of one persistent launch is
+bit-identical to the CPU oracle run on that problem alone."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2501_01461_amd import synth
+from tests.gpu_util import announce, assert_same_run, bits, dev, host
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    import paper_2501_01461_amd as P
+    P.load()
+    return P
+
+
+def random_problem(seed, ny, nx, thr, n):
+    r = np.random.default_rng([31, seed])
+    d = r.normal(0, 0.02, (ny, nx)) + (r.random((ny, nx)) < 0.03) * r.uniform(-2, 2, (ny, nx))
+    psf = synth.random_psf(2 * ny + 2 * (seed % 3), 2 * nx + 2 * (seed % 2), r, 0.3)
+    return dict(dirty=d.astype(np.float32), psf=psf.astype(np.float32), threshold=thr, max_iter=n)
+
+
+def to_dev(problems):
+    return [dict(dirty=dev(p["dirty"]), psf=dev(p["psf"]), threshold=p["threshold"], max_iter=p["max_iter"],
+                 **({"cap": p["cap"]} if "cap" in p else {})) for p in problems]
+
+
+def test_batched_uneven_scalar_groups(lib):
+    """Mixed sizes, some widths not a multiple of 4 (the whole batch uses 1-wide groups)."""
+    sizes = [(20, 30), (64, 64), (33, 47), (100, 80), (8, 8), (150, 122), (64, 12), (90, 90)]
+    probs = [random_problem(i, ny, nx, 0.05 * (i % 2), 60 + 25 * i) for i, (ny, nx) in enumerate(sizes)]
+    probs[3]["cap"] = 20
+    announce("batched scalar", sizes)
+    outs = lib.batched(to_dev(probs), gain=0.1)
+    for p, o in zip(probs, outs):
+        ref = oracle.hogbom(p["dirty"], p["psf"], 0.1, p["threshold"], p["max_iter"], cap=p.get("cap"))
+        assert_same_run(o, ref)
+
+
+@pytest.mark.parametrize("ppt", [0, 8, 64])
+def test_batched_y_array_problems(lib, ppt):
+    """Own Y-array PSF per problem, threshold stops, several launch shapes."""
+    sides = [64, 256, 128, 96, 192, 64, 320, 128, 256, 64, 160, 96]
+    probs = []
+    for i, s in enumerate(sides):
+        d, p, _ = synth.make_problem(s, 5 + 3 * i, 0.01, 2.1, (), 1e-3, config=93, problem=i)
+        probs.append(dict(dirty=d, psf=p, threshold=5e-3, max_iter=3000))
+    announce("batched y-array", ppt)
+    outs = lib.batched(to_dev(probs), gain=0.1, px_per_thread=ppt)
+    for p, o in zip(probs, outs):
+        ref = oracle.hogbom(p["dirty"], p["psf"], 0.1, p["threshold"], p["max_iter"])
+        assert ref["stop"] == 1
+        assert_same_run(o, ref)
+
+
+def test_batched_equals_single_calls(lib):
+    probs = [random_problem(40 + i, 48 + 16 * i, 64, 0.0, 150) for i in range(6)]
+    announce("batched vs single")
+    outs = lib.batched(to_dev(probs))
+    for p, o in zip(probs, outs):
+        s = lib.hogbom(dev(p["dirty"]), dev(p["psf"]), 0.1, 0.0, p["max_iter"])
+        assert np.array_equal(host(o["idx"]), host(s["idx"]))
+        assert np.array_equal(bits(host(o["flux"])), bits(host(s["flux"])))
+        assert np.array_equal(bits(host(o["residual"])), bits(host(s["residual"])))
+
+
+def test_batched_fp16_psfs(lib):
+    sides = [64, 128, 96]
+    probs, refs = [], []
+    for i, s in enumerate(sides):
+        d, p, _ = synth.make_problem(s, 10, 0.01, 2.1, (), 1e-3, config=94, problem=i)
+        probs.append(dict(dirty=dev(d), psf=lib.psf_to_f16(dev(p)), threshold=5e-3, max_iter=2000))
+        refs.append(oracle.hogbom(d, p.astype(np.float16).astype(np.float32), 0.1, 5e-3, 2000))
+    announce("batched fp16")
+    outs = lib.batched(probs)
+    for o, ref in zip(outs, refs):
+        assert_same_run(o, ref)
+
+
+def test_batched_config3_sampled(lib):
+    """The 256-problem workload (sides 128..1024, own PSFs, threshold 5 sigma) in
+    one launch; a spread sample of problems is checked against the oracle."""
+    announce("batched config3")
+    probs = synth.make_batch(256)
+    dprobs = [dict(dirty=dev(p["dirty"]), psf=dev(p["psf"]), threshold=p["threshold"], max_iter=100000)
+              for p in probs]
+    outs = lib.batched(dprobs)
+    assert all(o["stats"]["stop_reason"] == 1 for o in outs)
+    order = sorted(range(len(probs)), key=lambda i: probs[i]["n"])
+    sample = order[::37][:6] + [order[-1]]
+    for i in sample:
+        p = probs[i]
+        ref = oracle.hogbom(p["dirty"], p["psf"], 0.1, p["threshold"], 100000)
+        assert_same_run(outs[i], ref)
