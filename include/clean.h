@@ -79,7 +79,9 @@ typedef enum {
 typedef enum { CLEAN_PSF_F32 = 0, CLEAN_PSF_F16 = 1 } clean_psf_dtype;
 
 enum {
-    CLEAN_FLAG_CHECK_FINITE = 1   /* scan inputs for NaN/Inf before starting   */
+    CLEAN_FLAG_CHECK_FINITE = 1,   /* scan inputs for NaN/Inf before starting      */
+    CLEAN_FLAG_STREAM_RESIDUAL = 2 /* keep the residual in HBM even when it would
+                                      fit the register file (plain and tiled)     */
 };
 
 typedef struct {
@@ -90,7 +92,8 @@ typedef struct {
     int32_t flags;        /* CLEAN_FLAG_* bits                                    */
     int32_t wg_per_tile;  /* launch shape: workgroups per tile (0 = library pick) */
     int32_t px_per_thread;/* launch shape: residual pixels per thread, one of
-                             4, 8, 16, 32, 64 (0 = library pick)              */
+                             4, 8, 16, 32, 64 when tile widths are multiples of
+                             4, else 4, 16, 32 (0 = library pick)             */
 } clean_params;
 
 typedef struct {
@@ -107,6 +110,9 @@ typedef struct {
     float phase_us[3];    /* tiled: device time in the local loops, the feedback
                              gather and the apply + re-peak phases, summed over
                              rounds (microseconds, wall clock); 0 for plain       */
+    int32_t streamed;     /* 1: the residual was kept in HBM (image too large for
+                             the register file of the co-resident workgroups);
+                             0: held in registers for the whole run              */
 } clean_stats;
 
 /*
@@ -125,7 +131,9 @@ typedef struct {
  *   workspace  device scratch of workspace_bytes (>= clean_workspace_size()),
  *              or NULL to use a library-owned buffer.
  *   stats      host output, may be NULL.
- * Limits: ny*nx <= 2^28 - 1; psf byte size < 2^32.
+ * Limits: ny*nx <= 2^28 - 1; (ny-1)*psf_nx + nx < 2^31 / element size.
+ * Images whose residual fits the register file of the co-resident workgroups
+ * keep it there for the whole run; larger ones stream it through `residual`.
  */
 int clean_hogbom(const float *dirty, int ny, int nx,
                  const void *psf, int psf_ny, int psf_nx,

@@ -19,6 +19,7 @@ STATUS = {0: "CLEAN_OK", -1: "CLEAN_E_INVAL", -2: "CLEAN_E_NONFINITE", -3: "CLEA
 STOP_NAMES = {0: "maxiter", 1: "threshold", 2: "capacity"}
 PSF_F32, PSF_F16 = 0, 1
 FLAG_CHECK_FINITE = 1
+FLAG_STREAM_RESIDUAL = 2
 
 # every symbol include/clean.h declares
 EXPORTS = ("clean_hogbom", "clean_tiled_feedback", "clean_batched", "clean_workspace_size",
@@ -35,7 +36,7 @@ class Stats(C.Structure):
     _fields_ = [("n_iter", C.c_int64), ("stop_reason", C.c_int32), ("n_rounds", C.c_int32),
                 ("final_peak", C.c_double), ("residual_rms", C.c_double), ("model_flux", C.c_double),
                 ("device_ms", C.c_float), ("wg_per_tile", C.c_int32), ("px_per_thread", C.c_int32),
-                ("workgroups", C.c_int32), ("phase_us", C.c_float * 3)]
+                ("workgroups", C.c_int32), ("phase_us", C.c_float * 3), ("streamed", C.c_int32)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_}
@@ -139,15 +140,18 @@ def _outputs(dirty, cap, model):
     return res, idx, flux, mod
 
 
+def _flags(check_finite, stream):
+    return (FLAG_CHECK_FINITE if check_finite else 0) | (FLAG_STREAM_RESIDUAL if stream else 0)
+
+
 def hogbom(dirty, psf, gain=0.1, threshold=0.0, max_iter=1000, cap=None, model=True, check_finite=False,
-           wg_per_tile=0, px_per_thread=0, out=None):
+           wg_per_tile=0, px_per_thread=0, stream=False, out=None):
     """Plain Hogbom CLEAN; returns dict(residual, idx, flux, model, stats)."""
     lib = load()
     dirty, psf = _prep(dirty, psf)
     cap = int(max_iter if cap is None else cap)
     res, idx, flux, mod = out if out is not None else _outputs(dirty, cap, model)
-    p = _params(gain, threshold, max_iter, psf, FLAG_CHECK_FINITE if check_finite else 0, wg_per_tile,
-                px_per_thread)
+    p = _params(gain, threshold, max_iter, psf, _flags(check_finite, stream), wg_per_tile, px_per_thread)
     st = Stats()
     ny, nx = dirty.shape
     _check(lib.clean_hogbom(_ptr(dirty), ny, nx, _ptr(psf), psf.shape[0], psf.shape[1], C.byref(p), _ptr(res),
@@ -157,14 +161,13 @@ def hogbom(dirty, psf, gain=0.1, threshold=0.0, max_iter=1000, cap=None, model=T
 
 
 def tiled_feedback(dirty, psf, tiles=(2, 2), interval=100, gain=0.1, threshold=0.0, max_iter=1000, cap=None,
-                   model=True, check_finite=False, wg_per_tile=0, px_per_thread=0, out=None):
+                   model=True, check_finite=False, wg_per_tile=0, px_per_thread=0, stream=False, out=None):
     """Tiled Hogbom CLEAN with feedback; returns dict(residual, idx, flux, model, stats)."""
     lib = load()
     dirty, psf = _prep(dirty, psf)
     cap = int(max_iter if cap is None else cap)
     res, idx, flux, mod = out if out is not None else _outputs(dirty, cap, model)
-    p = _params(gain, threshold, max_iter, psf, FLAG_CHECK_FINITE if check_finite else 0, wg_per_tile,
-                px_per_thread)
+    p = _params(gain, threshold, max_iter, psf, _flags(check_finite, stream), wg_per_tile, px_per_thread)
     st = Stats()
     ny, nx = dirty.shape
     _check(lib.clean_tiled_feedback(_ptr(dirty), ny, nx, _ptr(psf), psf.shape[0], psf.shape[1], int(tiles[0]),

@@ -18,9 +18,11 @@
 #include "clean_device.h"
 
 namespace cleanhip {
-template <int K, int V, typename PT> __global__ void hogbom_kernel(const KArgs a);
-template <int K, int V, typename PT> __global__ void tiled_kernel(const KArgs a);
-template <int K, int V, typename PT> __global__ void batched_kernel(const BatchArgs b);
+template <int K, int V, typename PT> struct RegTile;
+template <int K, int V, typename PT> struct StreamTile;
+template <class Tile> __global__ void hogbom_kernel(const KArgs a);
+template <class Tile> __global__ void tiled_kernel(const KArgs a);
+template <class Tile> __global__ void batched_kernel(const BatchArgs b);
 __global__ void finalize_batch_kernel(const PlainJob *jobs, int n);
 __global__ void finite_check_kernel(const float *x, int64_t n, uint32_t *flag);
 __global__ void finite_check_half_kernel(const unsigned short *x, int64_t n, uint32_t *flag);
@@ -124,17 +126,17 @@ template <int V, typename PT> KFn plain_fn(int K)
 {
     if constexpr (V == 4) {
         switch (K) {
-        case 1: return hogbom_kernel<1, 4, PT>;
-        case 2: return hogbom_kernel<2, 4, PT>;
-        case 4: return hogbom_kernel<4, 4, PT>;
-        case 8: return hogbom_kernel<8, 4, PT>;
-        case 16: return hogbom_kernel<16, 4, PT>;
+        case 1: return hogbom_kernel<RegTile<1, 4, PT>>;
+        case 2: return hogbom_kernel<RegTile<2, 4, PT>>;
+        case 4: return hogbom_kernel<RegTile<4, 4, PT>>;
+        case 8: return hogbom_kernel<RegTile<8, 4, PT>>;
+        case 16: return hogbom_kernel<RegTile<16, 4, PT>>;
         }
     } else {
         switch (K) {
-        case 4: return hogbom_kernel<4, 1, PT>;
-        case 16: return hogbom_kernel<16, 1, PT>;
-        case 64: return hogbom_kernel<64, 1, PT>;
+        case 4: return hogbom_kernel<RegTile<4, 1, PT>>;
+        case 16: return hogbom_kernel<RegTile<16, 1, PT>>;
+        case 32: return hogbom_kernel<RegTile<32, 1, PT>>;
         }
     }
     return nullptr;
@@ -144,17 +146,17 @@ template <int V, typename PT> KFn tiled_fn(int K)
 {
     if constexpr (V == 4) {
         switch (K) {
-        case 1: return tiled_kernel<1, 4, PT>;
-        case 2: return tiled_kernel<2, 4, PT>;
-        case 4: return tiled_kernel<4, 4, PT>;
-        case 8: return tiled_kernel<8, 4, PT>;
-        case 16: return tiled_kernel<16, 4, PT>;
+        case 1: return tiled_kernel<RegTile<1, 4, PT>>;
+        case 2: return tiled_kernel<RegTile<2, 4, PT>>;
+        case 4: return tiled_kernel<RegTile<4, 4, PT>>;
+        case 8: return tiled_kernel<RegTile<8, 4, PT>>;
+        case 16: return tiled_kernel<RegTile<16, 4, PT>>;
         }
     } else {
         switch (K) {
-        case 4: return tiled_kernel<4, 1, PT>;
-        case 16: return tiled_kernel<16, 1, PT>;
-        case 64: return tiled_kernel<64, 1, PT>;
+        case 4: return tiled_kernel<RegTile<4, 1, PT>>;
+        case 16: return tiled_kernel<RegTile<16, 1, PT>>;
+        case 32: return tiled_kernel<RegTile<32, 1, PT>>;
         }
     }
     return nullptr;
@@ -166,17 +168,17 @@ template <int V, typename PT> BFn batched_fn(int K)
 {
     if constexpr (V == 4) {
         switch (K) {
-        case 1: return batched_kernel<1, 4, PT>;
-        case 2: return batched_kernel<2, 4, PT>;
-        case 4: return batched_kernel<4, 4, PT>;
-        case 8: return batched_kernel<8, 4, PT>;
-        case 16: return batched_kernel<16, 4, PT>;
+        case 1: return batched_kernel<RegTile<1, 4, PT>>;
+        case 2: return batched_kernel<RegTile<2, 4, PT>>;
+        case 4: return batched_kernel<RegTile<4, 4, PT>>;
+        case 8: return batched_kernel<RegTile<8, 4, PT>>;
+        case 16: return batched_kernel<RegTile<16, 4, PT>>;
         }
     } else {
         switch (K) {
-        case 4: return batched_kernel<4, 1, PT>;
-        case 16: return batched_kernel<16, 1, PT>;
-        case 64: return batched_kernel<64, 1, PT>;
+        case 4: return batched_kernel<RegTile<4, 1, PT>>;
+        case 16: return batched_kernel<RegTile<16, 1, PT>>;
+        case 32: return batched_kernel<RegTile<32, 1, PT>>;
         }
     }
     return nullptr;
@@ -186,6 +188,16 @@ BFn pick_batched(bool half, int V, int K)
 {
     if (V == 4) return half ? batched_fn<4, __half>(K) : batched_fn<4, float>(K);
     return half ? batched_fn<1, __half>(K) : batched_fn<1, float>(K);
+}
+
+KFn pick_stream(bool tiled, bool half, int V)
+{
+    if (tiled) {
+        if (V == 4) return half ? tiled_kernel<StreamTile<STREAM_K, 4, __half>> : tiled_kernel<StreamTile<STREAM_K, 4, float>>;
+        return half ? tiled_kernel<StreamTile<STREAM_K, 1, __half>> : tiled_kernel<StreamTile<STREAM_K, 1, float>>;
+    }
+    if (V == 4) return half ? hogbom_kernel<StreamTile<STREAM_K, 4, __half>> : hogbom_kernel<StreamTile<STREAM_K, 4, float>>;
+    return half ? hogbom_kernel<StreamTile<STREAM_K, 1, __half>> : hogbom_kernel<StreamTile<STREAM_K, 1, float>>;
 }
 
 KFn pick(bool tiled, bool half, int V, int K)
@@ -201,13 +213,13 @@ KFn pick(bool tiled, bool half, int V, int K)
 bool valid_ppt(int V, int ppt)
 {
     if (V == 4) return ppt == 4 || ppt == 8 || ppt == 16 || ppt == 32 || ppt == 64;
-    return ppt == 4 || ppt == 16 || ppt == 64;
+    return ppt == 4 || ppt == 16 || ppt == 32;
 }
 
 // Launch shape for a tile of npix pixels: workgroups per cluster (cs) and
 // pixels per thread (ppt = K*V).  Small clusters keep the per-iteration
 // exchange short; the pixels per thread bound each workgroup's PSF traffic.
-int choose_shape(int64_t npix, int V, int user_cs, int user_ppt, int &cs, int &ppt)
+int choose_shape(int64_t npix, int V, int user_cs, int user_ppt, int max_ppt, int &cs, int &ppt)
 {
     if (user_ppt) {
         if (!valid_ppt(V, user_ppt))
@@ -217,23 +229,25 @@ int choose_shape(int64_t npix, int V, int user_cs, int user_ppt, int &cs, int &p
         cs = user_cs ? user_cs : (int)((npix + (int64_t)WG * ppt - 1) / ((int64_t)WG * ppt));
     } else if (user_cs) {
         cs = user_cs;
-        const int opts4[] = {4, 8, 16, 32, 64}, opts1[] = {4, 16, 64};
+        const int opts4[] = {4, 8, 16, 32, 64}, opts1[] = {4, 16, 32};
         const int *opts = V == 4 ? opts4 : opts1;
-        const int nopt = V == 4 ? 5 : 3;
+        int nopt = V == 4 ? 5 : 3;
+        while (nopt > 1 && opts[nopt - 1] > max_ppt) --nopt;
         ppt = opts[nopt - 1];
         for (int i = 0; i < nopt; ++i)
             if ((int64_t)cs * WG * opts[i] >= npix) { ppt = opts[i]; break; }
     } else {
-        const int opts4[] = {4, 8, 16, 32, 64}, opts1[] = {4, 16, 64};
+        const int opts4[] = {4, 8, 16, 32, 64}, opts1[] = {4, 16, 32};
         const int *opts = V == 4 ? opts4 : opts1;
-        const int nopt = V == 4 ? 5 : 3;
-        // smallest ppt up to 32 that fits one workgroup, else 32 px/thread with
-        // as many workgroups as needed, growing ppt when clusters get large
+        int nopt = V == 4 ? 5 : 3;
+        while (nopt > 1 && opts[nopt - 1] > max_ppt) --nopt;
+        // smallest ppt that fits one workgroup, else 32 px/thread with as many
+        // workgroups as needed, growing ppt (up to max_ppt) when clusters get large
         ppt = 0;
         for (int i = 0; i < nopt; ++i)
-            if ((int64_t)WG * opts[i] >= npix && opts[i] <= 64) { ppt = opts[i]; cs = 1; break; }
+            if ((int64_t)WG * opts[i] >= npix) { ppt = opts[i]; cs = 1; break; }
         if (!ppt) {
-            ppt = V == 4 ? 32 : 16;
+            ppt = std::min(V == 4 ? 32 : 16, max_ppt);
             cs = (int)((npix + (int64_t)WG * ppt - 1) / ((int64_t)WG * ppt));
             while (cs > 16 && ppt < opts[nopt - 1]) {
                 for (int i = 0; i < nopt; ++i)
@@ -319,53 +333,79 @@ int run(bool tiled, const float *dirty, int ny, int nx, const void *psf, int psf
             if (w % 4) w4 = false;
         }
     const int V = w4 ? 4 : 1;
-    int cs = 0, ppt = 0;
-    st = choose_shape(max_tile, V, p->wg_per_tile, p->px_per_thread, cs, ppt);
-    if (st) return st;
-    const int K = ppt / V;
     const bool half = p->psf_dtype == CLEAN_PSF_F16;
-    KFn fn = pick(tiled, half, V, K);
-    if (!fn) return fail(CLEAN_E_UNSUPPORTED, "no kernel for %d x %d pixels per thread", K, V);
-
     const size_t dyn_lds = tiled ? std::max((size_t)16 * interval, (size_t)8 * GATHER_CHUNK) : 0;
-    int occ = 0;
-    HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void *)fn, WG, dyn_lds));
-    const int max_wg = occ * ncu;
 
-    // placement: cluster c lives on XCD c % 8 (workgroup b runs on XCD b % 8)
-    int W;
-    std::vector<int32_t> role;
-    if (!tiled) {
-        W = cs;
-        if (W > max_wg) return fail(CLEAN_E_UNSUPPORTED, "%d workgroups cannot be co-resident (max %d)", W, max_wg);
-        role.resize(W);
-        for (int b = 0; b < W; ++b) role[b] = b;
-    } else {
+    // placement: cluster c lives on XCD c % 8 (workgroup b runs on XCD b % 8);
+    // tiled launches add helper workgroups for the feedback gather
+    auto place = [&](int cs, int max_wg, int &W, std::vector<int32_t> &role) -> bool {
+        if (!tiled) {
+            W = cs;
+            if (W > max_wg) return false;
+            role.resize(W);
+            for (int b = 0; b < W; ++b) role[b] = b;
+            return true;
+        }
         std::vector<int> need(8, 0);
         for (int c = 0; c < T; ++c) need[c % 8] += cs;
-        int per_xcd = *std::max_element(need.begin(), need.end());
-        W = 8 * per_xcd;
-        const int helpers_target = std::min(max_wg, 2 * ncu);   // workgroups for the feedback gather
-        if (W < helpers_target) W = helpers_target / 8 * 8;
+        W = 8 * *std::max_element(need.begin(), need.end());
+        const int helpers_target = std::min(max_wg, 2 * ncu) / 8 * 8;
+        if (W < helpers_target) W = helpers_target;
         if (W > max_wg) {
-            // fall back to packing clusters without XCD affinity
-            W = T * cs;
-            if (W > max_wg) return fail(CLEAN_E_UNSUPPORTED, "%d workgroups cannot be co-resident (max %d)", W, max_wg);
+            W = T * cs;                      // pack without XCD affinity
+            if (W > max_wg) return false;
             role.assign(W, -1);
             for (int c = 0; c < T; ++c)
                 for (int g = 0; g < cs; ++g) role[c * cs + g] = (c << 16) | g;
-        } else {
-            per_xcd = W / 8;
-            role.assign(W, -1);
-            std::vector<int> fill(8, 0);
-            for (int c = 0; c < T; ++c) {
-                const int x = c % 8;
-                for (int g = 0; g < cs; ++g) {
-                    const int j = fill[x]++;
-                    role[x + 8 * j] = (c << 16) | g;
-                }
-            }
+            return true;
         }
+        role.assign(W, -1);
+        std::vector<int> fill(8, 0);
+        for (int c = 0; c < T; ++c) {
+            const int x = c % 8;
+            for (int g = 0; g < cs; ++g) role[x + 8 * fill[x]++] = (c << 16) | g;
+        }
+        return true;
+    };
+
+    // register-resident residual when the launch fits, else streamed through HBM
+    int cs = 0, ppt = 0, W = 0;
+    bool streamed = false;
+    KFn fn = nullptr;
+    std::vector<int32_t> role;
+    const bool force_stream = (p->flags & CLEAN_FLAG_STREAM_RESIDUAL) != 0;
+    if (force_stream && p->px_per_thread)
+        return fail(CLEAN_E_INVAL, "px_per_thread applies to the register-resident form only");
+    st = force_stream ? CLEAN_E_UNSUPPORTED
+                      : choose_shape(max_tile, V, p->wg_per_tile, p->px_per_thread, tiled ? 32 : 64, cs, ppt);
+    if (st == CLEAN_OK) {
+        fn = pick(tiled, half, V, ppt / V);
+        if (!fn) return fail(CLEAN_E_UNSUPPORTED, "no kernel for %d pixels per thread", ppt);
+        int occ = 0;
+        HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void *)fn, WG, dyn_lds));
+        if (!place(cs, occ * ncu, W, role)) {
+            if (p->px_per_thread)
+                return fail(CLEAN_E_UNSUPPORTED, "%d x %d workgroups cannot be co-resident (max %d)", T, cs, occ * ncu);
+            streamed = true;
+        }
+    } else if (p->px_per_thread == 0) {
+        streamed = true;
+    } else {
+        return st;
+    }
+    if (streamed) {
+        g_last_error.clear();
+        fn = pick_stream(tiled, half, V);
+        int occ = 0;
+        HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void *)fn, WG, dyn_lds));
+        const int max_wg = occ * ncu;
+        const int64_t per_wg = (int64_t)WG * STREAM_K * V;
+        const int64_t need = (max_tile + per_wg - 1) / per_wg;
+        if (p->wg_per_tile) cs = p->wg_per_tile;
+        else cs = (int)std::max<int64_t>(1, std::min<int64_t>(need, tiled ? std::max(1, max_wg / T) : 128));
+        ppt = 0;
+        if (cs > 4096 || !place(cs, max_wg, W, role))
+            return fail(CLEAN_E_UNSUPPORTED, "%d x %d streaming workgroups cannot be co-resident (max %d)", T, cs, max_wg);
     }
 
     const int slot_pad = (cs + 31) / 32 * 32;
@@ -471,6 +511,7 @@ int run(bool tiled, const float *dirty, int ny, int nx, const void *psf, int psf
         stats->wg_per_tile = cs;
         stats->px_per_thread = ppt;
         stats->workgroups = W;
+        stats->streamed = streamed;
         const double us_per_tick = 1e6 / (double)(a.timeout_ticks / 20ull);
         for (int i = 0; i < 3; ++i) stats->phase_us[i] = (float)(ds.phase_ticks[i] * us_per_tick);
     }
@@ -663,6 +704,7 @@ int clean_batched(const clean_problem *probs, int n, const clean_params *shared,
             s.wg_per_tile = cs[i];
             s.px_per_thread = ppt;
             s.workgroups = W;
+            s.streamed = 0;
         }
     }
     return CLEAN_OK;

@@ -240,7 +240,12 @@ struct Img {
     int nx, psf_nx, cy, cx;
 };
 
+// Residual held in VGPRs: thread t of cluster rank g owns K groups of V
+// consecutive pixels, group k at tile-local index ((k*cs + g)*WG + t)*V.
 template <int K, int V, typename PT> struct RegTile {
+    static constexpr bool kResident = true;
+    static constexpr int kV = V;
+    using psf_t = PT;
     float r[K][V];
     int32_t qoff[K];        // (y)*psf_nx + (x) of the group's first pixel, image coords
     uint64_t valid;         // bit k: group k inside the tile
@@ -252,8 +257,9 @@ template <int K, int V, typename PT> struct RegTile {
         return (uint32_t)(((k * cs + rank) * WG + (int)threadIdx.x) * V);
     }
 
-    __device__ void load(const Img &a)
+    __device__ void init(const Img &a, int ty0, int tx0, int th, int tw, int ncs, int rk)
     {
+        y0 = ty0; x0 = tx0; h = th; w = tw; cs = ncs; rank = rk;
         valid = 0;
         const int hw = h * w;
 #pragma unroll
@@ -278,9 +284,10 @@ template <int K, int V, typename PT> struct RegTile {
         }
     }
 
-    __device__ void store(const Img &a, double &sumsq) const
+    // Writes the residual out; returns this thread's sum of squares.
+    __device__ double finish(const Img &a) const
     {
-        sumsq = 0.0;
+        double sumsq = 0.0;
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             if (valid & (1ull << k)) {
@@ -294,10 +301,11 @@ template <int K, int V, typename PT> struct RegTile {
                 }
             }
         }
+        return sumsq;
     }
 
     // Thread-local peak key over the owned pixels (lowest f wins ties).
-    __device__ __forceinline__ uint64_t local_key() const
+    __device__ __forceinline__ uint64_t key(const Img &) const
     {
         if (!(valid & 1ull)) return 0;
         uint32_t bb = __float_as_uint(r[0][0]);
@@ -316,8 +324,8 @@ template <int K, int V, typename PT> struct RegTile {
         return make_key(bb, bf);
     }
 
-    // r -= c * PSF centred on image pixel (py, px).
-    __device__ __forceinline__ void subtract(const Img &a, int py, int px, float c)
+    // r -= c * PSF centred on image pixel (py, px); then, if asked, the new key.
+    __device__ __forceinline__ uint64_t subtract(const Img &a, int py, int px, float c, bool want_key)
     {
         const int64_t w0 = (int64_t)(a.cy - py) * a.psf_nx + (a.cx - px);
         const char *base = (const char *)a.psf + w0 * (int64_t)sizeof(PT);
@@ -329,10 +337,11 @@ template <int K, int V, typename PT> struct RegTile {
         for (int k = 0; k < K; ++k)
 #pragma unroll
             for (int e = 0; e < V; ++e) r[k][e] = __builtin_fmaf(-c, pv[k][e], r[k][e]);
+        return want_key ? key(a) : 0;
     }
 
-    // r -= acc (float32 feedback buffer, image layout).
-    __device__ __forceinline__ void apply_feedback(const Img &a)
+    // r -= acc (float32 feedback sums, image layout); returns the new key.
+    __device__ __forceinline__ uint64_t apply_feedback(const Img &a)
     {
 #pragma unroll
         for (int k = 0; k < K; ++k) {
@@ -344,9 +353,160 @@ template <int K, int V, typename PT> struct RegTile {
                 for (int e = 0; e < V; ++e) r[k][e] = r[k][e] - a.accbuf[img + e];
             }
         }
+        return key(a);
     }
 
-    // Which (rank, thread) owns tile-local index f.
+    // Does this thread own tile-local index f?
+    __device__ __forceinline__ bool owns(uint32_t f) const
+    {
+        const uint32_t u = f / (uint32_t)V;
+        const uint32_t t = u % (uint32_t)WG;
+        const uint32_t g = (u / (uint32_t)WG) % (uint32_t)cs;
+        return t == threadIdx.x && (int)g == rank;
+    }
+};
+
+// Residual kept in HBM (the caller's residual array) for tiles too large for
+// the register file: every pass streams K groups per thread through
+// registers, group index ((p*K + k)*cs + g)*WG + t for pass p.
+template <int K, int V, typename PT> struct StreamTile {
+    static constexpr bool kResident = false;
+    static constexpr int kV = V;
+    using psf_t = PT;
+    int y0, x0, h, w, cs, rank, passes;
+
+    __device__ __forceinline__ uint32_t group_f(int p, int k) const
+    {
+        return (uint32_t)((((p * K + k) * cs + rank) * WG + (int)threadIdx.x) * V);
+    }
+    __device__ __forceinline__ int64_t img_of(const Img &a, uint32_t f) const
+    {
+        const int y = (int)(f / (uint32_t)w), x = (int)(f % (uint32_t)w);
+        return (int64_t)(y0 + y) * a.nx + (x0 + x);
+    }
+
+    __device__ void init(const Img &a, int ty0, int tx0, int th, int tw, int ncs, int rk)
+    {
+        y0 = ty0; x0 = tx0; h = th; w = tw; cs = ncs; rank = rk;
+        const int64_t per_pass = (int64_t)K * cs * WG * V;
+        passes = (int)(((int64_t)h * w + per_pass - 1) / per_pass);
+        const int64_t hw = (int64_t)h * w;
+        for (int p = 0; p < passes; ++p)
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const uint32_t f = group_f(p, k);
+                if ((int64_t)f >= hw) continue;
+                const int64_t img = img_of(a, f);
+#pragma unroll
+                for (int e = 0; e < V; ++e) {
+                    if (a.residual != a.dirty) a.residual[img + e] = a.dirty[img + e];
+                    if (a.model) a.model[img + e] = 0.0;
+                }
+            }
+    }
+
+    __device__ double finish(const Img &a) const
+    {
+        double sumsq = 0.0;
+        const int64_t hw = (int64_t)h * w;
+        for (int p = 0; p < passes; ++p)
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const uint32_t f = group_f(p, k);
+                if ((int64_t)f >= hw) continue;
+                const int64_t img = img_of(a, f);
+#pragma unroll
+                for (int e = 0; e < V; ++e) sumsq += (double)a.residual[img + e] * (double)a.residual[img + e];
+            }
+        return sumsq;
+    }
+
+    __device__ __forceinline__ static void take(uint32_t bits, uint32_t f, uint32_t &bb, uint32_t &bf, bool &any)
+    {
+        const bool t = !any || ((bits & 0x7FFFFFFFu) > (bb & 0x7FFFFFFFu));
+        bb = t ? bits : bb;
+        bf = t ? f : bf;
+        any = true;
+    }
+
+    __device__ uint64_t key(const Img &a) const
+    {
+        uint32_t bb = 0, bf = 0;
+        bool any = false;
+        const int64_t hw = (int64_t)h * w;
+        for (int p = 0; p < passes; ++p)
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const uint32_t f = group_f(p, k);
+                if ((int64_t)f >= hw) continue;
+                const int64_t img = img_of(a, f);
+#pragma unroll
+                for (int e = 0; e < V; ++e) take(__float_as_uint(a.residual[img + e]), f + e, bb, bf, any);
+            }
+        return any ? make_key(bb, bf) : 0;
+    }
+
+    __device__ uint64_t subtract(const Img &a, int py, int px, float c, bool want_key)
+    {
+        const int64_t w0 = (int64_t)(a.cy - py) * a.psf_nx + (a.cx - px);
+        const char *base = (const char *)a.psf + w0 * (int64_t)sizeof(PT);
+        const __amdgpu_buffer_rsrc_t rs = make_rsrc(base, a.psf_bytes - (uint64_t)w0 * sizeof(PT));
+        uint32_t bb = 0, bf = 0;
+        bool any = false;
+        const int64_t hw = (int64_t)h * w;
+        for (int p = 0; p < passes; ++p) {
+            float rv[K][V], pv[K][V];
+            int64_t img[K];
+            bool ok[K];
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const uint32_t f = group_f(p, k);
+                ok[k] = (int64_t)f < hw;
+                const int y = (int)(f / (uint32_t)w), x = (int)(f % (uint32_t)w);
+                img[k] = (int64_t)(y0 + y) * a.nx + (x0 + x);
+                const uint32_t qo = (uint32_t)((y0 + y) * a.psf_nx + (x0 + x));
+                if (ok[k]) {
+                    PsfLoad<PT, V>::load(rs, qo * (uint32_t)sizeof(PT), pv[k]);
+#pragma unroll
+                    for (int e = 0; e < V; ++e) rv[k][e] = a.residual[img[k] + e];
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                if (!ok[k]) continue;
+                const uint32_t f = group_f(p, k);
+#pragma unroll
+                for (int e = 0; e < V; ++e) {
+                    const float r = __builtin_fmaf(-c, pv[k][e], rv[k][e]);
+                    a.residual[img[k] + e] = r;
+                    if (want_key) take(__float_as_uint(r), f + e, bb, bf, any);
+                }
+            }
+        }
+        return any ? make_key(bb, bf) : 0;
+    }
+
+    __device__ uint64_t apply_feedback(const Img &a)
+    {
+        uint32_t bb = 0, bf = 0;
+        bool any = false;
+        const int64_t hw = (int64_t)h * w;
+        for (int p = 0; p < passes; ++p)
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const uint32_t f = group_f(p, k);
+                if ((int64_t)f >= hw) continue;
+                const int64_t img = img_of(a, f);
+#pragma unroll
+                for (int e = 0; e < V; ++e) {
+                    const float r = a.residual[img + e] - a.accbuf[img + e];
+                    a.residual[img + e] = r;
+                    take(__float_as_uint(r), f + e, bb, bf, any);
+                }
+            }
+        return any ? make_key(bb, bf) : 0;
+    }
+
     __device__ __forceinline__ bool owns(uint32_t f) const
     {
         const uint32_t u = f / (uint32_t)V;
@@ -359,12 +519,10 @@ template <int K, int V, typename PT> struct RegTile {
 // ------------------------------------------------------ plain kernel -----
 
 // Sum of the workgroup's squared residuals, in a fixed order, to partial[slot].
-template <int K, int V, typename PT>
-__device__ void store_and_sum(const RegTile<K, V, PT> &R, const Img &im, double *partial, int slot)
+template <class Tile> __device__ void store_and_sum(const Tile &R, const Img &im, double *partial, int slot)
 {
     __shared__ double s_ss[NWAVES];
-    double ss;
-    R.store(im, ss);
+    double ss = R.finish(im);
     ss = wave_sum64f(ss);
     if ((threadIdx.x & 63) == 0) s_ss[threadIdx.x >> 6] = ss;
     __syncthreads();
@@ -378,22 +536,20 @@ __device__ void store_and_sum(const RegTile<K, V, PT> &R, const Img &im, double 
 
 // Plain Hogbom CLEAN of one image by a cluster of j.cs workgroups; this
 // workgroup is cluster rank `rank`.  Returns false if the run was aborted.
-template <int K, int V, typename PT> __device__ bool run_plain(const PlainJob &j, int rank, const Sync &y)
+template <class Tile> __device__ bool run_plain(const PlainJob &j, int rank, const Sync &y)
 {
     __shared__ uint64_t s_red[NWAVES];
     __shared__ uint64_t s_bcast;
     __shared__ int s_ok;
 
     const Img im{j.dirty, j.residual, j.model, nullptr, j.psf, j.psf_bytes, j.nx, j.psf_nx, j.cy, j.cx};
-    RegTile<K, V, PT> T;
-    T.cs = j.cs;
-    T.rank = rank;
-    T.y0 = 0; T.x0 = 0; T.h = j.ny; T.w = j.nx;
-    T.load(im);
+    Tile T;
+    T.init(im, 0, 0, j.ny, j.nx, j.cs, rank);
+    if (!Tile::kResident) __syncthreads();
 
     uint32_t e = 0;
     uint64_t cur;
-    if (!cluster_max(y, j.slots, j.slot_pad, j.cs, rank, e++, wg_max_key(T.local_key(), s_red), &s_bcast, &s_ok, cur))
+    if (!cluster_max(y, j.slots, j.slot_pad, j.cs, rank, e++, wg_max_key(T.key(im), s_red), &s_bcast, &s_ok, cur))
         return false;
 
     const bool leader = rank == 0 && threadIdx.x == 0;
@@ -416,8 +572,7 @@ template <int K, int V, typename PT> __device__ bool run_plain(const PlainJob &j
         }
         if (j.model && T.owns(fp)) j.model[fp] += (double)c;
         // subtraction (eq. 2) fused with the next peak search
-        T.subtract(im, py, px, c);
-        const uint64_t wk = wg_max_key(T.local_key(), s_red);
+        const uint64_t wk = wg_max_key(T.subtract(im, py, px, c, true), s_red);
         if (!cluster_max(y, j.slots, j.slot_pad, j.cs, rank, e++, wk, &s_bcast, &s_ok, cur)) return false;
         n += 1;
     }
@@ -432,8 +587,7 @@ template <int K, int V, typename PT> __device__ bool run_plain(const PlainJob &j
     return true;
 }
 
-template <int K, int V, typename PT>
-__global__ void __launch_bounds__(WG) hogbom_kernel(const KArgs a)
+template <class Tile> __global__ void __launch_bounds__(WG) hogbom_kernel(const KArgs a)
 {
     const int32_t role = a.role[blockIdx.x];
     if (role < 0) return;                       // no helpers in the plain form
@@ -446,7 +600,7 @@ __global__ void __launch_bounds__(WG) hogbom_kernel(const KArgs a)
     j.comp_idx = a.comp_idx; j.comp_flux = a.comp_flux;
     j.slots = a.xslots; j.slot_pad = a.slot_pad; j.cs = a.cs;
     j.dstat = a.dstat; j.partial = a.partial;
-    run_plain<K, V, PT>(j, role & 0xFFFF, y);
+    run_plain<Tile>(j, role & 0xFFFF, y);
 }
 
 // Many independent images in one launch.  Problems are laid out largest
@@ -455,8 +609,7 @@ __global__ void __launch_bounds__(WG) hogbom_kernel(const KArgs a)
 // counter, runs that problem with its cluster, then takes another.  Seats go
 // out in order and every workgroup is resident, so the earliest unfinished
 // problem always has its seats held by running workgroups: no deadlock.
-template <int K, int V, typename PT>
-__global__ void __launch_bounds__(WG) batched_kernel(const BatchArgs b)
+template <class Tile> __global__ void __launch_bounds__(WG) batched_kernel(const BatchArgs b)
 {
     __shared__ int s_seat;
     const Sync y{b.ctl, b.timeout_ticks};
@@ -474,7 +627,7 @@ __global__ void __launch_bounds__(WG) batched_kernel(const BatchArgs b)
             if (b.seat0[mid] <= seat) lo = mid; else hi = mid;
         }
         const PlainJob j = b.jobs[lo];
-        if (!run_plain<K, V, PT>(j, seat - b.seat0[lo], y)) return;
+        if (!run_plain<Tile>(j, seat - b.seat0[lo], y)) return;
         if (aborted(y)) return;
     }
 }
@@ -547,9 +700,10 @@ __device__ __forceinline__ int wg_sum_int(int v, int *s_tmp)
     return r;
 }
 
-template <int K, int V, typename PT>
-__global__ void __launch_bounds__(WG) tiled_kernel(const KArgs a)
+template <class Tile> __global__ void __launch_bounds__(WG) tiled_kernel(const KArgs a)
 {
+    constexpr int V = Tile::kV;
+    using PT = typename Tile::psf_t;
     __shared__ uint64_t s_red[NWAVES];
     __shared__ uint64_t s_bcast;
     __shared__ int s_ok, s_tmp, s_cnt;
@@ -575,15 +729,15 @@ __global__ void __launch_bounds__(WG) tiled_kernel(const KArgs a)
     int32_t *g_shift = (int32_t *)s_dyn;
     float *g_flux = (float *)(s_dyn + 4 * (size_t)GATHER_CHUNK);
 
-    RegTile<K, V, PT> R;
+    Tile R;
     uint32_t e = 0, epoch = 0;
     uint64_t cur = 0;
     if (is_cluster) {
-        R.cs = cs;
-        R.rank = rank;
-        tile_rect(a, tile, R.y0, R.x0, R.h, R.w);
-        R.load(im);
-        if (!cluster_max(y, slots, a.slot_pad, cs, rank, e++, wg_max_key(R.local_key(), s_red), &s_bcast, &s_ok, cur))
+        int ty0, tx0, th, tw;
+        tile_rect(a, tile, ty0, tx0, th, tw);
+        R.init(im, ty0, tx0, th, tw, cs, rank);
+        if (!Tile::kResident) __syncthreads();
+        if (!cluster_max(y, slots, a.slot_pad, cs, rank, e++, wg_max_key(R.key(im), s_red), &s_bcast, &s_ok, cur))
             return;
         if (tile_leader_wg && threadIdx.x == 0) a.tile_key[tile] = cur;
     }
@@ -630,10 +784,11 @@ __global__ void __launch_bounds__(WG) tiled_kernel(const KArgs a)
                 const int32_t img = py * a.nx + px;
                 if (tile_leader_wg && threadIdx.x == 0) { l_idx[L] = img; l_flux[L] = c; }
                 if (a.model && R.owns(fp)) a.model[img] += (double)c;
-                R.subtract(im, py, px, c);
+                const bool more = it + 1 < budget;
+                const uint64_t tk = R.subtract(im, py, px, c, more);
                 L += 1;
-                if (it + 1 < budget) {
-                    const uint64_t wk = wg_max_key(R.local_key(), s_red);
+                if (more) {
+                    const uint64_t wk = wg_max_key(tk, s_red);
                     if (!cluster_max(y, slots, a.slot_pad, cs, rank, e++, wk, &s_bcast, &s_ok, cur)) return;
                 }
             }
@@ -757,8 +912,7 @@ __global__ void __launch_bounds__(WG) tiled_kernel(const KArgs a)
 
         // ---- apply feedback and find each tile's new peak
         if (is_cluster) {
-            R.apply_feedback(im);
-            const uint64_t wk = wg_max_key(R.local_key(), s_red);
+            const uint64_t wk = wg_max_key(R.apply_feedback(im), s_red);
             if (!cluster_max(y, slots, a.slot_pad, cs, rank, e++, wk, &s_bcast, &s_ok, cur)) return;
             if (tile_leader_wg && threadIdx.x == 0) a.tile_key[tile] = cur;
         }
@@ -832,15 +986,19 @@ __global__ void finalize_batch_kernel(const PlainJob *jobs, int n)
 
 // ----------------------------------------------------- instantiations ----
 
-#define INST(K, V, PT)                                                       \
-    template __global__ void hogbom_kernel<K, V, PT>(const KArgs a);        \
-    template __global__ void batched_kernel<K, V, PT>(const BatchArgs b);   \
-    template __global__ void tiled_kernel<K, V, PT>(const KArgs a);
+#define INST(K, V, PT)                                                                   \
+    template __global__ void hogbom_kernel<RegTile<K, V, PT>>(const KArgs a);           \
+    template __global__ void batched_kernel<RegTile<K, V, PT>>(const BatchArgs b);      \
+    template __global__ void tiled_kernel<RegTile<K, V, PT>>(const KArgs a);
+#define INST_STREAM(V, PT)                                                               \
+    template __global__ void hogbom_kernel<StreamTile<STREAM_K, V, PT>>(const KArgs a);  \
+    template __global__ void tiled_kernel<StreamTile<STREAM_K, V, PT>>(const KArgs a);
 
 #define INST_ALL_K(V, PT) INST(1, V, PT) INST(2, V, PT) INST(4, V, PT) INST(8, V, PT) INST(16, V, PT)
 INST_ALL_K(4, float)
 INST_ALL_K(4, __half)
-INST(4, 1, float) INST(16, 1, float) INST(64, 1, float)
-INST(4, 1, __half) INST(16, 1, __half) INST(64, 1, __half)
+INST(4, 1, float) INST(16, 1, float) INST(32, 1, float)
+INST(4, 1, __half) INST(16, 1, __half) INST(32, 1, __half)
+INST_STREAM(4, float) INST_STREAM(4, __half) INST_STREAM(1, float) INST_STREAM(1, __half)
 
 } // namespace cleanhip

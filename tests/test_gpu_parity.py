@@ -220,3 +220,59 @@ def test_nonfinite_input_rejected(lib):
     with pytest.raises(lib.CleanError) as e:
         lib.hogbom(dev(d), dev(psf), 0.1, 0.0, 10, check_finite=True)
     assert e.value.status == -2
+
+
+# ------------------------------------------------- residual kept in HBM --
+
+@pytest.mark.parametrize("case", PLAIN_CASES[:5], ids=[f"{c[0]}x{c[1]}-wg{c[4]}" for c in PLAIN_CASES[:5]])
+def test_plain_streamed_small(lib, case):
+    ny, nx, extra, seed, wg, ppt, n, thr = case
+    announce("plain streamed", case)
+    dirty = sparse_dirty(ny, nx, seed)
+    psf = asym_psf(2 * ny + extra[0], 2 * nx + extra[1], seed)
+    ref = oracle.hogbom(dirty, psf, 0.1, thr, n)
+    out = lib.hogbom(dev(dirty), dev(psf), 0.1, thr, n, wg_per_tile=wg, stream=True)
+    assert out["stats"]["streamed"] == 1
+    assert_same_run(out, ref)
+
+
+@pytest.mark.parametrize("case", TILED_CASES[:6], ids=[f"{c[0]}x{c[1]}-{c[2][0]}x{c[2][1]}-I{c[3]}" for c in TILED_CASES[:6]])
+def test_tiled_streamed_small(lib, case):
+    ny, nx, tiles, interval, seed, n, thr, wg, ppt = case
+    announce("tiled streamed", case)
+    dirty = sparse_dirty(ny, nx, seed, density=0.03)
+    psf = asym_psf(2 * ny, 2 * nx + 2, seed, spread=0.2)
+    ref = oracle.tiled(dirty, psf, tiles, interval, 0.1, thr, n)
+    out = lib.tiled_feedback(dev(dirty), dev(psf), tiles, interval, 0.1, thr, n, wg_per_tile=wg, stream=True)
+    assert out["stats"]["streamed"] == 1
+    assert out["stats"]["n_rounds"] == ref["n_rounds"]
+    assert_same_run(out, ref)
+
+
+@pytest.fixture(scope="module")
+def config2():
+    return synth.make_config(2)
+
+
+def test_plain_config2_prefix(lib, config2):
+    """4096^2 image, 8192^2 PSF: too large for the register file, so the
+    residual streams through HBM; the first 200 iterations, bit for bit."""
+    c = config2
+    announce("plain config2 prefix")
+    ref = oracle.hogbom(c["dirty"], c["psf"], 0.1, 0.0, 200)
+    out = lib.hogbom(dev(c["dirty"]), dev(c["psf"]), 0.1, 0.0, 200)
+    assert out["stats"]["streamed"] == 1
+    assert_same_run(out, ref)
+
+
+@pytest.mark.parametrize("f16", [False, True])
+def test_tiled_config2_prefix(lib, config2, f16):
+    """8x8 tiles of 512^2, interval 10, two feedback rounds (1280 iterations)."""
+    c = config2
+    announce("tiled config2 prefix", f16)
+    psf_ref = c["psf"].astype(np.float16).astype(np.float32) if f16 else c["psf"]
+    ref = oracle.tiled(c["dirty"], psf_ref, (8, 8), 10, 0.1, 0.0, 1280)
+    p = dev(c["psf"])
+    out = lib.tiled_feedback(dev(c["dirty"]), lib.psf_to_f16(p) if f16 else p, (8, 8), 10, 0.1, 0.0, 1280)
+    assert out["stats"]["n_rounds"] == ref["n_rounds"] == 2
+    assert_same_run(out, ref)
