@@ -1,0 +1,116 @@
+"""The C ABI without a GPU: the library loads, exports every symbol that
+include/clean.h declares, and rejects bad arguments before it touches any
+memory or calls the HIP runtime (the fake pointers below are never read)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_2501_01461_amd import _native as N
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "clean.h")
+
+INVAL, UNSUPPORTED = -1, -6
+FAKE = C.c_void_p(0x1000)     # never dereferenced on the argument-error paths
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(clean_\w+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return N.load()
+
+
+def test_exports_every_declared_symbol(lib):
+    names = declared_functions()
+    assert len(names) >= 8
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(N.EXPORTS)
+
+
+def test_version_and_strerror(lib):
+    assert b"gfx950" in lib.clean_version()
+    for code in (0, -1, -2, -3, -4, -5, -6):
+        assert lib.clean_strerror(code)
+    assert lib.clean_strerror(12345) == b"unknown status"
+
+
+def params(**kw):
+    p = N.Params(0.1, 0.0, 100, 0, 0, 0, 0)
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+def hogbom(lib, ny=16, nx=16, psf_ny=32, psf_nx=32, p=None, cap=100, null_dirty=False):
+    p = p or params()
+    st = N.Stats()
+    return lib.clean_hogbom(None if null_dirty else FAKE, ny, nx, FAKE, psf_ny, psf_nx, C.byref(p), FAKE,
+                            FAKE, FAKE, cap, None, None, 0, C.byref(st), None)
+
+
+def tiled(lib, ty=2, tx=2, interval=10, ny=16, nx=16, p=None):
+    p = p or params()
+    st = N.Stats()
+    return lib.clean_tiled_feedback(FAKE, ny, nx, FAKE, 2 * ny, 2 * nx, ty, tx, interval, C.byref(p), FAKE, FAKE,
+                                    FAKE, 100, None, None, 0, C.byref(st), None)
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(ny=0), INVAL), (dict(nx=-3), INVAL), (dict(psf_ny=31), INVAL), (dict(psf_nx=20), INVAL),
+    (dict(p=params(gain=0.0)), INVAL), (dict(p=params(gain=1.5)), INVAL), (dict(p=params(threshold=-1.0)), INVAL),
+    (dict(p=params(max_iter=-1)), INVAL), (dict(p=params(psf_dtype=7)), INVAL), (dict(cap=-1), INVAL),
+    (dict(null_dirty=True), INVAL), (dict(p=params(wg_per_tile=-2)), INVAL),
+    (dict(ny=20000, nx=20000, psf_ny=40000, psf_nx=40000), UNSUPPORTED),
+])
+def test_plain_argument_errors(lib, kw, code):
+    assert hogbom(lib, **kw) == code
+    assert lib.clean_last_error()
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(ty=0), INVAL), (dict(tx=17), INVAL), (dict(interval=0), INVAL), (dict(interval=2049), INVAL),
+    (dict(ty=40, tx=40, ny=64, nx=64), UNSUPPORTED),
+])
+def test_tiled_argument_errors(lib, kw, code):
+    assert tiled(lib, **kw) == code
+
+
+def test_nan_gain_rejected(lib):
+    assert hogbom(lib, p=params(gain=float("nan"))) == INVAL
+    assert hogbom(lib, p=params(threshold=float("nan"))) == INVAL
+
+
+def test_batched_argument_errors(lib):
+    p = params()
+    st = (N.Stats * 1)()
+    assert lib.clean_batched(None, 1, C.byref(p), st, None) == INVAL
+    arr = (N.Problem * 1)()
+    assert lib.clean_batched(arr, -1, C.byref(p), st, None) == INVAL
+    assert lib.clean_batched(arr, 70000, C.byref(p), st, None) == INVAL
+    # a problem with a PSF smaller than twice the image
+    arr[0] = N.Problem(0x1000, 0x1000, 0x1000, 0x1000, 0x1000, None, 10, 10, 0.0, 16, 16, 16, 32)
+    assert lib.clean_batched(arr, 1, C.byref(p), st, None) == INVAL
+    assert b"problem 0" in lib.clean_last_error()
+    assert lib.clean_batched(arr, 0, C.byref(p), st, None) == 0
+
+
+def test_workspace_size(lib):
+    p = params()
+    a = lib.clean_workspace_size(1024, 1024, 2, 2, 100, C.byref(p))
+    b = lib.clean_workspace_size(1024, 1024, 1, 1, 1, C.byref(p))
+    assert a > 4 * 1024 * 1024 > 0 and b > 0
+    assert lib.clean_workspace_size(1024, 1024, 0, 2, 100, C.byref(p)) == 0
+    assert lib.clean_workspace_size(1024, 1024, 2, 2, 0, C.byref(p)) == 0
+
+
+def test_psf_to_f16_argument_errors(lib):
+    assert lib.clean_psf_to_f16(None, FAKE, 10, None) == INVAL
+    assert lib.clean_psf_to_f16(FAKE, FAKE, -1, None) == INVAL
