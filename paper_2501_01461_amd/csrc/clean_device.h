@@ -10,7 +10,8 @@ constexpr int NWAVES = WG / 64;
 constexpr int MAX_TILES = 1024;
 constexpr int MAX_INTERVAL = 2048;
 constexpr int GATHER_CHUNK = 2048;      // components staged in LDS per pass
-constexpr int GATHER_M = 4;             // pixel groups per thread per gather pass
+constexpr int GATHER_M = 2;             // pixel groups per thread per gather pass
+constexpr int GATHER_J = 8;             // components whose loads are issued together
 constexpr int STREAM_K = 4;             // pixel groups per thread per streamed pass
 
 enum { STOP_MAXITER = 0, STOP_THRESHOLD = 1, STOP_CAPACITY = 2 };

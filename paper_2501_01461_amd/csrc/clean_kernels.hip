@@ -47,6 +47,21 @@ __device__ __forceinline__ void st_agent(uint64_t *p, uint64_t v)
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Data written by one workgroup and read by another inside the launch goes
+// through agent-coherent accesses (write-through stores, loads that do not hit
+// stale cache lines).  The grid barrier then only has to order them: every
+// wave has waited for its stores before the workgroup arrives, and readers
+// load after the barrier has released, so no cache write-back or invalidation
+// is needed and the PSF stays cached across rounds.
+template <typename T> __device__ __forceinline__ T ldc(const T *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T> __device__ __forceinline__ void stc(T *p, T v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 __device__ __forceinline__ uint64_t make_key(uint32_t bits, uint32_t f)
 {
     return ((uint64_t)(bits & 0x7FFFFFFFu) << 33) | ((uint64_t)(0x0FFFFFFFu - f) << 5) |
@@ -64,11 +79,29 @@ __device__ __forceinline__ uint32_t key_f(uint64_t k)
 }
 __device__ __forceinline__ uint64_t umax64(uint64_t a, uint64_t b) { return a > b ? a : b; }
 
+// One DPP step of a 64-bit max: take the (row-shifted or row-broadcast)
+// neighbour's key when it is larger; lanes without a source read 0.
+#define CLEAN_DPP_MAX_STEP(k, CTRL, ROW_MASK)                                                          \
+    do {                                                                                              \
+        const uint32_t plo_ = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(k), CTRL, ROW_MASK, 0xf, true); \
+        const uint32_t phi_ = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)((k) >> 32), CTRL, ROW_MASK, 0xf, true); \
+        const uint64_t p_ = ((uint64_t)phi_ << 32) | plo_;                                            \
+        k = p_ > (k) ? p_ : (k);                                                                      \
+    } while (0)
+
+// Max of a 64-bit key over the wave, uniform on return: row_shr 1/2/4/8 leaves
+// each row's maximum in its lane 15, row_bcast 15/31 carries them up to lane 63.
 __device__ __forceinline__ uint64_t wave_max64(uint64_t k)
 {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) k = umax64(k, __shfl_xor(k, off));
-    return k;
+    CLEAN_DPP_MAX_STEP(k, 0x111, 0xf);   // row_shr:1
+    CLEAN_DPP_MAX_STEP(k, 0x112, 0xf);   // row_shr:2
+    CLEAN_DPP_MAX_STEP(k, 0x114, 0xf);   // row_shr:4
+    CLEAN_DPP_MAX_STEP(k, 0x118, 0xf);   // row_shr:8
+    CLEAN_DPP_MAX_STEP(k, 0x142, 0xa);   // row_bcast:15 into rows 1 and 3
+    CLEAN_DPP_MAX_STEP(k, 0x143, 0xc);   // row_bcast:31 into rows 2 and 3
+    const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)k, 63);
+    const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(k >> 32), 63);
+    return ((uint64_t)hi << 32) | lo;
 }
 
 __device__ __forceinline__ double wave_sum64f(double v)
@@ -136,70 +169,70 @@ __device__ __forceinline__ void raise_abort(const Sync &y, uint32_t code)
     __hip_atomic_fetch_or(&y.ctl->abort, code, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// ------------------------------------------------ workgroup reduction ----
+// ------------------------------------------------ cluster reduction ------
 
-// Max of the workgroup's keys; valid in every thread on return.
-__device__ __forceinline__ uint64_t wg_max_key(uint64_t k, uint64_t *s_red)
+// Cluster-wide max of the threads' keys for exchange number `e`.  A DPP wave
+// max, one LDS step, then wave 0 publishes the workgroup's key in its slot and
+// polls the cluster's slots (agent-scope relaxed atomics) until every slot
+// carries this exchange's tag.  Two workgroup barriers per call.  Returns
+// false if the run was aborted; `out` is uniform on return.
+__device__ bool cluster_reduce(const Sync &y, uint64_t *slots, int slot_pad, int cs, int rank, uint32_t e,
+                               uint64_t tkey, uint64_t &out)
 {
+    __shared__ uint64_t s_wave[NWAVES];
+    __shared__ uint64_t s_res;
+    __shared__ int s_good;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    k = wave_max64(k);
-    if (lane == 0) s_red[wave] = k;
+    const uint64_t wk = wave_max64(tkey);
+    if (lane == 0) s_wave[wave] = wk;
     __syncthreads();
-    uint64_t r = s_red[0];
-#pragma unroll
-    for (int w = 1; w < NWAVES; ++w) r = umax64(r, s_red[w]);
-    __syncthreads();
-    return r;
-}
-
-// Cluster all-reduce (max) of workgroup keys, exchange number `e`.
-// Returns false if the run was aborted.  `wgkey` must be uniform in the WG.
-__device__ bool cluster_max(const Sync &y, uint64_t *slots, int slot_pad, int cs, int rank, uint32_t e,
-                            uint64_t wgkey, uint64_t *s_bcast, int *s_ok, uint64_t &out)
-{
-    if (cs == 1) { out = wgkey; return true; }
-    const uint64_t tag = (uint64_t)((e & 7u) + 1u);
-    uint64_t *blk = slots + (size_t)(e & 1u) * slot_pad;
-    if (threadIdx.x < 64) {
-        if (threadIdx.x == 0) st_agent(&blk[rank], (wgkey & ~15ull) | tag);
-        uint64_t best = 0;
+    if (wave == 0) {
+        uint64_t g = wave_max64(lane < NWAVES ? s_wave[lane] : 0ull);
         bool ok = true;
-        const uint64_t t0 = wall_clock64();
-        uint32_t spins = 0;
-        for (;;) {
-            bool have = true;
-            best = 0;
-            for (int s = threadIdx.x; s < cs; s += 64) {
-                uint64_t v = ld_agent(&blk[s]);
-                if ((v & 15ull) != tag) have = false;
-                best = umax64(best, v);
-            }
-            if (__all(have)) break;
-            if ((++spins & 63u) == 0) {
-                if (aborted(y)) { ok = false; break; }
-                if (wall_clock64() - t0 > y.timeout_ticks) { raise_abort(y, ABORT_TIMEOUT); ok = false; break; }
+        if (cs > 1) {
+            const uint64_t tag = (uint64_t)((e & 7u) + 1u);
+            uint64_t *blk = slots + (size_t)(e & 1u) * slot_pad;
+            if (lane == 0) st_agent(&blk[rank], (g & ~15ull) | tag);
+            const uint64_t t0 = wall_clock64();
+            uint32_t spins = 0;
+            for (;;) {
+                bool have = true;
+                uint64_t best = 0;
+                for (int s = lane; s < cs; s += 64) {
+                    const uint64_t v = ld_agent(&blk[s]);
+                    if ((v & 15ull) != tag) have = false;
+                    best = umax64(best, v);
+                }
+                if (__all(have)) { g = wave_max64(best) & ~15ull; break; }
+                if ((++spins & 63u) == 0) {
+                    if (aborted(y)) { ok = false; break; }
+                    if (wall_clock64() - t0 > y.timeout_ticks) { raise_abort(y, ABORT_TIMEOUT); ok = false; break; }
+                }
             }
         }
-        best = wave_max64(best);
-        if (threadIdx.x == 0) { *s_bcast = best & ~15ull; *s_ok = ok; }
+        if (lane == 0) { s_res = g; s_good = ok; }
     }
     __syncthreads();
-    out = *s_bcast;
-    bool ok = *s_ok;
-    __syncthreads();
-    return ok;
+    out = s_res;
+    return s_good != 0;
 }
 
-// Grid-wide barrier with release/acquire at agent scope.  `epoch` counts the
-// barriers this workgroup has passed; all workgroups pass them in order.
+// Grid-wide barrier.  Data that crosses it is written and read with the
+// agent-coherent accessors above; the barrier itself only orders: every wave
+// waits for its own memory operations to complete, the workgroup barrier
+// collects the waves, one agent-scope atomic arrives, and readers issue their
+// loads only after they have seen all arrivals.
+// `epoch` counts the barriers this workgroup has passed.
 __device__ bool grid_barrier(const Sync &y, uint32_t &epoch, int *s_ok)
 {
+    // every wave's vector memory operations (its coherent stores) complete
+    // before the workgroup can arrive
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads();
     epoch += 1;
     if (threadIdx.x == 0) {
         bool ok = true;
         const uint32_t target = epoch * (uint32_t)gridDim.x;
-        __threadfence();
         __hip_atomic_fetch_add(&y.ctl->barrier, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         const uint64_t t0 = wall_clock64();
         while (ld_agent32(&y.ctl->barrier) < target) {
@@ -207,7 +240,6 @@ __device__ bool grid_barrier(const Sync &y, uint32_t &epoch, int *s_ok)
             if (wall_clock64() - t0 > y.timeout_ticks) { raise_abort(y, ABORT_TIMEOUT); ok = false; break; }
             __builtin_amdgcn_s_sleep(1);
         }
-        __threadfence();
         *s_ok = ok;
     }
     __syncthreads();
@@ -234,7 +266,7 @@ struct Img {
     const float *dirty;
     float *residual;
     double *model;          // may be null
-    const float *accbuf;    // tiled feedback sums (image layout), else null
+    float *accbuf;          // tiled feedback sums (image layout), else null
     const void *psf;
     uint64_t psf_bytes;
     int nx, psf_nx, cy, cx;
@@ -304,24 +336,27 @@ template <int K, int V, typename PT> struct RegTile {
         return sumsq;
     }
 
-    // Thread-local peak key over the owned pixels (lowest f wins ties).
+    // Thread-local peak key over the owned pixels: the largest |r|, then the
+    // lowest index holding it.  Groups outside the tile hold +0 and come after
+    // every valid group, so they never win unless all valid pixels are 0 too,
+    // and then group 0 (valid) wins.
     __device__ __forceinline__ uint64_t key(const Img &) const
     {
         if (!(valid & 1ull)) return 0;
-        uint32_t bb = __float_as_uint(r[0][0]);
-        uint32_t bf = group_f(0);
+        float m = 0.0f;
 #pragma unroll
-        for (int k = 0; k < K; ++k) {
+        for (int k = 0; k < K; ++k)
 #pragma unroll
-            for (int e = 0; e < V; ++e) {
-                if (k == 0 && e == 0) continue;
-                const uint32_t bits = __float_as_uint(r[k][e]);
-                const bool take = ((valid >> k) & 1ull) && ((bits & 0x7FFFFFFFu) > (bb & 0x7FFFFFFFu));
-                bb = take ? bits : bb;
-                bf = take ? group_f(k) + e : bf;
-            }
+            for (int e = 0; e < V; ++e) m = fmaxf(m, fabsf(r[k][e]));
+        uint32_t bb = 0, bi = 0;
+#pragma unroll
+        for (int i = K * V - 1; i >= 0; --i) {
+            const float x = r[i / V][i % V];
+            const bool hit = fabsf(x) == m;
+            bb = hit ? __float_as_uint(x) : bb;
+            bi = hit ? (uint32_t)i : bi;
         }
-        return make_key(bb, bf);
+        return make_key(bb, group_f((int)(bi / V)) + bi % V);
     }
 
     // r -= c * PSF centred on image pixel (py, px); then, if asked, the new key.
@@ -334,9 +369,11 @@ template <int K, int V, typename PT> struct RegTile {
 #pragma unroll
         for (int k = 0; k < K; ++k) PsfLoad<PT, V>::load(rs, (uint32_t)qoff[k] * (uint32_t)sizeof(PT), pv[k]);
 #pragma unroll
-        for (int k = 0; k < K; ++k)
+        for (int k = 0; k < K; ++k) {
+            const float ck = (valid >> k) & 1ull ? c : 0.0f;    // groups outside the tile stay +0
 #pragma unroll
-            for (int e = 0; e < V; ++e) r[k][e] = __builtin_fmaf(-c, pv[k][e], r[k][e]);
+            for (int e = 0; e < V; ++e) r[k][e] = __builtin_fmaf(-ck, pv[k][e], r[k][e]);
+        }
         return want_key ? key(a) : 0;
     }
 
@@ -350,7 +387,7 @@ template <int K, int V, typename PT> struct RegTile {
                 const int y = (int)(f / (uint32_t)w), x = (int)(f % (uint32_t)w);
                 const int64_t img = (int64_t)(y0 + y) * a.nx + (x0 + x);
 #pragma unroll
-                for (int e = 0; e < V; ++e) r[k][e] = r[k][e] - a.accbuf[img + e];
+                for (int e = 0; e < V; ++e) r[k][e] = r[k][e] - ldc(&a.accbuf[img + e]);
             }
         }
         return key(a);
@@ -499,7 +536,7 @@ template <int K, int V, typename PT> struct StreamTile {
                 const int64_t img = img_of(a, f);
 #pragma unroll
                 for (int e = 0; e < V; ++e) {
-                    const float r = a.residual[img + e] - a.accbuf[img + e];
+                    const float r = a.residual[img + e] - ldc(&a.accbuf[img + e]);
                     a.residual[img + e] = r;
                     take(__float_as_uint(r), f + e, bb, bf, any);
                 }
@@ -538,10 +575,6 @@ template <class Tile> __device__ void store_and_sum(const Tile &R, const Img &im
 // workgroup is cluster rank `rank`.  Returns false if the run was aborted.
 template <class Tile> __device__ bool run_plain(const PlainJob &j, int rank, const Sync &y)
 {
-    __shared__ uint64_t s_red[NWAVES];
-    __shared__ uint64_t s_bcast;
-    __shared__ int s_ok;
-
     const Img im{j.dirty, j.residual, j.model, nullptr, j.psf, j.psf_bytes, j.nx, j.psf_nx, j.cy, j.cx};
     Tile T;
     T.init(im, 0, 0, j.ny, j.nx, j.cs, rank);
@@ -549,8 +582,7 @@ template <class Tile> __device__ bool run_plain(const PlainJob &j, int rank, con
 
     uint32_t e = 0;
     uint64_t cur;
-    if (!cluster_max(y, j.slots, j.slot_pad, j.cs, rank, e++, wg_max_key(T.key(im), s_red), &s_bcast, &s_ok, cur))
-        return false;
+    if (!cluster_reduce(y, j.slots, j.slot_pad, j.cs, rank, e++, T.key(im), cur)) return false;
 
     const bool leader = rank == 0 && threadIdx.x == 0;
     int64_t n = 0;
@@ -572,8 +604,8 @@ template <class Tile> __device__ bool run_plain(const PlainJob &j, int rank, con
         }
         if (j.model && T.owns(fp)) j.model[fp] += (double)c;
         // subtraction (eq. 2) fused with the next peak search
-        const uint64_t wk = wg_max_key(T.subtract(im, py, px, c, true), s_red);
-        if (!cluster_max(y, j.slots, j.slot_pad, j.cs, rank, e++, wk, &s_bcast, &s_ok, cur)) return false;
+        if (!cluster_reduce(y, j.slots, j.slot_pad, j.cs, rank, e++, T.subtract(im, py, px, c, true), cur))
+            return false;
         n += 1;
     }
     store_and_sum(T, im, j.partial, rank);
@@ -643,8 +675,8 @@ __device__ void aggregate_round(const KArgs &a, int t, int L, int32_t *l_idx, fl
 {
     const size_t base = (size_t)t * a.interval;
     for (int j = threadIdx.x; j < L; j += WG) {
-        a.rb_idx[base + j] = l_idx[j];
-        a.rb_flux[base + j] = l_flux[j];
+        stc(&a.rb_idx[base + j], l_idx[j]);
+        stc(&a.rb_flux[base + j], l_flux[j]);
     }
     // pass 1: heads (first occurrence) get their sum; l_tmp = 1 for a kept head
     for (int j = threadIdx.x; j < L; j += WG) {
@@ -671,8 +703,8 @@ __device__ void aggregate_round(const KArgs &a, int t, int L, int32_t *l_idx, fl
         const int32_t q = l_idx[j];
         int rk = 0;
         for (int k = 0; k < L; ++k) rk += (l_tmp[k] != 0) & (l_idx[k] < q);
-        a.ag_pos[base + rk] = q;
-        a.ag_flux[base + rk] = l_sum[j];
+        stc(&a.ag_pos[base + rk], q);
+        stc(&a.ag_flux[base + rk], l_sum[j]);
     }
     if (threadIdx.x == 0) *s_cnt = 0;
     __syncthreads();
@@ -681,8 +713,8 @@ __device__ void aggregate_round(const KArgs &a, int t, int L, int32_t *l_idx, fl
     if (mine) atomicAdd(s_cnt, mine);
     __syncthreads();
     if (threadIdx.x == 0) {
-        a.rb_n[t] = L;
-        a.ag_n[t] = *s_cnt;
+        stc(&a.rb_n[t], (int32_t)L);
+        stc(&a.ag_n[t], (int32_t)*s_cnt);
     }
 }
 
@@ -704,8 +736,6 @@ template <class Tile> __global__ void __launch_bounds__(WG) tiled_kernel(const K
 {
     constexpr int V = Tile::kV;
     using PT = typename Tile::psf_t;
-    __shared__ uint64_t s_red[NWAVES];
-    __shared__ uint64_t s_bcast;
     __shared__ int s_ok, s_tmp, s_cnt;
     __shared__ int32_t s_off[MAX_TILES + 1];    // exclusive prefix of per-tile counts
     extern __shared__ __align__(16) unsigned char s_dyn[];
@@ -737,9 +767,8 @@ template <class Tile> __global__ void __launch_bounds__(WG) tiled_kernel(const K
         tile_rect(a, tile, ty0, tx0, th, tw);
         R.init(im, ty0, tx0, th, tw, cs, rank);
         if (!Tile::kResident) __syncthreads();
-        if (!cluster_max(y, slots, a.slot_pad, cs, rank, e++, wg_max_key(R.key(im), s_red), &s_bcast, &s_ok, cur))
-            return;
-        if (tile_leader_wg && threadIdx.x == 0) a.tile_key[tile] = cur;
+        if (!cluster_reduce(y, slots, a.slot_pad, cs, rank, e++, R.key(im), cur)) return;
+        if (tile_leader_wg && threadIdx.x == 0) stc(&a.tile_key[tile], cur);
     }
     if (!grid_barrier(y, epoch, &s_ok)) return;
 
@@ -752,7 +781,7 @@ template <class Tile> __global__ void __launch_bounds__(WG) tiled_kernel(const K
         // ---- round control, computed identically by every workgroup
         int na_part = 0, rk_part = 0;
         for (int t = threadIdx.x; t < T; t += WG) {
-            const uint64_t k = a.tile_key[t];
+            const uint64_t k = ldc(&a.tile_key[t]);
             const int act = (double)fabsf(key_value(k)) >= a.threshold;
             na_part += act;
             rk_part += act && (t < tile);
@@ -787,10 +816,7 @@ template <class Tile> __global__ void __launch_bounds__(WG) tiled_kernel(const K
                 const bool more = it + 1 < budget;
                 const uint64_t tk = R.subtract(im, py, px, c, more);
                 L += 1;
-                if (more) {
-                    const uint64_t wk = wg_max_key(tk, s_red);
-                    if (!cluster_max(y, slots, a.slot_pad, cs, rank, e++, wk, &s_bcast, &s_ok, cur)) return;
-                }
+                if (more && !cluster_reduce(y, slots, a.slot_pad, cs, rank, e++, tk, cur)) return;
             }
             if (tile_leader_wg) {
                 __syncthreads();
@@ -801,7 +827,7 @@ template <class Tile> __global__ void __launch_bounds__(WG) tiled_kernel(const K
         if (blockIdx.x == 0) { tp1 = wall_clock64(); ph_local += tp1 - tp0; tp0 = tp1; }
 
         // ---- round bookkeeping: every workgroup reads the counts
-        for (int t = threadIdx.x; t < T; t += WG) s_off[t + 1] = a.rb_n[t];
+        for (int t = threadIdx.x; t < T; t += WG) s_off[t + 1] = ldc(&a.rb_n[t]);
         __syncthreads();
         if (threadIdx.x == 0) {
             s_off[0] = 0;
@@ -815,8 +841,8 @@ template <class Tile> __global__ void __launch_bounds__(WG) tiled_kernel(const K
             for (int t = 0; t < T; ++t) {
                 const int32_t cnt = s_off[t + 1] - s_off[t];
                 for (int j = threadIdx.x; j < cnt; j += WG) {
-                    const float fl = a.rb_flux[(size_t)t * a.interval + j];
-                    a.comp_idx[used + s_off[t] + j] = a.rb_idx[(size_t)t * a.interval + j];
+                    const float fl = ldc(&a.rb_flux[(size_t)t * a.interval + j]);
+                    a.comp_idx[used + s_off[t] + j] = ldc(&a.rb_idx[(size_t)t * a.interval + j]);
                     a.comp_flux[used + s_off[t] + j] = fl;
                     fsum += (double)fl;
                 }
@@ -830,7 +856,7 @@ template <class Tile> __global__ void __launch_bounds__(WG) tiled_kernel(const K
         }
         used += nround;
         __syncthreads();
-        for (int t = threadIdx.x; t < T; t += WG) s_off[t + 1] = a.ag_n[t];
+        for (int t = threadIdx.x; t < T; t += WG) s_off[t + 1] = ldc(&a.ag_n[t]);
         __syncthreads();
         if (threadIdx.x == 0) {
             s_off[0] = 0;
@@ -840,10 +866,19 @@ template <class Tile> __global__ void __launch_bounds__(WG) tiled_kernel(const K
 
         // ---- feedback gather: acc[q] = sum over other tiles' components
         {
+            // items are (tile, row band) in tile-major order; each XCD takes a
+            // contiguous range of them so its L2 sees one compact PSF region
+            // per component (workgroup b runs on XCD b % 8)
             const int parts = a.gather_parts;
             const int nitems = T * parts;
-            for (int item = blockIdx.x; item < nitems; item += gridDim.x) {
-                const int s = item % T, part = item / T;
+            const bool by_xcd = (gridDim.x % 8) == 0;
+            const int per_xcd_wg = by_xcd ? (int)gridDim.x / 8 : (int)gridDim.x;
+            const int items_per_xcd = by_xcd ? (nitems + 7) / 8 : nitems;
+            const int xcd = by_xcd ? (int)(blockIdx.x % 8) : 0;
+            const int item_end = min(nitems, (xcd + 1) * items_per_xcd);
+            for (int item = xcd * items_per_xcd + (by_xcd ? (int)(blockIdx.x / 8) : (int)blockIdx.x);
+                 item < item_end; item += per_xcd_wg) {
+                const int s = item / parts, part = item % parts;
                 int y0, x0, h, w;
                 tile_rect(a, s, y0, x0, h, w);
                 const int ngroups = (h * w) / V;
@@ -878,13 +913,36 @@ template <class Tile> __global__ void __launch_bounds__(WG) tiled_kernel(const K
                             int lo = 0, hi = T;                  // s_off[lo] <= gi < s_off[hi]
                             while (hi - lo > 1) { const int mid = (lo + hi) >> 1; if (s_off[mid] <= gi) lo = mid; else hi = mid; }
                             const size_t src = (size_t)lo * a.interval + (gi - s_off[lo]);
-                            const int32_t pos = a.ag_pos[src];
+                            const int32_t pos = ldc(&a.ag_pos[src]);
                             const int py = pos / a.nx, px = pos % a.nx;
                             g_shift[j] = (a.cy - py) * a.psf_nx + (a.cx - px);
-                            g_flux[j] = a.ag_flux[src];
+                            g_flux[j] = ldc(&a.ag_flux[src]);
                         }
                         __syncthreads();
-                        for (int j = 0; j < cn; ++j) {
+                        // GATHER_J components at a time: all their PSF loads are
+                        // issued before the fmas, which keep the component order
+                        int j = 0;
+                        for (; j + GATHER_J <= cn; j += GATHER_J) {
+                            float fl[GATHER_J];
+                            float pv[GATHER_J][GATHER_M][V];
+#pragma unroll
+                            for (int u = 0; u < GATHER_J; ++u) {
+                                const int32_t sh = __builtin_amdgcn_readfirstlane(g_shift[j + u]);
+                                fl[u] = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, g_flux[j + u])));
+                                const char *base = (const char *)a.psf + (int64_t)sh * (int64_t)sizeof(PT);
+                                const __amdgpu_buffer_rsrc_t rs = make_rsrc(base, a.psf_bytes - (uint64_t)sh * sizeof(PT));
+#pragma unroll
+                                for (int m = 0; m < GATHER_M; ++m)
+                                    PsfLoad<PT, V>::load(rs, (uint32_t)goff[m] * (uint32_t)sizeof(PT), pv[u][m]);
+                            }
+#pragma unroll
+                            for (int u = 0; u < GATHER_J; ++u)
+#pragma unroll
+                                for (int m = 0; m < GATHER_M; ++m)
+#pragma unroll
+                                    for (int v = 0; v < V; ++v) acc[m][v] = __builtin_fmaf(fl[u], pv[u][m][v], acc[m][v]);
+                        }
+                        for (; j < cn; ++j) {
                             const int32_t sh = __builtin_amdgcn_readfirstlane(g_shift[j]);
                             const float fl = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, g_flux[j])));
                             const char *base = (const char *)a.psf + (int64_t)sh * (int64_t)sizeof(PT);
@@ -902,7 +960,7 @@ template <class Tile> __global__ void __launch_bounds__(WG) tiled_kernel(const K
                     for (int m = 0; m < GATHER_M; ++m)
                         if (gv[m]) {
 #pragma unroll
-                            for (int v = 0; v < V; ++v) a.accbuf[gimg[m] + v] = acc[m][v];
+                            for (int v = 0; v < V; ++v) stc(&a.accbuf[gimg[m] + v], acc[m][v]);
                         }
                 }
             }
@@ -912,9 +970,8 @@ template <class Tile> __global__ void __launch_bounds__(WG) tiled_kernel(const K
 
         // ---- apply feedback and find each tile's new peak
         if (is_cluster) {
-            const uint64_t wk = wg_max_key(R.apply_feedback(im), s_red);
-            if (!cluster_max(y, slots, a.slot_pad, cs, rank, e++, wk, &s_bcast, &s_ok, cur)) return;
-            if (tile_leader_wg && threadIdx.x == 0) a.tile_key[tile] = cur;
+            if (!cluster_reduce(y, slots, a.slot_pad, cs, rank, e++, R.apply_feedback(im), cur)) return;
+            if (tile_leader_wg && threadIdx.x == 0) stc(&a.tile_key[tile], cur);
         }
         rounds += 1;
         if (!grid_barrier(y, epoch, &s_ok)) return;                        // C
@@ -924,9 +981,9 @@ template <class Tile> __global__ void __launch_bounds__(WG) tiled_kernel(const K
     // ---- results
     if (is_cluster) store_and_sum(R, im, a.partial, tile * cs + rank);
     if (blockIdx.x == 0 && threadIdx.x == 0) {
-        uint64_t best = a.tile_key[0];
+        uint64_t best = ldc(&a.tile_key[0]);
         for (int t = 1; t < T; ++t) {
-            const uint64_t k = a.tile_key[t];
+            const uint64_t k = ldc(&a.tile_key[t]);
             if ((k >> 33) > (best >> 33)) best = k;       // largest |v|, lowest tile id on ties
         }
         a.dstat->n_iter = used;
