@@ -163,6 +163,25 @@ def main():
     jy = {"tiled_minus_plain_model_min": float(delta.min()), "tiled_minus_plain_model_max": float(delta.max()),
           "paper_band": [-0.1, 0.04]}
 
+    # the same comparison under the other readings of the method: the flux
+    # trigger, and a 10-minute-track PSF (GPU runs; they are bit-identical to
+    # the oracle, so these bands are the method's, not the implementation's)
+    def band(cfg, level):
+        d_ = torch.from_numpy(cfg["dirty"]).to(dev)
+        p_ = torch.from_numpy(cfg["psf"]).to(dev)
+        mt = P.tiled_feedback(d_, p_, tiles, interval, gain, thr, n_iter, level=level)
+        mp = P.hogbom(d_, p_, gain, thr, n_iter)
+        dm = (mt["model"] - mp["model"]).cpu().numpy()
+        return {"min": float(dm.min()), "max": float(dm.max()), "rounds": mt["stats"]["n_rounds"],
+                "tiled_ms": mt["stats"]["device_ms"]}
+    ctrack = synth.make_config(1, psf_track=True)
+    jy["bands_tiled_minus_plain_model"] = {
+        "snapshot_psf_interval100": {"min": jy["tiled_minus_plain_model_min"], "max": jy["tiled_minus_plain_model_max"]},
+        "snapshot_psf_flux_level_0.5": band(c, 0.5),
+        "track_psf_interval100": band(ctrack, 0.0),
+        "track_psf_flux_level_0.5": band(ctrack, 0.5),
+    }
+
     cpu = None
     if not args.no_cpu or not args.no_jy:
         import oracle

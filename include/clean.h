@@ -94,6 +94,12 @@ typedef struct {
     int32_t px_per_thread;/* launch shape: residual pixels per thread, one of
                              4, 8, 16, 32, 64 when tile widths are multiples of
                              4, else 4, 16, 32 (0 = library pick)             */
+    double feedback_level;/* tiled only, in [0, 1]: the flux trigger.  Each
+                             round's level is this fraction of the largest tile
+                             peak at the round's start; a tile takes part only
+                             if its peak is at or above the level and ends its
+                             round when its peak drops below it (or after
+                             feedback_interval iterations).  0 = interval only */
 } clean_params;
 
 typedef struct {
@@ -151,6 +157,8 @@ int clean_hogbom(const float *dirty, int ny, int nx,
  * (i+1)*ny/tiles_y) and columns [j*nx/tiles_x, (j+1)*nx/tiles_x) (floor
  * division).  Each round: tiles whose peak is >= threshold are active; each
  * active tile runs up to `feedback_interval` minor iterations on its own pixels
+ * (with p->feedback_level > 0, a tile is active only at or above the round's
+ * flux level and its round also ends when its peak falls below it)
  * (when fewer than |active| * interval iterations remain, the remainder is split
  * evenly, lower tile ids taking the extra one); then every tile's new
  * components are placed on a component image (float64 sums in the order found,

@@ -45,7 +45,7 @@ def load():
     plain = [P, i32, i32, P, i32, i32, f64, f64, i64, P, P, P, i64, P, P, P]
     lib.oracle_hogbom_f32.argtypes = plain
     lib.oracle_hogbom_f64.argtypes = plain
-    tiled = [P, i32, i32, P, i32, i32, i32, i32, i32, f64, f64, i64, P, P, P, i64, P, P, P, P]
+    tiled = [P, i32, i32, P, i32, i32, i32, i32, i32, f64, f64, f64, i64, P, P, P, i64, P, P, P, P]
     lib.oracle_tiled_f32.argtypes = tiled
     lib.oracle_tiled_f64.argtypes = tiled
     fb = [P, i32, i32, i32, i32, P, i32, i32, P, P, P, i64]
@@ -94,8 +94,11 @@ def hogbom(dirty, psf, gain=0.1, threshold=0.0, max_iter=1000, cap=None, precisi
 
 
 def tiled(dirty, psf, tiles=(2, 2), interval=100, gain=0.1, threshold=0.0, max_iter=1000, cap=None,
-          precision="f32", model=True):
-    """Tiled Hogbom CLEAN with feedback.  Returns dict(..., n_rounds)."""
+          precision="f32", model=True, level=0.0):
+    """Tiled Hogbom CLEAN with feedback.  Returns dict(..., n_rounds).
+
+    level: the flux trigger, a fraction of the largest tile peak at each
+    round's start below which a tile ends its round (0: interval only)."""
     lib = load()
     dirty, psf = _inputs(dirty, psf)
     ny, nx = dirty.shape
@@ -110,7 +113,7 @@ def tiled(dirty, psf, tiles=(2, 2), interval=100, gain=0.1, threshold=0.0, max_i
     rounds = C.c_int32(0)
     fn = lib.oracle_tiled_f32 if precision == "f32" else lib.oracle_tiled_f64
     st = fn(_ptr(dirty), ny, nx, _ptr(psf), psf.shape[0], psf.shape[1], int(tiles[0]), int(tiles[1]),
-            int(interval), float(gain), float(threshold), int(max_iter), _ptr(res), _ptr(idx), _ptr(flux),
+            int(interval), float(level), float(gain), float(threshold), int(max_iter), _ptr(res), _ptr(idx), _ptr(flux),
             int(cap), _ptr(mod), C.byref(n), C.byref(stop), C.byref(rounds))
     if st != 0:
         raise ValueError(f"oracle_tiled returned {st}")

@@ -39,6 +39,12 @@
  *     component pixels in raster order) and the sum is subtracted once.
  *   - "total iterations" for the tiled form counts the minor iterations of all
  *     tiles together; per-round budgets split what remains evenly.
+ *   - feedback "at regular intervals" is the interval: a tile's round ends
+ *     after `interval` local iterations.  Feedback "triggered by meeting a
+ *     flux threshold" is the level: with level_frac > 0 a round's flux level
+ *     is level_frac times the largest tile peak at the round's start, a tile
+ *     takes part only if its peak is at or above it, and its round also ends
+ *     when its peak drops below it.
  */
 #include <math.h>
 #include <stdint.h>
@@ -376,7 +382,7 @@ int oracle_feedback_f64(double *r, int ny, int nx, int ty, int tx, const float *
 /* Tiled Hogbom CLEAN with feedback (Sections 2 and 3, Figs. 1-3), FP32.
  * Component output order: round, then tile, then local iteration. */
 int oracle_tiled_f32(const float *dirty, int ny, int nx, const float *psf, int psf_ny, int psf_nx,
-                     int tiles_y, int tiles_x, int interval,
+                     int tiles_y, int tiles_x, int interval, double level_frac,
                      double gain, double threshold, int64_t max_iter,
                      float *residual, int32_t *comp_idx, float *comp_flux, int64_t comp_cap,
                      double *model, int64_t *n_iter_out, int32_t *stop_out, int32_t *n_rounds_out)
@@ -384,6 +390,7 @@ int oracle_tiled_f32(const float *dirty, int ny, int nx, const float *psf, int p
     int st = check_common(ny, nx, psf_ny, psf_nx, gain, threshold, max_iter, comp_cap);
     if (st) return st;
     if (tiles_y < 1 || tiles_x < 1 || tiles_y > ny || tiles_x > nx || interval < 1) return OR_EINVAL;
+    if (!(level_frac >= 0.0 && level_frac <= 1.0)) return OR_EINVAL;
     const int ntiles = tiles_y * tiles_x;
     const int64_t npix = (int64_t)ny * nx;
     const float g = (float)gain;
@@ -392,24 +399,32 @@ int oracle_tiled_f32(const float *dirty, int ny, int nx, const float *psf, int p
     if (model) memset(model, 0, sizeof(double) * npix);
 
     int *active = (int *)calloc(ntiles, sizeof(int));
+    double *tpeak = (double *)calloc(ntiles, sizeof(double));
     int64_t *budget = (int64_t *)calloc(ntiles, sizeof(int64_t));
     int32_t *rtile = (int32_t *)malloc(sizeof(int32_t) * (size_t)ntiles * interval);
     int32_t *ridx = (int32_t *)malloc(sizeof(int32_t) * (size_t)ntiles * interval);
     float *rflux = (float *)malloc(sizeof(float) * (size_t)ntiles * interval);
-    if (!active || !budget || !rtile || !ridx || !rflux) {
-        free(active); free(budget); free(rtile); free(ridx); free(rflux);
+    if (!active || !tpeak || !budget || !rtile || !ridx || !rflux) {
+        free(active); free(tpeak); free(budget); free(rtile); free(ridx); free(rflux);
         return OR_ENOMEM;
     }
     const int64_t limit = max_iter < comp_cap ? max_iter : comp_cap;
     int64_t used = 0;
     int32_t rounds = 0, stop;
     for (;;) {
-        /* each tile's current peak decides whether it takes part */
-        int nactive = 0;
+        /* each tile's current peak decides whether it takes part: at or above
+         * the threshold, and at or above the round's flux level, the fraction
+         * level_frac of the largest tile peak (0: every tile above threshold) */
+        double vmax = 0.0;
         for (int t = 0; t < ntiles; ++t) {
             rect tr = tile_rect(ny, nx, tiles_y, tiles_x, t);
-            int64_t p = peak_f32(residual, nx, tr.y0, tr.y1, tr.x0, tr.x1);
-            active[t] = (double)fabsf(residual[p]) >= threshold;
+            tpeak[t] = (double)fabsf(residual[peak_f32(residual, nx, tr.y0, tr.y1, tr.x0, tr.x1)]);
+            vmax = tpeak[t] > vmax ? tpeak[t] : vmax;
+        }
+        const double level = level_frac * vmax;
+        int nactive = 0;
+        for (int t = 0; t < ntiles; ++t) {
+            active[t] = tpeak[t] >= threshold && tpeak[t] >= level;
             nactive += active[t];
         }
         if (used == max_iter) { stop = STOP_MAXITER; break; }
@@ -424,7 +439,7 @@ int oracle_tiled_f32(const float *dirty, int ny, int nx, const float *psf, int p
             for (int64_t k = 0; k < budget[t]; ++k) {
                 int64_t p = peak_f32(residual, nx, tr.y0, tr.y1, tr.x0, tr.x1);
                 float v = residual[p];
-                if ((double)fabsf(v) < threshold) break;
+                if ((double)fabsf(v) < threshold || (double)fabsf(v) < level) break;
                 float c = g * v;
                 rtile[nround] = t;
                 ridx[nround] = (int32_t)p;
@@ -445,7 +460,7 @@ int oracle_tiled_f32(const float *dirty, int ny, int nx, const float *psf, int p
         st = feedback_f32(residual, ny, nx, tiles_y, tiles_x, psf, psf_nx, cy, cx, rtile, ridx, rflux, nround);
         if (st) break;
     }
-    free(active); free(budget); free(rtile); free(ridx); free(rflux);
+    free(active); free(tpeak); free(budget); free(rtile); free(ridx); free(rflux);
     if (st) return st;
     *n_iter_out = used;
     *stop_out = stop;
@@ -454,7 +469,7 @@ int oracle_tiled_f32(const float *dirty, int ny, int nx, const float *psf, int p
 }
 
 int oracle_tiled_f64(const float *dirty, int ny, int nx, const float *psf, int psf_ny, int psf_nx,
-                     int tiles_y, int tiles_x, int interval,
+                     int tiles_y, int tiles_x, int interval, double level_frac,
                      double gain, double threshold, int64_t max_iter,
                      double *residual, int32_t *comp_idx, double *comp_flux, int64_t comp_cap,
                      double *model, int64_t *n_iter_out, int32_t *stop_out, int32_t *n_rounds_out)
@@ -462,6 +477,7 @@ int oracle_tiled_f64(const float *dirty, int ny, int nx, const float *psf, int p
     int st = check_common(ny, nx, psf_ny, psf_nx, gain, threshold, max_iter, comp_cap);
     if (st) return st;
     if (tiles_y < 1 || tiles_x < 1 || tiles_y > ny || tiles_x > nx || interval < 1) return OR_EINVAL;
+    if (!(level_frac >= 0.0 && level_frac <= 1.0)) return OR_EINVAL;
     const int ntiles = tiles_y * tiles_x;
     const int64_t npix = (int64_t)ny * nx;
     const int cy = psf_ny / 2, cx = psf_nx / 2;
@@ -469,23 +485,29 @@ int oracle_tiled_f64(const float *dirty, int ny, int nx, const float *psf, int p
     if (model) memset(model, 0, sizeof(double) * npix);
 
     int *active = (int *)calloc(ntiles, sizeof(int));
+    double *tpeak = (double *)calloc(ntiles, sizeof(double));
     int64_t *budget = (int64_t *)calloc(ntiles, sizeof(int64_t));
     int32_t *rtile = (int32_t *)malloc(sizeof(int32_t) * (size_t)ntiles * interval);
     int32_t *ridx = (int32_t *)malloc(sizeof(int32_t) * (size_t)ntiles * interval);
     double *rflux = (double *)malloc(sizeof(double) * (size_t)ntiles * interval);
-    if (!active || !budget || !rtile || !ridx || !rflux) {
-        free(active); free(budget); free(rtile); free(ridx); free(rflux);
+    if (!active || !tpeak || !budget || !rtile || !ridx || !rflux) {
+        free(active); free(tpeak); free(budget); free(rtile); free(ridx); free(rflux);
         return OR_ENOMEM;
     }
     const int64_t limit = max_iter < comp_cap ? max_iter : comp_cap;
     int64_t used = 0;
     int32_t rounds = 0, stop;
     for (;;) {
-        int nactive = 0;
+        double vmax = 0.0;
         for (int t = 0; t < ntiles; ++t) {
             rect tr = tile_rect(ny, nx, tiles_y, tiles_x, t);
-            int64_t p = peak_f64(residual, nx, tr.y0, tr.y1, tr.x0, tr.x1);
-            active[t] = fabs(residual[p]) >= threshold;
+            tpeak[t] = fabs(residual[peak_f64(residual, nx, tr.y0, tr.y1, tr.x0, tr.x1)]);
+            vmax = tpeak[t] > vmax ? tpeak[t] : vmax;
+        }
+        const double level = level_frac * vmax;
+        int nactive = 0;
+        for (int t = 0; t < ntiles; ++t) {
+            active[t] = tpeak[t] >= threshold && tpeak[t] >= level;
             nactive += active[t];
         }
         if (used == max_iter) { stop = STOP_MAXITER; break; }
@@ -498,7 +520,7 @@ int oracle_tiled_f64(const float *dirty, int ny, int nx, const float *psf, int p
             for (int64_t k = 0; k < budget[t]; ++k) {
                 int64_t p = peak_f64(residual, nx, tr.y0, tr.y1, tr.x0, tr.x1);
                 double v = residual[p];
-                if (fabs(v) < threshold) break;
+                if (fabs(v) < threshold || fabs(v) < level) break;
                 double c = gain * v;
                 rtile[nround] = t;
                 ridx[nround] = (int32_t)p;
@@ -517,7 +539,7 @@ int oracle_tiled_f64(const float *dirty, int ny, int nx, const float *psf, int p
         st = feedback_f64(residual, ny, nx, tiles_y, tiles_x, psf, psf_nx, cy, cx, rtile, ridx, rflux, nround);
         if (st) break;
     }
-    free(active); free(budget); free(rtile); free(ridx); free(rflux);
+    free(active); free(tpeak); free(budget); free(rtile); free(ridx); free(rflux);
     if (st) return st;
     *n_iter_out = used;
     *stop_out = stop;

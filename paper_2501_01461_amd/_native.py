@@ -29,7 +29,7 @@ EXPORTS = ("clean_hogbom", "clean_tiled_feedback", "clean_batched", "clean_works
 class Params(C.Structure):
     _fields_ = [("gain", C.c_double), ("threshold", C.c_double), ("max_iter", C.c_int64),
                 ("psf_dtype", C.c_int32), ("flags", C.c_int32), ("wg_per_tile", C.c_int32),
-                ("px_per_thread", C.c_int32)]
+                ("px_per_thread", C.c_int32), ("feedback_level", C.c_double)]
 
 
 class Stats(C.Structure):
@@ -161,13 +161,18 @@ def hogbom(dirty, psf, gain=0.1, threshold=0.0, max_iter=1000, cap=None, model=T
 
 
 def tiled_feedback(dirty, psf, tiles=(2, 2), interval=100, gain=0.1, threshold=0.0, max_iter=1000, cap=None,
-                   model=True, check_finite=False, wg_per_tile=0, px_per_thread=0, stream=False, out=None):
-    """Tiled Hogbom CLEAN with feedback; returns dict(residual, idx, flux, model, stats)."""
+                   model=True, check_finite=False, wg_per_tile=0, px_per_thread=0, stream=False, out=None,
+                   level=0.0):
+    """Tiled Hogbom CLEAN with feedback; returns dict(residual, idx, flux, model, stats).
+
+    level: flux trigger, the fraction of the largest tile peak at a round's
+    start below which a tile ends its round (0: interval only)."""
     lib = load()
     dirty, psf = _prep(dirty, psf)
     cap = int(max_iter if cap is None else cap)
     res, idx, flux, mod = out if out is not None else _outputs(dirty, cap, model)
     p = _params(gain, threshold, max_iter, psf, _flags(check_finite, stream), wg_per_tile, px_per_thread)
+    p.feedback_level = float(level)
     st = Stats()
     ny, nx = dirty.shape
     _check(lib.clean_tiled_feedback(_ptr(dirty), ny, nx, _ptr(psf), psf.shape[0], psf.shape[1], int(tiles[0]),
@@ -207,7 +212,7 @@ def batched(problems, gain=0.1, model=True, check_finite=False, px_per_thread=0)
     if n == 0:
         return []
     dt = PSF_F16 if psf_dtype == torch.float16 else PSF_F32
-    prm = Params(float(gain), 0.0, 0, dt, FLAG_CHECK_FINITE if check_finite else 0, 0, int(px_per_thread))
+    prm = Params(float(gain), 0.0, 0, dt, FLAG_CHECK_FINITE if check_finite else 0, 0, int(px_per_thread), 0.0)
     stats = (Stats * n)()
     _check(lib.clean_batched(arr, n, C.byref(prm), stats, _stream()))
     res = []

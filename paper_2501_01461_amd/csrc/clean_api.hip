@@ -312,6 +312,8 @@ int run(bool tiled, const float *dirty, int ny, int nx, const void *psf, int psf
             return fail(CLEAN_E_UNSUPPORTED, "%d tiles exceed %d", tiles_y * tiles_x, MAX_TILES);
         if (interval < 1 || interval > MAX_INTERVAL)
             return fail(CLEAN_E_INVAL, "feedback interval %d not in [1, %d]", interval, MAX_INTERVAL);
+        if (!(p->feedback_level >= 0.0 && p->feedback_level <= 1.0))
+            return fail(CLEAN_E_INVAL, "feedback_level %g not in [0, 1]", p->feedback_level);
     } else {
         tiles_y = tiles_x = 1;
         interval = 1;
@@ -435,6 +437,7 @@ int run(bool tiled, const float *dirty, int ny, int nx, const void *psf, int psf
     a.cs = cs;
     a.slot_pad = slot_pad;
     a.interval = interval;
+    a.level_frac = tiled ? p->feedback_level : 0.0;
     a.gather_parts = std::max(1, W / T);
     a.gain = (float)p->gain;
     a.threshold = p->threshold;

@@ -79,6 +79,7 @@ struct KArgs {
     int cs;                 // workgroups per tile cluster
     int slot_pad;           // u64 slots per parity block of a cluster
     int interval;           // feedback interval (tiled)
+    double level_frac;      // flux trigger: fraction of the largest tile peak (0: off)
     int gather_parts;       // gather work items per tile
     float gain;
     double threshold;

@@ -737,6 +737,7 @@ template <class Tile> __global__ void __launch_bounds__(WG) tiled_kernel(const K
     constexpr int V = Tile::kV;
     using PT = typename Tile::psf_t;
     __shared__ int s_ok, s_tmp, s_cnt;
+    __shared__ uint32_t s_vmax;
     __shared__ int32_t s_off[MAX_TILES + 1];    // exclusive prefix of per-tile counts
     extern __shared__ __align__(16) unsigned char s_dyn[];
 
@@ -778,11 +779,20 @@ template <class Tile> __global__ void __launch_bounds__(WG) tiled_kernel(const K
     double mflux = 0.0;
     uint64_t ph_local = 0, ph_gather = 0, ph_apply = 0, tp0 = 0, tp1 = 0;
     for (;;) {
-        // ---- round control, computed identically by every workgroup
+        // ---- round control, computed identically by every workgroup: a tile
+        // takes part when its peak is at or above the threshold and at or above
+        // the round's flux level (level_frac times the largest tile peak)
+        uint32_t vbits = 0;
+        for (int t = threadIdx.x; t < T; t += WG) vbits = max(vbits, (uint32_t)(ldc(&a.tile_key[t]) >> 33));
+        if (threadIdx.x == 0) s_vmax = 0;
+        __syncthreads();
+        if (vbits) atomicMax(&s_vmax, vbits);
+        __syncthreads();
+        const double level = a.level_frac * (double)__uint_as_float(s_vmax);
         int na_part = 0, rk_part = 0;
         for (int t = threadIdx.x; t < T; t += WG) {
-            const uint64_t k = ldc(&a.tile_key[t]);
-            const int act = (double)fabsf(key_value(k)) >= a.threshold;
+            const double pk = (double)fabsf(key_value(ldc(&a.tile_key[t])));
+            const int act = pk >= a.threshold && pk >= level;
             na_part += act;
             rk_part += act && (t < tile);
         }
@@ -794,7 +804,8 @@ template <class Tile> __global__ void __launch_bounds__(WG) tiled_kernel(const K
         const int64_t rem = limit - used;
         int64_t budget = 0;
         if (is_cluster) {
-            const bool act = (double)fabsf(key_value(cur)) >= a.threshold;
+            const double pk = (double)fabsf(key_value(cur));
+            const bool act = pk >= a.threshold && pk >= level;
             if (act) budget = rem >= (int64_t)na * a.interval ? a.interval
                                                                 : rem / na + (my_rank < rem % na ? 1 : 0);
         }
@@ -805,7 +816,7 @@ template <class Tile> __global__ void __launch_bounds__(WG) tiled_kernel(const K
             int L = 0;
             for (int64_t it = 0; it < budget; ++it) {
                 const float v = key_value(cur);
-                if ((double)fabsf(v) < a.threshold) break;
+                if ((double)fabsf(v) < a.threshold || (double)fabsf(v) < level) break;
                 const float c = a.gain * v;
                 const uint32_t fp = key_f(cur);
                 const int ly = (int)(fp / (uint32_t)R.w), lx = (int)(fp % (uint32_t)R.w);

@@ -6,7 +6,9 @@ definition of a minor iteration (find the largest |r|, lowest row-major index
 on a tie; component = gain * value; subtract component * PSF centred on the
 peak), and the tiled form with feedback, where a tile cleans only its own
 pixels and, at the end of each round, every component found in the round has
-its PSF subtracted from all pixels outside its tile.  In exact arithmetic that
+its PSF subtracted from all pixels outside its tile.  A round ends after the
+interval or, with a flux level, when the tile's peak falls below that fraction
+of the largest tile peak at the round's start.  In exact arithmetic that
 equals subtracting the cross-coupling images (component image convolved with
 the PSF), so aggregation order and rounding do not enter.
 """
@@ -63,7 +65,7 @@ def tile_pixels(ny, nx, ty, tx, t):
     return [(y, x) for y in range(y0, y1) for x in range(x0, x1)]
 
 
-def tiled(dirty, psf, tiles, interval, gain, threshold, max_iter):
+def tiled(dirty, psf, tiles, interval, gain, threshold, max_iter, level=0.0):
     ny, nx = dirty.shape
     ty, tx = tiles
     r = to_frac_image(dirty)
@@ -75,8 +77,13 @@ def tiled(dirty, psf, tiles, interval, gain, threshold, max_iter):
     tpix = [tile_pixels(ny, nx, ty, tx, t) for t in range(T)]
     all_pix = list(r.keys())
     comps, margins, rounds = [], [], 0
+    lev_frac = Fraction(level)
     while True:
-        active = [abs(peak(r, tpix[t])[1]) >= thr for t in range(T)]
+        # a tile takes part at or above the threshold and at or above the round's
+        # flux level (a fraction of the largest tile peak at the round's start)
+        tpk = [abs(peak(r, tpix[t])[1]) for t in range(T)]
+        lev = lev_frac * max(tpk)
+        active = [tpk[t] >= thr and tpk[t] >= lev for t in range(T)]
         if len(comps) == max_iter or not any(active):
             break
         rem, na = max_iter - len(comps), sum(active)
@@ -91,7 +98,7 @@ def tiled(dirty, psf, tiles, interval, gain, threshold, max_iter):
         for t in range(T):
             for _ in range(budget[t]):
                 p, v, m = peak(r, tpix[t])
-                if abs(v) < thr:
+                if abs(v) < thr or abs(v) < lev:
                     break
                 c = g * v
                 found.append((t, p, c))

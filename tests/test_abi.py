@@ -43,7 +43,7 @@ def test_version_and_strerror(lib):
 
 
 def params(**kw):
-    p = N.Params(0.1, 0.0, 100, 0, 0, 0, 0)
+    p = N.Params(0.1, 0.0, 100, 0, 0, 0, 0, 0.0)
     for k, v in kw.items():
         setattr(p, k, v)
     return p
@@ -77,7 +77,8 @@ def test_plain_argument_errors(lib, kw, code):
 
 @pytest.mark.parametrize("kw,code", [
     (dict(ty=0), INVAL), (dict(tx=17), INVAL), (dict(interval=0), INVAL), (dict(interval=2049), INVAL),
-    (dict(ty=40, tx=40, ny=64, nx=64), UNSUPPORTED),
+    (dict(ty=40, tx=40, ny=64, nx=64), UNSUPPORTED), (dict(p=params(feedback_level=1.5)), INVAL),
+    (dict(p=params(feedback_level=-0.1)), INVAL),
 ])
 def test_tiled_argument_errors(lib, kw, code):
     assert tiled(lib, **kw) == code

@@ -276,3 +276,34 @@ def test_tiled_config2_prefix(lib, config2, f16):
     out = lib.tiled_feedback(dev(c["dirty"]), lib.psf_to_f16(p) if f16 else p, (8, 8), 10, 0.1, 0.0, 1280)
     assert out["stats"]["n_rounds"] == ref["n_rounds"] == 2
     assert_same_run(out, ref)
+
+
+# -------------------------------------------- feedback by a flux level --
+
+@pytest.mark.parametrize("case", [
+    (64, 64, (2, 2), 50, 51, 600, 0.0, 0.5, False),
+    (60, 72, (3, 2), 1000, 52, 800, 0.02, 0.7, False),
+    (96, 96, (2, 3), 20, 53, 500, 0.0, 0.3, True),
+    (50, 62, (2, 2), 2048, 54, 700, 0.01, 0.9, False),
+], ids=["2x2-I50-f0.5", "3x2-I1000-f0.7", "2x3-I20-f0.3-stream", "2x2-odd-f0.9"])
+def test_tiled_flux_trigger_small(lib, case):
+    ny, nx, tiles, interval, seed, n, thr, level, stream = case
+    announce("tiled flux", case)
+    dirty = sparse_dirty(ny, nx, seed, density=0.03)
+    psf = asym_psf(2 * ny, 2 * nx + 2, seed, spread=0.2)
+    ref = oracle.tiled(dirty, psf, tiles, interval, 0.1, thr, n, level=level)
+    out = lib.tiled_feedback(dev(dirty), dev(psf), tiles, interval, 0.1, thr, n, level=level, stream=stream)
+    assert out["stats"]["n_rounds"] == ref["n_rounds"]
+    assert_same_run(out, ref)
+
+
+def test_tiled_flux_trigger_config1(lib):
+    """The 1024^2 / 2x2 workload with feedback at half the largest tile peak
+    (interval 100 as the cap), full 20000 iterations, bit for bit."""
+    announce("tiled flux config1")
+    c = synth.make_config(1)
+    ref = oracle.tiled(c["dirty"], c["psf"], c["tiles"], c["interval"], 0.1, 0.0, c["max_iter"], level=0.5)
+    out = lib.tiled_feedback(dev(c["dirty"]), dev(c["psf"]), c["tiles"], c["interval"], 0.1, 0.0, c["max_iter"],
+                             level=0.5)
+    assert out["stats"]["n_rounds"] == ref["n_rounds"]
+    assert_same_run(out, ref)

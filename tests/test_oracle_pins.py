@@ -197,6 +197,35 @@ def test_tiled_threshold_against_exact_rationals():
     assert np.max(np.abs(out["flux"] - np.array([float(c[1]) for c in comps]))) < 1e-12
 
 
+@pytest.mark.parametrize("level,interval,n", [(0.5, 50, 150), (0.8, 7, 150), (0.3, 1000, 600)])
+def test_tiled_flux_trigger_against_exact_rationals(level, interval, n):
+    """Feedback triggered by a flux level: round count and every component
+    against exact arithmetic."""
+    r = np.random.default_rng([7, 178])
+    ny, nx = 12, 14
+    d = np.round(r.normal(0, 0.01, (ny, nx)) * 2 ** 20) / 2 ** 20
+    for _ in range(6):
+        d[r.integers(ny), r.integers(nx)] += np.round(r.uniform(-2, 2) * 2 ** 20) / 2 ** 20
+    dirty = d.astype(np.float32)
+    psf = gauss_dyadic_psf(24, 28, 1.2)
+    r_ex, comps, margins, rounds = exact_clean.tiled(dirty, psf, (2, 2), interval, 0.1, 0.05, n, level=level)
+    out = oracle.tiled(dirty, psf, (2, 2), interval, 0.1, 0.05, n, precision="f64", level=level)
+    assert rounds > 3
+    assert out["n_iter"] == len(comps) and out["n_rounds"] == rounds
+    assert min(float(m) for m in margins) > 1e-9
+    assert np.array_equal(out["idx"], np.array([c[0] for c in comps]))
+    assert np.max(np.abs(out["flux"] - np.array([float(c[1]) for c in comps]))) < 1e-12
+
+
+def test_flux_level_zero_is_the_interval_rule():
+    c = synth.make_config(0)
+    a = oracle.tiled(c["dirty"], c["psf"], (2, 2), 40, 0.1, 5e-3, 600)
+    b = oracle.tiled(c["dirty"], c["psf"], (2, 2), 40, 0.1, 5e-3, 600, level=0.0)
+    assert np.array_equal(a["idx"], b["idx"]) and np.array_equal(a["residual"], b["residual"])
+    with pytest.raises(ValueError):
+        oracle.tiled(c["dirty"], c["psf"], (2, 2), 40, 0.1, 5e-3, 600, level=1.5)
+
+
 # -------------------------------------------------------- ties and stops --
 
 @pytest.mark.parametrize("precision", ["f32", "f64"])
