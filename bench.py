@@ -49,6 +49,24 @@ def measured_traffic():
     return rec if rec.get("source_sha256") == h.hexdigest() else None
 
 
+def clean_beam_sigma(psf):
+    """Gaussian clean beam from the PSF main lobe: FWHM = 2 sqrt(A/pi), with A
+    the area (pixels) of the connected region around the peak above one half."""
+    from scipy import ndimage
+    M0, M1 = psf.shape
+    lab, _ = ndimage.label(psf > 0.5)
+    area = float(np.count_nonzero(lab == lab[M0 // 2, M1 // 2]))
+    fwhm = 2.0 * np.sqrt(area / np.pi)
+    return fwhm / (2.0 * np.sqrt(2.0 * np.log(2.0)))
+
+
+def restored(model, residual, sigma):
+    """model (*) peak-1 Gaussian beam + residual, in Jy/beam (evaluation only)."""
+    from scipy import ndimage
+    sm = ndimage.gaussian_filter(model, sigma, mode="constant", truncate=5.0) * (2.0 * np.pi * sigma * sigma)
+    return sm + residual.astype(np.float64)
+
+
 def feedback_bytes(idx, ny, nx, tiles, interval, n_total, psf_bytes):
     """Algorithmic bytes of the feedback rounds of a threshold-0 run.
 
@@ -84,6 +102,7 @@ def main():
     ap.add_argument("--psf-f16", action="store_true", help="store the PSF as float16")
     ap.add_argument("--no-batched", action="store_true", help="skip the 256-problem batched measurement")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain comparison (profiling runs)")
+    ap.add_argument("--no-4096", action="store_true", help="skip the 4096^2 / 8x8-tile measurement")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the tiled CLEAN path here runs on a single device "
@@ -166,21 +185,30 @@ def main():
     # the same comparison under the other readings of the method: the flux
     # trigger, and a 10-minute-track PSF (GPU runs; they are bit-identical to
     # the oracle, so these bands are the method's, not the implementation's)
-    def band(cfg, level):
+    def band(cfg, level, ivl):
         d_ = torch.from_numpy(cfg["dirty"]).to(dev)
         p_ = torch.from_numpy(cfg["psf"]).to(dev)
-        mt = P.tiled_feedback(d_, p_, tiles, interval, gain, thr, n_iter, level=level)
+        mt = P.tiled_feedback(d_, p_, tiles, ivl, gain, thr, n_iter, level=level)
         mp = P.hogbom(d_, p_, gain, thr, n_iter)
-        dm = (mt["model"] - mp["model"]).cpu().numpy()
-        return {"min": float(dm.min()), "max": float(dm.max()), "rounds": mt["stats"]["n_rounds"],
-                "tiled_ms": mt["stats"]["device_ms"]}
+        mt_m, mp_m = mt["model"].cpu().numpy(), mp["model"].cpu().numpy()
+        dm = mt_m - mp_m
+        sg = clean_beam_sigma(cfg["psf"])
+        dr = restored(mt_m, mt["residual"].cpu().numpy(), sg) - restored(mp_m, mp["residual"].cpu().numpy(), sg)
+        out = {"model_min": float(dm.min()), "model_max": float(dm.max()),
+               "restored_min": float(dr.min()), "restored_max": float(dr.max()),
+               "rounds": mt["stats"]["n_rounds"], "tiled_ms": mt["stats"]["device_ms"]}
+        out["restored_in_paper_band"] = bool(out["restored_min"] >= -0.1 and out["restored_max"] <= 0.04)
+        return out
     ctrack = synth.make_config(1, psf_track=True)
-    jy["bands_tiled_minus_plain_model"] = {
-        "snapshot_psf_interval100": {"min": jy["tiled_minus_plain_model_min"], "max": jy["tiled_minus_plain_model_max"]},
-        "snapshot_psf_flux_level_0.5": band(c, 0.5),
-        "track_psf_interval100": band(ctrack, 0.0),
-        "track_psf_flux_level_0.5": band(ctrack, 0.5),
+    jy["bands_tiled_minus_plain"] = {
+        "snapshot_psf_interval100": band(c, 0.0, interval),
+        "snapshot_psf_flux_level_0.5": band(c, 0.5, interval),
+        "track_psf_interval100": band(ctrack, 0.0, interval),
+        "track_psf_interval10": band(ctrack, 0.0, 10),
+        "track_psf_flux_level_0.5": band(ctrack, 0.5, interval),
     }
+    jy["bands_note"] = ("differences tiled - plain (Jy) after the same 20000 total minor iterations; "
+                        "restored = model (*) Gaussian clean beam fitted to the PSF main lobe + residual")
 
     cpu = None
     if not args.no_cpu or not args.no_jy:
@@ -243,6 +271,38 @@ def main():
                                "sources, threshold 5e-3 Jy"}
         log(f"batched: {b_ms:.1f} ms per launch, {sum(its)} iterations; one call per problem: {seq_ms:.1f} ms")
 
+    big = None
+    if not args.no_4096:
+        import oracle
+        t1 = time.time()
+        c2 = synth.make_config(2)
+        d2 = torch.from_numpy(c2["dirty"]).to(dev)
+        p2 = torch.from_numpy(c2["psf"]).to(dev)
+        p2h = P.psf_to_f16(p2)
+        big = {"workload": "4096x4096 image, 8192x8192 Y-array snapshot PSF, 2000 sources, 8x8 tiles, "
+                           "200000 total minor iterations (residual streamed through HBM)", "runs": {}}
+        for ivl in (50, 200, 1000):
+            for nm, pp, sp in (("f32", p2, 4), ("f16", p2h, 2)):
+                r = P.tiled_feedback(d2, pp, (8, 8), ivl, gain, 0.0, c2["max_iter"])
+                st = r["stats"]
+                big["runs"][f"I{ivl}_{nm}"] = {
+                    "kernel_ms": st["device_ms"], "iters_per_s": st["n_iter"] / (st["device_ms"] * 1e-3),
+                    "n_iter": st["n_iter"], "stop": st["stop_reason"], "rounds": st["n_rounds"],
+                    "phase_us": st["phase_us"], "wg_per_tile": st["wg_per_tile"]}
+        pr = P.hogbom(d2, p2, gain, 0.0, 2000)
+        big["plain_prefix_2000"] = {"kernel_ms": pr["stats"]["device_ms"],
+                                    "iters_per_s": 2000 / (pr["stats"]["device_ms"] * 1e-3),
+                                    "note": "plain clean_hogbom on the same input, first 2000 iterations"}
+        if not args.no_jy:
+            # errors against the float64 oracle over the first round (12800 iterations at interval 200)
+            npre = 64 * 200
+            o64 = oracle.tiled(c2["dirty"], c2["psf"], (8, 8), 200, gain, 0.0, npre, precision="f64")
+            for nm, pp in (("f32", p2), ("f16", p2h)):
+                r = P.tiled_feedback(d2, pp, (8, 8), 200, gain, 0.0, npre)
+                big[f"first_round_{nm}_vs_fp64_oracle_model_max_abs"] = float(
+                    np.max(np.abs(r["model"].cpu().numpy() - o64["model"])))
+        log(f"4096^2 workload: {time.time() - t1:.1f} s")
+
     traffic = measured_traffic()
     line = {
         "metric": "CLEAN minor-iters/s + achieved GB/s: tiled-feedback vs plain, 1 GPU, at Jy error",
@@ -279,6 +339,7 @@ def main():
                   "launch": {"wg_per_tile": st_p["wg_per_tile"], "px_per_thread": st_p["px_per_thread"]}},
         "speedup_tiled_vs_plain": ms_p / ms_t,
         "batched": batched,
+        "tiled_4096": big,
         "jy": jy,
     }
     print(json.dumps(line), flush=True)

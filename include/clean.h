@@ -215,6 +215,22 @@ typedef struct {
 int clean_batched(const clean_problem *probs, int n, const clean_params *shared,
                   clean_stats *stats, void *stream);
 
+/*
+ * clean_autotune -- picks the launch shape (p->wg_per_tile, p->px_per_thread)
+ * of clean_hogbom (tiles_y = tiles_x = 1) or clean_tiled_feedback for this
+ * image, PSF dtype and tile grid by timing trial runs of `trial_iter` minor
+ * iterations (capped by p->max_iter) on the caller's buffers, and writes the
+ * fastest into *best (a copy of *p with the two shape fields set).  Every
+ * shape gives bit-identical results; only the speed differs.  The residual and
+ * component arrays are overwritten by the trials.  The choice is cached per
+ * process by (device, ny, nx, tile grid, interval, PSF dtype, streaming flag).
+ * Arguments otherwise as for clean_tiled_feedback.
+ */
+int clean_autotune(const float *dirty, int ny, int nx, const void *psf, int psf_ny, int psf_nx,
+                   int tiles_y, int tiles_x, int feedback_interval, const clean_params *p,
+                   float *residual, int32_t *comp_idx, float *comp_flux, int64_t comp_cap,
+                   int64_t trial_iter, clean_params *best, void *stream);
+
 /* Bytes of device workspace clean_hogbom (tiles 1x1) or clean_tiled_feedback
  * needs for this shape; 0 on invalid arguments. */
 size_t clean_workspace_size(int ny, int nx, int tiles_y, int tiles_x,

@@ -22,7 +22,7 @@ FLAG_CHECK_FINITE = 1
 FLAG_STREAM_RESIDUAL = 2
 
 # every symbol include/clean.h declares
-EXPORTS = ("clean_hogbom", "clean_tiled_feedback", "clean_batched", "clean_workspace_size",
+EXPORTS = ("clean_hogbom", "clean_tiled_feedback", "clean_batched", "clean_autotune", "clean_workspace_size",
            "clean_psf_to_f16", "clean_strerror", "clean_last_error", "clean_version")
 
 
@@ -74,6 +74,9 @@ def load():
     lib.clean_tiled_feedback.argtypes = [P, i32, i32, P, i32, i32, i32, i32, i32, C.POINTER(Params), P, P, P,
                                          i64, P, P, sz, C.POINTER(Stats), P]
     lib.clean_batched.argtypes = [C.POINTER(Problem), i32, C.POINTER(Params), C.POINTER(Stats), P]
+    lib.clean_autotune.argtypes = [P, i32, i32, P, i32, i32, i32, i32, i32, C.POINTER(Params), P, P, P, i64, i64,
+                                   C.POINTER(Params), P]
+    lib.clean_autotune.restype = C.c_int
     lib.clean_workspace_size.argtypes = [i32, i32, i32, i32, i32, C.POINTER(Params)]
     lib.clean_workspace_size.restype = sz
     lib.clean_psf_to_f16.argtypes = [P, P, i64, P]
@@ -221,6 +224,23 @@ def batched(problems, gain=0.1, model=True, check_finite=False, px_per_thread=0)
         k = stats[i].n_iter
         res.append(dict(residual=r, idx=idx[:k], flux=flux[:k], model=mod, stats=stats[i].as_dict()))
     return res
+
+
+def autotune(dirty, psf, tiles=(1, 1), interval=100, gain=0.1, threshold=0.0, max_iter=1000, trial_iter=2000,
+             stream=False):
+    """The launch shape the library's tuner measures fastest for this problem:
+    returns dict(wg_per_tile, px_per_thread) to pass to hogbom/tiled_feedback."""
+    lib = load()
+    dirty, psf = _prep(dirty, psf)
+    cap = int(min(max_iter, trial_iter))
+    res, idx, flux, _ = _outputs(dirty, cap, False)
+    p = _params(gain, threshold, max_iter, psf, _flags(False, stream), 0, 0)
+    best = Params()
+    ny, nx = dirty.shape
+    _check(lib.clean_autotune(_ptr(dirty), ny, nx, _ptr(psf), psf.shape[0], psf.shape[1], int(tiles[0]),
+                              int(tiles[1]), int(interval), C.byref(p), _ptr(res), _ptr(idx), _ptr(flux), cap,
+                              int(trial_iter), C.byref(best), _stream()))
+    return dict(wg_per_tile=best.wg_per_tile, px_per_thread=best.px_per_thread)
 
 
 def psf_to_f16(psf):

@@ -10,8 +10,10 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "clean.h"
@@ -728,6 +730,80 @@ size_t clean_workspace_size(int ny, int nx, int tiles_y, int tiles_x, int feedba
     const Layout L = make_layout(T, tiled ? cs_max / T + 64 : cs_max, (cs_max + 31) / 32 * 32,
                                  tiled ? feedback_interval : 1, W_max, npix, tiled);
     return L.total;
+}
+
+namespace {
+using TuneKey = std::tuple<int, int, int, int, int, int, int, int>;   // dev, ny, nx, ty, tx, dtype, stream flag, interval
+std::mutex g_tune_mu;
+std::map<TuneKey, std::pair<int, int>> g_tune_cache;
+}
+
+int clean_autotune(const float *dirty, int ny, int nx, const void *psf, int psf_ny, int psf_nx, int tiles_y,
+                   int tiles_x, int feedback_interval, const clean_params *p, float *residual, int32_t *comp_idx,
+                   float *comp_flux, int64_t comp_cap, int64_t trial_iter, clean_params *best, void *stream)
+{
+    g_last_error.clear();
+    if (!best || !p) return fail(CLEAN_E_INVAL, "params and best must be non-NULL");
+    const bool tiled = !(tiles_y == 1 && tiles_x == 1);
+    if (trial_iter < 1) return fail(CLEAN_E_INVAL, "trial_iter must be >= 1");
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    const TuneKey key{dev, ny, nx, tiles_y, tiles_x, p->psf_dtype, p->flags & CLEAN_FLAG_STREAM_RESIDUAL,
+                      tiled ? feedback_interval : 0};
+    *best = *p;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune_cache.find(key);
+        if (it != g_tune_cache.end()) {
+            best->wg_per_tile = it->second.first;
+            best->px_per_thread = it->second.second;
+            return CLEAN_OK;
+        }
+    }
+    // candidate shapes: each pixels-per-thread option with the smallest
+    // cluster that holds the largest tile, and with twice that many workgroups
+    int64_t max_tile = 0;
+    bool w4 = true;
+    for (int i = 0; i < tiles_y; ++i)
+        for (int j = 0; j < tiles_x; ++j) {
+            const int h = (int)((int64_t)(i + 1) * ny / tiles_y - (int64_t)i * ny / tiles_y);
+            const int w = (int)((int64_t)(j + 1) * nx / tiles_x - (int64_t)j * nx / tiles_x);
+            max_tile = std::max<int64_t>(max_tile, (int64_t)h * w);
+            if (w % 4) w4 = false;
+        }
+    std::vector<int> ppts = w4 ? std::vector<int>{8, 16, 32, 64} : std::vector<int>{4, 16, 32};
+    clean_params trial = *p;
+    trial.max_iter = std::min<int64_t>(trial_iter, p->max_iter);
+    const int64_t cap = std::min<int64_t>(comp_cap, trial.max_iter);
+    float best_ms = -1.f;
+    int best_cs = 0, best_ppt = 0;
+    for (int ppt : ppts) {
+        if (tiled && ppt > 32) continue;
+        const int cs0 = (int)((max_tile + (int64_t)WG * ppt - 1) / ((int64_t)WG * ppt));
+        for (int mult = 1; mult <= 2; ++mult) {
+            trial.wg_per_tile = cs0 * mult;
+            trial.px_per_thread = ppt;
+            clean_stats st{};
+            const int rc = tiled ? run(true, dirty, ny, nx, psf, psf_ny, psf_nx, tiles_y, tiles_x, feedback_interval,
+                                       &trial, residual, comp_idx, comp_flux, cap, nullptr, nullptr, 0, &st, stream)
+                                 : run(false, dirty, ny, nx, psf, psf_ny, psf_nx, 1, 1, 1, &trial, residual, comp_idx,
+                                       comp_flux, cap, nullptr, nullptr, 0, &st, stream);
+            if (rc == CLEAN_E_INVAL || rc == CLEAN_E_UNSUPPORTED) continue;   // shape does not fit
+            if (rc) return rc;
+            if (best_ms < 0 || st.device_ms < best_ms) {
+                best_ms = st.device_ms;
+                best_cs = trial.wg_per_tile;
+                best_ppt = ppt;
+            }
+        }
+    }
+    g_last_error.clear();
+    if (best_ms < 0) return fail(CLEAN_E_UNSUPPORTED, "no candidate launch shape fits");
+    best->wg_per_tile = best_cs;
+    best->px_per_thread = best_ppt;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune_cache[key] = {best_cs, best_ppt};
+    return CLEAN_OK;
 }
 
 int clean_psf_to_f16(const float *psf, uint16_t *out, int64_t n, void *stream_v)

@@ -115,3 +115,12 @@ def test_workspace_size(lib):
 def test_psf_to_f16_argument_errors(lib):
     assert lib.clean_psf_to_f16(None, FAKE, 10, None) == INVAL
     assert lib.clean_psf_to_f16(FAKE, FAKE, -1, None) == INVAL
+
+
+def test_autotune_argument_errors(lib):
+    p = params()
+    best = N.Params()
+    assert lib.clean_autotune(FAKE, 16, 16, FAKE, 32, 32, 1, 1, 1, C.byref(p), FAKE, FAKE, FAKE, 10, 10, None,
+                              None) == INVAL
+    assert lib.clean_autotune(FAKE, 16, 16, FAKE, 32, 32, 1, 1, 1, C.byref(p), FAKE, FAKE, FAKE, 10, 0,
+                              C.byref(best), None) == INVAL

@@ -307,3 +307,20 @@ def test_tiled_flux_trigger_config1(lib):
                              level=0.5)
     assert out["stats"]["n_rounds"] == ref["n_rounds"]
     assert_same_run(out, ref)
+
+
+def test_autotune_returns_a_shape_with_identical_results(lib):
+    announce("autotune")
+    c = synth.make_config(0)
+    d, p = dev(c["dirty"]), dev(c["psf"])
+    sh = lib.autotune(d, p, (1, 1), 1, 0.1, 5e-3, 1000, trial_iter=300)
+    assert sh["wg_per_tile"] >= 1 and sh["px_per_thread"] in (4, 8, 16, 32, 64)
+    a = lib.hogbom(d, p, 0.1, 5e-3, 1000)
+    b = lib.hogbom(d, p, 0.1, 5e-3, 1000, **sh)
+    assert np.array_equal(host(a["idx"]), host(b["idx"]))
+    assert np.array_equal(bits(host(a["residual"])), bits(host(b["residual"])))
+    st = lib.autotune(d, p, (2, 2), 50, 0.1, 5e-3, 1000, trial_iter=300)
+    t1 = lib.tiled_feedback(d, p, (2, 2), 50, 0.1, 5e-3, 1000)
+    t2 = lib.tiled_feedback(d, p, (2, 2), 50, 0.1, 5e-3, 1000, **st)
+    assert np.array_equal(host(t1["idx"]), host(t2["idx"]))
+    assert np.array_equal(bits(host(t1["residual"])), bits(host(t2["residual"])))
