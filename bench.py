@@ -19,6 +19,7 @@ Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu] [--no-jy]
 from __future__ import annotations
 
 import argparse
+import itertools
 import json
 import os
 import sys
@@ -161,6 +162,10 @@ def main():
         return r, wall / args.steps * 1e3, float(np.mean(dev_ms))
 
     rt, ms_t, kms_t = timed(tiled, "tiled")
+    rf = P.tiled_feedback(dirty, psf, tiles, interval, gain, thr, n_iter, fft=True)
+    tiled_fft = {"kernel_ms": rf["stats"]["device_ms"], "n_rounds": rf["stats"]["n_rounds"],
+                 "phase_us": rf["stats"]["phase_us"],
+                 "note": "the same workload with the feedback sums computed by FFT convolution"}
     if args.no_plain:
         print(json.dumps({"tiled_kernel_ms": kms_t, "steps": args.steps}), flush=True)
         return
@@ -282,10 +287,10 @@ def main():
         big = {"workload": "4096x4096 image, 8192x8192 Y-array snapshot PSF, 2000 sources, 8x8 tiles, "
                            "200000 total minor iterations (residual streamed through HBM)", "runs": {}}
         for ivl in (50, 200, 1000):
-            for nm, pp, sp in (("f32", p2, 4), ("f16", p2h, 2)):
-                r = P.tiled_feedback(d2, pp, (8, 8), ivl, gain, 0.0, c2["max_iter"])
+            for (nm, pp, sp), fft in itertools.product((("f32", p2, 4), ("f16", p2h, 2)), (False, True)):
+                r = P.tiled_feedback(d2, pp, (8, 8), ivl, gain, 0.0, c2["max_iter"], fft=fft)
                 st = r["stats"]
-                big["runs"][f"I{ivl}_{nm}"] = {
+                big["runs"][f"I{ivl}_{nm}" + ("_fft" if fft else "")] = {
                     "kernel_ms": st["device_ms"], "iters_per_s": st["n_iter"] / (st["device_ms"] * 1e-3),
                     "n_iter": st["n_iter"], "stop": st["stop_reason"], "rounds": st["n_rounds"],
                     "phase_us": st["phase_us"], "wg_per_tile": st["wg_per_tile"]}
@@ -337,6 +342,7 @@ def main():
         "plain": {"iters_per_s": st_p["n_iter"] / (ms_p * 1e-3), "ms": ms_p, "kernel_ms": kms_p,
                   "achieved_GBs": gbs_p, "frac_hbm": gbs_p / HBM_PEAK_GBS,
                   "launch": {"wg_per_tile": st_p["wg_per_tile"], "px_per_thread": st_p["px_per_thread"]}},
+        "tiled_fft_feedback": tiled_fft,
         "speedup_tiled_vs_plain": ms_p / ms_t,
         "batched": batched,
         "tiled_4096": big,

@@ -80,8 +80,16 @@ typedef enum { CLEAN_PSF_F32 = 0, CLEAN_PSF_F16 = 1 } clean_psf_dtype;
 
 enum {
     CLEAN_FLAG_CHECK_FINITE = 1,   /* scan inputs for NaN/Inf before starting      */
-    CLEAN_FLAG_STREAM_RESIDUAL = 2 /* keep the residual in HBM even when it would
+    CLEAN_FLAG_STREAM_RESIDUAL = 2,/* keep the residual in HBM even when it would
                                       fit the register file (plain and tiled)     */
+    CLEAN_FLAG_FFT_FEEDBACK = 4    /* tiled: compute each round's cross-coupling
+                                      sum by one FFT convolution of the round's
+                                      component image (minus each tile's own part,
+                                      summed directly) instead of the direct
+                                      gather; images up to 4096 x 4096.  Not
+                                      bit-identical to the direct form: the FFT
+                                      rounds differently (float32, relative error
+                                      ~1e-6 of the component flux)               */
 };
 
 typedef struct {

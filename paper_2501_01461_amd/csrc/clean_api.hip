@@ -26,6 +26,11 @@ template <class Tile> __global__ void hogbom_kernel(const KArgs a);
 template <class Tile> __global__ void tiled_kernel(const KArgs a);
 template <class Tile> __global__ void batched_kernel(const BatchArgs b);
 __global__ void finalize_batch_kernel(const PlainJob *jobs, int n);
+template <typename PT>
+__global__ void fft_kernel_rows(const void *psf, int psf_nx, int cy, int cx, int ny, int nx, int lgx, int lgy,
+                                const float2 *tw_x, float2 *A);
+__global__ void fft_transpose_kernel(const float2 *src, int ss, float2 *dst, int ds, int rows, int cols);
+__global__ void fft_rows_kernel(float2 *X, int rows, int lg, const float2 *tw);
 __global__ void finite_check_kernel(const float *x, int64_t n, uint32_t *flag);
 __global__ void finite_check_half_kernel(const unsigned short *x, int64_t n, uint32_t *flag);
 __global__ void to_half_kernel(const float *x, unsigned short *y, int64_t n);
@@ -94,10 +99,19 @@ size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 // exchange slots, tile keys, counts) is cleared before each launch.
 struct Layout {
     size_t ctl, dstat, xslots, tile_key, rb_n, ag_n, header_end;
-    size_t role, rb_idx, rb_flux, ag_pos, ag_flux, accbuf, partial, total;
+    size_t role, rb_idx, rb_flux, ag_pos, ag_flux, accbuf, partial;
+    size_t fft_a, fft_b, fft_ks, tw_x, tw_y, total;
 };
 
-Layout make_layout(int T, int cs, int slot_pad, int interval, int W, int64_t npix, bool tiled)
+int ceil_log2(int64_t v)
+{
+    int lg = 0;
+    while (((int64_t)1 << lg) < v) ++lg;
+    return lg;
+}
+
+Layout make_layout(int T, int cs, int slot_pad, int interval, int W, int64_t npix, bool tiled, int ny = 0,
+                   int lgx = 0, int lgy = 0)
 {
     Layout L{};
     size_t o = 0;
@@ -116,6 +130,12 @@ Layout make_layout(int T, int cs, int slot_pad, int interval, int W, int64_t npi
     L.ag_flux = o;   o = align_up(o + list, 256);
     L.accbuf = o;    o = align_up(o + (tiled ? (size_t)npix * 4 : 0), 256);
     L.partial = o;   o = align_up(o + (size_t)T * cs * 8, 256);
+    const size_t Lx = lgx ? (size_t)1 << lgx : 0, Ly = lgy ? (size_t)1 << lgy : 0;
+    L.fft_a = o;     o = align_up(o + Ly * Lx * 8, 256);
+    L.fft_b = o;     o = align_up(o + Lx * (size_t)ny * 8, 256);
+    L.fft_ks = o;    o = align_up(o + Lx * Ly * 8, 256);
+    L.tw_x = o;      o = align_up(o + Lx / 2 * 8, 256);
+    L.tw_y = o;      o = align_up(o + Ly / 2 * 8, 256);
     L.total = o;
     return L;
 }
@@ -320,6 +340,14 @@ int run(bool tiled, const float *dirty, int ny, int nx, const void *psf, int psf
         tiles_y = tiles_x = 1;
         interval = 1;
     }
+    const bool fft = tiled && (p->flags & CLEAN_FLAG_FFT_FEEDBACK);
+    int lgx = 0, lgy = 0;
+    if (fft) {
+        lgx = std::max(1, ceil_log2(2 * (int64_t)nx - 1));
+        lgy = std::max(1, ceil_log2(2 * (int64_t)ny - 1));
+        if (lgx > 13 || lgy > 13)
+            return fail(CLEAN_E_UNSUPPORTED, "FFT feedback supports images up to 4096 x 4096 (transforms of 8192)");
+    }
     hipStream_t stream = (hipStream_t)stream_v;
     int dev = 0;
     HIPCHK(hipGetDevice(&dev));
@@ -339,7 +367,8 @@ int run(bool tiled, const float *dirty, int ny, int nx, const void *psf, int psf
         }
     const int V = w4 ? 4 : 1;
     const bool half = p->psf_dtype == CLEAN_PSF_F16;
-    const size_t dyn_lds = tiled ? std::max((size_t)16 * interval, (size_t)8 * GATHER_CHUNK) : 0;
+    size_t dyn_lds = tiled ? std::max((size_t)16 * interval, (size_t)8 * GATHER_CHUNK) : 0;
+    if (fft) dyn_lds = std::max(dyn_lds, (size_t)8 << std::max(lgx, lgy));
 
     // placement: cluster c lives on XCD c % 8 (workgroup b runs on XCD b % 8);
     // tiled launches add helper workgroups for the feedback gather
@@ -386,6 +415,8 @@ int run(bool tiled, const float *dirty, int ny, int nx, const void *psf, int psf
     if (st == CLEAN_OK) {
         fn = pick(tiled, half, V, ppt / V);
         if (!fn) return fail(CLEAN_E_UNSUPPORTED, "no kernel for %d pixels per thread", ppt);
+        if (dyn_lds > 48 * 1024)
+            HIPCHK(hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn_lds));
         int occ = 0;
         HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void *)fn, WG, dyn_lds));
         if (!place(cs, occ * ncu, W, role)) {
@@ -401,6 +432,8 @@ int run(bool tiled, const float *dirty, int ny, int nx, const void *psf, int psf
     if (streamed) {
         g_last_error.clear();
         fn = pick_stream(tiled, half, V);
+        if (dyn_lds > 48 * 1024)
+            HIPCHK(hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn_lds));
         int occ = 0;
         HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void *)fn, WG, dyn_lds));
         const int max_wg = occ * ncu;
@@ -415,7 +448,7 @@ int run(bool tiled, const float *dirty, int ny, int nx, const void *psf, int psf
 
     const int slot_pad = (cs + 31) / 32 * 32;
     const int64_t npix = (int64_t)ny * nx;
-    const Layout L = make_layout(T, cs, slot_pad, interval, W, npix, tiled);
+    const Layout L = make_layout(T, cs, slot_pad, interval, W, npix, tiled, ny, lgx, lgy);
     char *ws = (char *)workspace;
     if (ws) {
         if (workspace_bytes < L.total)
@@ -462,6 +495,13 @@ int run(bool tiled, const float *dirty, int ny, int nx, const void *psf, int psf
     a.ag_n = (int32_t *)(ws + L.ag_n);
     a.accbuf = (float *)(ws + L.accbuf);
     a.partial = (double *)(ws + L.partial);
+    a.fft_lgx = lgx;
+    a.fft_lgy = lgy;
+    a.fft_a = (float2 *)(ws + L.fft_a);
+    a.fft_b = (float2 *)(ws + L.fft_b);
+    a.fft_ks = (const float2 *)(ws + L.fft_ks);
+    a.tw_x = (const float2 *)(ws + L.tw_x);
+    a.tw_y = (const float2 *)(ws + L.tw_y);
 
     HIPCHK(hipMemsetAsync(ws, 0, L.header_end, stream));
     HIPCHK(hipMemcpyAsync(ws + L.role, role.data(), role.size() * 4, hipMemcpyHostToDevice, stream));
@@ -479,6 +519,38 @@ int run(bool tiled, const float *dirty, int ny, int nx, const void *psf, int psf
         HIPCHK(hipMemcpyAsync(&bad, flag, 4, hipMemcpyDeviceToHost, stream));
         HIPCHK(hipStreamSynchronize(stream));
         if (bad) return fail(CLEAN_E_NONFINITE, "non-finite value in the dirty image or PSF");
+    }
+
+    std::vector<float2> twx, twy;
+    if (fft) {
+        // twiddles in double, rounded once; then the PSF kernel's spectrum
+        for (int pass = 0; pass < 2; ++pass) {
+            const int lg = pass ? lgy : lgx;
+            std::vector<float2> &tw = pass ? twy : twx;
+            const int Lh = 1 << (lg - 1);
+            tw.resize(Lh);
+            for (int m = 0; m < Lh; ++m) {
+                const double ang = -2.0 * M_PI * (double)m / (double)(2 * Lh);
+                tw[m] = make_float2((float)std::cos(ang), (float)std::sin(ang));
+            }
+        }
+        HIPCHK(hipMemcpyAsync(ws + L.tw_x, twx.data(), twx.size() * 8, hipMemcpyHostToDevice, stream));
+        HIPCHK(hipMemcpyAsync(ws + L.tw_y, twy.data(), twy.size() * 8, hipMemcpyHostToDevice, stream));
+        const int Lx = 1 << lgx, Ly = 1 << lgy;
+        const void *krows = half ? (const void *)fft_kernel_rows<__half> : (const void *)fft_kernel_rows<float>;
+        HIPCHK(hipFuncSetAttribute(krows, hipFuncAttributeMaxDynamicSharedMemorySize, 8 * Lx));
+        HIPCHK(hipFuncSetAttribute((const void *)fft_rows_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, 8 * Ly));
+        if (half)
+            hipLaunchKernelGGL(fft_kernel_rows<__half>, dim3(std::min(Ly, 2048)), dim3(WG), 8 * Lx, stream, psf, psf_nx,
+                               a.cy, a.cx, ny, nx, lgx, lgy, a.tw_x, a.fft_a);
+        else
+            hipLaunchKernelGGL(fft_kernel_rows<float>, dim3(std::min(Ly, 2048)), dim3(WG), 8 * Lx, stream, psf, psf_nx,
+                               a.cy, a.cx, ny, nx, lgx, lgy, a.tw_x, a.fft_a);
+        hipLaunchKernelGGL(fft_transpose_kernel, dim3(2048), dim3(WG), 0, stream, (const float2 *)a.fft_a, Lx,
+                           (float2 *)a.fft_ks, Ly, Ly, Lx);
+        hipLaunchKernelGGL(fft_rows_kernel, dim3(std::min(Lx, 2048)), dim3(WG), 8 * Ly, stream, (float2 *)a.fft_ks, Lx,
+                           lgy, a.tw_y);
+        HIPCHK(hipGetLastError());
     }
 
     hipEvent_t e0, e1;
@@ -727,8 +799,14 @@ size_t clean_workspace_size(int ny, int nx, int tiles_y, int tiles_x, int feedba
     const int64_t npix = (int64_t)ny * nx;
     const int cs_max = 4096;
     const int W_max = 8192;
+    int lgx = 0, lgy = 0;
+    if (tiled && (p->flags & CLEAN_FLAG_FFT_FEEDBACK)) {
+        lgx = std::max(1, ceil_log2(2 * (int64_t)nx - 1));
+        lgy = std::max(1, ceil_log2(2 * (int64_t)ny - 1));
+        if (lgx > 13 || lgy > 13) return 0;
+    }
     const Layout L = make_layout(T, tiled ? cs_max / T + 64 : cs_max, (cs_max + 31) / 32 * 32,
-                                 tiled ? feedback_interval : 1, W_max, npix, tiled);
+                                 tiled ? feedback_interval : 1, W_max, npix, tiled, ny, lgx, lgy);
     return L.total;
 }
 

@@ -101,6 +101,13 @@ struct KArgs {
     float *ag_flux;
     int32_t *ag_n;          // [T]
     float *accbuf;          // [ny*nx] feedback sums
+    // FFT form of the feedback (fft_lgx = 0: direct gather)
+    int fft_lgx, fft_lgy;   // log2 of the transform sizes Lx, Ly
+    float2 *fft_a;          // [Ly][Lx] row transforms of the component image
+    float2 *fft_b;          // [Lx][ny] after the column pass
+    const float2 *fft_ks;   // [Lx][Ly] spectrum of the PSF kernel, transposed
+    const float2 *tw_x;     // [Lx/2] twiddles exp(-2 pi i m / Lx)
+    const float2 *tw_y;     // [Ly/2]
     double *partial;        // [T*cs] per-workgroup sum of squared residuals
 };
 

@@ -1,0 +1,98 @@
+// clean_fft.h -- the FFT form of the feedback step: the cross-coupling images
+// (each tile's component image convolved with the full PSF, paper Section 3)
+// computed as one circular convolution per round, for large images where the
+// direct gather would read K_d * N^2 PSF values.
+//
+// Sizes: Lx, Ly are powers of two with Lx >= 2*nx - 1, Ly >= 2*ny - 1, so the
+// circular convolution of the component image (support [0,ny) x [0,nx)) with
+// the kernel K(d) = psf[centre + d], |d| < (ny, nx), has no wrap-around on the
+// output window [0,ny) x [0,nx).  K's spectrum is computed once per call.
+//
+// One length-L transform runs in one workgroup, in LDS (L <= 8192 complex
+// floats = 64 KB): iterative radix-2 decimation in time, input placed in
+// bit-reversed order, twiddles W_L^m = exp(-2 pi i m / L) from a float table
+// computed in double on the host.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace cleanhip {
+
+constexpr int FFT_MAX_LG = 13;          // length 8192
+
+// Agent-coherent 8-byte accesses: the FFT buffers are written by one
+// workgroup and read by others within one launch.
+__device__ __forceinline__ float2 ldc2(const float2 *p)
+{
+    const uint64_t u = __hip_atomic_load((const uint64_t *)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return make_float2(__uint_as_float((uint32_t)u), __uint_as_float((uint32_t)(u >> 32)));
+}
+__device__ __forceinline__ void stc2(float2 *p, float2 v)
+{
+    const uint64_t u = (uint64_t)__float_as_uint(v.x) | ((uint64_t)__float_as_uint(v.y) << 32);
+    __hip_atomic_store((uint64_t *)p, u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ uint32_t bitrev(uint32_t i, int lg) { return __builtin_bitreverse32(i) >> (32 - lg); }
+
+// In-place FFT of a[0 .. 2^lg) (bit-reversed input, natural-order output).
+// inverse: conjugate twiddles (no 1/L scaling).  All threads of the workgroup.
+__device__ inline void fft_lds(float2 *a, int lg, const float2 *tw, bool inverse)
+{
+    const int H = 1 << (lg - 1);
+    __syncthreads();
+    for (int s = 0; s < lg; ++s) {
+        const int half = 1 << s;
+        for (int j = threadIdx.x; j < H; j += blockDim.x) {
+            const int k = j & (half - 1);
+            const int i0 = ((j >> s) << (s + 1)) + k, i1 = i0 + half;
+            float2 w = tw[k << (lg - 1 - s)];
+            if (inverse) w.y = -w.y;
+            const float2 u = a[i0], v = a[i1];
+            const float2 t = make_float2(v.x * w.x - v.y * w.y, v.x * w.y + v.y * w.x);
+            a[i0] = make_float2(u.x + t.x, u.y + t.y);
+            a[i1] = make_float2(u.x - t.x, u.y - t.y);
+        }
+        __syncthreads();
+    }
+}
+
+// Puts a natural-order array into bit-reversed order, in place.
+__device__ inline void bitrev_permute(float2 *a, int lg)
+{
+    __syncthreads();
+    const int L = 1 << lg;
+    for (int i = threadIdx.x; i < L; i += blockDim.x) {
+        const int j = (int)bitrev((uint32_t)i, lg);
+        if (i < j) {
+            const float2 t = a[i];
+            a[i] = a[j];
+            a[j] = t;
+        }
+    }
+    __syncthreads();
+}
+
+// 32 x 32 tiled transpose of the rows [0, rows) x columns [0, cols) of `src`
+// (row stride ss) into dst (row stride ds): dst[c][r] = src[r][c].  Tiles are
+// dealt over the workgroups (work item w of nwork).
+__device__ inline void transpose_tiles(const float2 *src, int ss, float2 *dst, int ds, int rows, int cols, int w0,
+                                       int nwork, float2 (*lds)[33])
+{
+    const int tr = (rows + 31) / 32, tc = (cols + 31) / 32;
+    for (int t = w0; t < tr * tc; t += nwork) {
+        const int br = (t / tc) * 32, bc = (t % tc) * 32;
+        __syncthreads();
+        for (int e = threadIdx.x; e < 1024; e += blockDim.x) {
+            const int r = e / 32, c = e % 32;
+            if (br + r < rows && bc + c < cols) lds[r][c] = ldc2(&src[(size_t)(br + r) * ss + bc + c]);
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < 1024; e += blockDim.x) {
+            const int c = e / 32, r = e % 32;
+            if (br + r < rows && bc + c < cols) stc2(&dst[(size_t)(bc + c) * ds + br + r], lds[r][c]);
+        }
+    }
+}
+
+} // namespace cleanhip

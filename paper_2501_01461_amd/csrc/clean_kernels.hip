@@ -29,6 +29,7 @@
 #include <stdint.h>
 
 #include "clean_device.h"
+#include "clean_fft.h"
 
 namespace cleanhip {
 
@@ -664,6 +665,173 @@ template <class Tile> __global__ void __launch_bounds__(WG) batched_kernel(const
     }
 }
 
+
+// ----------------------------------------------------- FFT feedback -----
+
+__device__ __forceinline__ int tile_row_of(const KArgs &a, int y)
+{
+    int i = (int)((int64_t)y * a.ty / a.ny);
+    while (i + 1 < a.ty && (int)((int64_t)(i + 1) * a.ny / a.ty) <= y) ++i;
+    while (i > 0 && (int)((int64_t)i * a.ny / a.ty) > y) --i;
+    return i;
+}
+
+__device__ __forceinline__ int tile_col_of(const KArgs &a, int x)
+{
+    int j = (int)((int64_t)x * a.tx / a.nx);
+    while (j + 1 < a.tx && (int)((int64_t)(j + 1) * a.nx / a.tx) <= x) ++j;
+    while (j > 0 && (int)((int64_t)j * a.nx / a.tx) > x) --j;
+    return j;
+}
+
+// First index k in [lo, hi) of tile t's aggregated list with position >= key.
+__device__ __forceinline__ int lower_pos(const KArgs &a, int t, int lo, int hi, int32_t key)
+{
+    const size_t base = (size_t)t * a.interval;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (ldc(&a.ag_pos[base + mid]) < key) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+// The round's feedback through one circular convolution.  Phases, each ended
+// by a grid barrier: (1) row transforms of the component image, built per row
+// from the aggregated lists; (2) transpose; (3) per column: transform, times
+// the PSF kernel's spectrum, inverse transform; (4) transpose; (5) inverse row
+// transforms, minus each tile's own part (a direct sum over its own
+// components), into the feedback buffer.
+template <typename PT>
+__device__ bool fft_feedback(const KArgs &a, const Sync &y, uint32_t &epoch, int *s_ok, const int32_t *s_off)
+{
+    extern __shared__ __align__(16) unsigned char s_dyn[];
+    __shared__ float2 s_tr[32][33];
+    float2 *lds = (float2 *)s_dyn;
+    const int lgx = a.fft_lgx, lgy = a.fft_lgy;
+    const int Lx = 1 << lgx, Ly = 1 << lgy;
+    const int ny = a.ny, nx = a.nx;
+
+    // (1) rows of the component image
+    for (int row = blockIdx.x; row < ny; row += gridDim.x) {
+        for (int x = threadIdx.x; x < Lx; x += WG) lds[x] = make_float2(0.f, 0.f);
+        __syncthreads();
+        const int ti = tile_row_of(a, row);
+        for (int j = threadIdx.x; j < a.tx; j += WG) {
+            const int t = ti * a.tx + j;
+            const int n = s_off[t + 1] - s_off[t];
+            const int32_t r0 = row * nx;
+            const int lo = lower_pos(a, t, 0, n, r0), hi = lower_pos(a, t, lo, n, r0 + nx);
+            for (int q = lo; q < hi; ++q) {
+                const size_t e = (size_t)t * a.interval + q;
+                lds[bitrev((uint32_t)(ldc(&a.ag_pos[e]) - r0), lgx)] = make_float2(ldc(&a.ag_flux[e]), 0.f);
+            }
+        }
+        fft_lds(lds, lgx, a.tw_x, false);
+        for (int x = threadIdx.x; x < Lx; x += WG) stc2(&a.fft_a[(size_t)row * Lx + x], lds[x]);
+        __syncthreads();
+    }
+    if (!grid_barrier(y, epoch, s_ok)) return false;
+    // (2) A[y][x] -> B[x][y], y < ny
+    transpose_tiles(a.fft_a, Lx, a.fft_b, ny, ny, Lx, blockIdx.x, gridDim.x, s_tr);
+    if (!grid_barrier(y, epoch, s_ok)) return false;
+    // (3) columns: forward transform over y, times K's spectrum, inverse transform
+    for (int col = blockIdx.x; col < Lx; col += gridDim.x) {
+        for (int v = threadIdx.x; v < Ly; v += WG) lds[v] = make_float2(0.f, 0.f);
+        __syncthreads();
+        for (int v = threadIdx.x; v < ny; v += WG) lds[bitrev((uint32_t)v, lgy)] = ldc2(&a.fft_b[(size_t)col * ny + v]);
+        fft_lds(lds, lgy, a.tw_y, false);
+        for (int v = threadIdx.x; v < Ly; v += WG) {
+            const float2 p = lds[v], q = a.fft_ks[(size_t)col * Ly + v];
+            lds[v] = make_float2(p.x * q.x - p.y * q.y, p.x * q.y + p.y * q.x);
+        }
+        bitrev_permute(lds, lgy);
+        fft_lds(lds, lgy, a.tw_y, true);
+        for (int v = threadIdx.x; v < ny; v += WG) stc2(&a.fft_b[(size_t)col * ny + v], lds[v]);
+        __syncthreads();
+    }
+    if (!grid_barrier(y, epoch, s_ok)) return false;
+    // (4) B[x][y] -> A[y][x]
+    transpose_tiles(a.fft_b, ny, a.fft_a, Lx, Lx, ny, blockIdx.x, gridDim.x, s_tr);
+    if (!grid_barrier(y, epoch, s_ok)) return false;
+    // (5) inverse row transforms; subtract each tile's own cross-coupling
+    const float scale = 1.0f / ((float)Lx * (float)Ly);
+    const __amdgpu_buffer_rsrc_t rs = make_rsrc(a.psf, a.psf_bytes);
+    for (int row = blockIdx.x; row < ny; row += gridDim.x) {
+        for (int x = threadIdx.x; x < Lx; x += WG) lds[bitrev((uint32_t)x, lgx)] = ldc2(&a.fft_a[(size_t)row * Lx + x]);
+        fft_lds(lds, lgx, a.tw_x, true);
+        const int ti = tile_row_of(a, row);
+        for (int x = threadIdx.x; x < nx; x += WG) {
+            const float X = lds[x].x * scale;
+            const int t = ti * a.tx + tile_col_of(a, x);
+            const int n = s_off[t + 1] - s_off[t];
+            float own = 0.0f;
+            for (int q = 0; q < n; ++q) {
+                const size_t e = (size_t)t * a.interval + q;
+                const int32_t pos = ldc(&a.ag_pos[e]);
+                const int py = pos / nx, px = pos % nx;
+                const uint32_t off = (uint32_t)((row - py + a.cy) * a.psf_nx + (x - px + a.cx));
+                float pv[1];
+                PsfLoad<PT, 1>::load(rs, off * (uint32_t)sizeof(PT), pv);
+                own = __builtin_fmaf(ldc(&a.ag_flux[e]), pv[0], own);
+            }
+            stc(&a.accbuf[(size_t)row * nx + x], X - own);
+        }
+        __syncthreads();
+    }
+    return true;
+}
+
+// ------------------------------------------ PSF kernel spectrum (once) --
+
+// Rows of K(d) = psf[centre + d] for |d| < (ny, nx), placed circularly on the
+// Ly x Lx grid, transformed along x into A.
+template <typename PT>
+__global__ void __launch_bounds__(WG) fft_kernel_rows(const void *psf, int psf_nx, int cy, int cx, int ny, int nx,
+                                                      int lgx, int lgy, const float2 *tw_x, float2 *A)
+{
+    extern __shared__ __align__(16) unsigned char s_dyn[];
+    float2 *lds = (float2 *)s_dyn;
+    const int Lx = 1 << lgx, Ly = 1 << lgy;
+    const PT *p = (const PT *)psf;
+    for (int row = blockIdx.x; row < Ly; row += gridDim.x) {
+        const int dy = row < ny ? row : row - Ly;
+        const bool vy = dy > -ny && dy < ny;
+        for (int x = threadIdx.x; x < Lx; x += WG) {
+            const int dx = x < nx ? x : x - Lx;
+            float v = 0.0f;
+            if (vy && dx > -nx && dx < nx) v = (float)p[(int64_t)(cy + dy) * psf_nx + (cx + dx)];
+            lds[bitrev((uint32_t)x, lgx)] = make_float2(v, 0.f);
+        }
+        fft_lds(lds, lgx, tw_x, false);
+        for (int x = threadIdx.x; x < Lx; x += WG) A[(size_t)row * Lx + x] = lds[x];
+        __syncthreads();
+    }
+}
+
+__global__ void __launch_bounds__(WG) fft_transpose_kernel(const float2 *src, int ss, float2 *dst, int ds, int rows,
+                                                           int cols)
+{
+    __shared__ float2 s_tr[32][33];
+    transpose_tiles(src, ss, dst, ds, rows, cols, blockIdx.x, gridDim.x, s_tr);
+}
+
+// In-place forward transforms of `rows` rows of length 2^lg.
+__global__ void __launch_bounds__(WG) fft_rows_kernel(float2 *X, int rows, int lg, const float2 *tw)
+{
+    extern __shared__ __align__(16) unsigned char s_dyn[];
+    float2 *lds = (float2 *)s_dyn;
+    const int L = 1 << lg;
+    for (int row = blockIdx.x; row < rows; row += gridDim.x) {
+        for (int v = threadIdx.x; v < L; v += WG) lds[bitrev((uint32_t)v, lg)] = X[(size_t)row * L + v];
+        fft_lds(lds, lg, tw, false);
+        for (int v = threadIdx.x; v < L; v += WG) X[(size_t)row * L + v] = lds[v];
+        __syncthreads();
+    }
+}
+
+template __global__ void fft_kernel_rows<float>(const void *, int, int, int, int, int, int, int, const float2 *, float2 *);
+template __global__ void fft_kernel_rows<__half>(const void *, int, int, int, int, int, int, int, const float2 *, float2 *);
+
 // ------------------------------------------------------ tiled kernel -----
 
 // Aggregate the leader's round list (LDS) by position: distinct positions in
@@ -875,6 +1043,10 @@ template <class Tile> __global__ void __launch_bounds__(WG) tiled_kernel(const K
         }
         __syncthreads();
 
+        // ---- feedback by FFT: acc = (component image (*) K) - own tile's part
+        if (a.fft_lgx) {
+            if (!fft_feedback<PT>(a, y, epoch, &s_ok, s_off)) return;
+        } else
         // ---- feedback gather: acc[q] = sum over other tiles' components
         {
             // items are (tile, row band) in tile-major order; each XCD takes a
