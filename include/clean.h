@@ -82,14 +82,18 @@ enum {
     CLEAN_FLAG_CHECK_FINITE = 1,   /* scan inputs for NaN/Inf before starting      */
     CLEAN_FLAG_STREAM_RESIDUAL = 2,/* keep the residual in HBM even when it would
                                       fit the register file (plain and tiled)     */
-    CLEAN_FLAG_FFT_FEEDBACK = 4    /* tiled: compute each round's cross-coupling
-                                      sum by one FFT convolution of the round's
-                                      component image (minus each tile's own part,
-                                      summed directly) instead of the direct
-                                      gather; images up to 4096 x 4096.  Not
-                                      bit-identical to the direct form: the FFT
-                                      rounds differently (float32, relative error
-                                      ~1e-6 of the component flux)               */
+    CLEAN_FLAG_FFT_FEEDBACK = 4    /* tiled: after each round, compute the
+                                      residual as the round's starting residual
+                                      minus one FFT convolution of all the
+                                      round's components with the PSF (the same
+                                      update as the direct gather, own tile
+                                      included); images up to 4096 x 4096.  Not
+                                      bit-identical to the direct form: float32
+                                      transforms, relative error ~1e-6 of the
+                                      convolution's scale per round.  Adds
+                                      (2 Ly Lx + Lx ny) * 8 + ny nx * 4 bytes of
+                                      workspace, Lx, Ly the powers of two
+                                      >= 2 nx - 1, 2 ny - 1                   */
 };
 
 typedef struct {

@@ -100,7 +100,7 @@ size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 struct Layout {
     size_t ctl, dstat, xslots, tile_key, rb_n, ag_n, header_end;
     size_t role, rb_idx, rb_flux, ag_pos, ag_flux, accbuf, partial;
-    size_t fft_a, fft_b, fft_ks, tw_x, tw_y, total;
+    size_t fft_a, fft_b, fft_ks, tw_x, tw_y, rstart, total;
 };
 
 int ceil_log2(int64_t v)
@@ -136,6 +136,7 @@ Layout make_layout(int T, int cs, int slot_pad, int interval, int W, int64_t npi
     L.fft_ks = o;    o = align_up(o + Lx * Ly * 8, 256);
     L.tw_x = o;      o = align_up(o + Lx / 2 * 8, 256);
     L.tw_y = o;      o = align_up(o + Ly / 2 * 8, 256);
+    L.rstart = o;    o = align_up(o + (lgx ? (size_t)npix * 4 : 0), 256);
     L.total = o;
     return L;
 }
@@ -502,6 +503,7 @@ int run(bool tiled, const float *dirty, int ny, int nx, const void *psf, int psf
     a.fft_ks = (const float2 *)(ws + L.fft_ks);
     a.tw_x = (const float2 *)(ws + L.tw_x);
     a.tw_y = (const float2 *)(ws + L.tw_y);
+    a.rstart = fft ? (float *)(ws + L.rstart) : nullptr;
 
     HIPCHK(hipMemsetAsync(ws, 0, L.header_end, stream));
     HIPCHK(hipMemcpyAsync(ws + L.role, role.data(), role.size() * 4, hipMemcpyHostToDevice, stream));
@@ -534,6 +536,7 @@ int run(bool tiled, const float *dirty, int ny, int nx, const void *psf, int psf
                 tw[m] = make_float2((float)std::cos(ang), (float)std::sin(ang));
             }
         }
+        HIPCHK(hipMemcpyAsync(ws + L.rstart, dirty, (size_t)npix * 4, hipMemcpyDeviceToDevice, stream));
         HIPCHK(hipMemcpyAsync(ws + L.tw_x, twx.data(), twx.size() * 8, hipMemcpyHostToDevice, stream));
         HIPCHK(hipMemcpyAsync(ws + L.tw_y, twy.data(), twy.size() * 8, hipMemcpyHostToDevice, stream));
         const int Lx = 1 << lgx, Ly = 1 << lgy;

@@ -108,6 +108,7 @@ struct KArgs {
     const float2 *fft_ks;   // [Lx][Ly] spectrum of the PSF kernel, transposed
     const float2 *tw_x;     // [Lx/2] twiddles exp(-2 pi i m / Lx)
     const float2 *tw_y;     // [Ly/2]
+    float *rstart;          // [ny*nx] residual at the round's start (FFT form), else null
     double *partial;        // [T*cs] per-workgroup sum of squared residuals
 };
 

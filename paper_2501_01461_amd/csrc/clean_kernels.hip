@@ -268,6 +268,7 @@ struct Img {
     float *residual;
     double *model;          // may be null
     float *accbuf;          // tiled feedback sums (image layout), else null
+    float *rstart;          // FFT feedback: residual at the round's start, else null
     const void *psf;
     uint64_t psf_bytes;
     int nx, psf_nx, cy, cx;
@@ -378,7 +379,9 @@ template <int K, int V, typename PT> struct RegTile {
         return want_key ? key(a) : 0;
     }
 
-    // r -= acc (float32 feedback sums, image layout); returns the new key.
+    // r -= acc (float32 feedback sums, image layout); with rstart (FFT form,
+    // acc holds every tile's contribution): r = rstart - acc, and rstart = r.
+    // Returns the new key.  Only the owning thread touches rstart.
     __device__ __forceinline__ uint64_t apply_feedback(const Img &a)
     {
 #pragma unroll
@@ -387,8 +390,16 @@ template <int K, int V, typename PT> struct RegTile {
                 const uint32_t f = group_f(k);
                 const int y = (int)(f / (uint32_t)w), x = (int)(f % (uint32_t)w);
                 const int64_t img = (int64_t)(y0 + y) * a.nx + (x0 + x);
+                if (a.rstart) {
 #pragma unroll
-                for (int e = 0; e < V; ++e) r[k][e] = r[k][e] - ldc(&a.accbuf[img + e]);
+                    for (int e = 0; e < V; ++e) {
+                        r[k][e] = a.rstart[img + e] - ldc(&a.accbuf[img + e]);
+                        a.rstart[img + e] = r[k][e];
+                    }
+                } else {
+#pragma unroll
+                    for (int e = 0; e < V; ++e) r[k][e] = r[k][e] - ldc(&a.accbuf[img + e]);
+                }
             }
         }
         return key(a);
@@ -537,8 +548,9 @@ template <int K, int V, typename PT> struct StreamTile {
                 const int64_t img = img_of(a, f);
 #pragma unroll
                 for (int e = 0; e < V; ++e) {
-                    const float r = a.residual[img + e] - ldc(&a.accbuf[img + e]);
+                    const float r = (a.rstart ? a.rstart[img + e] : a.residual[img + e]) - ldc(&a.accbuf[img + e]);
                     a.residual[img + e] = r;
+                    if (a.rstart) a.rstart[img + e] = r;
                     take(__float_as_uint(r), f + e, bb, bf, any);
                 }
             }
@@ -576,7 +588,7 @@ template <class Tile> __device__ void store_and_sum(const Tile &R, const Img &im
 // workgroup is cluster rank `rank`.  Returns false if the run was aborted.
 template <class Tile> __device__ bool run_plain(const PlainJob &j, int rank, const Sync &y)
 {
-    const Img im{j.dirty, j.residual, j.model, nullptr, j.psf, j.psf_bytes, j.nx, j.psf_nx, j.cy, j.cx};
+    const Img im{j.dirty, j.residual, j.model, nullptr, nullptr, j.psf, j.psf_bytes, j.nx, j.psf_nx, j.cy, j.cx};
     Tile T;
     T.init(im, 0, 0, j.ny, j.nx, j.cs, rank);
     if (!Tile::kResident) __syncthreads();
@@ -695,47 +707,76 @@ __device__ __forceinline__ int lower_pos(const KArgs &a, int t, int lo, int hi, 
     return lo;
 }
 
-// The round's feedback through one circular convolution.  Phases, each ended
-// by a grid barrier: (1) row transforms of the component image, built per row
-// from the aggregated lists; (2) transpose; (3) per column: transform, times
-// the PSF kernel's spectrum, inverse transform; (4) transpose; (5) inverse row
-// transforms, minus each tile's own part (a direct sum over its own
-// components), into the feedback buffer.
-template <typename PT>
+// The round's feedback through one circular convolution of the round's
+// component image (every tile's components) with the PSF.  The image is real,
+// so rows go two at a time through one complex transform (row 2m as the real
+// part, row 2m+1 as the imaginary part) and only the Lx/2 + 1 non-redundant
+// columns of the row spectra are carried on.  Phases, each ended by a grid
+// barrier: (1) row-pair transforms of the component image, built from the
+// aggregated lists, split into the two rows' half spectra; (2) transpose;
+// (3) per column: transform, times the PSF kernel's spectrum, inverse
+// transform; (4) transpose; (5) row-pair inverse transforms from the two
+// rows' half spectra (Hermitian symmetry gives the rest) into the feedback
+// buffer.  The buffer then holds every tile's contribution, own tile
+// included, so the apply step recomputes the residual from the round's
+// starting residual: mathematically the paper's update (own components
+// subtracted locally, the others' by feedback), rounded once.
 __device__ bool fft_feedback(const KArgs &a, const Sync &y, uint32_t &epoch, int *s_ok, const int32_t *s_off)
 {
     extern __shared__ __align__(16) unsigned char s_dyn[];
     __shared__ float2 s_tr[32][33];
+    __shared__ int s_nz;
     float2 *lds = (float2 *)s_dyn;
     const int lgx = a.fft_lgx, lgy = a.fft_lgy;
-    const int Lx = 1 << lgx, Ly = 1 << lgy;
-    const int ny = a.ny, nx = a.nx;
+    const int Lx = 1 << lgx, Ly = 1 << lgy, Hx = Lx / 2 + 1;
+    const int ny = a.ny, nx = a.nx, tx = a.tx;
+    const int npairs = (ny + 1) / 2;
 
-    // (1) rows of the component image
-    for (int row = blockIdx.x; row < ny; row += gridDim.x) {
+    // (1) row pairs of the component image -> half spectra, rows of stride Hx
+    for (int pr = blockIdx.x; pr < npairs; pr += gridDim.x) {
+        const int r0 = 2 * pr;
+        const bool has1 = r0 + 1 < ny;
         for (int x = threadIdx.x; x < Lx; x += WG) lds[x] = make_float2(0.f, 0.f);
+        if (threadIdx.x == 0) s_nz = 0;
         __syncthreads();
-        const int ti = tile_row_of(a, row);
-        for (int j = threadIdx.x; j < a.tx; j += WG) {
-            const int t = ti * a.tx + j;
+        for (int j = threadIdx.x; j < 2 * tx; j += WG) {
+            const int row = r0 + (j >= tx);
+            if (row >= ny) continue;
+            const int t = tile_row_of(a, row) * tx + (j % tx);
             const int n = s_off[t + 1] - s_off[t];
-            const int32_t r0 = row * nx;
-            const int lo = lower_pos(a, t, 0, n, r0), hi = lower_pos(a, t, lo, n, r0 + nx);
+            const int32_t b0 = row * nx;
+            const int lo = lower_pos(a, t, 0, n, b0), hi = lower_pos(a, t, lo, n, b0 + nx);
+            if (hi > lo) atomicAdd(&s_nz, hi - lo);
             for (int q = lo; q < hi; ++q) {
                 const size_t e = (size_t)t * a.interval + q;
-                lds[bitrev((uint32_t)(ldc(&a.ag_pos[e]) - r0), lgx)] = make_float2(ldc(&a.ag_flux[e]), 0.f);
+                float *dst = (float *)&lds[bitrev((uint32_t)(ldc(&a.ag_pos[e]) - b0), lgx)];
+                dst[j >= tx] = ldc(&a.ag_flux[e]);
             }
         }
-        fft_lds(lds, lgx, a.tw_x, false);
-        for (int x = threadIdx.x; x < Lx; x += WG) stc2(&a.fft_a[(size_t)row * Lx + x], lds[x]);
+        __syncthreads();
+        float2 *o0 = a.fft_a + (size_t)r0 * Hx, *o1 = o0 + Hx;
+        if (s_nz == 0) {                        // both rows empty: zero spectra
+            for (int k = threadIdx.x; k < Hx; k += WG) {
+                stc2(&o0[k], make_float2(0.f, 0.f));
+                if (has1) stc2(&o1[k], make_float2(0.f, 0.f));
+            }
+        } else {
+            fft_lds(lds, lgx, a.tw_x, false);
+            for (int k = threadIdx.x; k < Hx; k += WG) {
+                const float2 zk = lds[k], zm = lds[(Lx - k) & (Lx - 1)];
+                // A = (Z[k] + conj Z[-k]) / 2,  B = (Z[k] - conj Z[-k]) / 2i
+                stc2(&o0[k], make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y)));
+                if (has1) stc2(&o1[k], make_float2(0.5f * (zk.y + zm.y), -0.5f * (zk.x - zm.x)));
+            }
+        }
         __syncthreads();
     }
     if (!grid_barrier(y, epoch, s_ok)) return false;
-    // (2) A[y][x] -> B[x][y], y < ny
-    transpose_tiles(a.fft_a, Lx, a.fft_b, ny, ny, Lx, blockIdx.x, gridDim.x, s_tr);
+    // (2) A[y][kx] -> B[kx][y]
+    transpose_tiles(a.fft_a, Hx, a.fft_b, ny, ny, Hx, blockIdx.x, gridDim.x, s_tr);
     if (!grid_barrier(y, epoch, s_ok)) return false;
     // (3) columns: forward transform over y, times K's spectrum, inverse transform
-    for (int col = blockIdx.x; col < Lx; col += gridDim.x) {
+    for (int col = blockIdx.x; col < Hx; col += gridDim.x) {
         for (int v = threadIdx.x; v < Ly; v += WG) lds[v] = make_float2(0.f, 0.f);
         __syncthreads();
         for (int v = threadIdx.x; v < ny; v += WG) lds[bitrev((uint32_t)v, lgy)] = ldc2(&a.fft_b[(size_t)col * ny + v]);
@@ -750,31 +791,27 @@ __device__ bool fft_feedback(const KArgs &a, const Sync &y, uint32_t &epoch, int
         __syncthreads();
     }
     if (!grid_barrier(y, epoch, s_ok)) return false;
-    // (4) B[x][y] -> A[y][x]
-    transpose_tiles(a.fft_b, ny, a.fft_a, Lx, Lx, ny, blockIdx.x, gridDim.x, s_tr);
+    // (4) B[kx][y] -> A[y][kx]
+    transpose_tiles(a.fft_b, ny, a.fft_a, Hx, Hx, ny, blockIdx.x, gridDim.x, s_tr);
     if (!grid_barrier(y, epoch, s_ok)) return false;
-    // (5) inverse row transforms; subtract each tile's own cross-coupling
+    // (5) row pairs: Z = A + iB over the full length, inverse transform;
+    // row 2m is the real part, row 2m+1 the imaginary part
     const float scale = 1.0f / ((float)Lx * (float)Ly);
-    const __amdgpu_buffer_rsrc_t rs = make_rsrc(a.psf, a.psf_bytes);
-    for (int row = blockIdx.x; row < ny; row += gridDim.x) {
-        for (int x = threadIdx.x; x < Lx; x += WG) lds[bitrev((uint32_t)x, lgx)] = ldc2(&a.fft_a[(size_t)row * Lx + x]);
+    for (int pr = blockIdx.x; pr < npairs; pr += gridDim.x) {
+        const int r0 = 2 * pr;
+        const bool has1 = r0 + 1 < ny;
+        const float2 *i0 = a.fft_a + (size_t)r0 * Hx, *i1 = i0 + Hx;
+        for (int k = threadIdx.x; k < Hx; k += WG) {
+            const float2 A = ldc2(&i0[k]);
+            const float2 B = has1 ? ldc2(&i1[k]) : make_float2(0.f, 0.f);
+            lds[bitrev((uint32_t)k, lgx)] = make_float2(A.x - B.y, A.y + B.x);
+            if (k > 0 && k < Lx / 2) lds[bitrev((uint32_t)(Lx - k), lgx)] = make_float2(A.x + B.y, B.x - A.y);
+        }
         fft_lds(lds, lgx, a.tw_x, true);
-        const int ti = tile_row_of(a, row);
         for (int x = threadIdx.x; x < nx; x += WG) {
-            const float X = lds[x].x * scale;
-            const int t = ti * a.tx + tile_col_of(a, x);
-            const int n = s_off[t + 1] - s_off[t];
-            float own = 0.0f;
-            for (int q = 0; q < n; ++q) {
-                const size_t e = (size_t)t * a.interval + q;
-                const int32_t pos = ldc(&a.ag_pos[e]);
-                const int py = pos / nx, px = pos % nx;
-                const uint32_t off = (uint32_t)((row - py + a.cy) * a.psf_nx + (x - px + a.cx));
-                float pv[1];
-                PsfLoad<PT, 1>::load(rs, off * (uint32_t)sizeof(PT), pv);
-                own = __builtin_fmaf(ldc(&a.ag_flux[e]), pv[0], own);
-            }
-            stc(&a.accbuf[(size_t)row * nx + x], X - own);
+            const float2 z = lds[x];
+            stc(&a.accbuf[(size_t)r0 * nx + x], z.x * scale);
+            if (has1) stc(&a.accbuf[(size_t)(r0 + 1) * nx + x], z.y * scale);
         }
         __syncthreads();
     }
@@ -910,7 +947,7 @@ template <class Tile> __global__ void __launch_bounds__(WG) tiled_kernel(const K
     extern __shared__ __align__(16) unsigned char s_dyn[];
 
     const Sync y{a.ctl, a.timeout_ticks};
-    const Img im{a.dirty, a.residual, a.model, a.accbuf, a.psf, a.psf_bytes, a.nx, a.psf_nx, a.cy, a.cx};
+    const Img im{a.dirty, a.residual, a.model, a.accbuf, a.rstart, a.psf, a.psf_bytes, a.nx, a.psf_nx, a.cy, a.cx};
     const int32_t role = a.role[blockIdx.x];
     const bool is_cluster = role >= 0;
     const int tile = is_cluster ? (role >> 16) : -1;
@@ -1045,7 +1082,7 @@ template <class Tile> __global__ void __launch_bounds__(WG) tiled_kernel(const K
 
         // ---- feedback by FFT: acc = (component image (*) K) - own tile's part
         if (a.fft_lgx) {
-            if (!fft_feedback<PT>(a, y, epoch, &s_ok, s_off)) return;
+            if (!fft_feedback(a, y, epoch, &s_ok, s_off)) return;
         } else
         // ---- feedback gather: acc[q] = sum over other tiles' components
         {
