@@ -82,18 +82,26 @@ enum {
     CLEAN_FLAG_CHECK_FINITE = 1,   /* scan inputs for NaN/Inf before starting      */
     CLEAN_FLAG_STREAM_RESIDUAL = 2,/* keep the residual in HBM even when it would
                                       fit the register file (plain and tiled)     */
-    CLEAN_FLAG_FFT_FEEDBACK = 4    /* tiled: after each round, compute the
+    CLEAN_FLAG_FFT_FEEDBACK = 4,   /* tiled: after each round, compute the
                                       residual as the round's starting residual
                                       minus one FFT convolution of all the
                                       round's components with the PSF (the same
                                       update as the direct gather, own tile
-                                      included); images up to 4096 x 4096.  Not
-                                      bit-identical to the direct form: float32
-                                      transforms, relative error ~1e-6 of the
-                                      convolution's scale per round.  Adds
-                                      (2 Ly Lx + Lx ny) * 8 + ny nx * 4 bytes of
-                                      workspace, Lx, Ly the powers of two
-                                      >= 2 nx - 1, 2 ny - 1                   */
+                                      included); images up to 32768 x 32768.
+                                      Not bit-identical to the direct form:
+                                      float32 transforms, relative error ~1e-6
+                                      of the convolution's scale per round.
+                                      Workspace grows by about
+                                      (3 Hx R + Hx Ly) * 8 + ny nx * 4 bytes,
+                                      Lx, Ly the powers of two >= 2 nx - 1,
+                                      2 ny - 1, Hx = Lx/2 + 1, R = max(ny, Ly);
+                                      axes longer than 8192 points add two-level
+                                      work buffers (clean_workspace_size)      */
+    CLEAN_FLAG_FFT_TWO_LEVEL = 8   /* with CLEAN_FLAG_FFT_FEEDBACK: use the
+                                      two-level (four-step) transforms on every
+                                      axis of length >= 4, as they are used
+                                      automatically above 8192 points (slower;
+                                      for testing that path at small sizes)    */
 };
 
 typedef struct {
@@ -149,7 +157,7 @@ typedef struct {
  *   workspace  device scratch of workspace_bytes (>= clean_workspace_size()),
  *              or NULL to use a library-owned buffer.
  *   stats      host output, may be NULL.
- * Limits: ny*nx <= 2^28 - 1; (ny-1)*psf_nx + nx < 2^31 / element size.
+ * Limits: ny*nx <= 2^28; ((ny-1)*psf_nx + nx) * element size < 2^32.
  * Images whose residual fits the register file of the co-resident workgroups
  * keep it there for the whole run; larger ones stream it through `residual`.
  */

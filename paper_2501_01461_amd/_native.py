@@ -21,6 +21,7 @@ PSF_F32, PSF_F16 = 0, 1
 FLAG_CHECK_FINITE = 1
 FLAG_STREAM_RESIDUAL = 2
 FLAG_FFT_FEEDBACK = 4
+FLAG_FFT_TWO_LEVEL = 8
 
 # every symbol include/clean.h declares
 EXPORTS = ("clean_hogbom", "clean_tiled_feedback", "clean_batched", "clean_autotune", "clean_workspace_size",
@@ -166,7 +167,7 @@ def hogbom(dirty, psf, gain=0.1, threshold=0.0, max_iter=1000, cap=None, model=T
 
 def tiled_feedback(dirty, psf, tiles=(2, 2), interval=100, gain=0.1, threshold=0.0, max_iter=1000, cap=None,
                    model=True, check_finite=False, wg_per_tile=0, px_per_thread=0, stream=False, out=None,
-                   level=0.0, fft=False):
+                   level=0.0, fft=False, fft_two_level=False):
     """Tiled Hogbom CLEAN with feedback; returns dict(residual, idx, flux, model, stats).
 
     level: flux trigger, the fraction of the largest tile peak at a round's
@@ -179,6 +180,8 @@ def tiled_feedback(dirty, psf, tiles=(2, 2), interval=100, gain=0.1, threshold=0
     p.feedback_level = float(level)
     if fft:
         p.flags |= FLAG_FFT_FEEDBACK
+    if fft_two_level:
+        p.flags |= FLAG_FFT_FEEDBACK | FLAG_FFT_TWO_LEVEL
     st = Stats()
     ny, nx = dirty.shape
     _check(lib.clean_tiled_feedback(_ptr(dirty), ny, nx, _ptr(psf), psf.shape[0], psf.shape[1], int(tiles[0]),

@@ -26,11 +26,6 @@ template <class Tile> __global__ void hogbom_kernel(const KArgs a);
 template <class Tile> __global__ void tiled_kernel(const KArgs a);
 template <class Tile> __global__ void batched_kernel(const BatchArgs b);
 __global__ void finalize_batch_kernel(const PlainJob *jobs, int n);
-template <typename PT>
-__global__ void fft_kernel_rows(const void *psf, int psf_nx, int cy, int cx, int ny, int nx, int lgx, int lgy,
-                                const float2 *tw_x, float2 *A);
-__global__ void fft_transpose_kernel(const float2 *src, int ss, float2 *dst, int ds, int rows, int cols);
-__global__ void fft_rows_kernel(float2 *X, int rows, int lg, const float2 *tw);
 __global__ void finite_check_kernel(const float *x, int64_t n, uint32_t *flag);
 __global__ void finite_check_half_kernel(const unsigned short *x, int64_t n, uint32_t *flag);
 __global__ void to_half_kernel(const float *x, unsigned short *y, int64_t n);
@@ -100,7 +95,7 @@ size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 struct Layout {
     size_t ctl, dstat, xslots, tile_key, rb_n, ag_n, header_end;
     size_t role, rb_idx, rb_flux, ag_pos, ag_flux, accbuf, partial;
-    size_t fft_a, fft_b, fft_ks, tw_x, tw_y, rstart, total;
+    size_t fft_a, fft_b, fft_wx, fft_wy, fft_ks, comp_img, tw_x, tw_y, rstart, total;
 };
 
 int ceil_log2(int64_t v)
@@ -110,8 +105,14 @@ int ceil_log2(int64_t v)
     return lg;
 }
 
+// FFT feedback geometry: transform sizes and which axes take two levels.
+struct FftGeom {
+    int lgx = 0, lgy = 0;       // 0: direct gather
+    bool two_x = false, two_y = false;
+};
+
 Layout make_layout(int T, int cs, int slot_pad, int interval, int W, int64_t npix, bool tiled, int ny = 0,
-                   int lgx = 0, int lgy = 0)
+                   const FftGeom &g = FftGeom())
 {
     Layout L{};
     size_t o = 0;
@@ -130,13 +131,18 @@ Layout make_layout(int T, int cs, int slot_pad, int interval, int W, int64_t npi
     L.ag_flux = o;   o = align_up(o + list, 256);
     L.accbuf = o;    o = align_up(o + (tiled ? (size_t)npix * 4 : 0), 256);
     L.partial = o;   o = align_up(o + (size_t)T * cs * 8, 256);
-    const size_t Lx = lgx ? (size_t)1 << lgx : 0, Ly = lgy ? (size_t)1 << lgy : 0;
-    L.fft_a = o;     o = align_up(o + Ly * Lx * 8, 256);
-    L.fft_b = o;     o = align_up(o + Lx * (size_t)ny * 8, 256);
-    L.fft_ks = o;    o = align_up(o + Lx * Ly * 8, 256);
-    L.tw_x = o;      o = align_up(o + Lx / 2 * 8, 256);
-    L.tw_y = o;      o = align_up(o + Ly / 2 * 8, 256);
-    L.rstart = o;    o = align_up(o + (lgx ? (size_t)npix * 4 : 0), 256);
+    const bool fft = g.lgx > 0;
+    const size_t Lx = fft ? (size_t)1 << g.lgx : 0, Ly = fft ? (size_t)1 << g.lgy : 0;
+    const size_t Hx = fft ? Lx / 2 + 1 : 0, rows = std::max<size_t>(ny, Ly);
+    L.fft_a = o;     o = align_up(o + rows * Hx * 8, 256);
+    L.fft_b = o;     o = align_up(o + Hx * rows * 8, 256);
+    L.fft_wx = o;    o = align_up(o + (g.two_x ? (rows + 1) / 2 * Lx * 8 : 0), 256);
+    L.fft_wy = o;    o = align_up(o + (g.two_y ? Hx * Ly * 8 : 0), 256);
+    L.fft_ks = o;    o = align_up(o + Hx * Ly * 8, 256);
+    L.comp_img = o;  o = align_up(o + (g.two_x ? (size_t)npix * 4 : 0), 256);
+    L.tw_x = o;      o = align_up(o + Lx * 8, 256);
+    L.tw_y = o;      o = align_up(o + Ly * 8, 256);
+    L.rstart = o;    o = align_up(o + (fft ? (size_t)npix * 4 : 0), 256);
     L.total = o;
     return L;
 }
@@ -296,6 +302,21 @@ int device_timeout_ticks(int dev, uint64_t &ticks)
     return CLEAN_OK;
 }
 
+// Transform sizes for FFT feedback: powers of two >= 2n - 1 per axis; an axis
+// longer than 8192 points (or any axis of length >= 4, when asked) takes two
+// levels.
+int fft_geometry(int ny, int nx, int flags, FftGeom &g)
+{
+    g.lgx = std::max(1, ceil_log2(2 * (int64_t)nx - 1));
+    g.lgy = std::max(1, ceil_log2(2 * (int64_t)ny - 1));
+    if (g.lgx > FFT_MAX_LG2 || g.lgy > FFT_MAX_LG2)
+        return fail(CLEAN_E_UNSUPPORTED, "FFT feedback supports images up to 32768 x 32768 (transforms of 65536)");
+    const bool force = flags & CLEAN_FLAG_FFT_TWO_LEVEL;
+    g.two_x = g.lgx > FFT_MAX_LG || (force && g.lgx >= 2);
+    g.two_y = g.lgy > FFT_MAX_LG || (force && g.lgy >= 2);
+    return CLEAN_OK;
+}
+
 int check_common(const float *dirty, int ny, int nx, const void *psf, int psf_ny, int psf_nx, const clean_params *p,
                  float *residual, int32_t *comp_idx, float *comp_flux, int64_t comp_cap)
 {
@@ -303,12 +324,12 @@ int check_common(const float *dirty, int ny, int nx, const void *psf, int psf_ny
     if (!dirty || !psf || !residual) return fail(CLEAN_E_INVAL, "dirty, psf and residual must be non-NULL");
     if (comp_cap > 0 && (!comp_idx || !comp_flux)) return fail(CLEAN_E_INVAL, "component arrays are NULL");
     if (ny <= 0 || nx <= 0) return fail(CLEAN_E_INVAL, "image size %d x %d", ny, nx);
-    if ((int64_t)ny * nx > (1ll << 28) - 1) return fail(CLEAN_E_UNSUPPORTED, "image of %lld pixels exceeds 2^28-1", (long long)ny * nx);
+    if ((int64_t)ny * nx > (1ll << 28)) return fail(CLEAN_E_UNSUPPORTED, "image of %lld pixels exceeds 2^28", (long long)ny * nx);
     if (psf_ny < 2 * (int64_t)ny || psf_nx < 2 * (int64_t)nx)
         return fail(CLEAN_E_INVAL, "PSF %d x %d must be at least twice the image %d x %d", psf_ny, psf_nx, ny, nx);
     const uint64_t es = p->psf_dtype == CLEAN_PSF_F16 ? 2 : 4;
     if ((uint64_t)psf_ny * psf_nx * es > (1ull << 34)) return fail(CLEAN_E_UNSUPPORTED, "PSF larger than 16 GiB");
-    if ((int64_t)ny * psf_nx + nx >= (1ll << 31) / (int64_t)es)
+    if ((uint64_t)((int64_t)(ny - 1) * psf_nx + nx) * es > 0xFFFFFFFFull)
         return fail(CLEAN_E_UNSUPPORTED, "image x PSF row length too large for 32-bit offsets");
     if (!(p->gain > 0.0 && p->gain <= 1.0)) return fail(CLEAN_E_INVAL, "gain %g not in (0, 1]", p->gain);
     if (!(p->threshold >= 0.0)) return fail(CLEAN_E_INVAL, "threshold %g < 0", p->threshold);
@@ -342,12 +363,10 @@ int run(bool tiled, const float *dirty, int ny, int nx, const void *psf, int psf
         interval = 1;
     }
     const bool fft = tiled && (p->flags & CLEAN_FLAG_FFT_FEEDBACK);
-    int lgx = 0, lgy = 0;
+    FftGeom fg;
     if (fft) {
-        lgx = std::max(1, ceil_log2(2 * (int64_t)nx - 1));
-        lgy = std::max(1, ceil_log2(2 * (int64_t)ny - 1));
-        if (lgx > 13 || lgy > 13)
-            return fail(CLEAN_E_UNSUPPORTED, "FFT feedback supports images up to 4096 x 4096 (transforms of 8192)");
+        st = fft_geometry(ny, nx, p->flags, fg);
+        if (st) return st;
     }
     hipStream_t stream = (hipStream_t)stream_v;
     int dev = 0;
@@ -369,7 +388,11 @@ int run(bool tiled, const float *dirty, int ny, int nx, const void *psf, int psf
     const int V = w4 ? 4 : 1;
     const bool half = p->psf_dtype == CLEAN_PSF_F16;
     size_t dyn_lds = tiled ? std::max((size_t)16 * interval, (size_t)8 * GATHER_CHUNK) : 0;
-    if (fft) dyn_lds = std::max(dyn_lds, (size_t)8 << std::max(lgx, lgy));
+    if (fft) {
+        if (!fg.two_x) dyn_lds = std::max(dyn_lds, (size_t)8 << fg.lgx);
+        if (!fg.two_y) dyn_lds = std::max(dyn_lds, (size_t)8 << fg.lgy);
+        if (fg.two_x || fg.two_y) dyn_lds = std::max(dyn_lds, (size_t)8 * FFT_LDS_CPLX);
+    }
 
     // placement: cluster c lives on XCD c % 8 (workgroup b runs on XCD b % 8);
     // tiled launches add helper workgroups for the feedback gather
@@ -449,7 +472,7 @@ int run(bool tiled, const float *dirty, int ny, int nx, const void *psf, int psf
 
     const int slot_pad = (cs + 31) / 32 * 32;
     const int64_t npix = (int64_t)ny * nx;
-    const Layout L = make_layout(T, cs, slot_pad, interval, W, npix, tiled, ny, lgx, lgy);
+    const Layout L = make_layout(T, cs, slot_pad, interval, W, npix, tiled, ny, fg);
     char *ws = (char *)workspace;
     if (ws) {
         if (workspace_bytes < L.total)
@@ -496,11 +519,16 @@ int run(bool tiled, const float *dirty, int ny, int nx, const void *psf, int psf
     a.ag_n = (int32_t *)(ws + L.ag_n);
     a.accbuf = (float *)(ws + L.accbuf);
     a.partial = (double *)(ws + L.partial);
-    a.fft_lgx = lgx;
-    a.fft_lgy = lgy;
+    a.fft_lgx = fg.lgx;
+    a.fft_lgy = fg.lgy;
+    a.fft_two_x = fg.two_x;
+    a.fft_two_y = fg.two_y;
     a.fft_a = (float2 *)(ws + L.fft_a);
     a.fft_b = (float2 *)(ws + L.fft_b);
-    a.fft_ks = (const float2 *)(ws + L.fft_ks);
+    a.fft_wx = (float2 *)(ws + L.fft_wx);
+    a.fft_wy = (float2 *)(ws + L.fft_wy);
+    a.fft_ks = (float2 *)(ws + L.fft_ks);
+    a.comp_img = fg.two_x ? (float *)(ws + L.comp_img) : nullptr;
     a.tw_x = (const float2 *)(ws + L.tw_x);
     a.tw_y = (const float2 *)(ws + L.tw_y);
     a.rstart = fft ? (float *)(ws + L.rstart) : nullptr;
@@ -525,35 +553,22 @@ int run(bool tiled, const float *dirty, int ny, int nx, const void *psf, int psf
 
     std::vector<float2> twx, twy;
     if (fft) {
-        // twiddles in double, rounded once; then the PSF kernel's spectrum
+        // twiddles W_L^m = exp(-2 pi i m / L), m < L, in double, rounded once;
+        // the PSF kernel's spectrum is computed at the start of the launch
         for (int pass = 0; pass < 2; ++pass) {
-            const int lg = pass ? lgy : lgx;
+            const int lg = pass ? fg.lgy : fg.lgx;
             std::vector<float2> &tw = pass ? twy : twx;
-            const int Lh = 1 << (lg - 1);
-            tw.resize(Lh);
-            for (int m = 0; m < Lh; ++m) {
-                const double ang = -2.0 * M_PI * (double)m / (double)(2 * Lh);
+            const int Lt = 1 << lg;
+            tw.resize(Lt);
+            for (int m = 0; m < Lt; ++m) {
+                const double ang = -2.0 * M_PI * (double)m / (double)Lt;
                 tw[m] = make_float2((float)std::cos(ang), (float)std::sin(ang));
             }
         }
         HIPCHK(hipMemcpyAsync(ws + L.rstart, dirty, (size_t)npix * 4, hipMemcpyDeviceToDevice, stream));
+        if (fg.two_x) HIPCHK(hipMemsetAsync(ws + L.comp_img, 0, (size_t)npix * 4, stream));
         HIPCHK(hipMemcpyAsync(ws + L.tw_x, twx.data(), twx.size() * 8, hipMemcpyHostToDevice, stream));
         HIPCHK(hipMemcpyAsync(ws + L.tw_y, twy.data(), twy.size() * 8, hipMemcpyHostToDevice, stream));
-        const int Lx = 1 << lgx, Ly = 1 << lgy;
-        const void *krows = half ? (const void *)fft_kernel_rows<__half> : (const void *)fft_kernel_rows<float>;
-        HIPCHK(hipFuncSetAttribute(krows, hipFuncAttributeMaxDynamicSharedMemorySize, 8 * Lx));
-        HIPCHK(hipFuncSetAttribute((const void *)fft_rows_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, 8 * Ly));
-        if (half)
-            hipLaunchKernelGGL(fft_kernel_rows<__half>, dim3(std::min(Ly, 2048)), dim3(WG), 8 * Lx, stream, psf, psf_nx,
-                               a.cy, a.cx, ny, nx, lgx, lgy, a.tw_x, a.fft_a);
-        else
-            hipLaunchKernelGGL(fft_kernel_rows<float>, dim3(std::min(Ly, 2048)), dim3(WG), 8 * Lx, stream, psf, psf_nx,
-                               a.cy, a.cx, ny, nx, lgx, lgy, a.tw_x, a.fft_a);
-        hipLaunchKernelGGL(fft_transpose_kernel, dim3(2048), dim3(WG), 0, stream, (const float2 *)a.fft_a, Lx,
-                           (float2 *)a.fft_ks, Ly, Ly, Lx);
-        hipLaunchKernelGGL(fft_rows_kernel, dim3(std::min(Lx, 2048)), dim3(WG), 8 * Ly, stream, (float2 *)a.fft_ks, Lx,
-                           lgy, a.tw_y);
-        HIPCHK(hipGetLastError());
     }
 
     hipEvent_t e0, e1;
@@ -802,14 +817,13 @@ size_t clean_workspace_size(int ny, int nx, int tiles_y, int tiles_x, int feedba
     const int64_t npix = (int64_t)ny * nx;
     const int cs_max = 4096;
     const int W_max = 8192;
-    int lgx = 0, lgy = 0;
+    FftGeom fg;
     if (tiled && (p->flags & CLEAN_FLAG_FFT_FEEDBACK)) {
-        lgx = std::max(1, ceil_log2(2 * (int64_t)nx - 1));
-        lgy = std::max(1, ceil_log2(2 * (int64_t)ny - 1));
-        if (lgx > 13 || lgy > 13) return 0;
+        g_last_error.clear();
+        if (fft_geometry(ny, nx, p->flags, fg) != CLEAN_OK) return 0;
     }
     const Layout L = make_layout(T, tiled ? cs_max / T + 64 : cs_max, (cs_max + 31) / 32 * 32,
-                                 tiled ? feedback_interval : 1, W_max, npix, tiled, ny, lgx, lgy);
+                                 tiled ? feedback_interval : 1, W_max, npix, tiled, ny, fg);
     return L.total;
 }
 

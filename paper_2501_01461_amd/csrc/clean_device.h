@@ -13,6 +13,9 @@ constexpr int GATHER_CHUNK = 2048;      // components staged in LDS per pass
 constexpr int GATHER_M = 2;             // pixel groups per thread per gather pass
 constexpr int GATHER_J = 8;             // components whose loads are issued together
 constexpr int STREAM_K = 4;             // pixel groups per thread per streamed pass
+constexpr int FFT_MAX_LG = 13;          // one-level FFT transforms: length <= 8192 (64 KB of LDS)
+constexpr int FFT_MAX_LG2 = 16;         // two-level FFT transforms: length <= 65536
+constexpr int FFT_LDS_CPLX = 8192 + 64; // LDS complex slots of the two-level passes
 
 enum { STOP_MAXITER = 0, STOP_THRESHOLD = 1, STOP_CAPACITY = 2 };
 enum : uint32_t { ABORT_TIMEOUT = 1u };
@@ -102,12 +105,16 @@ struct KArgs {
     int32_t *ag_n;          // [T]
     float *accbuf;          // [ny*nx] feedback sums
     // FFT form of the feedback (fft_lgx = 0: direct gather)
-    int fft_lgx, fft_lgy;   // log2 of the transform sizes Lx, Ly
-    float2 *fft_a;          // [Ly][Lx] row transforms of the component image
-    float2 *fft_b;          // [Lx][ny] after the column pass
-    const float2 *fft_ks;   // [Lx][Ly] spectrum of the PSF kernel, transposed
-    const float2 *tw_x;     // [Lx/2] twiddles exp(-2 pi i m / Lx)
-    const float2 *tw_y;     // [Ly/2]
+    int fft_lgx, fft_lgy;   // log2 of the transform sizes Lx, Ly (0: direct gather)
+    int fft_two_x, fft_two_y;  // axis uses two-level transforms
+    float2 *fft_a;          // [max(ny, Ly)][Lx/2+1] carried x bins per row
+    float2 *fft_b;          // [Lx/2+1][max(ny, Ly)] the same, by column
+    float2 *fft_wx;         // [max(ny, Ly)/2][Lx] two-level x work rows (row pairs)
+    float2 *fft_wy;         // [Lx/2+1][Ly] two-level y work columns
+    float2 *fft_ks;         // [Lx/2+1][Ly] spectrum of the PSF kernel by carried column
+    float *comp_img;        // [ny*nx] dense component image (two-level x), zero between rounds
+    const float2 *tw_x;     // [Lx] twiddles exp(-2 pi i m / Lx)
+    const float2 *tw_y;     // [Ly]
     float *rstart;          // [ny*nx] residual at the round's start (FFT form), else null
     double *partial;        // [T*cs] per-workgroup sum of squared residuals
 };

@@ -16,9 +16,10 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "clean_device.h"
+
 namespace cleanhip {
 
-constexpr int FFT_MAX_LG = 13;          // length 8192
 
 // Agent-coherent 8-byte accesses: the FFT buffers are written by one
 // workgroup and read by others within one launch.
@@ -55,6 +56,42 @@ __device__ inline void fft_lds(float2 *a, int lg, const float2 *tw, bool inverse
         }
         __syncthreads();
     }
+}
+
+// `count` independent in-place transforms of length 2^lg, segment i at
+// a[i * stride ..], bit-reversed input, natural output.  tw is a table of
+// W_L^m for a length L = 2^lg * tw_step (entries m < L/2 are read).
+__device__ inline void fft_lds_multi(float2 *a, int lg, int count, int stride, const float2 *tw, int tw_step,
+                                     bool inverse)
+{
+    const int H = 1 << (lg - 1);
+    const int total = count * H;
+    __syncthreads();
+    for (int s = 0; s < lg; ++s) {
+        const int half = 1 << s;
+        for (int j = threadIdx.x; j < total; j += blockDim.x) {
+            const int seg = j >> (lg - 1), jj = j & (H - 1);
+            const int k = jj & (half - 1);
+            float2 *b = a + seg * stride;
+            const int i0 = ((jj >> s) << (s + 1)) + k, i1 = i0 + half;
+            float2 w = tw[(k << (lg - 1 - s)) * tw_step];
+            if (inverse) w.y = -w.y;
+            const float2 u = b[i0], v = b[i1];
+            const float2 t = make_float2(v.x * w.x - v.y * w.y, v.x * w.y + v.y * w.x);
+            b[i0] = make_float2(u.x + t.x, u.y + t.y);
+            b[i1] = make_float2(u.x - t.x, u.y - t.y);
+        }
+        __syncthreads();
+    }
+}
+
+__device__ __forceinline__ float2 cmul(float2 p, float2 q)
+{
+    return make_float2(p.x * q.x - p.y * q.y, p.x * q.y + p.y * q.x);
+}
+__device__ __forceinline__ float2 cmulc(float2 p, float2 q)   // p * conj(q)
+{
+    return make_float2(p.x * q.x + p.y * q.y, p.y * q.x - p.x * q.y);
 }
 
 // Puts a natural-order array into bit-reversed order, in place.

@@ -679,21 +679,81 @@ template <class Tile> __global__ void __launch_bounds__(WG) batched_kernel(const
 
 
 // ----------------------------------------------------- FFT feedback -----
+//
+// The feedback step in FFT form: per round, the residual becomes the round's
+// starting residual minus (the round's component image (*) the PSF), one
+// circular convolution on an Ly x Lx grid (powers of two >= 2n - 1, so the
+// image window sees no wrap-around).  The component image is real: rows go
+// two at a time through one complex transform along x, and only the
+// Lx/2 + 1 non-redundant bins are carried through the y transforms.
+//
+// An axis of length L <= 8192 is transformed in one pass in LDS (one
+// transform per workgroup).  Longer axes use two levels, L = L1 * L2 with
+// n = L2 n1 + n2 and k = k1 + L1 k2 (the four-step scheme): transforms of
+// length L1 over n1 (strided), times W_L^(n2 k1), then transforms of length
+// L2 over n2 (contiguous); the inverse runs the same steps backwards.  The
+// two-level spectra come out in (k1, k2) order; the PSF kernel's spectrum is
+// computed once per call by the same code, so both orders agree.
 
+struct FftAxis {
+    int lg, L, H;           // length 2^lg; H = L/2 + 1 (x axis: carried bins)
+    bool two;               // two levels: L = L1 * L2
+    int lg1, lg2, L1, L2;
+    const float2 *tw;       // W_L^m, m < L
+};
+
+__device__ __forceinline__ FftAxis fft_axis(int lg, int two, const float2 *tw)
+{
+    FftAxis f;
+    f.lg = lg;
+    f.L = 1 << lg;
+    f.H = f.L / 2 + 1;
+    f.two = two != 0;
+    f.tw = tw;
+    f.lg1 = lg / 2;
+    f.lg2 = lg - f.lg1;
+    f.L1 = 1 << f.lg1;
+    f.L2 = 1 << f.lg2;
+    return f;
+}
+
+// Carried column of x bin (k1, k2), two levels: bins k = k1 + L1 k2 <= L/2,
+// laid out k1-major (L2/2 per row k1) with k = L/2 last.
+__device__ __forceinline__ int chat_of(const FftAxis &f, int k1, int k2)
+{
+    return k2 < f.L2 / 2 ? k1 * (f.L2 / 2) + k2 : f.L / 2;
+}
+
+// The bin holding index L - k (two levels).
+__device__ __forceinline__ void mirror_of(const FftAxis &f, int k1, int k2, int &q1, int &q2)
+{
+    if (k1 == 0) {
+        q1 = 0;
+        q2 = (f.L2 - k2) & (f.L2 - 1);
+    } else {
+        q1 = f.L1 - k1;
+        q2 = f.L2 - 1 - k2;
+    }
+}
+
+// Value of the PSF kernel image at grid point (row, x): K(d) = psf[centre + d]
+// for |d| < (ny, nx), placed circularly, zero elsewhere.
+template <typename PT>
+__device__ __forceinline__ float kernel_value(const KArgs &a, int Ly, int Lx, int row, int x)
+{
+    const int dy = row < a.ny ? row : row - Ly;
+    const int dx = x < a.nx ? x : x - Lx;
+    if (dy <= -a.ny || dx <= -a.nx) return 0.0f;
+    return (float)((const PT *)a.psf)[(int64_t)(a.cy + dy) * a.psf_nx + (a.cx + dx)];
+}
+
+// Tile row / column of an image row / column (floor split).
 __device__ __forceinline__ int tile_row_of(const KArgs &a, int y)
 {
     int i = (int)((int64_t)y * a.ty / a.ny);
     while (i + 1 < a.ty && (int)((int64_t)(i + 1) * a.ny / a.ty) <= y) ++i;
     while (i > 0 && (int)((int64_t)i * a.ny / a.ty) > y) --i;
     return i;
-}
-
-__device__ __forceinline__ int tile_col_of(const KArgs &a, int x)
-{
-    int j = (int)((int64_t)x * a.tx / a.nx);
-    while (j + 1 < a.tx && (int)((int64_t)(j + 1) * a.nx / a.tx) <= x) ++j;
-    while (j > 0 && (int)((int64_t)j * a.nx / a.tx) > x) --j;
-    return j;
 }
 
 // First index k in [lo, hi) of tile t's aggregated list with position >= key.
@@ -707,107 +767,294 @@ __device__ __forceinline__ int lower_pos(const KArgs &a, int t, int lo, int hi, 
     return lo;
 }
 
-// The round's feedback through one circular convolution of the round's
-// component image (every tile's components) with the PSF.  The image is real,
-// so rows go two at a time through one complex transform (row 2m as the real
-// part, row 2m+1 as the imaginary part) and only the Lx/2 + 1 non-redundant
-// columns of the row spectra are carried on.  Phases, each ended by a grid
-// barrier: (1) row-pair transforms of the component image, built from the
-// aggregated lists, split into the two rows' half spectra; (2) transpose;
-// (3) per column: transform, times the PSF kernel's spectrum, inverse
-// transform; (4) transpose; (5) row-pair inverse transforms from the two
-// rows' half spectra (Hermitian symmetry gives the rest) into the feedback
-// buffer.  The buffer then holds every tile's contribution, own tile
-// included, so the apply step recomputes the residual from the round's
-// starting residual: mathematically the paper's update (own components
-// subtracted locally, the others' by feedback), rounded once.
-__device__ bool fft_feedback(const KArgs &a, const Sync &y, uint32_t &epoch, int *s_ok, const int32_t *s_off)
+// Split of a row pair's transform Z (row r0 real part, r0+1 imaginary part)
+// at bin k: A = (Z[k] + conj Z[L-k]) / 2 and B = (Z[k] - conj Z[L-k]) / 2i.
+__device__ __forceinline__ void store_split(float2 *o0, float2 *o1, bool has1, int c, float2 zk, float2 zm)
 {
-    extern __shared__ __align__(16) unsigned char s_dyn[];
-    __shared__ float2 s_tr[32][33];
-    __shared__ int s_nz;
-    float2 *lds = (float2 *)s_dyn;
-    const int lgx = a.fft_lgx, lgy = a.fft_lgy;
-    const int Lx = 1 << lgx, Ly = 1 << lgy, Hx = Lx / 2 + 1;
-    const int ny = a.ny, nx = a.nx, tx = a.tx;
-    const int npairs = (ny + 1) / 2;
+    stc2(&o0[c], make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y)));
+    if (has1) stc2(&o1[c], make_float2(0.5f * (zk.y + zm.y), -0.5f * (zk.x - zm.x)));
+}
 
-    // (1) row pairs of the component image -> half spectra, rows of stride Hx
-    for (int pr = blockIdx.x; pr < npairs; pr += gridDim.x) {
+// x forward, one level: row pairs -> carried bins (natural order) of `rows`
+// rows, into fft_a (row stride H).  Source: the round's aggregated component
+// lists, or (KSRC) the PSF kernel image.
+template <typename PT, bool KSRC>
+__device__ void xfwd_one(const KArgs &a, const FftAxis &fx, int Ly, int rows, const int32_t *s_off, float2 *lds,
+                         int *s_nz)
+{
+    const int Lx = fx.L, lgx = fx.lg, nx = a.nx, tx = a.tx;
+    for (int pr = blockIdx.x; pr < (rows + 1) / 2; pr += gridDim.x) {
         const int r0 = 2 * pr;
-        const bool has1 = r0 + 1 < ny;
-        for (int x = threadIdx.x; x < Lx; x += WG) lds[x] = make_float2(0.f, 0.f);
-        if (threadIdx.x == 0) s_nz = 0;
-        __syncthreads();
-        for (int j = threadIdx.x; j < 2 * tx; j += WG) {
-            const int row = r0 + (j >= tx);
-            if (row >= ny) continue;
-            const int t = tile_row_of(a, row) * tx + (j % tx);
-            const int n = s_off[t + 1] - s_off[t];
-            const int32_t b0 = row * nx;
-            const int lo = lower_pos(a, t, 0, n, b0), hi = lower_pos(a, t, lo, n, b0 + nx);
-            if (hi > lo) atomicAdd(&s_nz, hi - lo);
-            for (int q = lo; q < hi; ++q) {
-                const size_t e = (size_t)t * a.interval + q;
-                float *dst = (float *)&lds[bitrev((uint32_t)(ldc(&a.ag_pos[e]) - b0), lgx)];
-                dst[j >= tx] = ldc(&a.ag_flux[e]);
-            }
-        }
-        __syncthreads();
-        float2 *o0 = a.fft_a + (size_t)r0 * Hx, *o1 = o0 + Hx;
-        if (s_nz == 0) {                        // both rows empty: zero spectra
-            for (int k = threadIdx.x; k < Hx; k += WG) {
-                stc2(&o0[k], make_float2(0.f, 0.f));
-                if (has1) stc2(&o1[k], make_float2(0.f, 0.f));
-            }
+        const bool has1 = r0 + 1 < rows;
+        if (KSRC) {
+            for (int x = threadIdx.x; x < Lx; x += WG)
+                lds[bitrev((uint32_t)x, lgx)] = make_float2(kernel_value<PT>(a, Ly, Lx, r0, x),
+                                                            has1 ? kernel_value<PT>(a, Ly, Lx, r0 + 1, x) : 0.0f);
+            if (threadIdx.x == 0) *s_nz = 1;
+            __syncthreads();
         } else {
-            fft_lds(lds, lgx, a.tw_x, false);
-            for (int k = threadIdx.x; k < Hx; k += WG) {
-                const float2 zk = lds[k], zm = lds[(Lx - k) & (Lx - 1)];
-                // A = (Z[k] + conj Z[-k]) / 2,  B = (Z[k] - conj Z[-k]) / 2i
-                stc2(&o0[k], make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y)));
-                if (has1) stc2(&o1[k], make_float2(0.5f * (zk.y + zm.y), -0.5f * (zk.x - zm.x)));
+            for (int x = threadIdx.x; x < Lx; x += WG) lds[x] = make_float2(0.f, 0.f);
+            if (threadIdx.x == 0) *s_nz = 0;
+            __syncthreads();
+            for (int j = threadIdx.x; j < 2 * tx; j += WG) {
+                const int row = r0 + (j >= tx);
+                if (row >= rows) continue;
+                const int t = tile_row_of(a, row) * tx + (j % tx);
+                const int n = s_off[t + 1] - s_off[t];
+                const int32_t b0 = row * nx;
+                const int lo = lower_pos(a, t, 0, n, b0), hi = lower_pos(a, t, lo, n, b0 + nx);
+                if (hi > lo) atomicAdd(s_nz, hi - lo);
+                for (int q = lo; q < hi; ++q) {
+                    const size_t e = (size_t)t * a.interval + q;
+                    float *dst = (float *)&lds[bitrev((uint32_t)(ldc(&a.ag_pos[e]) - b0), lgx)];
+                    dst[j >= tx] = ldc(&a.ag_flux[e]);
+                }
+            }
+            __syncthreads();
+        }
+        float2 *o0 = a.fft_a + (size_t)r0 * fx.H, *o1 = o0 + fx.H;
+        if (*s_nz == 0) {                       // both rows empty: zero spectra
+            for (int k = threadIdx.x; k < fx.H; k += WG) store_split(o0, o1, has1, k, make_float2(0.f, 0.f),
+                                                                    make_float2(0.f, 0.f));
+        } else {
+            fft_lds(lds, lgx, fx.tw, false);
+            for (int k = threadIdx.x; k < fx.H; k += WG) store_split(o0, o1, has1, k, lds[k], lds[(Lx - k) & (Lx - 1)]);
+        }
+        __syncthreads();
+    }
+}
+
+// x forward, two levels, step 1: per row pair and n2, transforms of length L1
+// over n1 (input x = L2 n1 + n2), times W_L^(n2 k1), into fft_wx[pair][L2 k1 + n2].
+// Source: the dense component image, or (KSRC) the PSF kernel image.
+template <typename PT, bool KSRC>
+__device__ void xfwd_two_a(const KArgs &a, const FftAxis &fx, int Ly, int rows, float2 *lds)
+{
+    const int NB = min(fx.L2, 4096 >> fx.lg1);
+    const int nblk = fx.L2 / NB, stride = fx.L1 + 1;
+    const int ncols = KSRC ? fx.L : a.nx;
+    for (int item = blockIdx.x; item < (rows + 1) / 2 * nblk; item += gridDim.x) {
+        const int pr = item / nblk, b = item % nblk;
+        const int r0 = 2 * pr;
+        const bool has1 = r0 + 1 < rows;
+        __syncthreads();
+        for (int e = threadIdx.x; e < NB * fx.L1; e += WG) {
+            const int j = e % NB, n1 = e / NB;
+            const int x = fx.L2 * n1 + b * NB + j;
+            float v0 = 0.f, v1 = 0.f;
+            if (x < ncols) {
+                if (KSRC) {
+                    v0 = kernel_value<PT>(a, Ly, fx.L, r0, x);
+                    if (has1) v1 = kernel_value<PT>(a, Ly, fx.L, r0 + 1, x);
+                } else {
+                    v0 = ldc(&a.comp_img[(size_t)r0 * a.nx + x]);
+                    if (has1) v1 = ldc(&a.comp_img[(size_t)(r0 + 1) * a.nx + x]);
+                }
+            }
+            lds[j * stride + bitrev((uint32_t)n1, fx.lg1)] = make_float2(v0, v1);
+        }
+        fft_lds_multi(lds, fx.lg1, NB, stride, fx.tw, fx.L2, false);
+        float2 *w = a.fft_wx + (size_t)pr * fx.L;
+        for (int e = threadIdx.x; e < NB * fx.L1; e += WG) {
+            const int j = e % NB, k1 = e / NB, n2 = b * NB + j;
+            stc2(&w[(size_t)fx.L2 * k1 + n2], cmul(lds[j * stride + k1], fx.tw[n2 * k1]));
+        }
+    }
+}
+
+// x forward, two levels, step 2: per row pair, rows k1 and L1 - k1 of the
+// step-1 output transformed over n2 (length L2), then split into the two
+// image rows' carried bins (chat order) in fft_a.  Unless KSRC, also clears
+// the dense component image at this round's positions.
+template <bool KSRC>
+__device__ void xfwd_two_b(const KArgs &a, const FftAxis &fx, int rows, float2 *lds, const int32_t *s_off)
+{
+    const int nslot = fx.L1 / 2 + 1;
+    const int stride = fx.L2 + 1;
+    const int G = max(1, min(nslot, FFT_LDS_CPLX / (2 * stride)));
+    const int nblk = (nslot + G - 1) / G;
+    const int hq = fx.L2 / 2;
+    for (int item = blockIdx.x; item < (rows + 1) / 2 * nblk; item += gridDim.x) {
+        const int pr = item / nblk, s0 = (item % nblk) * G, ns = min(G, nslot - s0);
+        const int r0 = 2 * pr;
+        const bool has1 = r0 + 1 < rows;
+        const float2 *w = a.fft_wx + (size_t)pr * fx.L;
+        __syncthreads();
+        // segment 2i: row k1 = s0 + i; segment 2i+1: row (L1 - k1) mod L1
+        for (int e = threadIdx.x; e < 2 * ns * fx.L2; e += WG) {
+            const int seg = e / fx.L2, n2 = e % fx.L2;
+            const int k1 = s0 + seg / 2;
+            const int kr = (seg & 1) ? ((fx.L1 - k1) & (fx.L1 - 1)) : k1;
+            lds[seg * stride + bitrev((uint32_t)n2, fx.lg2)] = ldc2(&w[(size_t)fx.L2 * kr + n2]);
+        }
+        fft_lds_multi(lds, fx.lg2, 2 * ns, stride, fx.tw, fx.L1, false);
+        float2 *o0 = a.fft_a + (size_t)r0 * fx.H, *o1 = o0 + fx.H;
+        for (int e = threadIdx.x; e < 2 * ns * (hq + 1); e += WG) {
+            const int seg = e / (hq + 1), k2 = e % (hq + 1);
+            const int k1 = s0 + seg / 2;
+            const bool second = seg & 1;
+            if (second && (k1 == 0 || 2 * k1 == fx.L1)) continue;      // row is its own mirror
+            const int kr = second ? fx.L1 - k1 : k1;
+            if (k2 == hq && kr != 0) continue;                          // only row 0 carries k2 = L2/2
+            int q1, q2;
+            mirror_of(fx, kr, k2, q1, q2);
+            const int qs = q1 == kr ? seg : (seg ^ 1);
+            store_split(o0, o1, has1, chat_of(fx, kr, k2), lds[seg * stride + k2], lds[qs * stride + q2]);
+        }
+    }
+    if (!KSRC) {
+        const int total = s_off[a.T];
+        for (int i = blockIdx.x * WG + threadIdx.x; i < total; i += gridDim.x * WG) {
+            int lo = 0, hi = a.T;                   // largest t with s_off[t] <= i
+            while (hi - lo > 1) {
+                const int mid = (lo + hi) >> 1;
+                if (s_off[mid] <= i) lo = mid; else hi = mid;
+            }
+            stc(&a.comp_img[ldc(&a.ag_pos[(size_t)lo * a.interval + (i - s_off[lo])])], 0.0f);
+        }
+    }
+}
+
+// y, one level, per carried column: forward transform of the `rows` values
+// in fft_b; then either (PRE) store the spectrum as the PSF kernel's, or
+// multiply by it, transform back and store the first `rows` values.
+template <bool PRE>
+__device__ void ycol_one(const KArgs &a, const FftAxis &fx, const FftAxis &fy, int rows, float2 *lds)
+{
+    for (int col = blockIdx.x; col < fx.H; col += gridDim.x) {
+        for (int v = threadIdx.x; v < fy.L; v += WG) lds[v] = make_float2(0.f, 0.f);
+        __syncthreads();
+        float2 *b = a.fft_b + (size_t)col * rows;
+        for (int v = threadIdx.x; v < rows; v += WG) lds[bitrev((uint32_t)v, fy.lg)] = ldc2(&b[v]);
+        fft_lds(lds, fy.lg, fy.tw, false);
+        float2 *ks = a.fft_ks + (size_t)col * fy.L;
+        if (PRE) {
+            for (int v = threadIdx.x; v < fy.L; v += WG) stc2(&ks[v], lds[v]);
+        } else {
+            for (int v = threadIdx.x; v < fy.L; v += WG) lds[v] = cmul(lds[v], ldc2(&ks[v]));
+            bitrev_permute(lds, fy.lg);
+            fft_lds(lds, fy.lg, fy.tw, true);
+            for (int v = threadIdx.x; v < rows; v += WG) stc2(&b[v], lds[v]);
+        }
+        __syncthreads();
+    }
+}
+
+// y, two levels, step 1: per carried column and n2, transforms of length L1
+// over n1 (input y = L2 n1 + n2 < rows), times W_L^(n2 k1), into
+// fft_wy[col][L2 k1 + n2].
+__device__ void ycol_two_a(const KArgs &a, const FftAxis &fx, const FftAxis &fy, int rows, float2 *lds)
+{
+    const int NB = min(fy.L2, 4096 >> fy.lg1);
+    const int nblk = fy.L2 / NB, stride = fy.L1 + 1;
+    for (int item = blockIdx.x; item < fx.H * nblk; item += gridDim.x) {
+        const int col = item / nblk, b = item % nblk;
+        const float2 *src = a.fft_b + (size_t)col * rows;
+        __syncthreads();
+        for (int e = threadIdx.x; e < NB * fy.L1; e += WG) {
+            const int j = e % NB, n1 = e / NB;
+            const int yy = fy.L2 * n1 + b * NB + j;
+            lds[j * stride + bitrev((uint32_t)n1, fy.lg1)] = yy < rows ? ldc2(&src[yy]) : make_float2(0.f, 0.f);
+        }
+        fft_lds_multi(lds, fy.lg1, NB, stride, fy.tw, fy.L2, false);
+        float2 *w = a.fft_wy + (size_t)col * fy.L;
+        for (int e = threadIdx.x; e < NB * fy.L1; e += WG) {
+            const int j = e % NB, k1 = e / NB, n2 = b * NB + j;
+            stc2(&w[(size_t)fy.L2 * k1 + n2], cmul(lds[j * stride + k1], fy.tw[n2 * k1]));
+        }
+    }
+}
+
+// y, two levels, step 2: per carried column and row k1 of the step-1 output,
+// transform over n2 (length L2); then either (PRE) store as the PSF kernel's
+// spectrum in (k1, k2) order, or multiply by it, transform back over k2,
+// times conj W_L^(n2 k1), into fft_wy.
+template <bool PRE>
+__device__ void ycol_two_b(const KArgs &a, const FftAxis &fx, const FftAxis &fy, float2 *lds)
+{
+    const int stride = fy.L2 + 1;
+    const int G = max(1, min(fy.L1, FFT_LDS_CPLX / stride));
+    const int nblk = (fy.L1 + G - 1) / G;
+    for (int item = blockIdx.x; item < fx.H * nblk; item += gridDim.x) {
+        const int col = item / nblk, k0 = (item % nblk) * G, ng = min(G, fy.L1 - k0);
+        float2 *w = a.fft_wy + (size_t)col * fy.L;
+        float2 *ks = a.fft_ks + (size_t)col * fy.L;
+        __syncthreads();
+        for (int e = threadIdx.x; e < ng * fy.L2; e += WG) {
+            const int g = e / fy.L2, n2 = e % fy.L2;
+            lds[g * stride + bitrev((uint32_t)n2, fy.lg2)] = ldc2(&w[(size_t)fy.L2 * (k0 + g) + n2]);
+        }
+        fft_lds_multi(lds, fy.lg2, ng, stride, fy.tw, fy.L1, false);
+        if (PRE) {
+            for (int e = threadIdx.x; e < ng * fy.L2; e += WG) {
+                const int g = e / fy.L2, k2 = e % fy.L2;
+                stc2(&ks[(size_t)fy.L2 * (k0 + g) + k2], lds[g * stride + k2]);
+            }
+            continue;
+        }
+        for (int e = threadIdx.x; e < ng * fy.L2; e += WG) {
+            const int g = e / fy.L2, k2 = e % fy.L2;
+            lds[g * stride + k2] = cmul(lds[g * stride + k2], ldc2(&ks[(size_t)fy.L2 * (k0 + g) + k2]));
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < ng * fy.L2; e += WG) {    // back to bit-reversed order
+            const int g = e / fy.L2, i = e % fy.L2;
+            const int j = (int)bitrev((uint32_t)i, fy.lg2);
+            if (i < j) {
+                const float2 t = lds[g * stride + i];
+                lds[g * stride + i] = lds[g * stride + j];
+                lds[g * stride + j] = t;
             }
         }
-        __syncthreads();
-    }
-    if (!grid_barrier(y, epoch, s_ok)) return false;
-    // (2) A[y][kx] -> B[kx][y]
-    transpose_tiles(a.fft_a, Hx, a.fft_b, ny, ny, Hx, blockIdx.x, gridDim.x, s_tr);
-    if (!grid_barrier(y, epoch, s_ok)) return false;
-    // (3) columns: forward transform over y, times K's spectrum, inverse transform
-    for (int col = blockIdx.x; col < Hx; col += gridDim.x) {
-        for (int v = threadIdx.x; v < Ly; v += WG) lds[v] = make_float2(0.f, 0.f);
-        __syncthreads();
-        for (int v = threadIdx.x; v < ny; v += WG) lds[bitrev((uint32_t)v, lgy)] = ldc2(&a.fft_b[(size_t)col * ny + v]);
-        fft_lds(lds, lgy, a.tw_y, false);
-        for (int v = threadIdx.x; v < Ly; v += WG) {
-            const float2 p = lds[v], q = a.fft_ks[(size_t)col * Ly + v];
-            lds[v] = make_float2(p.x * q.x - p.y * q.y, p.x * q.y + p.y * q.x);
+        fft_lds_multi(lds, fy.lg2, ng, stride, fy.tw, fy.L1, true);
+        for (int e = threadIdx.x; e < ng * fy.L2; e += WG) {
+            const int g = e / fy.L2, n2 = e % fy.L2, k1 = k0 + g;
+            stc2(&w[(size_t)fy.L2 * k1 + n2], cmulc(lds[g * stride + n2], fy.tw[n2 * k1]));
         }
-        bitrev_permute(lds, lgy);
-        fft_lds(lds, lgy, a.tw_y, true);
-        for (int v = threadIdx.x; v < ny; v += WG) stc2(&a.fft_b[(size_t)col * ny + v], lds[v]);
-        __syncthreads();
     }
-    if (!grid_barrier(y, epoch, s_ok)) return false;
-    // (4) B[kx][y] -> A[y][kx]
-    transpose_tiles(a.fft_b, ny, a.fft_a, Hx, Hx, ny, blockIdx.x, gridDim.x, s_tr);
-    if (!grid_barrier(y, epoch, s_ok)) return false;
-    // (5) row pairs: Z = A + iB over the full length, inverse transform;
-    // row 2m is the real part, row 2m+1 the imaginary part
-    const float scale = 1.0f / ((float)Lx * (float)Ly);
-    for (int pr = blockIdx.x; pr < npairs; pr += gridDim.x) {
+}
+
+// y, two levels, step 3: per carried column and n2, inverse transforms of
+// length L1 over k1, giving y = L2 n1 + n2; the first `rows` go to fft_b.
+__device__ void ycol_two_c(const KArgs &a, const FftAxis &fx, const FftAxis &fy, int rows, float2 *lds)
+{
+    const int NB = min(fy.L2, 4096 >> fy.lg1);
+    const int nblk = fy.L2 / NB, stride = fy.L1 + 1;
+    for (int item = blockIdx.x; item < fx.H * nblk; item += gridDim.x) {
+        const int col = item / nblk, b = item % nblk;
+        const float2 *w = a.fft_wy + (size_t)col * fy.L;
+        __syncthreads();
+        for (int e = threadIdx.x; e < NB * fy.L1; e += WG) {
+            const int j = e % NB, k1 = e / NB;
+            lds[j * stride + bitrev((uint32_t)k1, fy.lg1)] = ldc2(&w[(size_t)fy.L2 * k1 + b * NB + j]);
+        }
+        fft_lds_multi(lds, fy.lg1, NB, stride, fy.tw, fy.L2, true);
+        float2 *dst = a.fft_b + (size_t)col * rows;
+        for (int e = threadIdx.x; e < NB * fy.L1; e += WG) {
+            const int j = e % NB, n1 = e / NB;
+            const int yy = fy.L2 * n1 + b * NB + j;
+            if (yy < rows) stc2(&dst[yy], lds[j * stride + n1]);
+        }
+    }
+}
+
+// x inverse, one level: row pairs rebuilt from their carried bins (Hermitian
+// symmetry gives the rest), one inverse transform, real part -> row 2m,
+// imaginary part -> row 2m+1, scaled, into the feedback buffer.
+__device__ void xinv_one(const KArgs &a, const FftAxis &fx, float scale, float2 *lds)
+{
+    const int Lx = fx.L, lgx = fx.lg, ny = a.ny, nx = a.nx;
+    for (int pr = blockIdx.x; pr < (ny + 1) / 2; pr += gridDim.x) {
         const int r0 = 2 * pr;
         const bool has1 = r0 + 1 < ny;
-        const float2 *i0 = a.fft_a + (size_t)r0 * Hx, *i1 = i0 + Hx;
-        for (int k = threadIdx.x; k < Hx; k += WG) {
+        const float2 *i0 = a.fft_a + (size_t)r0 * fx.H, *i1 = i0 + fx.H;
+        for (int k = threadIdx.x; k < fx.H; k += WG) {
             const float2 A = ldc2(&i0[k]);
             const float2 B = has1 ? ldc2(&i1[k]) : make_float2(0.f, 0.f);
             lds[bitrev((uint32_t)k, lgx)] = make_float2(A.x - B.y, A.y + B.x);
             if (k > 0 && k < Lx / 2) lds[bitrev((uint32_t)(Lx - k), lgx)] = make_float2(A.x + B.y, B.x - A.y);
         }
-        fft_lds(lds, lgx, a.tw_x, true);
+        fft_lds(lds, lgx, fx.tw, true);
         for (int x = threadIdx.x; x < nx; x += WG) {
             const float2 z = lds[x];
             stc(&a.accbuf[(size_t)r0 * nx + x], z.x * scale);
@@ -815,59 +1062,155 @@ __device__ bool fft_feedback(const KArgs &a, const Sync &y, uint32_t &epoch, int
         }
         __syncthreads();
     }
+}
+
+// x inverse, two levels, step 1: per row pair and row k1, Z(k1, k2) for all
+// k2 from the carried bins (A + iB, or conj A + i conj B at mirrored bins),
+// inverse transform over k2 (length L2), times conj W_L^(n2 k1), into fft_wx.
+__device__ void xinv_two_a(const KArgs &a, const FftAxis &fx, float2 *lds)
+{
+    const int ny = a.ny, stride = fx.L2 + 1, hq = fx.L2 / 2;
+    const int G = max(1, min(fx.L1, FFT_LDS_CPLX / stride));
+    const int nblk = (fx.L1 + G - 1) / G;
+    for (int item = blockIdx.x; item < (ny + 1) / 2 * nblk; item += gridDim.x) {
+        const int pr = item / nblk, k0 = (item % nblk) * G, ng = min(G, fx.L1 - k0);
+        const int r0 = 2 * pr;
+        const bool has1 = r0 + 1 < ny;
+        const float2 *i0 = a.fft_a + (size_t)r0 * fx.H, *i1 = i0 + fx.H;
+        __syncthreads();
+        for (int e = threadIdx.x; e < ng * fx.L2; e += WG) {
+            const int g = e / fx.L2, k2 = e % fx.L2, k1 = k0 + g;
+            const bool carried = k2 < hq || (k2 == hq && k1 == 0);
+            int q1 = k1, q2 = k2;
+            if (!carried) mirror_of(fx, k1, k2, q1, q2);
+            const int c = chat_of(fx, q1, q2);
+            const float2 A = ldc2(&i0[c]);
+            const float2 B = has1 ? ldc2(&i1[c]) : make_float2(0.f, 0.f);
+            lds[g * stride + bitrev((uint32_t)k2, fx.lg2)] =
+                carried ? make_float2(A.x - B.y, A.y + B.x) : make_float2(A.x + B.y, B.x - A.y);
+        }
+        fft_lds_multi(lds, fx.lg2, ng, stride, fx.tw, fx.L1, true);
+        float2 *w = a.fft_wx + (size_t)pr * fx.L;
+        for (int e = threadIdx.x; e < ng * fx.L2; e += WG) {
+            const int g = e / fx.L2, n2 = e % fx.L2, k1 = k0 + g;
+            stc2(&w[(size_t)fx.L2 * k1 + n2], cmulc(lds[g * stride + n2], fx.tw[n2 * k1]));
+        }
+    }
+}
+
+// x inverse, two levels, step 2: per row pair and n2, inverse transforms of
+// length L1 over k1 giving x = L2 n1 + n2; real / imaginary parts of the
+// first nx, scaled, into the feedback buffer rows 2m / 2m+1.
+__device__ void xinv_two_b(const KArgs &a, const FftAxis &fx, float scale, float2 *lds)
+{
+    const int ny = a.ny, nx = a.nx;
+    const int NB = min(fx.L2, 4096 >> fx.lg1);
+    const int nblk = fx.L2 / NB, stride = fx.L1 + 1;
+    for (int item = blockIdx.x; item < (ny + 1) / 2 * nblk; item += gridDim.x) {
+        const int pr = item / nblk, b = item % nblk;
+        const int r0 = 2 * pr;
+        const bool has1 = r0 + 1 < ny;
+        const float2 *w = a.fft_wx + (size_t)pr * fx.L;
+        __syncthreads();
+        for (int e = threadIdx.x; e < NB * fx.L1; e += WG) {
+            const int j = e % NB, k1 = e / NB;
+            lds[j * stride + bitrev((uint32_t)k1, fx.lg1)] = ldc2(&w[(size_t)fx.L2 * k1 + b * NB + j]);
+        }
+        fft_lds_multi(lds, fx.lg1, NB, stride, fx.tw, fx.L2, true);
+        for (int e = threadIdx.x; e < NB * fx.L1; e += WG) {
+            const int j = e % NB, n1 = e / NB;
+            const int x = fx.L2 * n1 + b * NB + j;
+            if (x < nx) {
+                const float2 z = lds[j * stride + n1];
+                stc(&a.accbuf[(size_t)r0 * nx + x], z.x * scale);
+                if (has1) stc(&a.accbuf[(size_t)(r0 + 1) * nx + x], z.y * scale);
+            }
+        }
+    }
+}
+
+#define FFT_BARRIER() do { if (!grid_barrier(y, epoch, s_ok)) return false; } while (0)
+
+// The PSF kernel's spectrum, once per call, by the same transforms as the
+// rounds: x forward over all Ly rows of the kernel image, transpose, y forward.
+template <typename PT>
+__device__ bool fft_spectrum(const KArgs &a, const Sync &y, uint32_t &epoch, int *s_ok)
+{
+    extern __shared__ __align__(16) unsigned char s_dyn[];
+    __shared__ float2 s_tr[32][33];
+    __shared__ int s_nz;
+    float2 *lds = (float2 *)s_dyn;
+    const FftAxis fx = fft_axis(a.fft_lgx, a.fft_two_x, a.tw_x), fy = fft_axis(a.fft_lgy, a.fft_two_y, a.tw_y);
+    const int Ly = fy.L;
+    if (!fx.two) {
+        xfwd_one<PT, true>(a, fx, Ly, Ly, nullptr, lds, &s_nz);
+    } else {
+        xfwd_two_a<PT, true>(a, fx, Ly, Ly, lds);
+        FFT_BARRIER();
+        xfwd_two_b<true>(a, fx, Ly, lds, nullptr);
+    }
+    FFT_BARRIER();
+    transpose_tiles(a.fft_a, fx.H, a.fft_b, Ly, Ly, fx.H, blockIdx.x, gridDim.x, s_tr);
+    FFT_BARRIER();
+    if (!fy.two) {
+        ycol_one<true>(a, fx, fy, Ly, lds);
+    } else {
+        ycol_two_a(a, fx, fy, Ly, lds);
+        FFT_BARRIER();
+        ycol_two_b<true>(a, fx, fy, lds);
+    }
+    FFT_BARRIER();
     return true;
 }
 
-// ------------------------------------------ PSF kernel spectrum (once) --
-
-// Rows of K(d) = psf[centre + d] for |d| < (ny, nx), placed circularly on the
-// Ly x Lx grid, transformed along x into A.
+// One round's feedback sums: the component image (*) the PSF, every tile's
+// components, own tile included, into the feedback buffer.  The apply step
+// then recomputes the residual from the round's starting residual:
+// mathematically the paper's update (own components subtracted locally, the
+// others' by feedback), rounded once.
 template <typename PT>
-__global__ void __launch_bounds__(WG) fft_kernel_rows(const void *psf, int psf_nx, int cy, int cx, int ny, int nx,
-                                                      int lgx, int lgy, const float2 *tw_x, float2 *A)
+__device__ bool fft_feedback(const KArgs &a, const Sync &y, uint32_t &epoch, int *s_ok, const int32_t *s_off)
 {
     extern __shared__ __align__(16) unsigned char s_dyn[];
-    float2 *lds = (float2 *)s_dyn;
-    const int Lx = 1 << lgx, Ly = 1 << lgy;
-    const PT *p = (const PT *)psf;
-    for (int row = blockIdx.x; row < Ly; row += gridDim.x) {
-        const int dy = row < ny ? row : row - Ly;
-        const bool vy = dy > -ny && dy < ny;
-        for (int x = threadIdx.x; x < Lx; x += WG) {
-            const int dx = x < nx ? x : x - Lx;
-            float v = 0.0f;
-            if (vy && dx > -nx && dx < nx) v = (float)p[(int64_t)(cy + dy) * psf_nx + (cx + dx)];
-            lds[bitrev((uint32_t)x, lgx)] = make_float2(v, 0.f);
-        }
-        fft_lds(lds, lgx, tw_x, false);
-        for (int x = threadIdx.x; x < Lx; x += WG) A[(size_t)row * Lx + x] = lds[x];
-        __syncthreads();
-    }
-}
-
-__global__ void __launch_bounds__(WG) fft_transpose_kernel(const float2 *src, int ss, float2 *dst, int ds, int rows,
-                                                           int cols)
-{
     __shared__ float2 s_tr[32][33];
-    transpose_tiles(src, ss, dst, ds, rows, cols, blockIdx.x, gridDim.x, s_tr);
-}
-
-// In-place forward transforms of `rows` rows of length 2^lg.
-__global__ void __launch_bounds__(WG) fft_rows_kernel(float2 *X, int rows, int lg, const float2 *tw)
-{
-    extern __shared__ __align__(16) unsigned char s_dyn[];
+    __shared__ int s_nz;
     float2 *lds = (float2 *)s_dyn;
-    const int L = 1 << lg;
-    for (int row = blockIdx.x; row < rows; row += gridDim.x) {
-        for (int v = threadIdx.x; v < L; v += WG) lds[bitrev((uint32_t)v, lg)] = X[(size_t)row * L + v];
-        fft_lds(lds, lg, tw, false);
-        for (int v = threadIdx.x; v < L; v += WG) X[(size_t)row * L + v] = lds[v];
-        __syncthreads();
+    const FftAxis fx = fft_axis(a.fft_lgx, a.fft_two_x, a.tw_x), fy = fft_axis(a.fft_lgy, a.fft_two_y, a.tw_y);
+    const int ny = a.ny;
+    const float scale = 1.0f / ((float)fx.L * (float)fy.L);
+    if (!fx.two) {
+        xfwd_one<PT, false>(a, fx, fy.L, ny, s_off, lds, &s_nz);
+    } else {
+        xfwd_two_a<PT, false>(a, fx, fy.L, ny, lds);
+        FFT_BARRIER();
+        xfwd_two_b<false>(a, fx, ny, lds, s_off);
     }
+    FFT_BARRIER();
+    transpose_tiles(a.fft_a, fx.H, a.fft_b, ny, ny, fx.H, blockIdx.x, gridDim.x, s_tr);
+    FFT_BARRIER();
+    if (!fy.two) {
+        ycol_one<false>(a, fx, fy, ny, lds);
+    } else {
+        ycol_two_a(a, fx, fy, ny, lds);
+        FFT_BARRIER();
+        ycol_two_b<false>(a, fx, fy, lds);
+        FFT_BARRIER();
+        ycol_two_c(a, fx, fy, ny, lds);
+    }
+    FFT_BARRIER();
+    transpose_tiles(a.fft_b, ny, a.fft_a, fx.H, fx.H, ny, blockIdx.x, gridDim.x, s_tr);
+    FFT_BARRIER();
+    if (!fx.two) {
+        xinv_one(a, fx, scale, lds);
+    } else {
+        xinv_two_a(a, fx, lds);
+        FFT_BARRIER();
+        xinv_two_b(a, fx, scale, lds);
+    }
+    return true;
 }
 
-template __global__ void fft_kernel_rows<float>(const void *, int, int, int, int, int, int, int, const float2 *, float2 *);
-template __global__ void fft_kernel_rows<__half>(const void *, int, int, int, int, int, int, int, const float2 *, float2 *);
+#undef FFT_BARRIER
 
 // ------------------------------------------------------ tiled kernel -----
 
@@ -910,6 +1253,7 @@ __device__ void aggregate_round(const KArgs &a, int t, int L, int32_t *l_idx, fl
         for (int k = 0; k < L; ++k) rk += (l_tmp[k] != 0) & (l_idx[k] < q);
         stc(&a.ag_pos[base + rk], q);
         stc(&a.ag_flux[base + rk], l_sum[j]);
+        if (a.comp_img) stc(&a.comp_img[q], l_sum[j]);
     }
     if (threadIdx.x == 0) *s_cnt = 0;
     __syncthreads();
@@ -977,6 +1321,7 @@ template <class Tile> __global__ void __launch_bounds__(WG) tiled_kernel(const K
         if (tile_leader_wg && threadIdx.x == 0) stc(&a.tile_key[tile], cur);
     }
     if (!grid_barrier(y, epoch, &s_ok)) return;
+    if (a.fft_lgx && !fft_spectrum<PT>(a, y, epoch, &s_ok)) return;
 
     const int64_t limit = a.max_iter < a.cap ? a.max_iter : a.cap;
     int64_t used = 0;
@@ -1082,7 +1427,7 @@ template <class Tile> __global__ void __launch_bounds__(WG) tiled_kernel(const K
 
         // ---- feedback by FFT: acc = (component image (*) K) - own tile's part
         if (a.fft_lgx) {
-            if (!fft_feedback(a, y, epoch, &s_ok, s_off)) return;
+            if (!fft_feedback<PT>(a, y, epoch, &s_ok, s_off)) return;
         } else
         // ---- feedback gather: acc[q] = sum over other tiles' components
         {

@@ -51,6 +51,32 @@ except ImportError:  # pragma: no cover
 
 SEED_ROOT = 1461
 
+# Grids at least this large take their float64 FFTs on a torch device when the
+# caller names one (the 32768^2 PSF of the 16384^2 workload needs ~60 GB and
+# minutes on the host); smaller ones always use the host FFT above.
+DEVICE_FFT_MIN = 16384
+
+
+def _dev_irfft2_half(half: np.ndarray, M: int, device) -> np.ndarray:
+    """irfft2 of a real, Hermitian-symmetric grid given by its first M/2+1 columns, on `device`."""
+    import torch
+    t = torch.from_numpy(np.ascontiguousarray(half)).to(device).to(torch.complex128)
+    out = torch.fft.irfft2(t, s=(M, M))
+    del t
+    return out
+
+
+def _dev_convolve(grid: np.ndarray, psf: np.ndarray, n_y: int, n_x: int, device) -> np.ndarray:
+    import torch
+    g = torch.fft.rfft2(torch.from_numpy(grid).to(device))
+    k = torch.fft.rfft2(torch.fft.ifftshift(torch.from_numpy(psf).to(device).to(torch.float64)))
+    g *= k
+    del k
+    out = torch.fft.irfft2(g, s=grid.shape)[:n_y, :n_x].cpu().numpy()
+    del g
+    torch.cuda.empty_cache()
+    return out
+
 
 def streams(config: int, problem: int = 0, n: int = 5):
     """Independent child generators for one (config, problem) pair.
@@ -73,11 +99,14 @@ def y_array_positions(n_per_arm: int = 9, exponent: float = 1.7) -> np.ndarray:
 
 
 def y_array_psf(M: int, rng: np.random.Generator, n_samples: int = 1,
-                track_rad: float = 0.0, uv_fill: float = 0.25) -> np.ndarray:
+                track_rad: float = 0.0, uv_fill: float = 0.25, device=None) -> np.ndarray:
     """Y-array PSF on an M x M grid, peak exactly 1.0 at (M//2, M//2).
 
     n_samples == 1 is a snapshot at one seeded hour angle; n_samples > 1 spreads
-    the samples evenly over track_rad radians starting at that angle.
+    the samples evenly over track_rad radians starting at that angle.  With a
+    torch `device` and M >= DEVICE_FFT_MIN the inverse FFT runs there (float64;
+    the result agrees with the host FFT to rounding) and a float32 array is
+    returned.
     """
     if M < 4 or M % 2:
         raise ValueError("PSF side must be even and >= 4")
@@ -101,6 +130,16 @@ def y_array_psf(M: int, rng: np.random.Generator, n_samples: int = 1,
         np.add.at(grid, ((-iv) % M, (-iu) % M), 1.0)
     # the grid is real and symmetric under (u, v) -> (-u, -v), so its inverse
     # FFT is real: take it from the half spectrum
+    if device is not None and M >= DEVICE_FFT_MIN:
+        import torch
+        img = _dev_irfft2_half(grid[:, :M // 2 + 1], M, device)
+        del grid
+        img = torch.fft.fftshift(img)
+        img /= img[M // 2, M // 2].clone()
+        out = img.to(torch.float32).cpu().numpy()
+        del img
+        torch.cuda.empty_cache()
+        return out
     img = _irfft2(grid[:, :M // 2 + 1], s=(M, M))
     img = np.fft.fftshift(img)
     img /= img[M // 2, M // 2]
@@ -128,8 +167,10 @@ def sky(n_y: int, n_x: int, n_src: int, lo: float, hi: float,
     return idx, flux
 
 
-def convolve_sky(n_y: int, n_x: int, idx: np.ndarray, flux: np.ndarray, psf: np.ndarray) -> np.ndarray:
-    """dirty[q] = sum_p flux_p * psf[q - p + centre] in float64, via FFT.
+def convolve_sky(n_y: int, n_x: int, idx: np.ndarray, flux: np.ndarray, psf: np.ndarray,
+                 device=None) -> np.ndarray:
+    """dirty[q] = sum_p flux_p * psf[q - p + centre] in float64, via FFT
+    (on a torch `device` for grids of DEVICE_FFT_MIN and up when one is named).
 
     The PSF must be at least twice the image on each axis, so no index wraps.
     """
@@ -138,14 +179,16 @@ def convolve_sky(n_y: int, n_x: int, idx: np.ndarray, flux: np.ndarray, psf: np.
         raise ValueError("PSF must be at least twice the image size")
     grid = np.zeros((M_y, M_x), dtype=np.float64)
     np.add.at(grid, (idx // n_x, idx % n_x), flux)
+    if device is not None and min(M_y, M_x) >= DEVICE_FFT_MIN:
+        return _dev_convolve(grid, psf, n_y, n_x, device)
     kern = np.fft.ifftshift(psf.astype(np.float64))     # centre moved to (0, 0)
     out = _irfft2(_rfft2(grid) * _rfft2(kern), s=(M_y, M_x))
     return out[:n_y, :n_x]
 
 
 def dirty_image(n_y: int, n_x: int, psf: np.ndarray, idx, flux, sigma: float,
-                rng_noise: np.random.Generator) -> np.ndarray:
-    d = convolve_sky(n_y, n_x, idx, flux, psf)
+                rng_noise: np.random.Generator, device=None) -> np.ndarray:
+    d = convolve_sky(n_y, n_x, idx, flux, psf, device)
     if sigma > 0:
         d = d + rng_noise.normal(0.0, sigma, size=d.shape)
     return d
@@ -173,27 +216,34 @@ BATCH_SIDES = (128, 192, 256, 384, 512, 768, 1024)
 
 def make_problem(n: int, n_src: int, lo: float, hi: float, extra, sigma: float,
                  config: int, problem: int = 0, psf_track: bool = False,
-                 psf_factor: int = 2) -> tuple[np.ndarray, np.ndarray, dict]:
+                 psf_factor: int = 2, device=None) -> tuple[np.ndarray, np.ndarray, dict]:
     """(dirty float32 [n, n], psf float32 [psf_factor*n]^2, info)."""
     r_ha, r_pos, r_flux, r_noise, _ = streams(config, problem)
     M = psf_factor * n
     if psf_track:
-        psf = y_array_psf(M, r_ha, n_samples=6, track_rad=np.deg2rad(2.5))
+        psf = y_array_psf(M, r_ha, n_samples=6, track_rad=np.deg2rad(2.5), device=device)
     else:
-        psf = y_array_psf(M, r_ha)
-    psf32 = psf.astype(np.float32)
+        psf = y_array_psf(M, r_ha, device=device)
+    psf32 = psf.astype(np.float32, copy=False)
+    del psf
     idx, flux = sky(n, n, n_src, lo, hi, r_pos, r_flux, extra)
     # the dirty image is made with the float32-stored PSF, the one CLEAN sees
-    d = dirty_image(n, n, psf32.astype(np.float64), idx, flux, sigma, r_noise)
+    if device is not None and M >= DEVICE_FFT_MIN:
+        d = dirty_image(n, n, psf32, idx, flux, sigma, r_noise, device)
+    else:
+        d = dirty_image(n, n, psf32.astype(np.float64), idx, flux, sigma, r_noise)
     info = dict(src_idx=idx, src_flux=flux, brightest=float(flux.max()))
     return d.astype(np.float32), psf32, info
 
 
-def make_config(k: int, psf_track: bool = False):
-    """Inputs and parameters of one of the single-image workloads (0, 1, 2, 4)."""
+def make_config(k: int, psf_track: bool = False, device=None):
+    """Inputs and parameters of one of the single-image workloads (0, 1, 2, 4).
+
+    `device` (a torch device) only matters for workload 4, whose float64 FFTs
+    then run there."""
     c = dict(CONFIGS[k])
     dirty, psf, info = make_problem(c["n"], c["n_src"], c["lo"], c["hi"], c["extra"], c["sigma"],
-                                    config=k, psf_track=psf_track)
+                                    config=k, psf_track=psf_track, device=device)
     c.update(dirty=dirty, psf=psf, info=info)
     return c
 

@@ -79,7 +79,7 @@ def test_plain_argument_errors(lib, kw, code):
     (dict(ty=0), INVAL), (dict(tx=17), INVAL), (dict(interval=0), INVAL), (dict(interval=2049), INVAL),
     (dict(ty=40, tx=40, ny=64, nx=64), UNSUPPORTED), (dict(p=params(feedback_level=1.5)), INVAL),
     (dict(p=params(feedback_level=-0.1)), INVAL),
-    (dict(ny=4097, nx=64, p=params(flags=N.FLAG_FFT_FEEDBACK)), UNSUPPORTED),
+    (dict(ny=40000, nx=16, p=params(flags=N.FLAG_FFT_FEEDBACK)), UNSUPPORTED),   # transforms > 65536
 ])
 def test_tiled_argument_errors(lib, kw, code):
     assert tiled(lib, **kw) == code
@@ -111,10 +111,14 @@ def test_workspace_size(lib):
     assert a > 4 * 1024 * 1024 > 0 and b > 0
     assert lib.clean_workspace_size(1024, 1024, 0, 2, 100, C.byref(p)) == 0
     assert lib.clean_workspace_size(1024, 1024, 2, 2, 0, C.byref(p)) == 0
-    # FFT feedback adds three complex 2048 x 2048-class buffers
+    # FFT feedback: carried-bin buffers (2048 rows x 1025 bins, twice), the PSF
+    # spectrum (1025 x 2048), the round-start residual; two levels add work buffers
     f = params(flags=N.FLAG_FFT_FEEDBACK)
-    assert lib.clean_workspace_size(1024, 1024, 2, 2, 100, C.byref(f)) >= a + (2 * 2048 * 2048 + 2048 * 1024) * 8
-    assert lib.clean_workspace_size(8192, 64, 2, 2, 100, C.byref(f)) == 0
+    fa = lib.clean_workspace_size(1024, 1024, 2, 2, 100, C.byref(f))
+    assert fa >= a + 3 * 2048 * 1025 * 8 + 1024 * 1024 * 4
+    f2 = params(flags=N.FLAG_FFT_FEEDBACK | N.FLAG_FFT_TWO_LEVEL)
+    assert lib.clean_workspace_size(1024, 1024, 2, 2, 100, C.byref(f2)) >= fa + 2 * 1025 * 2048 * 8
+    assert lib.clean_workspace_size(40000, 16, 2, 2, 100, C.byref(f)) == 0
 
 
 def test_psf_to_f16_argument_errors(lib):

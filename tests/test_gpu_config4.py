@@ -1,0 +1,124 @@
+"""Full-size parity of the 16384^2 workload: 32768^2 Y-array PSF, 16x16 tiles,
+20005 sources, gain 0.1, threshold 5 mJy, 10^6 iterations, feedback by FFT
+(the x and y transforms take two levels at this size; the direct gather would
+read ~1 GiB of PSF per component per round).
+
+The oracle cannot run this whole job, so the checks are the properties it can
+compute at any size:
+
+* round 1 of every tile is bit-exact against the plain oracle run on that
+  tile's crop (with the PSF cropped about its centre): one round of the tiled
+  form is plain CLEAN restricted to the tile, a property the CPU pins check
+  on small inputs;
+* the invariant residual = dirty - components (*) PSF holds at sampled pixels
+  (float64, one component at a time), to the accumulated FFT tolerance;
+* the run ends as the stop rules say.
+"""
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2501_01461_amd import synth
+from tests import fft_tol
+from tests.gpu_util import announce, bits, dev, host
+
+pytestmark = pytest.mark.gpu
+
+U = fft_tol.U32
+TILES = (16, 16)
+INTERVAL = 100
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    import paper_2501_01461_amd as P
+    P.load()
+    return P
+
+
+@pytest.fixture(scope="module")
+def run4(lib):
+    announce("config4: generating inputs")
+    t0 = time.time()
+    c = synth.make_config(4, device="cuda")
+    announce(f"config4: inputs in {time.time() - t0:.1f} s; running the GPU")
+    d, p = dev(c["dirty"]), dev(c["psf"])
+    out = lib.tiled_feedback(d, p, TILES, INTERVAL, c["gain"], c["threshold"], c["max_iter"], model=False, fft=True)
+    st = out["stats"]
+    announce(f"config4: {st['n_iter']} iterations, {st['n_rounds']} rounds, stop {st['stop_reason']}, "
+             f"{st['device_ms']:.1f} ms, phases {st['phase_us']}")
+    res = dict(c=c, stats=st, idx=host(out["idx"]), flux=host(out["flux"]), residual=host(out["residual"]))
+    del d, p, out
+    import torch
+    torch.cuda.empty_cache()
+    return res
+
+
+def test_config4_first_round_per_tile(run4):
+    c = run4["c"]
+    dirty, psf = c["dirty"], c["psf"]
+    n = dirty.shape[0]
+    cy, cx = psf.shape[0] // 2, psf.shape[1] // 2
+    exp_idx, exp_flux = [], []
+    t0 = time.time()
+    for i in range(TILES[0]):
+        y0, y1 = i * n // TILES[0], (i + 1) * n // TILES[0]
+        for j in range(TILES[1]):
+            x0, x1 = j * n // TILES[1], (j + 1) * n // TILES[1]
+            h, w = y1 - y0, x1 - x0
+            crop = np.ascontiguousarray(dirty[y0:y1, x0:x1])
+            pc = np.ascontiguousarray(psf[cy - h:cy + h, cx - w:cx + w])
+            r = oracle.hogbom(crop, pc, c["gain"], c["threshold"], INTERVAL, model=False)
+            ly, lx = np.divmod(r["idx"].astype(np.int64), w)
+            exp_idx.append(((y0 + ly) * n + (x0 + lx)).astype(np.int32))
+            exp_flux.append(r["flux"])
+    exp_idx, exp_flux = np.concatenate(exp_idx), np.concatenate(exp_flux)
+    announce(f"config4: oracle round 1 ({len(exp_idx)} components) in {time.time() - t0:.1f} s")
+    k = len(exp_idx)
+    assert len(run4["idx"]) >= k
+    assert np.array_equal(run4["idx"][:k], exp_idx)
+    assert np.array_equal(bits(run4["flux"][:k]), bits(exp_flux))
+
+
+def test_config4_invariant_at_sampled_pixels(run4):
+    c = run4["c"]
+    dirty, psf = c["dirty"], c["psf"]
+    n = dirty.shape[0]
+    cy, cx = psf.shape[0] // 2, psf.shape[1] // 2
+    idx, flux, res = run4["idx"], run4["flux"], run4["residual"]
+    py, px = np.divmod(idx.astype(np.int64), n)
+    f64 = flux.astype(np.float64)
+    r = np.random.default_rng([1461, 4, 77])
+    sample = np.concatenate([r.integers(0, n * n, 96),
+                             np.argsort(np.abs(dirty).ravel())[-32:]])
+    R = run4["stats"]["n_rounds"]
+    lg = sum(fft_tol.fft_sizes(n, n))
+    rmax = 2 * max(float(np.abs(dirty).max()), float(np.abs(res).max()))
+    # per round the transforms err by <= 2 u log2(N) max|c_R (*) K|, and
+    # max|c_R (*) K| <= sum_R |f| max|K| (the PSF peak is 1); each round's
+    # update rounds once more
+    kmax = float(np.abs(psf).max())
+    tol = 2 * U * lg * float(np.abs(f64).sum()) * kmax + (R + 1) * 2 * U * rmax
+    worst = 0.0
+    for q in sample:
+        qy, qx = divmod(int(q), n)
+        pv = psf[cy + qy - py, cx + qx - px].astype(np.float64)
+        exact = float(dirty[qy, qx]) - float(np.dot(f64, pv))
+        worst = max(worst, abs(float(res[qy, qx]) - exact))
+    announce(f"config4: invariant max error {worst:.3e} over {len(sample)} pixels, tolerance {tol:.3e}")
+    assert worst <= tol
+
+
+def test_config4_stop_rule(run4):
+    c, st = run4["c"], run4["stats"]
+    if st["stop_reason"] == 0:
+        assert st["n_iter"] == c["max_iter"]
+    else:
+        assert st["stop_reason"] == 1
+        assert float(np.abs(run4["residual"]).max()) < c["threshold"]
+    assert len(run4["idx"]) == st["n_iter"]

@@ -88,29 +88,33 @@ ONE_ROUND = [
 ]
 
 
+@pytest.mark.parametrize("two", [False, True], ids=["one-level", "two-level"])
 @pytest.mark.parametrize("case", ONE_ROUND, ids=[f"{c[0]}x{c[1]}-{c[2][0]}x{c[2][1]}-I{c[3]}" + ("-stream" if c[5] else "")
                                                   + ("-f16" if c[6] else "") for c in ONE_ROUND])
-def test_fft_one_round_small(lib, case):
+def test_fft_one_round_small(lib, case, two):
     import torch
     ny, nx, tiles, interval, seed, stream, f16 = case
-    announce("fft one round", case)
+    announce("fft one round", case, "two-level" if two else "one-level")
     dirty = sparse_dirty(ny, nx, seed)
     psf = asym_psf(2 * ny, 2 * nx + 2, seed)
     n = tiles[0] * tiles[1] * interval
     psf_ref = psf.astype(np.float16).astype(np.float32) if f16 else psf
     ref = oracle.tiled(dirty, psf_ref, tiles, interval, 0.1, 0.0, n)
     dpsf = dev(psf).to(torch.float16) if f16 else dev(psf)
-    out = lib.tiled_feedback(dev(dirty), dpsf, tiles, interval, 0.1, 0.0, n, stream=stream, fft=True)
+    out = lib.tiled_feedback(dev(dirty), dpsf, tiles, interval, 0.1, 0.0, n, stream=stream, fft=True,
+                             fft_two_level=two)
     check_one_round(out, ref, psf_ref, tiles, dirty)
 
 
-def test_fft_one_round_config1(lib):
+@pytest.mark.parametrize("two", [False, True], ids=["one-level", "two-level"])
+def test_fft_one_round_config1(lib, two):
     """1024^2 image, 2048^2 snapshot PSF, 2x2 tiles, interval 100: one round (400 components)."""
-    announce("fft one round config1")
+    announce("fft one round config1", "two-level" if two else "one-level")
     c = synth.make_config(1)
     n = 4 * c["interval"]
     ref = oracle.tiled(c["dirty"], c["psf"], c["tiles"], c["interval"], 0.1, 0.0, n)
-    out = lib.tiled_feedback(dev(c["dirty"]), dev(c["psf"]), c["tiles"], c["interval"], 0.1, 0.0, n, fft=True)
+    out = lib.tiled_feedback(dev(c["dirty"]), dev(c["psf"]), c["tiles"], c["interval"], 0.1, 0.0, n, fft=True,
+                             fft_two_level=two)
     check_one_round(out, ref, c["psf"], c["tiles"], c["dirty"])
 
 
@@ -201,15 +205,17 @@ MANY = [
 ]
 
 
+@pytest.mark.parametrize("two", [False, True], ids=["one-level", "two-level"])
 @pytest.mark.parametrize("case", MANY, ids=[f"{c[0]}x{c[1]}-{c[2][0]}x{c[2][1]}-I{c[3]}-f{c[6]}"
                                              + ("-stream" if c[7] else "") for c in MANY])
-def test_fft_many_rounds_small(lib, case):
+def test_fft_many_rounds_small(lib, case, two):
     ny, nx, tiles, interval, seed, n, level, stream = case
-    announce("fft many rounds", case)
+    announce("fft many rounds", case, "two-level" if two else "one-level")
     dirty = sparse_dirty(ny, nx, seed)
     psf = asym_psf(2 * ny, 2 * nx + 2, seed)
     ref = oracle.tiled(dirty, psf, tiles, interval, 0.1, 0.0, n, level=level)
-    out = lib.tiled_feedback(dev(dirty), dev(psf), tiles, interval, 0.1, 0.0, n, level=level, stream=stream, fft=True)
+    out = lib.tiled_feedback(dev(dirty), dev(psf), tiles, interval, 0.1, 0.0, n, level=level, stream=stream, fft=True,
+                             fft_two_level=two)
     check_many_rounds(out, ref, dirty, psf, tiles, interval)
 
 
