@@ -162,6 +162,18 @@ def main():
         return r, wall / args.steps * 1e3, float(np.mean(dev_ms))
 
     rt, ms_t, kms_t = timed(tiled, "tiled")
+    # the interval tuner on this input and on its 10-minute-track variant
+    tuner = {}
+    for nm, cfg_psf in (("snapshot", psf), ("track", None)):
+        if cfg_psf is None:
+            ct = synth.make_config(1, psf_track=True)
+            d_t, p_t = torch.from_numpy(ct["dirty"]).to(dev), torch.from_numpy(ct["psf"]).to(dev)
+        else:
+            d_t, p_t = dirty, cfg_psf
+        cands = [10, 25, 50, 100]
+        tr = P.autotune_interval(d_t, p_t, tiles, cands, gain, thr, n_iter, trial_iter=n_iter)
+        tuner[nm] = {"candidates": cands, "chosen": tr["interval"], "peak_ratio": tr["peak_ratios"],
+                     "iters_per_s": tr["rates"]}
     rf = P.tiled_feedback(dirty, psf, tiles, interval, gain, thr, n_iter, fft=True)
     tiled_fft = {"kernel_ms": rf["stats"]["device_ms"], "n_rounds": rf["stats"]["n_rounds"],
                  "phase_us": rf["stats"]["phase_us"],
@@ -343,6 +355,7 @@ def main():
                   "achieved_GBs": gbs_p, "frac_hbm": gbs_p / HBM_PEAK_GBS,
                   "launch": {"wg_per_tile": st_p["wg_per_tile"], "px_per_thread": st_p["px_per_thread"]}},
         "tiled_fft_feedback": tiled_fft,
+        "interval_tuner": tuner,
         "speedup_tiled_vs_plain": ms_p / ms_t,
         "batched": batched,
         "tiled_4096": big,

@@ -95,12 +95,12 @@ enum {
                                       (3 Hx R + Hx Ly) * 8 + ny nx * 4 bytes,
                                       Lx, Ly the powers of two >= 2 nx - 1,
                                       2 ny - 1, Hx = Lx/2 + 1, R = max(ny, Ly);
-                                      axes longer than 8192 points add two-level
+                                      axes longer than 4096 points add two-level
                                       work buffers (clean_workspace_size)      */
     CLEAN_FLAG_FFT_TWO_LEVEL = 8   /* with CLEAN_FLAG_FFT_FEEDBACK: use the
                                       two-level (four-step) transforms on every
                                       axis of length >= 4, as they are used
-                                      automatically above 8192 points (slower;
+                                      automatically above 4096 points (slower;
                                       for testing that path at small sizes)    */
 };
 
@@ -250,6 +250,30 @@ int clean_autotune(const float *dirty, int ny, int nx, const void *psf, int psf_
                    int tiles_y, int tiles_x, int feedback_interval, const clean_params *p,
                    float *residual, int32_t *comp_idx, float *comp_flux, int64_t comp_cap,
                    int64_t trial_iter, clean_params *best, void *stream);
+
+/*
+ * clean_autotune_interval -- picks the feedback interval of
+ * clean_tiled_feedback among `candidates` (n_candidates in 1..64, each in
+ * 1..2048).  Unlike the launch shape, the interval changes the result (the
+ * tiles run longer between feedback rounds), and with a PSF of high
+ * sidelobes a long interval can make the method diverge.  Each candidate gets
+ * a trial run of min(trial_iter, p->max_iter) total iterations on the
+ * caller's buffers (p's flags, trigger level and launch shape apply).  A
+ * candidate is acceptable when the trial's residual stays finite and its
+ * final peak |residual| is at most growth_limit times the dirty image's peak;
+ * the acceptable candidate with the highest iteration rate is written to
+ * *interval, or 0 when none is acceptable (status still CLEAN_OK).
+ * rate_out / peak_ratio_out (host, n_candidates, may be NULL) receive each
+ * trial's iterations per second and final-peak / dirty-peak ratio.  The
+ * residual and component arrays are overwritten by the trials.  Errors:
+ * CLEAN_E_INVAL for a NULL p or interval, bad candidates, a 1x1 grid,
+ * trial_iter < 1 or growth_limit <= 0; otherwise as clean_tiled_feedback.
+ */
+int clean_autotune_interval(const float *dirty, int ny, int nx, const void *psf, int psf_ny, int psf_nx,
+                            int tiles_y, int tiles_x, const int *candidates, int n_candidates,
+                            const clean_params *p, int64_t trial_iter, double growth_limit,
+                            float *residual, int32_t *comp_idx, float *comp_flux, int64_t comp_cap,
+                            int *interval, double *rate_out, double *peak_ratio_out, void *stream);
 
 /* Bytes of device workspace clean_hogbom (tiles 1x1) or clean_tiled_feedback
  * needs for this shape; 0 on invalid arguments. */

@@ -24,8 +24,8 @@ FLAG_FFT_FEEDBACK = 4
 FLAG_FFT_TWO_LEVEL = 8
 
 # every symbol include/clean.h declares
-EXPORTS = ("clean_hogbom", "clean_tiled_feedback", "clean_batched", "clean_autotune", "clean_workspace_size",
-           "clean_psf_to_f16", "clean_strerror", "clean_last_error", "clean_version")
+EXPORTS = ("clean_hogbom", "clean_tiled_feedback", "clean_batched", "clean_autotune", "clean_autotune_interval",
+           "clean_workspace_size", "clean_psf_to_f16", "clean_strerror", "clean_last_error", "clean_version")
 
 
 class Params(C.Structure):
@@ -79,6 +79,9 @@ def load():
     lib.clean_autotune.argtypes = [P, i32, i32, P, i32, i32, i32, i32, i32, C.POINTER(Params), P, P, P, i64, i64,
                                    C.POINTER(Params), P]
     lib.clean_autotune.restype = C.c_int
+    lib.clean_autotune_interval.argtypes = [P, i32, i32, P, i32, i32, i32, i32, P, i32, C.POINTER(Params), i64,
+                                            C.c_double, P, P, P, i64, C.POINTER(C.c_int), P, P, P]
+    lib.clean_autotune_interval.restype = C.c_int
     lib.clean_workspace_size.argtypes = [i32, i32, i32, i32, i32, C.POINTER(Params)]
     lib.clean_workspace_size.restype = sz
     lib.clean_psf_to_f16.argtypes = [P, P, i64, P]
@@ -247,6 +250,32 @@ def autotune(dirty, psf, tiles=(1, 1), interval=100, gain=0.1, threshold=0.0, ma
                               int(tiles[1]), int(interval), C.byref(p), _ptr(res), _ptr(idx), _ptr(flux), cap,
                               int(trial_iter), C.byref(best), _stream()))
     return dict(wg_per_tile=best.wg_per_tile, px_per_thread=best.px_per_thread)
+
+
+def autotune_interval(dirty, psf, tiles, candidates, gain=0.1, threshold=0.0, max_iter=1000, trial_iter=2000,
+                      growth_limit=1.0, level=0.0, fft=False, stream=False):
+    """The feedback interval the library's tuner picks among `candidates`:
+    the fastest whose trial run keeps the residual finite and its peak within
+    growth_limit x the dirty peak.  Returns dict(interval (0: none
+    acceptable), rates, peak_ratios) with one rate and ratio per candidate."""
+    lib = load()
+    dirty, psf = _prep(dirty, psf)
+    cap = int(min(max_iter, trial_iter))
+    res, idx, flux, _ = _outputs(dirty, cap, False)
+    flags = _flags(False, stream) | (FLAG_FFT_FEEDBACK if fft else 0)
+    p = _params(gain, threshold, max_iter, psf, flags, 0, 0)
+    p.feedback_level = float(level)
+    cand = (C.c_int * len(candidates))(*[int(c) for c in candidates])
+    rates = (C.c_double * len(candidates))()
+    ratios = (C.c_double * len(candidates))()
+    chosen = C.c_int(0)
+    ny, nx = dirty.shape
+    _check(lib.clean_autotune_interval(_ptr(dirty), ny, nx, _ptr(psf), psf.shape[0], psf.shape[1], int(tiles[0]),
+                                       int(tiles[1]), C.cast(cand, C.c_void_p), len(candidates), C.byref(p),
+                                       int(trial_iter), float(growth_limit), _ptr(res), _ptr(idx), _ptr(flux), cap,
+                                       C.byref(chosen), C.cast(rates, C.c_void_p), C.cast(ratios, C.c_void_p),
+                                       _stream()))
+    return dict(interval=chosen.value, rates=list(rates), peak_ratios=list(ratios))
 
 
 def psf_to_f16(psf):

@@ -23,7 +23,7 @@ namespace cleanhip {
 template <int K, int V, typename PT> struct RegTile;
 template <int K, int V, typename PT> struct StreamTile;
 template <class Tile> __global__ void hogbom_kernel(const KArgs a);
-template <class Tile> __global__ void tiled_kernel(const KArgs a);
+template <class Tile, bool FFT> __global__ void tiled_kernel(const KArgs a);
 template <class Tile> __global__ void batched_kernel(const BatchArgs b);
 __global__ void finalize_batch_kernel(const PlainJob *jobs, int n);
 __global__ void finite_check_kernel(const float *x, int64_t n, uint32_t *flag);
@@ -171,24 +171,29 @@ template <int V, typename PT> KFn plain_fn(int K)
     return nullptr;
 }
 
-template <int V, typename PT> KFn tiled_fn(int K)
+template <int V, typename PT, bool FFT> KFn tiled_fn(int K)
 {
     if constexpr (V == 4) {
         switch (K) {
-        case 1: return tiled_kernel<RegTile<1, 4, PT>>;
-        case 2: return tiled_kernel<RegTile<2, 4, PT>>;
-        case 4: return tiled_kernel<RegTile<4, 4, PT>>;
-        case 8: return tiled_kernel<RegTile<8, 4, PT>>;
-        case 16: return tiled_kernel<RegTile<16, 4, PT>>;
+        case 1: return tiled_kernel<RegTile<1, 4, PT>, FFT>;
+        case 2: return tiled_kernel<RegTile<2, 4, PT>, FFT>;
+        case 4: return tiled_kernel<RegTile<4, 4, PT>, FFT>;
+        case 8: return tiled_kernel<RegTile<8, 4, PT>, FFT>;
+        case 16: return tiled_kernel<RegTile<16, 4, PT>, FFT>;
         }
     } else {
         switch (K) {
-        case 4: return tiled_kernel<RegTile<4, 1, PT>>;
-        case 16: return tiled_kernel<RegTile<16, 1, PT>>;
-        case 32: return tiled_kernel<RegTile<32, 1, PT>>;
+        case 4: return tiled_kernel<RegTile<4, 1, PT>, FFT>;
+        case 16: return tiled_kernel<RegTile<16, 1, PT>, FFT>;
+        case 32: return tiled_kernel<RegTile<32, 1, PT>, FFT>;
         }
     }
     return nullptr;
+}
+
+template <int V, typename PT> KFn tiled_fn(int K, bool fft)
+{
+    return fft ? tiled_fn<V, PT, true>(K) : tiled_fn<V, PT, false>(K);
 }
 
 using BFn = void (*)(const BatchArgs);
@@ -219,21 +224,24 @@ BFn pick_batched(bool half, int V, int K)
     return half ? batched_fn<1, __half>(K) : batched_fn<1, float>(K);
 }
 
-KFn pick_stream(bool tiled, bool half, int V)
+template <bool FFT> KFn tiled_stream_fn(bool half, int V)
 {
-    if (tiled) {
-        if (V == 4) return half ? tiled_kernel<StreamTile<STREAM_K, 4, __half>> : tiled_kernel<StreamTile<STREAM_K, 4, float>>;
-        return half ? tiled_kernel<StreamTile<STREAM_K, 1, __half>> : tiled_kernel<StreamTile<STREAM_K, 1, float>>;
-    }
+    if (V == 4) return half ? tiled_kernel<StreamTile<STREAM_K, 4, __half>, FFT> : tiled_kernel<StreamTile<STREAM_K, 4, float>, FFT>;
+    return half ? tiled_kernel<StreamTile<STREAM_K, 1, __half>, FFT> : tiled_kernel<StreamTile<STREAM_K, 1, float>, FFT>;
+}
+
+KFn pick_stream(bool tiled, bool half, int V, bool fft)
+{
+    if (tiled) return fft ? tiled_stream_fn<true>(half, V) : tiled_stream_fn<false>(half, V);
     if (V == 4) return half ? hogbom_kernel<StreamTile<STREAM_K, 4, __half>> : hogbom_kernel<StreamTile<STREAM_K, 4, float>>;
     return half ? hogbom_kernel<StreamTile<STREAM_K, 1, __half>> : hogbom_kernel<StreamTile<STREAM_K, 1, float>>;
 }
 
-KFn pick(bool tiled, bool half, int V, int K)
+KFn pick(bool tiled, bool half, int V, int K, bool fft)
 {
     if (tiled) {
-        if (V == 4) return half ? tiled_fn<4, __half>(K) : tiled_fn<4, float>(K);
-        return half ? tiled_fn<1, __half>(K) : tiled_fn<1, float>(K);
+        if (V == 4) return half ? tiled_fn<4, __half>(K, fft) : tiled_fn<4, float>(K, fft);
+        return half ? tiled_fn<1, __half>(K, fft) : tiled_fn<1, float>(K, fft);
     }
     if (V == 4) return half ? plain_fn<4, __half>(K) : plain_fn<4, float>(K);
     return half ? plain_fn<1, __half>(K) : plain_fn<1, float>(K);
@@ -303,7 +311,7 @@ int device_timeout_ticks(int dev, uint64_t &ticks)
 }
 
 // Transform sizes for FFT feedback: powers of two >= 2n - 1 per axis; an axis
-// longer than 8192 points (or any axis of length >= 4, when asked) takes two
+// longer than 4096 points (or any axis of length >= 4, when asked) takes two
 // levels.
 int fft_geometry(int ny, int nx, int flags, FftGeom &g)
 {
@@ -437,7 +445,7 @@ int run(bool tiled, const float *dirty, int ny, int nx, const void *psf, int psf
     st = force_stream ? CLEAN_E_UNSUPPORTED
                       : choose_shape(max_tile, V, p->wg_per_tile, p->px_per_thread, tiled ? 32 : 64, cs, ppt);
     if (st == CLEAN_OK) {
-        fn = pick(tiled, half, V, ppt / V);
+        fn = pick(tiled, half, V, ppt / V, fft);
         if (!fn) return fail(CLEAN_E_UNSUPPORTED, "no kernel for %d pixels per thread", ppt);
         if (dyn_lds > 48 * 1024)
             HIPCHK(hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn_lds));
@@ -455,7 +463,7 @@ int run(bool tiled, const float *dirty, int ny, int nx, const void *psf, int psf
     }
     if (streamed) {
         g_last_error.clear();
-        fn = pick_stream(tiled, half, V);
+        fn = pick_stream(tiled, half, V, fft);
         if (dyn_lds > 48 * 1024)
             HIPCHK(hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn_lds));
         int occ = 0;
@@ -898,6 +906,52 @@ int clean_autotune(const float *dirty, int ny, int nx, const void *psf, int psf_
     best->px_per_thread = best_ppt;
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tune_cache[key] = {best_cs, best_ppt};
+    return CLEAN_OK;
+}
+
+int clean_autotune_interval(const float *dirty, int ny, int nx, const void *psf, int psf_ny, int psf_nx,
+                            int tiles_y, int tiles_x, const int *candidates, int n_candidates,
+                            const clean_params *p, int64_t trial_iter, double growth_limit, float *residual,
+                            int32_t *comp_idx, float *comp_flux, int64_t comp_cap, int *interval,
+                            double *rate_out, double *peak_ratio_out, void *stream)
+{
+    g_last_error.clear();
+    if (!p || !interval) return fail(CLEAN_E_INVAL, "params and interval must be non-NULL");
+    if (!candidates || n_candidates < 1 || n_candidates > 64)
+        return fail(CLEAN_E_INVAL, "need 1..64 candidate intervals");
+    for (int i = 0; i < n_candidates; ++i)
+        if (candidates[i] < 1 || candidates[i] > MAX_INTERVAL)
+            return fail(CLEAN_E_INVAL, "candidate interval %d not in [1, %d]", candidates[i], MAX_INTERVAL);
+    if (tiles_y == 1 && tiles_x == 1) return fail(CLEAN_E_INVAL, "the interval only matters for a tile grid");
+    if (trial_iter < 1) return fail(CLEAN_E_INVAL, "trial_iter must be >= 1");
+    if (!(growth_limit > 0.0)) return fail(CLEAN_E_INVAL, "growth_limit must be > 0");
+    *interval = 0;
+    // the dirty image's peak: a run of no iterations
+    clean_params trial = *p;
+    trial.max_iter = 0;
+    clean_stats st0{};
+    int rc = run(true, dirty, ny, nx, psf, psf_ny, psf_nx, tiles_y, tiles_x, candidates[0], &trial, residual,
+                 comp_idx, comp_flux, comp_cap, nullptr, nullptr, 0, &st0, stream);
+    if (rc) return rc;
+    const double peak0 = std::fabs(st0.final_peak);
+    trial.max_iter = std::min<int64_t>(trial_iter, p->max_iter);
+    const int64_t cap = std::min<int64_t>(comp_cap, trial.max_iter);
+    double best_rate = -1.0;
+    for (int i = 0; i < n_candidates; ++i) {
+        clean_stats st{};
+        rc = run(true, dirty, ny, nx, psf, psf_ny, psf_nx, tiles_y, tiles_x, candidates[i], &trial, residual, comp_idx,
+                 comp_flux, cap, nullptr, nullptr, 0, &st, stream);
+        if (rc) return rc;
+        const double ratio = peak0 > 0.0 ? std::fabs(st.final_peak) / peak0 : (st.final_peak == 0.0 ? 0.0 : INFINITY);
+        const double rate = st.device_ms > 0.f ? (double)st.n_iter / (st.device_ms * 1e-3) : 0.0;
+        if (rate_out) rate_out[i] = rate;
+        if (peak_ratio_out) peak_ratio_out[i] = ratio;
+        const bool ok = std::isfinite(ratio) && std::isfinite(st.residual_rms) && ratio <= growth_limit;
+        if (ok && rate > best_rate) {
+            best_rate = rate;
+            *interval = candidates[i];
+        }
+    }
     return CLEAN_OK;
 }
 

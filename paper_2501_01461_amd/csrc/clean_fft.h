@@ -1,17 +1,13 @@
-// clean_fft.h -- the FFT form of the feedback step: the cross-coupling images
-// (each tile's component image convolved with the full PSF, paper Section 3)
-// computed as one circular convolution per round, for large images where the
-// direct gather would read K_d * N^2 PSF values.
+// clean_fft.h -- transform primitives of the FFT form of the feedback step
+// (the cross-coupling images of paper Section 3 computed as one circular
+// convolution per round, for large images where the direct gather would read
+// K_d * N^2 PSF values).
 //
-// Sizes: Lx, Ly are powers of two with Lx >= 2*nx - 1, Ly >= 2*ny - 1, so the
-// circular convolution of the component image (support [0,ny) x [0,nx)) with
-// the kernel K(d) = psf[centre + d], |d| < (ny, nx), has no wrap-around on the
-// output window [0,ny) x [0,nx).  K's spectrum is computed once per call.
-//
-// One length-L transform runs in one workgroup, in LDS (L <= 8192 complex
-// floats = 64 KB): iterative radix-2 decimation in time, input placed in
+// Transforms run in LDS, one workgroup per transform or per block of short
+// transforms: iterative radix-2 decimation in time, input placed in
 // bit-reversed order, twiddles W_L^m = exp(-2 pi i m / L) from a float table
-// computed in double on the host.
+// computed in double on the host.  Cross-workgroup buffers move through
+// agent-coherent 8-byte loads and stores; transposes through 32 x 33 LDS tiles.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -19,7 +15,6 @@
 #include "clean_device.h"
 
 namespace cleanhip {
-
 
 // Agent-coherent 8-byte accesses: the FFT buffers are written by one
 // workgroup and read by others within one launch.
@@ -42,8 +37,10 @@ __device__ inline void fft_lds(float2 *a, int lg, const float2 *tw, bool inverse
 {
     const int H = 1 << (lg - 1);
     __syncthreads();
+    #pragma clang loop unroll(disable)
     for (int s = 0; s < lg; ++s) {
         const int half = 1 << s;
+        #pragma clang loop unroll(disable)
         for (int j = threadIdx.x; j < H; j += blockDim.x) {
             const int k = j & (half - 1);
             const int i0 = ((j >> s) << (s + 1)) + k, i1 = i0 + half;
@@ -67,8 +64,10 @@ __device__ inline void fft_lds_multi(float2 *a, int lg, int count, int stride, c
     const int H = 1 << (lg - 1);
     const int total = count * H;
     __syncthreads();
+    #pragma clang loop unroll(disable)
     for (int s = 0; s < lg; ++s) {
         const int half = 1 << s;
+        #pragma clang loop unroll(disable)
         for (int j = threadIdx.x; j < total; j += blockDim.x) {
             const int seg = j >> (lg - 1), jj = j & (H - 1);
             const int k = jj & (half - 1);
@@ -99,6 +98,7 @@ __device__ inline void bitrev_permute(float2 *a, int lg)
 {
     __syncthreads();
     const int L = 1 << lg;
+    #pragma clang loop unroll(disable)
     for (int i = threadIdx.x; i < L; i += blockDim.x) {
         const int j = (int)bitrev((uint32_t)i, lg);
         if (i < j) {
@@ -117,14 +117,17 @@ __device__ inline void transpose_tiles(const float2 *src, int ss, float2 *dst, i
                                        int nwork, float2 (*lds)[33])
 {
     const int tr = (rows + 31) / 32, tc = (cols + 31) / 32;
+    #pragma clang loop unroll(disable)
     for (int t = w0; t < tr * tc; t += nwork) {
         const int br = (t / tc) * 32, bc = (t % tc) * 32;
         __syncthreads();
+        #pragma clang loop unroll(disable)
         for (int e = threadIdx.x; e < 1024; e += blockDim.x) {
             const int r = e / 32, c = e % 32;
             if (br + r < rows && bc + c < cols) lds[r][c] = ldc2(&src[(size_t)(br + r) * ss + bc + c]);
         }
         __syncthreads();
+        #pragma clang loop unroll(disable)
         for (int e = threadIdx.x; e < 1024; e += blockDim.x) {
             const int c = e / 32, r = e % 32;
             if (br + r < rows && bc + c < cols) stc2(&dst[(size_t)(bc + c) * ds + br + r], lds[r][c]);

@@ -379,10 +379,10 @@ template <int K, int V, typename PT> struct RegTile {
         return want_key ? key(a) : 0;
     }
 
-    // r -= acc (float32 feedback sums, image layout); with rstart (FFT form,
+    // r -= acc (float32 feedback sums, image layout); FROM_START (FFT form,
     // acc holds every tile's contribution): r = rstart - acc, and rstart = r.
     // Returns the new key.  Only the owning thread touches rstart.
-    __device__ __forceinline__ uint64_t apply_feedback(const Img &a)
+    template <bool FROM_START> __device__ __forceinline__ uint64_t apply_feedback(const Img &a)
     {
 #pragma unroll
         for (int k = 0; k < K; ++k) {
@@ -390,7 +390,7 @@ template <int K, int V, typename PT> struct RegTile {
                 const uint32_t f = group_f(k);
                 const int y = (int)(f / (uint32_t)w), x = (int)(f % (uint32_t)w);
                 const int64_t img = (int64_t)(y0 + y) * a.nx + (x0 + x);
-                if (a.rstart) {
+                if constexpr (FROM_START) {
 #pragma unroll
                     for (int e = 0; e < V; ++e) {
                         r[k][e] = a.rstart[img + e] - ldc(&a.accbuf[img + e]);
@@ -535,7 +535,7 @@ template <int K, int V, typename PT> struct StreamTile {
         return any ? make_key(bb, bf) : 0;
     }
 
-    __device__ uint64_t apply_feedback(const Img &a)
+    template <bool FROM_START> __device__ uint64_t apply_feedback(const Img &a)
     {
         uint32_t bb = 0, bf = 0;
         bool any = false;
@@ -548,9 +548,9 @@ template <int K, int V, typename PT> struct StreamTile {
                 const int64_t img = img_of(a, f);
 #pragma unroll
                 for (int e = 0; e < V; ++e) {
-                    const float r = (a.rstart ? a.rstart[img + e] : a.residual[img + e]) - ldc(&a.accbuf[img + e]);
+                    const float r = (FROM_START ? a.rstart[img + e] : a.residual[img + e]) - ldc(&a.accbuf[img + e]);
                     a.residual[img + e] = r;
-                    if (a.rstart) a.rstart[img + e] = r;
+                    if constexpr (FROM_START) a.rstart[img + e] = r;
                     take(__float_as_uint(r), f + e, bb, bf, any);
                 }
             }
@@ -687,7 +687,7 @@ template <class Tile> __global__ void __launch_bounds__(WG) batched_kernel(const
 // two at a time through one complex transform along x, and only the
 // Lx/2 + 1 non-redundant bins are carried through the y transforms.
 //
-// An axis of length L <= 8192 is transformed in one pass in LDS (one
+// An axis of length L <= 4096 is transformed in one pass in LDS (one
 // transform per workgroup).  Longer axes use two levels, L = L1 * L2 with
 // n = L2 n1 + n2 and k = k1 + L1 k2 (the four-step scheme): transforms of
 // length L1 over n1 (strided), times W_L^(n2 k1), then transforms of length
@@ -715,6 +715,15 @@ __device__ __forceinline__ FftAxis fft_axis(int lg, int two, const float2 *tw)
     f.L1 = 1 << f.lg1;
     f.L2 = 1 << f.lg2;
     return f;
+}
+
+// log2 of the number of strided length-L1 transforms one workgroup holds in
+// LDS at a time (segments padded to L1 + 1 against bank conflicts).
+__device__ __forceinline__ int strided_block_lg(const FftAxis &f)
+{
+    int lg = 0;
+    while (lg < f.lg2 && (2 << lg) * (f.L1 + 1) <= FFT_LDS_CPLX) ++lg;
+    return lg;
 }
 
 // Carried column of x bin (k1, k2), two levels: bins k = k1 + L1 k2 <= L/2,
@@ -783,19 +792,23 @@ __device__ void xfwd_one(const KArgs &a, const FftAxis &fx, int Ly, int rows, co
                          int *s_nz)
 {
     const int Lx = fx.L, lgx = fx.lg, nx = a.nx, tx = a.tx;
+    #pragma clang loop unroll(disable)
     for (int pr = blockIdx.x; pr < (rows + 1) / 2; pr += gridDim.x) {
         const int r0 = 2 * pr;
         const bool has1 = r0 + 1 < rows;
         if (KSRC) {
+            #pragma clang loop unroll(disable)
             for (int x = threadIdx.x; x < Lx; x += WG)
                 lds[bitrev((uint32_t)x, lgx)] = make_float2(kernel_value<PT>(a, Ly, Lx, r0, x),
                                                             has1 ? kernel_value<PT>(a, Ly, Lx, r0 + 1, x) : 0.0f);
             if (threadIdx.x == 0) *s_nz = 1;
             __syncthreads();
         } else {
+            #pragma clang loop unroll(disable)
             for (int x = threadIdx.x; x < Lx; x += WG) lds[x] = make_float2(0.f, 0.f);
             if (threadIdx.x == 0) *s_nz = 0;
             __syncthreads();
+            #pragma clang loop unroll(disable)
             for (int j = threadIdx.x; j < 2 * tx; j += WG) {
                 const int row = r0 + (j >= tx);
                 if (row >= rows) continue;
@@ -804,6 +817,7 @@ __device__ void xfwd_one(const KArgs &a, const FftAxis &fx, int Ly, int rows, co
                 const int32_t b0 = row * nx;
                 const int lo = lower_pos(a, t, 0, n, b0), hi = lower_pos(a, t, lo, n, b0 + nx);
                 if (hi > lo) atomicAdd(s_nz, hi - lo);
+                #pragma clang loop unroll(disable)
                 for (int q = lo; q < hi; ++q) {
                     const size_t e = (size_t)t * a.interval + q;
                     float *dst = (float *)&lds[bitrev((uint32_t)(ldc(&a.ag_pos[e]) - b0), lgx)];
@@ -814,10 +828,12 @@ __device__ void xfwd_one(const KArgs &a, const FftAxis &fx, int Ly, int rows, co
         }
         float2 *o0 = a.fft_a + (size_t)r0 * fx.H, *o1 = o0 + fx.H;
         if (*s_nz == 0) {                       // both rows empty: zero spectra
+            #pragma clang loop unroll(disable)
             for (int k = threadIdx.x; k < fx.H; k += WG) store_split(o0, o1, has1, k, make_float2(0.f, 0.f),
                                                                     make_float2(0.f, 0.f));
         } else {
             fft_lds(lds, lgx, fx.tw, false);
+            #pragma clang loop unroll(disable)
             for (int k = threadIdx.x; k < fx.H; k += WG) store_split(o0, o1, has1, k, lds[k], lds[(Lx - k) & (Lx - 1)]);
         }
         __syncthreads();
@@ -830,16 +846,18 @@ __device__ void xfwd_one(const KArgs &a, const FftAxis &fx, int Ly, int rows, co
 template <typename PT, bool KSRC>
 __device__ void xfwd_two_a(const KArgs &a, const FftAxis &fx, int Ly, int rows, float2 *lds)
 {
-    const int NB = min(fx.L2, 4096 >> fx.lg1);
+    const int lgNB = strided_block_lg(fx), NB = 1 << lgNB;
     const int nblk = fx.L2 / NB, stride = fx.L1 + 1;
     const int ncols = KSRC ? fx.L : a.nx;
+    #pragma clang loop unroll(disable)
     for (int item = blockIdx.x; item < (rows + 1) / 2 * nblk; item += gridDim.x) {
         const int pr = item / nblk, b = item % nblk;
         const int r0 = 2 * pr;
         const bool has1 = r0 + 1 < rows;
         __syncthreads();
+        #pragma clang loop unroll(disable)
         for (int e = threadIdx.x; e < NB * fx.L1; e += WG) {
-            const int j = e % NB, n1 = e / NB;
+            const int j = e & (NB - 1), n1 = e >> lgNB;
             const int x = fx.L2 * n1 + b * NB + j;
             float v0 = 0.f, v1 = 0.f;
             if (x < ncols) {
@@ -855,8 +873,9 @@ __device__ void xfwd_two_a(const KArgs &a, const FftAxis &fx, int Ly, int rows, 
         }
         fft_lds_multi(lds, fx.lg1, NB, stride, fx.tw, fx.L2, false);
         float2 *w = a.fft_wx + (size_t)pr * fx.L;
+        #pragma clang loop unroll(disable)
         for (int e = threadIdx.x; e < NB * fx.L1; e += WG) {
-            const int j = e % NB, k1 = e / NB, n2 = b * NB + j;
+            const int j = e & (NB - 1), k1 = e >> lgNB, n2 = b * NB + j;
             stc2(&w[(size_t)fx.L2 * k1 + n2], cmul(lds[j * stride + k1], fx.tw[n2 * k1]));
         }
     }
@@ -874,6 +893,7 @@ __device__ void xfwd_two_b(const KArgs &a, const FftAxis &fx, int rows, float2 *
     const int G = max(1, min(nslot, FFT_LDS_CPLX / (2 * stride)));
     const int nblk = (nslot + G - 1) / G;
     const int hq = fx.L2 / 2;
+    #pragma clang loop unroll(disable)
     for (int item = blockIdx.x; item < (rows + 1) / 2 * nblk; item += gridDim.x) {
         const int pr = item / nblk, s0 = (item % nblk) * G, ns = min(G, nslot - s0);
         const int r0 = 2 * pr;
@@ -881,29 +901,33 @@ __device__ void xfwd_two_b(const KArgs &a, const FftAxis &fx, int rows, float2 *
         const float2 *w = a.fft_wx + (size_t)pr * fx.L;
         __syncthreads();
         // segment 2i: row k1 = s0 + i; segment 2i+1: row (L1 - k1) mod L1
+        #pragma clang loop unroll(disable)
         for (int e = threadIdx.x; e < 2 * ns * fx.L2; e += WG) {
-            const int seg = e / fx.L2, n2 = e % fx.L2;
-            const int k1 = s0 + seg / 2;
+            const int seg = e >> fx.lg2, n2 = e & (fx.L2 - 1);
+            const int k1 = s0 + (seg >> 1);
             const int kr = (seg & 1) ? ((fx.L1 - k1) & (fx.L1 - 1)) : k1;
             lds[seg * stride + bitrev((uint32_t)n2, fx.lg2)] = ldc2(&w[(size_t)fx.L2 * kr + n2]);
         }
         fft_lds_multi(lds, fx.lg2, 2 * ns, stride, fx.tw, fx.L1, false);
         float2 *o0 = a.fft_a + (size_t)r0 * fx.H, *o1 = o0 + fx.H;
-        for (int e = threadIdx.x; e < 2 * ns * (hq + 1); e += WG) {
-            const int seg = e / (hq + 1), k2 = e % (hq + 1);
-            const int k1 = s0 + seg / 2;
+        #pragma clang loop unroll(disable)
+        for (int e = threadIdx.x; e < 2 * ns * hq; e += WG) {
+            const int seg = e >> (fx.lg2 - 1), k2 = e & (hq - 1);
+            const int k1 = s0 + (seg >> 1);
             const bool second = seg & 1;
             if (second && (k1 == 0 || 2 * k1 == fx.L1)) continue;      // row is its own mirror
             const int kr = second ? fx.L1 - k1 : k1;
-            if (k2 == hq && kr != 0) continue;                          // only row 0 carries k2 = L2/2
             int q1, q2;
             mirror_of(fx, kr, k2, q1, q2);
             const int qs = q1 == kr ? seg : (seg ^ 1);
             store_split(o0, o1, has1, chat_of(fx, kr, k2), lds[seg * stride + k2], lds[qs * stride + q2]);
         }
+        if (s0 == 0 && threadIdx.x == 0)        // bin k = L/2: row 0, k2 = L2/2, its own mirror
+            store_split(o0, o1, has1, fx.L / 2, lds[hq], lds[hq]);
     }
     if (!KSRC) {
         const int total = s_off[a.T];
+        #pragma clang loop unroll(disable)
         for (int i = blockIdx.x * WG + threadIdx.x; i < total; i += gridDim.x * WG) {
             int lo = 0, hi = a.T;                   // largest t with s_off[t] <= i
             while (hi - lo > 1) {
@@ -921,19 +945,25 @@ __device__ void xfwd_two_b(const KArgs &a, const FftAxis &fx, int rows, float2 *
 template <bool PRE>
 __device__ void ycol_one(const KArgs &a, const FftAxis &fx, const FftAxis &fy, int rows, float2 *lds)
 {
+    #pragma clang loop unroll(disable)
     for (int col = blockIdx.x; col < fx.H; col += gridDim.x) {
+        #pragma clang loop unroll(disable)
         for (int v = threadIdx.x; v < fy.L; v += WG) lds[v] = make_float2(0.f, 0.f);
         __syncthreads();
         float2 *b = a.fft_b + (size_t)col * rows;
+        #pragma clang loop unroll(disable)
         for (int v = threadIdx.x; v < rows; v += WG) lds[bitrev((uint32_t)v, fy.lg)] = ldc2(&b[v]);
         fft_lds(lds, fy.lg, fy.tw, false);
         float2 *ks = a.fft_ks + (size_t)col * fy.L;
         if (PRE) {
+            #pragma clang loop unroll(disable)
             for (int v = threadIdx.x; v < fy.L; v += WG) stc2(&ks[v], lds[v]);
         } else {
+            #pragma clang loop unroll(disable)
             for (int v = threadIdx.x; v < fy.L; v += WG) lds[v] = cmul(lds[v], ldc2(&ks[v]));
             bitrev_permute(lds, fy.lg);
             fft_lds(lds, fy.lg, fy.tw, true);
+            #pragma clang loop unroll(disable)
             for (int v = threadIdx.x; v < rows; v += WG) stc2(&b[v], lds[v]);
         }
         __syncthreads();
@@ -945,21 +975,24 @@ __device__ void ycol_one(const KArgs &a, const FftAxis &fx, const FftAxis &fy, i
 // fft_wy[col][L2 k1 + n2].
 __device__ void ycol_two_a(const KArgs &a, const FftAxis &fx, const FftAxis &fy, int rows, float2 *lds)
 {
-    const int NB = min(fy.L2, 4096 >> fy.lg1);
+    const int lgNB = strided_block_lg(fy), NB = 1 << lgNB;
     const int nblk = fy.L2 / NB, stride = fy.L1 + 1;
+    #pragma clang loop unroll(disable)
     for (int item = blockIdx.x; item < fx.H * nblk; item += gridDim.x) {
         const int col = item / nblk, b = item % nblk;
         const float2 *src = a.fft_b + (size_t)col * rows;
         __syncthreads();
+        #pragma clang loop unroll(disable)
         for (int e = threadIdx.x; e < NB * fy.L1; e += WG) {
-            const int j = e % NB, n1 = e / NB;
+            const int j = e & (NB - 1), n1 = e >> lgNB;
             const int yy = fy.L2 * n1 + b * NB + j;
             lds[j * stride + bitrev((uint32_t)n1, fy.lg1)] = yy < rows ? ldc2(&src[yy]) : make_float2(0.f, 0.f);
         }
         fft_lds_multi(lds, fy.lg1, NB, stride, fy.tw, fy.L2, false);
         float2 *w = a.fft_wy + (size_t)col * fy.L;
+        #pragma clang loop unroll(disable)
         for (int e = threadIdx.x; e < NB * fy.L1; e += WG) {
-            const int j = e % NB, k1 = e / NB, n2 = b * NB + j;
+            const int j = e & (NB - 1), k1 = e >> lgNB, n2 = b * NB + j;
             stc2(&w[(size_t)fy.L2 * k1 + n2], cmul(lds[j * stride + k1], fy.tw[n2 * k1]));
         }
     }
@@ -975,30 +1008,35 @@ __device__ void ycol_two_b(const KArgs &a, const FftAxis &fx, const FftAxis &fy,
     const int stride = fy.L2 + 1;
     const int G = max(1, min(fy.L1, FFT_LDS_CPLX / stride));
     const int nblk = (fy.L1 + G - 1) / G;
+    #pragma clang loop unroll(disable)
     for (int item = blockIdx.x; item < fx.H * nblk; item += gridDim.x) {
         const int col = item / nblk, k0 = (item % nblk) * G, ng = min(G, fy.L1 - k0);
         float2 *w = a.fft_wy + (size_t)col * fy.L;
         float2 *ks = a.fft_ks + (size_t)col * fy.L;
         __syncthreads();
+        #pragma clang loop unroll(disable)
         for (int e = threadIdx.x; e < ng * fy.L2; e += WG) {
-            const int g = e / fy.L2, n2 = e % fy.L2;
+            const int g = e >> fy.lg2, n2 = e & (fy.L2 - 1);
             lds[g * stride + bitrev((uint32_t)n2, fy.lg2)] = ldc2(&w[(size_t)fy.L2 * (k0 + g) + n2]);
         }
         fft_lds_multi(lds, fy.lg2, ng, stride, fy.tw, fy.L1, false);
         if (PRE) {
+            #pragma clang loop unroll(disable)
             for (int e = threadIdx.x; e < ng * fy.L2; e += WG) {
-                const int g = e / fy.L2, k2 = e % fy.L2;
+                const int g = e >> fy.lg2, k2 = e & (fy.L2 - 1);
                 stc2(&ks[(size_t)fy.L2 * (k0 + g) + k2], lds[g * stride + k2]);
             }
             continue;
         }
+        #pragma clang loop unroll(disable)
         for (int e = threadIdx.x; e < ng * fy.L2; e += WG) {
-            const int g = e / fy.L2, k2 = e % fy.L2;
+            const int g = e >> fy.lg2, k2 = e & (fy.L2 - 1);
             lds[g * stride + k2] = cmul(lds[g * stride + k2], ldc2(&ks[(size_t)fy.L2 * (k0 + g) + k2]));
         }
         __syncthreads();
+        #pragma clang loop unroll(disable)
         for (int e = threadIdx.x; e < ng * fy.L2; e += WG) {    // back to bit-reversed order
-            const int g = e / fy.L2, i = e % fy.L2;
+            const int g = e >> fy.lg2, i = e & (fy.L2 - 1);
             const int j = (int)bitrev((uint32_t)i, fy.lg2);
             if (i < j) {
                 const float2 t = lds[g * stride + i];
@@ -1007,8 +1045,9 @@ __device__ void ycol_two_b(const KArgs &a, const FftAxis &fx, const FftAxis &fy,
             }
         }
         fft_lds_multi(lds, fy.lg2, ng, stride, fy.tw, fy.L1, true);
+        #pragma clang loop unroll(disable)
         for (int e = threadIdx.x; e < ng * fy.L2; e += WG) {
-            const int g = e / fy.L2, n2 = e % fy.L2, k1 = k0 + g;
+            const int g = e >> fy.lg2, n2 = e & (fy.L2 - 1), k1 = k0 + g;
             stc2(&w[(size_t)fy.L2 * k1 + n2], cmulc(lds[g * stride + n2], fy.tw[n2 * k1]));
         }
     }
@@ -1018,20 +1057,23 @@ __device__ void ycol_two_b(const KArgs &a, const FftAxis &fx, const FftAxis &fy,
 // length L1 over k1, giving y = L2 n1 + n2; the first `rows` go to fft_b.
 __device__ void ycol_two_c(const KArgs &a, const FftAxis &fx, const FftAxis &fy, int rows, float2 *lds)
 {
-    const int NB = min(fy.L2, 4096 >> fy.lg1);
+    const int lgNB = strided_block_lg(fy), NB = 1 << lgNB;
     const int nblk = fy.L2 / NB, stride = fy.L1 + 1;
+    #pragma clang loop unroll(disable)
     for (int item = blockIdx.x; item < fx.H * nblk; item += gridDim.x) {
         const int col = item / nblk, b = item % nblk;
         const float2 *w = a.fft_wy + (size_t)col * fy.L;
         __syncthreads();
+        #pragma clang loop unroll(disable)
         for (int e = threadIdx.x; e < NB * fy.L1; e += WG) {
-            const int j = e % NB, k1 = e / NB;
+            const int j = e & (NB - 1), k1 = e >> lgNB;
             lds[j * stride + bitrev((uint32_t)k1, fy.lg1)] = ldc2(&w[(size_t)fy.L2 * k1 + b * NB + j]);
         }
         fft_lds_multi(lds, fy.lg1, NB, stride, fy.tw, fy.L2, true);
         float2 *dst = a.fft_b + (size_t)col * rows;
+        #pragma clang loop unroll(disable)
         for (int e = threadIdx.x; e < NB * fy.L1; e += WG) {
-            const int j = e % NB, n1 = e / NB;
+            const int j = e & (NB - 1), n1 = e >> lgNB;
             const int yy = fy.L2 * n1 + b * NB + j;
             if (yy < rows) stc2(&dst[yy], lds[j * stride + n1]);
         }
@@ -1044,10 +1086,12 @@ __device__ void ycol_two_c(const KArgs &a, const FftAxis &fx, const FftAxis &fy,
 __device__ void xinv_one(const KArgs &a, const FftAxis &fx, float scale, float2 *lds)
 {
     const int Lx = fx.L, lgx = fx.lg, ny = a.ny, nx = a.nx;
+    #pragma clang loop unroll(disable)
     for (int pr = blockIdx.x; pr < (ny + 1) / 2; pr += gridDim.x) {
         const int r0 = 2 * pr;
         const bool has1 = r0 + 1 < ny;
         const float2 *i0 = a.fft_a + (size_t)r0 * fx.H, *i1 = i0 + fx.H;
+        #pragma clang loop unroll(disable)
         for (int k = threadIdx.x; k < fx.H; k += WG) {
             const float2 A = ldc2(&i0[k]);
             const float2 B = has1 ? ldc2(&i1[k]) : make_float2(0.f, 0.f);
@@ -1055,6 +1099,7 @@ __device__ void xinv_one(const KArgs &a, const FftAxis &fx, float scale, float2 
             if (k > 0 && k < Lx / 2) lds[bitrev((uint32_t)(Lx - k), lgx)] = make_float2(A.x + B.y, B.x - A.y);
         }
         fft_lds(lds, lgx, fx.tw, true);
+        #pragma clang loop unroll(disable)
         for (int x = threadIdx.x; x < nx; x += WG) {
             const float2 z = lds[x];
             stc(&a.accbuf[(size_t)r0 * nx + x], z.x * scale);
@@ -1072,14 +1117,16 @@ __device__ void xinv_two_a(const KArgs &a, const FftAxis &fx, float2 *lds)
     const int ny = a.ny, stride = fx.L2 + 1, hq = fx.L2 / 2;
     const int G = max(1, min(fx.L1, FFT_LDS_CPLX / stride));
     const int nblk = (fx.L1 + G - 1) / G;
+    #pragma clang loop unroll(disable)
     for (int item = blockIdx.x; item < (ny + 1) / 2 * nblk; item += gridDim.x) {
         const int pr = item / nblk, k0 = (item % nblk) * G, ng = min(G, fx.L1 - k0);
         const int r0 = 2 * pr;
         const bool has1 = r0 + 1 < ny;
         const float2 *i0 = a.fft_a + (size_t)r0 * fx.H, *i1 = i0 + fx.H;
         __syncthreads();
+        #pragma clang loop unroll(disable)
         for (int e = threadIdx.x; e < ng * fx.L2; e += WG) {
-            const int g = e / fx.L2, k2 = e % fx.L2, k1 = k0 + g;
+            const int g = e >> fx.lg2, k2 = e & (fx.L2 - 1), k1 = k0 + g;
             const bool carried = k2 < hq || (k2 == hq && k1 == 0);
             int q1 = k1, q2 = k2;
             if (!carried) mirror_of(fx, k1, k2, q1, q2);
@@ -1091,8 +1138,9 @@ __device__ void xinv_two_a(const KArgs &a, const FftAxis &fx, float2 *lds)
         }
         fft_lds_multi(lds, fx.lg2, ng, stride, fx.tw, fx.L1, true);
         float2 *w = a.fft_wx + (size_t)pr * fx.L;
+        #pragma clang loop unroll(disable)
         for (int e = threadIdx.x; e < ng * fx.L2; e += WG) {
-            const int g = e / fx.L2, n2 = e % fx.L2, k1 = k0 + g;
+            const int g = e >> fx.lg2, n2 = e & (fx.L2 - 1), k1 = k0 + g;
             stc2(&w[(size_t)fx.L2 * k1 + n2], cmulc(lds[g * stride + n2], fx.tw[n2 * k1]));
         }
     }
@@ -1104,21 +1152,24 @@ __device__ void xinv_two_a(const KArgs &a, const FftAxis &fx, float2 *lds)
 __device__ void xinv_two_b(const KArgs &a, const FftAxis &fx, float scale, float2 *lds)
 {
     const int ny = a.ny, nx = a.nx;
-    const int NB = min(fx.L2, 4096 >> fx.lg1);
+    const int lgNB = strided_block_lg(fx), NB = 1 << lgNB;
     const int nblk = fx.L2 / NB, stride = fx.L1 + 1;
+    #pragma clang loop unroll(disable)
     for (int item = blockIdx.x; item < (ny + 1) / 2 * nblk; item += gridDim.x) {
         const int pr = item / nblk, b = item % nblk;
         const int r0 = 2 * pr;
         const bool has1 = r0 + 1 < ny;
         const float2 *w = a.fft_wx + (size_t)pr * fx.L;
         __syncthreads();
+        #pragma clang loop unroll(disable)
         for (int e = threadIdx.x; e < NB * fx.L1; e += WG) {
-            const int j = e % NB, k1 = e / NB;
+            const int j = e & (NB - 1), k1 = e >> lgNB;
             lds[j * stride + bitrev((uint32_t)k1, fx.lg1)] = ldc2(&w[(size_t)fx.L2 * k1 + b * NB + j]);
         }
         fft_lds_multi(lds, fx.lg1, NB, stride, fx.tw, fx.L2, true);
+        #pragma clang loop unroll(disable)
         for (int e = threadIdx.x; e < NB * fx.L1; e += WG) {
-            const int j = e % NB, n1 = e / NB;
+            const int j = e & (NB - 1), n1 = e >> lgNB;
             const int x = fx.L2 * n1 + b * NB + j;
             if (x < nx) {
                 const float2 z = lds[j * stride + n1];
@@ -1281,7 +1332,9 @@ __device__ __forceinline__ int wg_sum_int(int v, int *s_tmp)
     return r;
 }
 
-template <class Tile> __global__ void __launch_bounds__(WG) tiled_kernel(const KArgs a)
+// FFT selects the feedback form at compile time, so the direct-gather kernels
+// carry none of the transform code (and its register needs).
+template <class Tile, bool FFT> __global__ void __launch_bounds__(WG) tiled_kernel(const KArgs a)
 {
     constexpr int V = Tile::kV;
     using PT = typename Tile::psf_t;
@@ -1321,7 +1374,9 @@ template <class Tile> __global__ void __launch_bounds__(WG) tiled_kernel(const K
         if (tile_leader_wg && threadIdx.x == 0) stc(&a.tile_key[tile], cur);
     }
     if (!grid_barrier(y, epoch, &s_ok)) return;
-    if (a.fft_lgx && !fft_spectrum<PT>(a, y, epoch, &s_ok)) return;
+    if constexpr (FFT) {
+        if (!fft_spectrum<PT>(a, y, epoch, &s_ok)) return;
+    }
 
     const int64_t limit = a.max_iter < a.cap ? a.max_iter : a.cap;
     int64_t used = 0;
@@ -1426,7 +1481,7 @@ template <class Tile> __global__ void __launch_bounds__(WG) tiled_kernel(const K
         __syncthreads();
 
         // ---- feedback by FFT: acc = (component image (*) K) - own tile's part
-        if (a.fft_lgx) {
+        if constexpr (FFT) {
             if (!fft_feedback<PT>(a, y, epoch, &s_ok, s_off)) return;
         } else
         // ---- feedback gather: acc[q] = sum over other tiles' components
@@ -1535,7 +1590,7 @@ template <class Tile> __global__ void __launch_bounds__(WG) tiled_kernel(const K
 
         // ---- apply feedback and find each tile's new peak
         if (is_cluster) {
-            if (!cluster_reduce(y, slots, a.slot_pad, cs, rank, e++, R.apply_feedback(im), cur)) return;
+            if (!cluster_reduce(y, slots, a.slot_pad, cs, rank, e++, R.template apply_feedback<FFT>(im), cur)) return;
             if (tile_leader_wg && threadIdx.x == 0) stc(&a.tile_key[tile], cur);
         }
         rounds += 1;
@@ -1611,10 +1666,12 @@ __global__ void finalize_batch_kernel(const PlainJob *jobs, int n)
 #define INST(K, V, PT)                                                                   \
     template __global__ void hogbom_kernel<RegTile<K, V, PT>>(const KArgs a);           \
     template __global__ void batched_kernel<RegTile<K, V, PT>>(const BatchArgs b);      \
-    template __global__ void tiled_kernel<RegTile<K, V, PT>>(const KArgs a);
+    template __global__ void tiled_kernel<RegTile<K, V, PT>, false>(const KArgs a);     \
+    template __global__ void tiled_kernel<RegTile<K, V, PT>, true>(const KArgs a);
 #define INST_STREAM(V, PT)                                                               \
     template __global__ void hogbom_kernel<StreamTile<STREAM_K, V, PT>>(const KArgs a);  \
-    template __global__ void tiled_kernel<StreamTile<STREAM_K, V, PT>>(const KArgs a);
+    template __global__ void tiled_kernel<StreamTile<STREAM_K, V, PT>, false>(const KArgs a); \
+    template __global__ void tiled_kernel<StreamTile<STREAM_K, V, PT>, true>(const KArgs a);
 
 #define INST_ALL_K(V, PT) INST(1, V, PT) INST(2, V, PT) INST(4, V, PT) INST(8, V, PT) INST(16, V, PT)
 INST_ALL_K(4, float)

@@ -126,6 +126,28 @@ def test_psf_to_f16_argument_errors(lib):
     assert lib.clean_psf_to_f16(FAKE, FAKE, -1, None) == INVAL
 
 
+def test_autotune_interval_argument_errors(lib):
+    p = params()
+    got = C.c_int(-1)
+    cand = (C.c_int * 3)(10, 50, 100)
+    bad = (C.c_int * 2)(10, 0)
+    big = (C.c_int * 1)(4096)
+
+    def call(cands=cand, n=3, ty=2, tx=2, trial=100, growth=1.0, pp=p, out=got):
+        return lib.clean_autotune_interval(FAKE, 16, 16, FAKE, 32, 32, ty, tx, C.cast(cands, C.c_void_p) if cands
+                                           else None, n, C.byref(pp) if pp else None, trial, growth, FAKE, FAKE,
+                                           FAKE, 100, C.byref(out) if out is not None else None, None, None, None)
+    assert call(cands=None) == INVAL
+    assert call(n=0) == INVAL
+    assert call(cands=bad, n=2) == INVAL
+    assert call(cands=big, n=1) == INVAL
+    assert call(ty=1, tx=1) == INVAL
+    assert call(trial=0) == INVAL
+    assert call(growth=0.0) == INVAL
+    assert call(pp=None) == INVAL
+    assert call(out=None) == INVAL
+
+
 def test_autotune_argument_errors(lib):
     p = params()
     best = N.Params()

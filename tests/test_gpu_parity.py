@@ -324,3 +324,35 @@ def test_autotune_returns_a_shape_with_identical_results(lib):
     t2 = lib.tiled_feedback(d, p, (2, 2), 50, 0.1, 5e-3, 1000, **st)
     assert np.array_equal(host(t1["idx"]), host(t2["idx"]))
     assert np.array_equal(bits(host(t1["residual"])), bits(host(t2["residual"])))
+
+
+# ------------------------------------------------------ interval tuner --
+
+@pytest.mark.parametrize("track", [False, True], ids=["snapshot", "track"])
+def test_interval_tuner_selection_rule(lib, track):
+    """clean_autotune_interval on the 1024^2 / 2x2 workload: every candidate's
+    reported peak ratio equals that of a direct run (runs are deterministic),
+    and the choice is the fastest candidate whose residual stayed finite and
+    within the growth limit.  With the snapshot PSF, interval 100 diverges
+    (the float64 oracle does too) and must be rejected."""
+    import math
+    announce("interval tuner", "track" if track else "snapshot")
+    c = synth.make_config(1, psf_track=track)
+    d, p = dev(c["dirty"]), dev(c["psf"])
+    cands = [10, 25, 100]
+    t = lib.autotune_interval(d, p, (2, 2), cands, 0.1, 0.0, c["max_iter"], trial_iter=c["max_iter"])
+    peak0 = abs(lib.tiled_feedback(d, p, (2, 2), 10, 0.1, 0.0, 0)["stats"]["final_peak"])
+    ok = []
+    for ivl, ratio in zip(cands, t["peak_ratios"]):
+        st = lib.tiled_feedback(d, p, (2, 2), ivl, 0.1, 0.0, c["max_iter"])["stats"]
+        direct = abs(st["final_peak"]) / peak0
+        assert ratio == direct or (math.isnan(ratio) and math.isnan(direct))
+        ok.append(math.isfinite(ratio) and math.isfinite(st["residual_rms"]) and ratio <= 1.0)
+    print("interval tuner:", dict(zip(cands, zip(t["peak_ratios"], t["rates"]))), "->", t["interval"])
+    if any(ok):
+        best = max((r, i) for i, r, a in zip(cands, t["rates"], ok) if a)[1]
+        assert t["interval"] == best
+    else:
+        assert t["interval"] == 0
+    if not track:
+        assert not ok[cands.index(100)]
