@@ -95,12 +95,12 @@ enum {
                                       (3 Hx R + Hx Ly) * 8 + ny nx * 4 bytes,
                                       Lx, Ly the powers of two >= 2 nx - 1,
                                       2 ny - 1, Hx = Lx/2 + 1, R = max(ny, Ly);
-                                      axes longer than 4096 points add two-level
+                                      axes longer than 8192 points add two-level
                                       work buffers (clean_workspace_size)      */
     CLEAN_FLAG_FFT_TWO_LEVEL = 8   /* with CLEAN_FLAG_FFT_FEEDBACK: use the
                                       two-level (four-step) transforms on every
                                       axis of length >= 4, as they are used
-                                      automatically above 4096 points (slower;
+                                      automatically above 8192 points (slower;
                                       for testing that path at small sizes)    */
 };
 

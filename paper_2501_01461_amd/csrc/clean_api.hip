@@ -311,7 +311,7 @@ int device_timeout_ticks(int dev, uint64_t &ticks)
 }
 
 // Transform sizes for FFT feedback: powers of two >= 2n - 1 per axis; an axis
-// longer than 4096 points (or any axis of length >= 4, when asked) takes two
+// longer than 8192 points (or any axis of length >= 4, when asked) takes two
 // levels.
 int fft_geometry(int ny, int nx, int flags, FftGeom &g)
 {

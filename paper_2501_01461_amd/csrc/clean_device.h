@@ -13,9 +13,9 @@ constexpr int GATHER_CHUNK = 2048;      // components staged in LDS per pass
 constexpr int GATHER_M = 2;             // pixel groups per thread per gather pass
 constexpr int GATHER_J = 8;             // components whose loads are issued together
 constexpr int STREAM_K = 4;             // pixel groups per thread per streamed pass
-constexpr int FFT_MAX_LG = 12;          // one-level FFT transforms: length <= 4096 (32 KB of LDS)
+constexpr int FFT_MAX_LG = 13;          // one-level FFT transforms: length <= 8192 (64 KB of LDS)
 constexpr int FFT_MAX_LG2 = 16;         // two-level FFT transforms: length <= 65536
-constexpr int FFT_LDS_CPLX = 4096 + 64; // LDS complex slots of the two-level passes
+constexpr int FFT_LDS_CPLX = 8192 + 64; // LDS complex slots of the two-level passes
 // (with the tiled kernel's static LDS, two workgroups fit one CU's 160 KB)
 
 enum { STOP_MAXITER = 0, STOP_THRESHOLD = 1, STOP_CAPACITY = 2 };

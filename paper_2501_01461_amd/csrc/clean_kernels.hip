@@ -687,7 +687,7 @@ template <class Tile> __global__ void __launch_bounds__(WG) batched_kernel(const
 // two at a time through one complex transform along x, and only the
 // Lx/2 + 1 non-redundant bins are carried through the y transforms.
 //
-// An axis of length L <= 4096 is transformed in one pass in LDS (one
+// An axis of length L <= 8192 is transformed in one pass in LDS (one
 // transform per workgroup).  Longer axes use two levels, L = L1 * L2 with
 // n = L2 n1 + n2 and k = k1 + L1 k2 (the four-step scheme): transforms of
 // length L1 over n1 (strided), times W_L^(n2 k1), then transforms of length
@@ -1188,9 +1188,9 @@ template <typename PT>
 __device__ bool fft_spectrum(const KArgs &a, const Sync &y, uint32_t &epoch, int *s_ok)
 {
     extern __shared__ __align__(16) unsigned char s_dyn[];
-    __shared__ float2 s_tr[32][33];
     __shared__ int s_nz;
     float2 *lds = (float2 *)s_dyn;
+    float2 (*s_tr)[33] = reinterpret_cast<float2 (*)[33]>(s_dyn);   // transposes reuse the arena
     const FftAxis fx = fft_axis(a.fft_lgx, a.fft_two_x, a.tw_x), fy = fft_axis(a.fft_lgy, a.fft_two_y, a.tw_y);
     const int Ly = fy.L;
     if (!fx.two) {
@@ -1223,9 +1223,9 @@ template <typename PT>
 __device__ bool fft_feedback(const KArgs &a, const Sync &y, uint32_t &epoch, int *s_ok, const int32_t *s_off)
 {
     extern __shared__ __align__(16) unsigned char s_dyn[];
-    __shared__ float2 s_tr[32][33];
     __shared__ int s_nz;
     float2 *lds = (float2 *)s_dyn;
+    float2 (*s_tr)[33] = reinterpret_cast<float2 (*)[33]>(s_dyn);   // transposes reuse the arena
     const FftAxis fx = fft_axis(a.fft_lgx, a.fft_two_x, a.tw_x), fy = fft_axis(a.fft_lgy, a.fft_two_y, a.tw_y);
     const int ny = a.ny;
     const float scale = 1.0f / ((float)fx.L * (float)fy.L);
@@ -1334,7 +1334,11 @@ __device__ __forceinline__ int wg_sum_int(int v, int *s_tmp)
 
 // FFT selects the feedback form at compile time, so the direct-gather kernels
 // carry none of the transform code (and its register needs).
-template <class Tile, bool FFT> __global__ void __launch_bounds__(WG) tiled_kernel(const KArgs a)
+// Streamed tiles with FFT feedback are capped at 128 VGPRs (four waves per
+// SIMD) so that two workgroups share a CU, as the direct-gather ones do.
+template <class Tile, bool FFT>
+__global__ void __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(FFT && !Tile::kResident ? 4 : 1)))
+tiled_kernel(const KArgs a)
 {
     constexpr int V = Tile::kV;
     using PT = typename Tile::psf_t;
