@@ -162,6 +162,9 @@ def main():
         return r, wall / args.steps * 1e3, float(np.mean(dev_ms))
 
     rt, ms_t, kms_t = timed(tiled, "tiled")
+    if args.no_plain:
+        print(json.dumps({"tiled_kernel_ms": kms_t, "steps": args.steps}), flush=True)
+        return
     # the interval tuner on this input and on its 10-minute-track variant
     tuner = {}
     for nm, cfg_psf in (("snapshot", psf), ("track", None)):
@@ -178,16 +181,13 @@ def main():
     tiled_fft = {"kernel_ms": rf["stats"]["device_ms"], "n_rounds": rf["stats"]["n_rounds"],
                  "phase_us": rf["stats"]["phase_us"],
                  "note": "the same workload with the feedback sums computed by FFT convolution"}
-    if args.no_plain:
-        print(json.dumps({"tiled_kernel_ms": kms_t, "steps": args.steps}), flush=True)
-        return
     rp, ms_p, kms_p = timed(plain, "plain")
     st_t, st_p = rt["stats"], rp["stats"]
     idx_t = rt["idx"].cpu().numpy()
     model_t = rt["model"].cpu().numpy()
     model_p = rp["model"].cpu().numpy()
 
-    # algorithmic bytes: local iterations T^2 (8 + s_psf), feedback rounds
+    # algorithmic bytes: local iterations T^2 (8 + s_psf) each, feedback rounds K_d (N^2 - T^2) s_psf + 8 N^2
     tpix = (ny // tiles[0]) * (nx // tiles[1])
     bytes_local = st_t["n_iter"] * tpix * (8.0 + s_psf)
     bytes_fb = feedback_bytes(idx_t, ny, nx, tiles, interval, st_t["n_iter"], s_psf)
@@ -224,6 +224,10 @@ def main():
         "track_psf_interval10": band(ctrack, 0.0, 10),
         "track_psf_flux_level_0.5": band(ctrack, 0.5, interval),
     }
+    for nm, cfg in (("snapshot", c), ("track", ctrack)):
+        ti = tuner[nm]["chosen"]
+        if ti:
+            jy["bands_tiled_minus_plain"][f"{nm}_psf_tuned_interval{ti}"] = band(cfg, 0.0, ti)
     jy["bands_note"] = ("differences tiled - plain (Jy) after the same 20000 total minor iterations; "
                         "restored = model (*) Gaussian clean beam fitted to the PSF main lobe + residual")
 
