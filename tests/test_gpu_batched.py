@@ -99,3 +99,22 @@ def test_batched_config3_sampled(lib):
         p = probs[i]
         ref = oracle.hogbom(p["dirty"], p["psf"], 0.1, p["threshold"], 100000)
         assert_same_run(outs[i], ref)
+
+
+def test_batched_degenerate_problems(lib):
+    """A batch of edge cases: no iterations asked, a 1 x 1 image, an image
+    whose peak is already under the threshold, a zero image, capacity 0."""
+    probs = [random_problem(40, 16, 20, 0.0, 0),                 # max_iter 0: the dirty image back
+             random_problem(41, 1, 1, 0.0, 5),                   # 1 x 1 image, 2 x 2 PSF (+ extra)
+             dict(random_problem(42, 24, 24, 0.0, 50)),
+             dict(random_problem(43, 12, 16, 0.0, 30)),
+             dict(random_problem(44, 20, 12, 0.0, 40), cap=0)]
+    probs[2]["threshold"] = 10.0                                  # first peak below the threshold
+    probs[3]["dirty"] = np.zeros((12, 16), np.float32)            # ties everywhere: index 0 each time
+    announce("batched degenerate")
+    outs = lib.batched(to_dev(probs), gain=0.1)
+    for p, o in zip(probs, outs):
+        ref = oracle.hogbom(p["dirty"], p["psf"], 0.1, p["threshold"], p["max_iter"], cap=p.get("cap"))
+        assert_same_run(o, ref)
+    assert outs[0]["stats"]["n_iter"] == 0 and outs[2]["stats"]["n_iter"] == 0
+    assert outs[4]["stats"]["n_iter"] == 0 and outs[4]["stats"]["stop_reason"] == 2

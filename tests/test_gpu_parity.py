@@ -356,3 +356,37 @@ def test_interval_tuner_selection_rule(lib, track):
         assert t["interval"] == 0
     if not track:
         assert not ok[cands.index(100)]
+
+
+# ------------------------------------------------------------- many tiles --
+
+@pytest.mark.parametrize("case", [
+    # ny, nx, tiles, interval, seed, n, threshold
+    (128, 128, (16, 16), 8, 81, 2400, 0.0),     # 256 tiles of 8 x 8 (the paper's largest count): one workgroup each
+    (96, 130, (16, 10), 5, 82, 1500, 0.02),     # 160 ragged tiles (widths 13 and 12: scalar groups), threshold stop
+], ids=["16x16-of-8x8", "16x10-ragged"])
+def test_tiled_many_tiles(lib, case):
+    ny, nx, tiles, interval, seed, n, thr = case
+    announce("tiled many tiles", case)
+    dirty = sparse_dirty(ny, nx, seed, density=0.05)
+    psf = asym_psf(2 * ny, 2 * nx + 2, seed, spread=0.2)
+    ref = oracle.tiled(dirty, psf, tiles, interval, 0.1, thr, n)
+    out = lib.tiled_feedback(dev(dirty), dev(psf), tiles, interval, 0.1, thr, n)
+    assert out["stats"]["n_rounds"] == ref["n_rounds"]
+    assert_same_run(out, ref)
+
+
+def test_tiled_more_tiles_than_coresident_workgroups(lib):
+    """1024 tiles (the library's maximum) need 1024 co-resident workgroups,
+    more than this GPU holds for these kernels: the call must fail cleanly
+    with CLEAN_E_UNSUPPORTED (or, on a GPU that holds them, match the oracle)."""
+    announce("tiled 32x32 tiles")
+    dirty = sparse_dirty(128, 128, 83, density=0.05)
+    psf = asym_psf(256, 258, 83, spread=0.2)
+    try:
+        out = lib.tiled_feedback(dev(dirty), dev(psf), (32, 32), 2, 0.1, 0.0, 4096)
+    except lib.CleanError as err:
+        assert err.status == -6, err          # CLEAN_E_UNSUPPORTED
+        return
+    ref = oracle.tiled(dirty, psf, (32, 32), 2, 0.1, 0.0, 4096)
+    assert_same_run(out, ref)
