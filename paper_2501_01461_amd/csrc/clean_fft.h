@@ -31,59 +31,6 @@ __device__ __forceinline__ void stc2(float2 *p, float2 v)
 
 __device__ __forceinline__ uint32_t bitrev(uint32_t i, int lg) { return __builtin_bitreverse32(i) >> (32 - lg); }
 
-// In-place FFT of a[0 .. 2^lg) (bit-reversed input, natural-order output).
-// inverse: conjugate twiddles (no 1/L scaling).  All threads of the workgroup.
-__device__ inline void fft_lds(float2 *a, int lg, const float2 *tw, bool inverse)
-{
-    const int H = 1 << (lg - 1);
-    __syncthreads();
-    #pragma clang loop unroll(disable)
-    for (int s = 0; s < lg; ++s) {
-        const int half = 1 << s;
-        #pragma clang loop unroll(disable)
-        for (int j = threadIdx.x; j < H; j += blockDim.x) {
-            const int k = j & (half - 1);
-            const int i0 = ((j >> s) << (s + 1)) + k, i1 = i0 + half;
-            float2 w = tw[k << (lg - 1 - s)];
-            if (inverse) w.y = -w.y;
-            const float2 u = a[i0], v = a[i1];
-            const float2 t = make_float2(v.x * w.x - v.y * w.y, v.x * w.y + v.y * w.x);
-            a[i0] = make_float2(u.x + t.x, u.y + t.y);
-            a[i1] = make_float2(u.x - t.x, u.y - t.y);
-        }
-        __syncthreads();
-    }
-}
-
-// `count` independent in-place transforms of length 2^lg, segment i at
-// a[i * stride ..], bit-reversed input, natural output.  tw is a table of
-// W_L^m for a length L = 2^lg * tw_step (entries m < L/2 are read).
-__device__ inline void fft_lds_multi(float2 *a, int lg, int count, int stride, const float2 *tw, int tw_step,
-                                     bool inverse)
-{
-    const int H = 1 << (lg - 1);
-    const int total = count * H;
-    __syncthreads();
-    #pragma clang loop unroll(disable)
-    for (int s = 0; s < lg; ++s) {
-        const int half = 1 << s;
-        #pragma clang loop unroll(disable)
-        for (int j = threadIdx.x; j < total; j += blockDim.x) {
-            const int seg = j >> (lg - 1), jj = j & (H - 1);
-            const int k = jj & (half - 1);
-            float2 *b = a + seg * stride;
-            const int i0 = ((jj >> s) << (s + 1)) + k, i1 = i0 + half;
-            float2 w = tw[(k << (lg - 1 - s)) * tw_step];
-            if (inverse) w.y = -w.y;
-            const float2 u = b[i0], v = b[i1];
-            const float2 t = make_float2(v.x * w.x - v.y * w.y, v.x * w.y + v.y * w.x);
-            b[i0] = make_float2(u.x + t.x, u.y + t.y);
-            b[i1] = make_float2(u.x - t.x, u.y - t.y);
-        }
-        __syncthreads();
-    }
-}
-
 __device__ __forceinline__ float2 cmul(float2 p, float2 q)
 {
     return make_float2(p.x * q.x - p.y * q.y, p.x * q.y + p.y * q.x);
@@ -91,6 +38,69 @@ __device__ __forceinline__ float2 cmul(float2 p, float2 q)
 __device__ __forceinline__ float2 cmulc(float2 p, float2 q)   // p * conj(q)
 {
     return make_float2(p.x * q.x + p.y * q.y, p.y * q.x - p.x * q.y);
+}
+
+// `count` independent in-place transforms of length 2^lg, segment i at
+// a[i * stride ..], bit-reversed input, natural output; inverse: conjugate
+// twiddles, no 1/L scaling.  tw is a table of W_L^m for a length
+// L = 2^lg * tw_step (entries m < L/2 are read).  Stages go two at a time
+// (radix 4: one thread reads four points, applies both radix-2 stages in
+// registers and writes them back), after one plain radix-2 stage when lg is
+// odd.  In a stage pair (s, s+1) the second stage's twiddle for the odd
+// butterfly is W_4 times the even one's, an exact rotation by -i (+i for the
+// inverse).  All threads of the workgroup.
+__device__ inline void fft_lds_multi(float2 *a, int lg, int count, int stride, const float2 *tw, int tw_step,
+                                     bool inverse)
+{
+    __syncthreads();
+    int s = 0;
+    if (lg & 1) {
+        const int H = 1 << (lg - 1);
+#pragma clang loop unroll(disable)
+        for (int j = threadIdx.x; j < count * H; j += blockDim.x) {
+            float2 *b = a + (j >> (lg - 1)) * stride + 2 * (j & (H - 1));
+            const float2 u = b[0], v = b[1];
+            b[0] = make_float2(u.x + v.x, u.y + v.y);
+            b[1] = make_float2(u.x - v.x, u.y - v.y);
+        }
+        __syncthreads();
+        s = 1;
+    }
+    const int Q = lg >= 2 ? 1 << (lg - 2) : 0;
+#pragma clang loop unroll(disable)
+    for (; s < lg; s += 2) {
+        const int half = 1 << s;
+#pragma clang loop unroll(disable)
+        for (int j = threadIdx.x; j < count * Q; j += blockDim.x) {
+            const int jj = j & (Q - 1);
+            const int k = jj & (half - 1);
+            float2 *b = a + (j >> (lg - 2)) * stride + ((jj >> s) << (s + 2)) + k;
+            float2 w1 = tw[(k << (lg - 1 - s)) * tw_step];
+            float2 w2 = tw[(k << (lg - 2 - s)) * tw_step];
+            if (inverse) {
+                w1.y = -w1.y;
+                w2.y = -w2.y;
+            }
+            const float2 x0 = b[0], x1 = b[half], x2 = b[2 * half], x3 = b[3 * half];
+            const float2 p1 = cmul(x1, w1), p3 = cmul(x3, w1);
+            const float2 a0 = make_float2(x0.x + p1.x, x0.y + p1.y), a1 = make_float2(x0.x - p1.x, x0.y - p1.y);
+            const float2 a2 = make_float2(x2.x + p3.x, x2.y + p3.y), a3 = make_float2(x2.x - p3.x, x2.y - p3.y);
+            const float2 t = cmul(a2, w2), v = cmul(a3, w2);
+            const float2 u = inverse ? make_float2(-v.y, v.x) : make_float2(v.y, -v.x);
+            b[0] = make_float2(a0.x + t.x, a0.y + t.y);
+            b[2 * half] = make_float2(a0.x - t.x, a0.y - t.y);
+            b[half] = make_float2(a1.x + u.x, a1.y + u.y);
+            b[3 * half] = make_float2(a1.x - u.x, a1.y - u.y);
+        }
+        __syncthreads();
+    }
+}
+
+// In-place FFT of a[0 .. 2^lg) (bit-reversed input, natural-order output),
+// tw the table W_L^m of this length.  All threads of the workgroup.
+__device__ inline void fft_lds(float2 *a, int lg, const float2 *tw, bool inverse)
+{
+    fft_lds_multi(a, lg, 1, 1 << lg, tw, 1, inverse);
 }
 
 // Puts a natural-order array into bit-reversed order, in place.
