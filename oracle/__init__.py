@@ -54,6 +54,10 @@ def load():
     for f in (lib.oracle_hogbom_f32, lib.oracle_hogbom_f64, lib.oracle_tiled_f32, lib.oracle_tiled_f64,
               lib.oracle_feedback_f32, lib.oracle_feedback_f64):
         f.restype = C.c_int
+    lib.oracle_main_lobe_area.argtypes = [P, i32, i32]
+    lib.oracle_main_lobe_area.restype = i64
+    lib.oracle_restore_f64.argtypes = [P, P, i32, i32, f64, P]
+    lib.oracle_restore_f64.restype = C.c_int
     _lib = lib
     return lib
 
@@ -137,3 +141,31 @@ def feedback(residual, psf, tiles, comp_tile, comp_idx, comp_flux, precision="f3
     if st != 0:
         raise ValueError(f"oracle_feedback returned {st}")
     return r
+
+
+def main_lobe_area(psf):
+    """Pixels of the PSF's main lobe: the 4-connected region above one half
+    that contains the centre (-1 if the centre is not above one half)."""
+    psf = np.ascontiguousarray(psf, dtype=np.float32)
+    return int(load().oracle_main_lobe_area(_ptr(psf), psf.shape[0], psf.shape[1]))
+
+
+def beam_sigma(psf):
+    """Clean-beam sigma (pixels): FWHM = 2 sqrt(A / pi), A the main-lobe area."""
+    area = main_lobe_area(psf)
+    if area <= 0:
+        raise ValueError("PSF centre is not above one half")
+    return 2.0 * np.sqrt(area / np.pi) / (2.0 * np.sqrt(2.0 * np.log(2.0)))
+
+
+def restore(model, residual, sigma):
+    """Restored image (float64): residual + model (*) exp(-|d|^2 / (2 sigma^2)),
+    over the square window |d| <= ceil(5 sigma)."""
+    model = np.ascontiguousarray(model, dtype=np.float64)
+    residual = np.ascontiguousarray(residual, dtype=np.float32)
+    out = np.empty(model.shape, np.float64)
+    st = load().oracle_restore_f64(_ptr(model), _ptr(residual), model.shape[0], model.shape[1], float(sigma),
+                                   _ptr(out))
+    if st != 0:
+        raise ValueError(f"oracle_restore_f64 returned {st}")
+    return out

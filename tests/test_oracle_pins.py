@@ -388,3 +388,81 @@ def test_fp32_close_to_fp64_on_the_small_workload():
     b = oracle.hogbom(c["dirty"], c["psf"], 0.1, 5e-3, 1000, precision="f64")
     assert a["n_iter"] == b["n_iter"]
     assert np.max(np.abs(a["model"] - b["model"])) < 1e-5
+
+
+# ------------------------------------------------------------ restoration --
+
+def _gauss_psf(M, sigma, r):
+    """Peak-1 circular Gaussian PSF on an M x M grid plus small noise far out."""
+    y, x = np.mgrid[0:M, 0:M] - M // 2
+    g = np.exp(-(x * x + y * y) / (2.0 * sigma * sigma))
+    g += r.uniform(-0.05, 0.05, g.shape) * (g < 1e-3)
+    g[M // 2, M // 2] = 1.0
+    return g.astype(np.float32)
+
+
+def test_main_lobe_area_matches_connected_component_labelling():
+    """Against scipy.ndimage.label (4-connectivity) on Y-array and asymmetric PSFs."""
+    from scipy import ndimage
+    psfs = [synth.make_config(0)["psf"], synth.y_array_psf(256, np.random.default_rng(5)).astype(np.float32)]
+    r = np.random.default_rng(3)
+    p = r.uniform(-0.3, 0.9, (60, 70)).astype(np.float32)
+    p[30, 35] = 1.0
+    psfs.append(p)
+    for psf in psfs:
+        lab, _ = ndimage.label(psf > 0.5)
+        ref = int(np.count_nonzero(lab == lab[psf.shape[0] // 2, psf.shape[1] // 2]))
+        assert oracle.main_lobe_area(psf) == ref
+
+
+def test_main_lobe_area_of_a_gaussian_psf():
+    """For a peak-1 Gaussian PSF the region above one half is exactly the
+    lattice points with x^2 + y^2 < 2 sigma^2 ln 2 (a connected disc), so the
+    area is that count; the sigma recovered from it approaches the true one
+    as the disc grows (pixel discretisation: 10% at sigma 2, 2.5% at 6)."""
+    r = np.random.default_rng(7)
+    prev = 1.0
+    for s0 in (2.0, 3.5, 6.0):
+        psf = _gauss_psf(128, s0, r)
+        y, x = np.mgrid[-64:64, -64:64]
+        assert oracle.main_lobe_area(psf) == int(np.count_nonzero(x * x + y * y < 2 * s0 * s0 * np.log(2.0)))
+        rel = abs(oracle.beam_sigma(psf) - s0) / s0
+        assert rel < 0.11 and rel <= prev
+        prev = rel
+
+
+def test_main_lobe_area_centre_not_above_half():
+    psf = np.full((16, 16), 0.2, np.float32)
+    assert oracle.main_lobe_area(psf) == -1
+
+
+def test_restore_single_component_closed_form():
+    """One component of flux f at p and a zero residual: out = f exp(-|q-p|^2 / 2 s^2)
+    inside the window |q-p| <= ceil(5 s) (clipped at the image edge), 0 outside."""
+    ny, nx, s = 40, 52, 2.3
+    R = int(np.ceil(5 * s))
+    for (py, px) in [(20, 26), (2, 3), (39, 51)]:
+        m = np.zeros((ny, nx))
+        m[py, px] = 1.75
+        out = oracle.restore(m, np.zeros((ny, nx), np.float32), s)
+        y, x = np.mgrid[0:ny, 0:nx]
+        exp = 1.75 * np.exp(-((y - py) ** 2 + (x - px) ** 2) / (2 * s * s))
+        exp[(np.abs(y - py) > R) | (np.abs(x - px) > R)] = 0.0
+        assert np.allclose(out, exp, rtol=1e-14, atol=1e-300)
+        assert out[py, px] == 1.75                         # beam peak exactly 1
+
+
+def test_restore_linear_and_adds_the_residual():
+    """Random sparse model and residual against scipy's direct 2-D convolution
+    with the sampled beam kernel (float64)."""
+    from scipy import signal
+    r = np.random.default_rng(11)
+    ny, nx, s = 48, 36, 1.7
+    R = int(np.ceil(5 * s))
+    m = np.where(r.random((ny, nx)) < 0.05, r.normal(0, 1, (ny, nx)), 0.0)
+    res = r.normal(0, 0.1, (ny, nx)).astype(np.float32)
+    d = np.arange(-R, R + 1)
+    k = np.exp(-(d[:, None] ** 2 + d[None, :] ** 2) / (2 * s * s))
+    ref = signal.convolve2d(m, k, mode="same") + res.astype(np.float64)
+    out = oracle.restore(m, res, s)
+    assert np.abs(out - ref).max() < 1e-12
