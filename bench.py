@@ -50,24 +50,6 @@ def measured_traffic():
     return rec if rec.get("source_sha256") == h.hexdigest() else None
 
 
-def clean_beam_sigma(psf):
-    """Gaussian clean beam from the PSF main lobe: FWHM = 2 sqrt(A/pi), with A
-    the area (pixels) of the connected region around the peak above one half."""
-    from scipy import ndimage
-    M0, M1 = psf.shape
-    lab, _ = ndimage.label(psf > 0.5)
-    area = float(np.count_nonzero(lab == lab[M0 // 2, M1 // 2]))
-    fwhm = 2.0 * np.sqrt(area / np.pi)
-    return fwhm / (2.0 * np.sqrt(2.0 * np.log(2.0)))
-
-
-def restored(model, residual, sigma):
-    """model (*) peak-1 Gaussian beam + residual, in Jy/beam (evaluation only)."""
-    from scipy import ndimage
-    sm = ndimage.gaussian_filter(model, sigma, mode="constant", truncate=5.0) * (2.0 * np.pi * sigma * sigma)
-    return sm + residual.astype(np.float64)
-
-
 def feedback_bytes(idx, ny, nx, tiles, interval, n_total, psf_bytes):
     """Algorithmic bytes of the feedback rounds of a threshold-0 run.
 
@@ -209,8 +191,8 @@ def main():
         mp = P.hogbom(d_, p_, gain, thr, n_iter)
         mt_m, mp_m = mt["model"].cpu().numpy(), mp["model"].cpu().numpy()
         dm = mt_m - mp_m
-        sg = clean_beam_sigma(cfg["psf"])
-        dr = restored(mt_m, mt["residual"].cpu().numpy(), sg) - restored(mp_m, mp["residual"].cpu().numpy(), sg)
+        sg = P.clean_beam(p_)["sigma"]
+        dr = (P.restore(mt["model"], mt["residual"], sg) - P.restore(mp["model"], mp["residual"], sg)).cpu().numpy()
         out = {"model_min": float(dm.min()), "model_max": float(dm.max()),
                "restored_min": float(dr.min()), "restored_max": float(dr.max()),
                "rounds": mt["stats"]["n_rounds"], "tiled_ms": mt["stats"]["device_ms"]}
@@ -228,8 +210,10 @@ def main():
         ti = tuner[nm]["chosen"]
         if ti:
             jy["bands_tiled_minus_plain"][f"{nm}_psf_tuned_interval{ti}"] = band(cfg, 0.0, ti)
+    jy["clean_beam"] = P.clean_beam(psf)
     jy["bands_note"] = ("differences tiled - plain (Jy) after the same 20000 total minor iterations; "
-                        "restored = model (*) Gaussian clean beam fitted to the PSF main lobe + residual")
+                        "restored = clean_restore: model (*) peak-1 circular Gaussian clean beam (clean_beam_fit: "
+                        "FWHM = 2 sqrt(A/pi), A the PSF main lobe above one half) + residual")
 
     cpu = None
     if not args.no_cpu or not args.no_jy:

@@ -280,6 +280,33 @@ int clean_autotune_interval(const float *dirty, int ny, int nx, const void *psf,
 size_t clean_workspace_size(int ny, int nx, int tiles_y, int tiles_x,
                             int feedback_interval, const clean_params *p);
 
+/*
+ * Restoration: the "reconstructed image" of the paper's comparison (Section 4)
+ * read as the usual restored image, the model convolved with a circular
+ * Gaussian clean beam of peak 1, plus the residual.
+ *
+ * clean_beam_fit -- the clean beam of a PSF (device memory, psf_ny x psf_nx,
+ * dtype CLEAN_PSF_F32/F16, centre (psf_ny/2, psf_nx/2)): *area (host) gets the
+ * pixel count of the main lobe (the 4-connected region of values above one
+ * half containing the centre) and *sigma (host) the beam's standard deviation
+ * in pixels, FWHM / (2 sqrt(2 ln 2)) with FWHM = 2 sqrt(area / pi).  Reads a
+ * crop about the centre (grown until the lobe stays inside it); synchronous.
+ * CLEAN_E_INVAL for NULL pointers, a bad size or dtype, or a centre value not
+ * above one half.
+ *
+ * clean_restore -- out[q] = residual[q] + sum over |dy|, |dx| <= R of
+ * model[q - d] exp(-(dy^2 + dx^2) / (2 sigma^2)), R = ceil(5 sigma), pixels
+ * outside the image counting as zero.  model and out float64 [ny][nx],
+ * residual float32 [ny][nx], all device memory owned by the caller (out must
+ * not alias the inputs); computed in float64 as two separable passes (the
+ * library's workspace holds the intermediate); synchronous on `stream`.
+ * CLEAN_E_INVAL for NULL pointers, a bad size or sigma outside (0, 1000].
+ */
+int clean_beam_fit(const void *psf, int psf_ny, int psf_nx, int psf_dtype, int64_t *area, double *sigma,
+                   void *stream);
+int clean_restore(const double *model, const float *residual, int ny, int nx, double sigma, double *out,
+                  void *stream);
+
 /* FP32 -> FP16 (round to nearest even) of n values, on `stream`; synchronous. */
 int clean_psf_to_f16(const float *psf, uint16_t *out, int64_t n, void *stream);
 

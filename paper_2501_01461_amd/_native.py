@@ -8,6 +8,7 @@ calls raise.
 from __future__ import annotations
 
 import ctypes as C
+import math
 import os
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -25,7 +26,8 @@ FLAG_FFT_TWO_LEVEL = 8
 
 # every symbol include/clean.h declares
 EXPORTS = ("clean_hogbom", "clean_tiled_feedback", "clean_batched", "clean_autotune", "clean_autotune_interval",
-           "clean_workspace_size", "clean_psf_to_f16", "clean_strerror", "clean_last_error", "clean_version")
+           "clean_beam_fit", "clean_restore", "clean_workspace_size", "clean_psf_to_f16", "clean_strerror",
+           "clean_last_error", "clean_version")
 
 
 class Params(C.Structure):
@@ -82,6 +84,10 @@ def load():
     lib.clean_autotune_interval.argtypes = [P, i32, i32, P, i32, i32, i32, i32, P, i32, C.POINTER(Params), i64,
                                             C.c_double, P, P, P, i64, C.POINTER(C.c_int), P, P, P]
     lib.clean_autotune_interval.restype = C.c_int
+    lib.clean_beam_fit.argtypes = [P, i32, i32, i32, C.POINTER(C.c_int64), C.POINTER(C.c_double), P]
+    lib.clean_beam_fit.restype = C.c_int
+    lib.clean_restore.argtypes = [P, P, i32, i32, C.c_double, P, P]
+    lib.clean_restore.restype = C.c_int
     lib.clean_workspace_size.argtypes = [i32, i32, i32, i32, i32, C.POINTER(Params)]
     lib.clean_workspace_size.restype = sz
     lib.clean_psf_to_f16.argtypes = [P, P, i64, P]
@@ -276,6 +282,34 @@ def autotune_interval(dirty, psf, tiles, candidates, gain=0.1, threshold=0.0, ma
                                        C.byref(chosen), C.cast(rates, C.c_void_p), C.cast(ratios, C.c_void_p),
                                        _stream()))
     return dict(interval=chosen.value, rates=list(rates), peak_ratios=list(ratios))
+
+
+def clean_beam(psf):
+    """The clean beam of a device PSF: dict(area (main-lobe pixels), sigma, fwhm) in pixels."""
+    torch = _torch()
+    lib = load()
+    psf = psf.contiguous()
+    dt = PSF_F16 if psf.dtype == torch.float16 else PSF_F32
+    if psf.dtype not in (torch.float16, torch.float32):
+        raise TypeError("psf must be float32 or float16")
+    area, sigma = C.c_int64(0), C.c_double(0.0)
+    _check(lib.clean_beam_fit(_ptr(psf), psf.shape[0], psf.shape[1], dt, C.byref(area), C.byref(sigma), _stream()))
+    return dict(area=area.value, sigma=sigma.value, fwhm=sigma.value * 2.0 * (2.0 * math.log(2.0)) ** 0.5)
+
+
+def restore(model, residual, sigma):
+    """Restored image (float64 device tensor): residual + model (*) peak-1
+    Gaussian clean beam of standard deviation sigma (pixels)."""
+    torch = _torch()
+    lib = load()
+    model = model.contiguous()
+    residual = residual.contiguous()
+    if model.dtype != torch.float64 or residual.dtype != torch.float32 or model.shape != residual.shape:
+        raise TypeError("model must be float64 and residual float32, of one shape")
+    out = torch.empty(model.shape, dtype=torch.float64, device=model.device)
+    _check(lib.clean_restore(_ptr(model), _ptr(residual), model.shape[0], model.shape[1], float(sigma), _ptr(out),
+                             _stream()))
+    return out
 
 
 def psf_to_f16(psf):

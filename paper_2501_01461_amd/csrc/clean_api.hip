@@ -30,6 +30,9 @@ __global__ void finite_check_kernel(const float *x, int64_t n, uint32_t *flag);
 __global__ void finite_check_half_kernel(const unsigned short *x, int64_t n, uint32_t *flag);
 __global__ void to_half_kernel(const float *x, unsigned short *y, int64_t n);
 __global__ void finalize_kernel(const double *partial, int n, DevStat *st);
+__global__ void restore_rows_kernel(const double *model, double *tmp, int ny, int nx, const double *b, int R);
+__global__ void restore_cols_kernel(const double *tmp, const float *residual, double *out, int ny, int nx,
+                                    const double *b, int R);
 } // namespace cleanhip
 
 using namespace cleanhip;
@@ -952,6 +955,94 @@ int clean_autotune_interval(const float *dirty, int ny, int nx, const void *psf,
             *interval = candidates[i];
         }
     }
+    return CLEAN_OK;
+}
+
+int clean_beam_fit(const void *psf, int psf_ny, int psf_nx, int psf_dtype, int64_t *area, double *sigma,
+                   void *stream_v)
+{
+    g_last_error.clear();
+    if (!psf || !area || !sigma) return fail(CLEAN_E_INVAL, "psf, area and sigma must be non-NULL");
+    if (psf_ny < 1 || psf_nx < 1) return fail(CLEAN_E_INVAL, "PSF size %d x %d", psf_ny, psf_nx);
+    if (psf_dtype != CLEAN_PSF_F32 && psf_dtype != CLEAN_PSF_F16) return fail(CLEAN_E_INVAL, "psf_dtype %d", psf_dtype);
+    hipStream_t stream = (hipStream_t)stream_v;
+    const size_t es = psf_dtype == CLEAN_PSF_F16 ? 2 : 4;
+    const int cy = psf_ny / 2, cx = psf_nx / 2;
+    // a crop about the centre, doubled until the lobe does not reach its edge
+    for (int half = 32;; half *= 2) {
+        const int y0 = std::max(0, cy - half), y1 = std::min(psf_ny, cy + half);
+        const int x0 = std::max(0, cx - half), x1 = std::min(psf_nx, cx + half);
+        const int h = y1 - y0, w = x1 - x0;
+        std::vector<unsigned char> raw((size_t)h * w * es);
+        HIPCHK(hipMemcpy2DAsync(raw.data(), (size_t)w * es, (const char *)psf + ((size_t)y0 * psf_nx + x0) * es,
+                                (size_t)psf_nx * es, (size_t)w * es, h, hipMemcpyDeviceToHost, stream));
+        HIPCHK(hipStreamSynchronize(stream));
+        std::vector<float> v((size_t)h * w);
+        for (size_t i = 0; i < v.size(); ++i) {
+            if (es == 4) {
+                std::memcpy(&v[i], &raw[i * 4], 4);
+            } else {
+                __half hv;
+                std::memcpy(&hv, &raw[i * 2], 2);
+                v[i] = __half2float(hv);
+            }
+        }
+        const int c = (cy - y0) * w + (cx - x0);
+        if (!(v[c] > 0.5f)) return fail(CLEAN_E_INVAL, "PSF centre value %g is not above one half", (double)v[c]);
+        std::vector<unsigned char> seen(v.size(), 0);
+        std::vector<int> queue;
+        queue.reserve(1024);
+        queue.push_back(c);
+        seen[c] = 1;
+        bool edge = false;
+        for (size_t head = 0; head < queue.size(); ++head) {
+            const int q = queue[head], y = q / w, x = q % w;
+            if (y == 0 || x == 0 || y == h - 1 || x == w - 1) edge = true;
+            const int yy[4] = {y - 1, y + 1, y, y}, xx[4] = {x, x, x - 1, x + 1};
+            for (int k = 0; k < 4; ++k) {
+                if (yy[k] < 0 || yy[k] >= h || xx[k] < 0 || xx[k] >= w) continue;
+                const int r = yy[k] * w + xx[k];
+                if (!seen[r] && v[r] > 0.5f) {
+                    seen[r] = 1;
+                    queue.push_back(r);
+                }
+            }
+        }
+        const bool whole = y0 == 0 && x0 == 0 && y1 == psf_ny && x1 == psf_nx;
+        if (edge && !whole) continue;            // the lobe may go on past the crop
+        *area = (int64_t)queue.size();
+        *sigma = 2.0 * std::sqrt((double)*area / M_PI) / (2.0 * std::sqrt(2.0 * std::log(2.0)));
+        return CLEAN_OK;
+    }
+}
+
+int clean_restore(const double *model, const float *residual, int ny, int nx, double sigma, double *out,
+                  void *stream_v)
+{
+    g_last_error.clear();
+    if (!model || !residual || !out) return fail(CLEAN_E_INVAL, "model, residual and out must be non-NULL");
+    if (ny < 1 || nx < 1) return fail(CLEAN_E_INVAL, "image size %d x %d", ny, nx);
+    if (!(sigma > 0.0 && sigma <= 1000.0)) return fail(CLEAN_E_INVAL, "sigma %g not in (0, 1000]", sigma);
+    if ((int64_t)ny * nx > ((int64_t)1 << 31)) return fail(CLEAN_E_UNSUPPORTED, "image larger than 2^31 pixels");
+    hipStream_t stream = (hipStream_t)stream_v;
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    const int R = (int)std::ceil(5.0 * sigma);
+    const int64_t npix = (int64_t)ny * nx;
+    const size_t taps = align_up((size_t)(2 * R + 1) * 8, 256);
+    void *wp = nullptr;
+    int st = internal_workspace(dev, taps + (size_t)npix * 8, &wp);
+    if (st) return st;
+    double *b = (double *)wp;
+    double *tmp = (double *)((char *)wp + taps);
+    std::vector<double> hb(2 * R + 1);
+    for (int d = -R; d <= R; ++d) hb[d + R] = std::exp(-((double)d * d) / (2.0 * sigma * sigma));
+    HIPCHK(hipMemcpyAsync(b, hb.data(), hb.size() * 8, hipMemcpyHostToDevice, stream));
+    const int blocks = (int)std::min<int64_t>(8192, (npix + 255) / 256);
+    hipLaunchKernelGGL(restore_rows_kernel, dim3(blocks), dim3(256), 0, stream, model, tmp, ny, nx, b, R);
+    hipLaunchKernelGGL(restore_cols_kernel, dim3(blocks), dim3(256), 0, stream, tmp, residual, out, ny, nx, b, R);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(stream));
     return CLEAN_OK;
 }
 

@@ -148,6 +148,19 @@ def test_autotune_interval_argument_errors(lib):
     assert call(out=None) == INVAL
 
 
+def test_restoration_argument_errors(lib):
+    area, sigma = C.c_int64(0), C.c_double(0.0)
+    assert lib.clean_beam_fit(None, 32, 32, 0, C.byref(area), C.byref(sigma), None) == INVAL
+    assert lib.clean_beam_fit(FAKE, 0, 32, 0, C.byref(area), C.byref(sigma), None) == INVAL
+    assert lib.clean_beam_fit(FAKE, 32, 32, 5, C.byref(area), C.byref(sigma), None) == INVAL
+    assert lib.clean_beam_fit(FAKE, 32, 32, 0, None, C.byref(sigma), None) == INVAL
+    assert lib.clean_restore(None, FAKE, 16, 16, 2.0, FAKE, None) == INVAL
+    assert lib.clean_restore(FAKE, FAKE, 0, 16, 2.0, FAKE, None) == INVAL
+    assert lib.clean_restore(FAKE, FAKE, 16, 16, 0.0, FAKE, None) == INVAL
+    assert lib.clean_restore(FAKE, FAKE, 16, 16, float("nan"), FAKE, None) == INVAL
+    assert lib.clean_restore(FAKE, FAKE, 16, 16, 2000.0, FAKE, None) == INVAL
+
+
 def test_autotune_argument_errors(lib):
     p = params()
     best = N.Params()
