@@ -3,10 +3,12 @@
 // Sections 2 and 3).  Host entry points live in clean_api.hip.
 //
 // Design (one persistent, cooperatively launched kernel per call):
-//  * The residual lives in VGPRs for the whole run.  A tile (the whole image for
-//    plain CLEAN) is owned by a cluster of `cs` workgroups; thread t of cluster
-//    rank g owns K groups of V consecutive pixels, group k at tile-local flat
-//    index ((k*cs + g)*WG + t)*V.  Only the peak key crosses workgroups.
+//  * The residual lives in VGPRs for the whole run (RegTile), or, when the
+//    co-resident register file cannot hold it, in the caller's residual array,
+//    streamed every iteration (StreamTile).  A tile (the whole image for plain
+//    CLEAN) is owned by a cluster of `cs` workgroups; thread t of cluster rank
+//    g owns K groups of V consecutive pixels, group k at tile-local flat index
+//    ((k*cs + g)*WG + t)*V.  Only the peak key crosses workgroups.
 //  * One minor iteration: every thread applies r = fma(-c, psf[q - p + ctr], r)
 //    to its pixels and keeps its own largest |r| (lowest index on ties); a
 //    wave/LDS reduction gives the workgroup's key; the cluster's keys are
@@ -16,6 +18,10 @@
 //    published), after the feedback gather (all workgroups, including helpers,
 //    compute the cross-coupling sum for a share of the pixels into a float32
 //    buffer), and after each cluster has applied it and re-found its peak.
+//    The FFT form (a compile-time specialisation) replaces the gather by
+//    transform phases with grid barriers of their own.
+//  * The batched kernel deals many independent images to clusters from a
+//    seat queue; each runs the same plain minor loop.
 //  * Every wait is bounded: a wall-clock limit or an abort flag set by any
 //    workgroup ends it, and the kernel then returns with an error code.
 //
@@ -1484,7 +1490,8 @@ tiled_kernel(const KArgs a)
         }
         __syncthreads();
 
-        // ---- feedback by FFT: acc = (component image (*) K) - own tile's part
+        // ---- feedback by FFT: acc = component image (*) K, every tile's
+        // components (apply then starts from the round's starting residual)
         if constexpr (FFT) {
             if (!fft_feedback<PT>(a, y, epoch, &s_ok, s_off)) return;
         } else
