@@ -59,6 +59,53 @@ int fail(int code, const char *fmt, ...)
             return fail(CLEAN_E_HIP, "%s failed: %s", #call, hipGetErrorString(e_));       \
     } while (0)
 
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// ---------------------------------------------------- device -> host ----
+
+// Small device-to-host reads (stats, flags) go through a pinned buffer of
+// this thread: an asynchronous copy into pinned memory is complete once the
+// stream is synchronised.  The buffer grows as needed and is kept until the
+// process ends (no release from thread-exit destructors, which could run
+// after the runtime has begun to shut down).
+struct PinnedStage {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+};
+thread_local PinnedStage t_stage;
+
+// Copies n_parts (dst, src, bytes) device -> host on `stream` and waits.
+struct D2H {
+    void *dst;
+    const void *src;
+    size_t bytes;
+};
+int read_back(const D2H *parts, int n_parts, hipStream_t stream)
+{
+    size_t total = 0;
+    for (int i = 0; i < n_parts; ++i) total += align_up(parts[i].bytes, 64);
+    if (t_stage.bytes < total) {
+        if (t_stage.ptr) (void)hipHostFree(t_stage.ptr);
+        t_stage.ptr = nullptr;
+        t_stage.bytes = 0;
+        const size_t sz = std::max(total, (size_t)4096);
+        HIPCHK(hipHostMalloc(&t_stage.ptr, sz, hipHostMallocDefault));
+        t_stage.bytes = sz;
+    }
+    size_t o = 0;
+    for (int i = 0; i < n_parts; ++i) {
+        HIPCHK(hipMemcpyAsync((char *)t_stage.ptr + o, parts[i].src, parts[i].bytes, hipMemcpyDeviceToHost, stream));
+        o += align_up(parts[i].bytes, 64);
+    }
+    HIPCHK(hipStreamSynchronize(stream));
+    o = 0;
+    for (int i = 0; i < n_parts; ++i) {
+        std::memcpy(parts[i].dst, (char *)t_stage.ptr + o, parts[i].bytes);
+        o += align_up(parts[i].bytes, 64);
+    }
+    return CLEAN_OK;
+}
+
 // ------------------------------------------------------------ workspace --
 
 struct Workspace {
@@ -91,7 +138,6 @@ int internal_workspace(int dev, size_t need, void **out)
     return CLEAN_OK;
 }
 
-size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 // Layout of one call's workspace.  The header part (control block, stats,
 // exchange slots, tile keys, counts) is cleared before each launch.
@@ -557,8 +603,9 @@ int run(bool tiled, const float *dirty, int ny, int nx, const void *psf, int psf
                                (int64_t)psf_ny * psf_nx, flag);
         HIPCHK(hipGetLastError());
         uint32_t bad = 0;
-        HIPCHK(hipMemcpyAsync(&bad, flag, 4, hipMemcpyDeviceToHost, stream));
-        HIPCHK(hipStreamSynchronize(stream));
+        const D2H rb[1] = {{&bad, flag, 4}};
+        st = read_back(rb, 1, stream);
+        if (st) return st;
         if (bad) return fail(CLEAN_E_NONFINITE, "non-finite value in the dirty image or PSF");
     }
 
@@ -598,9 +645,9 @@ int run(bool tiled, const float *dirty, int ny, int nx, const void *psf, int psf
     HIPCHK(hipGetLastError());
     DevStat ds{};
     DevCtl ctl{};
-    HIPCHK(hipMemcpyAsync(&ds, a.dstat, sizeof ds, hipMemcpyDeviceToHost, stream));
-    HIPCHK(hipMemcpyAsync(&ctl, a.ctl, sizeof ctl, hipMemcpyDeviceToHost, stream));
-    HIPCHK(hipStreamSynchronize(stream));
+    const D2H rb[2] = {{&ds, a.dstat, sizeof ds}, {&ctl, a.ctl, sizeof ctl}};
+    st = read_back(rb, 2, stream);
+    if (st) return st;
     float ms = 0.f;
     HIPCHK(hipEventElapsedTime(&ms, e0, e1));
     (void)hipEventDestroy(e0);
@@ -767,8 +814,9 @@ int clean_batched(const clean_problem *probs, int n, const clean_params *shared,
         }
         HIPCHK(hipGetLastError());
         uint32_t bad = 0;
-        HIPCHK(hipMemcpyAsync(&bad, flag, 4, hipMemcpyDeviceToHost, stream));
-        HIPCHK(hipStreamSynchronize(stream));
+        const D2H rb[1] = {{&bad, flag, 4}};
+        st = read_back(rb, 1, stream);
+        if (st) return st;
         if (bad) return fail(CLEAN_E_NONFINITE, "non-finite value in a dirty image or PSF");
     }
     const int W = std::min(max_wg, seat0[n]);
@@ -788,9 +836,9 @@ int clean_batched(const clean_problem *probs, int n, const clean_params *shared,
     HIPCHK(hipGetLastError());
     std::vector<DevStat> ds(n);
     DevCtl ctl{};
-    HIPCHK(hipMemcpyAsync(ds.data(), ws + o_stat, sizeof(DevStat) * n, hipMemcpyDeviceToHost, stream));
-    HIPCHK(hipMemcpyAsync(&ctl, b.ctl, sizeof ctl, hipMemcpyDeviceToHost, stream));
-    HIPCHK(hipStreamSynchronize(stream));
+    const D2H rb[2] = {{ds.data(), ws + o_stat, sizeof(DevStat) * n}, {&ctl, b.ctl, sizeof ctl}};
+    st = read_back(rb, 2, stream);
+    if (st) return st;
     float ms = 0.f;
     HIPCHK(hipEventElapsedTime(&ms, e0, e1));
     (void)hipEventDestroy(e0);
@@ -973,20 +1021,26 @@ int clean_beam_fit(const void *psf, int psf_ny, int psf_nx, int psf_dtype, int64
         const int y0 = std::max(0, cy - half), y1 = std::min(psf_ny, cy + half);
         const int x0 = std::max(0, cx - half), x1 = std::min(psf_nx, cx + half);
         const int h = y1 - y0, w = x1 - x0;
-        std::vector<unsigned char> raw((size_t)h * w * es);
-        HIPCHK(hipMemcpy2DAsync(raw.data(), (size_t)w * es, (const char *)psf + ((size_t)y0 * psf_nx + x0) * es,
-                                (size_t)psf_nx * es, (size_t)w * es, h, hipMemcpyDeviceToHost, stream));
-        HIPCHK(hipStreamSynchronize(stream));
+        // staged through pinned host memory: an asynchronous copy into it is
+        // complete once the stream is synchronised
+        unsigned char *raw = nullptr;
+        HIPCHK(hipHostMalloc((void **)&raw, (size_t)h * w * es, hipHostMallocDefault));
         std::vector<float> v((size_t)h * w);
-        for (size_t i = 0; i < v.size(); ++i) {
-            if (es == 4) {
-                std::memcpy(&v[i], &raw[i * 4], 4);
-            } else {
-                __half hv;
-                std::memcpy(&hv, &raw[i * 2], 2);
-                v[i] = __half2float(hv);
+        hipError_t ce = hipMemcpy2DAsync(raw, (size_t)w * es, (const char *)psf + ((size_t)y0 * psf_nx + x0) * es,
+                                         (size_t)psf_nx * es, (size_t)w * es, h, hipMemcpyDeviceToHost, stream);
+        if (ce == hipSuccess) ce = hipStreamSynchronize(stream);
+        if (ce == hipSuccess)
+            for (size_t i = 0; i < v.size(); ++i) {
+                if (es == 4) {
+                    std::memcpy(&v[i], &raw[i * 4], 4);
+                } else {
+                    __half hv;
+                    std::memcpy(&hv, &raw[i * 2], 2);
+                    v[i] = __half2float(hv);
+                }
             }
-        }
+        (void)hipHostFree(raw);
+        if (ce != hipSuccess) return fail(CLEAN_E_HIP, "PSF crop copy: %s", hipGetErrorString(ce));
         const int c = (cy - y0) * w + (cx - x0);
         if (!(v[c] > 0.5f)) return fail(CLEAN_E_INVAL, "PSF centre value %g is not above one half", (double)v[c]);
         std::vector<unsigned char> seen(v.size(), 0);
