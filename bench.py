@@ -29,6 +29,7 @@ import numpy as np
 
 HBM_PEAK_GBS = 8000.0
 CALIB_BYTES = 512 << 20
+SINGLE_CORE_ITERS = 5000
 
 
 def log(*a):
@@ -75,6 +76,40 @@ def feedback_bytes(idx, ny, nx, tiles, interval, n_total, psf_bytes):
     return total
 
 
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def oracle_child(n_iter):
+    """Times the float32 tiled oracle on the first n_iter iterations of the
+    workload (run in a child process whose OpenMP pool has one thread)."""
+    import oracle
+    from paper_2501_01461_amd import synth
+    c = synth.make_config(1)
+    t1 = time.perf_counter()
+    r = oracle.tiled(c["dirty"], c["psf"], c["tiles"], c["interval"], c["gain"], c["threshold"], n_iter,
+                     precision="f32", model=False)
+    dt = time.perf_counter() - t1
+    print(json.dumps({"n_iter": r["n_iter"], "seconds": dt, "rounds": r["n_rounds"]}), flush=True)
+
+
+def oracle_single_core(n_iter):
+    import subprocess
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    out = subprocess.run([sys.executable, os.path.abspath(__file__), "--oracle-child", str(n_iter)], env=env,
+                         capture_output=True, text=True, timeout=300)
+    if out.returncode != 0:
+        log(f"single-core oracle run failed: {out.stderr[-400:]}")
+        return None
+    return json.loads(out.stdout.strip().splitlines()[-1])
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -86,7 +121,11 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the 256-problem batched measurement")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain comparison (profiling runs)")
     ap.add_argument("--no-4096", action="store_true", help="skip the 4096^2 / 8x8-tile measurement")
+    ap.add_argument("--oracle-child", type=int, default=0, help=argparse.SUPPRESS)
     args = ap.parse_args()
+    if args.oracle_child:
+        oracle_child(args.oracle_child)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the tiled CLEAN path here runs on a single device "
               "(multi-GPU sharding is a design note, not built); run with --gpus 1", file=sys.stderr)
@@ -238,6 +277,12 @@ def main():
         same = (np.array_equal(ro["idx"], idx_t) and
                 np.array_equal(ro["residual"].view(np.uint32), rt["residual"].cpu().numpy().view(np.uint32)))
         cpu["bit_identical_to_gpu"] = bool(same)
+        cpu["cpu_model"] = cpu_model()
+        one = oracle_single_core(SINGLE_CORE_ITERS)
+        if one:
+            cpu["single_core"] = {"value": one["n_iter"] / one["seconds"], "unit": "minor-iters/s", "cores": 1,
+                                  "sample": f"the first {one['n_iter']} iterations ({one['rounds']} rounds) of the "
+                                            f"same workload, float32 oracle, OpenMP threads=1, {one['seconds']:.1f} s"}
 
     batched = None
     if not args.no_batched:
