@@ -179,7 +179,9 @@ __device__ __forceinline__ void raise_abort(const Sync &y, uint32_t code)
 // ------------------------------------------------ cluster reduction ------
 
 // Cluster-wide max of the threads' keys for exchange number `e`.  A DPP wave
-// max, one LDS step, then wave 0 publishes the workgroup's key in its slot and
+// max, then wave 0 takes the max of the waves' keys from LDS (every lane reads
+// all of them: a short scalar-like chain, no second cross-lane pass),
+// publishes the workgroup's key in its slot and
 // polls the cluster's slots (agent-scope relaxed atomics) until every slot
 // carries this exchange's tag.  Two workgroup barriers per call.  Returns
 // false if the run was aborted; `out` is uniform on return.
@@ -194,7 +196,9 @@ __device__ bool cluster_reduce(const Sync &y, uint64_t *slots, int slot_pad, int
     if (lane == 0) s_wave[wave] = wk;
     __syncthreads();
     if (wave == 0) {
-        uint64_t g = wave_max64(lane < NWAVES ? s_wave[lane] : 0ull);
+        uint64_t g = s_wave[0];
+#pragma unroll
+        for (int w = 1; w < NWAVES; ++w) g = umax64(g, s_wave[w]);
         bool ok = true;
         if (cs > 1) {
             const uint64_t tag = (uint64_t)((e & 7u) + 1u);
