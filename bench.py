@@ -371,7 +371,8 @@ def main():
                                "200 sources, interval 100, 20000 total minor iterations, gain 0.1",
                    "psf_storage": "f16" if args.psf_f16 else "f32",
                    "launch": {"wg_per_tile": st_t["wg_per_tile"], "px_per_thread": st_t["px_per_thread"],
-                              "workgroups": st_t["workgroups"]}},
+                              "workgroups": st_t["workgroups"],
+                              "xcd_local_clusters": st_t["xcd_local_clusters"]}},
         "roofline": {"bound": "hbm", "achieved": gbs_t, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": gbs_t / HBM_PEAK_GBS,
                      "traffic": traffic["traffic_bytes_per_launch"] if traffic else None,

@@ -139,6 +139,11 @@ typedef struct {
     int32_t streamed;     /* 1: the residual was kept in HBM (image too large for
                              the register file of the co-resident workgroups);
                              0: held in registers for the whole run              */
+    int32_t xcd_local_clusters; /* tiled: tile clusters whose per-iteration peak
+                             exchange stayed inside one XCD's L2 (all their
+                             workgroups ran on one XCD, checked on the device);
+                             the others used device-scope exchanges.  0 for
+                             plain and batched calls                             */
 } clean_stats;
 
 /*

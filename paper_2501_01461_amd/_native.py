@@ -40,7 +40,8 @@ class Stats(C.Structure):
     _fields_ = [("n_iter", C.c_int64), ("stop_reason", C.c_int32), ("n_rounds", C.c_int32),
                 ("final_peak", C.c_double), ("residual_rms", C.c_double), ("model_flux", C.c_double),
                 ("device_ms", C.c_float), ("wg_per_tile", C.c_int32), ("px_per_thread", C.c_int32),
-                ("workgroups", C.c_int32), ("phase_us", C.c_float * 3), ("streamed", C.c_int32)]
+                ("workgroups", C.c_int32), ("phase_us", C.c_float * 3), ("streamed", C.c_int32),
+                ("xcd_local_clusters", C.c_int32)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_}

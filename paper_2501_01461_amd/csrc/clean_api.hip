@@ -142,7 +142,7 @@ int internal_workspace(int dev, size_t need, void **out)
 // Layout of one call's workspace.  The header part (control block, stats,
 // exchange slots, tile keys, counts) is cleared before each launch.
 struct Layout {
-    size_t ctl, dstat, xslots, tile_key, rb_n, ag_n, header_end;
+    size_t ctl, dstat, xslots, lslots, tile_key, rb_n, ag_n, header_end;
     size_t role, rb_idx, rb_flux, ag_pos, ag_flux, accbuf, partial;
     size_t fft_a, fft_b, fft_wx, fft_wy, fft_ks, comp_img, tw_x, tw_y, rstart, total;
 };
@@ -168,6 +168,7 @@ Layout make_layout(int T, int cs, int slot_pad, int interval, int W, int64_t npi
     L.ctl = o;       o = align_up(o + sizeof(DevCtl), 256);
     L.dstat = o;     o = align_up(o + sizeof(DevStat), 256);
     L.xslots = o;    o = align_up(o + (size_t)T * 2 * slot_pad * 8, 256);
+    L.lslots = o;    o = align_up(o + (size_t)T * 2 * slot_pad * 8, 256);
     L.tile_key = o;  o = align_up(o + (size_t)T * 8, 256);
     L.rb_n = o;      o = align_up(o + (size_t)T * 4, 256);
     L.ag_n = o;      o = align_up(o + (size_t)T * 4, 256);
@@ -567,6 +568,7 @@ int run(bool tiled, const float *dirty, int ny, int nx, const void *psf, int psf
     a.dstat = (DevStat *)(ws + L.dstat);
     a.role = (const int32_t *)(ws + L.role);
     a.xslots = (uint64_t *)(ws + L.xslots);
+    a.lslots = (uint64_t *)(ws + L.lslots);
     a.tile_key = (uint64_t *)(ws + L.tile_key);
     a.rb_idx = (int32_t *)(ws + L.rb_idx);
     a.rb_flux = (float *)(ws + L.rb_flux);
@@ -666,6 +668,7 @@ int run(bool tiled, const float *dirty, int ny, int nx, const void *psf, int psf
         stats->px_per_thread = ppt;
         stats->workgroups = W;
         stats->streamed = streamed;
+        stats->xcd_local_clusters = ds.xcd_local;
         const double us_per_tick = 1e6 / (double)(a.timeout_ticks / 20ull);
         for (int i = 0; i < 3; ++i) stats->phase_us[i] = (float)(ds.phase_ticks[i] * us_per_tick);
     }

@@ -41,6 +41,7 @@ struct DevStat {
     double model_flux;
     double sumsq;
     uint64_t phase_ticks[3];   // tiled: local loops, feedback gather, apply + re-peak (wall-clock ticks)
+    int32_t xcd_local;         // tiled: clusters whose exchanges stayed inside one XCD
 };
 
 // One plain CLEAN problem as a workgroup cluster sees it.
@@ -96,7 +97,8 @@ struct KArgs {
     DevCtl *ctl;
     DevStat *dstat;
     const int32_t *role;    // per workgroup: tile << 16 | rank, or -1 (helper)
-    uint64_t *xslots;       // [T][2][slot_pad]
+    uint64_t *xslots;       // [T][2][slot_pad] device-scope exchange slots
+    uint64_t *lslots;       // [T][2][slot_pad] XCD-local exchange slots
     uint64_t *tile_key;     // [T]
     int32_t *rb_idx;        // [T][interval] raw round lists
     float *rb_flux;

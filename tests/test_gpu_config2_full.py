@@ -131,6 +131,7 @@ def test_config2_stop_rule(runs):
     for fft, run in runs["runs"].items():
         st, res = run["stats"], run["residual"]
         assert len(run["idx"]) == st["n_iter"]
+        assert st["xcd_local_clusters"] == TILES[0] * TILES[1]
         if st["stop_reason"] == 0:
             assert st["n_iter"] == c["max_iter"]
         else:
