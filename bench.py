@@ -36,9 +36,10 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def measured_traffic():
+def measured_traffic(launch):
     """HBM bytes per launch of the tiled kernel from the committed rocprofv3
-    counter summary, or None when the kernel sources changed since then."""
+    counter summary, or None when the kernel sources or the launch shape
+    changed since then."""
     import hashlib
     root = os.path.dirname(os.path.abspath(__file__))
     path = os.path.join(root, "profiles", "traffic.json")
@@ -48,7 +49,9 @@ def measured_traffic():
     h = hashlib.sha256()
     for f in ("clean_kernels.hip", "clean_device.h"):
         h.update(open(os.path.join(root, "paper_2501_01461_amd", "csrc", f), "rb").read())
-    return rec if rec.get("source_sha256") == h.hexdigest() else None
+    if rec.get("source_sha256") != h.hexdigest() or rec.get("launch") != launch:
+        return None
+    return rec
 
 
 def feedback_bytes(idx, ny, nx, tiles, interval, n_total, psf_bytes):
@@ -183,8 +186,9 @@ def main():
         return r, wall / args.steps * 1e3, float(np.mean(dev_ms))
 
     rt, ms_t, kms_t = timed(tiled, "tiled")
+    launch_t = {"wg_per_tile": rt["stats"]["wg_per_tile"], "px_per_thread": rt["stats"]["px_per_thread"]}
     if args.no_plain:
-        print(json.dumps({"tiled_kernel_ms": kms_t, "steps": args.steps}), flush=True)
+        print(json.dumps({"tiled_kernel_ms": kms_t, "steps": args.steps, "launch": launch_t}), flush=True)
         return
     # the interval tuner on this input and on its 10-minute-track variant
     tuner = {}
@@ -353,7 +357,7 @@ def main():
                     np.max(np.abs(r["model"].cpu().numpy() - o64["model"])))
         log(f"4096^2 workload: {time.time() - t1:.1f} s")
 
-    traffic = measured_traffic()
+    traffic = measured_traffic(launch_t)
     line = {
         "metric": "CLEAN minor-iters/s + achieved GB/s: tiled-feedback vs plain, 1 GPU, at Jy error",
         "value": st_t["n_iter"] / (ms_t * 1e-3),
