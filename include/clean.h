@@ -139,11 +139,12 @@ typedef struct {
     int32_t streamed;     /* 1: the residual was kept in HBM (image too large for
                              the register file of the co-resident workgroups);
                              0: held in registers for the whole run              */
-    int32_t xcd_local_clusters; /* tiled: tile clusters whose per-iteration peak
-                             exchange stayed inside one XCD's L2 (all their
-                             workgroups ran on one XCD, checked on the device);
-                             the others used device-scope exchanges.  0 for
-                             plain and batched calls                             */
+    int32_t xcd_local_clusters; /* clusters whose per-iteration peak exchange
+                             stayed inside one XCD's L2 (all their workgroups
+                             ran on one XCD, checked on the device); the others
+                             used device-scope exchanges.  Tiled: tile clusters
+                             counted; batched: 1 or 0 for that problem; plain:
+                             0                                                   */
 } clean_stats;
 
 /*
@@ -233,7 +234,9 @@ typedef struct {
 /*
  * clean_batched -- n independent plain Hogbom problems in one persistent
  * launch.  Workgroup clusters take problems from a device queue, largest
- * first; each problem's result is identical to clean_hogbom on it alone.
+ * first: per XCD when every XCD holds the largest cluster (each problem then
+ * runs on one XCD, stats[i].xcd_local_clusters = 1), else across the device.
+ * Each problem's result is identical to clean_hogbom on it alone.
  *   probs  host array of n problems; stats host array of n (may be NULL).
  * Uses the library's internal workspace; n <= 65536.
  */

@@ -733,19 +733,45 @@ int clean_batched(const clean_problem *probs, int n, const clean_params *shared,
         max_pix = std::max<int64_t>(max_pix, (int64_t)q.ny * q.nx);
     }
     const int V = w4 ? 4 : 1;
+    hipStream_t stream = (hipStream_t)stream_v;
+    int dev = 0, ncu = 0;
+    HIPCHK(hipGetDevice(&dev));
+    HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    // grid size of a launch shape, and whether its clusters fit the per-XCD
+    // schedule (the grid's share of each XCD holds the largest cluster)
+    auto plan = [&](int pp, int &max_wg_out, bool &xcd_out) -> int {
+        BFn f = pick_batched(half, V, pp / V);
+        if (!f) return CLEAN_E_UNSUPPORTED;
+        int oc = 0;
+        HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&oc, (const void *)f, WG, 0));
+        int64_t seats = 0, mcs = 0;
+        for (int i = 0; i < n; ++i) {
+            const int64_t c = ((int64_t)probs[i].ny * probs[i].nx + (int64_t)WG * pp - 1) / ((int64_t)WG * pp);
+            seats += c;
+            mcs = std::max(mcs, c);
+        }
+        max_wg_out = oc * ncu;
+        const int64_t w = std::min<int64_t>(max_wg_out, seats);
+        xcd_out = w % 8 == 0 && mcs <= w / 8 && mcs < 4096;
+        return CLEAN_OK;
+    };
     int ppt = shared->px_per_thread;
-    // 64 pixels per thread: half the workgroups per problem against 32, so
-    // twice as many problems run at once and each exchange is shorter (256
-    // images of 128^2..1024^2: 144 ms against 193 ms)
-    if (ppt == 0) ppt = V == 4 ? 64 : 16;
+    if (ppt == 0) {
+        // 32 pixels per thread when the per-XCD schedule takes it: two
+        // workgroups per CU and exchanges inside one L2 (256 images of
+        // 128^2..1024^2: 138 ms).  Else 64: half the workgroups per problem,
+        // so twice as many problems run at once across the device (153 ms;
+        // 32 px/thread across the device: 182 ms).
+        ppt = V == 4 ? 64 : 16;
+        int mw = 0;
+        bool xok = false;
+        if (V == 4 && plan(32, mw, xok) == CLEAN_OK && xok) ppt = 32;
+    }
     if (!valid_ppt(V, ppt)) return fail(CLEAN_E_INVAL, "px_per_thread %d not available", ppt);
     const int K = ppt / V;
     BFn fn = pick_batched(half, V, K);
     if (!fn) return fail(CLEAN_E_UNSUPPORTED, "no batched kernel for %d x %d pixels per thread", K, V);
-    hipStream_t stream = (hipStream_t)stream_v;
-    int dev = 0, ncu = 0, occ = 0;
-    HIPCHK(hipGetDevice(&dev));
-    HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    int occ = 0;
     HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void *)fn, WG, 0));
     const int max_wg = occ * ncu;
 
@@ -777,10 +803,13 @@ int clean_batched(const clean_problem *probs, int n, const clean_params *shared,
     const size_t o_ctl = o;   o = align_up(o + sizeof(DevCtl), 256);
     const size_t o_stat = o;  o = align_up(o + sizeof(DevStat) * n, 256);
     const size_t o_slots = o; o = align_up(o + nslots * 8, 256);
+    const size_t o_xq = o;    o = align_up(o + sizeof(XcdQueue), 256);
     const size_t head_end = o;
+    const size_t o_lslots = o; o = align_up(o + nslots * 8, 256);
     const size_t o_jobs = o;  o = align_up(o + sizeof(PlainJob) * n, 256);
     const size_t o_seat = o;  o = align_up(o + sizeof(int32_t) * (n + 1), 256);
     const size_t o_part = o;  o = align_up(o + npart * 8, 256);
+    const size_t o_xtab = o;  o = align_up(o + (size_t)XQ_N * seat0[n] * sizeof(int32_t), 256);
     void *wp = nullptr;
     int st = internal_workspace(dev, o, &wp);
     if (st) return st;
@@ -806,17 +835,27 @@ int clean_batched(const clean_problem *probs, int n, const clean_params *shared,
         j.cap = q.comp_cap;
         j.comp_idx = q.comp_idx; j.comp_flux = q.comp_flux;
         j.slots = (uint64_t *)(ws + o_slots) + so;
+        j.lslots = (uint64_t *)(ws + o_lslots) + so;
         j.dstat = (DevStat *)(ws + o_stat) + r;
         j.partial = (double *)(ws + o_part) + po;
         so += (size_t)2 * j.slot_pad;
         po += cs[i];
     }
+    const int W = std::min(max_wg, seat0[n]);
+    const int max_cs = *std::max_element(cs.begin(), cs.end());
     BatchArgs b{};
     b.jobs = (const PlainJob *)(ws + o_jobs);
     b.seat0 = (const int32_t *)(ws + o_seat);
     b.n = n;
     b.ctl = (DevCtl *)(ws + o_ctl);
     b.timeout_ticks = ticks;
+    // per-XCD schedule when each XCD's share of the grid can hold the largest
+    // cluster (the kernel checks the actual placement before using it)
+    b.xcd_mode = W % 8 == 0 && max_cs <= W / 8 && max_cs < 4096;
+    b.max_cs = max_cs;
+    b.tickets = seat0[n];
+    b.xq = (XcdQueue *)(ws + o_xq);
+    b.xtable = (int32_t *)(ws + o_xtab);
     HIPCHK(hipMemsetAsync(ws, 0, head_end, stream));
     HIPCHK(hipMemcpyAsync(ws + o_jobs, jobs.data(), sizeof(PlainJob) * n, hipMemcpyHostToDevice, stream));
     HIPCHK(hipMemcpyAsync(ws + o_seat, seat0.data(), sizeof(int32_t) * (n + 1), hipMemcpyHostToDevice, stream));
@@ -839,7 +878,6 @@ int clean_batched(const clean_problem *probs, int n, const clean_params *shared,
         if (st) return st;
         if (bad) return fail(CLEAN_E_NONFINITE, "non-finite value in a dirty image or PSF");
     }
-    const int W = std::min(max_wg, seat0[n]);
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
@@ -880,6 +918,7 @@ int clean_batched(const clean_problem *probs, int n, const clean_params *shared,
             s.px_per_thread = ppt;
             s.workgroups = W;
             s.streamed = 0;
+            s.xcd_local_clusters = ds[r].xcd_local;
         }
     }
     return CLEAN_OK;

@@ -41,7 +41,7 @@ struct DevStat {
     double model_flux;
     double sumsq;
     uint64_t phase_ticks[3];   // tiled: local loops, feedback gather, apply + re-peak (wall-clock ticks)
-    int32_t xcd_local;         // tiled: clusters whose exchanges stayed inside one XCD
+    int32_t xcd_local;         // clusters whose exchanges stayed inside one XCD
 };
 
 // One plain CLEAN problem as a workgroup cluster sees it.
@@ -60,9 +60,22 @@ struct PlainJob {
     int64_t cap;
     int32_t *comp_idx;
     float *comp_flux;
-    uint64_t *slots;        // [2][slot_pad]
+    uint64_t *slots;        // [2][slot_pad] device-scope exchange slots
+    uint64_t *lslots;       // [2][slot_pad] XCD-local exchange slots (batched), else null
     DevStat *dstat;
     double *partial;        // [cs]
+};
+
+// Per-XCD problem queues of the batched kernel (one 128-byte line per word),
+// indexed by the 4-bit XCC id.
+constexpr int XQ_STRIDE = 32;
+constexpr int XQ_N = 16;
+struct XcdQueue {
+    uint32_t count[XQ_N * XQ_STRIDE];   // workgroups found on each XCD
+    uint32_t next[XQ_N * XQ_STRIDE];    // next ticket of each XCD
+    uint32_t front[XQ_N * XQ_STRIDE];   // tickets below this are assigned
+    uint32_t closed[XQ_N * XQ_STRIDE];  // no problem left for this XCD
+    uint32_t problem[XQ_STRIDE];        // next problem to hand out (all XCDs)
 };
 
 struct BatchArgs {
@@ -71,6 +84,11 @@ struct BatchArgs {
     int n;
     DevCtl *ctl;
     uint64_t timeout_ticks;
+    int xcd_mode;           // try the per-XCD schedule (checked on the device)
+    int max_cs;             // largest cluster of the batch
+    int tickets;            // ticket slots per XCD (total seats)
+    XcdQueue *xq;
+    int32_t *xtable;        // [XQ_N][tickets] problem << 12 | rank per ticket
 };
 
 struct KArgs {

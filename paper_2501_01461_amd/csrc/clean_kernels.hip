@@ -666,14 +666,27 @@ template <class Tile> __device__ void store_and_sum(const Tile &R, const Img &im
 }
 
 // Plain Hogbom CLEAN of one image by a cluster of j.cs workgroups; this
-// workgroup is cluster rank `rank`.  Returns false if the run was aborted.
-template <class Tile> __device__ bool run_plain(const PlainJob &j, int rank, const Sync &y)
+// workgroup is cluster rank `rank`.  `local`: the whole cluster runs on this
+// XCD, so after the first exchange keys go through the XCD-local slots (each
+// member clears its entries of them before that first, device-scope
+// exchange, which no member passes until all have cleared theirs).  Returns
+// false if the run was aborted.
+template <class Tile> __device__ bool run_plain(const PlainJob &j, int rank, const Sync &y, bool local)
 {
     const Img im{j.dirty, j.residual, j.model, nullptr, nullptr, j.psf, j.psf_bytes, j.nx, j.psf_nx, j.cy, j.cx};
     Tile T;
     T.init(im, 0, 0, j.ny, j.nx, j.cs, rank);
     if (!Tile::kResident) __syncthreads();
 
+    uint64_t *ls = nullptr;
+    if (local) {
+        if (threadIdx.x == 0) {
+            st_xcd(&j.lslots[rank], 0);
+            st_xcd(&j.lslots[j.slot_pad + rank], 0);
+            asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        }
+        ls = j.lslots;
+    }
     uint32_t e = 0;
     uint64_t cur;
     if (!cluster_reduce(y, j.slots, nullptr, j.slot_pad, j.cs, rank, e++, T.key(im), cur)) return false;
@@ -698,7 +711,7 @@ template <class Tile> __device__ bool run_plain(const PlainJob &j, int rank, con
         }
         if (j.model && T.owns(fp)) j.model[fp] += (double)c;
         // subtraction (eq. 2) fused with the next peak search
-        if (!cluster_reduce(y, j.slots, nullptr, j.slot_pad, j.cs, rank, e++, T.subtract(im, py, px, c, true), cur))
+        if (!cluster_reduce(y, j.slots, ls, j.slot_pad, j.cs, rank, e++, T.subtract(im, py, px, c, true), cur))
             return false;
         n += 1;
     }
@@ -709,6 +722,7 @@ template <class Tile> __device__ bool run_plain(const PlainJob &j, int rank, con
         j.dstat->n_rounds = 0;
         j.dstat->final_peak = (double)key_value(cur);
         j.dstat->model_flux = mflux;
+        j.dstat->xcd_local = local ? 1 : 0;
     }
     return true;
 }
@@ -724,36 +738,113 @@ template <class Tile> __global__ void __launch_bounds__(WG) hogbom_kernel(const 
     j.ny = a.ny; j.nx = a.nx; j.psf_nx = a.psf_nx; j.cy = a.cy; j.cx = a.cx;
     j.gain = a.gain; j.threshold = a.threshold; j.max_iter = a.max_iter; j.cap = a.cap;
     j.comp_idx = a.comp_idx; j.comp_flux = a.comp_flux;
-    j.slots = a.xslots; j.slot_pad = a.slot_pad; j.cs = a.cs;
+    j.slots = a.xslots; j.lslots = nullptr; j.slot_pad = a.slot_pad; j.cs = a.cs;
     j.dstat = a.dstat; j.partial = a.partial;
-    run_plain<Tile>(j, role & 0xFFFF, y);
+    run_plain<Tile>(j, role & 0xFFFF, y, false);
+}
+
+// Ticket of the per-XCD schedule: the problem and cluster rank this
+// workgroup (on XCD x) takes next, or -1 when none is left.  Tickets of one
+// XCD go out in order; the holder of the first unassigned ticket (the front)
+// pulls the next problem of the batch, writes its cs tickets and moves the
+// front on.  Thread 0 only.
+__device__ int32_t xcd_ticket(const BatchArgs &b, const Sync &y, uint32_t x)
+{
+    XcdQueue *q = b.xq;
+    int32_t *table = b.xtable + (size_t)x * b.tickets;
+    const uint32_t t = __hip_atomic_fetch_add(&q->next[x * XQ_STRIDE], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint64_t t0 = wall_clock64();
+    uint32_t spins = 0;
+    for (;;) {
+        uint32_t f = ld_agent32(&q->front[x * XQ_STRIDE]);
+        if (t < f) return ldc(&table[t]);
+        if (t == f) {
+            const uint32_t p = __hip_atomic_fetch_add(&q->problem[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if ((int)p >= b.n) {
+                stc(&q->closed[x * XQ_STRIDE], 1u);
+                return -1;
+            }
+            const int cs = b.jobs[p].cs;
+            for (int r = 0; r < cs; ++r) stc(&table[t + r], (int32_t)((p << 12) | (uint32_t)r));
+            // the table entries land before the front that publishes them
+            asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+            stc(&q->front[x * XQ_STRIDE], t + (uint32_t)cs);
+            return (int32_t)(p << 12);
+        }
+        // t > f: wait for the front, or for the queue to close (re-reading
+        // the front: it may have passed t before the close)
+        if (ld_agent32(&q->closed[x * XQ_STRIDE])) {
+            f = ld_agent32(&q->front[x * XQ_STRIDE]);
+            return t < f ? ldc(&table[t]) : -1;
+        }
+        if ((++spins & 63u) == 0) {
+            if (aborted(y)) return -1;
+            if (wall_clock64() - t0 > y.timeout_ticks) { raise_abort(y, ABORT_TIMEOUT); return -1; }
+        }
+    }
 }
 
 // Many independent images in one launch.  Problems are laid out largest
 // first; problem i owns the seats [seat0[i], seat0[i+1]) and each seat is one
-// workgroup of its cluster.  A workgroup takes the next seat from a device
-// counter, runs that problem with its cluster, then takes another.  Seats go
-// out in order and every workgroup is resident, so the earliest unfinished
-// problem always has its seats held by running workgroups: no deadlock.
+// workgroup of its cluster.
+//
+// Per-XCD schedule (when every XCD that holds workgroups holds at least the
+// largest cluster's worth, counted at launch): each XCD pulls whole problems
+// from the batch in order and runs them with its own workgroups, whose
+// exchanges then stay in that XCD's L2.  Otherwise a workgroup takes the next
+// seat of the whole batch from a device counter.  Either way tickets (seats)
+// go out in order and every workgroup is resident, so the earliest
+// unfinished problem always has all its members running: no deadlock.
 template <class Tile> __global__ void __launch_bounds__(WG) batched_kernel(const BatchArgs b)
 {
-    __shared__ int s_seat;
+    __shared__ int s_work, s_ok;
     const Sync y{b.ctl, b.timeout_ticks};
     const int total = b.seat0[b.n];
-    for (;;) {
+    bool per_xcd = false;
+    uint32_t x = 0;
+    if (b.xcd_mode) {
+        x = xcc_id();
         if (threadIdx.x == 0)
-            s_seat = (int)__hip_atomic_fetch_add(&b.ctl->seat, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __syncthreads();
-        const int seat = s_seat;
-        __syncthreads();
-        if (seat >= total) return;
-        int lo = 0, hi = b.n;                   // seat0[lo] <= seat < seat0[lo + 1]
-        while (hi - lo > 1) {
-            const int mid = (lo + hi) >> 1;
-            if (b.seat0[mid] <= seat) lo = mid; else hi = mid;
+            __hip_atomic_fetch_add(&b.xq->count[x * XQ_STRIDE], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        uint32_t epoch = 0;
+        if (!grid_barrier(y, epoch, &s_ok)) return;
+        if (threadIdx.x == 0) {
+            int ok = 1;
+            for (int i = 0; i < XQ_N; ++i) {
+                const uint32_t c = ld_agent32(&b.xq->count[i * XQ_STRIDE]);
+                if (c != 0 && c < (uint32_t)b.max_cs) ok = 0;
+            }
+            s_work = ok;
         }
-        const PlainJob j = b.jobs[lo];
-        if (!run_plain<Tile>(j, seat - b.seat0[lo], y)) return;
+        __syncthreads();
+        per_xcd = s_work != 0;
+        __syncthreads();
+    }
+    for (;;) {
+        // the next (problem << 12 | rank) for this workgroup, or -1
+        if (threadIdx.x == 0) {
+            int32_t w = -1;
+            if (per_xcd) {
+                w = xcd_ticket(b, y, x);
+            } else {
+                const int seat =
+                    (int)__hip_atomic_fetch_add(&b.ctl->seat, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (seat < total) {
+                    int lo = 0, hi = b.n;       // seat0[lo] <= seat < seat0[lo + 1]
+                    while (hi - lo > 1) {
+                        const int mid = (lo + hi) >> 1;
+                        if (b.seat0[mid] <= seat) lo = mid; else hi = mid;
+                    }
+                    w = (int32_t)(((uint32_t)lo << 12) | (uint32_t)(seat - b.seat0[lo]));
+                }
+            }
+            s_work = w;
+        }
+        __syncthreads();
+        const int32_t w = s_work;
+        __syncthreads();
+        if (w < 0) return;
+        if (!run_plain<Tile>(b.jobs[w >> 12], w & 0xFFF, y, per_xcd)) return;
         if (aborted(y)) return;
     }
 }

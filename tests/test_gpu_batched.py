@@ -58,6 +58,26 @@ def test_batched_y_array_problems(lib, ppt):
         ref = oracle.hogbom(p["dirty"], p["psf"], 0.1, p["threshold"], p["max_iter"])
         assert ref["stop"] == 1
         assert_same_run(o, ref)
+    if ppt == 8:
+        # 25-workgroup clusters in a grid of about 100: the device-wide queue
+        assert all(o["stats"]["xcd_local_clusters"] == 0 for o in outs)
+
+
+def test_batched_per_xcd_schedule(lib):
+    """8 images of 256^2 (8-workgroup clusters) and 8 of 128^2 (2 workgroups)
+    at 16 px/thread: an 80-workgroup grid, 10 per XCD, so each XCD pulls whole
+    problems and keeps their exchanges in its L2.  Bit for bit the oracle."""
+    probs = []
+    for i, s in enumerate([256] * 8 + [128] * 8):
+        d, p, _ = synth.make_problem(s, 6 + i, 0.01, 2.1, (), 1e-3, config=96, problem=i)
+        probs.append(dict(dirty=d, psf=p, threshold=5e-3, max_iter=1500))
+    announce("batched per-XCD schedule")
+    outs = lib.batched(to_dev(probs), gain=0.1, px_per_thread=16)
+    assert outs[0]["stats"]["workgroups"] == 80
+    assert all(o["stats"]["xcd_local_clusters"] == 1 for o in outs)
+    for p, o in zip(probs, outs):
+        ref = oracle.hogbom(p["dirty"], p["psf"], 0.1, p["threshold"], p["max_iter"])
+        assert_same_run(o, ref)
 
 
 def test_batched_equals_single_calls(lib):
@@ -93,6 +113,8 @@ def test_batched_config3_sampled(lib):
               for p in probs]
     outs = lib.batched(dprobs)
     assert all(o["stats"]["stop_reason"] == 1 for o in outs)
+    # 32-workgroup clusters at most, 256 workgroups: the per-XCD schedule
+    assert all(o["stats"]["xcd_local_clusters"] == 1 for o in outs)
     order = sorted(range(len(probs)), key=lambda i: probs[i]["n"])
     sample = order[::37][:6] + [order[-1]]
     for i in sample:
