@@ -1440,48 +1440,69 @@ __device__ bool fft_feedback(const KArgs &a, const Sync &y, uint32_t &epoch, int
 // Aggregate the leader's round list (LDS) by position: distinct positions in
 // ascending order, each with the float64 sum of its components in the order
 // found, rounded once to float32; zero sums are dropped.  Writes the raw list
-// and the aggregated list of tile t to global memory.
+// and the aggregated list of tile t to global memory.  The four LDS arrays
+// start on 16-byte boundaries; every scan reads the list four entries at a
+// time and runs its full length (no early exit), so it is bound by LDS
+// throughput, not by the latency of one read after another.
 __device__ void aggregate_round(const KArgs &a, int t, int L, int32_t *l_idx, float *l_flux, int32_t *l_tmp,
                                 float *l_sum, int *s_cnt)
 {
+    constexpr int32_t NONE = 0x7FFFFFFF;        // above every pixel index
     const size_t base = (size_t)t * a.interval;
     for (int j = threadIdx.x; j < L; j += WG) {
         stc(&a.rb_idx[base + j], l_idx[j]);
         stc(&a.rb_flux[base + j], l_flux[j]);
     }
-    // pass 1: heads (first occurrence) get their sum; l_tmp = 1 for a kept head
+    const int L4 = L & ~3;
+    // pass 1: entry j is kept if no earlier entry has its position and the
+    // float64 sum of the entries from j on with that position, in order, is
+    // not zero; l_tmp[j] = its position if kept, else NONE
     for (int j = threadIdx.x; j < L; j += WG) {
         const int32_t q = l_idx[j];
-        bool head = true;
-        for (int k = 0; k < j; ++k)
-            if (l_idx[k] == q) { head = false; break; }
-        int keep = 0;
-        float fs = 0.0f;
-        if (head) {
-            double s = 0.0;
-            for (int k = j; k < L; ++k)
-                if (l_idx[k] == q) s += (double)l_flux[k];
-            keep = s != 0.0;
-            fs = (float)s;
+        bool dup = false;
+        double s = 0.0;
+        for (int k = 0; k < L4; k += 4) {
+            const int4 v = *(const int4 *)&l_idx[k];
+            const int32_t vv[4] = {v.x, v.y, v.z, v.w};
+            if ((vv[0] == q) | (vv[1] == q) | (vv[2] == q) | (vv[3] == q)) {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    if (vv[e] == q) {
+                        if (k + e < j) dup = true;
+                        else s += (double)l_flux[k + e];
+                    }
+                }
+            }
         }
-        l_tmp[j] = keep;
-        l_sum[j] = fs;
+        for (int k = L4; k < L; ++k) {
+            if (l_idx[k] == q) {
+                if (k < j) dup = true;
+                else s += (double)l_flux[k];
+            }
+        }
+        const bool keep = !dup && s != 0.0;
+        l_tmp[j] = keep ? q : NONE;
+        l_sum[j] = (float)s;
     }
     __syncthreads();
-    // pass 2: rank of each kept head among kept heads by position
+    // pass 2: rank of each kept position among the kept positions
+    int mine = 0;
     for (int j = threadIdx.x; j < L; j += WG) {
-        if (!l_tmp[j]) continue;
-        const int32_t q = l_idx[j];
+        const int32_t q = l_tmp[j];
+        if (q == NONE) continue;
         int rk = 0;
-        for (int k = 0; k < L; ++k) rk += (l_tmp[k] != 0) & (l_idx[k] < q);
+        for (int k = 0; k < L4; k += 4) {
+            const int4 v = *(const int4 *)&l_tmp[k];
+            rk += (v.x < q) + (v.y < q) + (v.z < q) + (v.w < q);
+        }
+        for (int k = L4; k < L; ++k) rk += l_tmp[k] < q;
         stc(&a.ag_pos[base + rk], q);
         stc(&a.ag_flux[base + rk], l_sum[j]);
         if (a.comp_img) stc(&a.comp_img[q], l_sum[j]);
+        ++mine;
     }
     if (threadIdx.x == 0) *s_cnt = 0;
     __syncthreads();
-    int mine = 0;
-    for (int j = threadIdx.x; j < L; j += WG) mine += l_tmp[j] != 0;
     if (mine) atomicAdd(s_cnt, mine);
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -1532,10 +1553,11 @@ tiled_kernel(const KArgs a)
     const bool tile_leader_wg = is_cluster && rank == 0;
 
     // round-list LDS (leader workgroup) and gather staging (everyone) share s_dyn
+    const size_t i4 = ((size_t)a.interval + 3) & ~(size_t)3;     // 16-byte aligned arrays
     int32_t *l_idx = (int32_t *)s_dyn;
-    float *l_flux = (float *)(s_dyn + 4 * (size_t)a.interval);
-    int32_t *l_tmp = (int32_t *)(s_dyn + 8 * (size_t)a.interval);
-    float *l_sum = (float *)(s_dyn + 12 * (size_t)a.interval);
+    float *l_flux = (float *)(s_dyn + 4 * i4);
+    int32_t *l_tmp = (int32_t *)(s_dyn + 8 * i4);
+    float *l_sum = (float *)(s_dyn + 12 * i4);
     int32_t *g_shift = (int32_t *)s_dyn;
     float *g_flux = (float *)(s_dyn + 4 * (size_t)GATHER_CHUNK);
 
