@@ -140,3 +140,25 @@ def test_batched_degenerate_problems(lib):
         assert_same_run(o, ref)
     assert outs[0]["stats"]["n_iter"] == 0 and outs[2]["stats"]["n_iter"] == 0
     assert outs[4]["stats"]["n_iter"] == 0 and outs[4]["stats"]["stop_reason"] == 2
+
+
+def test_batched_degenerate_problems_per_xcd(lib):
+    """The same edge cases under the per-XCD schedule: 16 one-workgroup
+    problems (a 16-workgroup grid, 2 per XCD), including odd widths."""
+    probs = [random_problem(50, 16, 20, 0.0, 0),
+             random_problem(51, 1, 1, 0.0, 5),
+             dict(random_problem(52, 24, 24, 0.0, 50)),
+             dict(random_problem(53, 12, 16, 0.0, 30)),
+             dict(random_problem(54, 20, 12, 0.0, 40), cap=0)]
+    probs[2]["threshold"] = 10.0
+    probs[3]["dirty"] = np.zeros((12, 16), np.float32)
+    probs += [random_problem(60 + i, 20 + 3 * i, 17 + 5 * i, 0.0, 60 + 10 * i) for i in range(11)]
+    announce("batched degenerate, per-XCD schedule")
+    outs = lib.batched(to_dev(probs), gain=0.1)
+    assert outs[0]["stats"]["workgroups"] == 16
+    assert all(o["stats"]["wg_per_tile"] == 1 for o in outs)
+    assert all(o["stats"]["xcd_local_clusters"] == 1 for o in outs)
+    for p, o in zip(probs, outs):
+        ref = oracle.hogbom(p["dirty"], p["psf"], 0.1, p["threshold"], p["max_iter"], cap=p.get("cap"))
+        assert_same_run(o, ref)
+    assert outs[4]["stats"]["n_iter"] == 0 and outs[4]["stats"]["stop_reason"] == 2
