@@ -809,7 +809,14 @@ int clean_batched(const clean_problem *probs, int n, const clean_params *shared,
     const size_t o_jobs = o;  o = align_up(o + sizeof(PlainJob) * n, 256);
     const size_t o_seat = o;  o = align_up(o + sizeof(int32_t) * (n + 1), 256);
     const size_t o_part = o;  o = align_up(o + npart * 8, 256);
-    const size_t o_xtab = o;  o = align_up(o + (size_t)XQ_N * seat0[n] * sizeof(int32_t), 256);
+    // per-XCD schedule when each XCD's share of the grid can hold the largest
+    // cluster (the kernel checks the actual placement before using it); its
+    // ticket table only then
+    const int W = std::min(max_wg, seat0[n]);
+    const int max_cs = *std::max_element(cs.begin(), cs.end());
+    const bool xcd_mode = W % 8 == 0 && max_cs <= W / 8 && max_cs < 4096;
+    const size_t o_xtab = o;
+    o = align_up(o + (xcd_mode ? (size_t)XQ_N * seat0[n] * sizeof(int32_t) : 0), 256);
     void *wp = nullptr;
     int st = internal_workspace(dev, o, &wp);
     if (st) return st;
@@ -841,17 +848,13 @@ int clean_batched(const clean_problem *probs, int n, const clean_params *shared,
         so += (size_t)2 * j.slot_pad;
         po += cs[i];
     }
-    const int W = std::min(max_wg, seat0[n]);
-    const int max_cs = *std::max_element(cs.begin(), cs.end());
     BatchArgs b{};
     b.jobs = (const PlainJob *)(ws + o_jobs);
     b.seat0 = (const int32_t *)(ws + o_seat);
     b.n = n;
     b.ctl = (DevCtl *)(ws + o_ctl);
     b.timeout_ticks = ticks;
-    // per-XCD schedule when each XCD's share of the grid can hold the largest
-    // cluster (the kernel checks the actual placement before using it)
-    b.xcd_mode = W % 8 == 0 && max_cs <= W / 8 && max_cs < 4096;
+    b.xcd_mode = xcd_mode;
     b.max_cs = max_cs;
     b.tickets = seat0[n];
     b.xq = (XcdQueue *)(ws + o_xq);
