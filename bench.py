@@ -253,6 +253,36 @@ def main():
         ti = tuner[nm]["chosen"]
         if ti:
             jy["bands_tiled_minus_plain"][f"{nm}_psf_tuned_interval{ti}"] = band(cfg, 0.0, ti)
+
+    # no feedback at all: each tile cleaned on its own (plain clean_hogbom on
+    # its crop, the crop's share of the iterations); the residual is then the
+    # consistent one, dirty - model (*) PSF (float64 on the host)
+    def band_no_feedback(cfg):
+        from scipy.signal import fftconvolve
+        d_np, p_np = cfg["dirty"], cfg["psf"]
+        cy, cx = p_np.shape[0] // 2, p_np.shape[1] // 2
+        model = np.zeros((ny, nx), np.float64)
+        T = tiles[0] * tiles[1]
+        for i in range(tiles[0]):
+            y0, y1 = i * ny // tiles[0], (i + 1) * ny // tiles[0]
+            for j in range(tiles[1]):
+                x0, x1 = j * nx // tiles[1], (j + 1) * nx // tiles[1]
+                h, w = y1 - y0, x1 - x0
+                crop = torch.from_numpy(np.ascontiguousarray(d_np[y0:y1, x0:x1])).to(dev)
+                pc = torch.from_numpy(np.ascontiguousarray(p_np[cy - h:cy + h, cx - w:cx + w])).to(dev)
+                r = P.hogbom(crop, pc, gain, thr, n_iter // T)
+                model[y0:y1, x0:x1] = r["model"].cpu().numpy()
+        conv = fftconvolve(model, p_np.astype(np.float64), mode="full")[cy:cy + ny, cx:cx + nx]
+        res = torch.from_numpy((d_np.astype(np.float64) - conv).astype(np.float32)).to(dev)
+        mp = P.hogbom(torch.from_numpy(d_np).to(dev), torch.from_numpy(p_np).to(dev), gain, thr, n_iter)
+        sg = P.clean_beam(torch.from_numpy(p_np).to(dev))["sigma"]
+        dm = model - mp["model"].cpu().numpy()
+        dr = (P.restore(torch.from_numpy(model).to(dev), res, sg) - P.restore(mp["model"], mp["residual"], sg))
+        dr = dr.cpu().numpy()
+        return {"model_min": float(dm.min()), "model_max": float(dm.max()),
+                "restored_min": float(dr.min()), "restored_max": float(dr.max()),
+                "note": f"each tile alone: plain CLEAN on its crop for {n_iter // T} iterations, no cross-coupling"}
+    jy["bands_no_feedback_minus_plain"] = {"snapshot_psf": band_no_feedback(c), "track_psf": band_no_feedback(ctrack)}
     jy["clean_beam"] = P.clean_beam(psf)
     jy["bands_note"] = ("differences tiled - plain (Jy) after the same 20000 total minor iterations; "
                         "restored = clean_restore: model (*) peak-1 circular Gaussian clean beam (clean_beam_fit: "
