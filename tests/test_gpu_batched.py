@@ -63,20 +63,27 @@ def test_batched_y_array_problems(lib, ppt):
         assert all(o["stats"]["xcd_local_clusters"] == 0 for o in outs)
 
 
-def test_batched_per_xcd_schedule(lib):
+@pytest.mark.parametrize("f16", [False, True], ids=["f32", "f16"])
+def test_batched_per_xcd_schedule(lib, f16):
     """8 images of 256^2 (8-workgroup clusters) and 8 of 128^2 (2 workgroups)
     at 16 px/thread: an 80-workgroup grid, 10 per XCD, so each XCD pulls whole
-    problems and keeps their exchanges in its L2.  Bit for bit the oracle."""
+    problems and keeps their exchanges in its L2.  Bit for bit the oracle
+    (on the float16-rounded PSFs when they are stored so)."""
     probs = []
     for i, s in enumerate([256] * 8 + [128] * 8):
         d, p, _ = synth.make_problem(s, 6 + i, 0.01, 2.1, (), 1e-3, config=96, problem=i)
         probs.append(dict(dirty=d, psf=p, threshold=5e-3, max_iter=1500))
-    announce("batched per-XCD schedule")
-    outs = lib.batched(to_dev(probs), gain=0.1, px_per_thread=16)
+    announce("batched per-XCD schedule", f16)
+    dprobs = to_dev(probs)
+    if f16:
+        for q in dprobs:
+            q["psf"] = lib.psf_to_f16(q["psf"])
+    outs = lib.batched(dprobs, gain=0.1, px_per_thread=16)
     assert outs[0]["stats"]["workgroups"] == 80
     assert all(o["stats"]["xcd_local_clusters"] == 1 for o in outs)
     for p, o in zip(probs, outs):
-        ref = oracle.hogbom(p["dirty"], p["psf"], 0.1, p["threshold"], p["max_iter"])
+        psf = p["psf"].astype(np.float16).astype(np.float32) if f16 else p["psf"]
+        ref = oracle.hogbom(p["dirty"], psf, 0.1, p["threshold"], p["max_iter"])
         assert_same_run(o, ref)
 
 

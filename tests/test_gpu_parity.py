@@ -214,6 +214,21 @@ def test_tiled_config1_full(lib):
     assert_same_run(out, ref)
 
 
+def test_tiled_config1_full_f16(lib):
+    """The same run with the PSF stored as float16 (widened to float32 before
+    each fma), against the oracle on the identically rounded PSF."""
+    announce("tiled config1 full, f16 PSF")
+    c = synth.make_config(1)
+    psf_ref = c["psf"].astype(np.float16).astype(np.float32)
+    ref = oracle.tiled(c["dirty"], psf_ref, c["tiles"], c["interval"], 0.1, 0.0, c["max_iter"])
+    out = lib.tiled_feedback(dev(c["dirty"]), lib.psf_to_f16(dev(c["psf"])), c["tiles"], c["interval"], 0.1, 0.0,
+                             c["max_iter"])
+    assert out["stats"]["px_per_thread"] == 16 and out["stats"]["wg_per_tile"] == 32
+    assert out["stats"]["xcd_local_clusters"] == 4
+    assert out["stats"]["n_rounds"] == ref["n_rounds"]
+    assert_same_run(out, ref)
+
+
 def test_tiled_clusters_across_xcds(lib):
     """Clusters too large for the per-XCD placement (3x3 tiles x 24 workgroups)
     are packed without XCD affinity and exchange through device-scope slots;
