@@ -22,6 +22,7 @@
 namespace cleanhip {
 template <int K, int V, typename PT> struct RegTile;
 template <int K, int V, typename PT> struct StreamTile;
+template <typename PT> struct WideTile;
 template <class Tile> __global__ void hogbom_kernel(const KArgs a);
 template <class Tile, bool FFT> __global__ void tiled_kernel(const KArgs a);
 template <class Tile> __global__ void batched_kernel(const BatchArgs b);
@@ -274,6 +275,12 @@ BFn pick_batched(bool half, int V, int K)
     return half ? batched_fn<1, __half>(K) : batched_fn<1, float>(K);
 }
 
+KFn pick_wide(bool half, bool fft)
+{
+    if (fft) return half ? tiled_kernel<WideTile<__half>, true> : tiled_kernel<WideTile<float>, true>;
+    return half ? tiled_kernel<WideTile<__half>, false> : tiled_kernel<WideTile<float>, false>;
+}
+
 template <bool FFT> KFn tiled_stream_fn(bool half, int V)
 {
     if (V == 4) return half ? tiled_kernel<StreamTile<STREAM_K, 4, __half>, FFT> : tiled_kernel<StreamTile<STREAM_K, 4, float>, FFT>;
@@ -524,6 +531,27 @@ int run(bool tiled, const float *dirty, int ny, int nx, const void *psf, int psf
         streamed = true;
     } else {
         return st;
+    }
+    // tiles too large for the register tiles: 128 px/thread held in registers
+    // during the local loops (WideTile) when the image fits the co-resident
+    // register file that way, else the residual streamed through HBM
+    if (streamed && !force_stream && tiled && V == 4 && !p->wg_per_tile && !p->px_per_thread && nx % tiles_x == 0) {
+        const int tw = nx / tiles_x;
+        const int64_t per_wg = (int64_t)WG * 128;
+        const int cw = (int)((max_tile + per_wg - 1) / per_wg);
+        if (((int64_t)cw * WG * 4) % tw == 0) {
+            KFn fw = pick_wide(half, fft);
+            if (dyn_lds > 48 * 1024)
+                HIPCHK(hipFuncSetAttribute((const void *)fw, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn_lds));
+            int occ = 0;
+            HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void *)fw, WG, dyn_lds));
+            if (occ > 0 && place(cw, occ * ncu, W, role)) {
+                streamed = false;
+                fn = fw;
+                cs = cw;
+                ppt = 128;
+            }
+        }
     }
     if (streamed) {
         g_last_error.clear();

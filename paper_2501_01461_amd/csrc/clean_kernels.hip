@@ -152,7 +152,12 @@ template <typename PT, int V> struct PsfLoad;
 template <> struct PsfLoad<float, 4> {
     static __device__ __forceinline__ void load(__amdgpu_buffer_rsrc_t rs, uint32_t off, float *o)
     {
-        auto v = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)off, 0, 0);
+        load_s(rs, off, 0, o);
+    }
+    // voffset plus a uniform (scalar) offset
+    static __device__ __forceinline__ void load_s(__amdgpu_buffer_rsrc_t rs, uint32_t voff, uint32_t soff, float *o)
+    {
+        auto v = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)voff, (int)soff, 0);
         o[0] = __uint_as_float(v[0]); o[1] = __uint_as_float(v[1]);
         o[2] = __uint_as_float(v[2]); o[3] = __uint_as_float(v[3]);
     }
@@ -166,7 +171,11 @@ template <> struct PsfLoad<float, 1> {
 template <> struct PsfLoad<__half, 4> {
     static __device__ __forceinline__ void load(__amdgpu_buffer_rsrc_t rs, uint32_t off, float *o)
     {
-        auto v = __builtin_amdgcn_raw_buffer_load_b64(rs, (int)off, 0, 0);
+        load_s(rs, off, 0, o);
+    }
+    static __device__ __forceinline__ void load_s(__amdgpu_buffer_rsrc_t rs, uint32_t voff, uint32_t soff, float *o)
+    {
+        auto v = __builtin_amdgcn_raw_buffer_load_b64(rs, (int)voff, (int)soff, 0);
         o[0] = __half2float(__ushort_as_half((unsigned short)(v[0] & 0xFFFFu)));
         o[1] = __half2float(__ushort_as_half((unsigned short)(v[0] >> 16)));
         o[2] = __half2float(__ushort_as_half((unsigned short)(v[1] & 0xFFFFu)));
@@ -359,6 +368,7 @@ struct Img {
 // consecutive pixels, group k at tile-local index ((k*cs + g)*WG + t)*V.
 template <int K, int V, typename PT> struct RegTile {
     static constexpr bool kResident = true;
+    static constexpr bool kWide = false;
     static constexpr int kV = V;
     using psf_t = PT;
     float r[K][V];
@@ -496,11 +506,224 @@ template <int K, int V, typename PT> struct RegTile {
     }
 };
 
+// Running peak of a stream of pixels in increasing index order: the largest
+// |value| (compared as magnitude bits), the lowest index on ties.
+__device__ __forceinline__ void take_key(uint32_t bits, uint32_t f, uint32_t &bb, uint32_t &bf, bool &any)
+{
+    const bool t = !any || ((bits & 0x7FFFFFFFu) > (bb & 0x7FFFFFFFu));
+    bb = t ? bits : bb;
+    bf = t ? f : bf;
+    any = true;
+}
+
+// Residual held in VGPRs at 128 pixels per thread during each round's local
+// loops, for images too large for RegTile's shapes: one 512-thread workgroup
+// per CU holds 64K pixels, so the co-resident grid holds 16M (a 4096^2
+// image).  Thread t of cluster rank g owns 32 groups of 4 pixels at
+// tile-local index f_k = f_0 + k*S, with f_0 = (g*WG + t)*4 and S = cs*WG*4
+// a multiple of the tile width w: group k sits k*S/w rows below group 0, so
+// one PSF offset plus a uniform step addresses all 32.  Groups
+// 0..nvalid-1 lie inside the tile; the others hold +0.
+//
+// Only wide_round() holds the residual in registers, loading it at the
+// start of each round's local loops from the round's residual array (the FFT
+// form's rstart, else `residual`) and, for the direct gather, storing it back
+// at their end.  Everything else (the first peak, applying the feedback, the
+// final write) streams those arrays like StreamTile, so the feedback phases
+// never carry 128 residual registers.
+template <typename PT> struct WideTile {
+    static constexpr bool kResident = false;
+    static constexpr bool kWide = true;
+    static constexpr int kV = 4;
+    static constexpr int K = 32, V = 4;
+    using psf_t = PT;
+    int32_t qoff;           // PSF offset (image coords) of group 0's first pixel
+    int32_t f0;             // tile-local index of group 0's first pixel
+    int nvalid;             // groups inside the tile
+    int y0, x0, h, w, cs, rank;
+    bool fft;               // the round's residual lives in rstart (else residual)
+
+    __device__ __forceinline__ uint32_t stride() const { return (uint32_t)(cs * WG * V); }
+    __device__ __forceinline__ uint32_t group_f(int k) const { return (uint32_t)f0 + (uint32_t)k * stride(); }
+    __device__ __forceinline__ int64_t img_of(const Img &a, int k) const
+    {
+        const int y = f0 / w + k * (int)(stride() / (uint32_t)w), x = f0 % w;
+        return (int64_t)(y0 + y) * a.nx + (x0 + x);
+    }
+    __device__ __forceinline__ float *cur(const Img &a) const { return fft ? a.rstart : a.residual; }
+
+    // Geometry; the direct gather's residual array starts as the dirty image.
+    __device__ void init(const Img &a, int ty0, int tx0, int th, int tw, int ncs, int rk)
+    {
+        y0 = ty0; x0 = tx0; h = th; w = tw; cs = ncs; rank = rk;
+        fft = a.rstart != nullptr;
+        f0 = (rank * WG + (int)threadIdx.x) * V;
+        const int hw = h * w;
+        nvalid = f0 < hw ? min(K, (int)(((uint32_t)(hw - f0) + stride() - 1) / stride())) : 0;
+        qoff = (y0 + f0 / w) * a.psf_nx + (x0 + f0 % w);
+        for (int k = 0; k < nvalid; ++k) {
+            const int64_t img = img_of(a, k);
+#pragma unroll
+            for (int e = 0; e < V; ++e) {
+                if (!fft) a.residual[img + e] = a.dirty[img + e];
+                if (a.model) a.model[img + e] = 0.0;
+            }
+        }
+    }
+
+    // Thread-local peak key of the round's residual array, streamed.
+    __device__ uint64_t key(const Img &a) const
+    {
+        const float *rr = cur(a);
+        uint32_t bb = 0, bf = 0;
+        bool any = false;
+        for (int k = 0; k < nvalid; ++k) {
+            const int64_t img = img_of(a, k);
+#pragma unroll
+            for (int e = 0; e < V; ++e) take_key(__float_as_uint(rr[img + e]), group_f(k) + e, bb, bf, any);
+        }
+        return any ? make_key(bb, bf) : 0;
+    }
+
+    // r = array - acc for every owned pixel, written back; returns the new key.
+    template <bool FROM_START> __device__ uint64_t apply_feedback(const Img &a)
+    {
+        float *rr = cur(a);
+        uint32_t bb = 0, bf = 0;
+        bool any = false;
+        for (int k = 0; k < nvalid; ++k) {
+            const int64_t img = img_of(a, k);
+#pragma unroll
+            for (int e = 0; e < V; ++e) {
+                const float r = rr[img + e] - ldc(&a.accbuf[img + e]);
+                rr[img + e] = r;
+                take_key(__float_as_uint(r), group_f(k) + e, bb, bf, any);
+            }
+        }
+        return any ? make_key(bb, bf) : 0;
+    }
+
+    __device__ double finish(const Img &a) const
+    {
+        const float *rr = cur(a);
+        double sumsq = 0.0;
+        for (int k = 0; k < nvalid; ++k) {
+            const int64_t img = img_of(a, k);
+#pragma unroll
+            for (int e = 0; e < V; ++e) {
+                const float r = rr[img + e];
+                if (fft) a.residual[img + e] = r;
+                sumsq += (double)r * (double)r;
+            }
+        }
+        return sumsq;
+    }
+
+    __device__ __forceinline__ bool owns(uint32_t f) const
+    {
+        const uint32_t u = (f % stride()) / (uint32_t)V;
+        return u % (uint32_t)WG == threadIdx.x && (int)(u / (uint32_t)WG) == rank;
+    }
+};
+
+// What one round's local loops of a WideTile cluster leave behind.
+struct WideRound {
+    uint64_t cur;           // the cluster's last peak key
+    uint32_t e;             // exchanges so far
+    int L;                  // components found
+    int ok;                 // 0: the run was aborted
+};
+
+// One round's local loops of a WideTile cluster (the same steps as the
+// register tiles' loop in tiled_kernel), in a function of its own so that its
+// 128 residual registers do not add to the rest of the kernel's.  The
+// residual comes from the round's residual array and, for the direct gather,
+// goes back to it at the end (the FFT form rebuilds it from the round's start).
+template <typename PT>
+__device__ __noinline__ WideRound wide_round(const KArgs &a, const Img im, const WideTile<PT> R, const Sync y,
+                                             uint64_t *slots, uint64_t *lslots, uint32_t e, uint64_t cur,
+                                             int64_t budget, double level, bool leader, int32_t *l_idx,
+                                             float *l_flux)
+{
+    constexpr int K = WideTile<PT>::K, V = WideTile<PT>::V;
+    float r[K][V];
+    const float *src = R.cur(im);
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int64_t img = R.img_of(im, k);
+#pragma unroll
+        for (int e2 = 0; e2 < V; ++e2) r[k][e2] = k < R.nvalid ? src[img + e2] : 0.0f;
+    }
+    const uint32_t voff = (uint32_t)R.qoff * (uint32_t)sizeof(PT);
+    const uint32_t step = (R.stride() / (uint32_t)R.w) * (uint32_t)a.psf_nx * (uint32_t)sizeof(PT);
+    WideRound out{cur, e, 0, 1};
+    for (int64_t it = 0; it < budget; ++it) {
+        const float v = key_value(out.cur);
+        if ((double)fabsf(v) < a.threshold || (double)fabsf(v) < level) break;
+        const float c = a.gain * v;
+        const uint32_t fp = key_f(out.cur);
+        const int ly = (int)(fp / (uint32_t)R.w), lx = (int)(fp % (uint32_t)R.w);
+        const int py = R.y0 + ly, px = R.x0 + lx;
+        const int32_t img = py * a.nx + px;
+        if (leader && threadIdx.x == 0) { l_idx[out.L] = img; l_flux[out.L] = c; }
+        if (a.model && R.owns(fp)) a.model[img] += (double)c;
+        // r -= c * PSF window (eq. 2)
+        const int64_t w0 = (int64_t)(a.cy - py) * a.psf_nx + (a.cx - px);
+        const char *base = (const char *)a.psf + w0 * (int64_t)sizeof(PT);
+        const __amdgpu_buffer_rsrc_t rs = make_rsrc(base, a.psf_bytes - (uint64_t)w0 * sizeof(PT));
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            // the whole offset in the (range-checked) vector offset; groups
+            // outside the tile read group 0's window and are multiplied by 0
+            const uint32_t off = k < R.nvalid ? voff + (uint32_t)k * step : voff;
+            float pv[V];
+            PsfLoad<PT, V>::load(rs, off, pv);
+            const float ck = k < R.nvalid ? c : 0.0f;          // groups outside the tile stay +0
+#pragma unroll
+            for (int e2 = 0; e2 < V; ++e2) r[k][e2] = __builtin_fmaf(-ck, pv[e2], r[k][e2]);
+        }
+        out.L += 1;
+        if (it + 1 < budget) {
+            // thread key: largest magnitude bits, lowest index (as take_key)
+            uint32_t m = 0;
+#pragma unroll
+            for (int k = 0; k < K; ++k)
+#pragma unroll
+                for (int e2 = 0; e2 < V; ++e2) m = max(m, __float_as_uint(r[k][e2]) & 0x7FFFFFFFu);
+            uint32_t bb = 0, bi = 0;
+#pragma unroll
+            for (int i = K * V - 1; i >= 0; --i) {
+                const uint32_t x = __float_as_uint(r[i / V][i % V]);
+                const bool hit = (x & 0x7FFFFFFFu) == m;
+                bb = hit ? x : bb;
+                bi = hit ? (uint32_t)i : bi;
+            }
+            const uint64_t tk = R.nvalid > 0 ? make_key(bb, R.group_f((int)(bi / V)) + bi % V) : 0;
+            if (!cluster_reduce(y, slots, lslots, a.slot_pad, R.cs, R.rank, out.e++, tk, out.cur)) {
+                out.ok = 0;
+                return out;
+            }
+        }
+    }
+    if (!R.fft) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            if (k < R.nvalid) {
+                const int64_t img = R.img_of(im, k);
+#pragma unroll
+                for (int e2 = 0; e2 < V; ++e2) im.residual[img + e2] = r[k][e2];
+            }
+        }
+    }
+    return out;
+}
+
 // Residual kept in HBM (the caller's residual array) for tiles too large for
 // the register file: every pass streams K groups per thread through
 // registers, group index ((p*K + k)*cs + g)*WG + t for pass p.
 template <int K, int V, typename PT> struct StreamTile {
     static constexpr bool kResident = false;
+    static constexpr bool kWide = false;
     static constexpr int kV = V;
     using psf_t = PT;
     int y0, x0, h, w, cs, rank, passes;
@@ -1530,7 +1753,7 @@ __device__ __forceinline__ int wg_sum_int(int v, int *s_tmp)
 // Streamed tiles with FFT feedback are capped at 128 VGPRs (four waves per
 // SIMD) so that two workgroups share a CU, as the direct-gather ones do.
 template <class Tile, bool FFT>
-__global__ void __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(FFT && !Tile::kResident ? 4 : 1)))
+__global__ void __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(FFT && !Tile::kResident && !Tile::kWide ? 4 : 1)))
 tiled_kernel(const KArgs a)
 {
     constexpr int V = Tile::kV;
@@ -1626,6 +1849,14 @@ tiled_kernel(const KArgs a)
         if (blockIdx.x == 0) tp0 = wall_clock64();
         if (is_cluster) {
             int L = 0;
+            if constexpr (Tile::kWide) {
+                const WideRound wr = wide_round<PT>(a, im, R, y, slots, lslots, e, cur, budget, level,
+                                                    tile_leader_wg, l_idx, l_flux);
+                if (!wr.ok) return;
+                cur = wr.cur;
+                e = wr.e;
+                L = wr.L;
+            } else
             for (int64_t it = 0; it < budget; ++it) {
                 const float v = key_value(cur);
                 if ((double)fabsf(v) < a.threshold || (double)fabsf(v) < level) break;
@@ -1881,6 +2112,10 @@ __global__ void finalize_batch_kernel(const PlainJob *jobs, int n)
     template __global__ void tiled_kernel<StreamTile<STREAM_K, V, PT>, false>(const KArgs a); \
     template __global__ void tiled_kernel<StreamTile<STREAM_K, V, PT>, true>(const KArgs a);
 
+template __global__ void tiled_kernel<WideTile<float>, false>(const KArgs a);
+template __global__ void tiled_kernel<WideTile<float>, true>(const KArgs a);
+template __global__ void tiled_kernel<WideTile<__half>, false>(const KArgs a);
+template __global__ void tiled_kernel<WideTile<__half>, true>(const KArgs a);
 #define INST_ALL_K(V, PT) INST(1, V, PT) INST(2, V, PT) INST(4, V, PT) INST(8, V, PT) INST(16, V, PT)
 INST_ALL_K(4, float)
 INST_ALL_K(4, __half)

@@ -297,15 +297,24 @@ def test_plain_config2_prefix(lib, config2):
     assert_same_run(out, ref)
 
 
-@pytest.mark.parametrize("f16", [False, True])
-def test_tiled_config2_prefix(lib, config2, f16):
-    """8x8 tiles of 512^2, interval 10, two feedback rounds (1280 iterations)."""
+@pytest.mark.parametrize("f16,stream", [(False, False), (True, False), (False, True)],
+                         ids=["f32-wide", "f16-wide", "f32-streamed"])
+def test_tiled_config2_prefix(lib, config2, f16, stream):
+    """8x8 tiles of 512^2, interval 10, two feedback rounds (1280 iterations).
+    By default the 128-px/thread register tile (4 workgroups per tile, one per
+    CU); with stream=True the residual streamed through HBM."""
     c = config2
-    announce("tiled config2 prefix", f16)
+    announce("tiled config2 prefix", f16, stream)
     psf_ref = c["psf"].astype(np.float16).astype(np.float32) if f16 else c["psf"]
     ref = oracle.tiled(c["dirty"], psf_ref, (8, 8), 10, 0.1, 0.0, 1280)
     p = dev(c["psf"])
-    out = lib.tiled_feedback(dev(c["dirty"]), lib.psf_to_f16(p) if f16 else p, (8, 8), 10, 0.1, 0.0, 1280)
+    out = lib.tiled_feedback(dev(c["dirty"]), lib.psf_to_f16(p) if f16 else p, (8, 8), 10, 0.1, 0.0, 1280,
+                             stream=stream)
+    if stream:
+        assert out["stats"]["streamed"] == 1
+    else:
+        assert out["stats"]["streamed"] == 0 and out["stats"]["px_per_thread"] == 128
+        assert out["stats"]["wg_per_tile"] == 4 and out["stats"]["xcd_local_clusters"] == 64
     assert out["stats"]["n_rounds"] == ref["n_rounds"] == 2
     assert_same_run(out, ref)
 
