@@ -678,24 +678,25 @@ __device__ __noinline__ WideRound wide_round(const KArgs &a, const Img im, const
             const uint32_t off = k < R.nvalid ? voff + (uint32_t)k * step : voff;
             float pv[V];
             PsfLoad<PT, V>::load(rs, off, pv);
-            const float ck = k < R.nvalid ? c : 0.0f;          // groups outside the tile stay +0
+            const float ck = k < R.nvalid ? c : 0.0f;      // groups outside the tile stay +0
 #pragma unroll
             for (int e2 = 0; e2 < V; ++e2) r[k][e2] = __builtin_fmaf(-ck, pv[e2], r[k][e2]);
         }
         out.L += 1;
         if (it + 1 < budget) {
-            // thread key: largest magnitude bits, lowest index (as take_key)
-            uint32_t m = 0;
+            // thread key: the largest |r|, then the lowest index holding it
+            // (RegTile's form; for finite values the same as take_key's)
+            float m = 0.0f;
 #pragma unroll
             for (int k = 0; k < K; ++k)
 #pragma unroll
-                for (int e2 = 0; e2 < V; ++e2) m = max(m, __float_as_uint(r[k][e2]) & 0x7FFFFFFFu);
+                for (int e2 = 0; e2 < V; ++e2) m = fmaxf(m, fabsf(r[k][e2]));
             uint32_t bb = 0, bi = 0;
 #pragma unroll
             for (int i = K * V - 1; i >= 0; --i) {
-                const uint32_t x = __float_as_uint(r[i / V][i % V]);
-                const bool hit = (x & 0x7FFFFFFFu) == m;
-                bb = hit ? x : bb;
+                const float x = r[i / V][i % V];
+                const bool hit = fabsf(x) == m;
+                bb = hit ? __float_as_uint(x) : bb;
                 bi = hit ? (uint32_t)i : bi;
             }
             const uint64_t tk = R.nvalid > 0 ? make_key(bb, R.group_f((int)(bi / V)) + bi % V) : 0;
