@@ -541,6 +541,7 @@ int run(bool tiled, const float *dirty, int ny, int nx, const void *psf, int psf
         const int cw = (int)((max_tile + per_wg - 1) / per_wg);
         if (((int64_t)cw * WG * 4) % tw == 0) {
             KFn fw = pick_wide(half, fft);
+            if (fft) dyn_lds = std::max(dyn_lds, (size_t)TR_LDS_WIDE);   // its transposes' tile group
             if (dyn_lds > 48 * 1024)
                 HIPCHK(hipFuncSetAttribute((const void *)fw, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn_lds));
             int occ = 0;

@@ -16,6 +16,8 @@ constexpr int STREAM_K = 4;             // pixel groups per thread per streamed 
 constexpr int FFT_MAX_LG = 13;          // one-level FFT transforms: length <= 8192 (64 KB of LDS)
 constexpr int FFT_MAX_LG2 = 16;         // two-level FFT transforms: length <= 65536
 constexpr int FFT_LDS_CPLX = 8192 + 64; // LDS complex slots of the two-level passes
+constexpr int TR_GROUP_WIDE = 4;         // transpose tiles in flight per workgroup in the wide-tile kernel
+constexpr int TR_LDS_WIDE = TR_GROUP_WIDE * 32 * 33 * 8;
 // (with the tiled kernel's static LDS, two workgroups fit one CU's 160 KB)
 
 enum { STOP_MAXITER = 0, STOP_THRESHOLD = 1, STOP_CAPACITY = 2 };

@@ -49,6 +49,32 @@ __device__ __forceinline__ float2 cmulc(float2 p, float2 q)   // p * conj(q)
 // odd.  In a stage pair (s, s+1) the second stage's twiddle for the odd
 // butterfly is W_4 times the even one's, an exact rotation by -i (+i for the
 // inverse).  All threads of the workgroup.
+// One radix-4 unit: stage pair (s, s+1) on x0..x3 at spacing 2^s, twiddles w1
+// (stage s) and w2 (stage s+1); the arithmetic of fft_lds_multi's passes.
+__device__ __forceinline__ void radix4_unit(float2 &x0, float2 &x1, float2 &x2, float2 &x3, float2 w1, float2 w2,
+                                            bool inverse)
+{
+    if (inverse) {
+        w1.y = -w1.y;
+        w2.y = -w2.y;
+    }
+    const float2 p1 = cmul(x1, w1), p3 = cmul(x3, w1);
+    const float2 a0 = make_float2(x0.x + p1.x, x0.y + p1.y), a1 = make_float2(x0.x - p1.x, x0.y - p1.y);
+    const float2 a2 = make_float2(x2.x + p3.x, x2.y + p3.y), a3 = make_float2(x2.x - p3.x, x2.y - p3.y);
+    const float2 t = cmul(a2, w2), v = cmul(a3, w2);
+    const float2 u = inverse ? make_float2(-v.y, v.x) : make_float2(v.y, -v.x);
+    x0 = make_float2(a0.x + t.x, a0.y + t.y);
+    x2 = make_float2(a0.x - t.x, a0.y - t.y);
+    x1 = make_float2(a1.x + u.x, a1.y + u.y);
+    x3 = make_float2(a1.x - u.x, a1.y - u.y);
+}
+
+// R16: while four stages remain, a thread takes 16 points at spacing 2^s and
+// applies both stage pairs (s, s+1) and (s+2, s+3) in registers, as four
+// radix-4 units each: the same operations on the same values as two radix-4
+// passes (bit-identical), with one LDS round trip and one barrier instead of
+// two.  Needs the registers of 16 points; used where the kernel has them.
+template <bool R16 = false>
 __device__ inline void fft_lds_multi(float2 *a, int lg, int count, int stride, const float2 *tw, int tw_step,
                                      bool inverse)
 {
@@ -65,6 +91,34 @@ __device__ inline void fft_lds_multi(float2 *a, int lg, int count, int stride, c
         }
         __syncthreads();
         s = 1;
+    }
+    if constexpr (R16) {
+        const int Q16 = lg >= 4 ? 1 << (lg - 4) : 0;
+#pragma clang loop unroll(disable)
+        for (; s + 4 <= lg; s += 4) {
+            const int half = 1 << s;
+#pragma clang loop unroll(disable)
+            for (int j = threadIdx.x; j < count * Q16; j += blockDim.x) {
+                const int jj = j & (Q16 - 1);
+                const int k = jj & (half - 1);
+                float2 *b = a + (j >> (lg - 4)) * stride + ((jj >> s) << (s + 4)) + k;
+                float2 x[16];
+#pragma unroll
+                for (int m = 0; m < 16; ++m) x[m] = b[m * half];
+                const float2 w1 = tw[(k << (lg - 1 - s)) * tw_step], w2 = tw[(k << (lg - 2 - s)) * tw_step];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) radix4_unit(x[4 * q], x[4 * q + 1], x[4 * q + 2], x[4 * q + 3], w1, w2, inverse);
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int k2 = k + r * half;
+                    radix4_unit(x[r], x[r + 4], x[r + 8], x[r + 12], tw[(k2 << (lg - 3 - s)) * tw_step],
+                                tw[(k2 << (lg - 4 - s)) * tw_step], inverse);
+                }
+#pragma unroll
+                for (int m = 0; m < 16; ++m) b[m * half] = x[m];
+            }
+            __syncthreads();
+        }
     }
     const int Q = lg >= 2 ? 1 << (lg - 2) : 0;
 #pragma clang loop unroll(disable)
@@ -98,9 +152,10 @@ __device__ inline void fft_lds_multi(float2 *a, int lg, int count, int stride, c
 
 // In-place FFT of a[0 .. 2^lg) (bit-reversed input, natural-order output),
 // tw the table W_L^m of this length.  All threads of the workgroup.
+template <bool R16 = false>
 __device__ inline void fft_lds(float2 *a, int lg, const float2 *tw, bool inverse)
 {
-    fft_lds_multi(a, lg, 1, 1 << lg, tw, 1, inverse);
+    fft_lds_multi<R16>(a, lg, 1, 1 << lg, tw, 1, inverse);
 }
 
 // Puts a natural-order array into bit-reversed order, in place.
@@ -123,9 +178,53 @@ __device__ inline void bitrev_permute(float2 *a, int lg)
 // 32 x 32 tiled transpose of the rows [0, rows) x columns [0, cols) of `src`
 // (row stride ss) into dst (row stride ds): dst[c][r] = src[r][c].  Tiles are
 // dealt over the workgroups (work item w of nwork).
+//
+// G > 1: the workgroup takes G tiles at a time (lds holds G tiles) and a
+// thread issues its loads of all of them before the first LDS write, so one
+// memory round trip serves G tiles.  Needs the registers of 2G values.
+template <int G = 1>
 __device__ inline void transpose_tiles(const float2 *src, int ss, float2 *dst, int ds, int rows, int cols, int w0,
                                        int nwork, float2 (*lds)[33])
 {
+    if constexpr (G > 1) {
+        constexpr int PER = 1024 / WG;   // elements of one tile per thread
+        const int tr = (rows + 31) / 32, tc = (cols + 31) / 32, nt = tr * tc;
+        #pragma clang loop unroll(disable)
+        for (int t0 = w0; t0 < nt; t0 += G * nwork) {
+            float2 v[G][PER] = {};
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                const int t = t0 + g * nwork;
+                const int br = (t / tc) * 32, bc = (t % tc) * 32;
+#pragma unroll
+                for (int k = 0; k < PER; ++k) {
+                    const int e = (int)threadIdx.x + k * WG, r = e / 32, c = e % 32;
+                    if (t < nt && br + r < rows && bc + c < cols) v[g][k] = ldc2(&src[(size_t)(br + r) * ss + bc + c]);
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int g = 0; g < G; ++g)
+#pragma unroll
+                for (int k = 0; k < PER; ++k) {
+                    const int e = (int)threadIdx.x + k * WG;
+                    lds[g * 32 + e / 32][e % 32] = v[g][k];
+                }
+            __syncthreads();
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                const int t = t0 + g * nwork;
+                const int br = (t / tc) * 32, bc = (t % tc) * 32;
+#pragma unroll
+                for (int k = 0; k < PER; ++k) {
+                    const int e = (int)threadIdx.x + k * WG, c = e / 32, r = e % 32;
+                    if (t < nt && br + r < rows && bc + c < cols)
+                        stc2(&dst[(size_t)(bc + c) * ds + br + r], lds[g * 32 + r][c]);
+                }
+            }
+        }
+        return;
+    }
     const int tr = (rows + 31) / 32, tc = (cols + 31) / 32;
     #pragma clang loop unroll(disable)
     for (int t = w0; t < tr * tc; t += nwork) {

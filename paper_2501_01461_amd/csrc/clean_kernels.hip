@@ -1183,7 +1183,7 @@ __device__ __forceinline__ void store_split(float2 *o0, float2 *o1, bool has1, i
 // x forward, one level: row pairs -> carried bins (natural order) of `rows`
 // rows, into fft_a (row stride H).  Source: the round's aggregated component
 // lists, or (KSRC) the PSF kernel image.
-template <typename PT, bool KSRC>
+template <typename PT, bool KSRC, bool BIG = false>
 __device__ void xfwd_one(const KArgs &a, const FftAxis &fx, int Ly, int rows, const int32_t *s_off, float2 *lds,
                          int *s_nz)
 {
@@ -1228,7 +1228,7 @@ __device__ void xfwd_one(const KArgs &a, const FftAxis &fx, int Ly, int rows, co
             for (int k = threadIdx.x; k < fx.H; k += WG) store_split(o0, o1, has1, k, make_float2(0.f, 0.f),
                                                                     make_float2(0.f, 0.f));
         } else {
-            fft_lds(lds, lgx, fx.tw, false);
+            fft_lds<BIG>(lds, lgx, fx.tw, false);
             #pragma clang loop unroll(disable)
             for (int k = threadIdx.x; k < fx.H; k += WG) store_split(o0, o1, has1, k, lds[k], lds[(Lx - k) & (Lx - 1)]);
         }
@@ -1338,27 +1338,51 @@ __device__ void xfwd_two_b(const KArgs &a, const FftAxis &fx, int rows, float2 *
 // y, one level, per carried column: forward transform of the `rows` values
 // in fft_b; then either (PRE) store the spectrum as the PSF kernel's, or
 // multiply by it, transform back and store the first `rows` values.
-template <bool PRE>
+template <bool PRE, bool BIG = false>
 __device__ void ycol_one(const KArgs &a, const FftAxis &fx, const FftAxis &fy, int rows, float2 *lds)
 {
     #pragma clang loop unroll(disable)
     for (int col = blockIdx.x; col < fx.H; col += gridDim.x) {
-        #pragma clang loop unroll(disable)
-        for (int v = threadIdx.x; v < fy.L; v += WG) lds[v] = make_float2(0.f, 0.f);
-        __syncthreads();
         float2 *b = a.fft_b + (size_t)col * rows;
-        #pragma clang loop unroll(disable)
-        for (int v = threadIdx.x; v < rows; v += WG) lds[bitrev((uint32_t)v, fy.lg)] = ldc2(&b[v]);
-        fft_lds(lds, fy.lg, fy.tw, false);
+        if constexpr (BIG) {
+            // one sweep: the column's rows and the zero padding, bit-reversed
+            __syncthreads();
+            #pragma clang loop unroll(disable)
+            for (int v = threadIdx.x; v < fy.L; v += WG)
+                lds[bitrev((uint32_t)v, fy.lg)] = v < rows ? ldc2(&b[v]) : make_float2(0.f, 0.f);
+        } else {
+            #pragma clang loop unroll(disable)
+            for (int v = threadIdx.x; v < fy.L; v += WG) lds[v] = make_float2(0.f, 0.f);
+            __syncthreads();
+            #pragma clang loop unroll(disable)
+            for (int v = threadIdx.x; v < rows; v += WG) lds[bitrev((uint32_t)v, fy.lg)] = ldc2(&b[v]);
+        }
+        fft_lds<BIG>(lds, fy.lg, fy.tw, false);
         float2 *ks = a.fft_ks + (size_t)col * fy.L;
         if (PRE) {
             #pragma clang loop unroll(disable)
             for (int v = threadIdx.x; v < fy.L; v += WG) stc2(&ks[v], lds[v]);
         } else {
-            #pragma clang loop unroll(disable)
-            for (int v = threadIdx.x; v < fy.L; v += WG) lds[v] = cmul(lds[v], ldc2(&ks[v]));
-            bitrev_permute(lds, fy.lg);
-            fft_lds(lds, fy.lg, fy.tw, true);
+            if constexpr (BIG) {
+                // the product with the PSF spectrum and the bit-reversal
+                // permutation in one sweep: each pair (v, bitrev v) is
+                // multiplied and swapped by one thread
+                #pragma clang loop unroll(disable)
+                for (int v = threadIdx.x; v < fy.L; v += WG) {
+                    const int w = (int)bitrev((uint32_t)v, fy.lg);
+                    if (v > w) continue;
+                    const float2 pv = cmul(lds[v], ldc2(&ks[v]));
+                    const float2 pw = cmul(lds[w], ldc2(&ks[w]));
+                    lds[w] = pv;
+                    lds[v] = pw;
+                }
+                __syncthreads();
+            } else {
+                #pragma clang loop unroll(disable)
+                for (int v = threadIdx.x; v < fy.L; v += WG) lds[v] = cmul(lds[v], ldc2(&ks[v]));
+                bitrev_permute(lds, fy.lg);
+            }
+            fft_lds<BIG>(lds, fy.lg, fy.tw, true);
             #pragma clang loop unroll(disable)
             for (int v = threadIdx.x; v < rows; v += WG) stc2(&b[v], lds[v]);
         }
@@ -1479,6 +1503,7 @@ __device__ void ycol_two_c(const KArgs &a, const FftAxis &fx, const FftAxis &fy,
 // x inverse, one level: row pairs rebuilt from their carried bins (Hermitian
 // symmetry gives the rest), one inverse transform, real part -> row 2m,
 // imaginary part -> row 2m+1, scaled, into the feedback buffer.
+template <bool BIG = false>
 __device__ void xinv_one(const KArgs &a, const FftAxis &fx, float scale, float2 *lds)
 {
     const int Lx = fx.L, lgx = fx.lg, ny = a.ny, nx = a.nx;
@@ -1494,7 +1519,7 @@ __device__ void xinv_one(const KArgs &a, const FftAxis &fx, float scale, float2 
             lds[bitrev((uint32_t)k, lgx)] = make_float2(A.x - B.y, A.y + B.x);
             if (k > 0 && k < Lx / 2) lds[bitrev((uint32_t)(Lx - k), lgx)] = make_float2(A.x + B.y, B.x - A.y);
         }
-        fft_lds(lds, lgx, fx.tw, true);
+        fft_lds<BIG>(lds, lgx, fx.tw, true);
         #pragma clang loop unroll(disable)
         for (int x = threadIdx.x; x < nx; x += WG) {
             const float2 z = lds[x];
@@ -1580,7 +1605,7 @@ __device__ void xinv_two_b(const KArgs &a, const FftAxis &fx, float scale, float
 
 // The PSF kernel's spectrum, once per call, by the same transforms as the
 // rounds: x forward over all Ly rows of the kernel image, transpose, y forward.
-template <typename PT>
+template <typename PT, bool BIG = false>
 __device__ bool fft_spectrum(const KArgs &a, const Sync &y, uint32_t &epoch, int *s_ok)
 {
     extern __shared__ __align__(16) unsigned char s_dyn[];
@@ -1590,17 +1615,17 @@ __device__ bool fft_spectrum(const KArgs &a, const Sync &y, uint32_t &epoch, int
     const FftAxis fx = fft_axis(a.fft_lgx, a.fft_two_x, a.tw_x), fy = fft_axis(a.fft_lgy, a.fft_two_y, a.tw_y);
     const int Ly = fy.L;
     if (!fx.two) {
-        xfwd_one<PT, true>(a, fx, Ly, Ly, nullptr, lds, &s_nz);
+        xfwd_one<PT, true, BIG>(a, fx, Ly, Ly, nullptr, lds, &s_nz);
     } else {
         xfwd_two_a<PT, true>(a, fx, Ly, Ly, lds);
         FFT_BARRIER();
         xfwd_two_b<true>(a, fx, Ly, lds, nullptr);
     }
     FFT_BARRIER();
-    transpose_tiles(a.fft_a, fx.H, a.fft_b, Ly, Ly, fx.H, blockIdx.x, gridDim.x, s_tr);
+    transpose_tiles<BIG ? TR_GROUP_WIDE : 1>(a.fft_a, fx.H, a.fft_b, Ly, Ly, fx.H, blockIdx.x, gridDim.x, s_tr);
     FFT_BARRIER();
     if (!fy.two) {
-        ycol_one<true>(a, fx, fy, Ly, lds);
+        ycol_one<true, BIG>(a, fx, fy, Ly, lds);
     } else {
         ycol_two_a(a, fx, fy, Ly, lds);
         FFT_BARRIER();
@@ -1615,7 +1640,7 @@ __device__ bool fft_spectrum(const KArgs &a, const Sync &y, uint32_t &epoch, int
 // then recomputes the residual from the round's starting residual:
 // mathematically the paper's update (own components subtracted locally, the
 // others' by feedback), rounded once.
-template <typename PT>
+template <typename PT, bool BIG = false>
 __device__ bool fft_feedback(const KArgs &a, const Sync &y, uint32_t &epoch, int *s_ok, const int32_t *s_off)
 {
     extern __shared__ __align__(16) unsigned char s_dyn[];
@@ -1626,17 +1651,17 @@ __device__ bool fft_feedback(const KArgs &a, const Sync &y, uint32_t &epoch, int
     const int ny = a.ny;
     const float scale = 1.0f / ((float)fx.L * (float)fy.L);
     if (!fx.two) {
-        xfwd_one<PT, false>(a, fx, fy.L, ny, s_off, lds, &s_nz);
+        xfwd_one<PT, false, BIG>(a, fx, fy.L, ny, s_off, lds, &s_nz);
     } else {
         xfwd_two_a<PT, false>(a, fx, fy.L, ny, lds);
         FFT_BARRIER();
         xfwd_two_b<false>(a, fx, ny, lds, s_off);
     }
     FFT_BARRIER();
-    transpose_tiles(a.fft_a, fx.H, a.fft_b, ny, ny, fx.H, blockIdx.x, gridDim.x, s_tr);
+    transpose_tiles<BIG ? TR_GROUP_WIDE : 1>(a.fft_a, fx.H, a.fft_b, ny, ny, fx.H, blockIdx.x, gridDim.x, s_tr);
     FFT_BARRIER();
     if (!fy.two) {
-        ycol_one<false>(a, fx, fy, ny, lds);
+        ycol_one<false, BIG>(a, fx, fy, ny, lds);
     } else {
         ycol_two_a(a, fx, fy, ny, lds);
         FFT_BARRIER();
@@ -1645,10 +1670,10 @@ __device__ bool fft_feedback(const KArgs &a, const Sync &y, uint32_t &epoch, int
         ycol_two_c(a, fx, fy, ny, lds);
     }
     FFT_BARRIER();
-    transpose_tiles(a.fft_b, ny, a.fft_a, fx.H, fx.H, ny, blockIdx.x, gridDim.x, s_tr);
+    transpose_tiles<BIG ? TR_GROUP_WIDE : 1>(a.fft_b, ny, a.fft_a, fx.H, fx.H, ny, blockIdx.x, gridDim.x, s_tr);
     FFT_BARRIER();
     if (!fx.two) {
-        xinv_one(a, fx, scale, lds);
+        xinv_one<BIG>(a, fx, scale, lds);
     } else {
         xinv_two_a(a, fx, lds);
         FFT_BARRIER();
@@ -1806,7 +1831,7 @@ tiled_kernel(const KArgs a)
     }
     if (!grid_barrier(y, epoch, &s_ok)) return;
     if constexpr (FFT) {
-        if (!fft_spectrum<PT>(a, y, epoch, &s_ok)) return;
+        if (!fft_spectrum<PT, Tile::kWide>(a, y, epoch, &s_ok)) return;
     }
 
     const int64_t limit = a.max_iter < a.cap ? a.max_iter : a.cap;
@@ -1922,7 +1947,7 @@ tiled_kernel(const KArgs a)
         // ---- feedback by FFT: acc = component image (*) K, every tile's
         // components (apply then starts from the round's starting residual)
         if constexpr (FFT) {
-            if (!fft_feedback<PT>(a, y, epoch, &s_ok, s_off)) return;
+            if (!fft_feedback<PT, Tile::kWide>(a, y, epoch, &s_ok, s_off)) return;
         } else
         // ---- feedback gather: acc[q] = sum over other tiles' components
         {
