@@ -254,6 +254,34 @@ def main():
         if ti:
             jy["bands_tiled_minus_plain"][f"{nm}_psf_tuned_interval{ti}"] = band(cfg, 0.0, ti)
 
+    # time to threshold: tiled iterations each remove less than plain ones, so
+    # next to minor-iters/s, the time each method needs to bring the residual
+    # peak below the level plain CLEAN reaches after the same 20000 iterations
+    def time_to_plain_peak(cfg, level, ivl):
+        d_ = torch.from_numpy(cfg["dirty"]).to(dev)
+        p_ = torch.from_numpy(cfg["psf"]).to(dev)
+        mp = P.hogbom(d_, p_, gain, thr, n_iter, model=False)
+        target = abs(mp["stats"]["final_peak"])
+        mt = P.tiled_feedback(d_, p_, tiles, ivl, gain, target, 10 * n_iter, model=False, level=level)
+        st = mt["stats"]
+        # a diverged run can also end on the threshold rule (non-finite peaks
+        # are never active), so the residual must be finite and below target
+        fin = bool(torch.isfinite(mt["residual"]).all().item())
+        reached = st["stop_reason"] == 1 and fin and abs(st["final_peak"]) < target
+        return {"target_peak": target, "plain_ms": mp["stats"]["device_ms"], "plain_iters": mp["stats"]["n_iter"],
+                "tiled_ms": st["device_ms"], "tiled_iters": st["n_iter"], "tiled_rounds": st["n_rounds"],
+                "tiled_final_peak": abs(st["final_peak"]), "residual_finite": fin, "reached": bool(reached),
+                "speedup": mp["stats"]["device_ms"] / st["device_ms"] if reached else None}
+    jy["time_to_plain_peak"] = {
+        "snapshot_psf_interval100": time_to_plain_peak(c, 0.0, interval),
+        "snapshot_psf_flux_level_0.5": time_to_plain_peak(c, 0.5, interval),
+        "track_psf_interval100": time_to_plain_peak(ctrack, 0.0, interval),
+        "track_psf_flux_level_0.5": time_to_plain_peak(ctrack, 0.5, interval),
+        "note": ("plain: 20000 iterations, target = |residual peak| after them; tiled: the same call with "
+                 "threshold = target (it stops when every tile peak is below it) and at most 200000 iterations; "
+                 "reached false: it never got there (diverged or ran out of iterations)"),
+    }
+
     # no feedback at all: each tile cleaned on its own (plain clean_hogbom on
     # its crop, the crop's share of the iterations); the residual is then the
     # consistent one, dirty - model (*) PSF (float64 on the host)
