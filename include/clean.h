@@ -113,7 +113,14 @@ typedef struct {
     int32_t wg_per_tile;  /* launch shape: workgroups per tile (0 = library pick) */
     int32_t px_per_thread;/* launch shape: residual pixels per thread, one of
                              4, 8, 16, 32, 64 when tile widths are multiples of
-                             4, else 4, 16, 32 (0 = library pick)             */
+                             4, else 4, 16, 32 (0 = library pick).  Tiled calls
+                             also take 128: the wide tile (one workgroup per
+                             CU, residual in registers during the local loops
+                             only), which the library picks by itself for
+                             tiles too large for the other shapes; it needs
+                             equal tile widths, multiples of 4, dividing
+                             2048 x (its workgroups per tile), and
+                             wg_per_tile = 0                                   */
     double feedback_level;/* tiled only, in [0, 1]: the flux trigger.  Each
                              round's level is this fraction of the largest tile
                              peak at the round's start; a tile takes part only

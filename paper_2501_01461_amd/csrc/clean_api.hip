@@ -512,7 +512,10 @@ int run(bool tiled, const float *dirty, int ny, int nx, const void *psf, int psf
     const bool force_stream = (p->flags & CLEAN_FLAG_STREAM_RESIDUAL) != 0;
     if (force_stream && p->px_per_thread)
         return fail(CLEAN_E_INVAL, "px_per_thread applies to the register-resident form only");
-    st = force_stream ? CLEAN_E_UNSUPPORTED
+    const bool want_wide = tiled && p->px_per_thread == 128;   // the wide tile on request
+    if (want_wide && p->wg_per_tile)
+        return fail(CLEAN_E_INVAL, "px_per_thread = 128 (the wide tile) picks its own workgroups per tile");
+    st = force_stream || want_wide ? CLEAN_E_UNSUPPORTED
                       : choose_shape(max_tile, V, p->wg_per_tile, p->px_per_thread, tiled ? 32 : 64,
                                      tiled ? (T + 7) / 8 : 0, ncu / 8, cs, ppt);
     if (st == CLEAN_OK) {
@@ -527,7 +530,7 @@ int run(bool tiled, const float *dirty, int ny, int nx, const void *psf, int psf
                 return fail(CLEAN_E_UNSUPPORTED, "%d x %d workgroups cannot be co-resident (max %d)", T, cs, occ * ncu);
             streamed = true;
         }
-    } else if (p->px_per_thread == 0) {
+    } else if (p->px_per_thread == 0 || want_wide) {
         streamed = true;
     } else {
         return st;
@@ -535,7 +538,8 @@ int run(bool tiled, const float *dirty, int ny, int nx, const void *psf, int psf
     // tiles too large for the register tiles: 128 px/thread held in registers
     // during the local loops (WideTile) when the image fits the co-resident
     // register file that way, else the residual streamed through HBM
-    if (streamed && !force_stream && tiled && V == 4 && !p->wg_per_tile && !p->px_per_thread && nx % tiles_x == 0) {
+    if (streamed && !force_stream && tiled && V == 4 && !p->wg_per_tile && (!p->px_per_thread || want_wide) &&
+        nx % tiles_x == 0) {
         const int tw = nx / tiles_x;
         const int64_t per_wg = (int64_t)WG * 128;
         const int cw = (int)((max_tile + per_wg - 1) / per_wg);
@@ -554,6 +558,10 @@ int run(bool tiled, const float *dirty, int ny, int nx, const void *psf, int psf
             }
         }
     }
+    if (want_wide && streamed)
+        return fail(CLEAN_E_UNSUPPORTED, "the wide tile needs tile widths that are equal, multiples of 4 and "
+                                         "divide %d x 2048 pixels, and a co-resident launch",
+                    (int)((max_tile + (int64_t)WG * 128 - 1) / ((int64_t)WG * 128)));
     if (streamed) {
         g_last_error.clear();
         fn = pick_stream(tiled, half, V, fft);

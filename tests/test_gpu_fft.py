@@ -106,6 +106,52 @@ def test_fft_one_round_small(lib, case, two):
     check_one_round(out, ref, psf_ref, tiles, dirty)
 
 
+# The wide tile (px_per_thread = 128) at small sizes: its kernel takes the
+# radix-16 transform passes, four transpose tiles in flight and the fused
+# column sweeps, at odd and even transform lengths (radix-2 and radix-4
+# leftovers) and with partial transpose tile groups.
+WIDE_ONE_ROUND = [
+    # ny, nx, tiles, interval, seed, f16
+    (64, 64, (2, 2), 50, 81, False),           # Lx = Ly = 128: radix-2, one radix-16, one radix-4 pass
+    (96, 128, (3, 2), 30, 82, False),          # 256: two radix-16 passes
+    (128, 128, (4, 4), 20, 83, True),          # FP16-stored PSF
+    (250, 256, (2, 2), 40, 84, False),         # 512; ragged 125-row tiles
+]
+
+
+@pytest.mark.parametrize("two", [False, True], ids=["one-level", "two-level"])
+@pytest.mark.parametrize("case", WIDE_ONE_ROUND, ids=[f"{c[0]}x{c[1]}-{c[2][0]}x{c[2][1]}-I{c[3]}"
+                                                       + ("-f16" if c[5] else "") for c in WIDE_ONE_ROUND])
+def test_fft_one_round_wide_tile(lib, case, two):
+    import torch
+    ny, nx, tiles, interval, seed, f16 = case
+    announce("fft one round wide tile", case, "two-level" if two else "one-level")
+    dirty = sparse_dirty(ny, nx, seed)
+    psf = asym_psf(2 * ny, 2 * nx + 2, seed)
+    n = tiles[0] * tiles[1] * interval
+    psf_ref = psf.astype(np.float16).astype(np.float32) if f16 else psf
+    ref = oracle.tiled(dirty, psf_ref, tiles, interval, 0.1, 0.0, n)
+    dpsf = dev(psf).to(torch.float16) if f16 else dev(psf)
+    out = lib.tiled_feedback(dev(dirty), dpsf, tiles, interval, 0.1, 0.0, n, fft=True, fft_two_level=two,
+                             px_per_thread=128)
+    assert out["stats"]["px_per_thread"] == 128 and out["stats"]["streamed"] == 0
+    check_one_round(out, ref, psf_ref, tiles, dirty)
+
+
+@pytest.mark.parametrize("case", [(64, 64, (2, 2), 20, 85, 1000, 0.0), (96, 128, (3, 2), 25, 86, 1200, 0.5)],
+                         ids=["64x64-2x2-I20", "96x128-3x2-I25-f0.5"])
+def test_fft_many_rounds_wide_tile(lib, case):
+    ny, nx, tiles, interval, seed, n, level = case
+    announce("fft many rounds wide tile", case)
+    dirty = sparse_dirty(ny, nx, seed)
+    psf = asym_psf(2 * ny, 2 * nx + 2, seed)
+    ref = oracle.tiled(dirty, psf, tiles, interval, 0.1, 0.0, n, level=level)
+    out = lib.tiled_feedback(dev(dirty), dev(psf), tiles, interval, 0.1, 0.0, n, level=level, fft=True,
+                             px_per_thread=128)
+    assert out["stats"]["px_per_thread"] == 128
+    check_many_rounds(out, ref, dirty, psf, tiles, interval)
+
+
 @pytest.mark.parametrize("two", [False, True], ids=["one-level", "two-level"])
 def test_fft_one_round_config1(lib, two):
     """1024^2 image, 2048^2 snapshot PSF, 2x2 tiles, interval 100: one round (400 components)."""

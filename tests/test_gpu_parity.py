@@ -31,6 +31,13 @@ def sparse_dirty(ny, nx, seed, density=0.02, noise=0.02):
     return d.astype(np.float32)
 
 
+def max_tile(ny, nx, tiles):
+    """Pixels of the largest tile of the floor split."""
+    hs = [(i + 1) * ny // tiles[0] - i * ny // tiles[0] for i in range(tiles[0])]
+    ws = [(j + 1) * nx // tiles[1] - j * nx // tiles[1] for j in range(tiles[1])]
+    return max(hs) * max(ws)
+
+
 def asym_psf(My, Mx, seed, spread=0.3):
     return synth.random_psf(My, Mx, np.random.default_rng([12, seed]), spread).astype(np.float32)
 
@@ -189,6 +196,66 @@ def test_tiled_bitexact_small(lib, case):
     out = lib.tiled_feedback(dev(dirty), dev(psf), tiles, interval, 0.1, thr, n, wg_per_tile=wg, px_per_thread=ppt)
     assert out["stats"]["n_rounds"] == ref["n_rounds"]
     assert_same_run(out, ref)
+
+
+# The wide tile (px_per_thread = 128) at small sizes: tiles of a few hundred
+# to 76800 pixels leave most of each thread's 32 pixel groups outside the tile
+# (groups past the tile's end hold +0 and read group 0's PSF window), ragged
+# heights give threads different group counts, and the last case has two
+# workgroups per tile.  Tile widths divide 2048 x the workgroups per tile.
+WIDE_CASES = [
+    # ny, nx, tiles, interval, seed, max_iter, threshold
+    (64, 64, (2, 2), 10, 41, 300, 0.0),
+    (60, 128, (3, 2), 7, 42, 250, 0.0),
+    (250, 256, (2, 2), 20, 43, 600, 0.0),         # 125-row tiles: 7 or 8 groups per thread
+    (96, 128, (2, 2), 50, 44, 400, 0.05),         # threshold stop
+    (300, 512, (1, 2), 30, 45, 800, 0.0),         # 76800-pixel tiles: 2 workgroups per tile
+    (40, 64, (1, 1), 9, 46, 100, 0.0),            # one tile
+]
+
+
+@pytest.mark.parametrize("case", WIDE_CASES, ids=[f"{c[0]}x{c[1]}-{c[2][0]}x{c[2][1]}-I{c[3]}" for c in WIDE_CASES])
+def test_tiled_wide_tile_small(lib, case):
+    ny, nx, tiles, interval, seed, n, thr = case
+    announce("tiled wide tile", case)
+    dirty = sparse_dirty(ny, nx, seed, density=0.03)
+    psf = asym_psf(2 * ny, 2 * nx + 2, seed, spread=0.2)
+    ref = oracle.tiled(dirty, psf, tiles, interval, 0.1, thr, n)
+    out = lib.tiled_feedback(dev(dirty), dev(psf), tiles, interval, 0.1, thr, n, px_per_thread=128)
+    st = out["stats"]
+    assert st["px_per_thread"] == 128 and st["streamed"] == 0
+    assert st["wg_per_tile"] == -(-max_tile(ny, nx, tiles) // (512 * 128))
+    assert st["n_rounds"] == ref["n_rounds"]
+    assert_same_run(out, ref)
+
+
+def test_tiled_wide_tile_f16(lib):
+    """The wide tile with an FP16-stored PSF against the oracle run on that
+    PSF's float32 values."""
+    import torch
+    announce("tiled wide tile f16")
+    ny, nx, tiles = 250, 256, (2, 2)
+    dirty = sparse_dirty(ny, nx, 47, density=0.03)
+    psf = asym_psf(2 * ny, 2 * nx + 2, 47, spread=0.2)
+    psf_ref = psf.astype(np.float16).astype(np.float32)
+    ref = oracle.tiled(dirty, psf_ref, tiles, 15, 0.1, 0.0, 500)
+    out = lib.tiled_feedback(dev(dirty), dev(psf).to(torch.float16), tiles, 15, 0.1, 0.0, 500, px_per_thread=128)
+    assert out["stats"]["px_per_thread"] == 128
+    assert_same_run(out, ref)
+
+
+def test_tiled_wide_tile_rejected(lib):
+    """px_per_thread = 128 is the tiled wide tile only: with a workgroup count,
+    with tile widths that do not divide 2048, or for the plain call it fails
+    with a message and touches nothing."""
+    dirty = sparse_dirty(64, 96, 48)
+    psf = asym_psf(128, 194, 48)
+    for call in (lambda: lib.tiled_feedback(dev(dirty), dev(psf), (2, 2), 10, 0.1, 0.0, 50, px_per_thread=128,
+                                            wg_per_tile=1),
+                 lambda: lib.tiled_feedback(dev(dirty), dev(psf), (2, 2), 10, 0.1, 0.0, 50, px_per_thread=128),
+                 lambda: lib.hogbom(dev(dirty), dev(psf), 0.1, 0.0, 50, px_per_thread=128)):
+        with pytest.raises(lib.CleanError):
+            call()
 
 
 def test_tiled_one_tile_equals_plain(lib):
