@@ -207,6 +207,7 @@ def batched(problems, gain=0.1, model=True, check_finite=False, px_per_thread=0)
     problems: list of dicts with device tensors "dirty" (float32 2-D) and "psf"
     (float32 or float16, all the same dtype), and "threshold", "max_iter",
     optional "cap".  Returns a list of dict(residual, idx, flux, model, stats).
+    The outputs are views into four allocations shared by the whole batch.
     """
     torch = _torch()
     lib = load()
@@ -214,17 +215,34 @@ def batched(problems, gain=0.1, model=True, check_finite=False, px_per_thread=0)
     arr = (Problem * max(n, 1))()
     keep, outs = [], []
     psf_dtype = None
+    prep = [_prep(q["dirty"], q["psf"]) for q in problems]
+    caps = [max(int(q.get("cap", q["max_iter"])), 1) for q in problems]
+    # the outputs of all problems in four allocations, one view per problem,
+    # each starting on a 256-byte boundary (64 elements) like a tensor of its own
+    npix = [d.numel() for d, _ in prep]
+    up = lambda v: (v + 63) // 64 * 64
+    dev_ = prep[0][0].device if n else None
+    if n:
+        slab_r = torch.empty(sum(map(up, npix)), dtype=torch.float32, device=dev_)
+        slab_i = torch.empty(sum(map(up, caps)), dtype=torch.int32, device=dev_)
+        slab_f = torch.empty(sum(map(up, caps)), dtype=torch.float32, device=dev_)
+        slab_m = torch.empty(sum(map(up, npix)), dtype=torch.float64, device=dev_) if model else None
+    op = oc = 0
     for i, q in enumerate(problems):
-        d, p = _prep(q["dirty"], q["psf"])
+        d, p = prep[i]
         if psf_dtype is None:
             psf_dtype = p.dtype
         elif p.dtype != psf_dtype:
             raise TypeError("all PSFs of a batch must share one dtype")
         cap = int(q.get("cap", q["max_iter"]))
-        res, idx, flux, mod = _outputs(d, cap, model)
+        ny, nx = d.shape
+        res = slab_r[op:op + npix[i]].view(ny, nx)
+        mod = slab_m[op:op + npix[i]].view(ny, nx) if model else None
+        idx, flux = slab_i[oc:oc + caps[i]], slab_f[oc:oc + caps[i]]
+        op += up(npix[i])
+        oc += up(caps[i])
         keep += [d, p]
         outs.append((res, idx, flux, mod))
-        ny, nx = d.shape
         arr[i] = Problem(d.data_ptr(), p.data_ptr(), res.data_ptr(), idx.data_ptr(), flux.data_ptr(),
                          mod.data_ptr() if mod is not None else None, cap, int(q["max_iter"]),
                          float(q["threshold"]), ny, nx, p.shape[0], p.shape[1])
