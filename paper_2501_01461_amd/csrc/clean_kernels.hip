@@ -147,6 +147,20 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void *base, ui
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)n, 0x00020000);
 }
 
+// The same for a base and size that are equal in all lanes of the wave (one
+// PSF window per wave) where the compiler cannot prove it (inside a
+// non-inlined function, or when the window comes from memory): both go to
+// scalar registers.  Without that the compiler wraps each load in a loop over
+// the wave's distinct descriptors and waits for every load before the next.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc_uniform(const void *base, uint64_t bytes)
+{
+    const uint32_t n = __builtin_amdgcn_readfirstlane(bytes > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)bytes);
+    const uint64_t p = (uint64_t)(uintptr_t)base;
+    const uint64_t u = ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(p >> 32)) << 32) |
+                       (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)p);
+    return __builtin_amdgcn_make_buffer_rsrc((void *)(uintptr_t)u, (short)0, (int)n, 0x00020000);
+}
+
 // V consecutive PSF values, widened to float, at byte offset `off`.
 template <typename PT, int V> struct PsfLoad;
 template <> struct PsfLoad<float, 4> {
@@ -457,7 +471,7 @@ template <int K, int V, typename PT> struct RegTile {
     {
         const int64_t w0 = (int64_t)(a.cy - py) * a.psf_nx + (a.cx - px);
         const char *base = (const char *)a.psf + w0 * (int64_t)sizeof(PT);
-        const __amdgpu_buffer_rsrc_t rs = make_rsrc(base, a.psf_bytes - (uint64_t)w0 * sizeof(PT));
+        const __amdgpu_buffer_rsrc_t rs = make_rsrc_uniform(base, a.psf_bytes - (uint64_t)w0 * sizeof(PT));
         float pv[K][V];
 #pragma unroll
         for (int k = 0; k < K; ++k) PsfLoad<PT, V>::load(rs, (uint32_t)qoff[k] * (uint32_t)sizeof(PT), pv[k]);
@@ -670,7 +684,7 @@ __device__ __noinline__ WideRound wide_round(const KArgs &a, const Img im, const
         // r -= c * PSF window (eq. 2)
         const int64_t w0 = (int64_t)(a.cy - py) * a.psf_nx + (a.cx - px);
         const char *base = (const char *)a.psf + w0 * (int64_t)sizeof(PT);
-        const __amdgpu_buffer_rsrc_t rs = make_rsrc(base, a.psf_bytes - (uint64_t)w0 * sizeof(PT));
+        const __amdgpu_buffer_rsrc_t rs = make_rsrc_uniform(base, a.psf_bytes - (uint64_t)w0 * sizeof(PT));
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             // the whole offset in the (range-checked) vector offset; groups
