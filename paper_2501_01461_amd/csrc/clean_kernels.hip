@@ -161,6 +161,21 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc_uniform(const void *
     return __builtin_amdgcn_make_buffer_rsrc((void *)(uintptr_t)u, (short)0, (int)n, 0x00020000);
 }
 
+// A value that is equal in all lanes of the wave, moved to scalar registers
+// (each 32-bit word from the first active lane), for code where the compiler
+// cannot prove it uniform: function arguments and loads through them.
+template <typename T> __device__ __forceinline__ T wave_uniform(const T &v)
+{
+    static_assert(sizeof(T) % 4 == 0, "whole 32-bit words");
+    uint32_t w[sizeof(T) / 4];
+    __builtin_memcpy(w, &v, sizeof(T));
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(T) / 4); ++i) w[i] = __builtin_amdgcn_readfirstlane(w[i]);
+    T r;
+    __builtin_memcpy(&r, w, sizeof(T));
+    return r;
+}
+
 // V consecutive PSF values, widened to float, at byte offset `off`.
 template <typename PT, int V> struct PsfLoad;
 template <> struct PsfLoad<float, 4> {
@@ -668,23 +683,34 @@ __device__ __noinline__ WideRound wide_round(const KArgs &a, const Img im, const
 #pragma unroll
         for (int e2 = 0; e2 < V; ++e2) r[k][e2] = k < R.nvalid ? src[img + e2] : 0.0f;
     }
+    // the round's scalars (equal in every lane) in scalar registers: this
+    // function's arguments and what is read through them are vector values
+    // to the compiler
+    const double thr = wave_uniform(a.threshold), lvl = wave_uniform(level);
+    const float gain = wave_uniform(a.gain);
+    const int anx = wave_uniform(a.nx), acy = wave_uniform(a.cy), acx = wave_uniform(a.cx);
+    const int apnx = wave_uniform(a.psf_nx), tw = wave_uniform(R.w), ty0 = wave_uniform(R.y0), tx0 = wave_uniform(R.x0);
+    const void *psf = wave_uniform(a.psf);
+    const uint64_t psf_bytes = wave_uniform(a.psf_bytes);
+    double *model = wave_uniform(a.model);
+    const int64_t nb = wave_uniform(budget);
     const uint32_t voff = (uint32_t)R.qoff * (uint32_t)sizeof(PT);
-    const uint32_t step = (R.stride() / (uint32_t)R.w) * (uint32_t)a.psf_nx * (uint32_t)sizeof(PT);
-    WideRound out{cur, e, 0, 1};
-    for (int64_t it = 0; it < budget; ++it) {
+    const uint32_t step = (R.stride() / (uint32_t)tw) * (uint32_t)apnx * (uint32_t)sizeof(PT);
+    WideRound out{wave_uniform(cur), e, 0, 1};
+    for (int64_t it = 0; it < nb; ++it) {
         const float v = key_value(out.cur);
-        if ((double)fabsf(v) < a.threshold || (double)fabsf(v) < level) break;
-        const float c = a.gain * v;
+        if ((double)fabsf(v) < thr || (double)fabsf(v) < lvl) break;
+        const float c = gain * v;
         const uint32_t fp = key_f(out.cur);
-        const int ly = (int)(fp / (uint32_t)R.w), lx = (int)(fp % (uint32_t)R.w);
-        const int py = R.y0 + ly, px = R.x0 + lx;
-        const int32_t img = py * a.nx + px;
+        const int ly = (int)(fp / (uint32_t)tw), lx = (int)(fp % (uint32_t)tw);
+        const int py = ty0 + ly, px = tx0 + lx;
+        const int32_t img = py * anx + px;
         if (leader && threadIdx.x == 0) { l_idx[out.L] = img; l_flux[out.L] = c; }
-        if (a.model && R.owns(fp)) a.model[img] += (double)c;
+        if (model && R.owns(fp)) model[img] += (double)c;
         // r -= c * PSF window (eq. 2)
-        const int64_t w0 = (int64_t)(a.cy - py) * a.psf_nx + (a.cx - px);
-        const char *base = (const char *)a.psf + w0 * (int64_t)sizeof(PT);
-        const __amdgpu_buffer_rsrc_t rs = make_rsrc_uniform(base, a.psf_bytes - (uint64_t)w0 * sizeof(PT));
+        const int64_t w0 = (int64_t)(acy - py) * apnx + (acx - px);
+        const char *base = (const char *)psf + w0 * (int64_t)sizeof(PT);
+        const __amdgpu_buffer_rsrc_t rs = make_rsrc_uniform(base, psf_bytes - (uint64_t)w0 * sizeof(PT));
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             // the whole offset in the (range-checked) vector offset; groups
@@ -697,7 +723,7 @@ __device__ __noinline__ WideRound wide_round(const KArgs &a, const Img im, const
             for (int e2 = 0; e2 < V; ++e2) r[k][e2] = __builtin_fmaf(-ck, pv[e2], r[k][e2]);
         }
         out.L += 1;
-        if (it + 1 < budget) {
+        if (it + 1 < nb) {
             // thread key: the largest |r|, then the lowest index holding it
             // (RegTile's form; for finite values the same as take_key's)
             float m = 0.0f;
@@ -718,6 +744,7 @@ __device__ __noinline__ WideRound wide_round(const KArgs &a, const Img im, const
                 out.ok = 0;
                 return out;
             }
+            out.cur = wave_uniform(out.cur);
         }
     }
     if (!R.fft) {
@@ -909,8 +936,10 @@ template <class Tile> __device__ void store_and_sum(const Tile &R, const Img &im
 // member clears its entries of them before that first, device-scope
 // exchange, which no member passes until all have cleared theirs).  Returns
 // false if the run was aborted.
-template <class Tile> __device__ bool run_plain(const PlainJob &j, int rank, const Sync &y, bool local)
+template <class Tile> __device__ bool run_plain(const PlainJob &j_arg, int rank_arg, const Sync &y, bool local)
 {
+    const PlainJob j = wave_uniform(j_arg);     // one problem per workgroup
+    const int rank = wave_uniform(rank_arg);
     const Img im{j.dirty, j.residual, j.model, nullptr, nullptr, j.psf, j.psf_bytes, j.nx, j.psf_nx, j.cy, j.cx};
     Tile T;
     T.init(im, 0, 0, j.ny, j.nx, j.cs, rank);
@@ -928,6 +957,7 @@ template <class Tile> __device__ bool run_plain(const PlainJob &j, int rank, con
     uint32_t e = 0;
     uint64_t cur;
     if (!cluster_reduce(y, j.slots, nullptr, j.slot_pad, j.cs, rank, e++, T.key(im), cur)) return false;
+    cur = wave_uniform(cur);
 
     const bool leader = rank == 0 && threadIdx.x == 0;
     int64_t n = 0;
@@ -951,6 +981,7 @@ template <class Tile> __device__ bool run_plain(const PlainJob &j, int rank, con
         // subtraction (eq. 2) fused with the next peak search
         if (!cluster_reduce(y, j.slots, ls, j.slot_pad, j.cs, rank, e++, T.subtract(im, py, px, c, true), cur))
             return false;
+        cur = wave_uniform(cur);
         n += 1;
     }
     store_and_sum(T, im, j.partial, rank);
