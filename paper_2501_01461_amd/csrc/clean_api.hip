@@ -795,10 +795,10 @@ int clean_batched(const clean_problem *probs, int n, const clean_params *shared,
     int ppt = shared->px_per_thread;
     if (ppt == 0) {
         // 32 pixels per thread when the per-XCD schedule takes it: two
-        // workgroups per CU and exchanges inside one L2 (256 images of
-        // 128^2..1024^2: 138 ms).  Else 64: half the workgroups per problem,
-        // so twice as many problems run at once across the device (153 ms;
-        // 32 px/thread across the device: 182 ms).
+        // workgroups per CU and exchanges inside one L2 (the fastest shape
+        // on 256 images of 128^2..1024^2).  Else 64: half the workgroups per
+        // problem, so twice as many problems run at once across the device
+        // (faster there than 32 px/thread across the device).
         ppt = V == 4 ? 64 : 16;
         int mw = 0;
         bool xok = false;
