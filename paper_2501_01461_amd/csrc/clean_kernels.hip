@@ -725,21 +725,31 @@ __device__ __noinline__ WideRound wide_round(const KArgs &a, const Img im, const
         out.L += 1;
         if (it + 1 < nb) {
             // thread key: the largest |r|, then the lowest index holding it
-            // (RegTile's form; for finite values the same as take_key's)
-            float m = 0.0f;
+            // (for finite values the same as take_key's).  One pass over the
+            // groups keeps the first group whose largest |r| is the largest so
+            // far, with its four values; then the lowest of those four at that
+            // magnitude.  Groups of NaNs are never taken (as the max skips them).
+            float m = -1.0f;
+            uint32_t kb = 0;
+            float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f, s3 = 0.0f;
 #pragma unroll
-            for (int k = 0; k < K; ++k)
-#pragma unroll
-                for (int e2 = 0; e2 < V; ++e2) m = fmaxf(m, fabsf(r[k][e2]));
-            uint32_t bb = 0, bi = 0;
-#pragma unroll
-            for (int i = K * V - 1; i >= 0; --i) {
-                const float x = r[i / V][i % V];
-                const bool hit = fabsf(x) == m;
-                bb = hit ? __float_as_uint(x) : bb;
-                bi = hit ? (uint32_t)i : bi;
+            for (int k = 0; k < K; ++k) {
+                const float g = fmaxf(fmaxf(fabsf(r[k][0]), fabsf(r[k][1])), fmaxf(fabsf(r[k][2]), fabsf(r[k][3])));
+                const bool hit = g > m;
+                m = hit ? g : m;
+                kb = hit ? (uint32_t)k : kb;
+                s0 = hit ? r[k][0] : s0;
+                s1 = hit ? r[k][1] : s1;
+                s2 = hit ? r[k][2] : s2;
+                s3 = hit ? r[k][3] : s3;
             }
-            const uint64_t tk = R.nvalid > 0 ? make_key(bb, R.group_f((int)(bi / V)) + bi % V) : 0;
+            uint32_t bb = __float_as_uint(s0), be = 0;      // no group taken: (+0, group 0)
+            if (m >= 0.0f && fabsf(s0) != m) {
+                const bool h1 = fabsf(s1) == m, h2 = fabsf(s2) == m;
+                bb = h1 ? __float_as_uint(s1) : h2 ? __float_as_uint(s2) : __float_as_uint(s3);
+                be = h1 ? 1u : h2 ? 2u : 3u;
+            }
+            const uint64_t tk = R.nvalid > 0 ? make_key(bb, R.group_f((int)kb) + be) : 0;
             if (!cluster_reduce(y, slots, lslots, a.slot_pad, R.cs, R.rank, out.e++, tk, out.cur)) {
                 out.ok = 0;
                 return out;
