@@ -465,6 +465,33 @@ template <int K, int V, typename PT> struct RegTile {
     __device__ __forceinline__ uint64_t key(const Img &) const
     {
         if (!(valid & 1ull)) return 0;
+        if constexpr (V == 4) {
+            // one pass over the groups: the first group whose largest |r| is
+            // the largest so far, with its four values, then the lowest of
+            // those at that magnitude (NaN groups are never taken, as the max
+            // below skips NaNs; no group taken: +0 at group 0)
+            float gm = -1.0f;
+            uint32_t kb = 0;
+            float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f, s3 = 0.0f;
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const float g = fmaxf(fmaxf(fabsf(r[k][0]), fabsf(r[k][1])), fmaxf(fabsf(r[k][2]), fabsf(r[k][3])));
+                const bool hit = g > gm;
+                gm = hit ? g : gm;
+                kb = hit ? (uint32_t)k : kb;
+                s0 = hit ? r[k][0] : s0;
+                s1 = hit ? r[k][1] : s1;
+                s2 = hit ? r[k][2] : s2;
+                s3 = hit ? r[k][3] : s3;
+            }
+            uint32_t bb = __float_as_uint(s0), be = 0;
+            if (gm >= 0.0f && fabsf(s0) != gm) {
+                const bool h1 = fabsf(s1) == gm, h2 = fabsf(s2) == gm;
+                bb = h1 ? __float_as_uint(s1) : h2 ? __float_as_uint(s2) : __float_as_uint(s3);
+                be = h1 ? 1u : h2 ? 2u : 3u;
+            }
+            return make_key(bb, group_f((int)kb) + be);
+        }
         float m = 0.0f;
 #pragma unroll
         for (int k = 0; k < K; ++k)
