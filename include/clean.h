@@ -40,13 +40,17 @@
  * - Arithmetic (the FP32 path): component = fl32((float)gain * v); each pixel
  *   update is one fused multiply-add r = fma(-component, psf, r); the peak is
  *   the largest |r| with ties going to the lowest index; the stop tests, made
- *   before each append, are n == max_iter, then (double)|v| < threshold, then
- *   n == capacity.  IEEE subnormals are kept.  With an FP32 PSF the plain
- *   path's components and residual are bit-identical to a serial CPU run of
- *   the same definition.
- * - Non-finite input: with CLEAN_FLAG_CHECK_FINITE the dirty image (and the
- *   PSF) are scanned first and CLEAN_E_NONFINITE is returned if any value is
- *   NaN or infinite; without it the result for such input is undefined.
+ *   before each append, are n == max_iter, then v not finite, then
+ *   (double)|v| < threshold, then n == capacity.  IEEE subnormals are kept.
+ *   With an FP32 PSF the plain path's components and residual are
+ *   bit-identical to a serial CPU run of the same definition.
+ * - Non-finite values: the peak search orders |r| with +Inf above every
+ *   finite value and every NaN above +Inf (all NaNs equal, lowest index
+ *   first), so a region holding a NaN or an infinity has a non-finite peak,
+ *   and a non-finite peak ends the run with CLEAN_STOP_NONFINITE before
+ *   anything is appended.  This covers a run that diverges (values overflow)
+ *   as well as non-finite input: with CLEAN_FLAG_CHECK_FINITE the dirty image
+ *   and the PSF are scanned first and CLEAN_E_NONFINITE is returned instead.
  * - Concurrency: calls that use the library's internal workspace (workspace ==
  *   NULL) must not overlap on one device; pass separate workspaces to overlap.
  */
@@ -73,7 +77,9 @@ typedef enum {
 typedef enum {
     CLEAN_STOP_MAXITER = 0,   /* max_iter components were found               */
     CLEAN_STOP_THRESHOLD = 1, /* every peak is below the threshold            */
-    CLEAN_STOP_CAPACITY = 2   /* comp_cap components were found first         */
+    CLEAN_STOP_CAPACITY = 2,  /* comp_cap components were found first         */
+    CLEAN_STOP_NONFINITE = 4  /* a peak was NaN or infinite (the run diverged,
+                                 or non-finite input was not screened out)    */
 } clean_stop;
 
 typedef enum { CLEAN_PSF_F32 = 0, CLEAN_PSF_F16 = 1 } clean_psf_dtype;
@@ -201,8 +207,10 @@ int clean_hogbom(const float *dirty, int ny, int nx,
  *             acc = fmaf(value_c, psf[q - c + centre], acc);
  *   r[q] = r[q] - acc.
  * The run stops at the start of a round when max_iter components exist, when
- * no tile is active, or when comp_cap components exist.  Every round ends with
- * its feedback, so residual + components (*) PSF = dirty holds at return.
+ * a tile's peak is not finite (CLEAN_STOP_NONFINITE), when no tile is active,
+ * or when comp_cap components exist; inside a round a tile's loop also ends
+ * at a non-finite peak.  Every round ends with its feedback, so
+ * residual + components (*) PSF = dirty holds at return.
  *
  *   comp_idx/comp_flux   order: round, then tile id, then local iteration.
  *   feedback_interval    1 .. 2048.

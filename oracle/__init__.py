@@ -21,7 +21,7 @@ _SRC = os.path.join(_HERE, "oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 _CFLAGS = ["-O3", "-mavx2", "-mfma", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-shared", "-fPIC"]
 
-STOP_NAMES = {0: "maxiter", 1: "threshold", 2: "capacity"}
+STOP_NAMES = {0: "maxiter", 1: "threshold", 2: "capacity", 4: "nonfinite"}
 _lib = None
 
 
@@ -54,6 +54,10 @@ def load():
     for f in (lib.oracle_hogbom_f32, lib.oracle_hogbom_f64, lib.oracle_tiled_f32, lib.oracle_tiled_f64,
               lib.oracle_feedback_f32, lib.oracle_feedback_f64):
         f.restype = C.c_int
+    lib.oracle_peak_f32.argtypes = [P, i32, i32, i32, i32, i32]
+    lib.oracle_peak_f32.restype = i64
+    lib.oracle_peak_f64.argtypes = [P, i32, i32, i32, i32, i32]
+    lib.oracle_peak_f64.restype = i64
     lib.oracle_main_lobe_area.argtypes = [P, i32, i32]
     lib.oracle_main_lobe_area.restype = i64
     lib.oracle_restore_f64.argtypes = [P, P, i32, i32, f64, P]
@@ -124,6 +128,22 @@ def tiled(dirty, psf, tiles=(2, 2), interval=100, gain=0.1, threshold=0.0, max_i
     k = n.value
     return dict(residual=res, idx=idx[:k].copy(), flux=flux[:k].copy(), model=mod, n_iter=k,
                 stop=stop.value, n_rounds=rounds.value)
+
+
+def peak(r, rect=None):
+    """Flat index of the peak of a 2-D float32/float64 array (or of the
+    rectangle (y0, y1, x0, x1) of it): the largest |r|, every NaN above +Inf
+    and equal to each other, the lowest row-major index on ties."""
+    lib = load()
+    r = np.ascontiguousarray(r)
+    if r.dtype not in (np.float32, np.float64) or r.ndim != 2:
+        raise ValueError("r must be a 2-D float32 or float64 array")
+    y0, y1, x0, x1 = rect if rect is not None else (0, r.shape[0], 0, r.shape[1])
+    fn = lib.oracle_peak_f32 if r.dtype == np.float32 else lib.oracle_peak_f64
+    k = int(fn(_ptr(r), r.shape[1], int(y0), int(y1), int(x0), int(x1)))
+    if k < 0:
+        raise ValueError("empty or out-of-range rectangle")
+    return k
 
 
 def feedback(residual, psf, tiles, comp_tile, comp_idx, comp_flux, precision="f32"):

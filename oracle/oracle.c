@@ -45,6 +45,17 @@
  *     is level_frac times the largest tile peak at the round's start, a tile
  *     takes part only if its peak is at or above it, and its round also ends
  *     when its peak drops below it.
+ *   - non-finite values (a run that diverges, or NaN/Inf input that was not
+ *     screened out): the peak search orders |r| as IEEE magnitudes with every
+ *     NaN above +Inf and all NaNs equal, so the lowest-index NaN, else the
+ *     lowest-index infinity, is the peak of a region holding any.  A
+ *     non-finite peak ends the run (stop reason "non-finite") before anything
+ *     is appended: the plain loop tests it right after n == max_iter; the
+ *     tiled form tests every tile's peak at a round's start (after
+ *     used == max_iter), and inside a round a non-finite local peak ends that
+ *     tile's round like a peak below the threshold does, so the round still
+ *     ends with its feedback.  The round's flux level is therefore always a
+ *     finite fraction of a finite peak.
  */
 #include <math.h>
 #include <stdint.h>
@@ -52,7 +63,7 @@
 #include <string.h>
 
 enum { OR_OK = 0, OR_EINVAL = -1, OR_ENOMEM = -3 };
-enum { STOP_MAXITER = 0, STOP_THRESHOLD = 1, STOP_CAPACITY = 2 };
+enum { STOP_MAXITER = 0, STOP_THRESHOLD = 1, STOP_CAPACITY = 2, STOP_NONFINITE = 4 };
 
 static int check_common(int ny, int nx, int psf_ny, int psf_nx, double gain, double threshold,
                         int64_t max_iter, int64_t cap)
@@ -71,13 +82,15 @@ static int check_common(int ny, int nx, int psf_ny, int psf_nx, double gain, dou
  * largest |r| (so the lowest index wins a tie).  Two plain scans: the largest
  * value, then the first pixel holding it.  |r| is compared through its bit
  * pattern: with the sign bit cleared, IEEE-754 values order exactly as their
- * bit patterns read as unsigned integers (NaN would rank above infinity; the
- * inputs are finite). */
-static uint32_t abs_bits_f32(float v)
+ * bit patterns read as unsigned integers, +Inf above every finite value.
+ * Every NaN is given one magnitude, the quiet NaN's, above +Inf, so a NaN is
+ * the peak of any region holding one and the first NaN wins among NaNs. */
+static uint32_t mag_f32(float v)
 {
     uint32_t b;
     memcpy(&b, &v, sizeof b);
-    return b & 0x7FFFFFFFu;
+    b &= 0x7FFFFFFFu;
+    return b > 0x7F800000u ? 0x7FC00000u : b;
 }
 
 static int64_t peak_f32(const float *r, int nx, int y0, int y1, int x0, int x1)
@@ -85,13 +98,20 @@ static int64_t peak_f32(const float *r, int nx, int y0, int y1, int x0, int x1)
     uint32_t best = 0;
     for (int y = y0; y < y1; ++y)
         for (int x = x0; x < x1; ++x) {
-            uint32_t a = abs_bits_f32(r[(int64_t)y * nx + x]);
+            uint32_t a = mag_f32(r[(int64_t)y * nx + x]);
             best = a > best ? a : best;
         }
     for (int y = y0; y < y1; ++y)
         for (int x = x0; x < x1; ++x)
-            if (abs_bits_f32(r[(int64_t)y * nx + x]) == best) return (int64_t)y * nx + x;
+            if (mag_f32(r[(int64_t)y * nx + x]) == best) return (int64_t)y * nx + x;
     return (int64_t)y0 * nx + x0;   /* not reached */
+}
+
+/* Exposed for the peak-order pin: the peak of a rectangle (-1 if empty). */
+int64_t oracle_peak_f32(const float *r, int nx, int y0, int y1, int x0, int x1)
+{
+    if (nx <= 0 || y0 < 0 || x0 < 0 || y1 <= y0 || x1 <= x0 || x1 > nx) return -1;
+    return peak_f32(r, nx, y0, y1, x0, x1);
 }
 
 /* r[q] -= c * PSF centred on p, for q in the rectangle (eq. 2 of Section 3). */
@@ -127,6 +147,7 @@ int oracle_hogbom_f32(const float *dirty, int ny, int nx, const float *psf, int 
         int64_t p = peak_f32(residual, nx, 0, ny, 0, nx);
         float v = residual[p];
         if (n == max_iter) { stop = STOP_MAXITER; break; }
+        if (!isfinite(v)) { stop = STOP_NONFINITE; break; }
         if ((double)fabsf(v) < threshold) { stop = STOP_THRESHOLD; break; }
         if (n == comp_cap) { stop = STOP_CAPACITY; break; }
         /* component = intensity x gain, saved with its position (eq. 1) */
@@ -145,11 +166,13 @@ int oracle_hogbom_f32(const float *dirty, int ny, int nx, const float *psf, int 
 
 /* ---------------------------------------------------------------- FP64 -- */
 
-static uint64_t abs_bits_f64(double v)
+/* The same order for doubles: magnitude bits, every NaN one value above +Inf. */
+static uint64_t mag_f64(double v)
 {
     uint64_t b;
     memcpy(&b, &v, sizeof b);
-    return b & 0x7FFFFFFFFFFFFFFFull;
+    b &= 0x7FFFFFFFFFFFFFFFull;
+    return b > 0x7FF0000000000000ull ? 0x7FF8000000000000ull : b;
 }
 
 static int64_t peak_f64(const double *r, int nx, int y0, int y1, int x0, int x1)
@@ -157,13 +180,19 @@ static int64_t peak_f64(const double *r, int nx, int y0, int y1, int x0, int x1)
     uint64_t best = 0;
     for (int y = y0; y < y1; ++y)
         for (int x = x0; x < x1; ++x) {
-            uint64_t a = abs_bits_f64(r[(int64_t)y * nx + x]);
+            uint64_t a = mag_f64(r[(int64_t)y * nx + x]);
             best = a > best ? a : best;
         }
     for (int y = y0; y < y1; ++y)
         for (int x = x0; x < x1; ++x)
-            if (abs_bits_f64(r[(int64_t)y * nx + x]) == best) return (int64_t)y * nx + x;
+            if (mag_f64(r[(int64_t)y * nx + x]) == best) return (int64_t)y * nx + x;
     return (int64_t)y0 * nx + x0;   /* not reached */
+}
+
+int64_t oracle_peak_f64(const double *r, int nx, int y0, int y1, int x0, int x1)
+{
+    if (nx <= 0 || y0 < 0 || x0 < 0 || y1 <= y0 || x1 <= x0 || x1 > nx) return -1;
+    return peak_f64(r, nx, y0, y1, x0, x1);
 }
 
 static void subtract_psf_f64(double *r, int nx, int y0, int y1, int x0, int x1, int64_t p, double c,
@@ -199,6 +228,7 @@ int oracle_hogbom_f64(const float *dirty, int ny, int nx, const float *psf, int 
         int64_t p = peak_f64(residual, nx, 0, ny, 0, nx);
         double v = residual[p];
         if (n == max_iter) { stop = STOP_MAXITER; break; }
+        if (!isfinite(v)) { stop = STOP_NONFINITE; break; }
         if (fabs(v) < threshold) { stop = STOP_THRESHOLD; break; }
         if (n == comp_cap) { stop = STOP_CAPACITY; break; }
         double c = gain * v;
@@ -416,18 +446,21 @@ int oracle_tiled_f32(const float *dirty, int ny, int nx, const float *psf, int p
          * the threshold, and at or above the round's flux level, the fraction
          * level_frac of the largest tile peak (0: every tile above threshold) */
         double vmax = 0.0;
+        int nonfinite = 0;
         for (int t = 0; t < ntiles; ++t) {
             rect tr = tile_rect(ny, nx, tiles_y, tiles_x, t);
             tpeak[t] = (double)fabsf(residual[peak_f32(residual, nx, tr.y0, tr.y1, tr.x0, tr.x1)]);
+            nonfinite |= !isfinite(tpeak[t]);
             vmax = tpeak[t] > vmax ? tpeak[t] : vmax;
         }
+        if (used == max_iter) { stop = STOP_MAXITER; break; }
+        if (nonfinite) { stop = STOP_NONFINITE; break; }
         const double level = level_frac * vmax;
         int nactive = 0;
         for (int t = 0; t < ntiles; ++t) {
             active[t] = tpeak[t] >= threshold && tpeak[t] >= level;
             nactive += active[t];
         }
-        if (used == max_iter) { stop = STOP_MAXITER; break; }
         if (nactive == 0) { stop = STOP_THRESHOLD; break; }
         if (used == comp_cap) { stop = STOP_CAPACITY; break; }
         round_budgets(active, ntiles, limit - used, interval, budget);
@@ -439,7 +472,7 @@ int oracle_tiled_f32(const float *dirty, int ny, int nx, const float *psf, int p
             for (int64_t k = 0; k < budget[t]; ++k) {
                 int64_t p = peak_f32(residual, nx, tr.y0, tr.y1, tr.x0, tr.x1);
                 float v = residual[p];
-                if ((double)fabsf(v) < threshold || (double)fabsf(v) < level) break;
+                if (!isfinite(v) || (double)fabsf(v) < threshold || (double)fabsf(v) < level) break;
                 float c = g * v;
                 rtile[nround] = t;
                 ridx[nround] = (int32_t)p;
@@ -499,18 +532,21 @@ int oracle_tiled_f64(const float *dirty, int ny, int nx, const float *psf, int p
     int32_t rounds = 0, stop;
     for (;;) {
         double vmax = 0.0;
+        int nonfinite = 0;
         for (int t = 0; t < ntiles; ++t) {
             rect tr = tile_rect(ny, nx, tiles_y, tiles_x, t);
             tpeak[t] = fabs(residual[peak_f64(residual, nx, tr.y0, tr.y1, tr.x0, tr.x1)]);
+            nonfinite |= !isfinite(tpeak[t]);
             vmax = tpeak[t] > vmax ? tpeak[t] : vmax;
         }
+        if (used == max_iter) { stop = STOP_MAXITER; break; }
+        if (nonfinite) { stop = STOP_NONFINITE; break; }
         const double level = level_frac * vmax;
         int nactive = 0;
         for (int t = 0; t < ntiles; ++t) {
             active[t] = tpeak[t] >= threshold && tpeak[t] >= level;
             nactive += active[t];
         }
-        if (used == max_iter) { stop = STOP_MAXITER; break; }
         if (nactive == 0) { stop = STOP_THRESHOLD; break; }
         if (used == comp_cap) { stop = STOP_CAPACITY; break; }
         round_budgets(active, ntiles, limit - used, interval, budget);
@@ -520,7 +556,7 @@ int oracle_tiled_f64(const float *dirty, int ny, int nx, const float *psf, int p
             for (int64_t k = 0; k < budget[t]; ++k) {
                 int64_t p = peak_f64(residual, nx, tr.y0, tr.y1, tr.x0, tr.x1);
                 double v = residual[p];
-                if (fabs(v) < threshold || fabs(v) < level) break;
+                if (!isfinite(v) || fabs(v) < threshold || fabs(v) < level) break;
                 double c = gain * v;
                 rtile[nround] = t;
                 ridx[nround] = (int32_t)p;

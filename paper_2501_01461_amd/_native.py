@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libclean.so")
 CLEAN_OK = 0
 STATUS = {0: "CLEAN_OK", -1: "CLEAN_E_INVAL", -2: "CLEAN_E_NONFINITE", -3: "CLEAN_E_NOMEM",
           -4: "CLEAN_E_HIP", -5: "CLEAN_E_TIMEOUT", -6: "CLEAN_E_UNSUPPORTED"}
-STOP_NAMES = {0: "maxiter", 1: "threshold", 2: "capacity"}
+STOP_NAMES = {0: "maxiter", 1: "threshold", 2: "capacity", 4: "nonfinite"}
 PSF_F32, PSF_F16 = 0, 1
 FLAG_CHECK_FINITE = 1
 FLAG_STREAM_RESIDUAL = 2

@@ -20,7 +20,7 @@ constexpr int TR_GROUP_WIDE = 4;         // transpose tiles in flight per workgr
 constexpr int TR_LDS_WIDE = TR_GROUP_WIDE * 32 * 33 * 8;
 // (with the tiled kernel's static LDS, two workgroups fit one CU's 160 KB)
 
-enum { STOP_MAXITER = 0, STOP_THRESHOLD = 1, STOP_CAPACITY = 2 };
+enum { STOP_MAXITER = 0, STOP_THRESHOLD = 1, STOP_CAPACITY = 2, STOP_NONFINITE = 4 };
 enum : uint32_t { ABORT_TIMEOUT = 1u };
 
 // Control words: each on its own 128-byte line.

@@ -28,7 +28,9 @@
 // Peak key (64 bits): |v| bits (31) << 33 | (0x0FFFFFFF - f) << 5 | sign << 4 |
 // tag (4).  The unsigned max of keys is the largest |v|, then the lowest
 // tile-local index f (row-major inside the tile, so the lowest image index);
-// the tag marks which exchange a published key belongs to.
+// the tag marks which exchange a published key belongs to.  Every NaN enters
+// the key as the one magnitude 0x7FC00000, above +Inf: a region holding a NaN
+// has its lowest-index NaN as its peak.  A non-finite peak ends the run.
 
 #include <hip/hip_runtime.h>
 #include <hip/hip_fp16.h>
@@ -90,11 +92,21 @@ template <typename T> __device__ __forceinline__ void stc(T *p, T v)
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// |v| as the peak search orders it: IEEE magnitude bits (+Inf above every
+// finite value), every NaN given the quiet NaN's magnitude, above +Inf.
+__device__ __forceinline__ uint32_t peak_mag(uint32_t bits)
+{
+    const uint32_t m = bits & 0x7FFFFFFFu;
+    return m > 0x7F800000u ? 0x7FC00000u : m;
+}
 __device__ __forceinline__ uint64_t make_key(uint32_t bits, uint32_t f)
 {
-    return ((uint64_t)(bits & 0x7FFFFFFFu) << 33) | ((uint64_t)(0x0FFFFFFFu - f) << 5) |
+    return ((uint64_t)peak_mag(bits) << 33) | ((uint64_t)(0x0FFFFFFFu - f) << 5) |
            ((uint64_t)(bits >> 31) << 4);
 }
+// Largest |a|, |b| with NaN propagating (one v_maximum3_f32 for three values).
+__device__ __forceinline__ float nan_max(float a, float b) { return __builtin_elementwise_maximum(a, b); }
+__device__ __forceinline__ bool is_nan(float x) { return x != x; }
 __device__ __forceinline__ float key_value(uint64_t k)
 {
     uint32_t a = (uint32_t)(k >> 33);
@@ -461,21 +473,24 @@ template <int K, int V, typename PT> struct RegTile {
     // Thread-local peak key over the owned pixels: the largest |r|, then the
     // lowest index holding it.  Groups outside the tile hold +0 and come after
     // every valid group, so they never win unless all valid pixels are 0 too,
-    // and then group 0 (valid) wins.
+    // and then group 0 (valid) wins.  A NaN among the valid pixels outranks
+    // everything: the lowest-index one is the key (a rare, terminal case,
+    // detected by a NaN-propagating max beside the fast path).
     __device__ __forceinline__ uint64_t key(const Img &) const
     {
         if (!(valid & 1ull)) return 0;
         if constexpr (V == 4) {
             // one pass over the groups: the first group whose largest |r| is
             // the largest so far, with its four values, then the lowest of
-            // those at that magnitude (NaN groups are never taken, as the max
-            // below skips NaNs; no group taken: +0 at group 0)
-            float gm = -1.0f;
+            // those at that magnitude (a group holding a NaN has a NaN
+            // maximum and is never taken here; no group taken: +0 at group 0)
+            float gm = -1.0f, gn = 0.0f;
             uint32_t kb = 0;
             float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f, s3 = 0.0f;
 #pragma unroll
             for (int k = 0; k < K; ++k) {
-                const float g = fmaxf(fmaxf(fabsf(r[k][0]), fabsf(r[k][1])), fmaxf(fabsf(r[k][2]), fabsf(r[k][3])));
+                const float g = nan_max(nan_max(fabsf(r[k][0]), fabsf(r[k][1])), nan_max(fabsf(r[k][2]), fabsf(r[k][3])));
+                gn = nan_max(gn, g);
                 const bool hit = g > gm;
                 gm = hit ? g : gm;
                 kb = hit ? (uint32_t)k : kb;
@@ -483,6 +498,10 @@ template <int K, int V, typename PT> struct RegTile {
                 s1 = hit ? r[k][1] : s1;
                 s2 = hit ? r[k][2] : s2;
                 s3 = hit ? r[k][3] : s3;
+            }
+            if (__builtin_expect(is_nan(gn), 0)) {
+                const uint64_t nk = nan_key();
+                if (nk) return nk;
             }
             uint32_t bb = __float_as_uint(s0), be = 0;
             if (gm >= 0.0f && fabsf(s0) != gm) {
@@ -492,11 +511,18 @@ template <int K, int V, typename PT> struct RegTile {
             }
             return make_key(bb, group_f((int)kb) + be);
         }
-        float m = 0.0f;
+        float m = 0.0f, mn = 0.0f;
 #pragma unroll
         for (int k = 0; k < K; ++k)
 #pragma unroll
-            for (int e = 0; e < V; ++e) m = fmaxf(m, fabsf(r[k][e]));
+            for (int e = 0; e < V; ++e) {
+                m = fmaxf(m, fabsf(r[k][e]));
+                mn = nan_max(mn, r[k][e]);
+            }
+        if (__builtin_expect(is_nan(mn), 0)) {
+            const uint64_t nk = nan_key();
+            if (nk) return nk;
+        }
         uint32_t bb = 0, bi = 0;
 #pragma unroll
         for (int i = K * V - 1; i >= 0; --i) {
@@ -506,6 +532,24 @@ template <int K, int V, typename PT> struct RegTile {
             bi = hit ? (uint32_t)i : bi;
         }
         return make_key(bb, group_f((int)(bi / V)) + bi % V);
+    }
+
+    // Key of the lowest-index NaN among the valid pixels, or 0 if there is
+    // none (a NaN can also reach a group outside the tile, which multiplies a
+    // PSF window by zero: such groups are skipped).
+    __device__ __forceinline__ uint64_t nan_key() const
+    {
+        uint32_t bb = 0, bi = 0;
+        bool any = false;
+#pragma unroll
+        for (int i = K * V - 1; i >= 0; --i) {
+            const float x = r[i / V][i % V];
+            const bool hit = ((valid >> (i / V)) & 1ull) && is_nan(x);
+            bb = hit ? __float_as_uint(x) : bb;
+            bi = hit ? (uint32_t)i : bi;
+            any = any || hit;
+        }
+        return any ? make_key(bb, group_f((int)(bi / V)) + bi % V) : 0;
     }
 
     // r -= c * PSF centred on image pixel (py, px); then, if asked, the new key.
@@ -563,10 +607,11 @@ template <int K, int V, typename PT> struct RegTile {
 };
 
 // Running peak of a stream of pixels in increasing index order: the largest
-// |value| (compared as magnitude bits), the lowest index on ties.
+// |value| (compared as magnitude bits, every NaN one value above +Inf), the
+// lowest index on ties.
 __device__ __forceinline__ void take_key(uint32_t bits, uint32_t f, uint32_t &bb, uint32_t &bf, bool &any)
 {
-    const bool t = !any || ((bits & 0x7FFFFFFFu) > (bb & 0x7FFFFFFFu));
+    const bool t = !any || peak_mag(bits) > peak_mag(bb);
     bb = t ? bits : bb;
     bf = t ? f : bf;
     any = true;
@@ -726,7 +771,7 @@ __device__ __noinline__ WideRound wide_round(const KArgs &a, const Img im, const
     WideRound out{wave_uniform(cur), e, 0, 1};
     for (int64_t it = 0; it < nb; ++it) {
         const float v = key_value(out.cur);
-        if ((double)fabsf(v) < thr || (double)fabsf(v) < lvl) break;
+        if (!__builtin_isfinite(v) || (double)fabsf(v) < thr || (double)fabsf(v) < lvl) break;
         const float c = gain * v;
         const uint32_t fp = key_f(out.cur);
         const int ly = (int)(fp / (uint32_t)tw), lx = (int)(fp % (uint32_t)tw);
@@ -752,16 +797,19 @@ __device__ __noinline__ WideRound wide_round(const KArgs &a, const Img im, const
         out.L += 1;
         if (it + 1 < nb) {
             // thread key: the largest |r|, then the lowest index holding it
-            // (for finite values the same as take_key's).  One pass over the
-            // groups keeps the first group whose largest |r| is the largest so
-            // far, with its four values; then the lowest of those four at that
-            // magnitude.  Groups of NaNs are never taken (as the max skips them).
-            float m = -1.0f;
+            // (the same as take_key's).  One pass over the groups keeps the
+            // first group whose largest |r| is the largest so far, with its
+            // four values; then the lowest of those four at that magnitude.
+            // A group holding a NaN has a NaN maximum and is never taken
+            // there; a NaN-propagating max beside it sends that rare,
+            // terminal case to a scan for the lowest-index NaN.
+            float m = -1.0f, gn = 0.0f;
             uint32_t kb = 0;
             float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f, s3 = 0.0f;
 #pragma unroll
             for (int k = 0; k < K; ++k) {
-                const float g = fmaxf(fmaxf(fabsf(r[k][0]), fabsf(r[k][1])), fmaxf(fabsf(r[k][2]), fabsf(r[k][3])));
+                const float g = nan_max(nan_max(fabsf(r[k][0]), fabsf(r[k][1])), nan_max(fabsf(r[k][2]), fabsf(r[k][3])));
+                gn = nan_max(gn, g);
                 const bool hit = g > m;
                 m = hit ? g : m;
                 kb = hit ? (uint32_t)k : kb;
@@ -776,7 +824,22 @@ __device__ __noinline__ WideRound wide_round(const KArgs &a, const Img im, const
                 bb = h1 ? __float_as_uint(s1) : h2 ? __float_as_uint(s2) : __float_as_uint(s3);
                 be = h1 ? 1u : h2 ? 2u : 3u;
             }
-            const uint64_t tk = R.nvalid > 0 ? make_key(bb, R.group_f((int)kb) + be) : 0;
+            uint64_t tk = R.nvalid > 0 ? make_key(bb, R.group_f((int)kb) + be) : 0;
+            if (__builtin_expect(is_nan(gn), 0)) {
+                // the lowest-index NaN of the groups inside the tile (groups
+                // past its end multiply a PSF window by zero and may hold NaN)
+                uint32_t nb_ = 0, ni = 0;
+                bool any = false;
+#pragma unroll
+                for (int i = K * V - 1; i >= 0; --i) {
+                    const float x = r[i / V][i % V];
+                    const bool hit = i / V < R.nvalid && is_nan(x);
+                    nb_ = hit ? __float_as_uint(x) : nb_;
+                    ni = hit ? (uint32_t)i : ni;
+                    any = any || hit;
+                }
+                if (any) tk = make_key(nb_, R.group_f((int)(ni / V)) + ni % V);
+            }
             if (!cluster_reduce(y, slots, lslots, a.slot_pad, R.cs, R.rank, out.e++, tk, out.cur)) {
                 out.ok = 0;
                 return out;
@@ -855,7 +918,7 @@ template <int K, int V, typename PT> struct StreamTile {
 
     __device__ __forceinline__ static void take(uint32_t bits, uint32_t f, uint32_t &bb, uint32_t &bf, bool &any)
     {
-        const bool t = !any || ((bits & 0x7FFFFFFFu) > (bb & 0x7FFFFFFFu));
+        const bool t = !any || peak_mag(bits) > peak_mag(bb);
         bb = t ? bits : bb;
         bf = t ? f : bf;
         any = true;
@@ -1004,6 +1067,7 @@ template <class Tile> __device__ bool run_plain(const PlainJob &j_arg, int rank_
         // peak (eq. 1): value and position from the cluster's key
         const float v = key_value(cur);
         if (n == j.max_iter) { stop = STOP_MAXITER; break; }
+        if (!__builtin_isfinite(v)) { stop = STOP_NONFINITE; break; }
         if ((double)fabsf(v) < j.threshold) { stop = STOP_THRESHOLD; break; }
         if (n == j.cap) { stop = STOP_CAPACITY; break; }
         const float c = j.gain * v;
@@ -1924,14 +1988,16 @@ tiled_kernel(const KArgs a)
     for (;;) {
         // ---- round control, computed identically by every workgroup: a tile
         // takes part when its peak is at or above the threshold and at or above
-        // the round's flux level (level_frac times the largest tile peak)
+        // the round's flux level (level_frac times the largest tile peak); a
+        // non-finite tile peak (magnitude bits at or above +Inf's) ends the run
         uint32_t vbits = 0;
         for (int t = threadIdx.x; t < T; t += WG) vbits = max(vbits, (uint32_t)(ldc(&a.tile_key[t]) >> 33));
         if (threadIdx.x == 0) s_vmax = 0;
         __syncthreads();
         if (vbits) atomicMax(&s_vmax, vbits);
         __syncthreads();
-        const double level = a.level_frac * (double)__uint_as_float(s_vmax);
+        const bool nonfinite = s_vmax >= 0x7F800000u;
+        const double level = nonfinite ? 0.0 : a.level_frac * (double)__uint_as_float(s_vmax);
         int na_part = 0, rk_part = 0;
         for (int t = threadIdx.x; t < T; t += WG) {
             const double pk = (double)fabsf(key_value(ldc(&a.tile_key[t])));
@@ -1942,6 +2008,7 @@ tiled_kernel(const KArgs a)
         const int na = wg_sum_int(na_part, &s_tmp);
         const int my_rank = wg_sum_int(rk_part, &s_tmp);
         if (used == a.max_iter) { stop = STOP_MAXITER; break; }
+        if (nonfinite) { stop = STOP_NONFINITE; break; }
         if (na == 0) { stop = STOP_THRESHOLD; break; }
         if (used == a.cap) { stop = STOP_CAPACITY; break; }
         const int64_t rem = limit - used;
@@ -1967,7 +2034,7 @@ tiled_kernel(const KArgs a)
             } else
             for (int64_t it = 0; it < budget; ++it) {
                 const float v = key_value(cur);
-                if ((double)fabsf(v) < a.threshold || (double)fabsf(v) < level) break;
+                if (!__builtin_isfinite(v) || (double)fabsf(v) < a.threshold || (double)fabsf(v) < level) break;
                 const float c = a.gain * v;
                 const uint32_t fp = key_f(cur);
                 const int ly = (int)(fp / (uint32_t)R.w), lx = (int)(fp % (uint32_t)R.w);
