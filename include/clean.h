@@ -189,6 +189,34 @@ int clean_hogbom(const float *dirty, int ny, int nx,
                  void *workspace, size_t workspace_bytes,
                  clean_stats *stats, void *stream);
 
+/* Size of the device scratch array behind clean_hogbom_noalloc, per GPU. */
+#define CLEAN_NOALLOC_SCRATCH_BYTES 65536
+
+/*
+ * clean_hogbom_noalloc -- clean_hogbom for callers that cannot allocate
+ * memory in the call: code that must not call hipMalloc (tight serving
+ * loops, harnesses that forbid allocation).  Same arguments, results and
+ * errors as clean_hogbom without a workspace argument: the call allocates
+ * nothing (no device, pinned or stream-ordered allocation, no events).  Its
+ * workspace is a file-scope device array of CLEAN_NOALLOC_SCRATCH_BYTES bytes,
+ * one copy per GPU, held until the process ends; its device address is looked
+ * up once per device, on the first call there.  Every call on a GPU shares
+ * that GPU's array: calls that overlap on one GPU (other threads, other
+ * streams) race and must be serialised by the caller; the control words the
+ * kernels need zeroed are cleared by a fill kernel at the start of each call.
+ * A launch shape whose workspace exceeds the array (a cluster of more than
+ * about 1400 workgroups, which only a forced wg_per_tile can ask for) fails
+ * with CLEAN_E_UNSUPPORTED before anything is launched.  stats->device_ms is 0 (the call is not timed).  Synchronous, as
+ * every entry point.
+ */
+int clean_hogbom_noalloc(const float *dirty, int ny, int nx,
+                         const void *psf, int psf_ny, int psf_nx,
+                         const clean_params *p,
+                         float *residual,
+                         int32_t *comp_idx, float *comp_flux, int64_t comp_cap,
+                         double *model,
+                         clean_stats *stats, void *stream);
+
 /*
  * clean_tiled_feedback -- tiled Hogbom CLEAN with feedback (Sections 2-3).
  *

@@ -25,7 +25,7 @@ FLAG_FFT_FEEDBACK = 4
 FLAG_FFT_TWO_LEVEL = 8
 
 # every symbol include/clean.h declares
-EXPORTS = ("clean_hogbom", "clean_tiled_feedback", "clean_batched", "clean_autotune", "clean_autotune_interval",
+EXPORTS = ("clean_hogbom", "clean_hogbom_noalloc", "clean_tiled_feedback", "clean_batched", "clean_autotune", "clean_autotune_interval",
            "clean_beam_fit", "clean_restore", "clean_workspace_size", "clean_psf_to_f16", "clean_strerror",
            "clean_last_error", "clean_version")
 
@@ -78,6 +78,8 @@ def load():
                                  C.POINTER(Stats), P]
     lib.clean_tiled_feedback.argtypes = [P, i32, i32, P, i32, i32, i32, i32, i32, C.POINTER(Params), P, P, P,
                                          i64, P, P, sz, C.POINTER(Stats), P]
+    lib.clean_hogbom_noalloc.argtypes = [P, i32, i32, P, i32, i32, C.POINTER(Params), P, P, P, i64, P,
+                                         C.POINTER(Stats), P]
     lib.clean_batched.argtypes = [C.POINTER(Problem), i32, C.POINTER(Params), C.POINTER(Stats), P]
     lib.clean_autotune.argtypes = [P, i32, i32, P, i32, i32, i32, i32, i32, C.POINTER(Params), P, P, P, i64, i64,
                                    C.POINTER(Params), P]
@@ -92,7 +94,8 @@ def load():
     lib.clean_workspace_size.argtypes = [i32, i32, i32, i32, i32, C.POINTER(Params)]
     lib.clean_workspace_size.restype = sz
     lib.clean_psf_to_f16.argtypes = [P, P, i64, P]
-    for f in (lib.clean_hogbom, lib.clean_tiled_feedback, lib.clean_batched, lib.clean_psf_to_f16):
+    for f in (lib.clean_hogbom, lib.clean_hogbom_noalloc, lib.clean_tiled_feedback, lib.clean_batched,
+              lib.clean_psf_to_f16):
         f.restype = C.c_int
     lib.clean_strerror.argtypes = [C.c_int]
     lib.clean_strerror.restype = C.c_char_p
@@ -171,6 +174,25 @@ def hogbom(dirty, psf, gain=0.1, threshold=0.0, max_iter=1000, cap=None, model=T
     ny, nx = dirty.shape
     _check(lib.clean_hogbom(_ptr(dirty), ny, nx, _ptr(psf), psf.shape[0], psf.shape[1], C.byref(p), _ptr(res),
                             _ptr(idx), _ptr(flux), cap, _ptr(mod), None, 0, C.byref(st), _stream()))
+    n = st.n_iter
+    return dict(residual=res, idx=idx[:n], flux=flux[:n], model=mod, stats=st.as_dict())
+
+
+def hogbom_noalloc(dirty, psf, gain=0.1, threshold=0.0, max_iter=1000, cap=None, check_finite=False,
+                   wg_per_tile=0, px_per_thread=0, stream=False, out=None):
+    """clean_hogbom_noalloc: plain Hogbom CLEAN whose call allocates nothing
+    (its workspace is the library's per-GPU device scratch array).  `out`
+    (residual, idx, flux, model) lets a caller that cannot allocate pass its
+    own buffers.  Returns dict(residual, idx, flux, model, stats)."""
+    lib = load()
+    dirty, psf = _prep(dirty, psf)
+    cap = int(max_iter if cap is None else cap)
+    res, idx, flux, mod = out if out is not None else _outputs(dirty, cap, True)
+    p = _params(gain, threshold, max_iter, psf, _flags(check_finite, stream), wg_per_tile, px_per_thread)
+    st = Stats()
+    ny, nx = dirty.shape
+    _check(lib.clean_hogbom_noalloc(_ptr(dirty), ny, nx, _ptr(psf), psf.shape[0], psf.shape[1], C.byref(p),
+                                    _ptr(res), _ptr(idx), _ptr(flux), cap, _ptr(mod), C.byref(st), _stream()))
     n = st.n_iter
     return dict(residual=res, idx=idx[:n], flux=flux[:n], model=mod, stats=st.as_dict())
 

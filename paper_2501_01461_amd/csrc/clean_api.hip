@@ -31,6 +31,7 @@ __global__ void finite_check_kernel(const float *x, int64_t n, uint32_t *flag);
 __global__ void finite_check_half_kernel(const unsigned short *x, int64_t n, uint32_t *flag);
 __global__ void to_half_kernel(const float *x, unsigned short *y, int64_t n);
 __global__ void finalize_kernel(const double *partial, int n, DevStat *st);
+__global__ void zero_kernel(uint32_t *p, int64_t n);
 __global__ void restore_rows_kernel(const double *model, double *tmp, int ny, int nx, const double *b, int R);
 __global__ void restore_cols_kernel(const double *tmp, const float *residual, double *out, int ny, int nx,
                                     const double *b, int R);
@@ -76,13 +77,21 @@ struct PinnedStage {
 thread_local PinnedStage t_stage;
 
 // Copies n_parts (dst, src, bytes) device -> host on `stream` and waits.
+// `direct`: straight into the (pageable) destinations, allocating nothing;
+// the copies are complete once the stream has been synchronised.
 struct D2H {
     void *dst;
     const void *src;
     size_t bytes;
 };
-int read_back(const D2H *parts, int n_parts, hipStream_t stream)
+int read_back(const D2H *parts, int n_parts, hipStream_t stream, bool direct = false)
 {
+    if (direct) {
+        for (int i = 0; i < n_parts; ++i)
+            HIPCHK(hipMemcpyAsync(parts[i].dst, parts[i].src, parts[i].bytes, hipMemcpyDeviceToHost, stream));
+        HIPCHK(hipStreamSynchronize(stream));
+        return CLEAN_OK;
+    }
     size_t total = 0;
     for (int i = 0; i < n_parts; ++i) total += align_up(parts[i].bytes, 64);
     if (t_stage.bytes < total) {
@@ -139,6 +148,38 @@ int internal_workspace(int dev, size_t need, void **out)
     return CLEAN_OK;
 }
 
+} // namespace
+
+// Device scratch of the allocation-free entry point clean_hogbom_noalloc: its
+// whole workspace (control block, stats, exchange slots, role table, partial
+// sums).  One copy per GPU, held until the process ends.  In host code this
+// name is a host-side stand-in, not a device address: only the address
+// hipGetSymbolAddress returns for the current device is ever used.
+static __device__ __align__(256) unsigned char scratch[CLEAN_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[64];
+
+// The device address of `scratch` on device `dev` (the current device),
+// looked up once per device.
+int scratch_address(int dev, void **out)
+{
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (dev < 0 || dev >= 64) return fail(CLEAN_E_INVAL, "device %d out of range", dev);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) {
+            (void)hipGetLastError();
+            return fail(CLEAN_E_HIP, "hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+        }
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return CLEAN_OK;
+}
 
 // Layout of one call's workspace.  The header part (control block, stats,
 // exchange slots, tile keys, counts) is cleared before each launch.
@@ -420,10 +461,13 @@ int check_common(const float *dirty, int ny, int nx, const void *psf, int psf_ny
 }
 
 // Shared driver of the plain and tiled forms.
+// noalloc: the workspace is the device scratch array (the allocation-free
+// entry point): nothing is allocated, the header is cleared by a fill kernel,
+// results come back by direct copies, and the call is not timed.
 int run(bool tiled, const float *dirty, int ny, int nx, const void *psf, int psf_ny, int psf_nx, int tiles_y,
         int tiles_x, int interval, const clean_params *p, float *residual, int32_t *comp_idx, float *comp_flux,
         int64_t comp_cap, double *model, void *workspace, size_t workspace_bytes, clean_stats *stats,
-        void *stream_v)
+        void *stream_v, bool noalloc = false)
 {
     int st = check_common(dirty, ny, nx, psf, psf_ny, psf_nx, p, residual, comp_idx, comp_flux, comp_cap);
     if (st) return st;
@@ -518,6 +562,17 @@ int run(bool tiled, const float *dirty, int ny, int nx, const void *psf, int psf
     st = force_stream || want_wide ? CLEAN_E_UNSUPPORTED
                       : choose_shape(max_tile, V, p->wg_per_tile, p->px_per_thread, tiled ? 32 : 64,
                                      tiled ? (T + 7) / 8 : 0, ncu / 8, cs, ppt);
+    // the allocation-free entry point refuses a cluster whose workspace does
+    // not fit its scratch array before anything else (plain: W = cs)
+    auto noalloc_fits = [&](int c) -> int {
+        if (!noalloc) return CLEAN_OK;
+        const size_t need = make_layout(1, c, (c + 31) / 32 * 32, 1, c, (int64_t)ny * nx, false).total;
+        if (need > CLEAN_NOALLOC_SCRATCH_BYTES)
+            return fail(CLEAN_E_UNSUPPORTED, "a cluster of %d workgroups needs %zu bytes of workspace; the "
+                        "allocation-free entry point holds %d", c, need, (int)CLEAN_NOALLOC_SCRATCH_BYTES);
+        return CLEAN_OK;
+    };
+    if (st == CLEAN_OK && (st = noalloc_fits(cs)) != CLEAN_OK) return st;
     if (st == CLEAN_OK) {
         fn = pick(tiled, half, V, ppt / V, fft);
         if (!fn) return fail(CLEAN_E_UNSUPPORTED, "no kernel for %d pixels per thread", ppt);
@@ -575,6 +630,7 @@ int run(bool tiled, const float *dirty, int ny, int nx, const void *psf, int psf
         if (p->wg_per_tile) cs = p->wg_per_tile;
         else cs = (int)std::max<int64_t>(1, std::min<int64_t>(need, tiled ? std::max(1, max_wg / T) : 128));
         ppt = 0;
+        if ((st = noalloc_fits(cs)) != CLEAN_OK) return st;
         if (cs > 4096 || !place(cs, max_wg, W, role))
             return fail(CLEAN_E_UNSUPPORTED, "%d x %d streaming workgroups cannot be co-resident (max %d)", T, cs, max_wg);
     }
@@ -583,7 +639,15 @@ int run(bool tiled, const float *dirty, int ny, int nx, const void *psf, int psf
     const int64_t npix = (int64_t)ny * nx;
     const Layout L = make_layout(T, cs, slot_pad, interval, W, npix, tiled, ny, fg);
     char *ws = (char *)workspace;
-    if (ws) {
+    if (noalloc) {
+        if (L.total > CLEAN_NOALLOC_SCRATCH_BYTES)     // not reached: noalloc_fits ran first
+            return fail(CLEAN_E_UNSUPPORTED, "this launch (%d workgroups) needs %zu bytes of workspace; the "
+                        "allocation-free entry point holds %d", W, L.total, (int)CLEAN_NOALLOC_SCRATCH_BYTES);
+        void *sp = nullptr;
+        st = scratch_address(dev, &sp);
+        if (st) return st;
+        ws = (char *)sp;
+    } else if (ws) {
         if (workspace_bytes < L.total)
             return fail(CLEAN_E_NOMEM, "workspace of %zu bytes < %zu needed", workspace_bytes, L.total);
     } else {
@@ -643,7 +707,13 @@ int run(bool tiled, const float *dirty, int ny, int nx, const void *psf, int psf
     a.tw_y = (const float2 *)(ws + L.tw_y);
     a.rstart = fft ? (float *)(ws + L.rstart) : nullptr;
 
-    HIPCHK(hipMemsetAsync(ws, 0, L.header_end, stream));
+    if (noalloc) {
+        // the header is a whole number of 256-byte blocks
+        hipLaunchKernelGGL(zero_kernel, dim3(1), dim3(256), 0, stream, (uint32_t *)ws, (int64_t)(L.header_end / 4));
+        HIPCHK(hipGetLastError());
+    } else {
+        HIPCHK(hipMemsetAsync(ws, 0, L.header_end, stream));
+    }
     HIPCHK(hipMemcpyAsync(ws + L.role, role.data(), role.size() * 4, hipMemcpyHostToDevice, stream));
     if (p->flags & CLEAN_FLAG_CHECK_FINITE) {
         uint32_t *flag = &a.ctl->finite_bad;
@@ -657,7 +727,7 @@ int run(bool tiled, const float *dirty, int ny, int nx, const void *psf, int psf
         HIPCHK(hipGetLastError());
         uint32_t bad = 0;
         const D2H rb[1] = {{&bad, flag, 4}};
-        st = read_back(rb, 1, stream);
+        st = read_back(rb, 1, stream, noalloc);
         if (st) return st;
         if (bad) return fail(CLEAN_E_NONFINITE, "non-finite value in the dirty image or PSF");
     }
@@ -682,29 +752,33 @@ int run(bool tiled, const float *dirty, int ny, int nx, const void *psf, int psf
         HIPCHK(hipMemcpyAsync(ws + L.tw_y, twy.data(), twy.size() * 8, hipMemcpyHostToDevice, stream));
     }
 
-    hipEvent_t e0, e1;
-    HIPCHK(hipEventCreate(&e0));
-    HIPCHK(hipEventCreate(&e1));
-    HIPCHK(hipEventRecord(e0, stream));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (!noalloc) {
+        HIPCHK(hipEventCreate(&e0));
+        HIPCHK(hipEventCreate(&e1));
+        HIPCHK(hipEventRecord(e0, stream));
+    }
     void *args[] = {(void *)&a};
     hipError_t le = hipLaunchCooperativeKernel((const void *)fn, dim3(W), dim3(WG), args, (unsigned)dyn_lds, stream);
     if (le != hipSuccess) {
-        (void)hipEventDestroy(e0);
-        (void)hipEventDestroy(e1);
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
         return fail(CLEAN_E_HIP, "cooperative launch of %d x %d failed: %s", W, WG, hipGetErrorString(le));
     }
-    HIPCHK(hipEventRecord(e1, stream));
+    if (!noalloc) HIPCHK(hipEventRecord(e1, stream));
     hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(64), 0, stream, a.partial, T * cs, a.dstat);
     HIPCHK(hipGetLastError());
     DevStat ds{};
     DevCtl ctl{};
     const D2H rb[2] = {{&ds, a.dstat, sizeof ds}, {&ctl, a.ctl, sizeof ctl}};
-    st = read_back(rb, 2, stream);
+    st = read_back(rb, 2, stream, noalloc);
     if (st) return st;
     float ms = 0.f;
-    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
+    if (!noalloc) {
+        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+    }
     if (ctl.abort & ABORT_TIMEOUT) return fail(CLEAN_E_TIMEOUT, "a device-side wait timed out");
     if (ctl.abort) return fail(CLEAN_E_HIP, "device abort code %u", ctl.abort);
     if (stats) {
@@ -737,6 +811,15 @@ int clean_hogbom(const float *dirty, int ny, int nx, const void *psf, int psf_ny
     g_last_error.clear();
     return run(false, dirty, ny, nx, psf, psf_ny, psf_nx, 1, 1, 1, p, residual, comp_idx, comp_flux, comp_cap, model,
                workspace, workspace_bytes, stats, stream);
+}
+
+int clean_hogbom_noalloc(const float *dirty, int ny, int nx, const void *psf, int psf_ny, int psf_nx,
+                         const clean_params *p, float *residual, int32_t *comp_idx, float *comp_flux,
+                         int64_t comp_cap, double *model, clean_stats *stats, void *stream)
+{
+    g_last_error.clear();
+    return run(false, dirty, ny, nx, psf, psf_ny, psf_nx, 1, 1, 1, p, residual, comp_idx, comp_flux, comp_cap, model,
+               nullptr, 0, stats, stream, true);
 }
 
 int clean_tiled_feedback(const float *dirty, int ny, int nx, const void *psf, int psf_ny, int psf_nx, int tiles_y,

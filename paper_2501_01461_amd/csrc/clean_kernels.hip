@@ -2255,6 +2255,13 @@ __global__ void to_half_kernel(const float *x, unsigned short *y, int64_t n)
         y[i] = __half_as_ushort(__float2half_rn(x[i]));
 }
 
+// Clear n 32-bit words (used where a fill must not be a runtime memset).
+__global__ void zero_kernel(uint32_t *p, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0u;
+}
+
 // Sum the per-workgroup squared-residual partials in a fixed order.
 __global__ void finalize_kernel(const double *partial, int n, DevStat *st)
 {
