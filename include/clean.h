@@ -158,6 +158,12 @@ typedef struct {
                              used device-scope exchanges.  Tiled: tile clusters
                              counted; batched: 1 or 0 for that problem; plain:
                              0                                                   */
+    int32_t exchange_levels; /* plain: 2 when the cluster's per-iteration
+                             exchange ran in two levels (keys gathered inside
+                             each XCD first, then across the 8 XCD leaders;
+                             clusters of 16 or more workgroups placed one
+                             rank per XCD in turn, checked on the device),
+                             else 1; tiled and batched: 1                     */
 } clean_stats;
 
 /*
@@ -205,8 +211,9 @@ int clean_hogbom(const float *dirty, int ny, int nx,
  * streams) race and must be serialised by the caller; the control words the
  * kernels need zeroed are cleared by a fill kernel at the start of each call.
  * A launch shape whose workspace exceeds the array (a cluster of more than
- * about 1400 workgroups, which only a forced wg_per_tile can ask for) fails
- * with CLEAN_E_UNSUPPORTED before anything is launched.  stats->device_ms is 0 (the call is not timed).  Synchronous, as
+ * about 1000 workgroups, which only a forced wg_per_tile can ask for: the
+ * library's launches hold at most two workgroups per CU) fails with
+ * CLEAN_E_UNSUPPORTED before anything is launched.  stats->device_ms is 0 (the call is not timed).  Synchronous, as
  * every entry point.
  */
 int clean_hogbom_noalloc(const float *dirty, int ny, int nx,
@@ -360,6 +367,20 @@ int clean_restore(const double *model, const float *residual, int ny, int nx, do
 
 /* FP32 -> FP16 (round to nearest even) of n values, on `stream`; synchronous. */
 int clean_psf_to_f16(const float *psf, uint16_t *out, int64_t n, void *stream);
+
+/*
+ * clean_bandwidth_probe -- not part of the method: the memory bandwidth a
+ * working set achieves on the current device, the denominators of the
+ * kernels' rooflines.  buf: caller-owned device memory of `bytes` bytes
+ * (>= 4096, a multiple of 32).  mode 0 reads the buffer `reps` times with
+ * 16-byte loads (every workgroup re-reads its own words, so a buffer small
+ * enough for the L2s, or for the Infinity Cache, is served from them after
+ * the first pass); mode 1 copies the first half onto the second half `reps`
+ * times.  *gbs (host) = bytes x reps / kernel time, in GB/s (1e9 B/s): the
+ * bytes read (mode 0) or read plus written (mode 1).  Synchronous.
+ * CLEAN_E_INVAL for NULL pointers or arguments out of range.
+ */
+int clean_bandwidth_probe(void *buf, size_t bytes, int mode, int reps, double *gbs, void *stream);
 
 /* Static description of a clean_status value. */
 const char *clean_strerror(int status);

@@ -26,7 +26,8 @@ FLAG_FFT_TWO_LEVEL = 8
 
 # every symbol include/clean.h declares
 EXPORTS = ("clean_hogbom", "clean_hogbom_noalloc", "clean_tiled_feedback", "clean_batched", "clean_autotune", "clean_autotune_interval",
-           "clean_beam_fit", "clean_restore", "clean_workspace_size", "clean_psf_to_f16", "clean_strerror",
+           "clean_beam_fit", "clean_restore", "clean_workspace_size", "clean_psf_to_f16", "clean_bandwidth_probe",
+           "clean_strerror",
            "clean_last_error", "clean_version")
 
 
@@ -41,7 +42,7 @@ class Stats(C.Structure):
                 ("final_peak", C.c_double), ("residual_rms", C.c_double), ("model_flux", C.c_double),
                 ("device_ms", C.c_float), ("wg_per_tile", C.c_int32), ("px_per_thread", C.c_int32),
                 ("workgroups", C.c_int32), ("phase_us", C.c_float * 3), ("streamed", C.c_int32),
-                ("xcd_local_clusters", C.c_int32)]
+                ("xcd_local_clusters", C.c_int32), ("exchange_levels", C.c_int32)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_}
@@ -94,6 +95,8 @@ def load():
     lib.clean_workspace_size.argtypes = [i32, i32, i32, i32, i32, C.POINTER(Params)]
     lib.clean_workspace_size.restype = sz
     lib.clean_psf_to_f16.argtypes = [P, P, i64, P]
+    lib.clean_bandwidth_probe.argtypes = [P, sz, i32, i32, C.POINTER(C.c_double), P]
+    lib.clean_bandwidth_probe.restype = C.c_int
     for f in (lib.clean_hogbom, lib.clean_hogbom_noalloc, lib.clean_tiled_feedback, lib.clean_batched,
               lib.clean_psf_to_f16):
         f.restype = C.c_int
@@ -361,6 +364,17 @@ def psf_to_f16(psf):
     out = torch.empty(psf.shape, dtype=torch.float16, device=psf.device)
     _check(lib.clean_psf_to_f16(_ptr(psf), _ptr(out), psf.numel(), _stream()))
     return out
+
+
+def bandwidth_probe(buf, mode=0, reps=10):
+    """GB/s that reading (mode 0) or copying half onto half (mode 1) of the
+    device tensor `buf` achieves, `reps` passes (the roofline denominators)."""
+    lib = load()
+    _torch()
+    g = C.c_double(0.0)
+    _check(lib.clean_bandwidth_probe(_ptr(buf), buf.numel() * buf.element_size(), int(mode), int(reps), C.byref(g),
+                                     _stream()))
+    return g.value
 
 
 def version():

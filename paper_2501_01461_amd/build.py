@@ -15,7 +15,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libclean.so")
-SOURCES = ["clean_kernels.hip", "clean_restore.hip", "clean_api.hip"]
+SOURCES = ["clean_kernels.hip", "clean_restore.hip", "clean_probe.hip", "clean_api.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

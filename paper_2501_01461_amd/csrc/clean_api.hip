@@ -32,6 +32,8 @@ __global__ void finite_check_half_kernel(const unsigned short *x, int64_t n, uin
 __global__ void to_half_kernel(const float *x, unsigned short *y, int64_t n);
 __global__ void finalize_kernel(const double *partial, int n, DevStat *st);
 __global__ void zero_kernel(uint32_t *p, int64_t n);
+__global__ void probe_read_kernel(const float4 *p, int64_t n4, int reps, float *sink);
+__global__ void probe_copy_kernel(const float4 *src, float4 *dst, int64_t n4, int reps);
 __global__ void restore_rows_kernel(const double *model, double *tmp, int ny, int nx, const double *b, int R);
 __global__ void restore_cols_kernel(const double *tmp, const float *residual, double *out, int ny, int nx,
                                     const double *b, int R);
@@ -184,7 +186,7 @@ int scratch_address(int dev, void **out)
 // Layout of one call's workspace.  The header part (control block, stats,
 // exchange slots, tile keys, counts) is cleared before each launch.
 struct Layout {
-    size_t ctl, dstat, xslots, lslots, tile_key, rb_n, ag_n, header_end;
+    size_t ctl, dstat, xslots, lslots, hslots, tile_key, rb_n, ag_n, header_end;
     size_t role, rb_idx, rb_flux, ag_pos, ag_flux, accbuf, partial;
     size_t fft_a, fft_b, fft_wx, fft_wy, fft_ks, comp_img, tw_x, tw_y, rstart, total;
 };
@@ -202,15 +204,24 @@ struct FftGeom {
     bool two_x = false, two_y = false;
 };
 
+// Slots per XCD of the two-level exchange of a plain cluster of cs
+// workgroups (0: the cluster exchanges in one level).
+int two_level_pad(bool tiled, int cs)
+{
+    return !tiled && cs >= TWO_LEVEL_MIN_CS ? ((cs + 7) / 8 + 31) / 32 * 32 : 0;
+}
+
 Layout make_layout(int T, int cs, int slot_pad, int interval, int W, int64_t npix, bool tiled, int ny = 0,
                    const FftGeom &g = FftGeom())
 {
+    const int hpad = two_level_pad(tiled, cs);
     Layout L{};
     size_t o = 0;
     L.ctl = o;       o = align_up(o + sizeof(DevCtl), 256);
     L.dstat = o;     o = align_up(o + sizeof(DevStat), 256);
     L.xslots = o;    o = align_up(o + (size_t)T * 2 * slot_pad * 8, 256);
     L.lslots = o;    o = align_up(o + (size_t)T * 2 * slot_pad * 8, 256);
+    L.hslots = o;    o = align_up(o + (hpad ? (size_t)2 * (8 * hpad + 32) * 8 : 0), 256);
     L.tile_key = o;  o = align_up(o + (size_t)T * 8, 256);
     L.rb_n = o;      o = align_up(o + (size_t)T * 4, 256);
     L.ag_n = o;      o = align_up(o + (size_t)T * 4, 256);
@@ -580,6 +591,7 @@ int run(bool tiled, const float *dirty, int ny, int nx, const void *psf, int psf
             HIPCHK(hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn_lds));
         int occ = 0;
         HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void *)fn, WG, dyn_lds));
+        occ = std::min(occ, MAX_WG_PER_CU);
         if (!place(cs, occ * ncu, W, role)) {
             if (p->px_per_thread)
                 return fail(CLEAN_E_UNSUPPORTED, "%d x %d workgroups cannot be co-resident (max %d)", T, cs, occ * ncu);
@@ -605,6 +617,7 @@ int run(bool tiled, const float *dirty, int ny, int nx, const void *psf, int psf
                 HIPCHK(hipFuncSetAttribute((const void *)fw, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn_lds));
             int occ = 0;
             HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void *)fw, WG, dyn_lds));
+            occ = std::min(occ, MAX_WG_PER_CU);
             if (occ > 0 && place(cw, occ * ncu, W, role)) {
                 streamed = false;
                 fn = fw;
@@ -624,11 +637,12 @@ int run(bool tiled, const float *dirty, int ny, int nx, const void *psf, int psf
             HIPCHK(hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn_lds));
         int occ = 0;
         HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void *)fn, WG, dyn_lds));
+        occ = std::min(occ, MAX_WG_PER_CU);
         const int max_wg = occ * ncu;
         const int64_t per_wg = (int64_t)WG * STREAM_K * V;
         const int64_t need = (max_tile + per_wg - 1) / per_wg;
         if (p->wg_per_tile) cs = p->wg_per_tile;
-        else cs = (int)std::max<int64_t>(1, std::min<int64_t>(need, tiled ? std::max(1, max_wg / T) : 128));
+        else cs = (int)std::max<int64_t>(1, std::min<int64_t>(need, tiled ? std::max(1, max_wg / T) : max_wg));
         ppt = 0;
         if ((st = noalloc_fits(cs)) != CLEAN_OK) return st;
         if (cs > 4096 || !place(cs, max_wg, W, role))
@@ -684,6 +698,8 @@ int run(bool tiled, const float *dirty, int ny, int nx, const void *psf, int psf
     a.role = (const int32_t *)(ws + L.role);
     a.xslots = (uint64_t *)(ws + L.xslots);
     a.lslots = (uint64_t *)(ws + L.lslots);
+    a.hpad = two_level_pad(tiled, cs);
+    a.hslots = a.hpad ? (uint64_t *)(ws + L.hslots) : nullptr;
     a.tile_key = (uint64_t *)(ws + L.tile_key);
     a.rb_idx = (int32_t *)(ws + L.rb_idx);
     a.rb_flux = (float *)(ws + L.rb_flux);
@@ -794,6 +810,7 @@ int run(bool tiled, const float *dirty, int ny, int nx, const void *psf, int psf
         stats->workgroups = W;
         stats->streamed = streamed;
         stats->xcd_local_clusters = ds.xcd_local;
+        stats->exchange_levels = ds.levels > 0 ? ds.levels : 1;
         const double us_per_tick = 1e6 / (double)(a.timeout_ticks / 20ull);
         for (int i = 0; i < 3; ++i) stats->phase_us[i] = (float)(ds.phase_ticks[i] * us_per_tick);
     }
@@ -864,6 +881,7 @@ int clean_batched(const clean_problem *probs, int n, const clean_params *shared,
         if (!f) return CLEAN_E_UNSUPPORTED;
         int oc = 0;
         HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&oc, (const void *)f, WG, 0));
+        oc = std::min(oc, MAX_WG_PER_CU);
         int64_t seats = 0, mcs = 0;
         for (int i = 0; i < n; ++i) {
             const int64_t c = ((int64_t)probs[i].ny * probs[i].nx + (int64_t)WG * pp - 1) / ((int64_t)WG * pp);
@@ -893,6 +911,7 @@ int clean_batched(const clean_problem *probs, int n, const clean_params *shared,
     if (!fn) return fail(CLEAN_E_UNSUPPORTED, "no batched kernel for %d x %d pixels per thread", K, V);
     int occ = 0;
     HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void *)fn, WG, 0));
+    occ = std::min(occ, MAX_WG_PER_CU);
     const int max_wg = occ * ncu;
 
     // cluster size per problem, then largest problems first
@@ -963,6 +982,8 @@ int clean_batched(const clean_problem *probs, int n, const clean_params *shared,
         j.comp_idx = q.comp_idx; j.comp_flux = q.comp_flux;
         j.slots = (uint64_t *)(ws + o_slots) + so;
         j.lslots = (uint64_t *)(ws + o_lslots) + so;
+        j.hslots = nullptr;
+        j.hpad = 0;
         j.dstat = (DevStat *)(ws + o_stat) + r;
         j.partial = (double *)(ws + o_part) + po;
         so += (size_t)2 * j.slot_pad;
@@ -1042,6 +1063,7 @@ int clean_batched(const clean_problem *probs, int n, const clean_params *shared,
             s.workgroups = W;
             s.streamed = 0;
             s.xcd_local_clusters = ds[r].xcd_local;
+            s.exchange_levels = 1;
         }
     }
     return CLEAN_OK;
@@ -1291,6 +1313,43 @@ int clean_psf_to_f16(const float *psf, uint16_t *out, int64_t n, void *stream_v)
     hipLaunchKernelGGL(to_half_kernel, dim3(2048), dim3(256), 0, stream, psf, (unsigned short *)out, n);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(stream));
+    return CLEAN_OK;
+}
+
+int clean_bandwidth_probe(void *buf, size_t bytes, int mode, int reps, double *gbs, void *stream_v)
+{
+    g_last_error.clear();
+    if (!buf || !gbs) return fail(CLEAN_E_INVAL, "buf and gbs must be non-NULL");
+    if (bytes < 4096 || bytes % 32) return fail(CLEAN_E_INVAL, "bytes %zu: at least 4096 and a multiple of 32", bytes);
+    if (mode != 0 && mode != 1) return fail(CLEAN_E_INVAL, "mode %d is not 0 (read) or 1 (copy)", mode);
+    if (reps < 1 || reps > 100000) return fail(CLEAN_E_INVAL, "reps %d not in [1, 100000]", reps);
+    hipStream_t stream = (hipStream_t)stream_v;
+    int dev = 0, ncu = 0;
+    HIPCHK(hipGetDevice(&dev));
+    HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    void *sink = nullptr;
+    int st = internal_workspace(dev, 4096, &sink);
+    if (st) return st;
+    const int blocks = 8 * ncu;             // 2048 workgroups of 256 threads on 256 CUs
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    HIPCHK(hipEventRecord(e0, stream));
+    if (mode == 0)
+        hipLaunchKernelGGL(probe_read_kernel, dim3(blocks), dim3(256), 0, stream, (const float4 *)buf,
+                           (int64_t)(bytes / 16), reps, (float *)sink);
+    else
+        hipLaunchKernelGGL(probe_copy_kernel, dim3(blocks), dim3(256), 0, stream, (const float4 *)buf,
+                           (float4 *)((char *)buf + bytes / 2), (int64_t)(bytes / 32), reps);
+    hipError_t le = hipGetLastError();
+    if (le == hipSuccess) le = hipEventRecord(e1, stream);
+    if (le == hipSuccess) le = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (le == hipSuccess) le = hipEventElapsedTime(&ms, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (le != hipSuccess) return fail(CLEAN_E_HIP, "bandwidth probe: %s", hipGetErrorString(le));
+    *gbs = ms > 0.f ? (double)bytes * reps / (ms * 1e-3) / 1e9 : 0.0;
     return CLEAN_OK;
 }
 

@@ -13,6 +13,8 @@ constexpr int GATHER_CHUNK = 2048;      // components staged in LDS per pass
 constexpr int GATHER_M = 2;             // pixel groups per thread per gather pass
 constexpr int GATHER_J = 8;             // components whose loads are issued together
 constexpr int STREAM_K = 4;             // pixel groups per thread per streamed pass
+constexpr int TWO_LEVEL_MIN_CS = 16;    // plain clusters this large exchange in two levels
+constexpr int MAX_WG_PER_CU = 2;        // co-resident 512-thread workgroups the launches count on per CU
 constexpr int FFT_MAX_LG = 13;          // one-level FFT transforms: length <= 8192 (64 KB of LDS)
 constexpr int FFT_MAX_LG2 = 16;         // two-level FFT transforms: length <= 65536
 constexpr int FFT_LDS_CPLX = 8192 + 64; // LDS complex slots of the two-level passes
@@ -44,6 +46,7 @@ struct DevStat {
     double sumsq;
     uint64_t phase_ticks[3];   // tiled: local loops, feedback gather, apply + re-peak (wall-clock ticks)
     int32_t xcd_local;         // clusters whose exchanges stayed inside one XCD
+    int32_t levels;            // plain: 2 if the cluster exchanged in two levels, else 1 (0: not set)
 };
 
 // One plain CLEAN problem as a workgroup cluster sees it.
@@ -64,6 +67,8 @@ struct PlainJob {
     float *comp_flux;
     uint64_t *slots;        // [2][slot_pad] device-scope exchange slots
     uint64_t *lslots;       // [2][slot_pad] XCD-local exchange slots (batched), else null
+    uint64_t *hslots;       // [2][8 * hpad + 32] two-level exchange slots (plain, large clusters), else null
+    int hpad;               // slots per XCD of the two-level exchange
     DevStat *dstat;
     double *partial;        // [cs]
 };
@@ -119,6 +124,8 @@ struct KArgs {
     const int32_t *role;    // per workgroup: tile << 16 | rank, or -1 (helper)
     uint64_t *xslots;       // [T][2][slot_pad] device-scope exchange slots
     uint64_t *lslots;       // [T][2][slot_pad] XCD-local exchange slots
+    uint64_t *hslots;       // plain, cs >= TWO_LEVEL_MIN_CS: [2][8 * hpad + 32] two-level slots, else null
+    int hpad;
     uint64_t *tile_key;     // [T]
     int32_t *rb_idx;        // [T][interval] raw round lists
     float *rb_flux;

@@ -349,6 +349,118 @@ __device__ int cluster_same_xcd(const Sync &y, uint64_t *slots, uint64_t *lslots
     return s_same;
 }
 
+// Two-level exchange for clusters spread over the XCDs (plain CLEAN's one
+// cluster of cs >= 16 workgroups, rank r on XCD r % 8, checked at launch).
+// Parity block: 8 XCD-local arrays of `hpad` slots, then 8 leader slots.
+// Each workgroup publishes its key into its XCD's array with an XCD-local
+// store; the XCD's leader (its lowest rank) takes their max and publishes it
+// in its leader slot with a device-scope store; every workgroup polls the 8
+// leader slots.  Two hops that stay short instead of one device-scope poll of
+// every workgroup's slot, whose cost grows with the cluster.
+__device__ bool cluster_reduce_xcd2(const Sync &y, uint64_t *hs, int hpad, int cs, int rank, uint32_t e,
+                                    uint64_t tkey, uint64_t &out)
+{
+    __shared__ uint64_t s_wave[NWAVES];
+    __shared__ uint64_t s_res;
+    __shared__ int s_good;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const uint64_t wk = wave_max64(tkey);
+    if (lane == 0) s_wave[wave] = wk;
+    __syncthreads();
+    if (wave == 0) {
+        uint64_t g = s_wave[0];
+#pragma unroll
+        for (int w = 1; w < NWAVES; ++w) g = umax64(g, s_wave[w]);
+        bool ok = true;
+        const uint64_t tag = (uint64_t)((e & 7u) + 1u);
+        uint64_t *base = hs + (size_t)(e & 1u) * (8 * (size_t)hpad + 32);
+        const int x = rank & 7, i = rank >> 3;
+        uint64_t *lb = base + (size_t)x * hpad;
+        uint64_t *gb = base + 8 * (size_t)hpad;
+        if (lane == 0) st_xcd(&lb[i], (g & ~15ull) | tag);
+        const uint64_t t0 = wall_clock64();
+        uint32_t spins = 0;
+        if (i == 0) {
+            // the XCD's leader: its members' keys, then its leader slot
+            const int nx = (cs - x + 7) >> 3;
+            for (;;) {
+                bool have = true;
+                uint64_t best = 0;
+                for (int s = lane; s < nx; s += 64) {
+                    const uint64_t v = ld_agent(&lb[s]);
+                    if ((v & 15ull) != tag) have = false;
+                    best = umax64(best, v);
+                }
+                if (__all(have)) { g = wave_max64(best) & ~15ull; break; }
+                if ((++spins & 63u) == 0) {
+                    if (aborted(y)) { ok = false; break; }
+                    if (wall_clock64() - t0 > y.timeout_ticks) { raise_abort(y, ABORT_TIMEOUT); ok = false; break; }
+                }
+            }
+            if (ok && lane == 0) st_agent(&gb[x], g | tag);
+        }
+        // every workgroup: the leaders' keys
+        const int nl = cs < 8 ? cs : 8;
+        while (ok) {
+            const uint64_t v = lane < nl ? ld_agent(&gb[lane]) : tag;
+            if (__all((v & 15ull) == tag)) { g = wave_max64(lane < nl ? v : 0) & ~15ull; break; }
+            if ((++spins & 63u) == 0) {
+                if (aborted(y)) { ok = false; break; }
+                if (wall_clock64() - t0 > y.timeout_ticks) { raise_abort(y, ABORT_TIMEOUT); ok = false; break; }
+            }
+        }
+        if (lane == 0) { s_res = g; s_good = ok; }
+    }
+    __syncthreads();
+    out = s_res;
+    return s_good != 0;
+}
+
+// Whether rank r of a cluster runs on XCD r % 8 for every r (what the
+// two-level exchange needs; plain launches place workgroup b on XCD b % 8),
+// agreed through exchange `e` of the flat device-scope slots.  Before
+// publishing, each workgroup clears its entries of the two-level XCD-local
+// arrays (both parities) and waits until the clears have reached L2, so that
+// no stale line of them can be read afterwards.  Returns 1 or 0, or -1 if the
+// run was aborted; uniform over the workgroup.
+__device__ int cluster_round_robin(const Sync &y, uint64_t *slots, int slot_pad, uint64_t *hs, int hpad, int cs,
+                                   int rank, uint32_t e)
+{
+    __shared__ int s_rr;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (wave == 0) {
+        const uint32_t me = xcc_id();
+        const uint64_t tag = (uint64_t)((e & 7u) + 1u);
+        uint64_t *blk = slots + (size_t)(e & 1u) * slot_pad;
+        if (lane == 0) {
+            const size_t at = (size_t)(rank & 7) * hpad + (size_t)(rank >> 3);
+            st_xcd(&hs[at], 0);
+            st_xcd(&hs[8 * (size_t)hpad + 32 + at], 0);
+            asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+            st_agent(&blk[rank], ((uint64_t)(me == (uint32_t)(rank & 7)) << 8) | tag);
+        }
+        int res = -1;
+        const uint64_t t0 = wall_clock64();
+        uint32_t spins = 0;
+        for (;;) {
+            bool have = true, good = true;
+            for (int s = lane; s < cs; s += 64) {
+                const uint64_t v = ld_agent(&blk[s]);
+                if ((v & 15ull) != tag) have = false;
+                else if (!((v >> 8) & 1ull)) good = false;
+            }
+            if (__all(have)) { res = __all(good) ? 1 : 0; break; }
+            if ((++spins & 63u) == 0) {
+                if (aborted(y)) break;
+                if (wall_clock64() - t0 > y.timeout_ticks) { raise_abort(y, ABORT_TIMEOUT); break; }
+            }
+        }
+        if (lane == 0) s_rr = res;
+    }
+    __syncthreads();
+    return s_rr;
+}
+
 // Grid-wide barrier.  Data that crosses it is written and read with the
 // agent-coherent accessors above; the barrier itself only orders: every wave
 // waits for its own memory operations to complete, the workgroup barrier
@@ -1055,6 +1167,14 @@ template <class Tile> __device__ bool run_plain(const PlainJob &j_arg, int rank_
         ls = j.lslots;
     }
     uint32_t e = 0;
+    // a large cluster spread over the XCDs (plain CLEAN) exchanges in two
+    // levels when every rank sits on the XCD the placement intends
+    bool two = false;
+    if (j.hslots) {
+        const int rr = cluster_round_robin(y, j.slots, j.slot_pad, j.hslots, j.hpad, j.cs, rank, e++);
+        if (rr < 0) return false;
+        two = rr > 0;
+    }
     uint64_t cur;
     if (!cluster_reduce(y, j.slots, nullptr, j.slot_pad, j.cs, rank, e++, T.key(im), cur)) return false;
     cur = wave_uniform(cur);
@@ -1080,7 +1200,9 @@ template <class Tile> __device__ bool run_plain(const PlainJob &j_arg, int rank_
         }
         if (j.model && T.owns(fp)) j.model[fp] += (double)c;
         // subtraction (eq. 2) fused with the next peak search
-        if (!cluster_reduce(y, j.slots, ls, j.slot_pad, j.cs, rank, e++, T.subtract(im, py, px, c, true), cur))
+        const uint64_t tk = T.subtract(im, py, px, c, true);
+        if (!(two ? cluster_reduce_xcd2(y, j.hslots, j.hpad, j.cs, rank, e++, tk, cur)
+                  : cluster_reduce(y, j.slots, ls, j.slot_pad, j.cs, rank, e++, tk, cur)))
             return false;
         cur = wave_uniform(cur);
         n += 1;
@@ -1093,6 +1215,7 @@ template <class Tile> __device__ bool run_plain(const PlainJob &j_arg, int rank_
         j.dstat->final_peak = (double)key_value(cur);
         j.dstat->model_flux = mflux;
         j.dstat->xcd_local = local ? 1 : 0;
+        j.dstat->levels = two ? 2 : 1;
     }
     return true;
 }
@@ -1109,6 +1232,7 @@ template <class Tile> __global__ void __launch_bounds__(WG) hogbom_kernel(const 
     j.gain = a.gain; j.threshold = a.threshold; j.max_iter = a.max_iter; j.cap = a.cap;
     j.comp_idx = a.comp_idx; j.comp_flux = a.comp_flux;
     j.slots = a.xslots; j.lslots = nullptr; j.slot_pad = a.slot_pad; j.cs = a.cs;
+    j.hslots = a.hslots; j.hpad = a.hpad;
     j.dstat = a.dstat; j.partial = a.partial;
     run_plain<Tile>(j, role & 0xFFFF, y, false);
 }
