@@ -78,6 +78,7 @@ typedef enum {
     CLEAN_STOP_MAXITER = 0,   /* max_iter components were found               */
     CLEAN_STOP_THRESHOLD = 1, /* every peak is below the threshold            */
     CLEAN_STOP_CAPACITY = 2,  /* comp_cap components were found first         */
+    CLEAN_STOP_CANCELLED = 3, /* the caller's cancel flag was set             */
     CLEAN_STOP_NONFINITE = 4  /* a peak was NaN or infinite (the run diverged,
                                  or non-finite input was not screened out)    */
 } clean_stop;
@@ -133,6 +134,17 @@ typedef struct {
                              if its peak is at or above the level and ends its
                              round when its peak drops below it (or after
                              feedback_interval iterations).  0 = interval only */
+    const volatile int32_t *cancel; /* NULL, or a flag in host memory the
+                             device can read (hipHostMalloc'ed, or pinned by
+                             torch), written by another host thread while the
+                             call runs.  Once it holds a non-zero value the run
+                             stops at its next checkpoint with
+                             CLEAN_STOP_CANCELLED: plain and batched problems
+                             every 4096 iterations (iteration 0 included),
+                             tiled runs at each round's start.  The results are
+                             then those of the same call with max_iter = the
+                             iterations done.  A checkpoint costs one extra
+                             peak exchange (plain) and one read of host memory */
 } clean_params;
 
 typedef struct {
@@ -242,13 +254,20 @@ int clean_hogbom_noalloc(const float *dirty, int ny, int nx,
  *             acc = fmaf(value_c, psf[q - c + centre], acc);
  *   r[q] = r[q] - acc.
  * The run stops at the start of a round when max_iter components exist, when
- * a tile's peak is not finite (CLEAN_STOP_NONFINITE), when no tile is active,
+ * the cancel flag is set, when a tile's peak is not finite
+ * (CLEAN_STOP_NONFINITE), when no tile is active,
  * or when comp_cap components exist; inside a round a tile's loop also ends
  * at a non-finite peak.  Every round ends with its feedback, so
  * residual + components (*) PSF = dirty holds at return.
  *
  *   comp_idx/comp_flux   order: round, then tile id, then local iteration.
- *   feedback_interval    1 .. 2048.
+ *   feedback_interval    1 .. 2048.  Without CLEAN_FLAG_FFT_FEEDBACK, a call
+ *                        whose direct gather could read more than 2^44 bytes
+ *                        of PSF in one round (tiles x interval components,
+ *                        each over the pixels outside its tile) is refused
+ *                        with CLEAN_E_UNSUPPORTED: that phase could outlast
+ *                        the device's wait limit; the FFT form has no such
+ *                        bound.
  *   tiles_y, tiles_x     1 .. ny (nx); at most 1024 tiles.
  * Other arguments as for clean_hogbom.  With tiles_y = tiles_x = 1 the result
  * equals clean_hogbom's bit for bit.
@@ -333,6 +352,48 @@ int clean_autotune_interval(const float *dirty, int ny, int nx, const void *psf,
                             float *residual, int32_t *comp_idx, float *comp_flux, int64_t comp_cap,
                             int *interval, double *rate_out, double *peak_ratio_out, void *stream);
 
+/*
+ * clean_autotune_plan -- picks the tile grid and the feedback interval of
+ * clean_tiled_feedback for this image under an accuracy budget.  The paper
+ * (Section 4) reports the tiled result within -0.1 .. +0.04 Jy of plain
+ * CLEAN, and the interval and tile count decide whether the method holds it
+ * at all (with a PSF of high sidelobes a long interval diverges).  So every
+ * candidate pair (grids[2i], grids[2i+1]) x intervals[j] gets a trial run of
+ * min(trial_iter, p->max_iter) total iterations on the caller's image, beside
+ * one plain clean_hogbom run of the same length; both are restored
+ * (clean_beam_fit, clean_restore) and the pair is acceptable when every pixel
+ * of restored(tiled) - restored(plain) lies in [band_min, band_max] Jy and
+ * the run did not go non-finite.  The acceptable pair with the highest trial
+ * rate (minor iterations per second) is written to *plan with its band and
+ * its launch shape; plan->interval = 0 when none is acceptable (status still
+ * CLEAN_OK).  band_out (host, 2 * n_grids * n_intervals, may be NULL) and
+ * rate_out (host, n_grids * n_intervals, may be NULL) get every candidate's
+ * band and rate, candidate index = grid index * n_intervals + interval
+ * index (NaN for a grid with no launch).
+ * cache_path (may be NULL): a text file of plans, one line per key (device
+ * architecture and name, image and PSF shape, PSF dtype, flags, gain,
+ * threshold, max_iter, trial length, trigger level, budget, candidates).  A
+ * key found there is returned without any trial (plan->from_cache = 1): the
+ * plan was validated on the image of the call that stored it.  New plans are
+ * appended.  The library allocates its trial buffers (about 40 bytes per
+ * pixel).  Arguments: 1..16 grids (not 1 x 1) and 1..16 intervals, trial_iter
+ * >= 1, band_min <= 0 <= band_max, otherwise CLEAN_E_INVAL; errors of the
+ * trial runs are returned as they are.
+ */
+typedef struct {
+    int32_t tiles_y, tiles_x, interval; /* the chosen pair; interval 0: none acceptable */
+    int32_t wg_per_tile, px_per_thread; /* the launch shape of its trial                  */
+    double band_min, band_max;          /* restored tiled - plain over the image, Jy     */
+    double iters_per_s;                 /* the trial's minor iterations per second       */
+    int32_t from_cache;                 /* 1: read from cache_path                       */
+} clean_plan;
+
+int clean_autotune_plan(const float *dirty, int ny, int nx, const void *psf, int psf_ny, int psf_nx,
+                        const int *grids, int n_grids, const int *intervals, int n_intervals,
+                        const clean_params *p, int64_t trial_iter, double band_min, double band_max,
+                        const char *cache_path, clean_plan *plan, double *band_out, double *rate_out,
+                        void *stream);
+
 /* Bytes of device workspace clean_hogbom (tiles 1x1) or clean_tiled_feedback
  * needs for this shape; 0 on invalid arguments. */
 size_t clean_workspace_size(int ny, int nx, int tiles_y, int tiles_x,
@@ -381,6 +442,15 @@ int clean_psf_to_f16(const float *psf, uint16_t *out, int64_t n, void *stream);
  * CLEAN_E_INVAL for NULL pointers or arguments out of range.
  */
 int clean_bandwidth_probe(void *buf, size_t bytes, int mode, int reps, double *gbs, void *stream);
+
+/*
+ * clean_set_workspace_limit -- caps the device memory the library allocates
+ * for its internal workspace (calls with workspace == NULL, batched calls,
+ * restoration): a call that would need more fails with CLEAN_E_NOMEM before
+ * anything is launched.  0 removes the cap (the default).  Returns the
+ * previous cap.  Applies to every device and thread of the process.
+ */
+size_t clean_set_workspace_limit(size_t bytes);
 
 /* Static description of a clean_status value. */
 const char *clean_strerror(int status);

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libclean.so")
 CLEAN_OK = 0
 STATUS = {0: "CLEAN_OK", -1: "CLEAN_E_INVAL", -2: "CLEAN_E_NONFINITE", -3: "CLEAN_E_NOMEM",
           -4: "CLEAN_E_HIP", -5: "CLEAN_E_TIMEOUT", -6: "CLEAN_E_UNSUPPORTED"}
-STOP_NAMES = {0: "maxiter", 1: "threshold", 2: "capacity", 4: "nonfinite"}
+STOP_NAMES = {0: "maxiter", 1: "threshold", 2: "capacity", 3: "cancelled", 4: "nonfinite"}
 PSF_F32, PSF_F16 = 0, 1
 FLAG_CHECK_FINITE = 1
 FLAG_STREAM_RESIDUAL = 2
@@ -25,8 +25,10 @@ FLAG_FFT_FEEDBACK = 4
 FLAG_FFT_TWO_LEVEL = 8
 
 # every symbol include/clean.h declares
-EXPORTS = ("clean_hogbom", "clean_hogbom_noalloc", "clean_tiled_feedback", "clean_batched", "clean_autotune", "clean_autotune_interval",
-           "clean_beam_fit", "clean_restore", "clean_workspace_size", "clean_psf_to_f16", "clean_bandwidth_probe",
+EXPORTS = ("clean_hogbom", "clean_hogbom_noalloc", "clean_tiled_feedback", "clean_batched", "clean_autotune",
+           "clean_autotune_interval", "clean_autotune_plan",
+           "clean_beam_fit", "clean_restore", "clean_workspace_size", "clean_set_workspace_limit", "clean_psf_to_f16",
+           "clean_bandwidth_probe",
            "clean_strerror",
            "clean_last_error", "clean_version")
 
@@ -34,7 +36,7 @@ EXPORTS = ("clean_hogbom", "clean_hogbom_noalloc", "clean_tiled_feedback", "clea
 class Params(C.Structure):
     _fields_ = [("gain", C.c_double), ("threshold", C.c_double), ("max_iter", C.c_int64),
                 ("psf_dtype", C.c_int32), ("flags", C.c_int32), ("wg_per_tile", C.c_int32),
-                ("px_per_thread", C.c_int32), ("feedback_level", C.c_double)]
+                ("px_per_thread", C.c_int32), ("feedback_level", C.c_double), ("cancel", C.c_void_p)]
 
 
 class Stats(C.Structure):
@@ -48,6 +50,12 @@ class Stats(C.Structure):
         d = {k: getattr(self, k) for k, _ in self._fields_}
         d["phase_us"] = list(self.phase_us)
         return d
+
+
+class Plan(C.Structure):
+    _fields_ = [("tiles_y", C.c_int32), ("tiles_x", C.c_int32), ("interval", C.c_int32),
+                ("wg_per_tile", C.c_int32), ("px_per_thread", C.c_int32), ("band_min", C.c_double),
+                ("band_max", C.c_double), ("iters_per_s", C.c_double), ("from_cache", C.c_int32)]
 
 
 class Problem(C.Structure):
@@ -88,6 +96,9 @@ def load():
     lib.clean_autotune_interval.argtypes = [P, i32, i32, P, i32, i32, i32, i32, P, i32, C.POINTER(Params), i64,
                                             C.c_double, P, P, P, i64, C.POINTER(C.c_int), P, P, P]
     lib.clean_autotune_interval.restype = C.c_int
+    lib.clean_autotune_plan.argtypes = [P, i32, i32, P, i32, i32, P, i32, P, i32, C.POINTER(Params), i64, C.c_double,
+                                        C.c_double, C.c_char_p, C.POINTER(Plan), P, P, P]
+    lib.clean_autotune_plan.restype = C.c_int
     lib.clean_beam_fit.argtypes = [P, i32, i32, i32, C.POINTER(C.c_int64), C.POINTER(C.c_double), P]
     lib.clean_beam_fit.restype = C.c_int
     lib.clean_restore.argtypes = [P, P, i32, i32, C.c_double, P, P]
@@ -95,6 +106,8 @@ def load():
     lib.clean_workspace_size.argtypes = [i32, i32, i32, i32, i32, C.POINTER(Params)]
     lib.clean_workspace_size.restype = sz
     lib.clean_psf_to_f16.argtypes = [P, P, i64, P]
+    lib.clean_set_workspace_limit.argtypes = [sz]
+    lib.clean_set_workspace_limit.restype = sz
     lib.clean_bandwidth_probe.argtypes = [P, sz, i32, i32, C.POINTER(C.c_double), P]
     lib.clean_bandwidth_probe.restype = C.c_int
     for f in (lib.clean_hogbom, lib.clean_hogbom_noalloc, lib.clean_tiled_feedback, lib.clean_batched,
@@ -141,6 +154,18 @@ def _params(gain, threshold, max_iter, psf, flags, wg_per_tile, px_per_thread):
                   int(px_per_thread))
 
 
+def _cancel(flag):
+    """The cancel flag: None, or a pinned host int32 tensor of one element
+    (torch.zeros(1, dtype=torch.int32).pin_memory()) that another thread sets
+    to a non-zero value to stop the run at its next checkpoint."""
+    if flag is None:
+        return None
+    torch = _torch()
+    if flag.dtype != torch.int32 or flag.is_cuda or not flag.is_pinned() or flag.numel() < 1:
+        raise TypeError("cancel must be a pinned host int32 tensor")
+    return flag.data_ptr()
+
+
 def _prep(dirty, psf):
     torch = _torch()
     if dirty.dtype != torch.float32 or dirty.dim() != 2 or psf.dim() != 2:
@@ -166,13 +191,14 @@ def _flags(check_finite, stream):
 
 
 def hogbom(dirty, psf, gain=0.1, threshold=0.0, max_iter=1000, cap=None, model=True, check_finite=False,
-           wg_per_tile=0, px_per_thread=0, stream=False, out=None):
+           wg_per_tile=0, px_per_thread=0, stream=False, out=None, cancel=None):
     """Plain Hogbom CLEAN; returns dict(residual, idx, flux, model, stats)."""
     lib = load()
     dirty, psf = _prep(dirty, psf)
     cap = int(max_iter if cap is None else cap)
     res, idx, flux, mod = out if out is not None else _outputs(dirty, cap, model)
     p = _params(gain, threshold, max_iter, psf, _flags(check_finite, stream), wg_per_tile, px_per_thread)
+    p.cancel = _cancel(cancel)
     st = Stats()
     ny, nx = dirty.shape
     _check(lib.clean_hogbom(_ptr(dirty), ny, nx, _ptr(psf), psf.shape[0], psf.shape[1], C.byref(p), _ptr(res),
@@ -182,7 +208,7 @@ def hogbom(dirty, psf, gain=0.1, threshold=0.0, max_iter=1000, cap=None, model=T
 
 
 def hogbom_noalloc(dirty, psf, gain=0.1, threshold=0.0, max_iter=1000, cap=None, check_finite=False,
-                   wg_per_tile=0, px_per_thread=0, stream=False, out=None):
+                   wg_per_tile=0, px_per_thread=0, stream=False, out=None, cancel=None):
     """clean_hogbom_noalloc: plain Hogbom CLEAN whose call allocates nothing
     (its workspace is the library's per-GPU device scratch array).  `out`
     (residual, idx, flux, model) lets a caller that cannot allocate pass its
@@ -192,6 +218,7 @@ def hogbom_noalloc(dirty, psf, gain=0.1, threshold=0.0, max_iter=1000, cap=None,
     cap = int(max_iter if cap is None else cap)
     res, idx, flux, mod = out if out is not None else _outputs(dirty, cap, True)
     p = _params(gain, threshold, max_iter, psf, _flags(check_finite, stream), wg_per_tile, px_per_thread)
+    p.cancel = _cancel(cancel)
     st = Stats()
     ny, nx = dirty.shape
     _check(lib.clean_hogbom_noalloc(_ptr(dirty), ny, nx, _ptr(psf), psf.shape[0], psf.shape[1], C.byref(p),
@@ -202,7 +229,7 @@ def hogbom_noalloc(dirty, psf, gain=0.1, threshold=0.0, max_iter=1000, cap=None,
 
 def tiled_feedback(dirty, psf, tiles=(2, 2), interval=100, gain=0.1, threshold=0.0, max_iter=1000, cap=None,
                    model=True, check_finite=False, wg_per_tile=0, px_per_thread=0, stream=False, out=None,
-                   level=0.0, fft=False, fft_two_level=False):
+                   level=0.0, fft=False, fft_two_level=False, cancel=None):
     """Tiled Hogbom CLEAN with feedback; returns dict(residual, idx, flux, model, stats).
 
     level: flux trigger, the fraction of the largest tile peak at a round's
@@ -213,6 +240,7 @@ def tiled_feedback(dirty, psf, tiles=(2, 2), interval=100, gain=0.1, threshold=0
     res, idx, flux, mod = out if out is not None else _outputs(dirty, cap, model)
     p = _params(gain, threshold, max_iter, psf, _flags(check_finite, stream), wg_per_tile, px_per_thread)
     p.feedback_level = float(level)
+    p.cancel = _cancel(cancel)
     if fft:
         p.flags |= FLAG_FFT_FEEDBACK
     if fft_two_level:
@@ -226,7 +254,7 @@ def tiled_feedback(dirty, psf, tiles=(2, 2), interval=100, gain=0.1, threshold=0
     return dict(residual=res, idx=idx[:n], flux=flux[:n], model=mod, stats=st.as_dict())
 
 
-def batched(problems, gain=0.1, model=True, check_finite=False, px_per_thread=0):
+def batched(problems, gain=0.1, model=True, check_finite=False, px_per_thread=0, cancel=None):
     """Independent plain Hogbom problems in one persistent launch.
 
     problems: list of dicts with device tensors "dirty" (float32 2-D) and "psf"
@@ -274,7 +302,8 @@ def batched(problems, gain=0.1, model=True, check_finite=False, px_per_thread=0)
     if n == 0:
         return []
     dt = PSF_F16 if psf_dtype == torch.float16 else PSF_F32
-    prm = Params(float(gain), 0.0, 0, dt, FLAG_CHECK_FINITE if check_finite else 0, 0, int(px_per_thread), 0.0)
+    prm = Params(float(gain), 0.0, 0, dt, FLAG_CHECK_FINITE if check_finite else 0, 0, int(px_per_thread), 0.0,
+                 _cancel(cancel))
     stats = (Stats * n)()
     _check(lib.clean_batched(arr, n, C.byref(prm), stats, _stream()))
     res = []
@@ -328,6 +357,44 @@ def autotune_interval(dirty, psf, tiles, candidates, gain=0.1, threshold=0.0, ma
     return dict(interval=chosen.value, rates=list(rates), peak_ratios=list(ratios))
 
 
+def autotune_plan(dirty, psf, grids, intervals, gain=0.1, threshold=0.0, max_iter=1000, trial_iter=None,
+                  band=(-0.1, 0.1), cache_path=None, level=0.0, fft=False):
+    """Tile grid and feedback interval under an accuracy budget: every
+    (grid, interval) candidate gets a trial of min(trial_iter, max_iter)
+    iterations beside plain CLEAN; acceptable when restored(tiled) -
+    restored(plain) stays inside `band` (Jy) everywhere; the fastest
+    acceptable one wins.  Returns dict(tiles, interval (0: none), wg_per_tile,
+    px_per_thread, band, iters_per_s, from_cache, candidates) with every
+    candidate's band and rate (not filled on a cache hit)."""
+    lib = load()
+    dirty, psf = _prep(dirty, psf)
+    flags = FLAG_FFT_FEEDBACK if fft else 0
+    p = _params(gain, threshold, max_iter, psf, flags, 0, 0)
+    p.feedback_level = float(level)
+    g = (C.c_int * (2 * len(grids)))(*[int(v) for gr in grids for v in gr])
+    iv = (C.c_int * len(intervals))(*[int(v) for v in intervals])
+    nc = len(grids) * len(intervals)
+    bands = (C.c_double * (2 * nc))()
+    rates = (C.c_double * nc)()
+    plan = Plan()
+    ny, nx = dirty.shape
+    trial = int(max_iter if trial_iter is None else trial_iter)
+    _check(lib.clean_autotune_plan(_ptr(dirty), ny, nx, _ptr(psf), psf.shape[0], psf.shape[1], C.cast(g, C.c_void_p),
+                                   len(grids), C.cast(iv, C.c_void_p), len(intervals), C.byref(p), trial,
+                                   float(band[0]), float(band[1]),
+                                   cache_path.encode() if cache_path else None, C.byref(plan),
+                                   C.cast(bands, C.c_void_p), C.cast(rates, C.c_void_p), _stream()))
+    cands = []
+    for gi, gr in enumerate(grids):
+        for ii, ivl in enumerate(intervals):
+            k = gi * len(intervals) + ii
+            cands.append(dict(tiles=tuple(gr), interval=int(ivl), band=[bands[2 * k], bands[2 * k + 1]],
+                              iters_per_s=rates[k]))
+    return dict(tiles=(plan.tiles_y, plan.tiles_x), interval=plan.interval, wg_per_tile=plan.wg_per_tile,
+                px_per_thread=plan.px_per_thread, band=[plan.band_min, plan.band_max],
+                iters_per_s=plan.iters_per_s, from_cache=bool(plan.from_cache), candidates=cands)
+
+
 def clean_beam(psf):
     """The clean beam of a device PSF: dict(area (main-lobe pixels), sigma, fwhm) in pixels."""
     torch = _torch()
@@ -364,6 +431,12 @@ def psf_to_f16(psf):
     out = torch.empty(psf.shape, dtype=torch.float16, device=psf.device)
     _check(lib.clean_psf_to_f16(_ptr(psf), _ptr(out), psf.numel(), _stream()))
     return out
+
+
+def set_workspace_limit(nbytes):
+    """Caps the library's internal device workspace (0: no cap); returns the
+    previous cap.  A call needing more fails with CLEAN_E_NOMEM."""
+    return int(load().clean_set_workspace_limit(int(nbytes)))
 
 
 def bandwidth_probe(buf, mode=0, reps=10):

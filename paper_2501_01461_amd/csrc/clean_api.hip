@@ -32,6 +32,7 @@ __global__ void finite_check_half_kernel(const unsigned short *x, int64_t n, uin
 __global__ void to_half_kernel(const float *x, unsigned short *y, int64_t n);
 __global__ void finalize_kernel(const double *partial, int n, DevStat *st);
 __global__ void zero_kernel(uint32_t *p, int64_t n);
+__global__ void diff_range_kernel(const double *a, const double *b, int64_t n, double *part);
 __global__ void probe_read_kernel(const float4 *p, int64_t n4, int reps, float *sink);
 __global__ void probe_copy_kernel(const float4 *src, float4 *dst, int64_t n4, int reps);
 __global__ void restore_rows_kernel(const double *model, double *tmp, int ny, int nx, const double *b, int R);
@@ -77,6 +78,7 @@ struct PinnedStage {
     size_t bytes = 0;
 };
 thread_local PinnedStage t_stage;
+void register_release();
 
 // Copies n_parts (dst, src, bytes) device -> host on `stream` and waits.
 // `direct`: straight into the (pageable) destinations, allocating nothing;
@@ -103,6 +105,7 @@ int read_back(const D2H *parts, int n_parts, hipStream_t stream, bool direct = f
         const size_t sz = std::max(total, (size_t)4096);
         HIPCHK(hipHostMalloc(&t_stage.ptr, sz, hipHostMallocDefault));
         t_stage.bytes = sz;
+        register_release();
     }
     size_t o = 0;
     for (int i = 0; i < n_parts; ++i) {
@@ -126,11 +129,35 @@ struct Workspace {
 };
 std::mutex g_ws_mu;
 Workspace g_ws[64];
+size_t g_ws_limit = 0;            // clean_set_workspace_limit (0: none)
+
+// The library's device and pinned buffers are released at process exit, by
+// a handler registered after the HIP runtime is up (so it runs before the
+// runtime's own teardown): the internal workspaces and this thread's pinned
+// stage.  Buffers of other threads' stages stay to the end of the process.
+void release_at_exit()
+{
+    for (Workspace &w : g_ws)
+        if (w.ptr) {
+            (void)hipFree(w.ptr);
+            w.ptr = nullptr;
+            w.bytes = 0;
+        }
+    if (t_stage.ptr) {
+        (void)hipHostFree(t_stage.ptr);
+        t_stage.ptr = nullptr;
+        t_stage.bytes = 0;
+    }
+}
+std::once_flag g_exit_once;
+void register_release() { std::call_once(g_exit_once, [] { std::atexit(release_at_exit); }); }
 
 int internal_workspace(int dev, size_t need, void **out)
 {
     std::lock_guard<std::mutex> lk(g_ws_mu);
     if (dev < 0 || dev >= 64) return fail(CLEAN_E_INVAL, "device %d out of range", dev);
+    if (g_ws_limit && need > g_ws_limit)
+        return fail(CLEAN_E_NOMEM, "workspace of %zu bytes exceeds the limit of %zu bytes", need, g_ws_limit);
     Workspace &w = g_ws[dev];
     if (w.bytes < need) {
         if (w.ptr) {
@@ -140,11 +167,13 @@ int internal_workspace(int dev, size_t need, void **out)
             w.bytes = 0;
         }
         size_t sz = std::max(need, (size_t)1 << 20);
+        if (g_ws_limit) sz = std::min(sz, g_ws_limit);
         if (hipMalloc(&w.ptr, sz) != hipSuccess) {
             (void)hipGetLastError();
             return fail(CLEAN_E_NOMEM, "workspace allocation of %zu bytes failed", sz);
         }
         w.bytes = sz;
+        register_release();
     }
     *out = w.ptr;
     return CLEAN_OK;
@@ -491,6 +520,18 @@ int run(bool tiled, const float *dirty, int ny, int nx, const void *psf, int psf
             return fail(CLEAN_E_INVAL, "feedback interval %d not in [1, %d]", interval, MAX_INTERVAL);
         if (!(p->feedback_level >= 0.0 && p->feedback_level <= 1.0))
             return fail(CLEAN_E_INVAL, "feedback_level %g not in [0, 1]", p->feedback_level);
+        if (!(p->flags & CLEAN_FLAG_FFT_FEEDBACK)) {
+            // worst case of one round's direct gather: every tile appends
+            // `interval` distinct components, each read over every pixel
+            // outside its tile
+            const int64_t smallest = (int64_t)(ny / tiles_y) * (nx / tiles_x);
+            const double worst = (double)tiles_y * tiles_x * interval * (double)((int64_t)ny * nx - smallest) *
+                                 (p->psf_dtype == CLEAN_PSF_F16 ? 2.0 : 4.0);
+            if (worst > GATHER_MAX_BYTES)
+                return fail(CLEAN_E_UNSUPPORTED, "a round of direct-gather feedback could read %.3g bytes of PSF, "
+                            "more than a round may take within the device's wait limit; use "
+                            "CLEAN_FLAG_FFT_FEEDBACK", worst);
+        }
     } else {
         tiles_y = tiles_x = 1;
         interval = 1;
@@ -693,6 +734,7 @@ int run(bool tiled, const float *dirty, int ny, int nx, const void *psf, int psf
     if (st) return st;
     a.comp_idx = comp_idx;
     a.comp_flux = comp_flux;
+    a.cancel = (const int32_t *)p->cancel;
     a.ctl = (DevCtl *)(ws + L.ctl);
     a.dstat = (DevStat *)(ws + L.dstat);
     a.role = (const int32_t *)(ws + L.role);
@@ -980,6 +1022,7 @@ int clean_batched(const clean_problem *probs, int n, const clean_params *shared,
         j.max_iter = q.max_iter;
         j.cap = q.comp_cap;
         j.comp_idx = q.comp_idx; j.comp_flux = q.comp_flux;
+        j.cancel = (const int32_t *)shared->cancel;
         j.slots = (uint64_t *)(ws + o_slots) + so;
         j.lslots = (uint64_t *)(ws + o_lslots) + so;
         j.hslots = nullptr;
@@ -1353,6 +1396,14 @@ int clean_bandwidth_probe(void *buf, size_t bytes, int mode, int reps, double *g
     return CLEAN_OK;
 }
 
+size_t clean_set_workspace_limit(size_t bytes)
+{
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    const size_t old = g_ws_limit;
+    g_ws_limit = bytes;
+    return old;
+}
+
 const char *clean_strerror(int status)
 {
     switch (status) {
@@ -1372,3 +1423,206 @@ const char *clean_last_error(void) { return g_last_error.c_str(); }
 const char *clean_version(void) { return "cleanhip 0.1.0 (gfx950)"; }
 
 } // extern "C"
+
+// ------------------------------------------------------------ plan tuner --
+namespace {
+
+// Cached plans: one line per key, "key<TAB>ty tx interval wg ppt lo hi rate".
+std::mutex g_plan_mu;
+
+std::string plan_key(int dev, int ny, int nx, int psf_ny, int psf_nx, const clean_params *p, int64_t trial_iter,
+                     const int *grids, int n_grids, const int *intervals, int n_intervals, double lo, double hi)
+{
+    hipDeviceProp_t prop{};
+    std::string arch = "unknown";
+    if (hipGetDeviceProperties(&prop, dev) == hipSuccess) arch = std::string(prop.gcnArchName) + "/" + prop.name;
+    for (char &ch : arch)
+        if (ch == '\t' || ch == '\n') ch = ' ';
+    char buf[512];
+    std::snprintf(buf, sizeof buf, "%s|%dx%d|%dx%d|d%d|f%d|g%.17g|t%.17g|m%lld|T%lld|L%.17g|b%.17g,%.17g", arch.c_str(),
+                  ny, nx, psf_ny, psf_nx, p->psf_dtype, p->flags, p->gain, p->threshold, (long long)p->max_iter,
+                  (long long)trial_iter, p->feedback_level, lo, hi);
+    std::string k = buf;
+    k += "|G";
+    for (int i = 0; i < n_grids; ++i) k += std::to_string(grids[2 * i]) + "x" + std::to_string(grids[2 * i + 1]) + ",";
+    k += "|I";
+    for (int i = 0; i < n_intervals; ++i) k += std::to_string(intervals[i]) + ",";
+    return k;
+}
+
+bool plan_lookup(const char *path, const std::string &key, clean_plan *plan)
+{
+    FILE *f = std::fopen(path, "r");
+    if (!f) return false;
+    char line[4096];
+    bool found = false;
+    while (std::fgets(line, sizeof line, f)) {
+        char *tab = std::strchr(line, '\t');
+        if (!tab) continue;
+        *tab = 0;
+        if (key != line) continue;
+        clean_plan q{};
+        if (std::sscanf(tab + 1, "%d %d %d %d %d %lf %lf %lf", &q.tiles_y, &q.tiles_x, &q.interval, &q.wg_per_tile,
+                        &q.px_per_thread, &q.band_min, &q.band_max, &q.iters_per_s) == 8) {
+            q.from_cache = 1;
+            *plan = q;
+            found = true;          // the last line for a key wins
+        }
+    }
+    std::fclose(f);
+    return found;
+}
+
+int plan_store(const char *path, const std::string &key, const clean_plan &q)
+{
+    FILE *f = std::fopen(path, "a");
+    if (!f) return fail(CLEAN_E_INVAL, "cannot open plan cache %s for appending", path);
+    std::fprintf(f, "%s\t%d %d %d %d %d %.17g %.17g %.17g\n", key.c_str(), q.tiles_y, q.tiles_x, q.interval,
+                 q.wg_per_tile, q.px_per_thread, q.band_min, q.band_max, q.iters_per_s);
+    std::fclose(f);
+    return CLEAN_OK;
+}
+
+// Device buffers of the tuner, freed on every exit path.
+struct DevBufs {
+    std::vector<void *> p;
+    ~DevBufs()
+    {
+        for (void *q : p) (void)hipFree(q);
+    }
+    int get(size_t bytes, void **out)
+    {
+        void *q = nullptr;
+        if (hipMalloc(&q, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(CLEAN_E_NOMEM, "tuner buffer of %zu bytes", bytes);
+        }
+        p.push_back(q);
+        *out = q;
+        return CLEAN_OK;
+    }
+};
+
+// Smallest and largest a[i] - b[i] (NaN if any difference is not finite).
+int diff_range(const double *a, const double *b, int64_t n, double *part, int nblk, hipStream_t stream, double &lo,
+               double &hi)
+{
+    hipLaunchKernelGGL(diff_range_kernel, dim3(nblk), dim3(256), 0, stream, a, b, n, part);
+    HIPCHK(hipGetLastError());
+    std::vector<double> h(2 * (size_t)nblk);
+    const D2H rb[1] = {{h.data(), part, h.size() * 8}};
+    int st = read_back(rb, 1, stream);
+    if (st) return st;
+    lo = INFINITY;
+    hi = -INFINITY;
+    for (int i = 0; i < nblk; ++i) {
+        if (std::isnan(h[2 * i]) || std::isnan(h[2 * i + 1])) { lo = hi = NAN; return CLEAN_OK; }
+        lo = std::min(lo, h[2 * i]);
+        hi = std::max(hi, h[2 * i + 1]);
+    }
+    return CLEAN_OK;
+}
+
+} // namespace
+
+extern "C" int clean_autotune_plan(const float *dirty, int ny, int nx, const void *psf, int psf_ny, int psf_nx,
+                                   const int *grids, int n_grids, const int *intervals, int n_intervals,
+                                   const clean_params *p, int64_t trial_iter, double band_min, double band_max,
+                                   const char *cache_path, clean_plan *plan, double *band_out, double *rate_out,
+                                   void *stream_v)
+{
+    g_last_error.clear();
+    if (!dirty || !psf || !p || !plan || !grids || !intervals) return fail(CLEAN_E_INVAL, "NULL argument");
+    if (n_grids < 1 || n_grids > 16 || n_intervals < 1 || n_intervals > 16)
+        return fail(CLEAN_E_INVAL, "need 1..16 tile grids and 1..16 intervals");
+    for (int i = 0; i < n_grids; ++i)
+        if (grids[2 * i] < 1 || grids[2 * i + 1] < 1 || grids[2 * i] > ny || grids[2 * i + 1] > nx ||
+            (grids[2 * i] == 1 && grids[2 * i + 1] == 1) || grids[2 * i] * grids[2 * i + 1] > MAX_TILES)
+            return fail(CLEAN_E_INVAL, "tile grid %d x %d", grids[2 * i], grids[2 * i + 1]);
+    for (int i = 0; i < n_intervals; ++i)
+        if (intervals[i] < 1 || intervals[i] > MAX_INTERVAL) return fail(CLEAN_E_INVAL, "interval %d", intervals[i]);
+    if (trial_iter < 1) return fail(CLEAN_E_INVAL, "trial_iter must be >= 1");
+    if (!(band_min <= 0.0 && band_max >= 0.0)) return fail(CLEAN_E_INVAL, "the band must contain 0");
+    int st = check_common(dirty, ny, nx, psf, psf_ny, psf_nx, p, (float *)dirty, nullptr, nullptr, 0);
+    if (st) return st;
+    hipStream_t stream = (hipStream_t)stream_v;
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    const std::string key = plan_key(dev, ny, nx, psf_ny, psf_nx, p, trial_iter, grids, n_grids, intervals,
+                                     n_intervals, band_min, band_max);
+    *plan = clean_plan{};
+    const int ncand = n_grids * n_intervals;
+    for (int i = 0; i < ncand; ++i) {
+        if (band_out) band_out[2 * i] = band_out[2 * i + 1] = NAN;
+        if (rate_out) rate_out[i] = NAN;
+    }
+    if (cache_path) {
+        std::lock_guard<std::mutex> lk(g_plan_mu);
+        if (plan_lookup(cache_path, key, plan)) return CLEAN_OK;
+    }
+    // the clean beam and the restored plain image of trial_iter iterations
+    int64_t area = 0;
+    double sigma = 0.0;
+    st = clean_beam_fit(psf, psf_ny, psf_nx, p->psf_dtype, &area, &sigma, stream_v);
+    if (st) return st;
+    const int64_t npix = (int64_t)ny * nx;
+    const int64_t n_it = std::min<int64_t>(trial_iter, p->max_iter);
+    const int nblk = 1024;
+    DevBufs B;
+    void *res = nullptr, *idx = nullptr, *flux = nullptr, *model = nullptr, *rest_p = nullptr, *rest_t = nullptr,
+         *part = nullptr;
+    if ((st = B.get((size_t)npix * 4, &res)) || (st = B.get((size_t)std::max<int64_t>(n_it, 1) * 4, &idx)) ||
+        (st = B.get((size_t)std::max<int64_t>(n_it, 1) * 4, &flux)) || (st = B.get((size_t)npix * 8, &model)) ||
+        (st = B.get((size_t)npix * 8, &rest_p)) || (st = B.get((size_t)npix * 8, &rest_t)) ||
+        (st = B.get((size_t)nblk * 16, &part)))
+        return st;
+    clean_params trial = *p;
+    trial.max_iter = n_it;
+    trial.wg_per_tile = 0;
+    trial.px_per_thread = 0;
+    clean_stats sp{};
+    st = run(false, dirty, ny, nx, psf, psf_ny, psf_nx, 1, 1, 1, &trial, (float *)res, (int32_t *)idx, (float *)flux,
+             n_it, (double *)model, nullptr, 0, &sp, stream_v);
+    if (st) return st;
+    st = clean_restore((const double *)model, (const float *)res, ny, nx, sigma, (double *)rest_p, stream_v);
+    if (st) return st;
+    // every (grid, interval): the band of restored(tiled) - restored(plain)
+    clean_plan best{};
+    for (int gi = 0; gi < n_grids; ++gi)
+        for (int ii = 0; ii < n_intervals; ++ii) {
+            clean_stats s{};
+            st = run(true, dirty, ny, nx, psf, psf_ny, psf_nx, grids[2 * gi], grids[2 * gi + 1], intervals[ii], &trial,
+                     (float *)res, (int32_t *)idx, (float *)flux, n_it, (double *)model, nullptr, 0, &s, stream_v);
+            if (st == CLEAN_E_UNSUPPORTED) continue;           // no launch for this grid
+            if (st) return st;
+            st = clean_restore((const double *)model, (const float *)res, ny, nx, sigma, (double *)rest_t, stream_v);
+            if (st) return st;
+            double lo = 0.0, hi = 0.0;
+            st = diff_range((const double *)rest_t, (const double *)rest_p, npix, (double *)part, nblk, stream, lo, hi);
+            if (st) return st;
+            const double rate = s.device_ms > 0.f ? (double)s.n_iter / (s.device_ms * 1e-3) : 0.0;
+            const int ci = gi * n_intervals + ii;
+            if (band_out) { band_out[2 * ci] = lo; band_out[2 * ci + 1] = hi; }
+            if (rate_out) rate_out[ci] = rate;
+            const bool ok = std::isfinite(lo) && std::isfinite(hi) && lo >= band_min && hi <= band_max &&
+                            s.stop_reason != CLEAN_STOP_NONFINITE;
+            if (ok && rate > best.iters_per_s) {
+                best.tiles_y = grids[2 * gi];
+                best.tiles_x = grids[2 * gi + 1];
+                best.interval = intervals[ii];
+                best.wg_per_tile = s.wg_per_tile;
+                best.px_per_thread = s.px_per_thread;
+                best.band_min = lo;
+                best.band_max = hi;
+                best.iters_per_s = rate;
+            }
+        }
+    g_last_error.clear();
+    *plan = best;
+    if (cache_path) {
+        std::lock_guard<std::mutex> lk(g_plan_mu);
+        st = plan_store(cache_path, key, best);
+        if (st) return st;
+    }
+    return CLEAN_OK;
+}

@@ -22,7 +22,9 @@ constexpr int TR_GROUP_WIDE = 4;         // transpose tiles in flight per workgr
 constexpr int TR_LDS_WIDE = TR_GROUP_WIDE * 32 * 33 * 8;
 // (with the tiled kernel's static LDS, two workgroups fit one CU's 160 KB)
 
-enum { STOP_MAXITER = 0, STOP_THRESHOLD = 1, STOP_CAPACITY = 2, STOP_NONFINITE = 4 };
+enum { STOP_MAXITER = 0, STOP_THRESHOLD = 1, STOP_CAPACITY = 2, STOP_CANCELLED = 3, STOP_NONFINITE = 4 };
+constexpr int64_t CANCEL_EVERY = 4096;  // plain: iterations between cancel checkpoints
+constexpr double GATHER_MAX_BYTES = 17592186044416.0;   // 2^44: most PSF bytes one direct-gather round may read
 enum : uint32_t { ABORT_TIMEOUT = 1u };
 
 // Control words: each on its own 128-byte line.
@@ -35,6 +37,8 @@ struct DevCtl {
     uint32_t pad2[31];
     uint32_t seat;          // batched: next seat to hand out
     uint32_t pad3[31];
+    uint32_t cancel;        // tiled: the caller's cancel flag as read before the last grid barrier
+    uint32_t pad4[31];
 };
 
 struct DevStat {
@@ -67,6 +71,7 @@ struct PlainJob {
     float *comp_flux;
     uint64_t *slots;        // [2][slot_pad] device-scope exchange slots
     uint64_t *lslots;       // [2][slot_pad] XCD-local exchange slots (batched), else null
+    const int32_t *cancel;  // the caller's cancel flag (host memory), or null
     uint64_t *hslots;       // [2][8 * hpad + 32] two-level exchange slots (plain, large clusters), else null
     int hpad;               // slots per XCD of the two-level exchange
     DevStat *dstat;
@@ -118,6 +123,7 @@ struct KArgs {
     uint64_t timeout_ticks;
     int32_t *comp_idx;
     float *comp_flux;
+    const int32_t *cancel;  // the caller's cancel flag (host memory), or null
     // workspace
     DevCtl *ctl;
     DevStat *dstat;

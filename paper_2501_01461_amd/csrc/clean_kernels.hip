@@ -55,6 +55,11 @@ __device__ __forceinline__ void st_agent(uint64_t *p, uint64_t v)
 {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+// The caller's cancel flag, a word of host memory (system scope: not cached).
+__device__ __forceinline__ uint32_t host_flag(const int32_t *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) != 0 ? 1u : 0u;
+}
 
 // A store that ends in this XCD's L2 (sc0: written through the CU's L1, not
 // on to the point of coherence of all XCDs as a device-scope store is).  A
@@ -1187,6 +1192,16 @@ template <class Tile> __device__ bool run_plain(const PlainJob &j_arg, int rank_
         // peak (eq. 1): value and position from the cluster's key
         const float v = key_value(cur);
         if (n == j.max_iter) { stop = STOP_MAXITER; break; }
+        if (j.cancel && n % CANCEL_EVERY == 0) {
+            // cancel checkpoint: rank 0 reads the caller's flag and the
+            // cluster takes the max, so every member stops at the same n
+            const uint64_t vote = rank == 0 && threadIdx.x == 0 && host_flag(j.cancel) ? (1ull << 33) : 0ull;
+            uint64_t got;
+            if (!(two ? cluster_reduce_xcd2(y, j.hslots, j.hpad, j.cs, rank, e++, vote, got)
+                      : cluster_reduce(y, j.slots, ls, j.slot_pad, j.cs, rank, e++, vote, got)))
+                return false;
+            if (got) { stop = STOP_CANCELLED; break; }
+        }
         if (!__builtin_isfinite(v)) { stop = STOP_NONFINITE; break; }
         if ((double)fabsf(v) < j.threshold) { stop = STOP_THRESHOLD; break; }
         if (n == j.cap) { stop = STOP_CAPACITY; break; }
@@ -1231,6 +1246,7 @@ template <class Tile> __global__ void __launch_bounds__(WG) hogbom_kernel(const 
     j.ny = a.ny; j.nx = a.nx; j.psf_nx = a.psf_nx; j.cy = a.cy; j.cx = a.cx;
     j.gain = a.gain; j.threshold = a.threshold; j.max_iter = a.max_iter; j.cap = a.cap;
     j.comp_idx = a.comp_idx; j.comp_flux = a.comp_flux;
+    j.cancel = a.cancel;
     j.slots = a.xslots; j.lslots = nullptr; j.slot_pad = a.slot_pad; j.cs = a.cs;
     j.hslots = a.hslots; j.hpad = a.hpad;
     j.dstat = a.dstat; j.partial = a.partial;
@@ -2099,6 +2115,8 @@ tiled_kernel(const KArgs a)
         if (!cluster_reduce(y, slots, lslots, a.slot_pad, cs, rank, e++, R.key(im), cur)) return;
         if (tile_leader_wg && threadIdx.x == 0) stc(&a.tile_key[tile], cur);
     }
+    // the caller's cancel flag, seen by every workgroup after the barrier
+    if (a.cancel && blockIdx.x == 0 && threadIdx.x == 0) stc(&a.ctl->cancel, host_flag(a.cancel));
     if (!grid_barrier(y, epoch, &s_ok)) return;
     if constexpr (FFT) {
         if (!fft_spectrum<PT, Tile::kWide>(a, y, epoch, &s_ok)) return;
@@ -2121,6 +2139,7 @@ tiled_kernel(const KArgs a)
         if (vbits) atomicMax(&s_vmax, vbits);
         __syncthreads();
         const bool nonfinite = s_vmax >= 0x7F800000u;
+        const bool cancelled = a.cancel && ldc(&a.ctl->cancel) != 0u;
         const double level = nonfinite ? 0.0 : a.level_frac * (double)__uint_as_float(s_vmax);
         int na_part = 0, rk_part = 0;
         for (int t = threadIdx.x; t < T; t += WG) {
@@ -2132,6 +2151,7 @@ tiled_kernel(const KArgs a)
         const int na = wg_sum_int(na_part, &s_tmp);
         const int my_rank = wg_sum_int(rk_part, &s_tmp);
         if (used == a.max_iter) { stop = STOP_MAXITER; break; }
+        if (cancelled) { stop = STOP_CANCELLED; break; }
         if (nonfinite) { stop = STOP_NONFINITE; break; }
         if (na == 0) { stop = STOP_THRESHOLD; break; }
         if (used == a.cap) { stop = STOP_CAPACITY; break; }
@@ -2332,6 +2352,7 @@ tiled_kernel(const KArgs a)
             if (tile_leader_wg && threadIdx.x == 0) stc(&a.tile_key[tile], cur);
         }
         rounds += 1;
+        if (a.cancel && blockIdx.x == 0 && threadIdx.x == 0) stc(&a.ctl->cancel, host_flag(a.cancel));
         if (!grid_barrier(y, epoch, &s_ok)) return;                        // C
         if (blockIdx.x == 0) { tp1 = wall_clock64(); ph_apply += tp1 - tp0; }
     }

@@ -38,4 +38,32 @@ __global__ void __launch_bounds__(256) restore_cols_kernel(const double *tmp, co
     }
 }
 
+// Per block: the smallest and largest a[i] - b[i] of its grid-stride share
+// (NaN in both when any difference is NaN), to part[2 * block], part[2 * block + 1].
+__global__ void __launch_bounds__(256) diff_range_kernel(const double *a, const double *b, int64_t n, double *part)
+{
+    __shared__ double s_lo[256], s_hi[256];
+    double lo = INFINITY, hi = -INFINITY;
+    bool nan = false;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const double d = a[i] - b[i];
+        nan = nan || d != d;
+        lo = fmin(lo, d);
+        hi = fmax(hi, d);
+    }
+    s_lo[threadIdx.x] = nan ? NAN : lo;
+    s_hi[threadIdx.x] = nan ? NAN : hi;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double l = s_lo[0], h = s_hi[0];
+        for (int t = 1; t < 256; ++t) {
+            if (s_lo[t] != s_lo[t] || l != l) { l = NAN; h = NAN; continue; }
+            l = fmin(l, s_lo[t]);
+            h = fmax(h, s_hi[t]);
+        }
+        part[2 * blockIdx.x] = l;
+        part[2 * blockIdx.x + 1] = h;
+    }
+}
+
 } // namespace cleanhip

@@ -168,3 +168,59 @@ def test_autotune_argument_errors(lib):
                               None) == INVAL
     assert lib.clean_autotune(FAKE, 16, 16, FAKE, 32, 32, 1, 1, 1, C.byref(p), FAKE, FAKE, FAKE, 10, 0,
                               C.byref(best), None) == INVAL
+
+
+def test_autotune_plan_argument_errors(lib):
+    p = params()
+    plan = N.Plan()
+    grids = (C.c_int * 4)(2, 2, 4, 4)
+    ivs = (C.c_int * 2)(10, 50)
+
+    def call(g=grids, ng=2, iv=ivs, ni=2, trial=100, lo=-0.1, hi=0.1, pp=p, out=plan, ny=16, nx=16):
+        return lib.clean_autotune_plan(FAKE, ny, nx, FAKE, 2 * ny, 2 * nx, C.cast(g, C.c_void_p) if g else None, ng,
+                                       C.cast(iv, C.c_void_p) if iv else None, ni, C.byref(pp) if pp else None,
+                                       trial, lo, hi, None, C.byref(out) if out is not None else None, None, None,
+                                       None)
+    assert call(g=None) == INVAL
+    assert call(iv=None) == INVAL
+    assert call(ng=0) == INVAL
+    assert call(ni=17) == INVAL
+    assert call(g=(C.c_int * 2)(1, 1), ng=1) == INVAL          # 1 x 1 is plain CLEAN
+    assert call(g=(C.c_int * 2)(20, 2), ng=1) == INVAL         # more tile rows than image rows
+    assert call(iv=(C.c_int * 1)(0), ni=1) == INVAL
+    assert call(trial=0) == INVAL
+    assert call(lo=0.05) == INVAL                              # the band must contain 0
+    assert call(hi=-0.01) == INVAL
+    assert call(pp=None) == INVAL
+    assert call(out=None) == INVAL
+    assert call(ny=0) == INVAL
+
+
+def test_bandwidth_probe_argument_errors(lib):
+    g = C.c_double(0.0)
+    assert lib.clean_bandwidth_probe(None, 1 << 20, 0, 10, C.byref(g), None) == INVAL
+    assert lib.clean_bandwidth_probe(FAKE, 1 << 20, 0, 10, None, None) == INVAL
+    assert lib.clean_bandwidth_probe(FAKE, 100, 0, 10, C.byref(g), None) == INVAL
+    assert lib.clean_bandwidth_probe(FAKE, (1 << 20) + 4, 0, 10, C.byref(g), None) == INVAL
+    assert lib.clean_bandwidth_probe(FAKE, 1 << 20, 2, 10, C.byref(g), None) == INVAL
+    assert lib.clean_bandwidth_probe(FAKE, 1 << 20, 0, 0, C.byref(g), None) == INVAL
+
+
+def test_workspace_limit_get_set(lib):
+    assert lib.clean_set_workspace_limit(1 << 20) == 0
+    assert lib.clean_set_workspace_limit(0) == 1 << 20
+    assert lib.clean_set_workspace_limit(0) == 0
+
+
+def test_direct_gather_that_cannot_finish_is_refused(lib):
+    """16384^2 in 16 x 16 tiles at interval 100: one round of the direct
+    gather could read 25600 components x 2.7e8 pixels x 4 B = 2.7e13 bytes;
+    refused before any device call.  The FFT form, or 4096^2 in 8 x 8 tiles
+    at interval 1000 (4.2e12 bytes), pass the check (and then fail here only
+    for want of a GPU)."""
+    assert tiled(lib, ty=16, tx=16, interval=100, ny=16384, nx=16384) == UNSUPPORTED
+    assert b"CLEAN_FLAG_FFT_FEEDBACK" in lib.clean_last_error()
+    assert tiled(lib, ty=16, tx=16, interval=200, ny=16384, nx=16384, p=params(psf_dtype=1)) == UNSUPPORTED
+    assert tiled(lib, ty=16, tx=16, interval=100, ny=16384, nx=16384,
+                 p=params(flags=N.FLAG_FFT_FEEDBACK)) not in (INVAL, UNSUPPORTED)
+    assert tiled(lib, ty=8, tx=8, interval=1000, ny=4096, nx=4096) not in (INVAL, UNSUPPORTED)
