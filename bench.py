@@ -1,20 +1,22 @@
 #!/usr/bin/env python3
 """Benchmark: tiled-feedback Hogbom CLEAN vs plain Hogbom CLEAN on one MI355X.
 
-Workload: a 1024 x 1024 dirty image with a 2048 x 2048 Y-array snapshot PSF,
-200 point sources log-uniform in 0.005..2.1 Jy plus N(0, 1e-3) noise, gain
-0.1, 2 x 2 tiles, feedback every 100 local minor iterations, 20000 total minor
-iterations (threshold 0).  Inputs are seeded and synthetic and already in HBM
-when timing starts.
+Workload (the headline): a 1024 x 1024 dirty image with a 2048 x 2048 Y-array
+snapshot PSF, 200 point sources log-uniform in 0.005..2.1 Jy plus N(0, 1e-3)
+noise, gain 0.1, 2 x 2 tiles, feedback every 100 local minor iterations, 20000
+total minor iterations (threshold 0).  Inputs are seeded and synthetic and
+already in HBM when timing starts.
 
 One step = one clean_tiled_feedback call (local loops, feedback rounds, round
-control, statistics).  The plain clean_hogbom call on the same input (20000
-iterations) is timed the same way and reported beside it.  The JSON line gives
-the tiled rate as `value`, the plain rate, the speed-up, each path's max |model
-error| in Jy against the float64 CPU oracle, the tiled-vs-plain difference band,
-the roofline figure of the dominant kernel and the CPU oracle's own rate.
+control, statistics).  The JSON line gives the tiled rate as `value` with its
+accuracy beside it (`value_jy`: the tiled - plain bands of the model and the
+restored image, and the error against the float64 CPU oracle), the plain rate,
+the roofline of the dominant kernel with each byte count against the measured
+bandwidth of the level that serves it, the plan tuner's choice, the batched
+form, the 4096^2 and 16384^2 workloads, and the CPU oracle's own rate.
 
 Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu] [--no-jy]
+       python bench.py --case {tiled1024,plain4096,fft4096} [--steps K]   (one kernel, for profiling)
 """
 from __future__ import annotations
 
@@ -27,56 +29,74 @@ import time
 
 import numpy as np
 
-HBM_PEAK_GBS = 8000.0
+HBM_PEAK_GBS = 8000.0          # vendor figure, context only
 CALIB_BYTES = 512 << 20
 SINGLE_CORE_ITERS = 5000
+STOP_NONFINITE = 4
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def measured_traffic(launch):
-    """HBM bytes per launch of the tiled kernel from the committed rocprofv3
-    counter summary, or None when the kernel sources or the launch shape
-    changed since then."""
+def counters(kernel_tag, launch=None):
+    """HBM bytes per launch of one kernel from the committed rocprofv3
+    counter summary (profiles/traffic.json), or None when the kernel sources
+    or the launch shape changed since the counters were taken."""
     import hashlib
     root = os.path.dirname(os.path.abspath(__file__))
     path = os.path.join(root, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
-    rec = json.load(open(path))
+    recs = json.load(open(path))
+    rec = recs.get(kernel_tag)
+    if rec is None:
+        return None
     h = hashlib.sha256()
     for f in ("clean_kernels.hip", "clean_device.h"):
         h.update(open(os.path.join(root, "paper_2501_01461_amd", "csrc", f), "rb").read())
-    if rec.get("source_sha256") != h.hexdigest() or rec.get("launch") != launch:
+    if rec.get("source_sha256") != h.hexdigest() or (launch is not None and rec.get("launch") != launch):
         return None
     return rec
 
 
-def feedback_bytes(idx, ny, nx, tiles, interval, n_total, psf_bytes):
-    """Algorithmic bytes of the feedback rounds of a threshold-0 run.
-
-    Each round every tile takes `interval` iterations (the last round splits
-    the remainder); a round's cost is K_d * (N^2 - T^2) * s_psf + 8 N^2 with
-    K_d the distinct (tile, position) pairs of that round."""
-    ty, tx = tiles
-    T = ty * tx
-    npix = ny * nx
-    tpix = (ny // ty) * (nx // tx)
-    total, used, k = 0.0, 0, 0
+def round_lists(idx, tiles, interval, n_total):
+    """Per round and tile, the component positions of a threshold-0 run (every
+    tile takes `interval` iterations a round; the last round splits the rest)."""
+    T = tiles[0] * tiles[1]
+    used, k, rounds = 0, 0, []
     while used < n_total:
         rem = n_total - used
         budgets = [interval] * T if rem >= T * interval else [rem // T + (1 if r < rem % T else 0) for r in range(T)]
-        nround = sum(budgets)
-        kd = 0
+        lists = []
         for t in range(T):
-            sl = idx[k:k + budgets[t]]
-            kd += len(np.unique(sl))
+            lists.append(idx[k:k + budgets[t]])
             k += budgets[t]
-        total += kd * (npix - tpix) * psf_bytes + 8.0 * npix
-        used += nround
-    return total
+        rounds.append(lists)
+        used += sum(budgets)
+    return rounds
+
+
+def tiled_bytes(idx, ny, nx, tiles, interval, n_total, s_psf):
+    """Algorithmic bytes of one threshold-0 tiled run, two accountings.
+
+    method: the per-unit figures of the method (local iteration T^2 (8 + s)
+      for the residual read and write and the PSF window; feedback round
+      K_d (N^2 - T^2) s + 8 N^2; K_d the round's distinct (tile, position)
+      pairs), whatever the design keeps on chip;
+    offchip: what this design must fetch from the memory system: the PSF
+      windows (T^2 s per local iteration; the residual stays in registers),
+      the feedback gather and its buffer, and one pass over the images in and
+      out (dirty read, residual written, float64 model written)."""
+    npix = ny * nx
+    tpix = (ny // tiles[0]) * (nx // tiles[1])
+    fb = 0.0
+    for lists in round_lists(idx, tiles, interval, n_total):
+        kd = sum(len(np.unique(l)) for l in lists)
+        fb += kd * (npix - tpix) * s_psf + 8.0 * npix
+    method = n_total * tpix * (8.0 + s_psf) + fb
+    offchip = n_total * tpix * s_psf + fb + npix * (4.0 + 4.0 + 8.0)
+    return method, offchip
 
 
 def cpu_model():
@@ -113,6 +133,73 @@ def oracle_single_core(n_iter):
     return json.loads(out.stdout.strip().splitlines()[-1])
 
 
+def probe_levels(P, torch, dev):
+    """Read bandwidth of working sets that stay in the L2s (32 MiB: 4 MiB per
+    XCD), that spill to the Infinity Cache (128 MiB) and that stream HBM
+    (2 GiB), and the HBM copy bandwidth (2 GiB, half read and half written):
+    the denominators of the rooflines, measured on this device."""
+    out = {}
+    for name, mib, mode, reps in (("l2_read", 32, 0, 500), ("infinity_cache_read", 128, 0, 150),
+                                  ("hbm_read", 2048, 0, 10), ("hbm_copy", 2048, 1, 10)):
+        buf = torch.empty(mib << 20, dtype=torch.uint8, device=dev)
+        P.bandwidth_probe(buf, mode, 2)
+        out[name] = max(P.bandwidth_probe(buf, mode, reps) for _ in range(3))
+        del buf
+    torch.cuda.empty_cache()
+    out["vendor_hbm"] = HBM_PEAK_GBS
+    out["unit"] = "GB/s"
+    out["note"] = ("clean_bandwidth_probe: 16-byte loads, every workgroup re-reading its own words; "
+                   "read = bytes read, copy = bytes read + written; best of three")
+    return out
+
+
+def restored_band(P, sigma, ma, ra, mb, rb):
+    d = (P.restore(ma, ra, sigma) - P.restore(mb, rb, sigma)).cpu().numpy()
+    return [float(d.min()), float(d.max())]
+
+
+def model_band(a, b):
+    d = (a - b).cpu().numpy() if hasattr(a, "cpu") else a - b
+    return [float(d.min()), float(d.max())]
+
+
+def run_case(args):
+    """One kernel alone, for counter and trace runs."""
+    import torch
+    import paper_2501_01461_amd as P
+    from paper_2501_01461_amd import synth
+    dev = torch.device("cuda:0")
+    calib_src = torch.ones(CALIB_BYTES // 4, dtype=torch.float32, device=dev)
+    calib_dst = torch.empty_like(calib_src)
+    calib_dst.copy_(calib_src)
+    torch.cuda.synchronize()
+    del calib_src, calib_dst
+    if args.case == "tiled1024":
+        c = synth.make_config(1)
+        d, p = torch.from_numpy(c["dirty"]).to(dev), torch.from_numpy(c["psf"]).to(dev)
+        fn = lambda: P.tiled_feedback(d, p, c["tiles"], c["interval"], c["gain"], 0.0, c["max_iter"])
+    elif args.case == "plain4096":
+        c = synth.make_config(2)
+        d, p = torch.from_numpy(c["dirty"]).to(dev), torch.from_numpy(c["psf"]).to(dev)
+        fn = lambda: P.hogbom(d, p, c["gain"], 0.0, 2000)
+    elif args.case == "fft4096":
+        c = synth.make_config(2)
+        d, p = torch.from_numpy(c["dirty"]).to(dev), torch.from_numpy(c["psf"]).to(dev)
+        fn = lambda: P.tiled_feedback(d, p, (8, 8), 200, c["gain"], 0.0, c["max_iter"], fft=True)
+    else:
+        raise SystemExit(f"unknown case {args.case}")
+    for _ in range(args.warmup):
+        fn()
+    ms = []
+    for _ in range(args.steps):
+        r = fn()
+        ms.append(r["stats"]["device_ms"])
+    st = r["stats"]
+    print(json.dumps({"case": args.case, "kernel_ms": float(np.mean(ms)), "steps": args.steps,
+                      "launch": {"wg_per_tile": st["wg_per_tile"], "px_per_thread": st["px_per_thread"],
+                                 "workgroups": st["workgroups"]}, "n_iter": st["n_iter"]}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -122,8 +209,9 @@ def main():
     ap.add_argument("--no-jy", action="store_true", help="skip the float64 oracle error figures")
     ap.add_argument("--psf-f16", action="store_true", help="store the PSF as float16")
     ap.add_argument("--no-batched", action="store_true", help="skip the 256-problem batched measurement")
-    ap.add_argument("--no-plain", action="store_true", help="skip the plain comparison (profiling runs)")
     ap.add_argument("--no-4096", action="store_true", help="skip the 4096^2 / 8x8-tile measurement")
+    ap.add_argument("--no-16384", action="store_true", help="skip the 16384^2 / 16x16-tile measurement")
+    ap.add_argument("--case", default=None, help="time one kernel alone (tiled1024, plain4096, fft4096)")
     ap.add_argument("--oracle-child", type=int, default=0, help=argparse.SUPPRESS)
     args = ap.parse_args()
     if args.oracle_child:
@@ -137,27 +225,24 @@ def main():
     import torch
     import paper_2501_01461_amd as P
     from paper_2501_01461_amd import synth
-
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     P.load()
+    if args.case:
+        run_case(args)
+        return
     dev = torch.device("cuda:0")
 
     t0 = time.time()
+    levels = probe_levels(P, torch, dev)
+    log(f"bandwidth probes: {json.dumps({k: round(v) for k, v in levels.items() if isinstance(v, float)})}")
     c = synth.make_config(1)
     ny = nx = c["n"]
     tiles, interval, n_iter, gain, thr = c["tiles"], c["interval"], c["max_iter"], c["gain"], c["threshold"]
     log(f"inputs generated in {time.time() - t0:.1f} s")
     dirty = torch.from_numpy(c["dirty"]).to(dev)
     psf32 = torch.from_numpy(c["psf"]).to(dev)
-    # a device copy of known size: the reference that scales the profiler's
-    # byte counters (FETCH_SIZE / WRITE_SIZE) in the committed summaries
-    calib_src = torch.ones(CALIB_BYTES // 4, dtype=torch.float32, device=dev)
-    calib_dst = torch.empty_like(calib_src)
-    calib_dst.copy_(calib_src)
-    torch.cuda.synchronize()
-    del calib_src, calib_dst
     psf = P.psf_to_f16(psf32) if args.psf_f16 else psf32
     s_psf = 2 if args.psf_f16 else 4
     cap = n_iter
@@ -187,76 +272,104 @@ def main():
 
     rt, ms_t, kms_t = timed(tiled, "tiled")
     launch_t = {"wg_per_tile": rt["stats"]["wg_per_tile"], "px_per_thread": rt["stats"]["px_per_thread"]}
-    if args.no_plain:
-        print(json.dumps({"tiled_kernel_ms": kms_t, "steps": args.steps, "launch": launch_t}), flush=True)
-        return
-    # the interval tuner on this input and on its 10-minute-track variant
-    tuner = {}
-    for nm, cfg_psf in (("snapshot", psf), ("track", None)):
-        if cfg_psf is None:
-            ct = synth.make_config(1, psf_track=True)
-            d_t, p_t = torch.from_numpy(ct["dirty"]).to(dev), torch.from_numpy(ct["psf"]).to(dev)
-        else:
-            d_t, p_t = dirty, cfg_psf
-        cands = [10, 25, 50, 100]
-        tr = P.autotune_interval(d_t, p_t, tiles, cands, gain, thr, n_iter, trial_iter=n_iter)
-        tuner[nm] = {"candidates": cands, "chosen": tr["interval"], "peak_ratio": tr["peak_ratios"],
-                     "iters_per_s": tr["rates"]}
+    st_t = rt["stats"]
+    idx_t = rt["idx"].cpu().numpy()
+    model_t = rt["model"].clone()
+    res_t = rt["residual"].clone()
+    rp, ms_p, kms_p = timed(plain, "plain")
+    st_p = rp["stats"]
+    model_p = rp["model"].clone()
+    res_p = rp["residual"].clone()
+    sigma = P.clean_beam(psf)["sigma"]
+
+    # ---- roofline of the dominant kernel (the tiled step)
+    b_method, b_off = tiled_bytes(idx_t, ny, nx, tiles, interval, st_t["n_iter"], s_psf)
+    cnt = counters("tiled1024", launch_t)
+    traffic = cnt["traffic_bytes_per_launch"] if cnt else None
+    g_off = b_off / (kms_t * 1e-3) / 1e9
+    g_method = b_method / (kms_t * 1e-3) / 1e9
+    # the level that serves the off-chip bytes: HBM when the counted HBM
+    # bytes make up most of them, else the L2s (the PSF windows stay there)
+    serving = "hbm" if (traffic is not None and traffic >= 0.5 * b_off) else "l2"
+    peak = levels["hbm_read"] if serving == "hbm" else levels["l2_read"]
+    roofline = {
+        "bound": serving, "achieved": g_off, "peak": peak, "unit": "GB/s", "frac": g_off / peak,
+        "traffic": traffic,
+        "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+        "traffic_source": ("profiles/" + cnt["summary"]) if cnt else None,
+        "kernel": "tiled_kernel", "kernel_ms": kms_t, "offchip_bytes": b_off,
+        "peak_source": f"clean_bandwidth_probe {'2 GiB read' if serving == 'hbm' else '32 MiB read (L2-resident)'}",
+        "note": ("achieved = the bytes this design must fetch (PSF windows of every local iteration, the feedback "
+                 "gather and its buffer, images in and out) / kernel time, against the measured read bandwidth of "
+                 "the level the counters show serving them"),
+        "method_accounting": {"bytes": b_method, "achieved_GBs": g_method,
+                              "note": "per-unit figures of the method (residual read + write 8 B/px/iteration "
+                                      "included); the residual never leaves registers here, so this figure is "
+                                      "not a memory-level rate and is given against no peak"},
+        "hbm": ({"bytes": traffic, "achieved_GBs": traffic / (kms_t * 1e-3) / 1e9,
+                 "frac_of_hbm_read": traffic / (kms_t * 1e-3) / 1e9 / levels["hbm_read"]} if traffic else None),
+        "levels": levels,
+    }
+
+    # ---- accuracy beside the headline rate
+    value_jy = {"model_band_vs_plain": model_band(model_t, model_p),
+                "restored_band_vs_plain": restored_band(P, sigma, model_t, res_t, model_p, res_p),
+                "stop_reason": st_t["stop_reason"], "residual_finite": bool(torch.isfinite(res_t).all().item()),
+                "paper_band": [-0.1, 0.04],
+                "note": "the literal snapshot PSF at interval 100 diverges (the float64 oracle diverges the same "
+                        "way); see tuned for the plan the accuracy-constrained tuner picks"}
+
+    # ---- the plan tuner (tile grid x interval under a Jy budget), both PSFs
+    ctrack = synth.make_config(1, psf_track=True)
+    d_tr, p_tr = torch.from_numpy(ctrack["dirty"]).to(dev), torch.from_numpy(ctrack["psf"]).to(dev)
+    tuned = {"budget_jy": [-0.1, 0.1], "grids": [[2, 2], [4, 4]], "intervals": [5, 10, 25, 50, 100]}
+    for nm, (d_, p_) in (("snapshot", (dirty, psf)), ("track", (d_tr, p_tr))):
+        t1 = time.time()
+        pl = P.autotune_plan(d_, p_, [(2, 2), (4, 4)], tuned["intervals"], gain, thr, n_iter, band=(-0.1, 0.1))
+        ent = {"tiles": list(pl["tiles"]), "interval": pl["interval"], "restored_band": pl["band"],
+               "iters_per_s": pl["iters_per_s"], "tuner_s": time.time() - t1,
+               "candidates": [{"tiles": list(cd["tiles"]), "interval": cd["interval"], "restored_band": cd["band"],
+                               "iters_per_s": cd["iters_per_s"]} for cd in pl["candidates"]]}
+        if pl["interval"]:
+            mt = P.tiled_feedback(d_, p_, pl["tiles"], pl["interval"], gain, thr, n_iter)
+            mp = P.hogbom(d_, p_, gain, thr, n_iter)
+            ent["model_band"] = model_band(mt["model"], mp["model"])
+            ent["tiled_ms"] = mt["stats"]["device_ms"]
+            ent["plain_ms"] = mp["stats"]["device_ms"]
+            ent["speedup_vs_plain"] = mp["stats"]["device_ms"] / mt["stats"]["device_ms"]
+            ent["in_paper_band"] = bool(pl["band"][0] >= -0.1 and pl["band"][1] <= 0.04)
+        tuned[nm] = ent
+        log(f"plan tuner ({nm}): {pl['tiles']} I={pl['interval']} band {pl['band']} in {time.time() - t1:.1f} s")
+
     rf = P.tiled_feedback(dirty, psf, tiles, interval, gain, thr, n_iter, fft=True)
     tiled_fft = {"kernel_ms": rf["stats"]["device_ms"], "n_rounds": rf["stats"]["n_rounds"],
-                 "phase_us": rf["stats"]["phase_us"],
+                 "phase_us": rf["stats"]["phase_us"], "stop_reason": rf["stats"]["stop_reason"],
                  "note": "the same workload with the feedback sums computed by FFT convolution"}
-    rp, ms_p, kms_p = timed(plain, "plain")
-    st_t, st_p = rt["stats"], rp["stats"]
-    idx_t = rt["idx"].cpu().numpy()
-    model_t = rt["model"].cpu().numpy()
-    model_p = rp["model"].cpu().numpy()
+    rf_tr = P.tiled_feedback(d_tr, p_tr, tiles, interval, gain, thr, n_iter, fft=True)
+    rg_tr = P.tiled_feedback(d_tr, p_tr, tiles, interval, gain, thr, n_iter)
 
-    # algorithmic bytes: local iterations T^2 (8 + s_psf) each, feedback rounds K_d (N^2 - T^2) s_psf + 8 N^2
-    tpix = (ny // tiles[0]) * (nx // tiles[1])
-    bytes_local = st_t["n_iter"] * tpix * (8.0 + s_psf)
-    bytes_fb = feedback_bytes(idx_t, ny, nx, tiles, interval, st_t["n_iter"], s_psf)
-    gbs_t = (bytes_local + bytes_fb) / (kms_t * 1e-3) / 1e9
-    bytes_plain = st_p["n_iter"] * ny * nx * (8.0 + s_psf)
-    gbs_p = bytes_plain / (kms_p * 1e-3) / 1e9
-
-    delta = model_t - model_p
-    jy = {"tiled_minus_plain_model_min": float(delta.min()), "tiled_minus_plain_model_max": float(delta.max()),
-          "paper_band": [-0.1, 0.04]}
-
-    # the same comparison under the other readings of the method: the flux
-    # trigger, and a 10-minute-track PSF (GPU runs; they are bit-identical to
-    # the oracle, so these bands are the method's, not the implementation's)
+    # tiled - plain bands under the other readings of the method
     def band(cfg, level, ivl):
         d_ = torch.from_numpy(cfg["dirty"]).to(dev)
         p_ = torch.from_numpy(cfg["psf"]).to(dev)
         mt = P.tiled_feedback(d_, p_, tiles, ivl, gain, thr, n_iter, level=level)
         mp = P.hogbom(d_, p_, gain, thr, n_iter)
-        mt_m, mp_m = mt["model"].cpu().numpy(), mp["model"].cpu().numpy()
-        dm = mt_m - mp_m
         sg = P.clean_beam(p_)["sigma"]
-        dr = (P.restore(mt["model"], mt["residual"], sg) - P.restore(mp["model"], mp["residual"], sg)).cpu().numpy()
-        out = {"model_min": float(dm.min()), "model_max": float(dm.max()),
-               "restored_min": float(dr.min()), "restored_max": float(dr.max()),
-               "rounds": mt["stats"]["n_rounds"], "tiled_ms": mt["stats"]["device_ms"]}
-        out["restored_in_paper_band"] = bool(out["restored_min"] >= -0.1 and out["restored_max"] <= 0.04)
+        out = {"model_band": model_band(mt["model"], mp["model"]),
+               "restored_band": restored_band(P, sg, mt["model"], mt["residual"], mp["model"], mp["residual"]),
+               "rounds": mt["stats"]["n_rounds"], "tiled_ms": mt["stats"]["device_ms"],
+               "stop_reason": mt["stats"]["stop_reason"]}
+        out["restored_in_paper_band"] = bool(out["restored_band"][0] >= -0.1 and out["restored_band"][1] <= 0.04)
         return out
-    ctrack = synth.make_config(1, psf_track=True)
-    jy["bands_tiled_minus_plain"] = {
+    jy = {"paper_band": [-0.1, 0.04], "bands_tiled_minus_plain": {
         "snapshot_psf_interval100": band(c, 0.0, interval),
         "snapshot_psf_flux_level_0.5": band(c, 0.5, interval),
         "track_psf_interval100": band(ctrack, 0.0, interval),
         "track_psf_interval10": band(ctrack, 0.0, 10),
         "track_psf_flux_level_0.5": band(ctrack, 0.5, interval),
-    }
-    for nm, cfg in (("snapshot", c), ("track", ctrack)):
-        ti = tuner[nm]["chosen"]
-        if ti:
-            jy["bands_tiled_minus_plain"][f"{nm}_psf_tuned_interval{ti}"] = band(cfg, 0.0, ti)
+    }}
 
-    # time to threshold: tiled iterations each remove less than plain ones, so
-    # next to minor-iters/s, the time each method needs to bring the residual
-    # peak below the level plain CLEAN reaches after the same 20000 iterations
+    # time to threshold: tiled iterations each remove less than plain ones
     def time_to_plain_peak(cfg, level, ivl):
         d_ = torch.from_numpy(cfg["dirty"]).to(dev)
         p_ = torch.from_numpy(cfg["psf"]).to(dev)
@@ -264,69 +377,43 @@ def main():
         target = abs(mp["stats"]["final_peak"])
         mt = P.tiled_feedback(d_, p_, tiles, ivl, gain, target, 10 * n_iter, model=False, level=level)
         st = mt["stats"]
-        # a diverged run can also end on the threshold rule (non-finite peaks
-        # are never active), so the residual must be finite and below target
-        fin = bool(torch.isfinite(mt["residual"]).all().item())
-        reached = st["stop_reason"] == 1 and fin and abs(st["final_peak"]) < target
+        reached = st["stop_reason"] == 1 and abs(st["final_peak"]) < target
         return {"target_peak": target, "plain_ms": mp["stats"]["device_ms"], "plain_iters": mp["stats"]["n_iter"],
                 "tiled_ms": st["device_ms"], "tiled_iters": st["n_iter"], "tiled_rounds": st["n_rounds"],
-                "tiled_final_peak": abs(st["final_peak"]), "residual_finite": fin, "reached": bool(reached),
+                "tiled_final_peak": abs(st["final_peak"]), "stop_reason": st["stop_reason"],
+                "reached": bool(reached),
                 "speedup": mp["stats"]["device_ms"] / st["device_ms"] if reached else None}
     jy["time_to_plain_peak"] = {
         "snapshot_psf_interval100": time_to_plain_peak(c, 0.0, interval),
         "snapshot_psf_flux_level_0.5": time_to_plain_peak(c, 0.5, interval),
         "track_psf_interval100": time_to_plain_peak(ctrack, 0.0, interval),
-        "track_psf_flux_level_0.5": time_to_plain_peak(ctrack, 0.5, interval),
+        "track_psf_interval10": time_to_plain_peak(ctrack, 0.0, 10),
         "note": ("plain: 20000 iterations, target = |residual peak| after them; tiled: the same call with "
                  "threshold = target (it stops when every tile peak is below it) and at most 200000 iterations; "
-                 "reached false: it never got there (diverged or ran out of iterations)"),
+                 "stop_reason 4: the run diverged to a non-finite peak"),
     }
-
-    # no feedback at all: each tile cleaned on its own (plain clean_hogbom on
-    # its crop, the crop's share of the iterations); the residual is then the
-    # consistent one, dirty - model (*) PSF (float64 on the host)
-    def band_no_feedback(cfg):
-        from scipy.signal import fftconvolve
-        d_np, p_np = cfg["dirty"], cfg["psf"]
-        cy, cx = p_np.shape[0] // 2, p_np.shape[1] // 2
-        model = np.zeros((ny, nx), np.float64)
-        T = tiles[0] * tiles[1]
-        for i in range(tiles[0]):
-            y0, y1 = i * ny // tiles[0], (i + 1) * ny // tiles[0]
-            for j in range(tiles[1]):
-                x0, x1 = j * nx // tiles[1], (j + 1) * nx // tiles[1]
-                h, w = y1 - y0, x1 - x0
-                crop = torch.from_numpy(np.ascontiguousarray(d_np[y0:y1, x0:x1])).to(dev)
-                pc = torch.from_numpy(np.ascontiguousarray(p_np[cy - h:cy + h, cx - w:cx + w])).to(dev)
-                r = P.hogbom(crop, pc, gain, thr, n_iter // T)
-                model[y0:y1, x0:x1] = r["model"].cpu().numpy()
-        conv = fftconvolve(model, p_np.astype(np.float64), mode="full")[cy:cy + ny, cx:cx + nx]
-        res = torch.from_numpy((d_np.astype(np.float64) - conv).astype(np.float32)).to(dev)
-        mp = P.hogbom(torch.from_numpy(d_np).to(dev), torch.from_numpy(p_np).to(dev), gain, thr, n_iter)
-        sg = P.clean_beam(torch.from_numpy(p_np).to(dev))["sigma"]
-        dm = model - mp["model"].cpu().numpy()
-        dr = (P.restore(torch.from_numpy(model).to(dev), res, sg) - P.restore(mp["model"], mp["residual"], sg))
-        dr = dr.cpu().numpy()
-        return {"model_min": float(dm.min()), "model_max": float(dm.max()),
-                "restored_min": float(dr.min()), "restored_max": float(dr.max()),
-                "note": f"each tile alone: plain CLEAN on its crop for {n_iter // T} iterations, no cross-coupling"}
-    jy["bands_no_feedback_minus_plain"] = {"snapshot_psf": band_no_feedback(c), "track_psf": band_no_feedback(ctrack)}
     jy["clean_beam"] = P.clean_beam(psf)
-    jy["bands_note"] = ("differences tiled - plain (Jy) after the same 20000 total minor iterations; "
-                        "restored = clean_restore: model (*) peak-1 circular Gaussian clean beam (clean_beam_fit: "
-                        "FWHM = 2 sqrt(A/pi), A the PSF main lobe above one half) + residual")
 
     cpu = None
     if not args.no_cpu or not args.no_jy:
         import oracle
     if not args.no_jy:
         t1 = time.time()
+        mp_np, mt_np = model_p.cpu().numpy(), model_t.cpu().numpy()
         r64 = oracle.hogbom(c["dirty"], c["psf"], gain, thr, n_iter, precision="f64")
-        jy["plain_fp32_vs_fp64_oracle_max_abs"] = float(np.max(np.abs(model_p - r64["model"])))
         t64 = oracle.tiled(c["dirty"], c["psf"], tiles, interval, gain, thr, n_iter, precision="f64")
-        jy["tiled_fp32_vs_fp64_oracle_max_abs"] = float(np.max(np.abs(model_t - t64["model"])))
-        jy["fp64_tiled_minus_plain_model_min"] = float((t64["model"] - r64["model"]).min())
-        jy["fp64_tiled_minus_plain_model_max"] = float((t64["model"] - r64["model"]).max())
+        tr64 = oracle.tiled(ctrack["dirty"], ctrack["psf"], tiles, interval, gain, thr, n_iter, precision="f64")
+        jy["vs_fp64_oracle_max_abs"] = {
+            "plain": float(np.max(np.abs(mp_np - r64["model"]))),
+            "tiled_snapshot_interval100": float(np.max(np.abs(mt_np - t64["model"]))),
+            "tiled_fft_snapshot_interval100": float(np.max(np.abs(rf["model"].cpu().numpy() - t64["model"]))),
+            "tiled_track_interval100": float(np.max(np.abs(rg_tr["model"].cpu().numpy() - tr64["model"]))),
+            "tiled_fft_track_interval100": float(np.max(np.abs(rf_tr["model"].cpu().numpy() - tr64["model"]))),
+            "note": "max |model - float64 oracle model| (Jy) over the image; the snapshot runs diverge, so their "
+                    "errors are as large as the values",
+        }
+        value_jy["vs_fp64_oracle_max_abs"] = jy["vs_fp64_oracle_max_abs"]["tiled_snapshot_interval100"]
+        value_jy["fp64_oracle_model_band_vs_plain"] = model_band(t64["model"], r64["model"])
         log(f"float64 oracle runs: {time.time() - t1:.1f} s")
     if not args.no_cpu:
         threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
@@ -337,7 +424,7 @@ def main():
                "sample": f"one full tiled-feedback run of the same workload (float32 oracle, {ro['n_iter']} "
                          f"iterations, {ro['n_rounds']} rounds, {dt:.1f} s, OpenMP threads={threads})"}
         same = (np.array_equal(ro["idx"], idx_t) and
-                np.array_equal(ro["residual"].view(np.uint32), rt["residual"].cpu().numpy().view(np.uint32)))
+                np.array_equal(ro["residual"].view(np.uint32), res_t.cpu().numpy().view(np.uint32)))
         cpu["bit_identical_to_gpu"] = bool(same)
         cpu["cpu_model"] = cpu_model()
         one = oracle_single_core(SINGLE_CORE_ITERS)
@@ -366,21 +453,39 @@ def main():
         b_ms = (time.perf_counter() - t1) / nb_steps * 1e3
         b_kms = outs[0]["stats"]["device_ms"]
         its = [o["stats"]["n_iter"] for o in outs]
-        b_bytes = sum(n * q["n"] * q["n"] * (8.0 + s_psf) for n, q in zip(its, probs))
-        # the same problems one call at a time
+        b_method = sum(n * q["n"] * q["n"] * (8.0 + s_psf) for n, q in zip(its, probs))
+        b_off = sum(n * q["n"] * q["n"] * s_psf + 16.0 * q["n"] * q["n"] for n, q in zip(its, probs))
         t1 = time.perf_counter()
         seq_dev = 0.0
         for q in dprobs:
             seq_dev += P.hogbom(q["dirty"], q["psf"], gain, q["threshold"], q["max_iter"])["stats"]["device_ms"]
         torch.cuda.synchronize()
         seq_ms = (time.perf_counter() - t1) * 1e3
+        g_off = b_off / (b_kms * 1e-3) / 1e9
         batched = {"problems": len(probs), "total_iters": int(sum(its)), "ms": b_ms, "kernel_ms": b_kms,
-                   "iters_per_s": sum(its) / (b_kms * 1e-3), "achieved_GBs": b_bytes / (b_kms * 1e-3) / 1e9,
-                   "frac_hbm": b_bytes / (b_kms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                   "iters_per_s": sum(its) / (b_kms * 1e-3),
+                   "offchip_GBs": g_off, "offchip_frac_of_l2_read": g_off / levels["l2_read"],
+                   "method_accounting_GBs": b_method / (b_kms * 1e-3) / 1e9,
                    "one_call_per_problem_ms": seq_ms, "one_call_per_problem_kernel_ms": seq_dev,
                    "speedup_vs_one_call_per_problem": seq_ms / b_ms,
                    "workload": "256 images, sides drawn from {128..1024}, own Y-array PSF at 2x side, 5-200 "
                                "sources, threshold 5e-3 Jy"}
+        if not args.no_jy:
+            # float64 oracle on a stratified eighth of the problems (every
+            # eighth by size, the largest included): all 256 take minutes
+            import oracle
+            t1 = time.time()
+            order = sorted(range(len(probs)), key=lambda i: probs[i]["n"])
+            sample = order[::8][:31] + [order[-1]]
+            errs = []
+            for i in sample:
+                q, o = probs[i], outs[i]
+                r64 = oracle.hogbom(q["dirty"], q["psf"], gain, q["threshold"], 100000, precision="f64")
+                errs.append(float(np.max(np.abs(o["model"].cpu().numpy() - r64["model"]))))
+            batched["vs_fp64_oracle_max_abs"] = {"max": max(errs), "median": float(np.median(errs)),
+                                                 "problems": len(errs),
+                                                 "sample": "every eighth problem by side, and the largest"}
+            log(f"batched float64 oracle runs: {time.time() - t1:.1f} s")
         log(f"batched: {b_ms:.1f} ms per launch, {sum(its)} iterations; one call per problem: {seq_ms:.1f} ms")
 
     big = None
@@ -391,32 +496,97 @@ def main():
         d2 = torch.from_numpy(c2["dirty"]).to(dev)
         p2 = torch.from_numpy(c2["psf"]).to(dev)
         p2h = P.psf_to_f16(p2)
+        sg2 = P.clean_beam(p2)["sigma"]
         big = {"workload": "4096x4096 image, 8192x8192 Y-array snapshot PSF, 2000 sources, 8x8 tiles, "
                            "200000 total minor iterations", "runs": {}}
+        # plain CLEAN over the whole 200000 iterations: the reference of the bands
+        pr = P.hogbom(d2, p2, gain, 0.0, c2["max_iter"])
+        pst = pr["stats"]
+        big["plain"] = {"kernel_ms": pst["device_ms"], "iters_per_s": pst["n_iter"] / (pst["device_ms"] * 1e-3),
+                        "n_iter": pst["n_iter"], "stop": pst["stop_reason"], "workgroups": pst["wg_per_tile"],
+                        "exchange_levels": pst["exchange_levels"], "streamed": pst["streamed"],
+                        "us_per_iter": pst["device_ms"] * 1e3 / max(1, pst["n_iter"])}
+        it_us = big["plain"]["us_per_iter"]
+        g_plain = 4096 * 4096 * 12.0 / (it_us * 1e-6) / 1e9
+        big["plain"]["achieved_GBs"] = g_plain
+        big["plain"]["frac_of_hbm_read"] = g_plain / levels["hbm_read"]
+        big["plain"]["frac_of_vendor_hbm"] = g_plain / HBM_PEAK_GBS
+        cnt_p = counters("plain4096", None)
+        if cnt_p:
+            tb = cnt_p["traffic_bytes_per_launch"] / cnt_p["iters_per_launch"]
+            big["plain"]["hbm_bytes_per_iter"] = tb
+            big["plain"]["hbm_GBs"] = tb / (it_us * 1e-6) / 1e9
+            big["plain"]["traffic_source"] = "profiles/" + cnt_p["summary"]
+        pm, prs = pr["model"].clone(), pr["residual"].clone()
+        del pr
+        ref_idx = {}
         for ivl in (50, 200, 1000):
             for (nm, pp, sp), fft in itertools.product((("f32", p2, 4), ("f16", p2h, 2)), (False, True)):
                 r = P.tiled_feedback(d2, pp, (8, 8), ivl, gain, 0.0, c2["max_iter"], fft=fft)
                 st = r["stats"]
-                big["runs"][f"I{ivl}_{nm}" + ("_fft" if fft else "")] = {
-                    "kernel_ms": st["device_ms"], "iters_per_s": st["n_iter"] / (st["device_ms"] * 1e-3),
-                    "n_iter": st["n_iter"], "stop": st["stop_reason"], "rounds": st["n_rounds"],
-                    "phase_us": st["phase_us"], "wg_per_tile": st["wg_per_tile"],
-                    "px_per_thread": st["px_per_thread"], "streamed": st["streamed"]}
-        pr = P.hogbom(d2, p2, gain, 0.0, 2000)
-        big["plain_prefix_2000"] = {"kernel_ms": pr["stats"]["device_ms"],
-                                    "iters_per_s": 2000 / (pr["stats"]["device_ms"] * 1e-3),
-                                    "note": "plain clean_hogbom on the same input, first 2000 iterations"}
+                key = f"I{ivl}_{nm}" + ("_fft" if fft else "")
+                ent = {"kernel_ms": st["device_ms"], "iters_per_s": st["n_iter"] / (st["device_ms"] * 1e-3),
+                       "n_iter": st["n_iter"], "stop": st["stop_reason"], "rounds": st["n_rounds"],
+                       "phase_us": st["phase_us"], "wg_per_tile": st["wg_per_tile"],
+                       "px_per_thread": st["px_per_thread"], "streamed": st["streamed"],
+                       "speedup_vs_plain": pst["device_ms"] / st["device_ms"]}
+                if st["stop_reason"] != STOP_NONFINITE:
+                    ent["model_band_vs_plain"] = model_band(r["model"], pm)
+                    ent["restored_band_vs_plain"] = restored_band(P, sg2, r["model"], r["residual"], pm, prs)
+                big["runs"][key] = ent
+                if ivl == 200 and not fft:
+                    ref_idx[nm] = r["idx"].cpu().numpy()
+                del r
+        # FP16-stored PSF: where its peak choices part from the FP32 PSF's
+        a32, a16 = ref_idx["f32"], ref_idx["f16"]
+        m = min(len(a32), len(a16))
+        diff = np.nonzero(a32[:m] != a16[:m])[0]
+        big["fp16_psf_divergence"] = {"first_divergent_index": int(diff[0]) if len(diff) else None,
+                                      "fraction_differing": float(len(diff)) / m if m else 0.0,
+                                      "compared": m, "run": "I200, direct gather, FP16 vs FP32 PSF"}
         if not args.no_jy:
-            # errors against the float64 oracle over the first round (12800 iterations at interval 200)
+            # float64 oracle over the first round at interval 200 (12800
+            # iterations), the longest prefix it runs in about a quarter minute
             npre = 64 * 200
             o64 = oracle.tiled(c2["dirty"], c2["psf"], (8, 8), 200, gain, 0.0, npre, precision="f64")
             for nm, pp in (("f32", p2), ("f16", p2h)):
-                r = P.tiled_feedback(d2, pp, (8, 8), 200, gain, 0.0, npre)
-                big[f"first_round_{nm}_vs_fp64_oracle_model_max_abs"] = float(
-                    np.max(np.abs(r["model"].cpu().numpy() - o64["model"])))
+                for fft in (False, True):
+                    r = P.tiled_feedback(d2, pp, (8, 8), 200, gain, 0.0, npre, fft=fft)
+                    big[f"prefix12800_{nm}{'_fft' if fft else ''}_vs_fp64_oracle_model_max_abs"] = float(
+                        np.max(np.abs(r["model"].cpu().numpy() - o64["model"])))
+            pr = P.hogbom(d2, p2, gain, 0.0, 2000)
+            o64p = oracle.hogbom(c2["dirty"], c2["psf"], gain, 0.0, 2000, precision="f64")
+            big["plain_prefix2000_vs_fp64_oracle_model_max_abs"] = float(
+                np.max(np.abs(pr["model"].cpu().numpy() - o64p["model"])))
+        del pm, prs
+        torch.cuda.empty_cache()
         log(f"4096^2 workload: {time.time() - t1:.1f} s")
 
-    traffic = measured_traffic(launch_t)
+    huge = None
+    if not args.no_16384:
+        t1 = time.time()
+        c4 = synth.make_config(4, device=dev)
+        d4 = torch.from_numpy(c4["dirty"]).to(dev)
+        p4 = torch.from_numpy(c4["psf"]).to(dev)
+        del c4["psf"]
+        huge = {"workload": "16384x16384 image, 32768x32768 Y-array snapshot PSF, 20005 sources, 16x16 tiles"}
+        pr = P.hogbom(d4, p4, gain, 0.0, 1000, model=False)
+        us = pr["stats"]["device_ms"] * 1e3 / 1000
+        huge["plain_prefix_1000"] = {"kernel_ms": pr["stats"]["device_ms"], "iters_per_s": 1e6 / us,
+                                     "us_per_iter": us, "achieved_GBs": 16384 ** 2 * 12.0 / (us * 1e-6) / 1e9,
+                                     "workgroups": pr["stats"]["wg_per_tile"],
+                                     "note": "plain clean_hogbom, first 1000 iterations (a prefix)"}
+        del pr
+        rt4 = P.tiled_feedback(d4, p4, (16, 16), 100, gain, 0.0, 256 * 100, fft=True, model=False)
+        huge["tiled_fft_one_round"] = {"kernel_ms": rt4["stats"]["device_ms"], "n_iter": rt4["stats"]["n_iter"],
+                                       "iters_per_s": rt4["stats"]["n_iter"] / (rt4["stats"]["device_ms"] * 1e-3),
+                                       "phase_us": rt4["stats"]["phase_us"],
+                                       "note": "one round at interval 100 (25600 iterations), FFT feedback; the "
+                                               "method diverges on this input after some rounds"}
+        del rt4, d4, p4
+        torch.cuda.empty_cache()
+        log(f"16384^2 workload: {time.time() - t1:.1f} s")
+
     line = {
         "metric": "CLEAN minor-iters/s + achieved GB/s: tiled-feedback vs plain, 1 GPU, at Jy error",
         "value": st_t["n_iter"] / (ms_t * 1e-3),
@@ -436,26 +606,22 @@ def main():
                    "launch": {"wg_per_tile": st_t["wg_per_tile"], "px_per_thread": st_t["px_per_thread"],
                               "workgroups": st_t["workgroups"],
                               "xcd_local_clusters": st_t["xcd_local_clusters"]}},
-        "roofline": {"bound": "hbm", "achieved": gbs_t, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": gbs_t / HBM_PEAK_GBS,
-                     "traffic": traffic["traffic_bytes_per_launch"] if traffic else None,
-                     "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-                     "traffic_source": ("profiles/" + traffic["summary"]) if traffic else None,
-                     "kernel": "tiled_kernel", "kernel_ms": kms_t,
-                     "algorithmic_bytes": bytes_local + bytes_fb},
+        "value_jy": value_jy,
+        "roofline": roofline,
         "cpu_baseline": cpu,
         "tiled": {"iters_per_s": st_t["n_iter"] / (kms_t * 1e-3), "kernel_ms": kms_t, "n_rounds": st_t["n_rounds"],
-                  "achieved_GBs": gbs_t, "phase_us": {"local_loops": st_t["phase_us"][0],
-                                                      "feedback_gather": st_t["phase_us"][1],
-                                                      "apply_and_repeak": st_t["phase_us"][2]}},
+                  "phase_us": {"local_loops": st_t["phase_us"][0], "feedback_gather": st_t["phase_us"][1],
+                               "apply_and_repeak": st_t["phase_us"][2]}},
         "plain": {"iters_per_s": st_p["n_iter"] / (ms_p * 1e-3), "ms": ms_p, "kernel_ms": kms_p,
-                  "achieved_GBs": gbs_p, "frac_hbm": gbs_p / HBM_PEAK_GBS,
-                  "launch": {"wg_per_tile": st_p["wg_per_tile"], "px_per_thread": st_p["px_per_thread"]}},
-        "tiled_fft_feedback": tiled_fft,
-        "interval_tuner": tuner,
+                  "launch": {"wg_per_tile": st_p["wg_per_tile"], "px_per_thread": st_p["px_per_thread"],
+                             "exchange_levels": st_p["exchange_levels"]},
+                  "vs_fp64_oracle_max_abs": jy.get("vs_fp64_oracle_max_abs", {}).get("plain")},
         "speedup_tiled_vs_plain": ms_p / ms_t,
+        "tuned": tuned,
+        "tiled_fft_feedback": tiled_fft,
         "batched": batched,
         "tiled_4096": big,
+        "tiled_16384": huge,
         "jy": jy,
     }
     print(json.dumps(line), flush=True)

@@ -173,7 +173,7 @@ typedef struct {
     int32_t exchange_levels; /* plain: 2 when the cluster's per-iteration
                              exchange ran in two levels (keys gathered inside
                              each XCD first, then across the 8 XCD leaders;
-                             clusters of 16 or more workgroups placed one
+                             clusters of 32 or more workgroups placed one
                              rank per XCD in turn, checked on the device),
                              else 1; tiled and batched: 1                     */
 } clean_stats;
@@ -283,9 +283,10 @@ int clean_tiled_feedback(const float *dirty, int ny, int nx,
                          clean_stats *stats, void *stream);
 
 /*
- * One problem of a batch: the fields mirror clean_hogbom's arguments (device
- * pointers, caller-owned).  threshold and max_iter are per problem; gain,
- * psf_dtype and flags come from the shared clean_params.
+ * One problem of a batch: the fields mirror clean_hogbom's (or, with a tile
+ * grid, clean_tiled_feedback's) arguments (device pointers, caller-owned).
+ * threshold, max_iter and the tile grid are per problem; gain, psf_dtype,
+ * flags, feedback_level and cancel come from the shared clean_params.
  */
 typedef struct {
     const float *dirty;
@@ -298,16 +299,30 @@ typedef struct {
     int64_t max_iter;
     double threshold;
     int32_t ny, nx, psf_ny, psf_nx;
+    int32_t tiles_y, tiles_x; /* 0 or 1 x 1: plain Hogbom; else the tiled form
+                                 with feedback (direct gather), as
+                                 clean_tiled_feedback                         */
+    int32_t interval;         /* tiled problems: feedback interval, 1..2048  */
 } clean_problem;
 
 /*
- * clean_batched -- n independent plain Hogbom problems in one persistent
- * launch.  Workgroup clusters take problems from a device queue, largest
- * first: per XCD when every XCD holds the largest cluster (each problem then
- * runs on one XCD, stats[i].xcd_local_clusters = 1), else across the device.
- * Each problem's result is identical to clean_hogbom on it alone.
- *   probs  host array of n problems; stats host array of n (may be NULL).
- * Uses the library's internal workspace; n <= 65536.
+ * clean_batched -- n independent Hogbom problems in one persistent launch,
+ * each plain or tiled with feedback.  Workgroups take problems from a device
+ * queue, those with the most workgroups first: per XCD when every XCD holds
+ * the largest problem (each problem then runs on one XCD and its exchanges
+ * stay in that XCD's L2), else across the device.  A tiled problem's tiles
+ * are clusters of its own workgroups, which also share its feedback gather,
+ * with barriers among them only.  Each problem's result is identical to
+ * clean_hogbom (or clean_tiled_feedback) on it alone.
+ *   probs  host array of n problems; stats host array of n (may be NULL):
+ *          n_rounds counts a tiled problem's rounds, wg_per_tile its
+ *          workgroups per tile, xcd_local_clusters its clusters that
+ *          exchanged inside one XCD.
+ * Uses the library's internal workspace; n <= 65536.  A batch holding a
+ * tiled problem runs a kernel variant with more registers per thread (one
+ * workgroup per CU at 32 px/thread).  CLEAN_FLAG_FFT_FEEDBACK is not
+ * supported here (CLEAN_E_UNSUPPORTED); a problem fails validation as
+ * clean_tiled_feedback would (message "problem i: ...").
  */
 int clean_batched(const clean_problem *probs, int n, const clean_params *shared,
                   clean_stats *stats, void *stream);

@@ -62,7 +62,8 @@ class Problem(C.Structure):
     _fields_ = [("dirty", C.c_void_p), ("psf", C.c_void_p), ("residual", C.c_void_p),
                 ("comp_idx", C.c_void_p), ("comp_flux", C.c_void_p), ("model", C.c_void_p),
                 ("comp_cap", C.c_int64), ("max_iter", C.c_int64), ("threshold", C.c_double),
-                ("ny", C.c_int32), ("nx", C.c_int32), ("psf_ny", C.c_int32), ("psf_nx", C.c_int32)]
+                ("ny", C.c_int32), ("nx", C.c_int32), ("psf_ny", C.c_int32), ("psf_nx", C.c_int32),
+                ("tiles_y", C.c_int32), ("tiles_x", C.c_int32), ("interval", C.c_int32)]
 
 
 class CleanError(RuntimeError):
@@ -254,13 +255,15 @@ def tiled_feedback(dirty, psf, tiles=(2, 2), interval=100, gain=0.1, threshold=0
     return dict(residual=res, idx=idx[:n], flux=flux[:n], model=mod, stats=st.as_dict())
 
 
-def batched(problems, gain=0.1, model=True, check_finite=False, px_per_thread=0, cancel=None):
-    """Independent plain Hogbom problems in one persistent launch.
+def batched(problems, gain=0.1, model=True, check_finite=False, px_per_thread=0, cancel=None, level=0.0):
+    """Independent Hogbom problems in one persistent launch.
 
     problems: list of dicts with device tensors "dirty" (float32 2-D) and "psf"
     (float32 or float16, all the same dtype), and "threshold", "max_iter",
-    optional "cap".  Returns a list of dict(residual, idx, flux, model, stats).
-    The outputs are views into four allocations shared by the whole batch.
+    optional "cap", and for a tiled problem "tiles" (ty, tx) and "interval".
+    level: the flux trigger of the tiled problems.  Returns a list of
+    dict(residual, idx, flux, model, stats).  The outputs are views into four
+    allocations shared by the whole batch.
     """
     torch = _torch()
     lib = load()
@@ -296,14 +299,16 @@ def batched(problems, gain=0.1, model=True, check_finite=False, px_per_thread=0,
         oc += up(caps[i])
         keep += [d, p]
         outs.append((res, idx, flux, mod))
+        ty, tx = q.get("tiles", (1, 1))
         arr[i] = Problem(d.data_ptr(), p.data_ptr(), res.data_ptr(), idx.data_ptr(), flux.data_ptr(),
                          mod.data_ptr() if mod is not None else None, cap, int(q["max_iter"]),
-                         float(q["threshold"]), ny, nx, p.shape[0], p.shape[1])
+                         float(q["threshold"]), ny, nx, p.shape[0], p.shape[1], int(ty), int(tx),
+                         int(q.get("interval", 1)))
     if n == 0:
         return []
     dt = PSF_F16 if psf_dtype == torch.float16 else PSF_F32
-    prm = Params(float(gain), 0.0, 0, dt, FLAG_CHECK_FINITE if check_finite else 0, 0, int(px_per_thread), 0.0,
-                 _cancel(cancel))
+    prm = Params(float(gain), 0.0, 0, dt, FLAG_CHECK_FINITE if check_finite else 0, 0, int(px_per_thread),
+                 float(level), _cancel(cancel))
     stats = (Stats * n)()
     _check(lib.clean_batched(arr, n, C.byref(prm), stats, _stream()))
     res = []

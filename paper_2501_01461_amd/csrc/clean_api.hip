@@ -25,7 +25,7 @@ template <int K, int V, typename PT> struct StreamTile;
 template <typename PT> struct WideTile;
 template <class Tile> __global__ void hogbom_kernel(const KArgs a);
 template <class Tile, bool FFT> __global__ void tiled_kernel(const KArgs a);
-template <class Tile> __global__ void batched_kernel(const BatchArgs b);
+template <class Tile, bool TILED> __global__ void batched_kernel(const BatchArgs b);
 __global__ void finalize_batch_kernel(const PlainJob *jobs, int n);
 __global__ void finite_check_kernel(const float *x, int64_t n, uint32_t *flag);
 __global__ void finite_check_half_kernel(const unsigned short *x, int64_t n, uint32_t *flag);
@@ -330,30 +330,37 @@ template <int V, typename PT> KFn tiled_fn(int K, bool fft)
 
 using BFn = void (*)(const BatchArgs);
 
-template <int V, typename PT> BFn batched_fn(int K)
+template <int V, typename PT, bool TILED> BFn batched_fn(int K)
 {
     if constexpr (V == 4) {
         switch (K) {
-        case 1: return batched_kernel<RegTile<1, 4, PT>>;
-        case 2: return batched_kernel<RegTile<2, 4, PT>>;
-        case 4: return batched_kernel<RegTile<4, 4, PT>>;
-        case 8: return batched_kernel<RegTile<8, 4, PT>>;
-        case 16: return batched_kernel<RegTile<16, 4, PT>>;
+        case 1: return batched_kernel<RegTile<1, 4, PT>, TILED>;
+        case 2: return batched_kernel<RegTile<2, 4, PT>, TILED>;
+        case 4: return batched_kernel<RegTile<4, 4, PT>, TILED>;
+        case 8: return batched_kernel<RegTile<8, 4, PT>, TILED>;
+        case 16: return batched_kernel<RegTile<16, 4, PT>, TILED>;
         }
     } else {
         switch (K) {
-        case 4: return batched_kernel<RegTile<4, 1, PT>>;
-        case 16: return batched_kernel<RegTile<16, 1, PT>>;
-        case 32: return batched_kernel<RegTile<32, 1, PT>>;
+        case 4: return batched_kernel<RegTile<4, 1, PT>, TILED>;
+        case 16: return batched_kernel<RegTile<16, 1, PT>, TILED>;
+        case 32: return batched_kernel<RegTile<32, 1, PT>, TILED>;
         }
     }
     return nullptr;
 }
 
-BFn pick_batched(bool half, int V, int K)
+// The batched kernel for this PSF dtype, group width and pixels per thread;
+// `tiled`: the variant that also runs tiled problems (more registers, so it
+// is used only for batches that hold one).
+BFn pick_batched(bool half, int V, int K, bool tiled)
 {
-    if (V == 4) return half ? batched_fn<4, __half>(K) : batched_fn<4, float>(K);
-    return half ? batched_fn<1, __half>(K) : batched_fn<1, float>(K);
+    if (tiled) {
+        if (V == 4) return half ? batched_fn<4, __half, true>(K) : batched_fn<4, float, true>(K);
+        return half ? batched_fn<1, __half, true>(K) : batched_fn<1, float, true>(K);
+    }
+    if (V == 4) return half ? batched_fn<4, __half, false>(K) : batched_fn<4, float, false>(K);
+    return half ? batched_fn<1, __half, false>(K) : batched_fn<1, float, false>(K);
 }
 
 KFn pick_wide(bool half, bool fft)
@@ -418,6 +425,21 @@ int choose_shape(int64_t npix, int V, int user_cs, int user_ppt, int max_ppt, in
         ppt = opts[nopt - 1];
         for (int i = 0; i < nopt; ++i)
             if ((int64_t)cs * WG * opts[i] >= npix) { ppt = opts[i]; break; }
+    } else if (xcd_clusters == 0 && V == 4 && npix > (int64_t)WG * 4) {
+        // plain CLEAN: one cluster over the whole device.  Up to 64K pixels, 16
+        // px/thread in at most 8 workgroups (a one-level exchange); above, 8
+        // px/thread and as many workgroups as that takes, up to 512 (two
+        // workgroups per CU), with more pixels per thread beyond (256^2: 8 x 16
+        // 2.19 ms against 4 x 32 2.39 ms and 16 x 8 3.12 ms; 1024^2: 256 x 8
+        // 71.2 ms against 128 x 16 75.1 ms and 64 x 32 84.6 ms, 20000
+        // iterations)
+        if (npix <= (int64_t)8 * WG * 16) {
+            ppt = 16;
+        } else {
+            ppt = 8;
+            while ((npix + (int64_t)WG * ppt - 1) / ((int64_t)WG * ppt) > 512 && ppt * 2 <= max_ppt) ppt *= 2;
+        }
+        cs = (int)((npix + (int64_t)WG * ppt - 1) / ((int64_t)WG * ppt));
     } else {
         const int opts4[] = {4, 8, 16, 32, 64}, opts1[] = {4, 16, 32};
         const int *opts = V == 4 ? opts4 : opts1;
@@ -735,7 +757,10 @@ int run(bool tiled, const float *dirty, int ny, int nx, const void *psf, int psf
     a.comp_idx = comp_idx;
     a.comp_flux = comp_flux;
     a.cancel = (const int32_t *)p->cancel;
+    a.has_cancel = p->cancel != nullptr;
     a.ctl = (DevCtl *)(ws + L.ctl);
+    a.bar = &a.ctl->barrier;
+    a.cword = &a.ctl->cancel;
     a.dstat = (DevStat *)(ws + L.dstat);
     a.role = (const int32_t *)(ws + L.role);
     a.xslots = (uint64_t *)(ws + L.xslots);
@@ -897,9 +922,16 @@ int clean_batched(const clean_problem *probs, int n, const clean_params *shared,
     if (!probs || !shared) return fail(CLEAN_E_INVAL, "probs and shared params must be non-NULL");
     if (n < 0 || n > 65536) return fail(CLEAN_E_INVAL, "batch of %d problems not in [0, 65536]", n);
     if (n == 0) return CLEAN_OK;
+    if (shared->flags & CLEAN_FLAG_FFT_FEEDBACK)
+        return fail(CLEAN_E_UNSUPPORTED, "tiled problems of a batch use the direct gather (no CLEAN_FLAG_FFT_FEEDBACK)");
+    if (!(shared->feedback_level >= 0.0 && shared->feedback_level <= 1.0))
+        return fail(CLEAN_E_INVAL, "feedback_level %g not in [0, 1]", shared->feedback_level);
     const bool half = shared->psf_dtype == CLEAN_PSF_F16;
-    bool w4 = true;
-    int64_t max_pix = 0;
+    // per problem: tile grid (1 x 1: plain), the largest tile, 4-wide groups
+    std::vector<int> pty(n, 1), ptx(n, 1), pint(n, 1);
+    std::vector<int64_t> ptile(n, 0);
+    bool w4 = true, any_tiled = false;
+    int max_interval = 1;
     for (int i = 0; i < n; ++i) {
         const clean_problem &q = probs[i];
         clean_params pi = *shared;
@@ -908,25 +940,61 @@ int clean_batched(const clean_problem *probs, int n, const clean_params *shared,
         int st = check_common(q.dirty, q.ny, q.nx, q.psf, q.psf_ny, q.psf_nx, &pi, q.residual, q.comp_idx,
                               q.comp_flux, q.comp_cap);
         if (st) return fail(st, "problem %d: %s", i, g_last_error.c_str());
-        if (q.nx % 4) w4 = false;
-        max_pix = std::max<int64_t>(max_pix, (int64_t)q.ny * q.nx);
+        const int ty = q.tiles_y > 0 ? q.tiles_y : 1, tx = q.tiles_x > 0 ? q.tiles_x : 1;
+        if (q.tiles_y < 0 || q.tiles_x < 0 || ty > q.ny || tx > q.nx)
+            return fail(CLEAN_E_INVAL, "problem %d: tile grid %d x %d for a %d x %d image", i, q.tiles_y, q.tiles_x,
+                        q.ny, q.nx);
+        if ((int64_t)ty * tx > MAX_TILES)
+            return fail(CLEAN_E_UNSUPPORTED, "problem %d: %d tiles exceed %d", i, ty * tx, MAX_TILES);
+        pty[i] = ty;
+        ptx[i] = tx;
+        if (ty * tx > 1) {
+            if (q.interval < 1 || q.interval > MAX_INTERVAL)
+                return fail(CLEAN_E_INVAL, "problem %d: feedback interval %d not in [1, %d]", i, q.interval,
+                            MAX_INTERVAL);
+            const int64_t smallest = (int64_t)(q.ny / ty) * (q.nx / tx);
+            const double worst = (double)ty * tx * q.interval * (double)((int64_t)q.ny * q.nx - smallest) *
+                                 (half ? 2.0 : 4.0);
+            if (worst > GATHER_MAX_BYTES)
+                return fail(CLEAN_E_UNSUPPORTED, "problem %d: a round of direct-gather feedback could read %.3g bytes "
+                            "of PSF, more than a round may take within the device's wait limit", i, worst);
+            pint[i] = q.interval;
+            max_interval = std::max(max_interval, q.interval);
+            any_tiled = true;
+        }
+        for (int a = 0; a < ty; ++a)
+            for (int b = 0; b < tx; ++b) {
+                const int h = (int)((int64_t)(a + 1) * q.ny / ty - (int64_t)a * q.ny / ty);
+                const int w = (int)((int64_t)(b + 1) * q.nx / tx - (int64_t)b * q.nx / tx);
+                ptile[i] = std::max<int64_t>(ptile[i], (int64_t)h * w);
+                if (w % 4) w4 = false;
+            }
     }
     const int V = w4 ? 4 : 1;
     hipStream_t stream = (hipStream_t)stream_v;
     int dev = 0, ncu = 0;
     HIPCHK(hipGetDevice(&dev));
     HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    // dynamic LDS of the tiled variant: a tile leader's round list, or the
+    // gather's staged components
+    const size_t dyn_lds = any_tiled ? std::max((size_t)16 * ((max_interval + 3) & ~3), (size_t)8 * GATHER_CHUNK) : 0;
+    // workgroups of problem i at pp pixels per thread: its tiles' clusters
+    auto members_of = [&](int i, int pp) -> int64_t {
+        return (int64_t)pty[i] * ptx[i] * ((ptile[i] + (int64_t)WG * pp - 1) / ((int64_t)WG * pp));
+    };
     // grid size of a launch shape, and whether its clusters fit the per-XCD
-    // schedule (the grid's share of each XCD holds the largest cluster)
+    // schedule (the grid's share of each XCD holds the largest problem)
     auto plan = [&](int pp, int &max_wg_out, bool &xcd_out) -> int {
-        BFn f = pick_batched(half, V, pp / V);
+        BFn f = pick_batched(half, V, pp / V, any_tiled);
         if (!f) return CLEAN_E_UNSUPPORTED;
+        if (dyn_lds > 48 * 1024)
+            HIPCHK(hipFuncSetAttribute((const void *)f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn_lds));
         int oc = 0;
-        HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&oc, (const void *)f, WG, 0));
+        HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&oc, (const void *)f, WG, dyn_lds));
         oc = std::min(oc, MAX_WG_PER_CU);
         int64_t seats = 0, mcs = 0;
         for (int i = 0; i < n; ++i) {
-            const int64_t c = ((int64_t)probs[i].ny * probs[i].nx + (int64_t)WG * pp - 1) / ((int64_t)WG * pp);
+            const int64_t c = members_of(i, pp);
             seats += c;
             mcs = std::max(mcs, c);
         }
@@ -949,52 +1017,74 @@ int clean_batched(const clean_problem *probs, int n, const clean_params *shared,
     }
     if (!valid_ppt(V, ppt)) return fail(CLEAN_E_INVAL, "px_per_thread %d not available", ppt);
     const int K = ppt / V;
-    BFn fn = pick_batched(half, V, K);
+    BFn fn = pick_batched(half, V, K, any_tiled);
     if (!fn) return fail(CLEAN_E_UNSUPPORTED, "no batched kernel for %d x %d pixels per thread", K, V);
+    if (dyn_lds > 48 * 1024)
+        HIPCHK(hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn_lds));
     int occ = 0;
-    HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void *)fn, WG, 0));
+    HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void *)fn, WG, dyn_lds));
     occ = std::min(occ, MAX_WG_PER_CU);
     const int max_wg = occ * ncu;
 
-    // cluster size per problem, then largest problems first
-    std::vector<int> cs(n);
+    // cluster size per problem (per tile for tiled ones), workgroups per
+    // problem, then most workgroups first (largest images first among equals)
+    std::vector<int> cs(n), mem(n);
     for (int i = 0; i < n; ++i) {
-        const int64_t np = (int64_t)probs[i].ny * probs[i].nx;
-        cs[i] = (int)((np + (int64_t)WG * ppt - 1) / ((int64_t)WG * ppt));
-        if (cs[i] > max_wg)
-            return fail(CLEAN_E_UNSUPPORTED, "problem %d needs %d workgroups, only %d fit", i, cs[i], max_wg);
+        cs[i] = (int)((ptile[i] + (int64_t)WG * ppt - 1) / ((int64_t)WG * ppt));
+        const int64_t m = members_of(i, ppt);
+        if (m > max_wg || m > 4095)
+            return fail(CLEAN_E_UNSUPPORTED, "problem %d needs %lld workgroups, only %d fit", i, (long long)m,
+                        std::min(max_wg, 4095));
+        mem[i] = (int)m;
     }
     std::vector<int> order(n);
     for (int i = 0; i < n; ++i) order[i] = i;
     std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+        if (mem[x] != mem[y]) return mem[x] > mem[y];
         const int64_t px = (int64_t)probs[x].ny * probs[x].nx, py = (int64_t)probs[y].ny * probs[y].nx;
         return px > py;
     });
 
-    // workspace: control | jobs | seat0 | stats | slots | partials
+    // workspace: header (cleared) | jobs | tiled descriptions | seat0 |
+    // partials | tiled round lists and feedback buffers | ticket table
     std::vector<int32_t> seat0(n + 1, 0);
-    size_t nslots = 0, npart = 0;
+    size_t nslots = 0, npart = 0, ntile_words = 0, nlist = 0, nacc = 0, nctl = 0;
+    int ntiled = 0;
     for (int r = 0; r < n; ++r) {
         const int i = order[r];
-        seat0[r + 1] = seat0[r] + cs[i];
-        nslots += (size_t)2 * ((cs[i] + 31) / 32 * 32);
-        npart += cs[i];
+        const int T = pty[i] * ptx[i];
+        seat0[r + 1] = seat0[r] + mem[i];
+        nslots += (size_t)T * 2 * ((cs[i] + 31) / 32 * 32);
+        npart += mem[i];
+        if (T > 1) {
+            ++ntiled;
+            ntile_words += align_up((size_t)T * 16, 256);                       // tile keys, round counts
+            nlist += 4 * align_up((size_t)T * pint[i] * 4, 256);
+            nacc += align_up((size_t)probs[i].ny * probs[i].nx * 4, 256);
+            nctl += 256;                                                        // barrier counter, cancel word
+        }
     }
     size_t o = 0;
     const size_t o_ctl = o;   o = align_up(o + sizeof(DevCtl), 256);
     const size_t o_stat = o;  o = align_up(o + sizeof(DevStat) * n, 256);
     const size_t o_slots = o; o = align_up(o + nslots * 8, 256);
     const size_t o_xq = o;    o = align_up(o + sizeof(XcdQueue), 256);
+    const size_t o_tctl = o;  o = align_up(o + nctl, 256);
+    const size_t o_twords = o; o = align_up(o + ntile_words, 256);
     const size_t head_end = o;
     const size_t o_lslots = o; o = align_up(o + nslots * 8, 256);
     const size_t o_jobs = o;  o = align_up(o + sizeof(PlainJob) * n, 256);
+    const size_t o_tjobs = o; o = align_up(o + sizeof(KArgs) * ntiled, 256);
+    const size_t o_tof = o;   o = align_up(o + sizeof(int32_t) * n, 256);
     const size_t o_seat = o;  o = align_up(o + sizeof(int32_t) * (n + 1), 256);
     const size_t o_part = o;  o = align_up(o + npart * 8, 256);
+    const size_t o_lists = o; o = align_up(o + nlist, 256);
+    const size_t o_acc = o;   o = align_up(o + nacc, 256);
     // per-XCD schedule when each XCD's share of the grid can hold the largest
-    // cluster (the kernel checks the actual placement before using it); its
+    // problem (the kernel checks the actual placement before using it); its
     // ticket table only then
     const int W = std::min(max_wg, seat0[n]);
-    const int max_cs = *std::max_element(cs.begin(), cs.end());
+    const int max_cs = *std::max_element(mem.begin(), mem.end());
     const bool xcd_mode = W % 8 == 0 && max_cs <= W / 8 && max_cs < 4096;
     const size_t o_xtab = o;
     o = align_up(o + (xcd_mode ? (size_t)XQ_N * seat0[n] * sizeof(int32_t) : 0), 256);
@@ -1007,30 +1097,81 @@ int clean_batched(const clean_problem *probs, int n, const clean_params *shared,
     st = device_timeout_ticks(dev, ticks);
     if (st) return st;
     std::vector<PlainJob> jobs(n);
-    size_t so = 0, po = 0;
+    std::vector<int32_t> tiled_of(n, -1);
+    std::vector<KArgs> tjobs;
+    tjobs.reserve(ntiled);
+    size_t so = 0, po = 0, two = 0, lo = 0, ao = 0, co = 0;
     for (int r = 0; r < n; ++r) {
         const int i = order[r];
         const clean_problem &q = probs[i];
+        const int T = pty[i] * ptx[i];
+        const int pad = (cs[i] + 31) / 32 * 32;
         PlainJob &j = jobs[r];
         j.dirty = q.dirty; j.residual = q.residual; j.model = q.model;
         j.psf = q.psf; j.psf_bytes = (uint64_t)q.psf_ny * q.psf_nx * (half ? 2 : 4);
         j.ny = q.ny; j.nx = q.nx; j.psf_nx = q.psf_nx; j.cy = q.psf_ny / 2; j.cx = q.psf_nx / 2;
-        j.cs = cs[i];
-        j.slot_pad = (cs[i] + 31) / 32 * 32;
+        j.cs = mem[i];               // workgroups of the problem (plain: its cluster)
+        j.slot_pad = pad;
         j.gain = (float)shared->gain;
         j.threshold = q.threshold;
         j.max_iter = q.max_iter;
         j.cap = q.comp_cap;
         j.comp_idx = q.comp_idx; j.comp_flux = q.comp_flux;
-        j.cancel = (const int32_t *)shared->cancel;
         j.slots = (uint64_t *)(ws + o_slots) + so;
         j.lslots = (uint64_t *)(ws + o_lslots) + so;
-        j.hslots = nullptr;
-        j.hpad = 0;
         j.dstat = (DevStat *)(ws + o_stat) + r;
         j.partial = (double *)(ws + o_part) + po;
-        so += (size_t)2 * j.slot_pad;
-        po += cs[i];
+        tiled_of[r] = -1;
+        if (T > 1) {
+            KArgs a{};
+            a.dirty = q.dirty; a.residual = q.residual; a.model = q.model;
+            a.psf = q.psf; a.psf_bytes = j.psf_bytes;
+            a.ny = q.ny; a.nx = q.nx; a.psf_ny = q.psf_ny; a.psf_nx = q.psf_nx;
+            a.cy = q.psf_ny / 2; a.cx = q.psf_nx / 2;
+            a.ty = pty[i]; a.tx = ptx[i]; a.T = T;
+            a.cs = cs[i];
+            a.slot_pad = pad;
+            a.interval = pint[i];
+            a.level_frac = shared->feedback_level;
+            a.gather_parts = std::max(1, mem[i] / T);
+            a.gain = (float)shared->gain;
+            a.threshold = q.threshold;
+            a.max_iter = q.max_iter;
+            a.cap = q.comp_cap;
+            a.timeout_ticks = ticks;
+            a.comp_idx = q.comp_idx;
+            a.comp_flux = q.comp_flux;
+            a.cancel = (const int32_t *)shared->cancel;
+            a.has_cancel = shared->cancel != nullptr;
+            a.ctl = (DevCtl *)(ws + o_ctl);
+            a.bar = (uint32_t *)(ws + o_tctl + co);
+            a.cword = (uint32_t *)(ws + o_tctl + co + 128);
+            a.dstat = j.dstat;
+            a.role = nullptr;
+            a.xslots = j.slots;
+            a.lslots = j.lslots;
+            char *tw = ws + o_twords + two;
+            a.tile_key = (uint64_t *)tw;
+            a.rb_n = (int32_t *)(tw + (size_t)T * 8);
+            a.ag_n = (int32_t *)(tw + (size_t)T * 12);
+            const size_t lb = align_up((size_t)T * pint[i] * 4, 256);
+            a.rb_idx = (int32_t *)(ws + o_lists + lo);
+            a.rb_flux = (float *)(ws + o_lists + lo + lb);
+            a.ag_pos = (int32_t *)(ws + o_lists + lo + 2 * lb);
+            a.ag_flux = (float *)(ws + o_lists + lo + 3 * lb);
+            a.accbuf = (float *)(ws + o_acc + ao);
+            a.partial = j.partial;
+            a.hslots = nullptr;
+            a.hpad = 0;
+            tiled_of[r] = (int)tjobs.size();
+            tjobs.push_back(a);
+            two += align_up((size_t)T * 16, 256);
+            lo += 4 * lb;
+            ao += align_up((size_t)q.ny * q.nx * 4, 256);
+            co += 256;
+        }
+        so += (size_t)T * 2 * pad;
+        po += mem[i];
     }
     BatchArgs b{};
     b.jobs = (const PlainJob *)(ws + o_jobs);
@@ -1043,8 +1184,14 @@ int clean_batched(const clean_problem *probs, int n, const clean_params *shared,
     b.tickets = seat0[n];
     b.xq = (XcdQueue *)(ws + o_xq);
     b.xtable = (int32_t *)(ws + o_xtab);
+    b.tjobs = (const KArgs *)(ws + o_tjobs);
+    b.tiled_of = (const int32_t *)(ws + o_tof);
+    b.cancel = (const int32_t *)shared->cancel;
     HIPCHK(hipMemsetAsync(ws, 0, head_end, stream));
     HIPCHK(hipMemcpyAsync(ws + o_jobs, jobs.data(), sizeof(PlainJob) * n, hipMemcpyHostToDevice, stream));
+    if (ntiled)
+        HIPCHK(hipMemcpyAsync(ws + o_tjobs, tjobs.data(), sizeof(KArgs) * ntiled, hipMemcpyHostToDevice, stream));
+    HIPCHK(hipMemcpyAsync(ws + o_tof, tiled_of.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, stream));
     HIPCHK(hipMemcpyAsync(ws + o_seat, seat0.data(), sizeof(int32_t) * (n + 1), hipMemcpyHostToDevice, stream));
     if (shared->flags & CLEAN_FLAG_CHECK_FINITE) {
         uint32_t *flag = &b.ctl->finite_bad;
@@ -1070,7 +1217,7 @@ int clean_batched(const clean_problem *probs, int n, const clean_params *shared,
     HIPCHK(hipEventCreate(&e1));
     HIPCHK(hipEventRecord(e0, stream));
     void *args[] = {(void *)&b};
-    hipError_t le = hipLaunchCooperativeKernel((const void *)fn, dim3(W), dim3(WG), args, 0, stream);
+    hipError_t le = hipLaunchCooperativeKernel((const void *)fn, dim3(W), dim3(WG), args, (unsigned)dyn_lds, stream);
     if (le != hipSuccess) {
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
@@ -1097,11 +1244,12 @@ int clean_batched(const clean_problem *probs, int n, const clean_params *shared,
             memset(&s, 0, sizeof s);
             s.n_iter = ds[r].n_iter;
             s.stop_reason = ds[r].stop;
+            s.n_rounds = ds[r].n_rounds;
             s.final_peak = ds[r].final_peak;
             s.residual_rms = std::sqrt(ds[r].sumsq / ((double)probs[i].ny * probs[i].nx));
             s.model_flux = ds[r].model_flux;
             s.device_ms = ms;
-            s.wg_per_tile = cs[i];
+            s.wg_per_tile = cs[i];                 // per tile for tiled problems
             s.px_per_thread = ppt;
             s.workgroups = W;
             s.streamed = 0;

@@ -13,7 +13,7 @@ constexpr int GATHER_CHUNK = 2048;      // components staged in LDS per pass
 constexpr int GATHER_M = 2;             // pixel groups per thread per gather pass
 constexpr int GATHER_J = 8;             // components whose loads are issued together
 constexpr int STREAM_K = 4;             // pixel groups per thread per streamed pass
-constexpr int TWO_LEVEL_MIN_CS = 16;    // plain clusters this large exchange in two levels
+constexpr int TWO_LEVEL_MIN_CS = 32;    // plain clusters this large exchange in two levels
 constexpr int MAX_WG_PER_CU = 2;        // co-resident 512-thread workgroups the launches count on per CU
 constexpr int FFT_MAX_LG = 13;          // one-level FFT transforms: length <= 8192 (64 KB of LDS)
 constexpr int FFT_MAX_LG2 = 16;         // two-level FFT transforms: length <= 65536
@@ -71,9 +71,6 @@ struct PlainJob {
     float *comp_flux;
     uint64_t *slots;        // [2][slot_pad] device-scope exchange slots
     uint64_t *lslots;       // [2][slot_pad] XCD-local exchange slots (batched), else null
-    const int32_t *cancel;  // the caller's cancel flag (host memory), or null
-    uint64_t *hslots;       // [2][8 * hpad + 32] two-level exchange slots (plain, large clusters), else null
-    int hpad;               // slots per XCD of the two-level exchange
     DevStat *dstat;
     double *partial;        // [cs]
 };
@@ -90,6 +87,8 @@ struct XcdQueue {
     uint32_t problem[XQ_STRIDE];        // next problem to hand out (all XCDs)
 };
 
+struct KArgs;
+
 struct BatchArgs {
     const PlainJob *jobs;   // [n], largest first
     const int32_t *seat0;   // [n + 1] first seat of each problem
@@ -101,6 +100,9 @@ struct BatchArgs {
     int tickets;            // ticket slots per XCD (total seats)
     XcdQueue *xq;
     int32_t *xtable;        // [XQ_N][tickets] problem << 12 | rank per ticket
+    const KArgs *tjobs;     // tiled problems' descriptions
+    const int32_t *tiled_of;   // [n] index into tjobs of problem i, or -1 (plain)
+    const int32_t *cancel;  // the caller's cancel flag (host memory), or null
 };
 
 struct KArgs {
@@ -124,8 +126,11 @@ struct KArgs {
     int32_t *comp_idx;
     float *comp_flux;
     const int32_t *cancel;  // the caller's cancel flag (host memory), or null
+    int has_cancel;         // cancel != null
     // workspace
     DevCtl *ctl;
+    uint32_t *bar;          // the rounds' barrier counter: &ctl->barrier, or a batched problem's own
+    uint32_t *cword;        // the cancel flag as read before a barrier: &ctl->cancel, or the problem's own
     DevStat *dstat;
     const int32_t *role;    // per workgroup: tile << 16 | rank, or -1 (helper)
     uint64_t *xslots;       // [T][2][slot_pad] device-scope exchange slots

@@ -471,8 +471,10 @@ __device__ int cluster_round_robin(const Sync &y, uint64_t *slots, int slot_pad,
 // waits for its own memory operations to complete, the workgroup barrier
 // collects the waves, one agent-scope atomic arrives, and readers issue their
 // loads only after they have seen all arrivals.
-// `epoch` counts the barriers this workgroup has passed.
-__device__ bool grid_barrier(const Sync &y, uint32_t &epoch, int *s_ok)
+// `epoch` counts the barriers this workgroup has passed.  scope_barrier is
+// the same over the `members` workgroups that share the counter `ctr` (one
+// problem of a batch); grid_barrier is it over the whole grid.
+__device__ bool scope_barrier(const Sync &y, uint32_t *ctr, uint32_t members, uint32_t &epoch, int *s_ok)
 {
     // every wave's vector memory operations (its coherent stores) complete
     // before the workgroup can arrive
@@ -481,10 +483,10 @@ __device__ bool grid_barrier(const Sync &y, uint32_t &epoch, int *s_ok)
     epoch += 1;
     if (threadIdx.x == 0) {
         bool ok = true;
-        const uint32_t target = epoch * (uint32_t)gridDim.x;
-        __hip_atomic_fetch_add(&y.ctl->barrier, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint32_t target = epoch * members;
+        __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         const uint64_t t0 = wall_clock64();
-        while (ld_agent32(&y.ctl->barrier) < target) {
+        while (ld_agent32(ctr) < target) {
             if (ld_agent32(&y.ctl->abort)) { ok = false; break; }
             if (wall_clock64() - t0 > y.timeout_ticks) { raise_abort(y, ABORT_TIMEOUT); ok = false; break; }
             __builtin_amdgcn_s_sleep(1);
@@ -495,6 +497,11 @@ __device__ bool grid_barrier(const Sync &y, uint32_t &epoch, int *s_ok)
     bool ok = *s_ok;
     __syncthreads();
     return ok;
+}
+
+__device__ __forceinline__ bool grid_barrier(const Sync &y, uint32_t &epoch, int *s_ok)
+{
+    return scope_barrier(y, &y.ctl->barrier, gridDim.x, epoch, s_ok);
 }
 
 __device__ __forceinline__ void tile_rect(const KArgs &a, int t, int &y0, int &x0, int &h, int &w)
@@ -601,14 +608,15 @@ template <int K, int V, typename PT> struct RegTile {
             // the largest so far, with its four values, then the lowest of
             // those at that magnitude (a group holding a NaN has a NaN
             // maximum and is never taken here; no group taken: +0 at group 0)
-            float gm = -1.0f, gn = 0.0f;
+            float gm = -1.0f;
             uint32_t kb = 0;
             float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f, s3 = 0.0f;
 #pragma unroll
             for (int k = 0; k < K; ++k) {
                 const float g = nan_max(nan_max(fabsf(r[k][0]), fabsf(r[k][1])), nan_max(fabsf(r[k][2]), fabsf(r[k][3])));
-                gn = nan_max(gn, g);
-                const bool hit = g > gm;
+                // taken when larger, or NaN (unordered): a NaN group makes gm
+                // NaN, which the slow path below handles
+                const bool hit = !(g <= gm);
                 gm = hit ? g : gm;
                 kb = hit ? (uint32_t)k : kb;
                 s0 = hit ? r[k][0] : s0;
@@ -616,10 +624,7 @@ template <int K, int V, typename PT> struct RegTile {
                 s2 = hit ? r[k][2] : s2;
                 s3 = hit ? r[k][3] : s3;
             }
-            if (__builtin_expect(is_nan(gn), 0)) {
-                const uint64_t nk = nan_key();
-                if (nk) return nk;
-            }
+            if (__builtin_expect(is_nan(gm), 0)) return key_slow();
             uint32_t bb = __float_as_uint(s0), be = 0;
             if (gm >= 0.0f && fabsf(s0) != gm) {
                 const bool h1 = fabsf(s1) == gm, h2 = fabsf(s2) == gm;
@@ -628,18 +633,12 @@ template <int K, int V, typename PT> struct RegTile {
             }
             return make_key(bb, group_f((int)kb) + be);
         }
-        float m = 0.0f, mn = 0.0f;
+        float m = 0.0f;
 #pragma unroll
         for (int k = 0; k < K; ++k)
 #pragma unroll
-            for (int e = 0; e < V; ++e) {
-                m = fmaxf(m, fabsf(r[k][e]));
-                mn = nan_max(mn, r[k][e]);
-            }
-        if (__builtin_expect(is_nan(mn), 0)) {
-            const uint64_t nk = nan_key();
-            if (nk) return nk;
-        }
+            for (int e = 0; e < V; ++e) m = nan_max(m, fabsf(r[k][e]));
+        if (__builtin_expect(is_nan(m), 0)) return key_slow();
         uint32_t bb = 0, bi = 0;
 #pragma unroll
         for (int i = K * V - 1; i >= 0; --i) {
@@ -651,22 +650,33 @@ template <int K, int V, typename PT> struct RegTile {
         return make_key(bb, group_f((int)(bi / V)) + bi % V);
     }
 
-    // Key of the lowest-index NaN among the valid pixels, or 0 if there is
-    // none (a NaN can also reach a group outside the tile, which multiplies a
-    // PSF window by zero: such groups are skipped).
-    __device__ __forceinline__ uint64_t nan_key() const
+    // The key when some group's maximum came out NaN.  A NaN among the valid
+    // pixels makes the tile's peak non-finite: the key is a NaN (its position
+    // is never used, as the run stops before appending).  Else the NaN sits in
+    // a group outside the tile (which multiplies a PSF window by zero) and the
+    // key is the largest |r| skipping NaN, as fmaxf does.  Rare and terminal.
+    __device__ __forceinline__ uint64_t key_slow() const
     {
+        bool vnan = false;
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+#pragma unroll
+            for (int e = 0; e < V; ++e) vnan = vnan || (((valid >> k) & 1ull) && is_nan(r[k][e]));
+        if (vnan) return make_key(0x7FC00000u, group_f(0));
+        float m = 0.0f;
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+#pragma unroll
+            for (int e = 0; e < V; ++e) m = fmaxf(m, fabsf(r[k][e]));
         uint32_t bb = 0, bi = 0;
-        bool any = false;
 #pragma unroll
         for (int i = K * V - 1; i >= 0; --i) {
             const float x = r[i / V][i % V];
-            const bool hit = ((valid >> (i / V)) & 1ull) && is_nan(x);
+            const bool hit = fabsf(x) == m;
             bb = hit ? __float_as_uint(x) : bb;
             bi = hit ? (uint32_t)i : bi;
-            any = any || hit;
         }
-        return any ? make_key(bb, group_f((int)(bi / V)) + bi % V) : 0;
+        return make_key(bb, group_f((int)(bi / V)) + bi % V);
     }
 
     // r -= c * PSF centred on image pixel (py, px); then, if asked, the new key.
@@ -920,14 +930,13 @@ __device__ __noinline__ WideRound wide_round(const KArgs &a, const Img im, const
             // A group holding a NaN has a NaN maximum and is never taken
             // there; a NaN-propagating max beside it sends that rare,
             // terminal case to a scan for the lowest-index NaN.
-            float m = -1.0f, gn = 0.0f;
+            float m = -1.0f;
             uint32_t kb = 0;
             float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f, s3 = 0.0f;
 #pragma unroll
             for (int k = 0; k < K; ++k) {
                 const float g = nan_max(nan_max(fabsf(r[k][0]), fabsf(r[k][1])), nan_max(fabsf(r[k][2]), fabsf(r[k][3])));
-                gn = nan_max(gn, g);
-                const bool hit = g > m;
+                const bool hit = !(g <= m);             // larger, or NaN
                 m = hit ? g : m;
                 kb = hit ? (uint32_t)k : kb;
                 s0 = hit ? r[k][0] : s0;
@@ -942,20 +951,41 @@ __device__ __noinline__ WideRound wide_round(const KArgs &a, const Img im, const
                 be = h1 ? 1u : h2 ? 2u : 3u;
             }
             uint64_t tk = R.nvalid > 0 ? make_key(bb, R.group_f((int)kb) + be) : 0;
-            if (__builtin_expect(is_nan(gn), 0)) {
-                // the lowest-index NaN of the groups inside the tile (groups
-                // past its end multiply a PSF window by zero and may hold NaN)
-                uint32_t nb_ = 0, ni = 0;
-                bool any = false;
+            if (__builtin_expect(is_nan(m), 0)) {
+                // a group's maximum is NaN: a NaN in a group inside the tile
+                // makes the peak non-finite (the key is a NaN; its position is
+                // never used); else the NaN is in a group past the tile's end
+                // (which multiplies a PSF window by zero) and the key is the
+                // largest |r| skipping NaN
+                bool vnan = false;
 #pragma unroll
-                for (int i = K * V - 1; i >= 0; --i) {
-                    const float x = r[i / V][i % V];
-                    const bool hit = i / V < R.nvalid && is_nan(x);
-                    nb_ = hit ? __float_as_uint(x) : nb_;
-                    ni = hit ? (uint32_t)i : ni;
-                    any = any || hit;
+                for (int k = 0; k < K; ++k)
+                    vnan = vnan || (k < R.nvalid && is_nan(nan_max(nan_max(r[k][0], r[k][1]), nan_max(r[k][2], r[k][3]))));
+                if (vnan) {
+                    tk = make_key(0x7FC00000u, R.group_f(0));
+                } else {
+                    float m2 = -1.0f;
+                    uint32_t k2 = 0;
+                    float t0 = 0.0f, t1 = 0.0f, t2 = 0.0f, t3 = 0.0f;
+#pragma unroll
+                    for (int k = 0; k < K; ++k) {
+                        const float g = fmaxf(fmaxf(fabsf(r[k][0]), fabsf(r[k][1])), fmaxf(fabsf(r[k][2]), fabsf(r[k][3])));
+                        const bool hit = g > m2;
+                        m2 = hit ? g : m2;
+                        k2 = hit ? (uint32_t)k : k2;
+                        t0 = hit ? r[k][0] : t0;
+                        t1 = hit ? r[k][1] : t1;
+                        t2 = hit ? r[k][2] : t2;
+                        t3 = hit ? r[k][3] : t3;
+                    }
+                    uint32_t b2 = __float_as_uint(t0), e2 = 0;
+                    if (m2 >= 0.0f && fabsf(t0) != m2) {
+                        const bool h1 = fabsf(t1) == m2, h2 = fabsf(t2) == m2;
+                        b2 = h1 ? __float_as_uint(t1) : h2 ? __float_as_uint(t2) : __float_as_uint(t3);
+                        e2 = h1 ? 1u : h2 ? 2u : 3u;
+                    }
+                    tk = R.nvalid > 0 ? make_key(b2, R.group_f((int)k2) + e2) : 0;
                 }
-                if (any) tk = make_key(nb_, R.group_f((int)(ni / V)) + ni % V);
             }
             if (!cluster_reduce(y, slots, lslots, a.slot_pad, R.cs, R.rank, out.e++, tk, out.cur)) {
                 out.ok = 0;
@@ -1153,7 +1183,11 @@ template <class Tile> __device__ void store_and_sum(const Tile &R, const Img &im
 // member clears its entries of them before that first, device-scope
 // exchange, which no member passes until all have cleared theirs).  Returns
 // false if the run was aborted.
-template <class Tile> __device__ bool run_plain(const PlainJob &j_arg, int rank_arg, const Sync &y, bool local)
+// `cancel`: the caller's flag (host memory) or null; `hslots`/`hpad`: the
+// two-level exchange slots of a large plain cluster, or null.
+template <class Tile>
+__device__ __forceinline__ bool run_plain(const PlainJob &j_arg, int rank_arg, const Sync &y, bool local,
+                                          const int32_t *cancel, uint64_t *hslots, int hpad)
 {
     const PlainJob j = wave_uniform(j_arg);     // one problem per workgroup
     const int rank = wave_uniform(rank_arg);
@@ -1175,8 +1209,8 @@ template <class Tile> __device__ bool run_plain(const PlainJob &j_arg, int rank_
     // a large cluster spread over the XCDs (plain CLEAN) exchanges in two
     // levels when every rank sits on the XCD the placement intends
     bool two = false;
-    if (j.hslots) {
-        const int rr = cluster_round_robin(y, j.slots, j.slot_pad, j.hslots, j.hpad, j.cs, rank, e++);
+    if (hslots) {
+        const int rr = cluster_round_robin(y, j.slots, j.slot_pad, hslots, hpad, j.cs, rank, e++);
         if (rr < 0) return false;
         two = rr > 0;
     }
@@ -1192,12 +1226,12 @@ template <class Tile> __device__ bool run_plain(const PlainJob &j_arg, int rank_
         // peak (eq. 1): value and position from the cluster's key
         const float v = key_value(cur);
         if (n == j.max_iter) { stop = STOP_MAXITER; break; }
-        if (j.cancel && n % CANCEL_EVERY == 0) {
+        if (cancel && n % CANCEL_EVERY == 0) {
             // cancel checkpoint: rank 0 reads the caller's flag and the
             // cluster takes the max, so every member stops at the same n
-            const uint64_t vote = rank == 0 && threadIdx.x == 0 && host_flag(j.cancel) ? (1ull << 33) : 0ull;
+            const uint64_t vote = rank == 0 && threadIdx.x == 0 && host_flag(cancel) ? (1ull << 33) : 0ull;
             uint64_t got;
-            if (!(two ? cluster_reduce_xcd2(y, j.hslots, j.hpad, j.cs, rank, e++, vote, got)
+            if (!(two ? cluster_reduce_xcd2(y, hslots, hpad, j.cs, rank, e++, vote, got)
                       : cluster_reduce(y, j.slots, ls, j.slot_pad, j.cs, rank, e++, vote, got)))
                 return false;
             if (got) { stop = STOP_CANCELLED; break; }
@@ -1216,7 +1250,7 @@ template <class Tile> __device__ bool run_plain(const PlainJob &j_arg, int rank_
         if (j.model && T.owns(fp)) j.model[fp] += (double)c;
         // subtraction (eq. 2) fused with the next peak search
         const uint64_t tk = T.subtract(im, py, px, c, true);
-        if (!(two ? cluster_reduce_xcd2(y, j.hslots, j.hpad, j.cs, rank, e++, tk, cur)
+        if (!(two ? cluster_reduce_xcd2(y, hslots, hpad, j.cs, rank, e++, tk, cur)
                   : cluster_reduce(y, j.slots, ls, j.slot_pad, j.cs, rank, e++, tk, cur)))
             return false;
         cur = wave_uniform(cur);
@@ -1246,11 +1280,9 @@ template <class Tile> __global__ void __launch_bounds__(WG) hogbom_kernel(const 
     j.ny = a.ny; j.nx = a.nx; j.psf_nx = a.psf_nx; j.cy = a.cy; j.cx = a.cx;
     j.gain = a.gain; j.threshold = a.threshold; j.max_iter = a.max_iter; j.cap = a.cap;
     j.comp_idx = a.comp_idx; j.comp_flux = a.comp_flux;
-    j.cancel = a.cancel;
     j.slots = a.xslots; j.lslots = nullptr; j.slot_pad = a.slot_pad; j.cs = a.cs;
-    j.hslots = a.hslots; j.hpad = a.hpad;
     j.dstat = a.dstat; j.partial = a.partial;
-    run_plain<Tile>(j, role & 0xFFFF, y, false);
+    run_plain<Tile>(j, role & 0xFFFF, y, false, a.cancel, a.hslots, a.hpad);
 }
 
 // Ticket of the per-XCD schedule: the problem and cluster rank this
@@ -1293,72 +1325,6 @@ __device__ int32_t xcd_ticket(const BatchArgs &b, const Sync &y, uint32_t x)
         }
     }
 }
-
-// Many independent images in one launch.  Problems are laid out largest
-// first; problem i owns the seats [seat0[i], seat0[i+1]) and each seat is one
-// workgroup of its cluster.
-//
-// Per-XCD schedule (when every XCD that holds workgroups holds at least the
-// largest cluster's worth, counted at launch): each XCD pulls whole problems
-// from the batch in order and runs them with its own workgroups, whose
-// exchanges then stay in that XCD's L2.  Otherwise a workgroup takes the next
-// seat of the whole batch from a device counter.  Either way tickets (seats)
-// go out in order and every workgroup is resident, so the earliest
-// unfinished problem always has all its members running: no deadlock.
-template <class Tile> __global__ void __launch_bounds__(WG) batched_kernel(const BatchArgs b)
-{
-    __shared__ int s_work, s_ok;
-    const Sync y{b.ctl, b.timeout_ticks};
-    const int total = b.seat0[b.n];
-    bool per_xcd = false;
-    uint32_t x = 0;
-    if (b.xcd_mode) {
-        x = xcc_id();
-        if (threadIdx.x == 0)
-            __hip_atomic_fetch_add(&b.xq->count[x * XQ_STRIDE], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        uint32_t epoch = 0;
-        if (!grid_barrier(y, epoch, &s_ok)) return;
-        if (threadIdx.x == 0) {
-            int ok = 1;
-            for (int i = 0; i < XQ_N; ++i) {
-                const uint32_t c = ld_agent32(&b.xq->count[i * XQ_STRIDE]);
-                if (c != 0 && c < (uint32_t)b.max_cs) ok = 0;
-            }
-            s_work = ok;
-        }
-        __syncthreads();
-        per_xcd = s_work != 0;
-        __syncthreads();
-    }
-    for (;;) {
-        // the next (problem << 12 | rank) for this workgroup, or -1
-        if (threadIdx.x == 0) {
-            int32_t w = -1;
-            if (per_xcd) {
-                w = xcd_ticket(b, y, x);
-            } else {
-                const int seat =
-                    (int)__hip_atomic_fetch_add(&b.ctl->seat, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                if (seat < total) {
-                    int lo = 0, hi = b.n;       // seat0[lo] <= seat < seat0[lo + 1]
-                    while (hi - lo > 1) {
-                        const int mid = (lo + hi) >> 1;
-                        if (b.seat0[mid] <= seat) lo = mid; else hi = mid;
-                    }
-                    w = (int32_t)(((uint32_t)lo << 12) | (uint32_t)(seat - b.seat0[lo]));
-                }
-            }
-            s_work = w;
-        }
-        __syncthreads();
-        const int32_t w = s_work;
-        __syncthreads();
-        if (w < 0) return;
-        if (!run_plain<Tile>(b.jobs[w >> 12], w & 0xFFF, y, per_xcd)) return;
-        if (aborted(y)) return;
-    }
-}
-
 
 // ----------------------------------------------------- FFT feedback -----
 //
@@ -1968,6 +1934,23 @@ __device__ bool fft_feedback(const KArgs &a, const Sync &y, uint32_t &epoch, int
     return true;
 }
 
+// The wide-tile kernel's feedback round in a function of its own: its
+// transform loops get a register allocation of their own, unaffected by the
+// state the round loop keeps live (inlined, that state pushed spills into the
+// transform passes).  Arguments are copied to scalar registers first: the
+// argument block's address and the wait settings are the same in every lane.
+template <typename PT>
+__device__ __noinline__ bool fft_feedback_wide(const KArgs *a_arg, const Sync y_arg, uint32_t epoch_in,
+                                               uint32_t *epoch_out, int *s_ok, const int32_t *s_off)
+{
+    const KArgs *ap = wave_uniform(a_arg);
+    const Sync y = wave_uniform(y_arg);
+    uint32_t epoch = wave_uniform(epoch_in);
+    const bool ok = fft_feedback<PT, true>(*ap, y, epoch, s_ok, s_off);
+    *epoch_out = epoch;
+    return ok;
+}
+
 #undef FFT_BARRIER
 
 // ------------------------------------------------------ tiled kernel -----
@@ -2064,10 +2047,20 @@ __device__ __forceinline__ int wg_sum_int(int v, int *s_tmp)
 // carry none of the transform code (and its register needs).
 // Streamed tiles with FFT feedback are capped at 128 VGPRs (four waves per
 // SIMD) so that two workgroups share a CU, as the direct-gather ones do.
-template <class Tile, bool FFT>
-__global__ void __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(FFT && !Tile::kResident && !Tile::kWide ? 4 : 1)))
-tiled_kernel(const KArgs a)
+//
+// tiled_body runs the rounds of one tiled problem on `members` workgroups,
+// this one being member `member` with role `role` (tile << 16 | cluster rank,
+// or -1: a helper of the feedback phases): the whole grid of tiled_kernel, or
+// one problem's share of a batched launch (a.bar is then that problem's
+// barrier counter and a.cword its cancel word).  xcd_items: spread the
+// gather's items over the XCDs by workgroup index (the whole grid only).
+template <class Tile, bool FFT, bool BATCH>
+__device__ __forceinline__ void tiled_body(const KArgs &a, int member_arg, int members_arg, int32_t role, bool xcd_items)
 {
+    // the whole grid reads its index, size and control words from the
+    // dispatch and the control block; a batched problem gets its own
+    const int member = BATCH ? member_arg : (int)blockIdx.x;
+    const int members = BATCH ? members_arg : (int)gridDim.x;
     constexpr int V = Tile::kV;
     using PT = typename Tile::psf_t;
     __shared__ int s_ok, s_tmp, s_cnt;
@@ -2077,7 +2070,6 @@ tiled_kernel(const KArgs a)
 
     const Sync y{a.ctl, a.timeout_ticks};
     const Img im{a.dirty, a.residual, a.model, a.accbuf, a.rstart, a.psf, a.psf_bytes, a.nx, a.psf_nx, a.cy, a.cx};
-    const int32_t role = a.role[blockIdx.x];
     const bool is_cluster = role >= 0;
     const int tile = is_cluster ? (role >> 16) : -1;
     const int rank = is_cluster ? (role & 0xFFFF) : 0;
@@ -2116,8 +2108,9 @@ tiled_kernel(const KArgs a)
         if (tile_leader_wg && threadIdx.x == 0) stc(&a.tile_key[tile], cur);
     }
     // the caller's cancel flag, seen by every workgroup after the barrier
-    if (a.cancel && blockIdx.x == 0 && threadIdx.x == 0) stc(&a.ctl->cancel, host_flag(a.cancel));
-    if (!grid_barrier(y, epoch, &s_ok)) return;
+    if (a.has_cancel && member == 0 && threadIdx.x == 0)
+        stc(BATCH ? a.cword : &a.ctl->cancel, host_flag(a.cancel));
+    if (!scope_barrier(y, BATCH ? a.bar : &a.ctl->barrier, members, epoch, &s_ok)) return;
     if constexpr (FFT) {
         if (!fft_spectrum<PT, Tile::kWide>(a, y, epoch, &s_ok)) return;
     }
@@ -2139,7 +2132,7 @@ tiled_kernel(const KArgs a)
         if (vbits) atomicMax(&s_vmax, vbits);
         __syncthreads();
         const bool nonfinite = s_vmax >= 0x7F800000u;
-        const bool cancelled = a.cancel && ldc(&a.ctl->cancel) != 0u;
+        const bool cancelled = a.has_cancel && ldc(BATCH ? a.cword : &a.ctl->cancel) != 0u;
         const double level = nonfinite ? 0.0 : a.level_frac * (double)__uint_as_float(s_vmax);
         int na_part = 0, rk_part = 0;
         for (int t = threadIdx.x; t < T; t += WG) {
@@ -2165,7 +2158,7 @@ tiled_kernel(const KArgs a)
         }
 
         // ---- local minor loops
-        if (blockIdx.x == 0) tp0 = wall_clock64();
+        if (member == 0) tp0 = wall_clock64();
         if (is_cluster) {
             int L = 0;
             if constexpr (Tile::kWide) {
@@ -2196,8 +2189,8 @@ tiled_kernel(const KArgs a)
                 aggregate_round(a, tile, L, l_idx, l_flux, l_tmp, l_sum, &s_cnt);
             }
         }
-        if (!grid_barrier(y, epoch, &s_ok)) return;                        // A
-        if (blockIdx.x == 0) { tp1 = wall_clock64(); ph_local += tp1 - tp0; tp0 = tp1; }
+        if (!scope_barrier(y, BATCH ? a.bar : &a.ctl->barrier, members, epoch, &s_ok)) return;   // A
+        if (member == 0) { tp1 = wall_clock64(); ph_local += tp1 - tp0; tp0 = tp1; }
 
         // ---- round bookkeeping: every workgroup reads the counts
         for (int t = threadIdx.x; t < T; t += WG) s_off[t + 1] = ldc(&a.rb_n[t]);
@@ -2208,7 +2201,7 @@ tiled_kernel(const KArgs a)
         }
         __syncthreads();
         const int32_t nround = s_off[T];
-        if (blockIdx.x == 0) {
+        if (member == 0) {
             // append this round's components in (tile, local iteration) order
             double fsum = 0.0;
             for (int t = 0; t < T; ++t) {
@@ -2240,7 +2233,13 @@ tiled_kernel(const KArgs a)
         // ---- feedback by FFT: acc = component image (*) K, every tile's
         // components (apply then starts from the round's starting residual)
         if constexpr (FFT) {
-            if (!fft_feedback<PT, Tile::kWide>(a, y, epoch, &s_ok, s_off)) return;
+            if constexpr (Tile::kWide) {
+                __shared__ uint32_t s_epoch;
+                if (!fft_feedback_wide<PT>(&a, y, epoch, &s_epoch, &s_ok, s_off)) return;
+                epoch = s_epoch;
+            } else {
+                if (!fft_feedback<PT, false>(a, y, epoch, &s_ok, s_off)) return;
+            }
         } else
         // ---- feedback gather: acc[q] = sum over other tiles' components
         {
@@ -2249,12 +2248,12 @@ tiled_kernel(const KArgs a)
             // per component (workgroup b runs on XCD b % 8)
             const int parts = a.gather_parts;
             const int nitems = T * parts;
-            const bool by_xcd = (gridDim.x % 8) == 0;
-            const int per_xcd_wg = by_xcd ? (int)gridDim.x / 8 : (int)gridDim.x;
+            const bool by_xcd = xcd_items && (members % 8) == 0;
+            const int per_xcd_wg = by_xcd ? members / 8 : members;
             const int items_per_xcd = by_xcd ? (nitems + 7) / 8 : nitems;
-            const int xcd = by_xcd ? (int)(blockIdx.x % 8) : 0;
+            const int xcd = by_xcd ? member % 8 : 0;
             const int item_end = min(nitems, (xcd + 1) * items_per_xcd);
-            for (int item = xcd * items_per_xcd + (by_xcd ? (int)(blockIdx.x / 8) : (int)blockIdx.x);
+            for (int item = xcd * items_per_xcd + (by_xcd ? member / 8 : member);
                  item < item_end; item += per_xcd_wg) {
                 const int s = item / parts, part = item % parts;
                 int y0, x0, h, w;
@@ -2308,7 +2307,8 @@ tiled_kernel(const KArgs a)
                                 const int32_t sh = __builtin_amdgcn_readfirstlane(g_shift[j + u]);
                                 fl[u] = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, g_flux[j + u])));
                                 const char *base = (const char *)a.psf + (int64_t)sh * (int64_t)sizeof(PT);
-                                const __amdgpu_buffer_rsrc_t rs = make_rsrc(base, a.psf_bytes - (uint64_t)sh * sizeof(PT));
+                                const __amdgpu_buffer_rsrc_t rs =
+                                    make_rsrc_uniform(base, a.psf_bytes - (uint64_t)sh * sizeof(PT));
 #pragma unroll
                                 for (int m = 0; m < GATHER_M; ++m)
                                     PsfLoad<PT, V>::load(rs, (uint32_t)goff[m] * (uint32_t)sizeof(PT), pv[u][m]);
@@ -2324,7 +2324,8 @@ tiled_kernel(const KArgs a)
                             const int32_t sh = __builtin_amdgcn_readfirstlane(g_shift[j]);
                             const float fl = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, g_flux[j])));
                             const char *base = (const char *)a.psf + (int64_t)sh * (int64_t)sizeof(PT);
-                            const __amdgpu_buffer_rsrc_t rs = make_rsrc(base, a.psf_bytes - (uint64_t)sh * sizeof(PT));
+                            const __amdgpu_buffer_rsrc_t rs =
+                                make_rsrc_uniform(base, a.psf_bytes - (uint64_t)sh * sizeof(PT));
 #pragma unroll
                             for (int m = 0; m < GATHER_M; ++m) {
                                 float pv[V];
@@ -2343,8 +2344,8 @@ tiled_kernel(const KArgs a)
                 }
             }
         }
-        if (!grid_barrier(y, epoch, &s_ok)) return;                        // B
-        if (blockIdx.x == 0) { tp1 = wall_clock64(); ph_gather += tp1 - tp0; tp0 = tp1; }
+        if (!scope_barrier(y, BATCH ? a.bar : &a.ctl->barrier, members, epoch, &s_ok)) return;   // B
+        if (member == 0) { tp1 = wall_clock64(); ph_gather += tp1 - tp0; tp0 = tp1; }
 
         // ---- apply feedback and find each tile's new peak
         if (is_cluster) {
@@ -2352,14 +2353,15 @@ tiled_kernel(const KArgs a)
             if (tile_leader_wg && threadIdx.x == 0) stc(&a.tile_key[tile], cur);
         }
         rounds += 1;
-        if (a.cancel && blockIdx.x == 0 && threadIdx.x == 0) stc(&a.ctl->cancel, host_flag(a.cancel));
-        if (!grid_barrier(y, epoch, &s_ok)) return;                        // C
-        if (blockIdx.x == 0) { tp1 = wall_clock64(); ph_apply += tp1 - tp0; }
+        if (a.has_cancel && member == 0 && threadIdx.x == 0)
+            stc(BATCH ? a.cword : &a.ctl->cancel, host_flag(a.cancel));
+        if (!scope_barrier(y, BATCH ? a.bar : &a.ctl->barrier, members, epoch, &s_ok)) return;   // C
+        if (member == 0) { tp1 = wall_clock64(); ph_apply += tp1 - tp0; }
     }
 
     // ---- results
     if (is_cluster) store_and_sum(R, im, a.partial, tile * cs + rank);
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (member == 0 && threadIdx.x == 0) {
         uint64_t best = ldc(&a.tile_key[0]);
         for (int t = 1; t < T; ++t) {
             const uint64_t k = ldc(&a.tile_key[t]);
@@ -2374,6 +2376,91 @@ tiled_kernel(const KArgs a)
         a.dstat->final_peak = (double)key_value(best);
         a.dstat->model_flux = mflux;
     }
+}
+
+// Many independent images in one launch.  Problems are laid out largest
+// first; problem i owns the seats [seat0[i], seat0[i+1]) and each seat is one
+// workgroup of its cluster.
+//
+// Per-XCD schedule (when every XCD that holds workgroups holds at least the
+// largest cluster's worth, counted at launch): each XCD pulls whole problems
+// from the batch in order and runs them with its own workgroups, whose
+// exchanges then stay in that XCD's L2.  Otherwise a workgroup takes the next
+// seat of the whole batch from a device counter.  Either way tickets (seats)
+// go out in order and every workgroup is resident, so the earliest
+// unfinished problem always has all its members running: no deadlock.
+template <class Tile, bool TILED> __global__ void __launch_bounds__(WG) batched_kernel(const BatchArgs b)
+{
+    __shared__ int s_work, s_ok;
+    const Sync y{b.ctl, b.timeout_ticks};
+    const int total = b.seat0[b.n];
+    bool per_xcd = false;
+    uint32_t x = 0;
+    if (b.xcd_mode) {
+        x = xcc_id();
+        if (threadIdx.x == 0)
+            __hip_atomic_fetch_add(&b.xq->count[x * XQ_STRIDE], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        uint32_t epoch = 0;
+        if (!grid_barrier(y, epoch, &s_ok)) return;
+        if (threadIdx.x == 0) {
+            int ok = 1;
+            for (int i = 0; i < XQ_N; ++i) {
+                const uint32_t c = ld_agent32(&b.xq->count[i * XQ_STRIDE]);
+                if (c != 0 && c < (uint32_t)b.max_cs) ok = 0;
+            }
+            s_work = ok;
+        }
+        __syncthreads();
+        per_xcd = s_work != 0;
+        __syncthreads();
+    }
+    for (;;) {
+        // the next (problem << 12 | rank) for this workgroup, or -1
+        if (threadIdx.x == 0) {
+            int32_t w = -1;
+            if (per_xcd) {
+                w = xcd_ticket(b, y, x);
+            } else {
+                const int seat =
+                    (int)__hip_atomic_fetch_add(&b.ctl->seat, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (seat < total) {
+                    int lo = 0, hi = b.n;       // seat0[lo] <= seat < seat0[lo + 1]
+                    while (hi - lo > 1) {
+                        const int mid = (lo + hi) >> 1;
+                        if (b.seat0[mid] <= seat) lo = mid; else hi = mid;
+                    }
+                    w = (int32_t)(((uint32_t)lo << 12) | (uint32_t)(seat - b.seat0[lo]));
+                }
+            }
+            s_work = w;
+        }
+        __syncthreads();
+        const int32_t w = s_work;
+        __syncthreads();
+        if (w < 0) return;
+        if constexpr (TILED) {
+            const int ti = b.tiled_of[w >> 12];
+            if (ti >= 0) {
+                // member m of a tiled problem: tile m / cs, cluster rank m % cs
+                const KArgs &ta = b.tjobs[ti];
+                const int m = w & 0xFFF;
+                tiled_body<Tile, false, true>(ta, m, b.jobs[w >> 12].cs, ((m / ta.cs) << 16) | (m % ta.cs), false);
+                if (aborted(y)) return;
+                continue;
+            }
+        }
+        if (!run_plain<Tile>(b.jobs[w >> 12], w & 0xFFF, y, per_xcd, b.cancel, nullptr, 0)) return;
+        if (aborted(y)) return;
+    }
+}
+
+
+// The tiled form on the whole grid (one persistent, cooperative launch).
+template <class Tile, bool FFT>
+__global__ void __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(FFT && !Tile::kResident && !Tile::kWide ? 4 : 1)))
+tiled_kernel(const KArgs a)
+{
+    tiled_body<Tile, FFT, false>(a, 0, 0, a.role[blockIdx.x], true);
 }
 
 // ------------------------------------------------------ small kernels ----
@@ -2431,7 +2518,8 @@ __global__ void finalize_batch_kernel(const PlainJob *jobs, int n)
 
 #define INST(K, V, PT)                                                                   \
     template __global__ void hogbom_kernel<RegTile<K, V, PT>>(const KArgs a);           \
-    template __global__ void batched_kernel<RegTile<K, V, PT>>(const BatchArgs b);      \
+    template __global__ void batched_kernel<RegTile<K, V, PT>, false>(const BatchArgs b); \
+    template __global__ void batched_kernel<RegTile<K, V, PT>, true>(const BatchArgs b);  \
     template __global__ void tiled_kernel<RegTile<K, V, PT>, false>(const KArgs a);     \
     template __global__ void tiled_kernel<RegTile<K, V, PT>, true>(const KArgs a);
 #define INST_STREAM(V, PT)                                                               \

@@ -111,9 +111,12 @@ def test_batched_fp16_psfs(lib):
         assert_same_run(o, ref)
 
 
-def test_batched_config3_sampled(lib):
-    """The 256-problem workload (sides 128..1024, own PSFs, threshold 5 sigma) in
-    one launch; a spread sample of problems is checked against the oracle."""
+def test_batched_config3_all_problems(lib):
+    """The 256-problem workload (sides 128..1024, own PSFs, threshold 5 sigma)
+    in one launch.  Every problem is compared bit for bit with a clean_hogbom
+    call on it alone (a seat-queue or per-XCD scheduling error in any problem
+    shows), and a stratified quarter of them (64, the largest included) with
+    the oracle directly."""
     announce("batched config3")
     probs = synth.make_batch(256)
     dprobs = [dict(dirty=dev(p["dirty"]), psf=dev(p["psf"]), threshold=p["threshold"], max_iter=100000)
@@ -122,12 +125,76 @@ def test_batched_config3_sampled(lib):
     assert all(o["stats"]["stop_reason"] == 1 for o in outs)
     # 32-workgroup clusters at most, 256 workgroups: the per-XCD schedule
     assert all(o["stats"]["xcd_local_clusters"] == 1 for o in outs)
+    for q, o in zip(dprobs, outs):
+        s = lib.hogbom(q["dirty"], q["psf"], 0.1, q["threshold"], q["max_iter"])
+        assert o["stats"]["n_iter"] == s["stats"]["n_iter"]
+        assert np.array_equal(host(o["idx"]), host(s["idx"]))
+        assert np.array_equal(bits(host(o["flux"])), bits(host(s["flux"])))
+        assert np.array_equal(bits(host(o["residual"])), bits(host(s["residual"])))
+        assert np.array_equal(bits(host(o["model"])), bits(host(s["model"])))
     order = sorted(range(len(probs)), key=lambda i: probs[i]["n"])
-    sample = order[::37][:6] + [order[-1]]
+    sample = order[::4][:63] + [order[-1]]
     for i in sample:
         p = probs[i]
         ref = oracle.hogbom(p["dirty"], p["psf"], 0.1, p["threshold"], 100000)
         assert_same_run(outs[i], ref)
+
+
+MIXED = [
+    # side, sources, tiles, interval, threshold
+    (128, 30, (2, 2), 20, 0.0),
+    (96, 12, (1, 1), 1, 5e-3),
+    (160, 40, (2, 3), 9, 0.0),
+    (64, 8, (1, 1), 1, 0.0),
+    (192, 50, (3, 2), 40, 5e-3),
+    (120, 20, (2, 1), 60, 0.0),
+    (256, 60, (4, 4), 7, 0.0),
+    (80, 10, (1, 2), 15, 5e-3),
+]
+
+
+@pytest.mark.parametrize("level", [0.0, 0.5], ids=["interval", "flux-trigger"])
+def test_batched_mixed_plain_and_tiled(lib, level):
+    """Plain and tiled problems (grids 1 x 2 .. 4 x 4, intervals 7..60,
+    thresholds) in one launch: each is bit for bit the oracle's plain or tiled
+    run, with its own round count."""
+    probs, refs = [], []
+    for i, (n, ns, tiles, ivl, thr) in enumerate(MIXED):
+        d, p, _ = synth.make_problem(n, ns, 0.01, 2.1, (), 1e-3, config=98, problem=i)
+        max_iter = 1500
+        if tiles == (1, 1):
+            refs.append(oracle.hogbom(d, p, 0.1, thr, max_iter))
+        else:
+            refs.append(oracle.tiled(d, p, tiles, ivl, 0.1, thr, max_iter, level=level))
+        probs.append(dict(dirty=dev(d), psf=dev(p), threshold=thr, max_iter=max_iter, tiles=tiles, interval=ivl))
+    announce("batched mixed", level)
+    outs = lib.batched(probs, gain=0.1, level=level)
+    for (n, ns, tiles, ivl, thr), o, ref in zip(MIXED, outs, refs):
+        if tiles != (1, 1):
+            assert o["stats"]["n_rounds"] == ref["n_rounds"], (tiles, ivl)
+        assert_same_run(o, ref)
+
+
+def test_batched_tiled_equals_single_calls(lib):
+    """Tiled problems of a batch run alone through clean_tiled_feedback give
+    the same bits (FP16 PSFs, so the half-precision loads of the tiled
+    batched path are covered too)."""
+    probs = []
+    for i, (n, ns, tiles, ivl, thr) in enumerate(MIXED):
+        if tiles == (1, 1):
+            continue
+        d, p, _ = synth.make_problem(n, ns, 0.01, 2.1, (), 1e-3, config=99, problem=i)
+        probs.append(dict(dirty=dev(d), psf=lib.psf_to_f16(dev(p)), threshold=thr, max_iter=1200, tiles=tiles,
+                          interval=ivl))
+    announce("batched tiled = single calls")
+    outs = lib.batched(probs, gain=0.1)
+    for q, o in zip(probs, outs):
+        s = lib.tiled_feedback(q["dirty"], q["psf"], q["tiles"], q["interval"], 0.1, q["threshold"], q["max_iter"])
+        assert o["stats"]["n_rounds"] == s["stats"]["n_rounds"]
+        assert np.array_equal(host(o["idx"]), host(s["idx"]))
+        assert np.array_equal(bits(host(o["flux"])), bits(host(s["flux"])))
+        assert np.array_equal(bits(host(o["residual"])), bits(host(s["residual"])))
+        assert np.array_equal(bits(host(o["model"])), bits(host(s["model"])))
 
 
 def test_batched_degenerate_problems(lib):
