@@ -675,17 +675,24 @@ int run(bool tiled, const float *dirty, int ny, int nx, const void *psf, int psf
         const int cw = (int)((max_tile + per_wg - 1) / per_wg);
         if (((int64_t)cw * WG * 4) % tw == 0) {
             KFn fw = pick_wide(half, fft);
-            if (fft) dyn_lds = std::max(dyn_lds, (size_t)TR_LDS_WIDE);   // its transposes' tile group
-            if (dyn_lds > 48 * 1024)
-                HIPCHK(hipFuncSetAttribute((const void *)fw, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn_lds));
+            size_t wide_lds = dyn_lds;
+            if (fft) {
+                // its transposes' tile group, its padded one-level arenas
+                wide_lds = std::max(wide_lds, (size_t)TR_LDS_WIDE);
+                if (!fg.two_x) wide_lds = std::max(wide_lds, (size_t)8 * fft_pad_slots(1 << fg.lgx));
+                if (!fg.two_y) wide_lds = std::max(wide_lds, (size_t)8 * fft_pad_slots(1 << fg.lgy));
+            }
+            if (wide_lds > 48 * 1024)
+                HIPCHK(hipFuncSetAttribute((const void *)fw, hipFuncAttributeMaxDynamicSharedMemorySize, (int)wide_lds));
             int occ = 0;
-            HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void *)fw, WG, dyn_lds));
+            HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void *)fw, WG, wide_lds));
             occ = std::min(occ, MAX_WG_PER_CU);
             if (occ > 0 && place(cw, occ * ncu, W, role)) {
                 streamed = false;
                 fn = fw;
                 cs = cw;
                 ppt = 128;
+                dyn_lds = wide_lds;
             }
         }
     }

@@ -88,13 +88,17 @@ __device__ __forceinline__ uint32_t xcc_id()
 // wave has waited for its stores before the workgroup arrives, and readers
 // load after the barrier has released, so no cache write-back or invalidation
 // is needed and the PSF stays cached across rounds.
+// The pointers are cast to the global address space: generic (flat) accesses
+// would also count against the LDS counter, so that every wait for an LDS
+// access would wait for them as well.
 template <typename T> __device__ __forceinline__ T ldc(const T *p)
 {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return __hip_atomic_load((__attribute__((address_space(1))) const T *)p, __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
 }
 template <typename T> __device__ __forceinline__ void stc(T *p, T v)
 {
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store((__attribute__((address_space(1))) T *)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // |v| as the peak search orders it: IEEE magnitude bits (+Inf above every
@@ -1440,6 +1444,10 @@ __device__ void xfwd_one(const KArgs &a, const FftAxis &fx, int Ly, int rows, co
                          int *s_nz)
 {
     const int Lx = fx.L, lgx = fx.lg, nx = a.nx, tx = a.tx;
+    // LDS slot of transform element i (the wide-tile kernel's arena is padded)
+    auto at = [](int i) { return BIG ? pad16(i) : i; };
+    Tw13 T13;
+    if (BIG && lgx == F13) tw13_load(T13, fx.tw);
     #pragma clang loop unroll(disable)
     for (int pr = blockIdx.x; pr < (rows + 1) / 2; pr += gridDim.x) {
         const int r0 = 2 * pr;
@@ -1447,13 +1455,14 @@ __device__ void xfwd_one(const KArgs &a, const FftAxis &fx, int Ly, int rows, co
         if (KSRC) {
             #pragma clang loop unroll(disable)
             for (int x = threadIdx.x; x < Lx; x += WG)
-                lds[bitrev((uint32_t)x, lgx)] = make_float2(kernel_value<PT>(a, Ly, Lx, r0, x),
-                                                            has1 ? kernel_value<PT>(a, Ly, Lx, r0 + 1, x) : 0.0f);
+                lds[at(bitrev((uint32_t)x, lgx))] = make_float2(kernel_value<PT>(a, Ly, Lx, r0, x),
+                                                                has1 ? kernel_value<PT>(a, Ly, Lx, r0 + 1, x) : 0.0f);
             if (threadIdx.x == 0) *s_nz = 1;
             __syncthreads();
         } else {
+            const int slots = BIG ? fft_pad_slots(Lx) : Lx;
             #pragma clang loop unroll(disable)
-            for (int x = threadIdx.x; x < Lx; x += WG) lds[x] = make_float2(0.f, 0.f);
+            for (int x = threadIdx.x; x < slots; x += WG) lds[x] = make_float2(0.f, 0.f);
             if (threadIdx.x == 0) *s_nz = 0;
             __syncthreads();
             #pragma clang loop unroll(disable)
@@ -1468,7 +1477,7 @@ __device__ void xfwd_one(const KArgs &a, const FftAxis &fx, int Ly, int rows, co
                 #pragma clang loop unroll(disable)
                 for (int q = lo; q < hi; ++q) {
                     const size_t e = (size_t)t * a.interval + q;
-                    float *dst = (float *)&lds[bitrev((uint32_t)(ldc(&a.ag_pos[e]) - b0), lgx)];
+                    float *dst = (float *)&lds[at(bitrev((uint32_t)(ldc(&a.ag_pos[e]) - b0), lgx))];
                     dst[j >= tx] = ldc(&a.ag_flux[e]);
                 }
             }
@@ -1480,9 +1489,15 @@ __device__ void xfwd_one(const KArgs &a, const FftAxis &fx, int Ly, int rows, co
             for (int k = threadIdx.x; k < fx.H; k += WG) store_split(o0, o1, has1, k, make_float2(0.f, 0.f),
                                                                     make_float2(0.f, 0.f));
         } else {
-            fft_lds<BIG>(lds, lgx, fx.tw, false);
+            if constexpr (BIG) {
+                if (lgx == F13) fft13<false, false>(lds, T13);
+                else fft_big<false>(lds, lgx, fx.tw, false);
+            } else {
+                fft_lds(lds, lgx, fx.tw, false);
+            }
             #pragma clang loop unroll(disable)
-            for (int k = threadIdx.x; k < fx.H; k += WG) store_split(o0, o1, has1, k, lds[k], lds[(Lx - k) & (Lx - 1)]);
+            for (int k = threadIdx.x; k < fx.H; k += WG)
+                store_split(o0, o1, has1, k, lds[at(k)], lds[at((Lx - k) & (Lx - 1))]);
         }
         __syncthreads();
     }
@@ -1590,53 +1605,108 @@ __device__ void xfwd_two_b(const KArgs &a, const FftAxis &fx, int rows, float2 *
 // y, one level, per carried column: forward transform of the `rows` values
 // in fft_b; then either (PRE) store the spectrum as the PSF kernel's, or
 // multiply by it, transform back and store the first `rows` values.
+// The wide-tile kernel's y phase at length 8192, per carried column: the
+// column and its zero padding (natural order) -> forward in frequency order
+// -> product with the PSF kernel's spectrum (held in the same bit-reversed
+// order) -> inverse in time order -> the first `rows` values.  The next
+// column's values and spectrum are loaded while this one is transformed.
+__device__ void ycol13(const KArgs &a, const FftAxis &fx, int rows, float2 *lds)
+{
+    constexpr int L = 1 << F13, M = L / WG;
+    Tw13 T;
+    tw13_load(T, a.tw_y);
+    const int t = threadIdx.x;
+    float2 *const slot = lds + pad16(t);           // element t + WG m at slot[pad16c(WG m)]
+    float2 nb[M], nk[M];
+    auto load_b = [&](int c) {
+        const float2 *b = a.fft_b + (size_t)c * rows;
+#pragma unroll
+        for (int m = 0; m < M; ++m) nb[m] = t + WG * m < rows ? ldc2(b + t + WG * m) : make_float2(0.f, 0.f);
+    };
+    auto load_k = [&](int c) {
+        const float2 *k = a.fft_ks + (size_t)c * L;
+#pragma unroll
+        for (int m = 0; m < M; ++m) nk[m] = ldc2(k + t + WG * m);
+    };
+    int col = blockIdx.x;
+    if (col < fx.H) {
+        load_b(col);
+        load_k(col);
+    }
+    #pragma clang loop unroll(disable)
+    for (; col < fx.H; col += gridDim.x) {
+        const int nxt = col + gridDim.x;
+        __syncthreads();
+#pragma unroll
+        for (int m = 0; m < M; ++m) slot[pad16c(WG * m)] = nb[m];
+        if (nxt < fx.H) load_b(nxt);
+        fft13<true, false>(lds, T);
+#pragma unroll
+        for (int m = 0; m < M; ++m) slot[pad16c(WG * m)] = twmul<false>(slot[pad16c(WG * m)], nk[m]);
+        if (nxt < fx.H) load_k(nxt);
+        fft13<false, true>(lds, T);
+        float2 *b = a.fft_b + (size_t)col * rows;
+#pragma unroll
+        for (int m = 0; m < M; ++m)
+            if (t + WG * m < rows) stc2(b + t + WG * m, slot[pad16c(WG * m)]);
+    }
+}
+
 template <bool PRE, bool BIG = false>
 __device__ void ycol_one(const KArgs &a, const FftAxis &fx, const FftAxis &fy, int rows, float2 *lds)
 {
+    if constexpr (BIG && !PRE) {
+        if (fy.lg == F13) {
+            ycol13(a, fx, rows, lds);
+            return;
+        }
+    }
     #pragma clang loop unroll(disable)
     for (int col = blockIdx.x; col < fx.H; col += gridDim.x) {
         float2 *b = a.fft_b + (size_t)col * rows;
+        float2 *ks = a.fft_ks + (size_t)col * fy.L;
         if constexpr (BIG) {
-            // one sweep: the column's rows and the zero padding, bit-reversed
-            __syncthreads();
-            #pragma clang loop unroll(disable)
-            for (int v = threadIdx.x; v < fy.L; v += WG)
-                lds[bitrev((uint32_t)v, fy.lg)] = v < rows ? ldc2(&b[v]) : make_float2(0.f, 0.f);
+            // padded arena, no permutation: the column and its zero padding in
+            // natural order, forward in frequency order (bit-reversed spectrum,
+            // the PSF kernel's spectrum stored in the same order), product,
+            // inverse in time order (natural output)
+            staged<16>(fy.L, true, [&](int v) { return v < rows ? ldc2(&b[v]) : make_float2(0.f, 0.f); },
+                       [&](int v, float2 z) { lds[pad16(v)] = z; });
+            if (fy.lg == F13) {
+                Tw13 T;
+                tw13_load(T, fy.tw);
+                fft13<true, false>(lds, T);
+            } else {
+                fft_big<true>(lds, fy.lg, fy.tw, false);
+            }
+            if (PRE) {
+                #pragma clang loop unroll(disable)
+                for (int v = threadIdx.x; v < fy.L; v += WG) stc2(&ks[v], lds[pad16(v)]);
+            } else {
+                staged<16>(fy.L, false, [&](int v) { return ldc2(&ks[v]); },
+                           [&](int v, float2 k) { lds[pad16(v)] = cmul(lds[pad16(v)], k); });
+                fft_big<false>(lds, fy.lg, fy.tw, true);
+                #pragma clang loop unroll(disable)
+                for (int v = threadIdx.x; v < rows; v += WG) stc2(&b[v], lds[pad16(v)]);
+            }
         } else {
             #pragma clang loop unroll(disable)
             for (int v = threadIdx.x; v < fy.L; v += WG) lds[v] = make_float2(0.f, 0.f);
             __syncthreads();
             #pragma clang loop unroll(disable)
             for (int v = threadIdx.x; v < rows; v += WG) lds[bitrev((uint32_t)v, fy.lg)] = ldc2(&b[v]);
-        }
-        fft_lds<BIG>(lds, fy.lg, fy.tw, false);
-        float2 *ks = a.fft_ks + (size_t)col * fy.L;
-        if (PRE) {
-            #pragma clang loop unroll(disable)
-            for (int v = threadIdx.x; v < fy.L; v += WG) stc2(&ks[v], lds[v]);
-        } else {
-            if constexpr (BIG) {
-                // the product with the PSF spectrum and the bit-reversal
-                // permutation in one sweep: each pair (v, bitrev v) is
-                // multiplied and swapped by one thread
+            fft_lds(lds, fy.lg, fy.tw, false);
+            if (PRE) {
                 #pragma clang loop unroll(disable)
-                for (int v = threadIdx.x; v < fy.L; v += WG) {
-                    const int w = (int)bitrev((uint32_t)v, fy.lg);
-                    if (v > w) continue;
-                    const float2 pv = cmul(lds[v], ldc2(&ks[v]));
-                    const float2 pw = cmul(lds[w], ldc2(&ks[w]));
-                    lds[w] = pv;
-                    lds[v] = pw;
-                }
-                __syncthreads();
+                for (int v = threadIdx.x; v < fy.L; v += WG) stc2(&ks[v], lds[v]);
             } else {
                 #pragma clang loop unroll(disable)
                 for (int v = threadIdx.x; v < fy.L; v += WG) lds[v] = cmul(lds[v], ldc2(&ks[v]));
                 bitrev_permute(lds, fy.lg);
+                fft_lds(lds, fy.lg, fy.tw, true);
+                #pragma clang loop unroll(disable)
+                for (int v = threadIdx.x; v < rows; v += WG) stc2(&b[v], lds[v]);
             }
-            fft_lds<BIG>(lds, fy.lg, fy.tw, true);
-            #pragma clang loop unroll(disable)
-            for (int v = threadIdx.x; v < rows; v += WG) stc2(&b[v], lds[v]);
         }
         __syncthreads();
     }
@@ -1759,6 +1829,9 @@ template <bool BIG = false>
 __device__ void xinv_one(const KArgs &a, const FftAxis &fx, float scale, float2 *lds)
 {
     const int Lx = fx.L, lgx = fx.lg, ny = a.ny, nx = a.nx;
+    auto at = [](int i) { return BIG ? pad16(i) : i; };
+    Tw13 T13;
+    if (BIG && lgx == F13) tw13_load(T13, fx.tw);
     #pragma clang loop unroll(disable)
     for (int pr = blockIdx.x; pr < (ny + 1) / 2; pr += gridDim.x) {
         const int r0 = 2 * pr;
@@ -1768,13 +1841,18 @@ __device__ void xinv_one(const KArgs &a, const FftAxis &fx, float scale, float2 
         for (int k = threadIdx.x; k < fx.H; k += WG) {
             const float2 A = ldc2(&i0[k]);
             const float2 B = has1 ? ldc2(&i1[k]) : make_float2(0.f, 0.f);
-            lds[bitrev((uint32_t)k, lgx)] = make_float2(A.x - B.y, A.y + B.x);
-            if (k > 0 && k < Lx / 2) lds[bitrev((uint32_t)(Lx - k), lgx)] = make_float2(A.x + B.y, B.x - A.y);
+            lds[at(bitrev((uint32_t)k, lgx))] = make_float2(A.x - B.y, A.y + B.x);
+            if (k > 0 && k < Lx / 2) lds[at(bitrev((uint32_t)(Lx - k), lgx))] = make_float2(A.x + B.y, B.x - A.y);
         }
-        fft_lds<BIG>(lds, lgx, fx.tw, true);
+        if constexpr (BIG) {
+            if (lgx == F13) fft13<false, true>(lds, T13);
+            else fft_big<false>(lds, lgx, fx.tw, true);
+        } else {
+            fft_lds(lds, lgx, fx.tw, true);
+        }
         #pragma clang loop unroll(disable)
         for (int x = threadIdx.x; x < nx; x += WG) {
-            const float2 z = lds[x];
+            const float2 z = lds[at(x)];
             stc(&a.accbuf[(size_t)r0 * nx + x], z.x * scale);
             if (has1) stc(&a.accbuf[(size_t)(r0 + 1) * nx + x], z.y * scale);
         }
@@ -1931,6 +2009,7 @@ __device__ bool fft_feedback(const KArgs &a, const Sync &y, uint32_t &epoch, int
         FFT_BARRIER();
         xinv_two_b(a, fx, scale, lds);
     }
+    __syncthreads();
     return true;
 }
 
