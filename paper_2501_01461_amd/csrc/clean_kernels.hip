@@ -1417,17 +1417,6 @@ __device__ __forceinline__ int tile_row_of(const KArgs &a, int y)
     return i;
 }
 
-// First index k in [lo, hi) of tile t's aggregated list with position >= key.
-__device__ __forceinline__ int lower_pos(const KArgs &a, int t, int lo, int hi, int32_t key)
-{
-    const size_t base = (size_t)t * a.interval;
-    while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if (ldc(&a.ag_pos[base + mid]) < key) lo = mid + 1; else hi = mid;
-    }
-    return lo;
-}
-
 // Split of a row pair's transform Z (row r0 real part, r0+1 imaginary part)
 // at bin k: A = (Z[k] + conj Z[L-k]) / 2 and B = (Z[k] - conj Z[L-k]) / 2i.
 __device__ __forceinline__ void store_split(float2 *o0, float2 *o1, bool has1, int c, float2 zk, float2 zm)
@@ -1465,21 +1454,40 @@ __device__ void xfwd_one(const KArgs &a, const FftAxis &fx, int Ly, int rows, co
             for (int x = threadIdx.x; x < slots; x += WG) lds[x] = make_float2(0.f, 0.f);
             if (threadIdx.x == 0) *s_nz = 0;
             __syncthreads();
+            // the components of the two rows: the aggregated list of every
+            // tile a row crosses is scanned by G threads, eight entries per
+            // thread in flight (positions are distinct, so no two threads
+            // write one slot)
+            const int G = max(1, WG / (2 * tx));
+            const int tr0 = tile_row_of(a, r0), tr1 = has1 ? tile_row_of(a, r0 + 1) : tr0;
             #pragma clang loop unroll(disable)
-            for (int j = threadIdx.x; j < 2 * tx; j += WG) {
-                const int row = r0 + (j >= tx);
+            for (int j = threadIdx.x; j < 2 * tx * G; j += WG) {
+                const int part = j / (tx * G);           // 0: row r0 (real part), 1: row r0 + 1
+                const int row = r0 + part;
                 if (row >= rows) continue;
-                const int t = tile_row_of(a, row) * tx + (j % tx);
+                const int t = (part ? tr1 : tr0) * tx + (j / G) % tx, q = j % G;
                 const int n = s_off[t + 1] - s_off[t];
                 const int32_t b0 = row * nx;
-                const int lo = lower_pos(a, t, 0, n, b0), hi = lower_pos(a, t, lo, n, b0 + nx);
-                if (hi > lo) atomicAdd(s_nz, hi - lo);
+                const size_t base = (size_t)t * a.interval;
+                int cnt = 0;
                 #pragma clang loop unroll(disable)
-                for (int q = lo; q < hi; ++q) {
-                    const size_t e = (size_t)t * a.interval + q;
-                    float *dst = (float *)&lds[at(bitrev((uint32_t)(ldc(&a.ag_pos[e]) - b0), lgx))];
-                    dst[j >= tx] = ldc(&a.ag_flux[e]);
+                for (int e0 = q; e0 < n; e0 += 8 * G) {
+                    int32_t pos[8];
+                    float fl[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        const int e = e0 + u * G;
+                        pos[u] = e < n ? ldc(&a.ag_pos[base + e]) : -1;
+                        fl[u] = e < n ? ldc(&a.ag_flux[base + e]) : 0.0f;
+                    }
+#pragma unroll
+                    for (int u = 0; u < 8; ++u)
+                        if (pos[u] >= b0 && pos[u] < b0 + nx) {
+                            ((float *)&lds[at(bitrev((uint32_t)(pos[u] - b0), lgx))])[part] = fl[u];
+                            ++cnt;
+                        }
                 }
+                if (cnt) atomicAdd(s_nz, cnt);
             }
             __syncthreads();
         }
@@ -1822,16 +1830,66 @@ __device__ void ycol_two_c(const KArgs &a, const FftAxis &fx, const FftAxis &fy,
     }
 }
 
+// The wide-tile kernel's x inverse at length 8192 (the steps of xinv_one):
+// the next row pair's carried bins are loaded while this one is transformed.
+__device__ void xinv13(const KArgs &a, const FftAxis &fx, float scale, float2 *lds)
+{
+    constexpr int L = 1 << F13, H = L / 2 + 1, M = (H + WG - 1) / WG;
+    Tw13 T;
+    tw13_load(T, a.tw_x);
+    const int t = threadIdx.x, ny = a.ny, nx = a.nx, npr = (ny + 1) / 2;
+    float2 nA[M], nB[M];
+    auto load = [&](int pr) {
+        const float2 *i0 = a.fft_a + (size_t)(2 * pr) * H, *i1 = i0 + H;
+        const bool has1 = 2 * pr + 1 < ny;
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            const int k = t + WG * m;
+            nA[m] = k < H ? ldc2(i0 + k) : make_float2(0.f, 0.f);
+            nB[m] = k < H && has1 ? ldc2(i1 + k) : make_float2(0.f, 0.f);
+        }
+    };
+    int pr = blockIdx.x;
+    if (pr < npr) load(pr);
+    #pragma clang loop unroll(disable)
+    for (; pr < npr; pr += gridDim.x) {
+        const int r0 = 2 * pr;
+        const bool has1 = r0 + 1 < ny;
+        __syncthreads();
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            const int k = t + WG * m;
+            if (k < H) {
+                const float2 A = nA[m], B = nB[m];
+                lds[pad16(bitrev((uint32_t)k, F13))] = make_float2(A.x - B.y, A.y + B.x);
+                if (k > 0 && k < L / 2) lds[pad16(bitrev((uint32_t)(L - k), F13))] = make_float2(A.x + B.y, B.x - A.y);
+            }
+        }
+        if (pr + (int)gridDim.x < npr) load(pr + gridDim.x);
+        fft13<false, true>(lds, T);
+        #pragma clang loop unroll(disable)
+        for (int x = t; x < nx; x += WG) {
+            const float2 z = lds[pad16(x)];
+            stc(&a.accbuf[(size_t)r0 * nx + x], z.x * scale);
+            if (has1) stc(&a.accbuf[(size_t)(r0 + 1) * nx + x], z.y * scale);
+        }
+    }
+}
+
 // x inverse, one level: row pairs rebuilt from their carried bins (Hermitian
 // symmetry gives the rest), one inverse transform, real part -> row 2m,
 // imaginary part -> row 2m+1, scaled, into the feedback buffer.
 template <bool BIG = false>
 __device__ void xinv_one(const KArgs &a, const FftAxis &fx, float scale, float2 *lds)
 {
+    if constexpr (BIG) {
+        if (fx.lg == F13) {
+            xinv13(a, fx, scale, lds);
+            return;
+        }
+    }
     const int Lx = fx.L, lgx = fx.lg, ny = a.ny, nx = a.nx;
     auto at = [](int i) { return BIG ? pad16(i) : i; };
-    Tw13 T13;
-    if (BIG && lgx == F13) tw13_load(T13, fx.tw);
     #pragma clang loop unroll(disable)
     for (int pr = blockIdx.x; pr < (ny + 1) / 2; pr += gridDim.x) {
         const int r0 = 2 * pr;
@@ -1844,12 +1902,8 @@ __device__ void xinv_one(const KArgs &a, const FftAxis &fx, float scale, float2 
             lds[at(bitrev((uint32_t)k, lgx))] = make_float2(A.x - B.y, A.y + B.x);
             if (k > 0 && k < Lx / 2) lds[at(bitrev((uint32_t)(Lx - k), lgx))] = make_float2(A.x + B.y, B.x - A.y);
         }
-        if constexpr (BIG) {
-            if (lgx == F13) fft13<false, true>(lds, T13);
-            else fft_big<false>(lds, lgx, fx.tw, true);
-        } else {
-            fft_lds(lds, lgx, fx.tw, true);
-        }
+        if constexpr (BIG) fft_big<false>(lds, lgx, fx.tw, true);
+        else fft_lds(lds, lgx, fx.tw, true);
         #pragma clang loop unroll(disable)
         for (int x = threadIdx.x; x < nx; x += WG) {
             const float2 z = lds[at(x)];
