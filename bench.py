@@ -444,6 +444,14 @@ def main():
             dprobs.append(dict(dirty=torch.from_numpy(q["dirty"]).to(dev), psf=P.psf_to_f16(pq) if args.psf_f16 else pq,
                                threshold=q["threshold"], max_iter=100000))
         nb_steps = max(1, min(3, args.steps))
+        # the library's built-in shape rule, then the batch tuner's choice
+        # (batched() with px_per_thread=0 uses the tuned shape from then on)
+        rule = P.batched(dprobs, model=False)[0]["stats"]
+        t1 = time.perf_counter()
+        tune = P.autotune_batched(dprobs, trial_iter=2000)
+        tune_s = time.perf_counter() - t1
+        log(f"batch tuner: {tune['px_per_thread']} px/thread (trial ms {tune['trial_ms']}); the rule's "
+            f"{rule['px_per_thread']} px/thread ran in {rule['device_ms']:.1f} ms")
         P.batched(dprobs)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
@@ -468,6 +476,11 @@ def main():
                    "method_accounting_GBs": b_method / (b_kms * 1e-3) / 1e9,
                    "one_call_per_problem_ms": seq_ms, "one_call_per_problem_kernel_ms": seq_dev,
                    "speedup_vs_one_call_per_problem": seq_ms / b_ms,
+                   "launch": {"px_per_thread": outs[0]["stats"]["px_per_thread"],
+                              "workgroups": outs[0]["stats"]["workgroups"], "from": "clean_autotune_batched",
+                              "tuner_trial_ms": dict(zip(("8", "16", "32", "64"), tune["trial_ms"])),
+                              "tuner_s": tune_s, "rule_px_per_thread": rule["px_per_thread"],
+                              "rule_kernel_ms": rule["device_ms"]},
                    "workload": "256 images, sides drawn from {128..1024}, own Y-array PSF at 2x side, 5-200 "
                                "sources, threshold 5e-3 Jy"}
         if not args.no_jy:

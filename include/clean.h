@@ -328,6 +328,24 @@ int clean_batched(const clean_problem *probs, int n, const clean_params *shared,
                   clean_stats *stats, void *stream);
 
 /*
+ * clean_autotune_batched -- picks the pixels per thread of clean_batched for
+ * this batch by timing one trial launch per candidate (8, 16, 32, 64; those
+ * that do not fit the batch are skipped) with every problem's max_iter capped
+ * at trial_iter, and writes the fastest to *px_per_thread.  The shape does
+ * not change any result, only the speed.  The trials overwrite the problems'
+ * residual, component and model arrays.  The choice is cached per process by
+ * device and batch signature (PSF dtype, flags, and every problem's image,
+ * PSF and tile-grid sizes and interval, in order); clean_batched with
+ * shared->px_per_thread = 0 then uses it instead of its built-in rule.
+ *   trial_ms  host array of CLEAN_BATCH_TUNE_CANDIDATES (may be NULL): each
+ *             candidate's launch time in ms, -1 where it did not fit.
+ * Errors as clean_batched; CLEAN_E_UNSUPPORTED if no candidate fits.
+ */
+#define CLEAN_BATCH_TUNE_CANDIDATES 4
+int clean_autotune_batched(const clean_problem *probs, int n, const clean_params *shared,
+                           int64_t trial_iter, int *px_per_thread, float *trial_ms, void *stream);
+
+/*
  * clean_autotune -- picks the launch shape (p->wg_per_tile, p->px_per_thread)
  * of clean_hogbom (tiles_y = tiles_x = 1) or clean_tiled_feedback for this
  * image, PSF dtype and tile grid by timing trial runs of `trial_iter` minor

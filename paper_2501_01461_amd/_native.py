@@ -26,7 +26,7 @@ FLAG_FFT_TWO_LEVEL = 8
 
 # every symbol include/clean.h declares
 EXPORTS = ("clean_hogbom", "clean_hogbom_noalloc", "clean_tiled_feedback", "clean_batched", "clean_autotune",
-           "clean_autotune_interval", "clean_autotune_plan",
+           "clean_autotune_interval", "clean_autotune_plan", "clean_autotune_batched",
            "clean_beam_fit", "clean_restore", "clean_workspace_size", "clean_set_workspace_limit", "clean_psf_to_f16",
            "clean_bandwidth_probe",
            "clean_strerror",
@@ -91,6 +91,8 @@ def load():
     lib.clean_hogbom_noalloc.argtypes = [P, i32, i32, P, i32, i32, C.POINTER(Params), P, P, P, i64, P,
                                          C.POINTER(Stats), P]
     lib.clean_batched.argtypes = [C.POINTER(Problem), i32, C.POINTER(Params), C.POINTER(Stats), P]
+    lib.clean_autotune_batched.argtypes = [C.POINTER(Problem), i32, C.POINTER(Params), i64, C.POINTER(i32),
+                                           C.POINTER(C.c_float), P]
     lib.clean_autotune.argtypes = [P, i32, i32, P, i32, i32, i32, i32, i32, C.POINTER(Params), P, P, P, i64, i64,
                                    C.POINTER(Params), P]
     lib.clean_autotune.restype = C.c_int
@@ -255,26 +257,17 @@ def tiled_feedback(dirty, psf, tiles=(2, 2), interval=100, gain=0.1, threshold=0
     return dict(residual=res, idx=idx[:n], flux=flux[:n], model=mod, stats=st.as_dict())
 
 
-def batched(problems, gain=0.1, model=True, check_finite=False, px_per_thread=0, cancel=None, level=0.0):
-    """Independent Hogbom problems in one persistent launch.
-
-    problems: list of dicts with device tensors "dirty" (float32 2-D) and "psf"
-    (float32 or float16, all the same dtype), and "threshold", "max_iter",
-    optional "cap", and for a tiled problem "tiles" (ty, tx) and "interval".
-    level: the flux trigger of the tiled problems.  Returns a list of
-    dict(residual, idx, flux, model, stats).  The outputs are views into four
-    allocations shared by the whole batch.
-    """
+def _batch(problems, model):
+    """The host problem array of a batch and its outputs: four allocations
+    shared by the whole batch, one view per problem."""
     torch = _torch()
-    lib = load()
     n = len(problems)
     arr = (Problem * max(n, 1))()
     keep, outs = [], []
     psf_dtype = None
     prep = [_prep(q["dirty"], q["psf"]) for q in problems]
     caps = [max(int(q.get("cap", q["max_iter"])), 1) for q in problems]
-    # the outputs of all problems in four allocations, one view per problem,
-    # each starting on a 256-byte boundary (64 elements) like a tensor of its own
+    # each view starts on a 256-byte boundary (64 elements) like a tensor of its own
     npix = [d.numel() for d, _ in prep]
     up = lambda v: (v + 63) // 64 * 64
     dev_ = prep[0][0].device if n else None
@@ -304,9 +297,26 @@ def batched(problems, gain=0.1, model=True, check_finite=False, px_per_thread=0,
                          mod.data_ptr() if mod is not None else None, cap, int(q["max_iter"]),
                          float(q["threshold"]), ny, nx, p.shape[0], p.shape[1], int(ty), int(tx),
                          int(q.get("interval", 1)))
+    dt = PSF_F16 if psf_dtype == torch.float16 else PSF_F32
+    return arr, outs, keep, dt
+
+
+def batched(problems, gain=0.1, model=True, check_finite=False, px_per_thread=0, cancel=None, level=0.0):
+    """Independent Hogbom problems in one persistent launch.
+
+    problems: list of dicts with device tensors "dirty" (float32 2-D) and "psf"
+    (float32 or float16, all the same dtype), and "threshold", "max_iter",
+    optional "cap", and for a tiled problem "tiles" (ty, tx) and "interval".
+    level: the flux trigger of the tiled problems.  px_per_thread 0: the shape
+    autotune_batched chose for this batch, else the library's rule.  Returns a
+    list of dict(residual, idx, flux, model, stats).  The outputs are views
+    into four allocations shared by the whole batch.
+    """
+    lib = load()
+    n = len(problems)
     if n == 0:
         return []
-    dt = PSF_F16 if psf_dtype == torch.float16 else PSF_F32
+    arr, outs, keep, dt = _batch(problems, model)
     prm = Params(float(gain), 0.0, 0, dt, FLAG_CHECK_FINITE if check_finite else 0, 0, int(px_per_thread),
                  float(level), _cancel(cancel))
     stats = (Stats * n)()
@@ -317,6 +327,21 @@ def batched(problems, gain=0.1, model=True, check_finite=False, px_per_thread=0,
         k = stats[i].n_iter
         res.append(dict(residual=r, idx=idx[:k], flux=flux[:k], model=mod, stats=stats[i].as_dict()))
     return res
+
+
+def autotune_batched(problems, gain=0.1, trial_iter=2000, level=0.0):
+    """The batch launch shape the library's tuner measures fastest: returns
+    dict(px_per_thread, trial_ms) (one launch time per candidate 8, 16, 32, 64;
+    -1 where it did not fit).  Later batched() calls on batches of the same
+    signature with px_per_thread=0 use it."""
+    lib = load()
+    arr, outs, keep, dt = _batch(problems, False)
+    prm = Params(float(gain), 0.0, 0, dt, 0, 0, 0, float(level), None)
+    best = C.c_int32(0)
+    ms = (C.c_float * 4)()
+    _check(lib.clean_autotune_batched(arr, len(problems), C.byref(prm), int(trial_iter), C.byref(best), ms,
+                                      _stream()))
+    return dict(px_per_thread=best.value, trial_ms=[float(v) for v in ms])
 
 
 def autotune(dirty, psf, tiles=(1, 1), interval=100, gain=0.1, threshold=0.0, max_iter=1000, trial_iter=2000,

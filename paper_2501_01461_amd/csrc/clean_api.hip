@@ -923,6 +923,60 @@ int clean_tiled_feedback(const float *dirty, int ny, int nx, const void *psf, in
                comp_flux, comp_cap, model, workspace, workspace_bytes, stats, stream);
 }
 
+namespace {
+// Launch shapes chosen by clean_autotune_batched, per process, keyed by the
+// device and a signature of the batch: the PSF dtype, the flags and every
+// problem's image, PSF and tile-grid sizes and interval, in order (FNV-1a).
+std::mutex g_btune_mu;
+std::map<std::pair<int, uint64_t>, int> g_btune_cache;
+
+uint64_t batch_signature(const clean_problem *probs, int n, const clean_params *p)
+{
+    uint64_t h = 1469598103934665603ull;
+    auto mix = [&](int64_t v) {
+        for (int b = 0; b < 8; ++b) {
+            h ^= (uint64_t)(v >> (8 * b)) & 0xFFu;
+            h *= 1099511628211ull;
+        }
+    };
+    mix(n);
+    mix(p->psf_dtype);
+    mix(p->flags);
+    for (int i = 0; i < n; ++i) {
+        const clean_problem &q = probs[i];
+        mix(q.ny);
+        mix(q.nx);
+        mix(q.psf_ny);
+        mix(q.psf_nx);
+        mix(q.tiles_y);
+        mix(q.tiles_x);
+        mix(q.tiles_y * q.tiles_x > 1 ? q.interval : 0);
+    }
+    return h;
+}
+
+// 4 when every tile of every problem is a multiple of 4 pixels wide (the
+// batched kernels' 4-wide groups), else 1: the rule clean_batched applies.
+int batch_group_width(const clean_problem *probs, int n)
+{
+    for (int i = 0; i < n; ++i) {
+        const int tx = probs[i].tiles_x > 0 ? probs[i].tiles_x : 1;
+        for (int b = 0; b < tx; ++b)
+            if ((int)((int64_t)(b + 1) * probs[i].nx / tx - (int64_t)b * probs[i].nx / tx) % 4) return 1;
+    }
+    return 4;
+}
+
+bool btune_lookup(int dev, uint64_t sig, int &ppt)
+{
+    std::lock_guard<std::mutex> lk(g_btune_mu);
+    auto it = g_btune_cache.find({dev, sig});
+    if (it == g_btune_cache.end()) return false;
+    ppt = it->second;
+    return true;
+}
+}   // namespace
+
 int clean_batched(const clean_problem *probs, int n, const clean_params *shared, clean_stats *stats, void *stream_v)
 {
     g_last_error.clear();
@@ -1011,7 +1065,9 @@ int clean_batched(const clean_problem *probs, int n, const clean_params *shared,
         return CLEAN_OK;
     };
     int ppt = shared->px_per_thread;
+    if (ppt == 0 && btune_lookup(dev, batch_signature(probs, n, shared), ppt) && !valid_ppt(V, ppt)) ppt = 0;
     if (ppt == 0) {
+        // no tuned shape for this batch (clean_autotune_batched): the rule.
         // 32 pixels per thread when the per-XCD schedule takes it: two
         // workgroups per CU and exchanges inside one L2 (the fastest shape
         // on 256 images of 128^2..1024^2).  Else 64: half the workgroups per
@@ -1264,6 +1320,47 @@ int clean_batched(const clean_problem *probs, int n, const clean_params *shared,
             s.exchange_levels = 1;
         }
     }
+    return CLEAN_OK;
+}
+
+int clean_autotune_batched(const clean_problem *probs, int n, const clean_params *shared, int64_t trial_iter,
+                           int *px_per_thread, float *trial_ms, void *stream)
+{
+    g_last_error.clear();
+    if (!probs || !shared || !px_per_thread) return fail(CLEAN_E_INVAL, "probs, shared and px_per_thread must be non-NULL");
+    if (n < 1 || n > 65536) return fail(CLEAN_E_INVAL, "batch of %d problems not in [1, 65536]", n);
+    if (trial_iter < 1) return fail(CLEAN_E_INVAL, "trial_iter must be >= 1");
+    *px_per_thread = 0;
+    static const int cand[CLEAN_BATCH_TUNE_CANDIDATES] = {8, 16, 32, 64};
+    if (trial_ms)
+        for (int c = 0; c < CLEAN_BATCH_TUNE_CANDIDATES; ++c) trial_ms[c] = -1.f;
+    // trial copies: each problem capped at trial_iter iterations
+    std::vector<clean_problem> trial(probs, probs + n);
+    for (auto &q : trial) q.max_iter = std::min<int64_t>(q.max_iter, trial_iter);
+    std::vector<clean_stats> st(n);
+    clean_params sp = *shared;
+    float best_ms = -1.f;
+    int best = 0;
+    const int V = batch_group_width(probs, n);
+    for (int c = 0; c < CLEAN_BATCH_TUNE_CANDIDATES; ++c) {
+        if (!valid_ppt(V, cand[c])) continue;
+        sp.px_per_thread = cand[c];
+        const int rc = clean_batched(trial.data(), n, &sp, st.data(), stream);
+        if (rc == CLEAN_E_UNSUPPORTED) continue;   // shape does not fit this batch
+        if (rc) return rc;                         // argument errors as clean_batched's
+        if (trial_ms) trial_ms[c] = st[0].device_ms;
+        if (best_ms < 0 || st[0].device_ms < best_ms) {
+            best_ms = st[0].device_ms;
+            best = cand[c];
+        }
+    }
+    g_last_error.clear();
+    if (best_ms < 0) return fail(CLEAN_E_UNSUPPORTED, "no candidate launch shape fits this batch");
+    *px_per_thread = best;
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_btune_mu);
+    g_btune_cache[{dev, batch_signature(probs, n, shared)}] = best;
     return CLEAN_OK;
 }
 

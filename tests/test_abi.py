@@ -104,6 +104,28 @@ def test_batched_argument_errors(lib):
     assert lib.clean_batched(arr, 0, C.byref(p), st, None) == 0
 
 
+def test_autotune_batched_argument_errors(lib):
+    p = params()
+    best = C.c_int(7)
+    ms = (C.c_float * 4)()
+    arr = (N.Problem * 1)()
+
+    def call(a=arr, n=1, pp=p, trial=100, out=best):
+        return lib.clean_autotune_batched(a, n, C.byref(pp) if pp else None, trial,
+                                          C.byref(out) if out is not None else None, ms, None)
+    assert call(a=None) == INVAL
+    assert call(pp=None) == INVAL
+    assert call(out=None) == INVAL
+    assert call(n=0) == INVAL
+    assert call(n=70000) == INVAL
+    assert call(trial=0) == INVAL
+    # a bad problem is reported as clean_batched reports it, not as "no shape fits"
+    arr[0] = N.Problem(0x1000, 0x1000, 0x1000, 0x1000, 0x1000, None, 10, 10, 0.0, 16, 16, 16, 32)
+    assert call() == INVAL
+    assert b"problem 0" in lib.clean_last_error()
+    assert best.value == 0
+
+
 def test_workspace_size(lib):
     p = params()
     a = lib.clean_workspace_size(1024, 1024, 2, 2, 100, C.byref(p))

@@ -197,6 +197,36 @@ def test_batched_tiled_equals_single_calls(lib):
         assert np.array_equal(bits(host(o["model"])), bits(host(s["model"])))
 
 
+def test_batched_tuned_shape(lib):
+    """The batch tuner times the candidate shapes, batched() with
+    px_per_thread=0 then runs the shape it chose, and the result is the
+    oracle's bit for bit (as it is for every shape)."""
+    probs, refs = [], []
+    for i, (n, ns, tiles, ivl, thr) in enumerate(MIXED):
+        d, p, _ = synth.make_problem(n, ns, 0.01, 2.1, (), 1e-3, config=97, problem=i)
+        if tiles == (1, 1):
+            refs.append(oracle.hogbom(d, p, 0.1, thr, 800))
+        else:
+            refs.append(oracle.tiled(d, p, tiles, ivl, 0.1, thr, 800))
+        probs.append(dict(dirty=dev(d), psf=dev(p), threshold=thr, max_iter=800, tiles=tiles, interval=ivl))
+    announce("batched tuned shape")
+    t = lib.autotune_batched(probs, gain=0.1, trial_iter=200)
+    assert t["px_per_thread"] in (8, 16, 32, 64)
+    ms = t["trial_ms"]
+    assert len(ms) == 4 and any(v > 0 for v in ms)
+    assert ms[(8, 16, 32, 64).index(t["px_per_thread"])] == min(v for v in ms if v > 0)
+    outs = lib.batched(probs, gain=0.1)
+    for o, ref in zip(outs, refs):
+        assert o["stats"]["px_per_thread"] == t["px_per_thread"]
+        assert_same_run(o, ref)
+    # an explicit shape still wins over the tuned one
+    other = 16 if t["px_per_thread"] != 16 else 32
+    outs = lib.batched(probs, gain=0.1, px_per_thread=other)
+    for o, ref in zip(outs, refs):
+        assert o["stats"]["px_per_thread"] == other
+        assert_same_run(o, ref)
+
+
 def test_batched_degenerate_problems(lib):
     """A batch of edge cases: no iterations asked, a 1 x 1 image, an image
     whose peak is already under the threshold, a zero image, capacity 0."""
