@@ -2593,7 +2593,14 @@ template <class Tile, bool FFT>
 __global__ void __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(FFT && !Tile::kResident && !Tile::kWide ? 4 : 1)))
 tiled_kernel(const KArgs a)
 {
-    tiled_body<Tile, FFT, false>(a, 0, 0, a.role[blockIdx.x], true);
+    // The argument block is used where it lies, in the kernel argument
+    // segment (it is the only argument, at offset 0): the wide tiles pass its
+    // address to their round functions, and a reference to the parameter
+    // itself would make the compiler copy the block to every lane's private
+    // memory first.
+    (void)a;
+    const KArgs &ka = *(const KArgs *)__builtin_amdgcn_kernarg_segment_ptr();
+    tiled_body<Tile, FFT, false>(ka, 0, 0, ka.role[blockIdx.x], true);
 }
 
 // ------------------------------------------------------ small kernels ----

@@ -297,15 +297,15 @@ def test_tiled_config1_full_f16(lib):
 
 
 def test_tiled_clusters_across_xcds(lib):
-    """Clusters too large for the per-XCD placement (3x3 tiles x 24 workgroups)
-    are packed without XCD affinity and exchange through device-scope slots;
-    the run is still bit-identical to the oracle."""
+    """Clusters too large for one XCD at any occupancy (72 workgroups against
+    at most 2 x 32 per XCD) are packed without XCD affinity and exchange
+    through device-scope slots; the run is still bit-identical to the oracle."""
     announce("tiled clusters across XCDs")
-    dirty = sparse_dirty(384, 384, 61, density=0.03)
-    psf = asym_psf(768, 770, 61, spread=0.2)
-    ref = oracle.tiled(dirty, psf, (3, 3), 40, 0.1, 0.0, 2000)
-    out = lib.tiled_feedback(dev(dirty), dev(psf), (3, 3), 40, 0.1, 0.0, 2000, wg_per_tile=24, px_per_thread=4)
-    assert out["stats"]["wg_per_tile"] == 24
+    dirty = sparse_dirty(768, 768, 61, density=0.01)
+    psf = asym_psf(1536, 1540, 61, spread=0.2)
+    ref = oracle.tiled(dirty, psf, (2, 2), 40, 0.1, 0.0, 2000)
+    out = lib.tiled_feedback(dev(dirty), dev(psf), (2, 2), 40, 0.1, 0.0, 2000, wg_per_tile=72, px_per_thread=4)
+    assert out["stats"]["wg_per_tile"] == 72
     assert out["stats"]["xcd_local_clusters"] == 0
     assert out["stats"]["n_rounds"] == ref["n_rounds"]
     assert_same_run(out, ref)
