@@ -310,6 +310,25 @@ def main():
                  "frac_of_hbm_read": traffic / (kms_t * 1e-3) / 1e9 / levels["hbm_read"]} if traffic else None),
         "levels": levels,
     }
+    # The local loops are latency-bound: every local iteration ends with a
+    # cluster exchange.  Their time per iteration beside that of the same
+    # exchange with almost nothing to compute (a 32 x 2048 image as one tile
+    # of 32 workgroups at 4 px/thread, XCD-local, interval 100), measured here.
+    T = tiles[0] * tiles[1]
+    local_us = st_t["phase_us"][0] / max(1, st_t["n_iter"] / T)
+    rng = np.random.default_rng([5, 7])
+    fd = torch.from_numpy(rng.normal(0, 1, (32, 2048)).astype(np.float32)).to(dev)
+    fp = torch.from_numpy(synth.random_psf(64, 4096, rng, 0.3).astype(np.float32)).to(dev)
+    fl = []
+    for _ in range(3):
+        rf = P.tiled_feedback(fd, fp, (1, 1), 100, gain, 0.0, 5000, wg_per_tile=32, px_per_thread=4)
+        fl.append(rf["stats"]["phase_us"][0] / max(1, rf["stats"]["n_iter"]))
+    floor_us = float(np.median(fl))
+    roofline["latency"] = {"local_iteration_us": local_us, "exchange_floor_us": floor_us,
+                           "frac": floor_us / local_us, "floor_xcd_local": rf["stats"]["xcd_local_clusters"],
+                           "note": "local-loop time per minor iteration of one tile against the same loop on a "
+                                   "32 x 2048 one-tile image (32 workgroups, 4 px/thread, XCD-local exchange), "
+                                   "where the exchange is nearly all the work"}
 
     # ---- accuracy beside the headline rate
     value_jy = {"model_band_vs_plain": model_band(model_t, model_p),
