@@ -585,8 +585,8 @@ int run(bool tiled, const float *dirty, int ny, int nx, const void *psf, int psf
     const bool half = p->psf_dtype == CLEAN_PSF_F16;
     size_t dyn_lds = tiled ? std::max((size_t)16 * ((interval + 3) & ~3), (size_t)8 * GATHER_CHUNK) : 0;
     if (fft) {
-        if (!fg.two_x) dyn_lds = std::max(dyn_lds, (size_t)8 << fg.lgx);
-        if (!fg.two_y) dyn_lds = std::max(dyn_lds, (size_t)8 << fg.lgy);
+        if (!fg.two_x) dyn_lds = std::max(dyn_lds, (size_t)8 * fft_pad_slots(1 << fg.lgx));
+        if (!fg.two_y) dyn_lds = std::max(dyn_lds, (size_t)8 * fft_pad_slots(1 << fg.lgy));
         if (fg.two_x || fg.two_y) dyn_lds = std::max(dyn_lds, (size_t)8 * FFT_LDS_CPLX);
     }
 

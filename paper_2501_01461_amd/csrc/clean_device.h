@@ -17,10 +17,12 @@ constexpr int TWO_LEVEL_MIN_CS = 32;    // plain clusters this large exchange in
 constexpr int MAX_WG_PER_CU = 2;        // co-resident 512-thread workgroups the launches count on per CU
 constexpr int FFT_MAX_LG = 13;          // one-level FFT transforms: length <= 8192 (64 KB of LDS)
 constexpr int FFT_MAX_LG2 = 16;         // two-level FFT transforms: length <= 65536
-constexpr int FFT_LDS_CPLX = 8192 + 64; // LDS complex slots of the two-level passes
-// LDS slots of the wide-tile kernel's padded transform arena for a length-L
-// axis: one spare slot after every 16 elements and one more after every 256.
+constexpr int FFT_LDS_CPLX = 8960;       // LDS complex slots of the two-level passes (>= fft_pad_slots(8192))
+// LDS slots of a padded transform arena for a length-L axis (one spare slot
+// after every 16 elements and one more after every 256), and the distance
+// between the padded segments of a pass (odd).
 __host__ __device__ constexpr int fft_pad_slots(int L) { return L + L / 16 + L / 256; }
+__host__ __device__ constexpr int fft_seg_stride(int L) { return fft_pad_slots(L) | 1; }
 constexpr int TR_GROUP_WIDE = 4;         // transpose tiles in flight per workgroup in the wide-tile kernel
 constexpr int TR_LDS_WIDE = TR_GROUP_WIDE * 32 * 33 * 8;
 // (with the tiled kernel's static LDS, two workgroups fit one CU's 160 KB)

@@ -67,6 +67,15 @@ __device__ __forceinline__ void staged(int n, bool sync, Load load, Put put)
     }
 }
 
+// LDS slot of element i of a transform: one spare slot after every 16
+// elements and one more after every 256.  The passes read points at spacing
+// 1 or 2 and the loaders write bit-reversed positions; unpadded, the 64 lanes
+// of a wave would then hit one bank (addresses 32 B to 1 KB apart), padded
+// they spread over all of them.  Every transform below works on padded
+// segments; several segments of one pass lie fft_seg_stride(L) slots apart
+// (odd, so that lanes running across segments also spread over the banks).
+__device__ __forceinline__ int pad16(int i) { return i + (i >> 4) + (i >> 8); }
+
 __device__ __forceinline__ uint32_t bitrev(uint32_t i, int lg) { return __builtin_bitreverse32(i) >> (32 - lg); }
 
 __device__ __forceinline__ float2 cmul(float2 p, float2 q)
@@ -99,7 +108,8 @@ __device__ __forceinline__ void radix4_unit(float2 &x0, float2 &x1, float2 &x2, 
 }
 
 // `count` independent in-place transforms of length 2^lg, segment i at
-// a[i * stride ..], bit-reversed input, natural output; inverse: conjugate
+// a[i * stride ..] (element e at slot pad16(e)), bit-reversed input, natural
+// output; inverse: conjugate
 // twiddles, no 1/L scaling.  tw is a table of W_L^m for a length
 // L = 2^lg * tw_step (entries m < L/2 are read).  Stages go two at a time
 // (radix 4: one thread reads four points, applies both radix-2 stages in
@@ -116,7 +126,7 @@ __device__ inline void fft_lds_multi(float2 *a, int lg, int count, int stride, c
         const int H = 1 << (lg - 1);
 #pragma clang loop unroll(disable)
         for (int j = threadIdx.x; j < count * H; j += blockDim.x) {
-            float2 *b = a + (j >> (lg - 1)) * stride + 2 * (j & (H - 1));
+            float2 *b = a + (j >> (lg - 1)) * stride + pad16(2 * (j & (H - 1)));   // 2j + 1 in the next slot
             const float2 u = b[0], v = b[1];
             b[0] = make_float2(u.x + v.x, u.y + v.y);
             b[1] = make_float2(u.x - v.x, u.y - v.y);
@@ -132,45 +142,42 @@ __device__ inline void fft_lds_multi(float2 *a, int lg, int count, int stride, c
         for (int j = threadIdx.x; j < count * Q; j += blockDim.x) {
             const int jj = j & (Q - 1);
             const int k = jj & (half - 1);
-            float2 *b = a + (j >> (lg - 2)) * stride + ((jj >> s) << (s + 2)) + k;
+            float2 *sg = a + (j >> (lg - 2)) * stride;
+            const int e0 = ((jj >> s) << (s + 2)) + k;
+            float2 *b0 = sg + pad16(e0), *b1 = sg + pad16(e0 + half), *b2 = sg + pad16(e0 + 2 * half),
+                   *b3 = sg + pad16(e0 + 3 * half);
             float2 w1 = tw[(k << (lg - 1 - s)) * tw_step];
             float2 w2 = tw[(k << (lg - 2 - s)) * tw_step];
             if (inverse) {
                 w1.y = -w1.y;
                 w2.y = -w2.y;
             }
-            const float2 x0 = b[0], x1 = b[half], x2 = b[2 * half], x3 = b[3 * half];
+            const float2 x0 = *b0, x1 = *b1, x2 = *b2, x3 = *b3;
             const float2 p1 = cmul(x1, w1), p3 = cmul(x3, w1);
             const float2 a0 = make_float2(x0.x + p1.x, x0.y + p1.y), a1 = make_float2(x0.x - p1.x, x0.y - p1.y);
             const float2 a2 = make_float2(x2.x + p3.x, x2.y + p3.y), a3 = make_float2(x2.x - p3.x, x2.y - p3.y);
             const float2 t = cmul(a2, w2), v = cmul(a3, w2);
             const float2 u = inverse ? make_float2(-v.y, v.x) : make_float2(v.y, -v.x);
-            b[0] = make_float2(a0.x + t.x, a0.y + t.y);
-            b[2 * half] = make_float2(a0.x - t.x, a0.y - t.y);
-            b[half] = make_float2(a1.x + u.x, a1.y + u.y);
-            b[3 * half] = make_float2(a1.x - u.x, a1.y - u.y);
+            *b0 = make_float2(a0.x + t.x, a0.y + t.y);
+            *b2 = make_float2(a0.x - t.x, a0.y - t.y);
+            *b1 = make_float2(a1.x + u.x, a1.y + u.y);
+            *b3 = make_float2(a1.x - u.x, a1.y - u.y);
         }
         __syncthreads();
     }
 }
 
-// In-place FFT of a[0 .. 2^lg) (bit-reversed input, natural-order output),
-// tw the table W_L^m of this length.  All threads of the workgroup.
+// In-place FFT of the padded arena a (length 2^lg; bit-reversed input,
+// natural-order output), tw the table W_L^m of this length.  All threads of
+// the workgroup.
 __device__ inline void fft_lds(float2 *a, int lg, const float2 *tw, bool inverse)
 {
-    fft_lds_multi(a, lg, 1, 1 << lg, tw, 1, inverse);
+    fft_lds_multi(a, lg, 1, fft_pad_slots(1 << lg), tw, 1, inverse);
 }
 
 // ------------------------------------------------------------------------
 // Transforms of the wide-tile kernel (one workgroup per transform, length up
 // to 8192, the workgroup's 512 threads holding up to 16 points each).
-//
-// The arena is padded: element i lives at LDS slot pad16(i), one spare slot
-// after every 16 elements and one more after every 256.  The passes below
-// read 16 points at spacing 1 or 2 per thread, and the loaders write
-// bit-reversed positions; unpadded, the 64 lanes of a wave would then all hit
-// one bank (addresses 128 B or 1 KB apart), padded they spread over all of
-// them.
 //
 // Two orders: decimation in time (bit-reversed input, natural output, the
 // passes of fft_lds_multi) and decimation in frequency (natural input,
@@ -181,7 +188,6 @@ __device__ inline void fft_lds(float2 *a, int lg, const float2 *tw, bool inverse
 // at all: forward in frequency order, product with a kernel spectrum held in
 // the same (bit-reversed) order, inverse in time order.
 
-__device__ __forceinline__ int pad16(int i) { return i + (i >> 4) + (i >> 8); }
 
 // radix4_unit with its flow graph transposed (stage s+1, then stage s).
 __device__ __forceinline__ void radix4_unit_dif(float2 &x0, float2 &x1, float2 &x2, float2 &x3, float2 w1, float2 w2,
@@ -425,7 +431,7 @@ __device__ __forceinline__ void fft13(float2 *a, const Tw13 &T)
     }
 }
 
-// Puts a natural-order array into bit-reversed order, in place.
+// Puts a natural-order padded arena into bit-reversed order, in place.
 __device__ inline void bitrev_permute(float2 *a, int lg)
 {
     __syncthreads();
@@ -434,9 +440,9 @@ __device__ inline void bitrev_permute(float2 *a, int lg)
     for (int i = threadIdx.x; i < L; i += blockDim.x) {
         const int j = (int)bitrev((uint32_t)i, lg);
         if (i < j) {
-            const float2 t = a[i];
-            a[i] = a[j];
-            a[j] = t;
+            const float2 t = a[pad16(i)];
+            a[pad16(i)] = a[pad16(j)];
+            a[pad16(j)] = t;
         }
     }
     __syncthreads();

@@ -1374,7 +1374,7 @@ __device__ __forceinline__ FftAxis fft_axis(int lg, int two, const float2 *tw)
 __device__ __forceinline__ int strided_block_lg(const FftAxis &f)
 {
     int lg = 0;
-    while (lg < f.lg2 && (2 << lg) * (f.L1 + 1) <= FFT_LDS_CPLX) ++lg;
+    while (lg < f.lg2 && (2 << lg) * fft_seg_stride(f.L1) <= FFT_LDS_CPLX) ++lg;
     return lg;
 }
 
@@ -1434,7 +1434,7 @@ __device__ void xfwd_one(const KArgs &a, const FftAxis &fx, int Ly, int rows, co
 {
     const int Lx = fx.L, lgx = fx.lg, nx = a.nx, tx = a.tx;
     // LDS slot of transform element i (the wide-tile kernel's arena is padded)
-    auto at = [](int i) { return BIG ? pad16(i) : i; };
+    auto at = [](int i) { return pad16(i); };
     Tw13 T13;
     if (BIG && lgx == F13) tw13_load(T13, fx.tw);
     #pragma clang loop unroll(disable)
@@ -1449,7 +1449,7 @@ __device__ void xfwd_one(const KArgs &a, const FftAxis &fx, int Ly, int rows, co
             if (threadIdx.x == 0) *s_nz = 1;
             __syncthreads();
         } else {
-            const int slots = BIG ? fft_pad_slots(Lx) : Lx;
+            const int slots = fft_pad_slots(Lx);
             #pragma clang loop unroll(disable)
             for (int x = threadIdx.x; x < slots; x += WG) lds[x] = make_float2(0.f, 0.f);
             if (threadIdx.x == 0) *s_nz = 0;
@@ -1518,7 +1518,7 @@ template <typename PT, bool KSRC>
 __device__ void xfwd_two_a(const KArgs &a, const FftAxis &fx, int Ly, int rows, float2 *lds)
 {
     const int lgNB = strided_block_lg(fx), NB = 1 << lgNB;
-    const int nblk = fx.L2 / NB, stride = fx.L1 + 1;
+    const int nblk = fx.L2 / NB, stride = fft_seg_stride(fx.L1);
     const int ncols = KSRC ? fx.L : a.nx;
     #pragma clang loop unroll(disable)
     for (int item = blockIdx.x; item < (rows + 1) / 2 * nblk; item += gridDim.x) {
@@ -1540,14 +1540,14 @@ __device__ void xfwd_two_a(const KArgs &a, const FftAxis &fx, int Ly, int rows, 
                     if (has1) v1 = ldc(&a.comp_img[(size_t)(r0 + 1) * a.nx + x]);
                 }
             }
-            lds[j * stride + bitrev((uint32_t)n1, fx.lg1)] = make_float2(v0, v1);
+            lds[j * stride + pad16(bitrev((uint32_t)n1, fx.lg1))] = make_float2(v0, v1);
         }
         fft_lds_multi(lds, fx.lg1, NB, stride, fx.tw, fx.L2, false);
         float2 *w = a.fft_wx + (size_t)pr * fx.L;
         #pragma clang loop unroll(disable)
         for (int e = threadIdx.x; e < NB * fx.L1; e += WG) {
             const int j = e & (NB - 1), k1 = e >> lgNB, n2 = b * NB + j;
-            stc2(&w[(size_t)fx.L2 * k1 + n2], cmul(lds[j * stride + k1], fx.tw[n2 * k1]));
+            stc2(&w[(size_t)fx.L2 * k1 + n2], cmul(lds[j * stride + pad16(k1)], fx.tw[n2 * k1]));
         }
     }
 }
@@ -1560,7 +1560,7 @@ template <bool KSRC>
 __device__ void xfwd_two_b(const KArgs &a, const FftAxis &fx, int rows, float2 *lds, const int32_t *s_off)
 {
     const int nslot = fx.L1 / 2 + 1;
-    const int stride = fx.L2 + 1;
+    const int stride = fft_seg_stride(fx.L2);
     const int G = max(1, min(nslot, FFT_LDS_CPLX / (2 * stride)));
     const int nblk = (nslot + G - 1) / G;
     const int hq = fx.L2 / 2;
@@ -1577,7 +1577,7 @@ __device__ void xfwd_two_b(const KArgs &a, const FftAxis &fx, int rows, float2 *
             const int seg = e >> fx.lg2, n2 = e & (fx.L2 - 1);
             const int k1 = s0 + (seg >> 1);
             const int kr = (seg & 1) ? ((fx.L1 - k1) & (fx.L1 - 1)) : k1;
-            lds[seg * stride + bitrev((uint32_t)n2, fx.lg2)] = ldc2(&w[(size_t)fx.L2 * kr + n2]);
+            lds[seg * stride + pad16(bitrev((uint32_t)n2, fx.lg2))] = ldc2(&w[(size_t)fx.L2 * kr + n2]);
         }
         fft_lds_multi(lds, fx.lg2, 2 * ns, stride, fx.tw, fx.L1, false);
         float2 *o0 = a.fft_a + (size_t)r0 * fx.H, *o1 = o0 + fx.H;
@@ -1591,10 +1591,10 @@ __device__ void xfwd_two_b(const KArgs &a, const FftAxis &fx, int rows, float2 *
             int q1, q2;
             mirror_of(fx, kr, k2, q1, q2);
             const int qs = q1 == kr ? seg : (seg ^ 1);
-            store_split(o0, o1, has1, chat_of(fx, kr, k2), lds[seg * stride + k2], lds[qs * stride + q2]);
+            store_split(o0, o1, has1, chat_of(fx, kr, k2), lds[seg * stride + pad16(k2)], lds[qs * stride + pad16(q2)]);
         }
         if (s0 == 0 && threadIdx.x == 0)        // bin k = L/2: row 0, k2 = L2/2, its own mirror
-            store_split(o0, o1, has1, fx.L / 2, lds[hq], lds[hq]);
+            store_split(o0, o1, has1, fx.L / 2, lds[pad16(hq)], lds[pad16(hq)]);
     }
     if (!KSRC) {
         const int total = s_off[a.T];
@@ -1699,21 +1699,21 @@ __device__ void ycol_one(const KArgs &a, const FftAxis &fx, const FftAxis &fy, i
             }
         } else {
             #pragma clang loop unroll(disable)
-            for (int v = threadIdx.x; v < fy.L; v += WG) lds[v] = make_float2(0.f, 0.f);
+            for (int v = threadIdx.x; v < fft_pad_slots(fy.L); v += WG) lds[v] = make_float2(0.f, 0.f);
             __syncthreads();
             #pragma clang loop unroll(disable)
-            for (int v = threadIdx.x; v < rows; v += WG) lds[bitrev((uint32_t)v, fy.lg)] = ldc2(&b[v]);
+            for (int v = threadIdx.x; v < rows; v += WG) lds[pad16(bitrev((uint32_t)v, fy.lg))] = ldc2(&b[v]);
             fft_lds(lds, fy.lg, fy.tw, false);
             if (PRE) {
                 #pragma clang loop unroll(disable)
-                for (int v = threadIdx.x; v < fy.L; v += WG) stc2(&ks[v], lds[v]);
+                for (int v = threadIdx.x; v < fy.L; v += WG) stc2(&ks[v], lds[pad16(v)]);
             } else {
                 #pragma clang loop unroll(disable)
-                for (int v = threadIdx.x; v < fy.L; v += WG) lds[v] = cmul(lds[v], ldc2(&ks[v]));
+                for (int v = threadIdx.x; v < fy.L; v += WG) lds[pad16(v)] = cmul(lds[pad16(v)], ldc2(&ks[v]));
                 bitrev_permute(lds, fy.lg);
                 fft_lds(lds, fy.lg, fy.tw, true);
                 #pragma clang loop unroll(disable)
-                for (int v = threadIdx.x; v < rows; v += WG) stc2(&b[v], lds[v]);
+                for (int v = threadIdx.x; v < rows; v += WG) stc2(&b[v], lds[pad16(v)]);
             }
         }
         __syncthreads();
@@ -1726,7 +1726,7 @@ __device__ void ycol_one(const KArgs &a, const FftAxis &fx, const FftAxis &fy, i
 __device__ void ycol_two_a(const KArgs &a, const FftAxis &fx, const FftAxis &fy, int rows, float2 *lds)
 {
     const int lgNB = strided_block_lg(fy), NB = 1 << lgNB;
-    const int nblk = fy.L2 / NB, stride = fy.L1 + 1;
+    const int nblk = fy.L2 / NB, stride = fft_seg_stride(fy.L1);
     #pragma clang loop unroll(disable)
     for (int item = blockIdx.x; item < fx.H * nblk; item += gridDim.x) {
         const int col = item / nblk, b = item % nblk;
@@ -1736,14 +1736,14 @@ __device__ void ycol_two_a(const KArgs &a, const FftAxis &fx, const FftAxis &fy,
         for (int e = threadIdx.x; e < NB * fy.L1; e += WG) {
             const int j = e & (NB - 1), n1 = e >> lgNB;
             const int yy = fy.L2 * n1 + b * NB + j;
-            lds[j * stride + bitrev((uint32_t)n1, fy.lg1)] = yy < rows ? ldc2(&src[yy]) : make_float2(0.f, 0.f);
+            lds[j * stride + pad16(bitrev((uint32_t)n1, fy.lg1))] = yy < rows ? ldc2(&src[yy]) : make_float2(0.f, 0.f);
         }
         fft_lds_multi(lds, fy.lg1, NB, stride, fy.tw, fy.L2, false);
         float2 *w = a.fft_wy + (size_t)col * fy.L;
         #pragma clang loop unroll(disable)
         for (int e = threadIdx.x; e < NB * fy.L1; e += WG) {
             const int j = e & (NB - 1), k1 = e >> lgNB, n2 = b * NB + j;
-            stc2(&w[(size_t)fy.L2 * k1 + n2], cmul(lds[j * stride + k1], fy.tw[n2 * k1]));
+            stc2(&w[(size_t)fy.L2 * k1 + n2], cmul(lds[j * stride + pad16(k1)], fy.tw[n2 * k1]));
         }
     }
 }
@@ -1755,7 +1755,7 @@ __device__ void ycol_two_a(const KArgs &a, const FftAxis &fx, const FftAxis &fy,
 template <bool PRE>
 __device__ void ycol_two_b(const KArgs &a, const FftAxis &fx, const FftAxis &fy, float2 *lds)
 {
-    const int stride = fy.L2 + 1;
+    const int stride = fft_seg_stride(fy.L2);
     const int G = max(1, min(fy.L1, FFT_LDS_CPLX / stride));
     const int nblk = (fy.L1 + G - 1) / G;
     #pragma clang loop unroll(disable)
@@ -1767,21 +1767,21 @@ __device__ void ycol_two_b(const KArgs &a, const FftAxis &fx, const FftAxis &fy,
         #pragma clang loop unroll(disable)
         for (int e = threadIdx.x; e < ng * fy.L2; e += WG) {
             const int g = e >> fy.lg2, n2 = e & (fy.L2 - 1);
-            lds[g * stride + bitrev((uint32_t)n2, fy.lg2)] = ldc2(&w[(size_t)fy.L2 * (k0 + g) + n2]);
+            lds[g * stride + pad16(bitrev((uint32_t)n2, fy.lg2))] = ldc2(&w[(size_t)fy.L2 * (k0 + g) + n2]);
         }
         fft_lds_multi(lds, fy.lg2, ng, stride, fy.tw, fy.L1, false);
         if (PRE) {
             #pragma clang loop unroll(disable)
             for (int e = threadIdx.x; e < ng * fy.L2; e += WG) {
                 const int g = e >> fy.lg2, k2 = e & (fy.L2 - 1);
-                stc2(&ks[(size_t)fy.L2 * (k0 + g) + k2], lds[g * stride + k2]);
+                stc2(&ks[(size_t)fy.L2 * (k0 + g) + k2], lds[g * stride + pad16(k2)]);
             }
             continue;
         }
         #pragma clang loop unroll(disable)
         for (int e = threadIdx.x; e < ng * fy.L2; e += WG) {
             const int g = e >> fy.lg2, k2 = e & (fy.L2 - 1);
-            lds[g * stride + k2] = cmul(lds[g * stride + k2], ldc2(&ks[(size_t)fy.L2 * (k0 + g) + k2]));
+            lds[g * stride + pad16(k2)] = cmul(lds[g * stride + pad16(k2)], ldc2(&ks[(size_t)fy.L2 * (k0 + g) + k2]));
         }
         __syncthreads();
         #pragma clang loop unroll(disable)
@@ -1789,16 +1789,16 @@ __device__ void ycol_two_b(const KArgs &a, const FftAxis &fx, const FftAxis &fy,
             const int g = e >> fy.lg2, i = e & (fy.L2 - 1);
             const int j = (int)bitrev((uint32_t)i, fy.lg2);
             if (i < j) {
-                const float2 t = lds[g * stride + i];
-                lds[g * stride + i] = lds[g * stride + j];
-                lds[g * stride + j] = t;
+                const float2 t = lds[g * stride + pad16(i)];
+                lds[g * stride + pad16(i)] = lds[g * stride + pad16(j)];
+                lds[g * stride + pad16(j)] = t;
             }
         }
         fft_lds_multi(lds, fy.lg2, ng, stride, fy.tw, fy.L1, true);
         #pragma clang loop unroll(disable)
         for (int e = threadIdx.x; e < ng * fy.L2; e += WG) {
             const int g = e >> fy.lg2, n2 = e & (fy.L2 - 1), k1 = k0 + g;
-            stc2(&w[(size_t)fy.L2 * k1 + n2], cmulc(lds[g * stride + n2], fy.tw[n2 * k1]));
+            stc2(&w[(size_t)fy.L2 * k1 + n2], cmulc(lds[g * stride + pad16(n2)], fy.tw[n2 * k1]));
         }
     }
 }
@@ -1808,7 +1808,7 @@ __device__ void ycol_two_b(const KArgs &a, const FftAxis &fx, const FftAxis &fy,
 __device__ void ycol_two_c(const KArgs &a, const FftAxis &fx, const FftAxis &fy, int rows, float2 *lds)
 {
     const int lgNB = strided_block_lg(fy), NB = 1 << lgNB;
-    const int nblk = fy.L2 / NB, stride = fy.L1 + 1;
+    const int nblk = fy.L2 / NB, stride = fft_seg_stride(fy.L1);
     #pragma clang loop unroll(disable)
     for (int item = blockIdx.x; item < fx.H * nblk; item += gridDim.x) {
         const int col = item / nblk, b = item % nblk;
@@ -1817,7 +1817,7 @@ __device__ void ycol_two_c(const KArgs &a, const FftAxis &fx, const FftAxis &fy,
         #pragma clang loop unroll(disable)
         for (int e = threadIdx.x; e < NB * fy.L1; e += WG) {
             const int j = e & (NB - 1), k1 = e >> lgNB;
-            lds[j * stride + bitrev((uint32_t)k1, fy.lg1)] = ldc2(&w[(size_t)fy.L2 * k1 + b * NB + j]);
+            lds[j * stride + pad16(bitrev((uint32_t)k1, fy.lg1))] = ldc2(&w[(size_t)fy.L2 * k1 + b * NB + j]);
         }
         fft_lds_multi(lds, fy.lg1, NB, stride, fy.tw, fy.L2, true);
         float2 *dst = a.fft_b + (size_t)col * rows;
@@ -1825,7 +1825,7 @@ __device__ void ycol_two_c(const KArgs &a, const FftAxis &fx, const FftAxis &fy,
         for (int e = threadIdx.x; e < NB * fy.L1; e += WG) {
             const int j = e & (NB - 1), n1 = e >> lgNB;
             const int yy = fy.L2 * n1 + b * NB + j;
-            if (yy < rows) stc2(&dst[yy], lds[j * stride + n1]);
+            if (yy < rows) stc2(&dst[yy], lds[j * stride + pad16(n1)]);
         }
     }
 }
@@ -1889,7 +1889,7 @@ __device__ void xinv_one(const KArgs &a, const FftAxis &fx, float scale, float2 
         }
     }
     const int Lx = fx.L, lgx = fx.lg, ny = a.ny, nx = a.nx;
-    auto at = [](int i) { return BIG ? pad16(i) : i; };
+    auto at = [](int i) { return pad16(i); };
     #pragma clang loop unroll(disable)
     for (int pr = blockIdx.x; pr < (ny + 1) / 2; pr += gridDim.x) {
         const int r0 = 2 * pr;
@@ -1919,7 +1919,7 @@ __device__ void xinv_one(const KArgs &a, const FftAxis &fx, float scale, float2 
 // inverse transform over k2 (length L2), times conj W_L^(n2 k1), into fft_wx.
 __device__ void xinv_two_a(const KArgs &a, const FftAxis &fx, float2 *lds)
 {
-    const int ny = a.ny, stride = fx.L2 + 1, hq = fx.L2 / 2;
+    const int ny = a.ny, stride = fft_seg_stride(fx.L2), hq = fx.L2 / 2;
     const int G = max(1, min(fx.L1, FFT_LDS_CPLX / stride));
     const int nblk = (fx.L1 + G - 1) / G;
     #pragma clang loop unroll(disable)
@@ -1938,7 +1938,7 @@ __device__ void xinv_two_a(const KArgs &a, const FftAxis &fx, float2 *lds)
             const int c = chat_of(fx, q1, q2);
             const float2 A = ldc2(&i0[c]);
             const float2 B = has1 ? ldc2(&i1[c]) : make_float2(0.f, 0.f);
-            lds[g * stride + bitrev((uint32_t)k2, fx.lg2)] =
+            lds[g * stride + pad16(bitrev((uint32_t)k2, fx.lg2))] =
                 carried ? make_float2(A.x - B.y, A.y + B.x) : make_float2(A.x + B.y, B.x - A.y);
         }
         fft_lds_multi(lds, fx.lg2, ng, stride, fx.tw, fx.L1, true);
@@ -1946,7 +1946,7 @@ __device__ void xinv_two_a(const KArgs &a, const FftAxis &fx, float2 *lds)
         #pragma clang loop unroll(disable)
         for (int e = threadIdx.x; e < ng * fx.L2; e += WG) {
             const int g = e >> fx.lg2, n2 = e & (fx.L2 - 1), k1 = k0 + g;
-            stc2(&w[(size_t)fx.L2 * k1 + n2], cmulc(lds[g * stride + n2], fx.tw[n2 * k1]));
+            stc2(&w[(size_t)fx.L2 * k1 + n2], cmulc(lds[g * stride + pad16(n2)], fx.tw[n2 * k1]));
         }
     }
 }
@@ -1958,7 +1958,7 @@ __device__ void xinv_two_b(const KArgs &a, const FftAxis &fx, float scale, float
 {
     const int ny = a.ny, nx = a.nx;
     const int lgNB = strided_block_lg(fx), NB = 1 << lgNB;
-    const int nblk = fx.L2 / NB, stride = fx.L1 + 1;
+    const int nblk = fx.L2 / NB, stride = fft_seg_stride(fx.L1);
     #pragma clang loop unroll(disable)
     for (int item = blockIdx.x; item < (ny + 1) / 2 * nblk; item += gridDim.x) {
         const int pr = item / nblk, b = item % nblk;
@@ -1969,7 +1969,7 @@ __device__ void xinv_two_b(const KArgs &a, const FftAxis &fx, float scale, float
         #pragma clang loop unroll(disable)
         for (int e = threadIdx.x; e < NB * fx.L1; e += WG) {
             const int j = e & (NB - 1), k1 = e >> lgNB;
-            lds[j * stride + bitrev((uint32_t)k1, fx.lg1)] = ldc2(&w[(size_t)fx.L2 * k1 + b * NB + j]);
+            lds[j * stride + pad16(bitrev((uint32_t)k1, fx.lg1))] = ldc2(&w[(size_t)fx.L2 * k1 + b * NB + j]);
         }
         fft_lds_multi(lds, fx.lg1, NB, stride, fx.tw, fx.L2, true);
         #pragma clang loop unroll(disable)
@@ -1977,7 +1977,7 @@ __device__ void xinv_two_b(const KArgs &a, const FftAxis &fx, float scale, float
             const int j = e & (NB - 1), n1 = e >> lgNB;
             const int x = fx.L2 * n1 + b * NB + j;
             if (x < nx) {
-                const float2 z = lds[j * stride + n1];
+                const float2 z = lds[j * stride + pad16(n1)];
                 stc(&a.accbuf[(size_t)r0 * nx + x], z.x * scale);
                 if (has1) stc(&a.accbuf[(size_t)(r0 + 1) * nx + x], z.y * scale);
             }
