@@ -42,7 +42,10 @@ __device__ __forceinline__ void stc2(float2 *p, float2 v)
 // A workgroup-strided loop over e < n (e = threadIdx.x + m * WG) whose body
 // reads global memory, then writes: the reads of U consecutive steps are
 // issued before the first write, so U memory round trips overlap instead of
-// following one another.  With `sync`, a workgroup barrier separates the
+// following one another.  The reads are unconditional (indices past n read
+// element n - 1 and are not written), since a branch between them would let
+// the compiler wait for each read on its own; `load` must therefore return
+// the raw values and leave every use to `put`.  With `sync`, a workgroup barrier separates the
 // first reads from the first writes (for writes into LDS that other threads
 // were reading before the call).  The loop bounds are uniform, so every
 // thread reaches the barrier.
@@ -54,10 +57,8 @@ __device__ __forceinline__ void staged(int n, bool sync, Load load, Put put)
     for (int e0 = 0; e0 < n || (sync && e0 == 0); e0 += U * WG) {
         V v[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int e = e0 + u * WG + (int)threadIdx.x;
-            if (e < n) v[u] = load(e);
-        }
+        for (int u = 0; u < U; ++u)     // unconditional (index clamped): no branch between the loads
+            v[u] = load(min(e0 + u * WG + (int)threadIdx.x, n - 1));
         if (sync && e0 == 0) __syncthreads();
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -105,6 +106,24 @@ __device__ __forceinline__ void radix4_unit(float2 &x0, float2 &x1, float2 &x2, 
     x2 = make_float2(a0.x - t.x, a0.y - t.y);
     x1 = make_float2(a1.x + u.x, a1.y + u.y);
     x3 = make_float2(a1.x - u.x, a1.y - u.y);
+}
+
+// radix4_unit with its flow graph transposed (stage s+1, then stage s).
+__device__ __forceinline__ void radix4_unit_dif(float2 &x0, float2 &x1, float2 &x2, float2 &x3, float2 w1, float2 w2,
+                                                bool inverse)
+{
+    if (inverse) {
+        w1.y = -w1.y;
+        w2.y = -w2.y;
+    }
+    const float2 a0 = make_float2(x0.x + x2.x, x0.y + x2.y), a1 = make_float2(x1.x + x3.x, x1.y + x3.y);
+    const float2 a2 = cmul(make_float2(x0.x - x2.x, x0.y - x2.y), w2);
+    const float2 v = cmul(make_float2(x1.x - x3.x, x1.y - x3.y), w2);
+    const float2 a3 = inverse ? make_float2(-v.y, v.x) : make_float2(v.y, -v.x);
+    x0 = make_float2(a0.x + a1.x, a0.y + a1.y);
+    x1 = cmul(make_float2(a0.x - a1.x, a0.y - a1.y), w1);
+    x2 = make_float2(a2.x + a3.x, a2.y + a3.y);
+    x3 = cmul(make_float2(a2.x - a3.x, a2.y - a3.y), w1);
 }
 
 // `count` independent in-place transforms of length 2^lg, segment i at
@@ -167,6 +186,48 @@ __device__ inline void fft_lds_multi(float2 *a, int lg, int count, int stride, c
     }
 }
 
+// fft_lds_multi in frequency order: natural input, bit-reversed output (its
+// stages in reverse order, each butterfly transposed: radix4_unit_dif, then
+// the plain radix-2 stage last when lg is odd).
+__device__ inline void fft_lds_multi_dif(float2 *a, int lg, int count, int stride, const float2 *tw, int tw_step,
+                                         bool inverse)
+{
+    __syncthreads();
+    const int Q = lg >= 2 ? 1 << (lg - 2) : 0;
+    #pragma clang loop unroll(disable)
+    for (int s = lg - 2; s >= (lg & 1); s -= 2) {
+        const int half = 1 << s;
+        #pragma clang loop unroll(disable)
+        for (int j = threadIdx.x; j < count * Q; j += blockDim.x) {
+            const int jj = j & (Q - 1);
+            const int k = jj & (half - 1);
+            float2 *sg = a + (j >> (lg - 2)) * stride;
+            const int e0 = ((jj >> s) << (s + 2)) + k;
+            float2 *b0 = sg + pad16(e0), *b1 = sg + pad16(e0 + half), *b2 = sg + pad16(e0 + 2 * half),
+                   *b3 = sg + pad16(e0 + 3 * half);
+            float2 x0 = *b0, x1 = *b1, x2 = *b2, x3 = *b3;
+            radix4_unit_dif(x0, x1, x2, x3, tw[(k << (lg - 1 - s)) * tw_step], tw[(k << (lg - 2 - s)) * tw_step],
+                            inverse);
+            *b0 = x0;
+            *b1 = x1;
+            *b2 = x2;
+            *b3 = x3;
+        }
+        __syncthreads();
+    }
+    if (lg & 1) {
+        const int H = 1 << (lg - 1);
+        #pragma clang loop unroll(disable)
+        for (int j = threadIdx.x; j < count * H; j += blockDim.x) {
+            float2 *b = a + (j >> (lg - 1)) * stride + pad16(2 * (j & (H - 1)));
+            const float2 u = b[0], v = b[1];
+            b[0] = make_float2(u.x + v.x, u.y + v.y);
+            b[1] = make_float2(u.x - v.x, u.y - v.y);
+        }
+        __syncthreads();
+    }
+}
+
 // In-place FFT of the padded arena a (length 2^lg; bit-reversed input,
 // natural-order output), tw the table W_L^m of this length.  All threads of
 // the workgroup.
@@ -188,24 +249,6 @@ __device__ inline void fft_lds(float2 *a, int lg, const float2 *tw, bool inverse
 // at all: forward in frequency order, product with a kernel spectrum held in
 // the same (bit-reversed) order, inverse in time order.
 
-
-// radix4_unit with its flow graph transposed (stage s+1, then stage s).
-__device__ __forceinline__ void radix4_unit_dif(float2 &x0, float2 &x1, float2 &x2, float2 &x3, float2 w1, float2 w2,
-                                                bool inverse)
-{
-    if (inverse) {
-        w1.y = -w1.y;
-        w2.y = -w2.y;
-    }
-    const float2 a0 = make_float2(x0.x + x2.x, x0.y + x2.y), a1 = make_float2(x1.x + x3.x, x1.y + x3.y);
-    const float2 a2 = cmul(make_float2(x0.x - x2.x, x0.y - x2.y), w2);
-    const float2 v = cmul(make_float2(x1.x - x3.x, x1.y - x3.y), w2);
-    const float2 a3 = inverse ? make_float2(-v.y, v.x) : make_float2(v.y, -v.x);
-    x0 = make_float2(a0.x + a1.x, a0.y + a1.y);
-    x1 = cmul(make_float2(a0.x - a1.x, a0.y - a1.y), w1);
-    x2 = make_float2(a2.x + a3.x, a2.y + a3.y);
-    x3 = cmul(make_float2(a2.x - a3.x, a2.y - a3.y), w1);
-}
 
 // Stages s .. s+3 of a length-2^lg transform: a thread takes 16 points at
 // spacing 2^s, both stage pairs in registers.

@@ -1347,6 +1347,10 @@ __device__ int32_t xcd_ticket(const BatchArgs &b, const Sync &y, uint32_t x)
 // two-level spectra come out in (k1, k2) order; the PSF kernel's spectrum is
 // computed once per call by the same code, so both orders agree.
 
+// Loads in flight per thread in the two-level phases: enough to overlap their
+// round trips, few enough to keep the streamed FFT kernel within 128 VGPRs.
+constexpr int STAGE_TWO = 4;
+
 struct FftAxis {
     int lg, L, H;           // length 2^lg; H = L/2 + 1 (x axis: carried bins)
     bool two;               // two levels: L = L1 * L2
@@ -1515,7 +1519,7 @@ __device__ void xfwd_one(const KArgs &a, const FftAxis &fx, int Ly, int rows, co
 // over n1 (input x = L2 n1 + n2), times W_L^(n2 k1), into fft_wx[pair][L2 k1 + n2].
 // Source: the dense component image, or (KSRC) the PSF kernel image.
 template <typename PT, bool KSRC>
-__device__ void xfwd_two_a(const KArgs &a, const FftAxis &fx, int Ly, int rows, float2 *lds)
+__device__ __forceinline__ void xfwd_two_a(const KArgs &a, const FftAxis &fx, int Ly, int rows, float2 *lds)
 {
     const int lgNB = strided_block_lg(fx), NB = 1 << lgNB;
     const int nblk = fx.L2 / NB, stride = fft_seg_stride(fx.L1);
@@ -1525,23 +1529,27 @@ __device__ void xfwd_two_a(const KArgs &a, const FftAxis &fx, int Ly, int rows, 
         const int pr = item / nblk, b = item % nblk;
         const int r0 = 2 * pr;
         const bool has1 = r0 + 1 < rows;
-        __syncthreads();
-        #pragma clang loop unroll(disable)
-        for (int e = threadIdx.x; e < NB * fx.L1; e += WG) {
-            const int j = e & (NB - 1), n1 = e >> lgNB;
-            const int x = fx.L2 * n1 + b * NB + j;
-            float v0 = 0.f, v1 = 0.f;
-            if (x < ncols) {
-                if (KSRC) {
-                    v0 = kernel_value<PT>(a, Ly, fx.L, r0, x);
-                    if (has1) v1 = kernel_value<PT>(a, Ly, fx.L, r0 + 1, x);
-                } else {
-                    v0 = ldc(&a.comp_img[(size_t)r0 * a.nx + x]);
-                    if (has1) v1 = ldc(&a.comp_img[(size_t)(r0 + 1) * a.nx + x]);
-                }
-            }
-            lds[j * stride + pad16(bitrev((uint32_t)n1, fx.lg1))] = make_float2(v0, v1);
-        }
+        staged<STAGE_TWO>(NB * fx.L1, true,
+                  [&](int e) {
+                      const int x = fx.L2 * (e >> lgNB) + b * NB + (e & (NB - 1));
+                      float v0 = 0.f, v1 = 0.f;
+                      if (KSRC) {                          // once per call
+                          if (x < ncols) {
+                              v0 = kernel_value<PT>(a, Ly, fx.L, r0, x);
+                              if (has1) v1 = kernel_value<PT>(a, Ly, fx.L, r0 + 1, x);
+                          }
+                      } else {                             // column clamped; zeroed in the write
+                          const int xc = min(x, ncols - 1);
+                          v0 = ldc(&a.comp_img[(size_t)r0 * a.nx + xc]);
+                          v1 = ldc(&a.comp_img[(size_t)(has1 ? r0 + 1 : r0) * a.nx + xc]);
+                      }
+                      return make_float2(v0, v1);
+                  },
+                  [&](int e, float2 v) {
+                      const int x = fx.L2 * (e >> lgNB) + b * NB + (e & (NB - 1));
+                      if (!KSRC) v = x < ncols ? make_float2(v.x, has1 ? v.y : 0.f) : make_float2(0.f, 0.f);
+                      lds[(e & (NB - 1)) * stride + pad16(bitrev((uint32_t)(e >> lgNB), fx.lg1))] = v;
+                  });
         fft_lds_multi(lds, fx.lg1, NB, stride, fx.tw, fx.L2, false);
         float2 *w = a.fft_wx + (size_t)pr * fx.L;
         #pragma clang loop unroll(disable)
@@ -1557,7 +1565,7 @@ __device__ void xfwd_two_a(const KArgs &a, const FftAxis &fx, int Ly, int rows, 
 // image rows' carried bins (chat order) in fft_a.  Unless KSRC, also clears
 // the dense component image at this round's positions.
 template <bool KSRC>
-__device__ void xfwd_two_b(const KArgs &a, const FftAxis &fx, int rows, float2 *lds, const int32_t *s_off)
+__device__ __forceinline__ void xfwd_two_b(const KArgs &a, const FftAxis &fx, int rows, float2 *lds, const int32_t *s_off)
 {
     const int nslot = fx.L1 / 2 + 1;
     const int stride = fft_seg_stride(fx.L2);
@@ -1570,15 +1578,15 @@ __device__ void xfwd_two_b(const KArgs &a, const FftAxis &fx, int rows, float2 *
         const int r0 = 2 * pr;
         const bool has1 = r0 + 1 < rows;
         const float2 *w = a.fft_wx + (size_t)pr * fx.L;
-        __syncthreads();
         // segment 2i: row k1 = s0 + i; segment 2i+1: row (L1 - k1) mod L1
-        #pragma clang loop unroll(disable)
-        for (int e = threadIdx.x; e < 2 * ns * fx.L2; e += WG) {
-            const int seg = e >> fx.lg2, n2 = e & (fx.L2 - 1);
-            const int k1 = s0 + (seg >> 1);
-            const int kr = (seg & 1) ? ((fx.L1 - k1) & (fx.L1 - 1)) : k1;
-            lds[seg * stride + pad16(bitrev((uint32_t)n2, fx.lg2))] = ldc2(&w[(size_t)fx.L2 * kr + n2]);
-        }
+        staged<STAGE_TWO>(2 * ns * fx.L2, true,
+                  [&](int e) {
+                      const int seg = e >> fx.lg2, n2 = e & (fx.L2 - 1);
+                      const int k1 = s0 + (seg >> 1);
+                      const int kr = (seg & 1) ? ((fx.L1 - k1) & (fx.L1 - 1)) : k1;
+                      return ldc2(&w[(size_t)fx.L2 * kr + n2]);
+                  },
+                  [&](int e, float2 v) { lds[(e >> fx.lg2) * stride + pad16(bitrev((uint32_t)(e & (fx.L2 - 1)), fx.lg2))] = v; });
         fft_lds_multi(lds, fx.lg2, 2 * ns, stride, fx.tw, fx.L1, false);
         float2 *o0 = a.fft_a + (size_t)r0 * fx.H, *o1 = o0 + fx.H;
         #pragma clang loop unroll(disable)
@@ -1678,8 +1686,8 @@ __device__ void ycol_one(const KArgs &a, const FftAxis &fx, const FftAxis &fy, i
             // natural order, forward in frequency order (bit-reversed spectrum,
             // the PSF kernel's spectrum stored in the same order), product,
             // inverse in time order (natural output)
-            staged<16>(fy.L, true, [&](int v) { return v < rows ? ldc2(&b[v]) : make_float2(0.f, 0.f); },
-                       [&](int v, float2 z) { lds[pad16(v)] = z; });
+            staged<16>(fy.L, true, [&](int v) { return ldc2(&b[min(v, rows - 1)]); },
+                       [&](int v, float2 z) { lds[pad16(v)] = v < rows ? z : make_float2(0.f, 0.f); });
             if (fy.lg == F13) {
                 Tw13 T;
                 tw13_load(T, fy.tw);
@@ -1723,7 +1731,7 @@ __device__ void ycol_one(const KArgs &a, const FftAxis &fx, const FftAxis &fy, i
 // y, two levels, step 1: per carried column and n2, transforms of length L1
 // over n1 (input y = L2 n1 + n2 < rows), times W_L^(n2 k1), into
 // fft_wy[col][L2 k1 + n2].
-__device__ void ycol_two_a(const KArgs &a, const FftAxis &fx, const FftAxis &fy, int rows, float2 *lds)
+__device__ __forceinline__ void ycol_two_a(const KArgs &a, const FftAxis &fx, const FftAxis &fy, int rows, float2 *lds)
 {
     const int lgNB = strided_block_lg(fy), NB = 1 << lgNB;
     const int nblk = fy.L2 / NB, stride = fft_seg_stride(fy.L1);
@@ -1731,13 +1739,13 @@ __device__ void ycol_two_a(const KArgs &a, const FftAxis &fx, const FftAxis &fy,
     for (int item = blockIdx.x; item < fx.H * nblk; item += gridDim.x) {
         const int col = item / nblk, b = item % nblk;
         const float2 *src = a.fft_b + (size_t)col * rows;
-        __syncthreads();
-        #pragma clang loop unroll(disable)
-        for (int e = threadIdx.x; e < NB * fy.L1; e += WG) {
-            const int j = e & (NB - 1), n1 = e >> lgNB;
-            const int yy = fy.L2 * n1 + b * NB + j;
-            lds[j * stride + pad16(bitrev((uint32_t)n1, fy.lg1))] = yy < rows ? ldc2(&src[yy]) : make_float2(0.f, 0.f);
-        }
+        staged<STAGE_TWO>(NB * fy.L1, true,
+                  [&](int e) { return ldc2(&src[min(fy.L2 * (e >> lgNB) + b * NB + (e & (NB - 1)), rows - 1)]); },
+                  [&](int e, float2 v) {
+                      const int yy = fy.L2 * (e >> lgNB) + b * NB + (e & (NB - 1));
+                      lds[(e & (NB - 1)) * stride + pad16(bitrev((uint32_t)(e >> lgNB), fy.lg1))] =
+                          yy < rows ? v : make_float2(0.f, 0.f);
+                  });
         fft_lds_multi(lds, fy.lg1, NB, stride, fy.tw, fy.L2, false);
         float2 *w = a.fft_wy + (size_t)col * fy.L;
         #pragma clang loop unroll(disable)
@@ -1749,11 +1757,12 @@ __device__ void ycol_two_a(const KArgs &a, const FftAxis &fx, const FftAxis &fy,
 }
 
 // y, two levels, step 2: per carried column and row k1 of the step-1 output,
-// transform over n2 (length L2); then either (PRE) store as the PSF kernel's
-// spectrum in (k1, k2) order, or multiply by it, transform back over k2,
-// times conj W_L^(n2 k1), into fft_wy.
+// transform over n2 (length L2, frequency order); then either (PRE) store as
+// the PSF kernel's spectrum in (k1, bit-reversed k2) order, or multiply by it,
+// transform back over k2 (time order: no permutation between), times
+// conj W_L^(n2 k1), into fft_wy.
 template <bool PRE>
-__device__ void ycol_two_b(const KArgs &a, const FftAxis &fx, const FftAxis &fy, float2 *lds)
+__device__ __forceinline__ void ycol_two_b(const KArgs &a, const FftAxis &fx, const FftAxis &fy, float2 *lds)
 {
     const int stride = fft_seg_stride(fy.L2);
     const int G = max(1, min(fy.L1, FFT_LDS_CPLX / stride));
@@ -1763,13 +1772,13 @@ __device__ void ycol_two_b(const KArgs &a, const FftAxis &fx, const FftAxis &fy,
         const int col = item / nblk, k0 = (item % nblk) * G, ng = min(G, fy.L1 - k0);
         float2 *w = a.fft_wy + (size_t)col * fy.L;
         float2 *ks = a.fft_ks + (size_t)col * fy.L;
-        __syncthreads();
-        #pragma clang loop unroll(disable)
-        for (int e = threadIdx.x; e < ng * fy.L2; e += WG) {
-            const int g = e >> fy.lg2, n2 = e & (fy.L2 - 1);
-            lds[g * stride + pad16(bitrev((uint32_t)n2, fy.lg2))] = ldc2(&w[(size_t)fy.L2 * (k0 + g) + n2]);
-        }
-        fft_lds_multi(lds, fy.lg2, ng, stride, fy.tw, fy.L1, false);
+        // natural order in, forward in frequency order: the spectrum (and the
+        // PSF kernel's, made by the same code) in bit-reversed k2 order, which
+        // the inverse below takes as it is
+        staged<STAGE_TWO>(ng * fy.L2, true,
+                  [&](int e) { return ldc2(&w[(size_t)fy.L2 * (k0 + (e >> fy.lg2)) + (e & (fy.L2 - 1))]); },
+                  [&](int e, float2 v) { lds[(e >> fy.lg2) * stride + pad16(e & (fy.L2 - 1))] = v; });
+        fft_lds_multi_dif(lds, fy.lg2, ng, stride, fy.tw, fy.L1, false);
         if (PRE) {
             #pragma clang loop unroll(disable)
             for (int e = threadIdx.x; e < ng * fy.L2; e += WG) {
@@ -1778,22 +1787,12 @@ __device__ void ycol_two_b(const KArgs &a, const FftAxis &fx, const FftAxis &fy,
             }
             continue;
         }
-        #pragma clang loop unroll(disable)
-        for (int e = threadIdx.x; e < ng * fy.L2; e += WG) {
-            const int g = e >> fy.lg2, k2 = e & (fy.L2 - 1);
-            lds[g * stride + pad16(k2)] = cmul(lds[g * stride + pad16(k2)], ldc2(&ks[(size_t)fy.L2 * (k0 + g) + k2]));
-        }
-        __syncthreads();
-        #pragma clang loop unroll(disable)
-        for (int e = threadIdx.x; e < ng * fy.L2; e += WG) {    // back to bit-reversed order
-            const int g = e >> fy.lg2, i = e & (fy.L2 - 1);
-            const int j = (int)bitrev((uint32_t)i, fy.lg2);
-            if (i < j) {
-                const float2 t = lds[g * stride + pad16(i)];
-                lds[g * stride + pad16(i)] = lds[g * stride + pad16(j)];
-                lds[g * stride + pad16(j)] = t;
-            }
-        }
+        staged<STAGE_TWO>(ng * fy.L2, false,
+                  [&](int e) { return ldc2(&ks[(size_t)fy.L2 * (k0 + (e >> fy.lg2)) + (e & (fy.L2 - 1))]); },
+                  [&](int e, float2 k) {
+                      float2 &z = lds[(e >> fy.lg2) * stride + pad16(e & (fy.L2 - 1))];
+                      z = cmul(z, k);
+                  });
         fft_lds_multi(lds, fy.lg2, ng, stride, fy.tw, fy.L1, true);
         #pragma clang loop unroll(disable)
         for (int e = threadIdx.x; e < ng * fy.L2; e += WG) {
@@ -1805,7 +1804,7 @@ __device__ void ycol_two_b(const KArgs &a, const FftAxis &fx, const FftAxis &fy,
 
 // y, two levels, step 3: per carried column and n2, inverse transforms of
 // length L1 over k1, giving y = L2 n1 + n2; the first `rows` go to fft_b.
-__device__ void ycol_two_c(const KArgs &a, const FftAxis &fx, const FftAxis &fy, int rows, float2 *lds)
+__device__ __forceinline__ void ycol_two_c(const KArgs &a, const FftAxis &fx, const FftAxis &fy, int rows, float2 *lds)
 {
     const int lgNB = strided_block_lg(fy), NB = 1 << lgNB;
     const int nblk = fy.L2 / NB, stride = fft_seg_stride(fy.L1);
@@ -1813,12 +1812,9 @@ __device__ void ycol_two_c(const KArgs &a, const FftAxis &fx, const FftAxis &fy,
     for (int item = blockIdx.x; item < fx.H * nblk; item += gridDim.x) {
         const int col = item / nblk, b = item % nblk;
         const float2 *w = a.fft_wy + (size_t)col * fy.L;
-        __syncthreads();
-        #pragma clang loop unroll(disable)
-        for (int e = threadIdx.x; e < NB * fy.L1; e += WG) {
-            const int j = e & (NB - 1), k1 = e >> lgNB;
-            lds[j * stride + pad16(bitrev((uint32_t)k1, fy.lg1))] = ldc2(&w[(size_t)fy.L2 * k1 + b * NB + j]);
-        }
+        staged<STAGE_TWO>(NB * fy.L1, true,
+                  [&](int e) { return ldc2(&w[(size_t)fy.L2 * (e >> lgNB) + b * NB + (e & (NB - 1))]); },
+                  [&](int e, float2 v) { lds[(e & (NB - 1)) * stride + pad16(bitrev((uint32_t)(e >> lgNB), fy.lg1))] = v; });
         fft_lds_multi(lds, fy.lg1, NB, stride, fy.tw, fy.L2, true);
         float2 *dst = a.fft_b + (size_t)col * rows;
         #pragma clang loop unroll(disable)
@@ -1917,7 +1913,7 @@ __device__ void xinv_one(const KArgs &a, const FftAxis &fx, float scale, float2 
 // x inverse, two levels, step 1: per row pair and row k1, Z(k1, k2) for all
 // k2 from the carried bins (A + iB, or conj A + i conj B at mirrored bins),
 // inverse transform over k2 (length L2), times conj W_L^(n2 k1), into fft_wx.
-__device__ void xinv_two_a(const KArgs &a, const FftAxis &fx, float2 *lds)
+__device__ __forceinline__ void xinv_two_a(const KArgs &a, const FftAxis &fx, float2 *lds)
 {
     const int ny = a.ny, stride = fft_seg_stride(fx.L2), hq = fx.L2 / 2;
     const int G = max(1, min(fx.L1, FFT_LDS_CPLX / stride));
@@ -1928,19 +1924,23 @@ __device__ void xinv_two_a(const KArgs &a, const FftAxis &fx, float2 *lds)
         const int r0 = 2 * pr;
         const bool has1 = r0 + 1 < ny;
         const float2 *i0 = a.fft_a + (size_t)r0 * fx.H, *i1 = i0 + fx.H;
-        __syncthreads();
-        #pragma clang loop unroll(disable)
-        for (int e = threadIdx.x; e < ng * fx.L2; e += WG) {
-            const int g = e >> fx.lg2, k2 = e & (fx.L2 - 1), k1 = k0 + g;
-            const bool carried = k2 < hq || (k2 == hq && k1 == 0);
-            int q1 = k1, q2 = k2;
-            if (!carried) mirror_of(fx, k1, k2, q1, q2);
-            const int c = chat_of(fx, q1, q2);
-            const float2 A = ldc2(&i0[c]);
-            const float2 B = has1 ? ldc2(&i1[c]) : make_float2(0.f, 0.f);
-            lds[g * stride + pad16(bitrev((uint32_t)k2, fx.lg2))] =
-                carried ? make_float2(A.x - B.y, A.y + B.x) : make_float2(A.x + B.y, B.x - A.y);
-        }
+        staged<STAGE_TWO>(ng * fx.L2, true,
+                  [&](int e) {
+                      const int k2 = e & (fx.L2 - 1), k1 = k0 + (e >> fx.lg2);
+                      const bool carried = k2 < hq || (k2 == hq && k1 == 0);
+                      int q1 = k1, q2 = k2;
+                      if (!carried) mirror_of(fx, k1, k2, q1, q2);
+                      const int c = chat_of(fx, q1, q2);
+                      const float2 A = ldc2(&i0[c]), B = ldc2(has1 ? &i1[c] : &i0[c]);   // B unused without row r0 + 1
+                      return make_float4(A.x, A.y, B.x, B.y);
+                  },
+                  [&](int e, float4 q) {
+                      const int k2 = e & (fx.L2 - 1), k1 = k0 + (e >> fx.lg2);
+                      const bool carried = k2 < hq || (k2 == hq && k1 == 0);
+                      const float2 A = make_float2(q.x, q.y), B = has1 ? make_float2(q.z, q.w) : make_float2(0.f, 0.f);
+                      lds[(e >> fx.lg2) * stride + pad16(bitrev((uint32_t)k2, fx.lg2))] =
+                          carried ? make_float2(A.x - B.y, A.y + B.x) : make_float2(A.x + B.y, B.x - A.y);
+                  });
         fft_lds_multi(lds, fx.lg2, ng, stride, fx.tw, fx.L1, true);
         float2 *w = a.fft_wx + (size_t)pr * fx.L;
         #pragma clang loop unroll(disable)
@@ -1954,7 +1954,7 @@ __device__ void xinv_two_a(const KArgs &a, const FftAxis &fx, float2 *lds)
 // x inverse, two levels, step 2: per row pair and n2, inverse transforms of
 // length L1 over k1 giving x = L2 n1 + n2; real / imaginary parts of the
 // first nx, scaled, into the feedback buffer rows 2m / 2m+1.
-__device__ void xinv_two_b(const KArgs &a, const FftAxis &fx, float scale, float2 *lds)
+__device__ __forceinline__ void xinv_two_b(const KArgs &a, const FftAxis &fx, float scale, float2 *lds)
 {
     const int ny = a.ny, nx = a.nx;
     const int lgNB = strided_block_lg(fx), NB = 1 << lgNB;
@@ -1965,12 +1965,9 @@ __device__ void xinv_two_b(const KArgs &a, const FftAxis &fx, float scale, float
         const int r0 = 2 * pr;
         const bool has1 = r0 + 1 < ny;
         const float2 *w = a.fft_wx + (size_t)pr * fx.L;
-        __syncthreads();
-        #pragma clang loop unroll(disable)
-        for (int e = threadIdx.x; e < NB * fx.L1; e += WG) {
-            const int j = e & (NB - 1), k1 = e >> lgNB;
-            lds[j * stride + pad16(bitrev((uint32_t)k1, fx.lg1))] = ldc2(&w[(size_t)fx.L2 * k1 + b * NB + j]);
-        }
+        staged<STAGE_TWO>(NB * fx.L1, true,
+                  [&](int e) { return ldc2(&w[(size_t)fx.L2 * (e >> lgNB) + b * NB + (e & (NB - 1))]); },
+                  [&](int e, float2 v) { lds[(e & (NB - 1)) * stride + pad16(bitrev((uint32_t)(e >> lgNB), fx.lg1))] = v; });
         fft_lds_multi(lds, fx.lg1, NB, stride, fx.tw, fx.L2, true);
         #pragma clang loop unroll(disable)
         for (int e = threadIdx.x; e < NB * fx.L1; e += WG) {
@@ -2025,7 +2022,7 @@ __device__ bool fft_spectrum(const KArgs &a, const Sync &y, uint32_t &epoch, int
 // mathematically the paper's update (own components subtracted locally, the
 // others' by feedback), rounded once.
 template <typename PT, bool BIG = false>
-__device__ bool fft_feedback(const KArgs &a, const Sync &y, uint32_t &epoch, int *s_ok, const int32_t *s_off)
+__device__ __forceinline__ bool fft_feedback(const KArgs &a, const Sync &y, uint32_t &epoch, int *s_ok, const int32_t *s_off)
 {
     extern __shared__ __align__(16) unsigned char s_dyn[];
     __shared__ int s_nz;
