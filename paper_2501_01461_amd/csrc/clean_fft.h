@@ -418,14 +418,8 @@ __device__ __forceinline__ void tw13_load(Tw13 &T, const float2 *tw)
 // not depend on the thread (for these S the padding of base + m * 2^S splits
 // into the padding of base and of m * 2^S).
 template <int S, bool DIF, bool INV>
-__device__ __forceinline__ void f13_pass16(float2 *a, const float2 (&w)[10])
+__device__ __forceinline__ void f13_units(float2 (&x)[16], const float2 (&w)[10])
 {
-    constexpr int half = 1 << S;
-    const int t = threadIdx.x;
-    float2 *b = a + pad16(((t >> S) << (S + 4)) + (t & (half - 1)));
-    float2 x[16];
-#pragma unroll
-    for (int m = 0; m < 16; ++m) x[m] = b[pad16c(m * half)];
     if (!DIF) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) unit4<false, INV>(x[4 * q], x[4 * q + 1], x[4 * q + 2], x[4 * q + 3], w[0], w[1]);
@@ -437,6 +431,27 @@ __device__ __forceinline__ void f13_pass16(float2 *a, const float2 (&w)[10])
 #pragma unroll
         for (int q = 0; q < 4; ++q) unit4<true, INV>(x[4 * q], x[4 * q + 1], x[4 * q + 2], x[4 * q + 3], w[0], w[1]);
     }
+}
+
+// The thread's first slot in the pass at stages S .. S+3.  At S = 9 the
+// unit's 16 points are elements t + 512 m, the thread's natural-order
+// elements, so that pass can take its input from registers (frequency order)
+// or leave its output there (time order).
+template <int S> __device__ __forceinline__ float2 *f13_base(float2 *a)
+{
+    const int t = threadIdx.x;
+    return a + pad16(((t >> S) << (S + 4)) + (t & ((1 << S) - 1)));
+}
+
+template <int S, bool DIF, bool INV>
+__device__ __forceinline__ void f13_pass16(float2 *a, const float2 (&w)[10])
+{
+    constexpr int half = 1 << S;
+    float2 *b = f13_base<S>(a);
+    float2 x[16];
+#pragma unroll
+    for (int m = 0; m < 16; ++m) x[m] = b[pad16c(m * half)];
+    f13_units<S, DIF, INV>(x, w);
 #pragma unroll
     for (int m = 0; m < 16; ++m) b[pad16c(m * half)] = x[m];
     __syncthreads();

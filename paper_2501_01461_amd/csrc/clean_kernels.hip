@@ -1624,26 +1624,35 @@ __device__ __forceinline__ void xfwd_two_b(const KArgs &a, const FftAxis &fx, in
 // The wide-tile kernel's y phase at length 8192, per carried column: the
 // column and its zero padding (natural order) -> forward in frequency order
 // -> product with the PSF kernel's spectrum (held in the same bit-reversed
-// order) -> inverse in time order -> the first `rows` values.  The next
-// column's values and spectrum are loaded while this one is transformed.
+// order) -> inverse in time order -> the first `rows` values.  Fused where
+// the data allow: the forward's first pass takes the column from registers,
+// the forward's last stage, the product and the inverse's first stage are one
+// sweep over the pairs (2j, 2j+1), and the inverse's last pass leaves the
+// result in registers for the stores.  The next column's values and spectrum
+// are loaded while this one is transformed.
 __device__ void ycol13(const KArgs &a, const FftAxis &fx, int rows, float2 *lds)
 {
     constexpr int L = 1 << F13, M = L / WG;
     Tw13 T;
     tw13_load(T, a.tw_y);
     const int t = threadIdx.x;
-    float2 *const slot = lds + pad16(t);           // element t + WG m at slot[pad16c(WG m)]
-    float2 nb[M], nk[M];
+    float2 nb[M];                   // the column, elements t + WG m
+    float4 nk[M / 2];               // the spectrum at slots 2j, 2j+1 of j = t + WG m
     auto load_b = [&](int c) {
         const float2 *b = a.fft_b + (size_t)c * rows;
 #pragma unroll
-        for (int m = 0; m < M; ++m) nb[m] = t + WG * m < rows ? ldc2(b + t + WG * m) : make_float2(0.f, 0.f);
+        for (int m = 0; m < M; ++m) nb[m] = ldc2(b + min(t + WG * m, rows - 1));
     };
     auto load_k = [&](int c) {
         const float2 *k = a.fft_ks + (size_t)c * L;
 #pragma unroll
-        for (int m = 0; m < M; ++m) nk[m] = ldc2(k + t + WG * m);
+        for (int m = 0; m < M / 2; ++m) {
+            const float2 k0 = ldc2(k + 2 * t + 2 * WG * m), k1 = ldc2(k + 2 * t + 2 * WG * m + 1);
+            nk[m] = make_float4(k0.x, k0.y, k1.x, k1.y);
+        }
     };
+    float2 *const b9 = f13_base<9>(lds);            // element t + WG m at b9[pad16c(WG m)]
+    float2 *const p2 = lds + pad16(2 * t);           // pair j = t + WG m at p2[pad16c(2 WG m)], +1
     int col = blockIdx.x;
     if (col < fx.H) {
         load_b(col);
@@ -1652,19 +1661,37 @@ __device__ void ycol13(const KArgs &a, const FftAxis &fx, int rows, float2 *lds)
     #pragma clang loop unroll(disable)
     for (; col < fx.H; col += gridDim.x) {
         const int nxt = col + gridDim.x;
-        __syncthreads();
+        float2 x[M];
 #pragma unroll
-        for (int m = 0; m < M; ++m) slot[pad16c(WG * m)] = nb[m];
+        for (int m = 0; m < M; ++m) x[m] = t + WG * m < rows ? nb[m] : make_float2(0.f, 0.f);
         if (nxt < fx.H) load_b(nxt);
-        fft13<true, false>(lds, T);
+        f13_units<9, true, false>(x, T.w[2]);
+        __syncthreads();                            // the previous column's last reads are done
 #pragma unroll
-        for (int m = 0; m < M; ++m) slot[pad16c(WG * m)] = twmul<false>(slot[pad16c(WG * m)], nk[m]);
+        for (int m = 0; m < M; ++m) b9[pad16c(WG * m)] = x[m];
+        __syncthreads();
+        f13_pass16<5, true, false>(lds, T.w[1]);
+        f13_pass16<1, true, false>(lds, T.w[0]);
+#pragma unroll
+        for (int m = 0; m < M / 2; ++m) {
+            float2 *q = p2 + pad16c(2 * WG * m);
+            const float2 u = q[0], v = q[1];
+            const float2 f0 = twmul<false>(make_float2(u.x + v.x, u.y + v.y), make_float2(nk[m].x, nk[m].y));
+            const float2 f1 = twmul<false>(make_float2(u.x - v.x, u.y - v.y), make_float2(nk[m].z, nk[m].w));
+            q[0] = make_float2(f0.x + f1.x, f0.y + f1.y);
+            q[1] = make_float2(f0.x - f1.x, f0.y - f1.y);
+        }
+        __syncthreads();
         if (nxt < fx.H) load_k(nxt);
-        fft13<false, true>(lds, T);
+        f13_pass16<1, false, true>(lds, T.w[0]);
+        f13_pass16<5, false, true>(lds, T.w[1]);
+#pragma unroll
+        for (int m = 0; m < M; ++m) x[m] = b9[pad16c(WG * m)];
+        f13_units<9, false, true>(x, T.w[2]);
         float2 *b = a.fft_b + (size_t)col * rows;
 #pragma unroll
         for (int m = 0; m < M; ++m)
-            if (t + WG * m < rows) stc2(b + t + WG * m, slot[pad16c(WG * m)]);
+            if (t + WG * m < rows) stc2(b + t + WG * m, x[m]);
     }
 }
 
