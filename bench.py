@@ -53,7 +53,7 @@ def counters(kernel_tag, launch=None):
     if rec is None:
         return None
     h = hashlib.sha256()
-    for f in ("clean_kernels.hip", "clean_device.h"):
+    for f in ("clean_kernels.hip", "clean_device.h", "clean_fft.h"):
         h.update(open(os.path.join(root, "paper_2501_01461_amd", "csrc", f), "rb").read())
     if rec.get("source_sha256") != h.hexdigest() or (launch is not None and rec.get("launch") != launch):
         return None
