@@ -382,6 +382,22 @@ def test_resume_continues_the_sequence():
     assert np.array_equal(full["residual"], b["residual"])
 
 
+def test_tiled_resume_at_round_boundaries():
+    """With the interval trigger and no early stops, a run of k full rounds
+    leaves everything the method carries in its residual: continuing from it
+    gives the rest of the longer run's components and its residual, bit for
+    bit (the plain loop's memorylessness, round by round)."""
+    c = synth.make_config(0)
+    T, I = 4, 25
+    full = oracle.tiled(c["dirty"], c["psf"], (2, 2), I, 0.1, 0.0, 8 * T * I)
+    a = oracle.tiled(c["dirty"], c["psf"], (2, 2), I, 0.1, 0.0, 3 * T * I)
+    b = oracle.tiled(a["residual"], c["psf"], (2, 2), I, 0.1, 0.0, 5 * T * I)
+    assert (a["n_rounds"], b["n_rounds"], full["n_rounds"]) == (3, 5, 8)
+    assert np.array_equal(full["idx"], np.concatenate([a["idx"], b["idx"]]))
+    assert np.array_equal(full["flux"].view(np.uint32), np.concatenate([a["flux"], b["flux"]]).view(np.uint32))
+    assert np.array_equal(full["residual"].view(np.uint32), b["residual"].view(np.uint32))
+
+
 def test_fp32_close_to_fp64_on_the_small_workload():
     c = synth.make_config(0)
     a = oracle.hogbom(c["dirty"], c["psf"], 0.1, 5e-3, 1000, precision="f32")
