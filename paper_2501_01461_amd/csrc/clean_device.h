@@ -44,6 +44,14 @@ struct DevCtl {
     uint32_t pad3[31];
     uint32_t cancel;        // tiled: the caller's cancel flag as read before the last grid barrier
     uint32_t pad4[31];
+    // tiled launches, the two-level round barrier: workgroups per XCD (counted
+    // at launch), per-XCD arrival counters and release words (one line each),
+    // and the counter the last arriver of each XCD arrives on
+    uint32_t xmem[32];
+    uint32_t xarr[16][32];
+    uint32_t xrel[16][32];
+    uint32_t xlead;
+    uint32_t pad5[31];
 };
 
 struct DevStat {

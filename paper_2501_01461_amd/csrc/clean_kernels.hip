@@ -508,6 +508,59 @@ __device__ __forceinline__ bool grid_barrier(const Sync &y, uint32_t &epoch, int
     return scope_barrier(y, &y.ctl->barrier, gridDim.x, epoch, s_ok);
 }
 
+// Two-level grid barrier for the rounds of a tiled launch.  One counter that
+// every workgroup of the grid arrives on serialises the arrivals at the
+// memory side (about 4 us for 256 workgroups, 9.5 us for 512); here a
+// workgroup arrives on its XCD's counter, the last arriver of each XCD
+// arrives on the leaders' counter, waits for every XCD that holds
+// workgroups, and releases its XCD through a word of its own (about 2 us and
+// 2.5 us).  The ordering argument is the flat barrier's: every wave's stores
+// complete before its workgroup arrives, a leader arrives only after its whole
+// XCD has, and a release is written only after every leader has arrived.
+// x: this workgroup's XCD; mx: workgroups on it; nx: XCDs holding workgroups
+// (both counted at launch); epoch counts these barriers.  The state lives in
+// LDS and only thread 0 touches it, so it costs the persistent kernels no
+// registers.
+struct XcdBar {
+    uint32_t x, mx, nx, epoch;
+};
+
+__device__ bool xcd_grid_barrier(const Sync &y, XcdBar *xb, int *s_ok)
+{
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        bool ok = true;
+        const uint32_t x = xb->x, ep = xb->epoch + 1;
+        xb->epoch = ep;
+        uint32_t *rel = &y.ctl->xrel[x][0];
+        const uint32_t old = __hip_atomic_fetch_add(&y.ctl->xarr[x][0], 1u, __ATOMIC_RELAXED,
+                                                    __HIP_MEMORY_SCOPE_AGENT);
+        const uint64_t t0 = wall_clock64();
+        if (old + 1 == ep * xb->mx) {               // the last of this XCD
+            __hip_atomic_fetch_add(&y.ctl->xlead, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const uint32_t all = ep * xb->nx;
+            while (ld_agent32(&y.ctl->xlead) < all) {
+                if (ld_agent32(&y.ctl->abort)) { ok = false; break; }
+                if (wall_clock64() - t0 > y.timeout_ticks) { raise_abort(y, ABORT_TIMEOUT); ok = false; break; }
+                __builtin_amdgcn_s_sleep(1);
+            }
+            __hip_atomic_store(rel, ep, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            while (ld_agent32(rel) < ep) {
+                if (ld_agent32(&y.ctl->abort)) { ok = false; break; }
+                if (wall_clock64() - t0 > y.timeout_ticks) { raise_abort(y, ABORT_TIMEOUT); ok = false; break; }
+                __builtin_amdgcn_s_sleep(1);
+            }
+        }
+        *s_ok = ok;
+    }
+    __syncthreads();
+    bool ok = *s_ok;
+    __syncthreads();
+    return ok;
+}
+
 __device__ __forceinline__ void tile_rect(const KArgs &a, int t, int &y0, int &x0, int &h, int &w)
 {
     const int i = t / a.tx, j = t % a.tx;
@@ -539,6 +592,7 @@ template <int K, int V, typename PT> struct RegTile {
     static constexpr bool kResident = true;
     static constexpr bool kWide = false;
     static constexpr int kV = V;
+    static constexpr int kPx = K * V;
     using psf_t = PT;
     float r[K][V];
     int32_t qoff[K];        // (y)*psf_nx + (x) of the group's first pixel, image coords
@@ -2248,6 +2302,11 @@ __device__ __forceinline__ void tiled_body(const KArgs &a, int member_arg, int m
     Tile R;
     uint32_t e = 0, epoch = 0;
     uint64_t cur = 0;
+    __shared__ XcdBar s_xb;
+    if (!BATCH && threadIdx.x == 0) {
+        s_xb = XcdBar{xcc_id(), 0, 0, 0};
+        __hip_atomic_fetch_add(&a.ctl->xmem[s_xb.x], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
     if (is_cluster) {
         int ty0, tx0, th, tw;
         tile_rect(a, tile, ty0, tx0, th, tw);
@@ -2268,6 +2327,14 @@ __device__ __forceinline__ void tiled_body(const KArgs &a, int member_arg, int m
     if (a.has_cancel && member == 0 && threadIdx.x == 0)
         stc(BATCH ? a.cword : &a.ctl->cancel, host_flag(a.cancel));
     if (!scope_barrier(y, BATCH ? a.bar : &a.ctl->barrier, members, epoch, &s_ok)) return;
+    if (!BATCH && threadIdx.x == 0) {
+        // every workgroup has counted itself into its XCD: the two-level
+        // round barrier's member counts
+        uint32_t n = 0;
+        for (int i = 0; i < 16; ++i) n += ld_agent32(&a.ctl->xmem[i]) != 0u;
+        s_xb.mx = ld_agent32(&a.ctl->xmem[s_xb.x]);
+        s_xb.nx = n;
+    }
     if constexpr (FFT) {
         if (!fft_spectrum<PT, Tile::kWide>(a, y, epoch, &s_ok)) return;
     }
@@ -2346,7 +2413,7 @@ __device__ __forceinline__ void tiled_body(const KArgs &a, int member_arg, int m
                 aggregate_round(a, tile, L, l_idx, l_flux, l_tmp, l_sum, &s_cnt);
             }
         }
-        if (!scope_barrier(y, BATCH ? a.bar : &a.ctl->barrier, members, epoch, &s_ok)) return;   // A
+        if (!(BATCH ? scope_barrier(y, a.bar, members, epoch, &s_ok) : xcd_grid_barrier(y, &s_xb, &s_ok))) return;   // A
         if (member == 0) { tp1 = wall_clock64(); ph_local += tp1 - tp0; tp0 = tp1; }
 
         // ---- round bookkeeping: every workgroup reads the counts
@@ -2501,7 +2568,7 @@ __device__ __forceinline__ void tiled_body(const KArgs &a, int member_arg, int m
                 }
             }
         }
-        if (!scope_barrier(y, BATCH ? a.bar : &a.ctl->barrier, members, epoch, &s_ok)) return;   // B
+        if (!(BATCH ? scope_barrier(y, a.bar, members, epoch, &s_ok) : xcd_grid_barrier(y, &s_xb, &s_ok))) return;   // B
         if (member == 0) { tp1 = wall_clock64(); ph_gather += tp1 - tp0; tp0 = tp1; }
 
         // ---- apply feedback and find each tile's new peak
@@ -2512,7 +2579,7 @@ __device__ __forceinline__ void tiled_body(const KArgs &a, int member_arg, int m
         rounds += 1;
         if (a.has_cancel && member == 0 && threadIdx.x == 0)
             stc(BATCH ? a.cword : &a.ctl->cancel, host_flag(a.cancel));
-        if (!scope_barrier(y, BATCH ? a.bar : &a.ctl->barrier, members, epoch, &s_ok)) return;   // C
+        if (!(BATCH ? scope_barrier(y, a.bar, members, epoch, &s_ok) : xcd_grid_barrier(y, &s_xb, &s_ok))) return;   // C
         if (member == 0) { tp1 = wall_clock64(); ph_apply += tp1 - tp0; }
     }
 
@@ -2612,9 +2679,20 @@ template <class Tile, bool TILED> __global__ void __launch_bounds__(WG) batched_
 }
 
 
+// Waves per SIMD the tiled kernel is compiled for: 4 (two 512-thread
+// workgroups per CU, 128 registers) where the launches count on two
+// co-resident workgroups per CU (the streamed tiles with the FFT feedback,
+// and the 4-pixel register tiles with the direct feedback, whose clusters are
+// the largest), else whatever the registers allow.
+template <class Tile, bool FFT> __host__ __device__ constexpr int tiled_waves()
+{
+    if constexpr (Tile::kResident) return !FFT && Tile::kPx <= 4 ? 4 : 1;
+    else return FFT && !Tile::kWide ? 4 : 1;
+}
+
 // The tiled form on the whole grid (one persistent, cooperative launch).
 template <class Tile, bool FFT>
-__global__ void __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(FFT && !Tile::kResident && !Tile::kWide ? 4 : 1)))
+__global__ void __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(tiled_waves<Tile, FFT>())))
 tiled_kernel(const KArgs a)
 {
     // The argument block is used where it lies, in the kernel argument
