@@ -39,6 +39,22 @@ __device__ __forceinline__ void stc2(float2 *p, float2 v)
     __hip_atomic_store((gmut_u64 *)p, u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Plain 8- and 16-byte global accesses (no coherence bits, so they may stay
+// in this XCD's L2): for buffers whose writers and readers a fenced grid
+// barrier separates.  The 16-byte forms need a 16-byte aligned address.
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(1))) f32x2 g_f32x2;
+typedef __attribute__((address_space(1))) f32x4 g_f32x4;
+__device__ __forceinline__ void stp2(float2 *p, float2 v) { *(g_f32x2 *)p = f32x2{v.x, v.y}; }
+__device__ __forceinline__ void stp4(float2 *p, float2 u, float2 v) { *(g_f32x4 *)p = f32x4{u.x, u.y, v.x, v.y}; }
+__device__ __forceinline__ float2 ldp2(const float2 *p)
+{
+    const f32x2 q = *(const g_f32x2 *)p;
+    return make_float2(q.x, q.y);
+}
+__device__ __forceinline__ f32x4 ldp4(const float2 *p) { return *(const g_f32x4 *)p; }
+
 // A workgroup-strided loop over e < n (e = threadIdx.x + m * WG) whose body
 // reads global memory, then writes: the reads of U consecutive steps are
 // issued before the first write, so U memory round trips overlap instead of

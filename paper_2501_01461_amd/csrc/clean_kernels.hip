@@ -521,15 +521,23 @@ __device__ __forceinline__ bool grid_barrier(const Sync &y, uint32_t &epoch, int
 // (both counted at launch); epoch counts these barriers.  The state lives in
 // LDS and only thread 0 touches it, so it costs the persistent kernels no
 // registers.
+// FENCE adds an agent-scope release fence before the arrival and an acquire
+// fence after the wait: plain (non-coherent) stores made before the barrier
+// are then written back from the writer's L2, and plain loads after it miss
+// every stale line in the reader's L1 and L2.  The transforms' column-major
+// spectra use it: their 16-byte pieces of a line, written by the workgroups of
+// one XCD, merge in that XCD's L2 instead of each going to memory on its own.
 struct XcdBar {
     uint32_t x, mx, nx, epoch;
 };
 
-__device__ bool xcd_grid_barrier(const Sync &y, XcdBar *xb, int *s_ok)
+template <bool FENCE = false>
+__device__ __forceinline__ bool xcd_grid_barrier(const Sync &y, XcdBar *xb, int *s_ok)
 {
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads();
     if (threadIdx.x == 0) {
+        if constexpr (FENCE) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         bool ok = true;
         const uint32_t x = xb->x, ep = xb->epoch + 1;
         xb->epoch = ep;
@@ -553,6 +561,7 @@ __device__ bool xcd_grid_barrier(const Sync &y, XcdBar *xb, int *s_ok)
                 __builtin_amdgcn_s_sleep(1);
             }
         }
+        if constexpr (FENCE) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         *s_ok = ok;
     }
     __syncthreads();
@@ -1483,9 +1492,39 @@ __device__ __forceinline__ void store_split(float2 *o0, float2 *o1, bool has1, i
     if (has1) stc2(&o1[c], make_float2(0.5f * (zk.y + zm.y), -0.5f * (zk.x - zm.x)));
 }
 
+// The same split, stored column-major for the y phase: bin k of rows r0 and
+// r0 + 1 at o[k * rows] and o[k * rows + 1] (o = buffer + r0), plain stores
+// (a fenced barrier follows); one 16-byte store when `rows` is even (row
+// r0 + 1 then always exists and the pair is 16-byte aligned).
+__device__ __forceinline__ void store_cols(float2 *o, int rows, bool has1, int k, float2 zk, float2 zm)
+{
+    const float2 v0 = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y));
+    const float2 v1 = make_float2(0.5f * (zk.y + zm.y), -0.5f * (zk.x - zm.x));
+    float2 *p = o + (size_t)k * rows;
+    if ((rows & 1) == 0) {
+        stp4(p, v0, v1);
+    } else {
+        stp2(p, v0);
+        if (has1) stp2(p + 1, v1);
+    }
+}
+
+// The one-level x phases' row-pair order: the workgroups of one XCD
+// (workgroup b runs on XCD b % 8) take consecutive row pairs, so that the
+// 16-byte pieces of one column-major line are written, and read, through a
+// single L2.  Any order is correct; this is the one-to-one map of
+// [0, gridDim.x) that groups them (the identity when the grid is not a
+// multiple of 8).
+__device__ __forceinline__ int xcd_slot()
+{
+    const int w = blockIdx.x, g = gridDim.x;
+    return (g & 7) ? w : (w & 7) * (g >> 3) + (w >> 3);
+}
+
 // x forward, one level: row pairs -> carried bins (natural order) of `rows`
-// rows, into fft_a (row stride H).  Source: the round's aggregated component
-// lists, or (KSRC) the PSF kernel image.
+// rows, column-major into fft_b (bin k of row r at k * rows + r, the layout
+// the y phase transforms).  Source: the round's aggregated component lists,
+// or (KSRC) the PSF kernel image.
 template <typename PT, bool KSRC, bool BIG = false>
 __device__ void xfwd_one(const KArgs &a, const FftAxis &fx, int Ly, int rows, const int32_t *s_off, float2 *lds,
                          int *s_nz)
@@ -1495,8 +1534,9 @@ __device__ void xfwd_one(const KArgs &a, const FftAxis &fx, int Ly, int rows, co
     auto at = [](int i) { return pad16(i); };
     Tw13 T13;
     if (BIG && lgx == F13) tw13_load(T13, fx.tw);
+    const int npr = (rows + 1) / 2;
     #pragma clang loop unroll(disable)
-    for (int pr = blockIdx.x; pr < (rows + 1) / 2; pr += gridDim.x) {
+    for (int pr = xcd_slot(); pr < npr; pr += gridDim.x) {
         const int r0 = 2 * pr;
         const bool has1 = r0 + 1 < rows;
         if (KSRC) {
@@ -1549,11 +1589,11 @@ __device__ void xfwd_one(const KArgs &a, const FftAxis &fx, int Ly, int rows, co
             }
             __syncthreads();
         }
-        float2 *o0 = a.fft_a + (size_t)r0 * fx.H, *o1 = o0 + fx.H;
+        float2 *o = a.fft_b + r0;
         if (*s_nz == 0) {                       // both rows empty: zero spectra
             #pragma clang loop unroll(disable)
-            for (int k = threadIdx.x; k < fx.H; k += WG) store_split(o0, o1, has1, k, make_float2(0.f, 0.f),
-                                                                    make_float2(0.f, 0.f));
+            for (int k = threadIdx.x; k < fx.H; k += WG) store_cols(o, rows, has1, k, make_float2(0.f, 0.f),
+                                                                   make_float2(0.f, 0.f));
         } else {
             if constexpr (BIG) {
                 if (lgx == F13) fft13<false, false>(lds, T13);
@@ -1563,7 +1603,7 @@ __device__ void xfwd_one(const KArgs &a, const FftAxis &fx, int Ly, int rows, co
             }
             #pragma clang loop unroll(disable)
             for (int k = threadIdx.x; k < fx.H; k += WG)
-                store_split(o0, o1, has1, k, lds[at(k)], lds[at((Lx - k) & (Lx - 1))]);
+                store_cols(o, rows, has1, k, lds[at(k)], lds[at((Lx - k) & (Lx - 1))]);
         }
         __syncthreads();
     }
@@ -1917,16 +1957,25 @@ __device__ void xinv13(const KArgs &a, const FftAxis &fx, float scale, float2 *l
     const int t = threadIdx.x, ny = a.ny, nx = a.nx, npr = (ny + 1) / 2;
     float2 nA[M], nB[M];
     auto load = [&](int pr) {
-        const float2 *i0 = a.fft_a + (size_t)(2 * pr) * H, *i1 = i0 + H;
+        const float2 *c0 = a.fft_b + 2 * pr;
         const bool has1 = 2 * pr + 1 < ny;
 #pragma unroll
         for (int m = 0; m < M; ++m) {
-            const int k = t + WG * m;
-            nA[m] = k < H ? ldc2(i0 + k) : make_float2(0.f, 0.f);
-            nB[m] = k < H && has1 ? ldc2(i1 + k) : make_float2(0.f, 0.f);
+            const int k = t + WG * m, kc = min(k, H - 1);
+            float2 A, B = make_float2(0.f, 0.f);
+            if ((ny & 1) == 0) {
+                const f32x4 q = ldp4(c0 + (size_t)kc * ny);
+                A = make_float2(q.x, q.y);
+                B = make_float2(q.z, q.w);
+            } else {
+                A = ldp2(c0 + (size_t)kc * ny);
+                if (has1) B = ldp2(c0 + (size_t)kc * ny + 1);
+            }
+            nA[m] = k < H ? A : make_float2(0.f, 0.f);
+            nB[m] = k < H ? B : make_float2(0.f, 0.f);
         }
     };
-    int pr = blockIdx.x;
+    int pr = xcd_slot();
     if (pr < npr) load(pr);
     #pragma clang loop unroll(disable)
     for (; pr < npr; pr += gridDim.x) {
@@ -1954,8 +2003,9 @@ __device__ void xinv13(const KArgs &a, const FftAxis &fx, float scale, float2 *l
 }
 
 // x inverse, one level: row pairs rebuilt from their carried bins (Hermitian
-// symmetry gives the rest), one inverse transform, real part -> row 2m,
-// imaginary part -> row 2m+1, scaled, into the feedback buffer.
+// symmetry gives the rest; read column-major from fft_b, where the y phase
+// leaves them), one inverse transform, real part -> row 2m, imaginary part ->
+// row 2m+1, scaled, into the feedback buffer.
 template <bool BIG = false>
 __device__ void xinv_one(const KArgs &a, const FftAxis &fx, float scale, float2 *lds)
 {
@@ -1968,14 +2018,21 @@ __device__ void xinv_one(const KArgs &a, const FftAxis &fx, float scale, float2 
     const int Lx = fx.L, lgx = fx.lg, ny = a.ny, nx = a.nx;
     auto at = [](int i) { return pad16(i); };
     #pragma clang loop unroll(disable)
-    for (int pr = blockIdx.x; pr < (ny + 1) / 2; pr += gridDim.x) {
+    for (int pr = xcd_slot(); pr < (ny + 1) / 2; pr += gridDim.x) {
         const int r0 = 2 * pr;
         const bool has1 = r0 + 1 < ny;
-        const float2 *i0 = a.fft_a + (size_t)r0 * fx.H, *i1 = i0 + fx.H;
+        const float2 *c0 = a.fft_b + r0;
         #pragma clang loop unroll(disable)
         for (int k = threadIdx.x; k < fx.H; k += WG) {
-            const float2 A = ldc2(&i0[k]);
-            const float2 B = has1 ? ldc2(&i1[k]) : make_float2(0.f, 0.f);
+            float2 A, B = make_float2(0.f, 0.f);
+            if ((ny & 1) == 0) {
+                const f32x4 q = ldp4(c0 + (size_t)k * ny);
+                A = make_float2(q.x, q.y);
+                B = make_float2(q.z, q.w);
+            } else {
+                A = ldp2(c0 + (size_t)k * ny);
+                if (has1) B = ldp2(c0 + (size_t)k * ny + 1);
+            }
             lds[at(bitrev((uint32_t)k, lgx))] = make_float2(A.x - B.y, A.y + B.x);
             if (k > 0 && k < Lx / 2) lds[at(bitrev((uint32_t)(Lx - k), lgx))] = make_float2(A.x + B.y, B.x - A.y);
         }
@@ -2063,13 +2120,20 @@ __device__ __forceinline__ void xinv_two_b(const KArgs &a, const FftAxis &fx, fl
     }
 }
 
-#define FFT_BARRIER() do { if (!grid_barrier(y, epoch, s_ok)) return false; } while (0)
+#define FFT_BARRIER() do { if (!xcd_grid_barrier(y, xb, s_ok)) return false; } while (0)
+#define FFT_BARRIER_FENCED() do { if (!xcd_grid_barrier<true>(y, xb, s_ok)) return false; } while (0)
 
 // The PSF kernel's spectrum, once per call, by the same transforms as the
-// rounds: x forward over all Ly rows of the kernel image, transpose, y forward.
+// rounds: x forward over all Ly rows of the kernel image (two levels: then
+// transposed), y forward.  A function of its own (called once per launch),
+// its arguments by value or by address, so that none of them needs a stack
+// copy.
 template <typename PT, bool BIG = false>
-__device__ bool fft_spectrum(const KArgs &a, const Sync &y, uint32_t &epoch, int *s_ok)
+__device__ __noinline__ bool fft_spectrum(const KArgs *a_arg, const Sync y_arg, XcdBar *xb_arg, int *s_ok)
 {
+    const KArgs &a = *wave_uniform(a_arg);
+    const Sync y = wave_uniform(y_arg);
+    XcdBar *xb = wave_uniform(xb_arg);
     extern __shared__ __align__(16) unsigned char s_dyn[];
     __shared__ int s_nz;
     float2 *lds = (float2 *)s_dyn;
@@ -2078,14 +2142,15 @@ __device__ bool fft_spectrum(const KArgs &a, const Sync &y, uint32_t &epoch, int
     const int Ly = fy.L;
     if (!fx.two) {
         xfwd_one<PT, true, BIG>(a, fx, Ly, Ly, nullptr, lds, &s_nz);
+        FFT_BARRIER_FENCED();
     } else {
         xfwd_two_a<PT, true>(a, fx, Ly, Ly, lds);
         FFT_BARRIER();
         xfwd_two_b<true>(a, fx, Ly, lds, nullptr);
+        FFT_BARRIER();
+        transpose_tiles<BIG ? TR_GROUP_WIDE : 1>(a.fft_a, fx.H, a.fft_b, Ly, Ly, fx.H, blockIdx.x, gridDim.x, s_tr);
+        FFT_BARRIER();
     }
-    FFT_BARRIER();
-    transpose_tiles<BIG ? TR_GROUP_WIDE : 1>(a.fft_a, fx.H, a.fft_b, Ly, Ly, fx.H, blockIdx.x, gridDim.x, s_tr);
-    FFT_BARRIER();
     if (!fy.two) {
         ycol_one<true, BIG>(a, fx, fy, Ly, lds);
     } else {
@@ -2101,9 +2166,11 @@ __device__ bool fft_spectrum(const KArgs &a, const Sync &y, uint32_t &epoch, int
 // components, own tile included, into the feedback buffer.  The apply step
 // then recomputes the residual from the round's starting residual:
 // mathematically the paper's update (own components subtracted locally, the
-// others' by feedback), rounded once.
+// others' by feedback), rounded once.  A one-level x axis writes and reads
+// the y phase's column-major layout directly (fenced barriers around it); two
+// levels go through fft_a and two transposes.
 template <typename PT, bool BIG = false>
-__device__ __forceinline__ bool fft_feedback(const KArgs &a, const Sync &y, uint32_t &epoch, int *s_ok, const int32_t *s_off)
+__device__ __forceinline__ bool fft_feedback(const KArgs &a, const Sync &y, XcdBar *xb, int *s_ok, const int32_t *s_off)
 {
     extern __shared__ __align__(16) unsigned char s_dyn[];
     __shared__ int s_nz;
@@ -2114,14 +2181,15 @@ __device__ __forceinline__ bool fft_feedback(const KArgs &a, const Sync &y, uint
     const float scale = 1.0f / ((float)fx.L * (float)fy.L);
     if (!fx.two) {
         xfwd_one<PT, false, BIG>(a, fx, fy.L, ny, s_off, lds, &s_nz);
+        FFT_BARRIER_FENCED();
     } else {
         xfwd_two_a<PT, false>(a, fx, fy.L, ny, lds);
         FFT_BARRIER();
         xfwd_two_b<false>(a, fx, ny, lds, s_off);
+        FFT_BARRIER();
+        transpose_tiles<BIG ? TR_GROUP_WIDE : 1>(a.fft_a, fx.H, a.fft_b, ny, ny, fx.H, blockIdx.x, gridDim.x, s_tr);
+        FFT_BARRIER();
     }
-    FFT_BARRIER();
-    transpose_tiles<BIG ? TR_GROUP_WIDE : 1>(a.fft_a, fx.H, a.fft_b, ny, ny, fx.H, blockIdx.x, gridDim.x, s_tr);
-    FFT_BARRIER();
     if (!fy.two) {
         ycol_one<false, BIG>(a, fx, fy, ny, lds);
     } else {
@@ -2131,12 +2199,13 @@ __device__ __forceinline__ bool fft_feedback(const KArgs &a, const Sync &y, uint
         FFT_BARRIER();
         ycol_two_c(a, fx, fy, ny, lds);
     }
-    FFT_BARRIER();
-    transpose_tiles<BIG ? TR_GROUP_WIDE : 1>(a.fft_b, ny, a.fft_a, fx.H, fx.H, ny, blockIdx.x, gridDim.x, s_tr);
-    FFT_BARRIER();
     if (!fx.two) {
+        FFT_BARRIER_FENCED();
         xinv_one<BIG>(a, fx, scale, lds);
     } else {
+        FFT_BARRIER();
+        transpose_tiles<BIG ? TR_GROUP_WIDE : 1>(a.fft_b, ny, a.fft_a, fx.H, fx.H, ny, blockIdx.x, gridDim.x, s_tr);
+        FFT_BARRIER();
         xinv_two_a(a, fx, lds);
         FFT_BARRIER();
         xinv_two_b(a, fx, scale, lds);
@@ -2151,18 +2220,17 @@ __device__ __forceinline__ bool fft_feedback(const KArgs &a, const Sync &y, uint
 // transform passes).  Arguments are copied to scalar registers first: the
 // argument block's address and the wait settings are the same in every lane.
 template <typename PT>
-__device__ __noinline__ bool fft_feedback_wide(const KArgs *a_arg, const Sync y_arg, uint32_t epoch_in,
-                                               uint32_t *epoch_out, int *s_ok, const int32_t *s_off)
+__device__ __noinline__ bool fft_feedback_wide(const KArgs *a_arg, const Sync y_arg, XcdBar *xb_arg, int *s_ok,
+                                               const int32_t *s_off)
 {
     const KArgs *ap = wave_uniform(a_arg);
     const Sync y = wave_uniform(y_arg);
-    uint32_t epoch = wave_uniform(epoch_in);
-    const bool ok = fft_feedback<PT, true>(*ap, y, epoch, s_ok, s_off);
-    *epoch_out = epoch;
-    return ok;
+    XcdBar *xb = wave_uniform(xb_arg);
+    return fft_feedback<PT, true>(*ap, y, xb, s_ok, s_off);
 }
 
 #undef FFT_BARRIER
+#undef FFT_BARRIER_FENCED
 
 // ------------------------------------------------------ tiled kernel -----
 
@@ -2336,7 +2404,7 @@ __device__ __forceinline__ void tiled_body(const KArgs &a, int member_arg, int m
         s_xb.nx = n;
     }
     if constexpr (FFT) {
-        if (!fft_spectrum<PT, Tile::kWide>(a, y, epoch, &s_ok)) return;
+        if (!fft_spectrum<PT, Tile::kWide>(&a, y, &s_xb, &s_ok)) return;
     }
 
     const int64_t limit = a.max_iter < a.cap ? a.max_iter : a.cap;
@@ -2458,11 +2526,9 @@ __device__ __forceinline__ void tiled_body(const KArgs &a, int member_arg, int m
         // components (apply then starts from the round's starting residual)
         if constexpr (FFT) {
             if constexpr (Tile::kWide) {
-                __shared__ uint32_t s_epoch;
-                if (!fft_feedback_wide<PT>(&a, y, epoch, &s_epoch, &s_ok, s_off)) return;
-                epoch = s_epoch;
+                if (!fft_feedback_wide<PT>(&a, y, &s_xb, &s_ok, s_off)) return;
             } else {
-                if (!fft_feedback<PT, false>(a, y, epoch, &s_ok, s_off)) return;
+                if (!fft_feedback<PT, false>(a, y, &s_xb, &s_ok, s_off)) return;
             }
         } else
         // ---- feedback gather: acc[q] = sum over other tiles' components
