@@ -217,7 +217,7 @@ int scratch_address(int dev, void **out)
 struct Layout {
     size_t ctl, dstat, xslots, lslots, hslots, tile_key, rb_n, ag_n, header_end;
     size_t role, rb_idx, rb_flux, ag_pos, ag_flux, accbuf, partial;
-    size_t fft_a, fft_b, fft_wx, fft_wy, fft_ks, comp_img, tw_x, tw_y, rstart, total;
+    size_t fft_b, fft_wx, fft_wy, fft_ks, comp_img, tw_x, tw_y, rstart, total;
 };
 
 int ceil_log2(int64_t v)
@@ -266,7 +266,6 @@ Layout make_layout(int T, int cs, int slot_pad, int interval, int W, int64_t npi
     const bool fft = g.lgx > 0;
     const size_t Lx = fft ? (size_t)1 << g.lgx : 0, Ly = fft ? (size_t)1 << g.lgy : 0;
     const size_t Hx = fft ? Lx / 2 + 1 : 0, rows = std::max<size_t>(ny, Ly);
-    L.fft_a = o;     o = align_up(o + rows * Hx * 8, 256);
     L.fft_b = o;     o = align_up(o + Hx * rows * 8, 256);
     L.fft_wx = o;    o = align_up(o + (g.two_x ? (rows + 1) / 2 * Lx * 8 : 0), 256);
     L.fft_wy = o;    o = align_up(o + (g.two_y ? Hx * Ly * 8 : 0), 256);
@@ -677,8 +676,7 @@ int run(bool tiled, const float *dirty, int ny, int nx, const void *psf, int psf
             KFn fw = pick_wide(half, fft);
             size_t wide_lds = dyn_lds;
             if (fft) {
-                // its transposes' tile group, its padded one-level arenas
-                wide_lds = std::max(wide_lds, (size_t)TR_LDS_WIDE);
+                // its padded one-level arenas
                 if (!fg.two_x) wide_lds = std::max(wide_lds, (size_t)8 * fft_pad_slots(1 << fg.lgx));
                 if (!fg.two_y) wide_lds = std::max(wide_lds, (size_t)8 * fft_pad_slots(1 << fg.lgy));
             }
@@ -787,7 +785,6 @@ int run(bool tiled, const float *dirty, int ny, int nx, const void *psf, int psf
     a.fft_lgy = fg.lgy;
     a.fft_two_x = fg.two_x;
     a.fft_two_y = fg.two_y;
-    a.fft_a = (float2 *)(ws + L.fft_a);
     a.fft_b = (float2 *)(ws + L.fft_b);
     a.fft_wx = (float2 *)(ws + L.fft_wx);
     a.fft_wy = (float2 *)(ws + L.fft_wy);

@@ -18,14 +18,12 @@ constexpr int MAX_WG_PER_CU = 2;        // co-resident 512-thread workgroups the
 constexpr int FFT_MAX_LG = 13;          // one-level FFT transforms: length <= 8192 (64 KB of LDS)
 constexpr int FFT_MAX_LG2 = 16;         // two-level FFT transforms: length <= 65536
 constexpr int FFT_LDS_CPLX = 8960;       // LDS complex slots of the two-level passes (>= fft_pad_slots(8192))
+                                         // (with the tiled kernel's static LDS, two workgroups fit one CU's 160 KB)
 // LDS slots of a padded transform arena for a length-L axis (one spare slot
 // after every 16 elements and one more after every 256), and the distance
 // between the padded segments of a pass (odd).
 __host__ __device__ constexpr int fft_pad_slots(int L) { return L + L / 16 + L / 256; }
 __host__ __device__ constexpr int fft_seg_stride(int L) { return fft_pad_slots(L) | 1; }
-constexpr int TR_GROUP_WIDE = 4;         // transpose tiles in flight per workgroup in the wide-tile kernel
-constexpr int TR_LDS_WIDE = TR_GROUP_WIDE * 32 * 33 * 8;
-// (with the tiled kernel's static LDS, two workgroups fit one CU's 160 KB)
 
 enum { STOP_MAXITER = 0, STOP_THRESHOLD = 1, STOP_CAPACITY = 2, STOP_CANCELLED = 3, STOP_NONFINITE = 4 };
 constexpr int64_t CANCEL_EVERY = 4096;  // plain: iterations between cancel checkpoints
@@ -161,8 +159,7 @@ struct KArgs {
     // FFT form of the feedback (fft_lgx = 0: direct gather)
     int fft_lgx, fft_lgy;   // log2 of the transform sizes Lx, Ly (0: direct gather)
     int fft_two_x, fft_two_y;  // axis uses two-level transforms
-    float2 *fft_a;          // [max(ny, Ly)][Lx/2+1] carried x bins per row
-    float2 *fft_b;          // [Lx/2+1][max(ny, Ly)] the same, by column
+    float2 *fft_b;          // [Lx/2+1][max(ny, Ly)] carried x bins of every row, by column
     float2 *fft_wx;         // [max(ny, Ly)/2][Lx] two-level x work rows (row pairs)
     float2 *fft_wy;         // [Lx/2+1][Ly] two-level y work columns
     float2 *fft_ks;         // [Lx/2+1][Ly] spectrum of the PSF kernel by carried column

@@ -522,73 +522,4 @@ __device__ inline void bitrev_permute(float2 *a, int lg)
     __syncthreads();
 }
 
-// 32 x 32 tiled transpose of the rows [0, rows) x columns [0, cols) of `src`
-// (row stride ss) into dst (row stride ds): dst[c][r] = src[r][c].  Tiles are
-// dealt over the workgroups (work item w of nwork).
-//
-// G > 1: the workgroup takes G tiles at a time (lds holds G tiles) and a
-// thread issues its loads of all of them before the first LDS write, so one
-// memory round trip serves G tiles.  Needs the registers of 2G values.
-template <int G = 1>
-__device__ inline void transpose_tiles(const float2 *src, int ss, float2 *dst, int ds, int rows, int cols, int w0,
-                                       int nwork, float2 (*lds)[33])
-{
-    if constexpr (G > 1) {
-        constexpr int PER = 1024 / WG;   // elements of one tile per thread
-        const int tr = (rows + 31) / 32, tc = (cols + 31) / 32, nt = tr * tc;
-        #pragma clang loop unroll(disable)
-        for (int t0 = w0; t0 < nt; t0 += G * nwork) {
-            float2 v[G][PER] = {};
-#pragma unroll
-            for (int g = 0; g < G; ++g) {
-                const int t = t0 + g * nwork;
-                const int br = (t / tc) * 32, bc = (t % tc) * 32;
-#pragma unroll
-                for (int k = 0; k < PER; ++k) {
-                    const int e = (int)threadIdx.x + k * WG, r = e / 32, c = e % 32;
-                    if (t < nt && br + r < rows && bc + c < cols) v[g][k] = ldc2(&src[(size_t)(br + r) * ss + bc + c]);
-                }
-            }
-            __syncthreads();
-#pragma unroll
-            for (int g = 0; g < G; ++g)
-#pragma unroll
-                for (int k = 0; k < PER; ++k) {
-                    const int e = (int)threadIdx.x + k * WG;
-                    lds[g * 32 + e / 32][e % 32] = v[g][k];
-                }
-            __syncthreads();
-#pragma unroll
-            for (int g = 0; g < G; ++g) {
-                const int t = t0 + g * nwork;
-                const int br = (t / tc) * 32, bc = (t % tc) * 32;
-#pragma unroll
-                for (int k = 0; k < PER; ++k) {
-                    const int e = (int)threadIdx.x + k * WG, c = e / 32, r = e % 32;
-                    if (t < nt && br + r < rows && bc + c < cols)
-                        stc2(&dst[(size_t)(bc + c) * ds + br + r], lds[g * 32 + r][c]);
-                }
-            }
-        }
-        return;
-    }
-    const int tr = (rows + 31) / 32, tc = (cols + 31) / 32;
-    #pragma clang loop unroll(disable)
-    for (int t = w0; t < tr * tc; t += nwork) {
-        const int br = (t / tc) * 32, bc = (t % tc) * 32;
-        __syncthreads();
-        #pragma clang loop unroll(disable)
-        for (int e = threadIdx.x; e < 1024; e += blockDim.x) {
-            const int r = e / 32, c = e % 32;
-            if (br + r < rows && bc + c < cols) lds[r][c] = ldc2(&src[(size_t)(br + r) * ss + bc + c]);
-        }
-        __syncthreads();
-        #pragma clang loop unroll(disable)
-        for (int e = threadIdx.x; e < 1024; e += blockDim.x) {
-            const int c = e / 32, r = e % 32;
-            if (br + r < rows && bc + c < cols) stc2(&dst[(size_t)(bc + c) * ds + br + r], lds[r][c]);
-        }
-    }
-}
-
 } // namespace cleanhip

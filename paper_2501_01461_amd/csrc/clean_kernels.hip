@@ -1485,17 +1485,11 @@ __device__ __forceinline__ int tile_row_of(const KArgs &a, int y)
 }
 
 // Split of a row pair's transform Z (row r0 real part, r0+1 imaginary part)
-// at bin k: A = (Z[k] + conj Z[L-k]) / 2 and B = (Z[k] - conj Z[L-k]) / 2i.
-__device__ __forceinline__ void store_split(float2 *o0, float2 *o1, bool has1, int c, float2 zk, float2 zm)
-{
-    stc2(&o0[c], make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y)));
-    if (has1) stc2(&o1[c], make_float2(0.5f * (zk.y + zm.y), -0.5f * (zk.x - zm.x)));
-}
-
-// The same split, stored column-major for the y phase: bin k of rows r0 and
-// r0 + 1 at o[k * rows] and o[k * rows + 1] (o = buffer + r0), plain stores
-// (a fenced barrier follows); one 16-byte store when `rows` is even (row
-// r0 + 1 then always exists and the pair is 16-byte aligned).
+// at bin k: A = (Z[k] + conj Z[L-k]) / 2 and B = (Z[k] - conj Z[L-k]) / 2i,
+// stored column-major for the y phase: bin k of rows r0 and r0 + 1 at
+// o[k * rows] and o[k * rows + 1] (o = buffer + r0), plain stores (a fenced
+// barrier follows); one 16-byte store when `rows` is even (row r0 + 1 then
+// always exists and the pair is 16-byte aligned).
 __device__ __forceinline__ void store_cols(float2 *o, int rows, bool has1, int k, float2 zk, float2 zm)
 {
     const float2 v0 = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y));
@@ -1509,7 +1503,7 @@ __device__ __forceinline__ void store_cols(float2 *o, int rows, bool has1, int k
     }
 }
 
-// The one-level x phases' row-pair order: the workgroups of one XCD
+// The x phases' row-pair order: the workgroups of one XCD
 // (workgroup b runs on XCD b % 8) take consecutive row pairs, so that the
 // 16-byte pieces of one column-major line are written, and read, through a
 // single L2.  Any order is correct; this is the one-to-one map of
@@ -1656,8 +1650,9 @@ __device__ __forceinline__ void xfwd_two_a(const KArgs &a, const FftAxis &fx, in
 
 // x forward, two levels, step 2: per row pair, rows k1 and L1 - k1 of the
 // step-1 output transformed over n2 (length L2), then split into the two
-// image rows' carried bins (chat order) in fft_a.  Unless KSRC, also clears
-// the dense component image at this round's positions.
+// image rows' carried bins (chat order), column-major into fft_b like
+// xfwd_one.  Unless KSRC, also clears the dense component image at this
+// round's positions.
 template <bool KSRC>
 __device__ __forceinline__ void xfwd_two_b(const KArgs &a, const FftAxis &fx, int rows, float2 *lds, const int32_t *s_off)
 {
@@ -1666,9 +1661,12 @@ __device__ __forceinline__ void xfwd_two_b(const KArgs &a, const FftAxis &fx, in
     const int G = max(1, min(nslot, FFT_LDS_CPLX / (2 * stride)));
     const int nblk = (nslot + G - 1) / G;
     const int hq = fx.L2 / 2;
+    const int npr = (rows + 1) / 2;
+    // items (slot block, row pair) with the row pair fastest: the workgroups
+    // of one XCD take consecutive row pairs of one block (xcd_slot)
     #pragma clang loop unroll(disable)
-    for (int item = blockIdx.x; item < (rows + 1) / 2 * nblk; item += gridDim.x) {
-        const int pr = item / nblk, s0 = (item % nblk) * G, ns = min(G, nslot - s0);
+    for (int item = xcd_slot(); item < npr * nblk; item += gridDim.x) {
+        const int pr = item % npr, s0 = (item / npr) * G, ns = min(G, nslot - s0);
         const int r0 = 2 * pr;
         const bool has1 = r0 + 1 < rows;
         const float2 *w = a.fft_wx + (size_t)pr * fx.L;
@@ -1682,7 +1680,7 @@ __device__ __forceinline__ void xfwd_two_b(const KArgs &a, const FftAxis &fx, in
                   },
                   [&](int e, float2 v) { lds[(e >> fx.lg2) * stride + pad16(bitrev((uint32_t)(e & (fx.L2 - 1)), fx.lg2))] = v; });
         fft_lds_multi(lds, fx.lg2, 2 * ns, stride, fx.tw, fx.L1, false);
-        float2 *o0 = a.fft_a + (size_t)r0 * fx.H, *o1 = o0 + fx.H;
+        float2 *o = a.fft_b + r0;
         #pragma clang loop unroll(disable)
         for (int e = threadIdx.x; e < 2 * ns * hq; e += WG) {
             const int seg = e >> (fx.lg2 - 1), k2 = e & (hq - 1);
@@ -1693,10 +1691,10 @@ __device__ __forceinline__ void xfwd_two_b(const KArgs &a, const FftAxis &fx, in
             int q1, q2;
             mirror_of(fx, kr, k2, q1, q2);
             const int qs = q1 == kr ? seg : (seg ^ 1);
-            store_split(o0, o1, has1, chat_of(fx, kr, k2), lds[seg * stride + pad16(k2)], lds[qs * stride + pad16(q2)]);
+            store_cols(o, rows, has1, chat_of(fx, kr, k2), lds[seg * stride + pad16(k2)], lds[qs * stride + pad16(q2)]);
         }
         if (s0 == 0 && threadIdx.x == 0)        // bin k = L/2: row 0, k2 = L2/2, its own mirror
-            store_split(o0, o1, has1, fx.L / 2, lds[pad16(hq)], lds[pad16(hq)]);
+            store_cols(o, rows, has1, fx.L / 2, lds[pad16(hq)], lds[pad16(hq)]);
     }
     if (!KSRC) {
         const int total = s_off[a.T];
@@ -2056,20 +2054,26 @@ __device__ __forceinline__ void xinv_two_a(const KArgs &a, const FftAxis &fx, fl
     const int ny = a.ny, stride = fft_seg_stride(fx.L2), hq = fx.L2 / 2;
     const int G = max(1, min(fx.L1, FFT_LDS_CPLX / stride));
     const int nblk = (fx.L1 + G - 1) / G;
+    const int npr = (ny + 1) / 2;
+    // items (row block, row pair) with the row pair fastest, as in xfwd_two_b
     #pragma clang loop unroll(disable)
-    for (int item = blockIdx.x; item < (ny + 1) / 2 * nblk; item += gridDim.x) {
-        const int pr = item / nblk, k0 = (item % nblk) * G, ng = min(G, fx.L1 - k0);
+    for (int item = xcd_slot(); item < npr * nblk; item += gridDim.x) {
+        const int pr = item % npr, k0 = (item / npr) * G, ng = min(G, fx.L1 - k0);
         const int r0 = 2 * pr;
         const bool has1 = r0 + 1 < ny;
-        const float2 *i0 = a.fft_a + (size_t)r0 * fx.H, *i1 = i0 + fx.H;
+        const float2 *c0 = a.fft_b + r0;       // bin c of the pair at c0[c * ny], c0[c * ny + 1]
         staged<STAGE_TWO>(ng * fx.L2, true,
                   [&](int e) {
                       const int k2 = e & (fx.L2 - 1), k1 = k0 + (e >> fx.lg2);
                       const bool carried = k2 < hq || (k2 == hq && k1 == 0);
                       int q1 = k1, q2 = k2;
                       if (!carried) mirror_of(fx, k1, k2, q1, q2);
-                      const int c = chat_of(fx, q1, q2);
-                      const float2 A = ldc2(&i0[c]), B = ldc2(has1 ? &i1[c] : &i0[c]);   // B unused without row r0 + 1
+                      const float2 *p = c0 + (size_t)chat_of(fx, q1, q2) * ny;
+                      if ((ny & 1) == 0) {
+                          const f32x4 q = ldp4(p);
+                          return make_float4(q.x, q.y, q.z, q.w);
+                      }
+                      const float2 A = ldp2(p), B = ldp2(has1 ? p + 1 : p);   // B unused without row r0 + 1
                       return make_float4(A.x, A.y, B.x, B.y);
                   },
                   [&](int e, float4 q) {
@@ -2124,8 +2128,7 @@ __device__ __forceinline__ void xinv_two_b(const KArgs &a, const FftAxis &fx, fl
 #define FFT_BARRIER_FENCED() do { if (!xcd_grid_barrier<true>(y, xb, s_ok)) return false; } while (0)
 
 // The PSF kernel's spectrum, once per call, by the same transforms as the
-// rounds: x forward over all Ly rows of the kernel image (two levels: then
-// transposed), y forward.  A function of its own (called once per launch),
+// rounds: x forward over all Ly rows of the kernel image, y forward.  A function of its own (called once per launch),
 // its arguments by value or by address, so that none of them needs a stack
 // copy.
 template <typename PT, bool BIG = false>
@@ -2137,20 +2140,16 @@ __device__ __noinline__ bool fft_spectrum(const KArgs *a_arg, const Sync y_arg, 
     extern __shared__ __align__(16) unsigned char s_dyn[];
     __shared__ int s_nz;
     float2 *lds = (float2 *)s_dyn;
-    float2 (*s_tr)[33] = reinterpret_cast<float2 (*)[33]>(s_dyn);   // transposes reuse the arena
     const FftAxis fx = fft_axis(a.fft_lgx, a.fft_two_x, a.tw_x), fy = fft_axis(a.fft_lgy, a.fft_two_y, a.tw_y);
     const int Ly = fy.L;
     if (!fx.two) {
         xfwd_one<PT, true, BIG>(a, fx, Ly, Ly, nullptr, lds, &s_nz);
-        FFT_BARRIER_FENCED();
     } else {
         xfwd_two_a<PT, true>(a, fx, Ly, Ly, lds);
         FFT_BARRIER();
         xfwd_two_b<true>(a, fx, Ly, lds, nullptr);
-        FFT_BARRIER();
-        transpose_tiles<BIG ? TR_GROUP_WIDE : 1>(a.fft_a, fx.H, a.fft_b, Ly, Ly, fx.H, blockIdx.x, gridDim.x, s_tr);
-        FFT_BARRIER();
     }
+    FFT_BARRIER_FENCED();
     if (!fy.two) {
         ycol_one<true, BIG>(a, fx, fy, Ly, lds);
     } else {
@@ -2166,30 +2165,25 @@ __device__ __noinline__ bool fft_spectrum(const KArgs *a_arg, const Sync y_arg, 
 // components, own tile included, into the feedback buffer.  The apply step
 // then recomputes the residual from the round's starting residual:
 // mathematically the paper's update (own components subtracted locally, the
-// others' by feedback), rounded once.  A one-level x axis writes and reads
-// the y phase's column-major layout directly (fenced barriers around it); two
-// levels go through fft_a and two transposes.
+// others' by feedback), rounded once.  The x phases write and read the y
+// phase's column-major layout directly; fenced barriers separate them from it.
 template <typename PT, bool BIG = false>
 __device__ __forceinline__ bool fft_feedback(const KArgs &a, const Sync &y, XcdBar *xb, int *s_ok, const int32_t *s_off)
 {
     extern __shared__ __align__(16) unsigned char s_dyn[];
     __shared__ int s_nz;
     float2 *lds = (float2 *)s_dyn;
-    float2 (*s_tr)[33] = reinterpret_cast<float2 (*)[33]>(s_dyn);   // transposes reuse the arena
     const FftAxis fx = fft_axis(a.fft_lgx, a.fft_two_x, a.tw_x), fy = fft_axis(a.fft_lgy, a.fft_two_y, a.tw_y);
     const int ny = a.ny;
     const float scale = 1.0f / ((float)fx.L * (float)fy.L);
     if (!fx.two) {
         xfwd_one<PT, false, BIG>(a, fx, fy.L, ny, s_off, lds, &s_nz);
-        FFT_BARRIER_FENCED();
     } else {
         xfwd_two_a<PT, false>(a, fx, fy.L, ny, lds);
         FFT_BARRIER();
         xfwd_two_b<false>(a, fx, ny, lds, s_off);
-        FFT_BARRIER();
-        transpose_tiles<BIG ? TR_GROUP_WIDE : 1>(a.fft_a, fx.H, a.fft_b, ny, ny, fx.H, blockIdx.x, gridDim.x, s_tr);
-        FFT_BARRIER();
     }
+    FFT_BARRIER_FENCED();
     if (!fy.two) {
         ycol_one<false, BIG>(a, fx, fy, ny, lds);
     } else {
@@ -2199,13 +2193,10 @@ __device__ __forceinline__ bool fft_feedback(const KArgs &a, const Sync &y, XcdB
         FFT_BARRIER();
         ycol_two_c(a, fx, fy, ny, lds);
     }
+    FFT_BARRIER_FENCED();
     if (!fx.two) {
-        FFT_BARRIER_FENCED();
         xinv_one<BIG>(a, fx, scale, lds);
     } else {
-        FFT_BARRIER();
-        transpose_tiles<BIG ? TR_GROUP_WIDE : 1>(a.fft_b, ny, a.fft_a, fx.H, fx.H, ny, blockIdx.x, gridDim.x, s_tr);
-        FFT_BARRIER();
         xinv_two_a(a, fx, lds);
         FFT_BARRIER();
         xinv_two_b(a, fx, scale, lds);

@@ -133,11 +133,12 @@ def test_workspace_size(lib):
     assert a > 4 * 1024 * 1024 > 0 and b > 0
     assert lib.clean_workspace_size(1024, 1024, 0, 2, 100, C.byref(p)) == 0
     assert lib.clean_workspace_size(1024, 1024, 2, 2, 0, C.byref(p)) == 0
-    # FFT feedback: carried-bin buffers (2048 rows x 1025 bins, twice), the PSF
-    # spectrum (1025 x 2048), the round-start residual; two levels add work buffers
+    # FFT feedback: the column-major carried-bin buffer (1025 bins x 2048 rows),
+    # the PSF spectrum (1025 x 2048), the round-start residual; two levels add
+    # work buffers
     f = params(flags=N.FLAG_FFT_FEEDBACK)
     fa = lib.clean_workspace_size(1024, 1024, 2, 2, 100, C.byref(f))
-    assert fa >= a + 3 * 2048 * 1025 * 8 + 1024 * 1024 * 4
+    assert fa >= a + 2 * 2048 * 1025 * 8 + 1024 * 1024 * 4
     f2 = params(flags=N.FLAG_FFT_FEEDBACK | N.FLAG_FFT_TWO_LEVEL)
     assert lib.clean_workspace_size(1024, 1024, 2, 2, 100, C.byref(f2)) >= fa + 2 * 1025 * 2048 * 8
     assert lib.clean_workspace_size(40000, 16, 2, 2, 100, C.byref(f)) == 0
