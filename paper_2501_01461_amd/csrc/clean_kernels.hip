@@ -182,6 +182,15 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc_uniform(const void *
     return __builtin_amdgcn_make_buffer_rsrc((void *)(uintptr_t)u, (short)0, (int)n, 0x00020000);
 }
 
+// min(max(x, 0), 2^32 - 1) for a 64-bit x, with 32-bit compares only: the
+// scalar unit has no 64-bit ordered compare, so a 64-bit one would move the
+// whole computation to the vector unit.
+__device__ __forceinline__ uint32_t clamp_u32(int64_t x)
+{
+    const int32_t hi = (int32_t)((uint64_t)x >> 32);
+    return hi < 0 ? 0u : hi > 0 ? 0xFFFFFFFFu : (uint32_t)x;
+}
+
 // A value that is equal in all lanes of the wave, moved to scalar registers
 // (each 32-bit word from the first active lane), for code where the compiler
 // cannot prove it uniform: function arguments and loads through them.
@@ -934,7 +943,11 @@ struct WideRound {
 // 128 residual registers do not add to the rest of the kernel's.  The
 // residual comes from the round's residual array and, for the direct gather,
 // goes back to it at the end (the FFT form rebuilds it from the round's start).
-template <typename PT>
+// FULL: the tile fills every group of every thread (its pixels are exactly
+// cs * WG * 4 * 32), so no group needs a test of whether it lies inside the
+// tile.  Such tests are loop-invariant per group, and the compiler hoists
+// them out of the minor loop into 32 mask registers that no longer fit.
+template <typename PT, bool FULL>
 __device__ __noinline__ WideRound wide_round(const KArgs &a, const Img im, const WideTile<PT> R, const Sync y,
                                              uint64_t *slots, uint64_t *lslots, uint32_t e, uint64_t cur,
                                              int64_t budget, double level, bool leader, int32_t *l_idx,
@@ -947,7 +960,7 @@ __device__ __noinline__ WideRound wide_round(const KArgs &a, const Img im, const
     for (int k = 0; k < K; ++k) {
         const int64_t img = R.img_of(im, k);
 #pragma unroll
-        for (int e2 = 0; e2 < V; ++e2) r[k][e2] = k < R.nvalid ? src[img + e2] : 0.0f;
+        for (int e2 = 0; e2 < V; ++e2) r[k][e2] = (FULL || k < R.nvalid) ? src[img + e2] : 0.0f;
     }
     // the round's scalars (equal in every lane) in scalar registers: this
     // function's arguments and what is read through them are vector values
@@ -961,32 +974,53 @@ __device__ __noinline__ WideRound wide_round(const KArgs &a, const Img im, const
     double *model = wave_uniform(a.model);
     const int64_t nb = wave_uniform(budget);
     const uint32_t voff = (uint32_t)R.qoff * (uint32_t)sizeof(PT);
-    const uint32_t step = (R.stride() / (uint32_t)tw) * (uint32_t)apnx * (uint32_t)sizeof(PT);
+    const uint32_t step = wave_uniform((R.stride() / (uint32_t)tw) * (uint32_t)apnx * (uint32_t)sizeof(PT));
     WideRound out{wave_uniform(cur), e, 0, 1};
     for (int64_t it = 0; it < nb; ++it) {
         const float v = key_value(out.cur);
         if (!__builtin_isfinite(v) || (double)fabsf(v) < thr || (double)fabsf(v) < lvl) break;
         const float c = gain * v;
         const uint32_t fp = key_f(out.cur);
-        const int ly = (int)(fp / (uint32_t)tw), lx = (int)(fp % (uint32_t)tw);
+        // the division runs on the vector unit; its result goes back to
+        // scalar registers, so that the 32 descriptors below are scalar work
+        const int ly = wave_uniform((int)(fp / (uint32_t)tw)), lx = wave_uniform((int)(fp % (uint32_t)tw));
         const int py = ty0 + ly, px = tx0 + lx;
         const int32_t img = py * anx + px;
         if (leader && threadIdx.x == 0) { l_idx[out.L] = img; l_flux[out.L] = c; }
         if (model && R.owns(fp)) model[img] += (double)c;
-        // r -= c * PSF window (eq. 2)
-        const int64_t w0 = (int64_t)(acy - py) * apnx + (acx - px);
-        const char *base = (const char *)psf + w0 * (int64_t)sizeof(PT);
-        const __amdgpu_buffer_rsrc_t rs = make_rsrc_uniform(base, psf_bytes - (uint64_t)w0 * sizeof(PT));
+        // r -= c * PSF window (eq. 2).  The loads go out WB at a time, on
+        // one descriptor per batch (base: the batch's first group's window,
+        // in scalar registers) with group k0 + j at scalar offset j * step and
+        // the thread's own offset in the vector offset.  Groups outside the
+        // tile take a vector offset past any range, so their loads read 0 and
+        // touch no memory; they are multiplied by 0.  (With the 32 group
+        // offsets held in vector registers instead, the compiler had waited
+        // for each load before issuing the next.)
+        const uint64_t wb = (uint64_t)((int64_t)(acy - py) * apnx + (acx - px)) * sizeof(PT);
+        constexpr int WB = 16;
+        constexpr uint32_t kOutside = 0xFFFFFFF0u;
+        // the group offsets j * step are made here, in each iteration, from
+        // a step the compiler cannot see through: hoisted out of the loop,
+        // 15 of them would hold scalar registers the loop runs short of
+        uint32_t st = step;
+        asm volatile("" : "+s"(st));
 #pragma unroll
-        for (int k = 0; k < K; ++k) {
-            // the whole offset in the (range-checked) vector offset; groups
-            // outside the tile read group 0's window and are multiplied by 0
-            const uint32_t off = k < R.nvalid ? voff + (uint32_t)k * step : voff;
-            float pv[V];
-            PsfLoad<PT, V>::load(rs, off, pv);
-            const float ck = k < R.nvalid ? c : 0.0f;      // groups outside the tile stay +0
+        for (int k0 = 0; k0 < K; k0 += WB) {
+            const uint64_t kb = wb + (uint64_t)k0 * st;
+            // the range stops short of kOutside, whatever the PSF's size
+            const uint32_t nrec = min(clamp_u32((int64_t)(psf_bytes - kb)), kOutside - 1u);
+            const __amdgpu_buffer_rsrc_t rs =
+                __builtin_amdgcn_make_buffer_rsrc((void *)((const char *)psf + kb), (short)0, (int)nrec, 0x00020000);
+            float pv[WB][V];
 #pragma unroll
-            for (int e2 = 0; e2 < V; ++e2) r[k][e2] = __builtin_fmaf(-ck, pv[e2], r[k][e2]);
+            for (int j = 0; j < WB; ++j)
+                PsfLoad<PT, V>::load_s(rs, (FULL || k0 + j < R.nvalid) ? voff : kOutside, (uint32_t)j * st, pv[j]);
+#pragma unroll
+            for (int j = 0; j < WB; ++j) {
+                const float ck = (FULL || k0 + j < R.nvalid) ? c : 0.0f;      // groups outside the tile stay +0
+#pragma unroll
+                for (int e2 = 0; e2 < V; ++e2) r[k0 + j][e2] = __builtin_fmaf(-ck, pv[j][e2], r[k0 + j][e2]);
+            }
         }
         out.L += 1;
         if (it + 1 < nb) {
@@ -1027,7 +1061,7 @@ __device__ __noinline__ WideRound wide_round(const KArgs &a, const Img im, const
                 bool vnan = false;
 #pragma unroll
                 for (int k = 0; k < K; ++k)
-                    vnan = vnan || (k < R.nvalid && is_nan(nan_max(nan_max(r[k][0], r[k][1]), nan_max(r[k][2], r[k][3]))));
+                    vnan = vnan || ((FULL || k < R.nvalid) && is_nan(nan_max(nan_max(r[k][0], r[k][1]), nan_max(r[k][2], r[k][3]))));
                 if (vnan) {
                     tk = make_key(0x7FC00000u, R.group_f(0));
                 } else {
@@ -1064,7 +1098,7 @@ __device__ __noinline__ WideRound wide_round(const KArgs &a, const Img im, const
     if (!R.fft) {
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-            if (k < R.nvalid) {
+            if (FULL || k < R.nvalid) {
                 const int64_t img = R.img_of(im, k);
 #pragma unroll
                 for (int e2 = 0; e2 < V; ++e2) im.residual[img + e2] = r[k][e2];
@@ -2445,8 +2479,12 @@ __device__ __forceinline__ void tiled_body(const KArgs &a, int member_arg, int m
         if (is_cluster) {
             int L = 0;
             if constexpr (Tile::kWide) {
-                const WideRound wr = wide_round<PT>(a, im, R, y, slots, lslots, e, cur, budget, level,
-                                                    tile_leader_wg, l_idx, l_flux);
+                const WideRound wr =
+                    (int64_t)R.h * R.w == (int64_t)R.stride() * WideTile<PT>::K
+                        ? wide_round<PT, true>(a, im, R, y, slots, lslots, e, cur, budget, level, tile_leader_wg,
+                                               l_idx, l_flux)
+                        : wide_round<PT, false>(a, im, R, y, slots, lslots, e, cur, budget, level, tile_leader_wg,
+                                                l_idx, l_flux);
                 if (!wr.ok) return;
                 cur = wr.cur;
                 e = wr.e;
