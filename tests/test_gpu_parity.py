@@ -211,6 +211,11 @@ WIDE_CASES = [
     (96, 128, (2, 2), 50, 44, 400, 0.05),         # threshold stop
     (300, 512, (1, 2), 30, 45, 800, 0.0),         # 76800-pixel tiles: 2 workgroups per tile
     (40, 64, (1, 1), 9, 46, 100, 0.0),            # one tile
+    # full tiles (exactly 65536 pixels per workgroup): the loop version with
+    # no per-group tests
+    (256, 256, (1, 1), 20, 48, 400, 0.0),
+    (512, 512, (2, 2), 25, 49, 600, 0.0),
+    (1024, 512, (2, 1), 30, 50, 500, 0.0),        # 512 x 512 tiles, 4 workgroups each
 ]
 
 
@@ -229,12 +234,13 @@ def test_tiled_wide_tile_small(lib, case):
     assert_same_run(out, ref)
 
 
-def test_tiled_wide_tile_f16(lib):
+@pytest.mark.parametrize("ny,nx", [(250, 256), (512, 512)], ids=["ragged", "full"])
+def test_tiled_wide_tile_f16(lib, ny, nx):
     """The wide tile with an FP16-stored PSF against the oracle run on that
-    PSF's float32 values."""
+    PSF's float32 values (ragged tiles, and full ones)."""
     import torch
-    announce("tiled wide tile f16")
-    ny, nx, tiles = 250, 256, (2, 2)
+    announce("tiled wide tile f16", (ny, nx))
+    tiles = (2, 2)
     dirty = sparse_dirty(ny, nx, 47, density=0.03)
     psf = asym_psf(2 * ny, 2 * nx + 2, 47, spread=0.2)
     psf_ref = psf.astype(np.float16).astype(np.float32)
