@@ -13,7 +13,7 @@
 //    convolution), four stages per pass in registers, and at length 8192
 //    compile-time LDS offsets and per-thread twiddles held in registers.
 // Cross-workgroup buffers move through agent-coherent 8-byte loads and
-// stores; transposes through 32 x 33 LDS tiles.
+// stores, or plain 8- and 16-byte ones between fenced grid barriers.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>

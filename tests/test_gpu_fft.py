@@ -107,9 +107,9 @@ def test_fft_one_round_small(lib, case, two):
 
 
 # The wide tile (px_per_thread = 128) at small sizes: its kernel takes the
-# radix-16 transform passes, four transpose tiles in flight and the fused
-# column sweeps, at odd and even transform lengths (radix-2 and radix-4
-# leftovers) and with partial transpose tile groups.
+# radix-16 transform passes and the fused column sweeps, at odd and even
+# transform lengths (radix-2 and radix-4 leftovers), with the x phases' row
+# pairs grouped by XCD.
 WIDE_ONE_ROUND = [
     # ny, nx, tiles, interval, seed, f16
     (64, 64, (2, 2), 50, 81, False),           # Lx = Ly = 128: radix-2, one radix-16, one radix-4 pass
