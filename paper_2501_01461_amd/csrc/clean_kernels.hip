@@ -2162,9 +2162,9 @@ __device__ __forceinline__ void xinv_two_b(const KArgs &a, const FftAxis &fx, fl
 #define FFT_BARRIER_FENCED() do { if (!xcd_grid_barrier<true>(y, xb, s_ok)) return false; } while (0)
 
 // The PSF kernel's spectrum, once per call, by the same transforms as the
-// rounds: x forward over all Ly rows of the kernel image, y forward.  A function of its own (called once per launch),
-// its arguments by value or by address, so that none of them needs a stack
-// copy.
+// rounds: x forward over all Ly rows of the kernel image, y forward.  A
+// function of its own (called once per launch), its arguments by value or by
+// address, so that none of them needs a stack copy.
 template <typename PT, bool BIG = false>
 __device__ __noinline__ bool fft_spectrum(const KArgs *a_arg, const Sync y_arg, XcdBar *xb_arg, int *s_ok)
 {
