@@ -590,7 +590,10 @@ int run(bool tiled, const float *dirty, int ny, int nx, const void *psf, int psf
     }
 
     // placement: cluster c lives on XCD c % 8 (workgroup b runs on XCD b % 8);
-    // tiled launches add helper workgroups for the feedback gather
+    // tiled launches add helper workgroups for the feedback gather.  There is
+    // one cluster per tile, except for the time-multiplexed wide tile, whose
+    // nclusters clusters each run several tiles in turn.
+    int nclusters = T;
     auto place = [&](int cs, int max_wg, int &W, std::vector<int32_t> &role) -> bool {
         if (!tiled) {
             W = cs;
@@ -600,21 +603,21 @@ int run(bool tiled, const float *dirty, int ny, int nx, const void *psf, int psf
             return true;
         }
         std::vector<int> need(8, 0);
-        for (int c = 0; c < T; ++c) need[c % 8] += cs;
+        for (int c = 0; c < nclusters; ++c) need[c % 8] += cs;
         W = 8 * *std::max_element(need.begin(), need.end());
         const int helpers_target = std::min(max_wg, 2 * ncu) / 8 * 8;
         if (W < helpers_target) W = helpers_target;
         if (W > max_wg) {
-            W = T * cs;                      // pack without XCD affinity
+            W = nclusters * cs;              // pack without XCD affinity
             if (W > max_wg) return false;
             role.assign(W, -1);
-            for (int c = 0; c < T; ++c)
+            for (int c = 0; c < nclusters; ++c)
                 for (int g = 0; g < cs; ++g) role[c * cs + g] = (c << 16) | g;
             return true;
         }
         role.assign(W, -1);
         std::vector<int> fill(8, 0);
-        for (int c = 0; c < T; ++c) {
+        for (int c = 0; c < nclusters; ++c) {
             const int x = c % 8;
             for (int g = 0; g < cs; ++g) role[x + 8 * fill[x]++] = (c << 16) | g;
         }
@@ -691,6 +694,24 @@ int run(bool tiled, const float *dirty, int ny, int nx, const void *psf, int psf
                 cs = cw;
                 ppt = 128;
                 dyn_lds = wide_lds;
+            } else if (occ > 0 && (want_wide || max_tile >= (int64_t)WG * 128)) {
+                // time-multiplexed: as many clusters as one XCD's share of the
+                // co-resident workgroups holds, eight XCDs' worth, each cluster
+                // running its tiles in turn in every round (tiles of at least
+                // one wide workgroup's pixels, or on request)
+                const int nc = std::min(T, 8 * ((occ * ncu / 8) / cw));
+                if (nc >= 1) {
+                    nclusters = nc;
+                    if (place(cw, occ * ncu, W, role)) {
+                        streamed = false;
+                        fn = fw;
+                        cs = cw;
+                        ppt = 128;
+                        dyn_lds = wide_lds;
+                    } else {
+                        nclusters = T;
+                    }
+                }
             }
         }
     }
@@ -749,6 +770,7 @@ int run(bool tiled, const float *dirty, int ny, int nx, const void *psf, int psf
     a.cy = psf_ny / 2; a.cx = psf_nx / 2;
     a.ty = tiles_y; a.tx = tiles_x; a.T = T;
     a.cs = cs;
+    a.ncl = nclusters;
     a.slot_pad = slot_pad;
     a.interval = interval;
     a.level_frac = tiled ? p->feedback_level : 0.0;
@@ -1190,6 +1212,7 @@ int clean_batched(const clean_problem *probs, int n, const clean_params *shared,
             a.cy = q.psf_ny / 2; a.cx = q.psf_nx / 2;
             a.ty = pty[i]; a.tx = ptx[i]; a.T = T;
             a.cs = cs[i];
+            a.ncl = T;
             a.slot_pad = pad;
             a.interval = pint[i];
             a.level_frac = shared->feedback_level;

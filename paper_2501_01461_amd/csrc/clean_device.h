@@ -125,6 +125,8 @@ struct KArgs {
     int ny, nx, psf_ny, psf_nx, cy, cx;
     int ty, tx, T;
     int cs;                 // workgroups per tile cluster
+    int ncl;                // tile clusters; below T (wide tile only) a cluster runs
+                            // tiles c, c + ncl, ... one after another in each round
     int slot_pad;           // u64 slots per parity block of a cluster
     int interval;           // feedback interval (tiled)
     double level_frac;      // flux trigger: fraction of the largest tile peak (0: off)

@@ -856,8 +856,9 @@ template <typename PT> struct WideTile {
     }
     __device__ __forceinline__ float *cur(const Img &a) const { return fft ? a.rstart : a.residual; }
 
-    // Geometry; the direct gather's residual array starts as the dirty image.
-    __device__ void init(const Img &a, int ty0, int tx0, int th, int tw, int ncs, int rk)
+    // Geometry; the direct gather's residual array starts as the dirty image
+    // (data: also that first copy and the model's zeros, once per tile).
+    __device__ void init(const Img &a, int ty0, int tx0, int th, int tw, int ncs, int rk, bool data = true)
     {
         y0 = ty0; x0 = tx0; h = th; w = tw; cs = ncs; rank = rk;
         fft = a.rstart != nullptr;
@@ -865,6 +866,7 @@ template <typename PT> struct WideTile {
         const int hw = h * w;
         nvalid = f0 < hw ? min(K, (int)(((uint32_t)(hw - f0) + stride() - 1) / stride())) : 0;
         qoff = (y0 + f0 / w) * a.psf_nx + (x0 + f0 % w);
+        if (!data) return;
         for (int k = 0; k < nvalid; ++k) {
             const int64_t img = img_of(a, k);
 #pragma unroll
@@ -2415,6 +2417,19 @@ __device__ __forceinline__ void tiled_body(const KArgs &a, int member_arg, int m
         }
         if (!cluster_reduce(y, slots, lslots, a.slot_pad, cs, rank, e++, R.key(im), cur)) return;
         if (tile_leader_wg && threadIdx.x == 0) stc(&a.tile_key[tile], cur);
+        if constexpr (Tile::kWide && !BATCH) {
+            // time-multiplexed clusters: the cluster's other tiles
+            for (int t = tile + a.ncl; t < T; t += a.ncl) {
+                int ty0, tx0, th, tw;
+                tile_rect(a, t, ty0, tx0, th, tw);
+                R.init(im, ty0, tx0, th, tw, cs, rank);
+                __syncthreads();
+                uint64_t k;
+                if (!cluster_reduce(y, slots, lslots, a.slot_pad, cs, rank, e++, R.key(im), k)) return;
+                if (tile_leader_wg && threadIdx.x == 0) stc(&a.tile_key[t], k);
+            }
+            if (a.ncl < T) R.init(im, ty0, tx0, th, tw, cs, rank, false);     // back to the first tile
+        }
     }
     // the caller's cancel flag, seen by every workgroup after the barrier
     if (a.has_cancel && member == 0 && threadIdx.x == 0)
@@ -2478,17 +2493,59 @@ __device__ __forceinline__ void tiled_body(const KArgs &a, int member_arg, int m
         if (member == 0) tp0 = wall_clock64();
         if (is_cluster) {
             int L = 0;
+            bool aggregated = false;    // the round lists already written (multiplexed tiles)
             if constexpr (Tile::kWide) {
-                const WideRound wr =
-                    (int64_t)R.h * R.w == (int64_t)R.stride() * WideTile<PT>::K
-                        ? wide_round<PT, true>(a, im, R, y, slots, lslots, e, cur, budget, level, tile_leader_wg,
-                                               l_idx, l_flux)
-                        : wide_round<PT, false>(a, im, R, y, slots, lslots, e, cur, budget, level, tile_leader_wg,
-                                                l_idx, l_flux);
-                if (!wr.ok) return;
-                cur = wr.cur;
-                e = wr.e;
-                L = wr.L;
+                // the cluster's tiles one after another (one tile unless the
+                // clusters are time-multiplexed), each with its own key,
+                // budget and round list
+                const int ncl = BATCH ? T : a.ncl;
+                for (int t = tile; t < T; t += ncl) {
+                    uint64_t kt = cur;
+                    int64_t bt = budget;
+                    if (ncl < T) {
+                        int ty0, tx0, th, tw;
+                        tile_rect(a, t, ty0, tx0, th, tw);
+                        R.init(im, ty0, tx0, th, tw, cs, rank, false);
+                        kt = ldc(&a.tile_key[t]);
+                        // this tile's budget: the round control's rule, with its
+                        // rank among the active tiles
+                        const double pk = (double)fabsf(key_value(kt));
+                        const bool act = pk >= a.threshold && pk >= level;
+                        int rk = 0;
+                        for (int u = threadIdx.x; u < t; u += WG) {
+                            const double pu = (double)fabsf(key_value(ldc(&a.tile_key[u])));
+                            rk += pu >= a.threshold && pu >= level;
+                        }
+                        rk = wg_sum_int(rk, &s_tmp);
+                        bt = !act ? 0
+                                  : rem >= (int64_t)na * a.interval ? a.interval
+                                                                     : rem / na + (rk < rem % na ? 1 : 0);
+                    }
+                    const WideRound wr =
+                        (int64_t)R.h * R.w == (int64_t)R.stride() * WideTile<PT>::K
+                            ? wide_round<PT, true>(a, im, R, y, slots, lslots, e, kt, bt, level, tile_leader_wg,
+                                                   l_idx, l_flux)
+                            : wide_round<PT, false>(a, im, R, y, slots, lslots, e, kt, bt, level, tile_leader_wg,
+                                                    l_idx, l_flux);
+                    if (!wr.ok) return;
+                    e = wr.e;
+                    if (ncl < T) {
+                        if (tile_leader_wg) {
+                            __syncthreads();
+                            aggregate_round(a, t, wr.L, l_idx, l_flux, l_tmp, l_sum, &s_cnt);
+                        }
+                        __syncthreads();
+                    } else {
+                        cur = wr.cur;
+                        L = wr.L;
+                    }
+                }
+                aggregated = ncl < T;
+                if (aggregated) {       // back to the first tile's geometry
+                    int ty0, tx0, th, tw;
+                    tile_rect(a, tile, ty0, tx0, th, tw);
+                    R.init(im, ty0, tx0, th, tw, cs, rank, false);
+                }
             } else
             for (int64_t it = 0; it < budget; ++it) {
                 const float v = key_value(cur);
@@ -2505,7 +2562,7 @@ __device__ __forceinline__ void tiled_body(const KArgs &a, int member_arg, int m
                 L += 1;
                 if (more && !cluster_reduce(y, slots, lslots, a.slot_pad, cs, rank, e++, tk, cur)) return;
             }
-            if (tile_leader_wg) {
+            if (tile_leader_wg && !aggregated) {
                 __syncthreads();
                 aggregate_round(a, tile, L, l_idx, l_flux, l_tmp, l_sum, &s_cnt);
             }
@@ -2670,6 +2727,23 @@ __device__ __forceinline__ void tiled_body(const KArgs &a, int member_arg, int m
         if (is_cluster) {
             if (!cluster_reduce(y, slots, lslots, a.slot_pad, cs, rank, e++, R.template apply_feedback<FFT>(im), cur)) return;
             if (tile_leader_wg && threadIdx.x == 0) stc(&a.tile_key[tile], cur);
+            if constexpr (Tile::kWide && !BATCH) {
+                // time-multiplexed clusters: the first tile above, then the others
+                for (int t = tile + a.ncl; t < T; t += a.ncl) {
+                    int ty0, tx0, th, tw;
+                    tile_rect(a, t, ty0, tx0, th, tw);
+                    R.init(im, ty0, tx0, th, tw, cs, rank, false);
+                    uint64_t k;
+                    if (!cluster_reduce(y, slots, lslots, a.slot_pad, cs, rank, e++, R.template apply_feedback<FFT>(im), k))
+                        return;
+                    if (tile_leader_wg && threadIdx.x == 0) stc(&a.tile_key[t], k);
+                }
+                if (a.ncl < T) {        // back to the first tile's geometry
+                    int ty0, tx0, th, tw;
+                    tile_rect(a, tile, ty0, tx0, th, tw);
+                    R.init(im, ty0, tx0, th, tw, cs, rank, false);
+                }
+            }
         }
         rounds += 1;
         if (a.has_cancel && member == 0 && threadIdx.x == 0)
@@ -2680,6 +2754,16 @@ __device__ __forceinline__ void tiled_body(const KArgs &a, int member_arg, int m
 
     // ---- results
     if (is_cluster) store_and_sum(R, im, a.partial, tile * cs + rank);
+    if constexpr (Tile::kWide && !BATCH) {
+        if (is_cluster) {
+            for (int t = tile + a.ncl; t < T; t += a.ncl) {
+                int ty0, tx0, th, tw;
+                tile_rect(a, t, ty0, tx0, th, tw);
+                R.init(im, ty0, tx0, th, tw, cs, rank, false);
+                store_and_sum(R, im, a.partial, t * cs + rank);
+            }
+        }
+    }
     if (member == 0 && threadIdx.x == 0) {
         uint64_t best = ldc(&a.tile_key[0]);
         for (int t = 1; t < T; ++t) {
