@@ -1449,6 +1449,10 @@ __device__ int32_t xcd_ticket(const BatchArgs &b, const Sync &y, uint32_t x)
 // Loads in flight per thread in the two-level phases: enough to overlap their
 // round trips, few enough to keep the streamed FFT kernel within 128 VGPRs.
 constexpr int STAGE_TWO = 4;
+// The same in the wide-tile kernel, whose transform phases run at one
+// workgroup per CU in functions with the whole register file to themselves:
+// half the waves to hide the round trips, and the registers for more.
+constexpr int STAGE_TWO_WIDE = 16;
 
 struct FftAxis {
     int lg, L, H;           // length 2^lg; H = L/2 + 1 (x axis: carried bins)
@@ -1642,7 +1646,7 @@ __device__ void xfwd_one(const KArgs &a, const FftAxis &fx, int Ly, int rows, co
 // x forward, two levels, step 1: per row pair and n2, transforms of length L1
 // over n1 (input x = L2 n1 + n2), times W_L^(n2 k1), into fft_wx[pair][L2 k1 + n2].
 // Source: the dense component image, or (KSRC) the PSF kernel image.
-template <typename PT, bool KSRC>
+template <typename PT, bool KSRC, int U = STAGE_TWO>
 __device__ __forceinline__ void xfwd_two_a(const KArgs &a, const FftAxis &fx, int Ly, int rows, float2 *lds)
 {
     const int lgNB = strided_block_lg(fx), NB = 1 << lgNB;
@@ -1653,7 +1657,7 @@ __device__ __forceinline__ void xfwd_two_a(const KArgs &a, const FftAxis &fx, in
         const int pr = item / nblk, b = item % nblk;
         const int r0 = 2 * pr;
         const bool has1 = r0 + 1 < rows;
-        staged<STAGE_TWO>(NB * fx.L1, true,
+        staged<U>(NB * fx.L1, true,
                   [&](int e) {
                       const int x = fx.L2 * (e >> lgNB) + b * NB + (e & (NB - 1));
                       float v0 = 0.f, v1 = 0.f;
@@ -1689,7 +1693,7 @@ __device__ __forceinline__ void xfwd_two_a(const KArgs &a, const FftAxis &fx, in
 // image rows' carried bins (chat order), column-major into fft_b like
 // xfwd_one.  Unless KSRC, also clears the dense component image at this
 // round's positions.
-template <bool KSRC>
+template <bool KSRC, int U = STAGE_TWO>
 __device__ __forceinline__ void xfwd_two_b(const KArgs &a, const FftAxis &fx, int rows, float2 *lds, const int32_t *s_off)
 {
     const int nslot = fx.L1 / 2 + 1;
@@ -1707,7 +1711,7 @@ __device__ __forceinline__ void xfwd_two_b(const KArgs &a, const FftAxis &fx, in
         const bool has1 = r0 + 1 < rows;
         const float2 *w = a.fft_wx + (size_t)pr * fx.L;
         // segment 2i: row k1 = s0 + i; segment 2i+1: row (L1 - k1) mod L1
-        staged<STAGE_TWO>(2 * ns * fx.L2, true,
+        staged<U>(2 * ns * fx.L2, true,
                   [&](int e) {
                       const int seg = e >> fx.lg2, n2 = e & (fx.L2 - 1);
                       const int k1 = s0 + (seg >> 1);
@@ -1886,6 +1890,7 @@ __device__ void ycol_one(const KArgs &a, const FftAxis &fx, const FftAxis &fy, i
 // y, two levels, step 1: per carried column and n2, transforms of length L1
 // over n1 (input y = L2 n1 + n2 < rows), times W_L^(n2 k1), into
 // fft_wy[col][L2 k1 + n2].
+template <int U = STAGE_TWO>
 __device__ __forceinline__ void ycol_two_a(const KArgs &a, const FftAxis &fx, const FftAxis &fy, int rows, float2 *lds)
 {
     const int lgNB = strided_block_lg(fy), NB = 1 << lgNB;
@@ -1894,7 +1899,7 @@ __device__ __forceinline__ void ycol_two_a(const KArgs &a, const FftAxis &fx, co
     for (int item = blockIdx.x; item < fx.H * nblk; item += gridDim.x) {
         const int col = item / nblk, b = item % nblk;
         const float2 *src = a.fft_b + (size_t)col * rows;
-        staged<STAGE_TWO>(NB * fy.L1, true,
+        staged<U>(NB * fy.L1, true,
                   [&](int e) { return ldc2(&src[min(fy.L2 * (e >> lgNB) + b * NB + (e & (NB - 1)), rows - 1)]); },
                   [&](int e, float2 v) {
                       const int yy = fy.L2 * (e >> lgNB) + b * NB + (e & (NB - 1));
@@ -1916,7 +1921,7 @@ __device__ __forceinline__ void ycol_two_a(const KArgs &a, const FftAxis &fx, co
 // the PSF kernel's spectrum in (k1, bit-reversed k2) order, or multiply by it,
 // transform back over k2 (time order: no permutation between), times
 // conj W_L^(n2 k1), into fft_wy.
-template <bool PRE>
+template <bool PRE, int U = STAGE_TWO>
 __device__ __forceinline__ void ycol_two_b(const KArgs &a, const FftAxis &fx, const FftAxis &fy, float2 *lds)
 {
     const int stride = fft_seg_stride(fy.L2);
@@ -1930,7 +1935,7 @@ __device__ __forceinline__ void ycol_two_b(const KArgs &a, const FftAxis &fx, co
         // natural order in, forward in frequency order: the spectrum (and the
         // PSF kernel's, made by the same code) in bit-reversed k2 order, which
         // the inverse below takes as it is
-        staged<STAGE_TWO>(ng * fy.L2, true,
+        staged<U>(ng * fy.L2, true,
                   [&](int e) { return ldc2(&w[(size_t)fy.L2 * (k0 + (e >> fy.lg2)) + (e & (fy.L2 - 1))]); },
                   [&](int e, float2 v) { lds[(e >> fy.lg2) * stride + pad16(e & (fy.L2 - 1))] = v; });
         fft_lds_multi_dif(lds, fy.lg2, ng, stride, fy.tw, fy.L1, false);
@@ -1942,7 +1947,7 @@ __device__ __forceinline__ void ycol_two_b(const KArgs &a, const FftAxis &fx, co
             }
             continue;
         }
-        staged<STAGE_TWO>(ng * fy.L2, false,
+        staged<U>(ng * fy.L2, false,
                   [&](int e) { return ldc2(&ks[(size_t)fy.L2 * (k0 + (e >> fy.lg2)) + (e & (fy.L2 - 1))]); },
                   [&](int e, float2 k) {
                       float2 &z = lds[(e >> fy.lg2) * stride + pad16(e & (fy.L2 - 1))];
@@ -1959,6 +1964,7 @@ __device__ __forceinline__ void ycol_two_b(const KArgs &a, const FftAxis &fx, co
 
 // y, two levels, step 3: per carried column and n2, inverse transforms of
 // length L1 over k1, giving y = L2 n1 + n2; the first `rows` go to fft_b.
+template <int U = STAGE_TWO>
 __device__ __forceinline__ void ycol_two_c(const KArgs &a, const FftAxis &fx, const FftAxis &fy, int rows, float2 *lds)
 {
     const int lgNB = strided_block_lg(fy), NB = 1 << lgNB;
@@ -1967,7 +1973,7 @@ __device__ __forceinline__ void ycol_two_c(const KArgs &a, const FftAxis &fx, co
     for (int item = blockIdx.x; item < fx.H * nblk; item += gridDim.x) {
         const int col = item / nblk, b = item % nblk;
         const float2 *w = a.fft_wy + (size_t)col * fy.L;
-        staged<STAGE_TWO>(NB * fy.L1, true,
+        staged<U>(NB * fy.L1, true,
                   [&](int e) { return ldc2(&w[(size_t)fy.L2 * (e >> lgNB) + b * NB + (e & (NB - 1))]); },
                   [&](int e, float2 v) { lds[(e & (NB - 1)) * stride + pad16(bitrev((uint32_t)(e >> lgNB), fy.lg1))] = v; });
         fft_lds_multi(lds, fy.lg1, NB, stride, fy.tw, fy.L2, true);
@@ -2085,6 +2091,7 @@ __device__ void xinv_one(const KArgs &a, const FftAxis &fx, float scale, float2 
 // x inverse, two levels, step 1: per row pair and row k1, Z(k1, k2) for all
 // k2 from the carried bins (A + iB, or conj A + i conj B at mirrored bins),
 // inverse transform over k2 (length L2), times conj W_L^(n2 k1), into fft_wx.
+template <int U = STAGE_TWO>
 __device__ __forceinline__ void xinv_two_a(const KArgs &a, const FftAxis &fx, float2 *lds)
 {
     const int ny = a.ny, stride = fft_seg_stride(fx.L2), hq = fx.L2 / 2;
@@ -2098,7 +2105,7 @@ __device__ __forceinline__ void xinv_two_a(const KArgs &a, const FftAxis &fx, fl
         const int r0 = 2 * pr;
         const bool has1 = r0 + 1 < ny;
         const float2 *c0 = a.fft_b + r0;       // bin c of the pair at c0[c * ny], c0[c * ny + 1]
-        staged<STAGE_TWO>(ng * fx.L2, true,
+        staged<U>(ng * fx.L2, true,
                   [&](int e) {
                       const int k2 = e & (fx.L2 - 1), k1 = k0 + (e >> fx.lg2);
                       const bool carried = k2 < hq || (k2 == hq && k1 == 0);
@@ -2132,6 +2139,7 @@ __device__ __forceinline__ void xinv_two_a(const KArgs &a, const FftAxis &fx, fl
 // x inverse, two levels, step 2: per row pair and n2, inverse transforms of
 // length L1 over k1 giving x = L2 n1 + n2; real / imaginary parts of the
 // first nx, scaled, into the feedback buffer rows 2m / 2m+1.
+template <int U = STAGE_TWO>
 __device__ __forceinline__ void xinv_two_b(const KArgs &a, const FftAxis &fx, float scale, float2 *lds)
 {
     const int ny = a.ny, nx = a.nx;
@@ -2143,7 +2151,7 @@ __device__ __forceinline__ void xinv_two_b(const KArgs &a, const FftAxis &fx, fl
         const int r0 = 2 * pr;
         const bool has1 = r0 + 1 < ny;
         const float2 *w = a.fft_wx + (size_t)pr * fx.L;
-        staged<STAGE_TWO>(NB * fx.L1, true,
+        staged<U>(NB * fx.L1, true,
                   [&](int e) { return ldc2(&w[(size_t)fx.L2 * (e >> lgNB) + b * NB + (e & (NB - 1))]); },
                   [&](int e, float2 v) { lds[(e & (NB - 1)) * stride + pad16(bitrev((uint32_t)(e >> lgNB), fx.lg1))] = v; });
         fft_lds_multi(lds, fx.lg1, NB, stride, fx.tw, fx.L2, true);
@@ -2181,17 +2189,17 @@ __device__ __noinline__ bool fft_spectrum(const KArgs *a_arg, const Sync y_arg, 
     if (!fx.two) {
         xfwd_one<PT, true, BIG>(a, fx, Ly, Ly, nullptr, lds, &s_nz);
     } else {
-        xfwd_two_a<PT, true>(a, fx, Ly, Ly, lds);
+        xfwd_two_a<PT, true, BIG ? STAGE_TWO_WIDE : STAGE_TWO>(a, fx, Ly, Ly, lds);
         FFT_BARRIER();
-        xfwd_two_b<true>(a, fx, Ly, lds, nullptr);
+        xfwd_two_b<true, BIG ? STAGE_TWO_WIDE : STAGE_TWO>(a, fx, Ly, lds, nullptr);
     }
     FFT_BARRIER_FENCED();
     if (!fy.two) {
         ycol_one<true, BIG>(a, fx, fy, Ly, lds);
     } else {
-        ycol_two_a(a, fx, fy, Ly, lds);
+        ycol_two_a<BIG ? STAGE_TWO_WIDE : STAGE_TWO>(a, fx, fy, Ly, lds);
         FFT_BARRIER();
-        ycol_two_b<true>(a, fx, fy, lds);
+        ycol_two_b<true, BIG ? STAGE_TWO_WIDE : STAGE_TWO>(a, fx, fy, lds);
     }
     FFT_BARRIER();
     return true;
@@ -2215,27 +2223,27 @@ __device__ __forceinline__ bool fft_feedback(const KArgs &a, const Sync &y, XcdB
     if (!fx.two) {
         xfwd_one<PT, false, BIG>(a, fx, fy.L, ny, s_off, lds, &s_nz);
     } else {
-        xfwd_two_a<PT, false>(a, fx, fy.L, ny, lds);
+        xfwd_two_a<PT, false, BIG ? STAGE_TWO_WIDE : STAGE_TWO>(a, fx, fy.L, ny, lds);
         FFT_BARRIER();
-        xfwd_two_b<false>(a, fx, ny, lds, s_off);
+        xfwd_two_b<false, BIG ? STAGE_TWO_WIDE : STAGE_TWO>(a, fx, ny, lds, s_off);
     }
     FFT_BARRIER_FENCED();
     if (!fy.two) {
         ycol_one<false, BIG>(a, fx, fy, ny, lds);
     } else {
-        ycol_two_a(a, fx, fy, ny, lds);
+        ycol_two_a<BIG ? STAGE_TWO_WIDE : STAGE_TWO>(a, fx, fy, ny, lds);
         FFT_BARRIER();
-        ycol_two_b<false>(a, fx, fy, lds);
+        ycol_two_b<false, BIG ? STAGE_TWO_WIDE : STAGE_TWO>(a, fx, fy, lds);
         FFT_BARRIER();
-        ycol_two_c(a, fx, fy, ny, lds);
+        ycol_two_c<BIG ? STAGE_TWO_WIDE : STAGE_TWO>(a, fx, fy, ny, lds);
     }
     FFT_BARRIER_FENCED();
     if (!fx.two) {
         xinv_one<BIG>(a, fx, scale, lds);
     } else {
-        xinv_two_a(a, fx, lds);
+        xinv_two_a<BIG ? STAGE_TWO_WIDE : STAGE_TWO>(a, fx, lds);
         FFT_BARRIER();
-        xinv_two_b(a, fx, scale, lds);
+        xinv_two_b<BIG ? STAGE_TWO_WIDE : STAGE_TWO>(a, fx, scale, lds);
     }
     __syncthreads();
     return true;
