@@ -234,17 +234,19 @@ def test_tiled_wide_tile_small(lib, case):
     assert_same_run(out, ref)
 
 
-@pytest.mark.parametrize("case", [(512, 512, (32, 32), 3, 51, 6000), (384, 512, (24, 32), 2, 52, 3000)],
-                         ids=["1024-tiles", "768-tiles"])
+@pytest.mark.parametrize("case", [(512, 512, (32, 32), 3, 51, 6000, 0.0), (384, 512, (24, 32), 2, 52, 3000, 0.0),
+                                  (512, 512, (32, 32), 4, 53, 20000, 1.0)],
+                         ids=["1024-tiles", "768-tiles", "1024-tiles-threshold"])
 def test_tiled_wide_tile_multiplexed(lib, case):
     """More wide-tile clusters than fit the chip at once: each cluster runs
-    several tiles in turn in every round; bit-identical to the oracle."""
-    ny, nx, tiles, interval, seed, n = case
+    several tiles in turn in every round (with a threshold, some of them sit
+    rounds out); bit-identical to the oracle."""
+    ny, nx, tiles, interval, seed, n, thr = case
     announce("tiled wide tile multiplexed", case)
     dirty = sparse_dirty(ny, nx, seed, density=0.03)
     psf = asym_psf(2 * ny, 2 * nx + 2, seed, spread=0.2)
-    ref = oracle.tiled(dirty, psf, tiles, interval, 0.1, 0.0, n)
-    out = lib.tiled_feedback(dev(dirty), dev(psf), tiles, interval, 0.1, 0.0, n, px_per_thread=128)
+    ref = oracle.tiled(dirty, psf, tiles, interval, 0.1, thr, n)
+    out = lib.tiled_feedback(dev(dirty), dev(psf), tiles, interval, 0.1, thr, n, px_per_thread=128)
     st = out["stats"]
     T = tiles[0] * tiles[1]
     assert st["px_per_thread"] == 128 and st["streamed"] == 0
