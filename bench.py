@@ -613,8 +613,12 @@ def main():
         huge["tiled_fft_one_round"] = {"kernel_ms": rt4["stats"]["device_ms"], "n_iter": rt4["stats"]["n_iter"],
                                        "iters_per_s": rt4["stats"]["n_iter"] / (rt4["stats"]["device_ms"] * 1e-3),
                                        "phase_us": rt4["stats"]["phase_us"],
+                                       "launch": {k: rt4["stats"][k] for k in ("wg_per_tile", "px_per_thread",
+                                                                               "workgroups", "streamed")},
                                        "note": "one round at interval 100 (25600 iterations), FFT feedback; the "
-                                               "method diverges on this input after some rounds"}
+                                               "method diverges on this input after some rounds; with "
+                                               "px_per_thread 128 and fewer workgroups than 256 tiles x "
+                                               "wg_per_tile, the tile clusters are time-multiplexed"}
         del rt4, d4, p4
         torch.cuda.empty_cache()
         log(f"16384^2 workload: {time.time() - t1:.1f} s")
