@@ -32,6 +32,7 @@ __global__ void finite_check_half_kernel(const unsigned short *x, int64_t n, uin
 __global__ void to_half_kernel(const float *x, unsigned short *y, int64_t n);
 __global__ void finalize_kernel(const double *partial, int n, DevStat *st);
 __global__ void zero_kernel(uint32_t *p, int64_t n);
+__global__ void shift_half_kernel(const unsigned short *x, unsigned short *y, int64_t n);
 __global__ void diff_range_kernel(const double *a, const double *b, int64_t n, double *part);
 __global__ void probe_read_kernel(const float4 *p, int64_t n4, int reps, float *sink);
 __global__ void probe_copy_kernel(const float4 *src, float4 *dst, int64_t n4, int reps);
@@ -217,7 +218,7 @@ int scratch_address(int dev, void **out)
 struct Layout {
     size_t ctl, dstat, xslots, lslots, hslots, tile_key, rb_n, ag_n, header_end;
     size_t role, rb_idx, rb_flux, ag_pos, ag_flux, accbuf, partial;
-    size_t fft_b, fft_wx, fft_wy, fft_ks, comp_img, tw_x, tw_y, rstart, total;
+    size_t fft_b, fft_wx, fft_wy, fft_ks, comp_img, tw_x, tw_y, rstart, psf1, total;
 };
 
 int ceil_log2(int64_t v)
@@ -241,7 +242,7 @@ int two_level_pad(bool tiled, int cs)
 }
 
 Layout make_layout(int T, int cs, int slot_pad, int interval, int W, int64_t npix, bool tiled, int ny = 0,
-                   const FftGeom &g = FftGeom())
+                   const FftGeom &g = FftGeom(), size_t psf1_bytes = 0)
 {
     const int hpad = two_level_pad(tiled, cs);
     Layout L{};
@@ -274,6 +275,7 @@ Layout make_layout(int T, int cs, int slot_pad, int interval, int W, int64_t npi
     L.tw_x = o;      o = align_up(o + Lx * 8, 256);
     L.tw_y = o;      o = align_up(o + Ly * 8, 256);
     L.rstart = o;    o = align_up(o + (fft ? (size_t)npix * 4 : 0), 256);
+    L.psf1 = o;      o = align_up(o + psf1_bytes, 256);
     L.total = o;
     return L;
 }
@@ -740,7 +742,12 @@ int run(bool tiled, const float *dirty, int ny, int nx, const void *psf, int psf
 
     const int slot_pad = (cs + 31) / 32 * 32;
     const int64_t npix = (int64_t)ny * nx;
-    const Layout L = make_layout(T, cs, slot_pad, interval, W, npix, tiled, ny, fg);
+    // the wide tile with an FP16 PSF: room for the PSF moved down one element
+    // (left out when a caller's workspace has no room for it)
+    const size_t psf1_bytes = tiled && half && ppt == 128 ? (size_t)psf_ny * psf_nx * 2 : 0;
+    Layout L = make_layout(T, cs, slot_pad, interval, W, npix, tiled, ny, fg, psf1_bytes);
+    if (psf1_bytes && workspace && !noalloc && workspace_bytes < L.total)
+        L = make_layout(T, cs, slot_pad, interval, W, npix, tiled, ny, fg);
     char *ws = (char *)workspace;
     if (noalloc) {
         if (L.total > CLEAN_NOALLOC_SCRATCH_BYTES)     // not reached: noalloc_fits ran first
@@ -815,6 +822,7 @@ int run(bool tiled, const float *dirty, int ny, int nx, const void *psf, int psf
     a.tw_x = (const float2 *)(ws + L.tw_x);
     a.tw_y = (const float2 *)(ws + L.tw_y);
     a.rstart = fft ? (float *)(ws + L.rstart) : nullptr;
+    a.psf1 = L.psf1 != L.total && psf1_bytes && L.total - L.psf1 >= psf1_bytes ? (const void *)(ws + L.psf1) : nullptr;
 
     if (noalloc) {
         // the header is a whole number of 256-byte blocks
@@ -839,6 +847,12 @@ int run(bool tiled, const float *dirty, int ny, int nx, const void *psf, int psf
         st = read_back(rb, 1, stream, noalloc);
         if (st) return st;
         if (bad) return fail(CLEAN_E_NONFINITE, "non-finite value in the dirty image or PSF");
+    }
+
+    if (a.psf1) {
+        hipLaunchKernelGGL(shift_half_kernel, dim3(2048), dim3(256), 0, stream, (const unsigned short *)psf,
+                           (unsigned short *)a.psf1, (int64_t)psf_ny * psf_nx);
+        HIPCHK(hipGetLastError());
     }
 
     std::vector<float2> twx, twy;

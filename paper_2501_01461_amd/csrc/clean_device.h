@@ -121,6 +121,8 @@ struct KArgs {
     float *residual;
     double *model;
     const void *psf;
+    const void *psf1;       // FP16 PSF moved down one element (psf1[i] = psf[i + 1]) for the wide tile's
+                            // odd-element windows, which then start on a 4-byte boundary; or null
     uint64_t psf_bytes;
     int ny, nx, psf_ny, psf_nx, cy, cx;
     int ty, tx, T;

@@ -972,6 +972,7 @@ __device__ __noinline__ WideRound wide_round(const KArgs &a, const Img im, const
     const int anx = wave_uniform(a.nx), acy = wave_uniform(a.cy), acx = wave_uniform(a.cx);
     const int apnx = wave_uniform(a.psf_nx), tw = wave_uniform(R.w), ty0 = wave_uniform(R.y0), tx0 = wave_uniform(R.x0);
     const void *psf = wave_uniform(a.psf);
+    const void *psf1 = wave_uniform(a.psf1);
     const uint64_t psf_bytes = wave_uniform(a.psf_bytes);
     double *model = wave_uniform(a.model);
     const int64_t nb = wave_uniform(budget);
@@ -998,7 +999,16 @@ __device__ __noinline__ WideRound wide_round(const KArgs &a, const Img im, const
         // touch no memory; they are multiplied by 0.  (With the 32 group
         // offsets held in vector registers instead, the compiler had waited
         // for each load before issuing the next.)
-        const uint64_t wb = (uint64_t)((int64_t)(acy - py) * apnx + (acx - px)) * sizeof(PT);
+        uint64_t wb = (uint64_t)((int64_t)(acy - py) * apnx + (acx - px)) * sizeof(PT);
+        // an FP16 window at an odd element is read from the copy moved down
+        // one element, where it starts on a 4-byte boundary (8-byte loads at
+        // 2-byte-aligned addresses cost the memory pipeline about what the
+        // FP32 window's 16 bytes do)
+        const char *pbase = (const char *)psf;
+        if (sizeof(PT) == 2 && psf1 != nullptr && (wb & 2) != 0) {
+            pbase = (const char *)psf1;
+            wb -= 2;
+        }
         constexpr int WB = 16;
         constexpr uint32_t kOutside = 0xFFFFFFF0u;
         // the group offsets j * step are made here, in each iteration, from
@@ -1012,7 +1022,7 @@ __device__ __noinline__ WideRound wide_round(const KArgs &a, const Img im, const
             // the range stops short of kOutside, whatever the PSF's size
             const uint32_t nrec = min(clamp_u32((int64_t)(psf_bytes - kb)), kOutside - 1u);
             const __amdgpu_buffer_rsrc_t rs =
-                __builtin_amdgcn_make_buffer_rsrc((void *)((const char *)psf + kb), (short)0, (int)nrec, 0x00020000);
+                __builtin_amdgcn_make_buffer_rsrc((void *)(pbase + kb), (short)0, (int)nrec, 0x00020000);
             float pv[WB][V];
 #pragma unroll
             for (int j = 0; j < WB; ++j)
@@ -2914,6 +2924,14 @@ __global__ void to_half_kernel(const float *x, unsigned short *y, int64_t n)
 {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         y[i] = __half_as_ushort(__float2half_rn(x[i]));
+}
+
+// y[i] = x[i + 1] (the last one 0): the FP16 PSF one element down, so that a
+// window starting at an odd element starts on a 4-byte boundary in y.
+__global__ void shift_half_kernel(const unsigned short *x, unsigned short *y, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        y[i] = i + 1 < n ? x[i + 1] : (unsigned short)0;
 }
 
 // Clear n 32-bit words (used where a fill must not be a runtime memset).
